@@ -1,0 +1,247 @@
+"""FP64 CPU oracle for the Gaussian-splatting fit step (ctypes wrapper of gsorc.c).
+
+TEST INFRASTRUCTURE ONLY: imported by the test suite, the package smoke check
+and the benchmark's CPU-baseline leg.  The product path never imports it.
+
+Functions follow the plain definitions written out in ``gsorc.c`` (projection by
+the local affine approximation of the pinhole map, brute-force front-to-back
+compositing over all Gaussians in depth order, the exact adjoint, the
+(tile, depth) discrete stage by nested loops and a comparison sort, L1 loss,
+bias-corrected Adam).  Inputs are the float32 arrays produced by ``synth``,
+widened to float64.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gsorc.c")
+_LIB = os.path.join(_HERE, "libgsorc.so")
+
+NREC = 22
+F_NEAR_ALPHA, F_NEAR_STOP, F_NEAR_TIE, F_NEAR_CLAMP = 1, 2, 4, 8
+F_NEAR_CULL, F_NEAR_BOX, F_NEAR_GRAD = 16, 32, 64
+# pixel flags that make the fp32 image legitimately differ
+IMAGE_FLAGS = F_NEAR_ALPHA | F_NEAR_STOP | F_NEAR_TIE
+REC_FIELDS = ["valid", "tz", "tx", "ty", "mx", "my", "A", "B", "C", "o", "r", "g", "b",
+              "sa", "sb", "sc", "ex0", "ex1", "ey0", "ey1", "d32", "colraw"]
+
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (FP64, OpenMP, no fast-math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+               "-fno-fast-math", "-Wall", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ct.CDLL(_LIB)
+        dp, i64p, i32p = ct.POINTER(ct.c_double), ct.POINTER(ct.c_int64), ct.POINTER(ct.c_int32)
+        L.orc_project.argtypes = [dp, ct.c_int64, ct.c_int, dp, dp, i32p]
+        L.orc_render.argtypes = [dp, ct.c_int64, ct.c_int, dp, i64p, ct.c_int64, dp, dp, i64p,
+                                 i64p, i32p]
+        L.orc_backward.argtypes = [dp, ct.c_int64, ct.c_int, dp, i64p, ct.c_int64, dp, dp, dp]
+        L.orc_discrete.argtypes = [dp, ct.c_int64, ct.c_int, dp, ct.c_int, ct.c_int, i64p, i64p,
+                                   ct.c_int64, i64p, i64p, i32p]
+        L.orc_loss_l1.argtypes = [dp, dp, ct.c_int64, ct.c_int64, dp, ct.c_double, dp, i64p]
+        L.orc_loss_l1.restype = ct.c_double
+        L.orc_adam.argtypes = [dp, dp, dp, dp, ct.c_int64, ct.c_double, ct.c_double, ct.c_double,
+                               ct.c_double, ct.c_int64]
+        L.orc_adam.restype = None
+        L.orc_sh_basis.argtypes = [ct.c_int, dp, ct.c_int64, dp]
+        L.orc_num_threads.restype = ct.c_int
+        _lib = L
+    return _lib
+
+
+def _d(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _p(a, t=ct.c_double):
+    return a.ctypes.data_as(ct.POINTER(t)) if a is not None else None
+
+
+def cam_array(cam) -> np.ndarray:
+    """27-double camera record of a ``synth.Camera``."""
+    return _d(np.concatenate([cam.R.reshape(-1), cam.t, cam.campos,
+                              [cam.fx, cam.fy, cam.cx, cam.cy, cam.tanx, cam.tany, cam.znear],
+                              cam.bg, [cam.width, cam.height]]))
+
+
+def sh_degree_of(params) -> int:
+    C = params.shape[0]
+    K = (C - 11) // 3
+    deg = int(round(K ** 0.5)) - 1
+    assert 11 + 3 * (deg + 1) ** 2 == C, "bad parameter plane count"
+    return deg
+
+
+def num_threads() -> int:
+    return lib().orc_num_threads()
+
+
+def project(params, cam):
+    """FP64 per-Gaussian projection records as a dict of arrays, plus flags."""
+    P = _d(params)
+    n = P.shape[1]
+    rec = np.zeros((n, NREC))
+    fl = np.zeros(n, np.int32)
+    rc = lib().orc_project(_p(P), n, sh_degree_of(P), _p(cam_array(cam)), _p(rec),
+                           _p(fl, ct.c_int32))
+    assert rc == 0
+    out = {k: rec[:, j] for j, k in enumerate(REC_FIELDS)}
+    out["flags"] = fl
+    return out
+
+
+@dataclass
+class Render:
+    rgba: np.ndarray      # [4][npix]
+    tfinal: np.ndarray    # [npix]
+    last: np.ndarray      # [npix] Gaussian index of the last included Gaussian, -1 if none
+    ncontrib: np.ndarray  # [npix]
+    flags: np.ndarray     # [npix]
+
+
+def render(params, cam, pixels=None) -> Render:
+    P = _d(params)
+    n = P.shape[1]
+    pix = None if pixels is None else np.ascontiguousarray(pixels, np.int64)
+    npix = cam.npix if pix is None else pix.size
+    rgba = np.zeros((4, npix))
+    tf = np.zeros(npix)
+    last = np.zeros(npix, np.int64)
+    nc = np.zeros(npix, np.int64)
+    fl = np.zeros(npix, np.int32)
+    rc = lib().orc_render(_p(P), n, sh_degree_of(P), _p(cam_array(cam)), _p(pix, ct.c_int64),
+                          npix, _p(rgba), _p(tf), _p(last, ct.c_int64), _p(nc, ct.c_int64),
+                          _p(fl, ct.c_int32))
+    assert rc == 0
+    return Render(rgba, tf, last, nc, fl)
+
+
+def backward(params, cam, dl_drgba, pixels=None, with_g2d=False):
+    """Gradient of sum <dl, rgba> over the listed pixels w.r.t. the raw
+    parameters ([C][n], float64); optionally also the per-Gaussian 2D gradient
+    (dmx, dmy, dA, dB, dC, do, dr, dg, db) as [9][n]."""
+    P = _d(params)
+    n = P.shape[1]
+    pix = None if pixels is None else np.ascontiguousarray(pixels, np.int64)
+    npix = cam.npix if pix is None else pix.size
+    dl = _d(dl_drgba).reshape(4, npix)
+    G = np.zeros_like(P)
+    g2 = np.zeros((9, n))
+    rc = lib().orc_backward(_p(P), n, sh_degree_of(P), _p(cam_array(cam)), _p(pix, ct.c_int64),
+                            npix, _p(dl), _p(G), _p(g2))
+    assert rc == 0
+    return (G, g2) if with_g2d else G
+
+
+@dataclass
+class Discrete:
+    keys: np.ndarray      # global tile id per key
+    vals: np.ndarray      # record r = v*n + i per key
+    ranges: np.ndarray    # [tiles][2] start, end
+    rflags: np.ndarray    # [V*n] per-record ambiguity flags
+    m: int
+
+
+def discrete(params, cams, tile: int) -> Discrete:
+    P = _d(params)
+    n = P.shape[1]
+    C = _d(np.concatenate([cam_array(c) for c in cams]))
+    tiles = sum(((c.width + tile - 1) // tile) * ((c.height + tile - 1) // tile) for c in cams)
+    ranges = np.zeros((tiles, 2), np.int64)
+    rflags = np.zeros(len(cams) * n, np.int32)
+    m = np.zeros(1, np.int64)
+    # first pass counts, second pass fills
+    lib().orc_discrete(_p(P), n, sh_degree_of(P), _p(C), len(cams), tile, None, None, 0,
+                       _p(m, ct.c_int64), _p(ranges, ct.c_int64), _p(rflags, ct.c_int32))
+    M = int(m[0])
+    keys = np.zeros(max(M, 1), np.int64)
+    vals = np.zeros(max(M, 1), np.int64)
+    lib().orc_discrete(_p(P), n, sh_degree_of(P), _p(C), len(cams), tile, _p(keys, ct.c_int64),
+                       _p(vals, ct.c_int64), M, _p(m, ct.c_int64), _p(ranges, ct.c_int64),
+                       _p(rflags, ct.c_int32))
+    return Discrete(keys[:M], vals[:M], ranges, rflags, M)
+
+
+def loss_l1_view(rgba, target, cam, gaze=None, radius=0.0):
+    """(sum, count, sign[4][npix]) of one view's masked L1 term."""
+    rgba = _d(rgba).reshape(4, -1)
+    target = _d(target).reshape(-1, rgba.shape[1])[:3]
+    target = np.ascontiguousarray(target)
+    dl = np.zeros_like(rgba)
+    cnt = np.zeros(1, np.int64)
+    g = None if gaze is None else _d(gaze)
+    s = lib().orc_loss_l1(_p(rgba), _p(target), cam.width, cam.height, _p(g), float(radius),
+                          _p(dl), _p(cnt, ct.c_int64))
+    return s, int(cnt[0]), dl
+
+
+def loss_l1(rgbas, targets, cams, gazes=None, radius_frac=0.2):
+    """Mean |RGB - target| over all masked (view, pixel, channel) entries and
+    dL/dRGBA per view."""
+    sums, cnts, dls = 0.0, 0, []
+    for v, cam in enumerate(cams):
+        g = None if gazes is None else gazes[v]
+        s, c, dl = loss_l1_view(rgbas[v], targets[v], cam, g, radius_frac * cam.width)
+        sums += s
+        cnts += c
+        dls.append(dl)
+    denom = max(cnts, 1)
+    return sums / denom, [d / denom for d in dls]
+
+
+def adam(p, g, m, v, t, lr=1e-3, betas=(0.9, 0.999), eps=1e-15):
+    """In-place bias-corrected Adam on float64 arrays; ``t`` is the step number
+    after increment (1 for the first step).  ``lr`` may be a per-element array."""
+    for a in (p, g, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    lr_arr = np.broadcast_to(np.asarray(lr, np.float64), p.shape)
+    if np.all(lr_arr == lr_arr.flat[0]):
+        lib().orc_adam(_p(p), _p(g), _p(m), _p(v), p.size, float(lr_arr.flat[0]), betas[0],
+                       betas[1], eps, int(t))
+        return
+    # per-segment learning rates: one call per distinct value on a masked copy
+    for val in np.unique(lr_arr):
+        sel = np.nonzero(lr_arr.reshape(-1) == val)[0]
+        ps, gs, ms, vs = (np.ascontiguousarray(a.reshape(-1)[sel]) for a in (p, g, m, v))
+        lib().orc_adam(_p(ps), _p(gs), _p(ms), _p(vs), ps.size, float(val), betas[0], betas[1],
+                       eps, int(t))
+        p.reshape(-1)[sel], m.reshape(-1)[sel], v.reshape(-1)[sel] = ps, ms, vs
+
+
+def fit_step(params, m, v, t, cams, targets, gazes=None, radius_frac=0.2, lr=1e-3,
+             betas=(0.9, 0.999), eps=1e-15):
+    """One full oracle step (render, L1 loss, adjoint, Adam) on float64 state.
+    Returns the loss; params, m, v are updated in place."""
+    rgbas = [render(params, c).rgba for c in cams]
+    loss, dls = loss_l1(rgbas, targets, cams, gazes, radius_frac)
+    G = np.zeros_like(params)
+    for cam, dl in zip(cams, dls):
+        G += backward(params, cam, dl)
+    adam(params, G, m, v, t, lr, betas, eps)
+    return loss
+
+
+def sh_basis(deg, dirs):
+    d = _d(dirs).reshape(-1, 3)
+    out = np.zeros((d.shape[0], 16))
+    lib().orc_sh_basis(deg, _p(d), d.shape[0], _p(out))
+    return out[:, :(deg + 1) ** 2]

@@ -1,0 +1,385 @@
+"""Seeded synthetic inputs for the Gaussian-fit hot path.
+
+This module only *produces inputs*: Gaussian parameter sets, pinhole cameras,
+a CT-like phantom volume, voxel-seeded Gaussians and emission-absorption
+ray-marched target images.  It contains none of the rasterizer's arithmetic
+(projection, compositing, adjoint, optimizer) and is the only code shared by
+the FP64 oracle and the HIP path.  Every value it returns is float32-exact, so
+both sides read bit-identical inputs (the oracle widens them to float64).
+
+The paper's CT datasets (its Datasets section) and its path tracer are not
+available; these generators stand in for them:
+
+* ``random_gaussians``  - independent Gaussians (means uniform in a cube,
+  log-normal scales, random unit quaternions, logit-normal opacity,
+  RGB-uniform degree-0 colour, optional higher SH bands).
+* ``phantom`` / ``seed_from_volume`` - a sum of random ellipsoids with HU-like
+  values and noise, and one Gaussian per voxel above a threshold (the paper
+  seeds its fit from points placed on the volume's surfaces, Method section,
+  "Volumetric Path Tracing").
+* ``raymarch`` - an emission-absorption ray march of that volume, standing in
+  for the path-traced training views.
+
+Parameter layout (planar float32, ``[C][n]``)::
+
+    0..2   mean (x, y, z)            world units
+    3..5   log-scale (x, y, z)       scale = exp(log-scale)
+    6..9   quaternion (w, x, y, z)   normalised by the rasterizer
+    10     opacity logit             opacity = sigmoid(logit)
+    11 + 3k + c   SH coefficient k (k = l*l + l + m) for colour channel c
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+# Seeds fixed by the workload recipes (each a separate stream).
+SEED_GAUSSIANS = 0
+SEED_TARGET_SET = 1
+SEED_POSES = 2
+SEED_VOLUME = 3
+SEED_CAP_SUBSET = 4
+SEED_RESOLUTIONS = 5
+SEED_GAZE = 6
+
+RESOLUTION_CHOICES = [(512, 512), (768, 1024), (1024, 1024), (1536, 1536), (2048, 2048)]
+
+_SH_DC = 0.5 / math.sqrt(math.pi)   # value of the constant (l = 0) basis function
+
+
+def n_sh_coeffs(sh_degree: int) -> int:
+    return (sh_degree + 1) ** 2
+
+
+def n_planes(sh_degree: int) -> int:
+    return 11 + 3 * n_sh_coeffs(sh_degree)
+
+
+def _rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def _f32(x):
+    return np.asarray(x, dtype=np.float32)
+
+
+# --------------------------------------------------------------------------------------
+# Gaussian sets
+# --------------------------------------------------------------------------------------
+
+def random_gaussians(n: int, seed: int = SEED_GAUSSIANS, sh_degree: int = 0,
+                     logscale_mean: float = -3.0, logscale_std: float = 0.5,
+                     mean_range: float = 1.0, sh_rest_std: float = 0.05) -> np.ndarray:
+    """Random Gaussian set, planar float32 ``[C][n]``.
+
+    means ~ U[-r, r]^3, log-scales ~ N(mu, sd^2) per axis, quaternions =
+    normalised N(0, I4) draws (uniform on the unit sphere), opacity logit ~
+    N(0, 1), colour: RGB ~ U[0, 1]^3 stored as degree-0 SH (rgb - 0.5) / Y00,
+    higher SH bands ~ N(0, sh_rest_std^2).
+    """
+    rng = _rng(seed)
+    K = n_sh_coeffs(sh_degree)
+    P = np.zeros((n_planes(sh_degree), n), dtype=np.float64)
+    P[0:3] = rng.uniform(-mean_range, mean_range, size=(3, n))
+    P[3:6] = rng.normal(logscale_mean, logscale_std, size=(3, n))
+    q = rng.normal(size=(4, n))
+    q /= np.linalg.norm(q, axis=0, keepdims=True)
+    P[6:10] = q
+    P[10] = rng.normal(0.0, 1.0, size=n)
+    rgb = rng.uniform(0.0, 1.0, size=(3, n))
+    P[11:14] = (rgb - 0.5) / _SH_DC
+    if K > 1:
+        P[14:11 + 3 * K] = rng.normal(0.0, sh_rest_std, size=(3 * (K - 1), n))
+    return _f32(P)
+
+
+def scaled_logscale_mean(n: int) -> float:
+    """Log-scale mean that keeps world-space overlap equal to the 1k-Gaussian set."""
+    return -3.0 - math.log(n / 1000.0) / 3.0
+
+
+# --------------------------------------------------------------------------------------
+# Cameras (OpenCV axes: x right, y down, z forward; pixel (i, j) centre at (i+.5, j+.5))
+# --------------------------------------------------------------------------------------
+
+@dataclass
+class Camera:
+    R: np.ndarray          # (3, 3) float32, world -> camera rotation
+    t: np.ndarray          # (3,)   float32, world -> camera translation
+    campos: np.ndarray     # (3,)   float32, camera centre in world
+    fx: float
+    fy: float
+    cx: float
+    cy: float
+    tanx: float            # tan of the half field of view along x
+    tany: float
+    width: int
+    height: int
+    znear: float = 0.2
+    bg: np.ndarray = field(default_factory=lambda: np.zeros(3, np.float32))
+
+    def __post_init__(self):
+        self.R = _f32(self.R).reshape(3, 3)
+        self.t = _f32(self.t).reshape(3)
+        self.campos = _f32(self.campos).reshape(3)
+        self.bg = _f32(self.bg).reshape(3)
+        for k in ("fx", "fy", "cx", "cy", "tanx", "tany", "znear"):
+            setattr(self, k, float(np.float32(getattr(self, k))))
+        self.width = int(self.width)
+        self.height = int(self.height)
+
+    @property
+    def npix(self) -> int:
+        return self.width * self.height
+
+
+def _intrinsics(width: int, height: int, fov_x_deg: float):
+    f = (width / 2.0) / math.tan(math.radians(fov_x_deg) / 2.0)
+    f32 = float(np.float32(f))
+    return dict(fx=f32, fy=f32, cx=width / 2.0, cy=height / 2.0,
+                tanx=(width / 2.0) / f32, tany=(height / 2.0) / f32)
+
+
+def axis_camera(width: int = 128, height: int = 128, distance: float = 3.0,
+                fov_x_deg: float = 60.0, bg=(0.0, 0.0, 0.0)) -> Camera:
+    """Camera with identity rotation at (0, 0, -distance), looking at the origin."""
+    return Camera(R=np.eye(3), t=[0.0, 0.0, distance], campos=[0.0, 0.0, -distance],
+                  width=width, height=height, bg=bg, **_intrinsics(width, height, fov_x_deg))
+
+
+def look_at_camera(center, target=(0.0, 0.0, 0.0), width: int = 512, height: int = 512,
+                   fov_x_deg: float = 60.0, bg=(0.0, 0.0, 0.0)) -> Camera:
+    """Pinhole camera at ``center`` looking at ``target``; world up is -y
+    (fallback +z when the view direction is nearly vertical)."""
+    c = np.asarray(center, np.float64)
+    f = np.asarray(target, np.float64) - c
+    f /= np.linalg.norm(f)
+    up = np.array([0.0, -1.0, 0.0])
+    if abs(float(f @ up)) > 0.99:
+        up = np.array([0.0, 0.0, 1.0])
+    x = np.cross(f, up)
+    x /= np.linalg.norm(x)
+    y = np.cross(f, x)
+    R = np.stack([x, y, f])
+    R32 = _f32(R)
+    t = -(R32.astype(np.float64) @ c)
+    return Camera(R=R32, t=t, campos=c, width=width, height=height, bg=bg,
+                  **_intrinsics(width, height, fov_x_deg))
+
+
+def sphere_directions(count: int, seed: int = SEED_POSES) -> np.ndarray:
+    d = _rng(seed).normal(size=(count, 3))
+    return d / np.linalg.norm(d, axis=1, keepdims=True)
+
+
+def sphere_cameras(resolutions, radius: float = 3.0, seed: int = SEED_POSES,
+                   fov_x_deg: float = 60.0):
+    dirs = sphere_directions(len(resolutions), seed)
+    return [look_at_camera(radius * d, width=w, height=h, fov_x_deg=fov_x_deg)
+            for d, (w, h) in zip(dirs, resolutions)]
+
+
+def draw_resolutions(count: int, seed: int = SEED_RESOLUTIONS):
+    idx = _rng(seed).integers(0, len(RESOLUTION_CHOICES), size=count)
+    return [RESOLUTION_CHOICES[i] for i in idx]
+
+
+def stereo_cameras(width: int = 2064, height: int = 2208, radius: float = 3.0,
+                   baseline: float = 0.064, seed: int = SEED_POSES, fov_x_deg: float = 60.0):
+    """Two eyes at +-baseline/2 along the head camera's x axis, parallel axes."""
+    head = look_at_camera(radius * sphere_directions(1, seed)[0], width=width,
+                          height=height, fov_x_deg=fov_x_deg)
+    cams = []
+    for s in (-0.5, 0.5):
+        c = head.campos.astype(np.float64) + s * baseline * head.R[0].astype(np.float64)
+        t = -(head.R.astype(np.float64) @ c)
+        cams.append(Camera(R=head.R, t=t, campos=c, width=width, height=height,
+                           **_intrinsics(width, height, fov_x_deg)))
+    return cams
+
+
+def gaze_points(cams, seed: int = SEED_GAZE) -> np.ndarray:
+    rng = _rng(seed)
+    g = [(rng.uniform(0.2 * c.width, 0.8 * c.width), rng.uniform(0.2 * c.height, 0.8 * c.height))
+         for c in cams]
+    return _f32(g)
+
+
+# --------------------------------------------------------------------------------------
+# CT-like phantom, voxel seeding, linear transfer function
+# --------------------------------------------------------------------------------------
+
+TF_LO = np.array([0.8, 0.3, 0.2])
+TF_HI = np.array([1.0, 0.95, 0.9])
+TF_THRESHOLD = 1200.0
+TF_RANGE = 1800.0
+EXTINCTION = 40.0     # per world unit at full transfer-function density
+
+
+def voxel_centres(n: int) -> np.ndarray:
+    return (np.arange(n) + 0.5) * (2.0 / n) - 1.0
+
+
+def _haar_rotation(rng: np.random.Generator) -> np.ndarray:
+    a = rng.normal(size=(3, 3))
+    q, r = np.linalg.qr(a)
+    q = q * np.sign(np.diag(r))
+    if np.linalg.det(q) < 0:
+        q[:, 0] = -q[:, 0]
+    return q
+
+
+def phantom(n: int = 128, seed: int = SEED_VOLUME, n_ellipsoids: int = 20,
+            noise_sigma: float = 20.0) -> np.ndarray:
+    """uint16 volume ``vol[ix, iy, iz]`` spanning [-1, 1]^3 (voxel centres at
+    (idx + 1/2) * 2/n - 1): a sum of random rotated ellipsoids adding
+    U[400, 1600] inside each, plus N(0, sigma^2) noise, clipped to [0, 3000]."""
+    rng = _rng(seed)
+    c = voxel_centres(n)
+    X, Y, Z = np.meshgrid(c, c, c, indexing="ij")
+    pts = np.stack([X, Y, Z], axis=-1).reshape(-1, 3)
+    vol = np.zeros(pts.shape[0], np.float64)
+    for _ in range(n_ellipsoids):
+        ctr = rng.uniform(-0.6, 0.6, size=3)
+        axes = rng.uniform(0.1, 0.5, size=3)
+        rot = _haar_rotation(rng)
+        val = rng.uniform(400.0, 1600.0)
+        local = (pts - ctr) @ rot          # coordinates in the ellipsoid frame
+        inside = np.sum((local / axes) ** 2, axis=1) <= 1.0
+        vol[inside] += val
+    vol += rng.normal(0.0, noise_sigma, size=vol.shape)
+    vol = np.clip(vol, 0.0, 3000.0)
+    return np.rint(vol).astype(np.uint16).reshape(n, n, n)
+
+
+def tf_density(v):
+    return np.clip((np.asarray(v, np.float64) - TF_THRESHOLD) / TF_RANGE, 0.0, 1.0)
+
+
+def tf_colour(t):
+    t = np.asarray(t, np.float64)[..., None]
+    return TF_LO * (1.0 - t) + TF_HI * t
+
+
+def seed_from_volume(vol: np.ndarray, threshold: float = TF_THRESHOLD, cap: int = 50_000,
+                     seed: int = SEED_CAP_SUBSET, opacity: float = 0.1) -> np.ndarray:
+    """One Gaussian per voxel above ``threshold`` (raster order), capped by a
+    seeded uniform subset without replacement (kept in raster order).  Mean at
+    the voxel centre, isotropic scale of one voxel, identity rotation, the
+    given initial opacity and the transfer-function colour as degree-0 SH."""
+    n = vol.shape[0]
+    flat = vol.reshape(-1)
+    idx = np.nonzero(flat > threshold)[0]
+    if idx.size > cap:
+        pick = _rng(seed).choice(idx.size, size=cap, replace=False)
+        idx = idx[np.sort(pick)]
+    ix, iy, iz = np.unravel_index(idx, vol.shape)
+    c = voxel_centres(n)
+    m = idx.size
+    P = np.zeros((n_planes(0), m), np.float64)
+    P[0], P[1], P[2] = c[ix], c[iy], c[iz]
+    P[3:6] = math.log(2.0 / n)
+    P[6] = 1.0
+    P[10] = math.log(opacity / (1.0 - opacity))
+    col = tf_colour(tf_density(flat[idx]))
+    P[11:14] = ((col - 0.5) / _SH_DC).T
+    return _f32(P)
+
+
+# --------------------------------------------------------------------------------------
+# Emission-absorption ray march (target images)
+# --------------------------------------------------------------------------------------
+
+def trilinear_sampler(vol: np.ndarray):
+    """Sampler returning (density t in [0,1], rgb) at world points, trilinear in
+    the raw values with zero outside the grid."""
+    n = vol.shape[0]
+    v = vol.astype(np.float64)
+
+    def sample(p):
+        u = (p + 1.0) * (n / 2.0) - 0.5
+        i0 = np.floor(u).astype(np.int64)
+        f = u - i0
+        acc = np.zeros(p.shape[0])
+        for dx in (0, 1):
+            for dy in (0, 1):
+                for dz in (0, 1):
+                    ix, iy, iz = i0[:, 0] + dx, i0[:, 1] + dy, i0[:, 2] + dz
+                    w = ((f[:, 0] if dx else 1 - f[:, 0]) * (f[:, 1] if dy else 1 - f[:, 1])
+                         * (f[:, 2] if dz else 1 - f[:, 2]))
+                    ok = (ix >= 0) & (ix < n) & (iy >= 0) & (iy < n) & (iz >= 0) & (iz < n)
+                    val = np.zeros(p.shape[0])
+                    val[ok] = v[ix[ok], iy[ok], iz[ok]]
+                    acc += w * val
+        t = tf_density(acc)
+        return t, tf_colour(t)
+
+    return sample
+
+
+def raymarch(sampler, cam: Camera, step: float, extinction: float = EXTINCTION,
+             t_stop: float = 1e-4, rows=None, chunk: int = 1 << 17) -> np.ndarray:
+    """Front-to-back emission-absorption march through the box [-1, 1]^3.
+
+    Segments of length ``step`` from the box entry point, the last one
+    shortened to end at the exit point; each segment takes the sample at its
+    midpoint, alpha = 1 - exp(-extinction * t * length).  Stops once the
+    transmittance falls below ``t_stop``.  Returns float32 RGBA ``[4][H][W]``
+    (or ``[4][len(rows)][W]`` for a row subset) with RGB = C + T * bg and
+    A = 1 - T.
+    """
+    W, H = cam.width, cam.height
+    rows = np.arange(H) if rows is None else np.asarray(rows)
+    jj, ii = np.meshgrid(rows, np.arange(W), indexing="ij")
+    dc = np.stack([(ii + 0.5 - cam.cx) / cam.fx, (jj + 0.5 - cam.cy) / cam.fy,
+                   np.ones_like(ii, dtype=np.float64)], axis=-1).reshape(-1, 3)
+    R = cam.R.astype(np.float64)
+    d = dc @ R                                  # R^T d_cam for each row vector
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    o = cam.campos.astype(np.float64)
+    npx = d.shape[0]
+    out_c = np.zeros((npx, 3))
+    out_T = np.ones(npx)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        inv = 1.0 / d
+        ta = (-1.0 - o) * inv
+        tb = (1.0 - o) * inv
+    t0 = np.max(np.minimum(ta, tb), axis=1)
+    t1 = np.min(np.maximum(ta, tb), axis=1)
+    t0 = np.maximum(t0, 0.0)
+    hit = np.nonzero(t1 > t0)[0]
+    for s in range(0, hit.size, chunk):
+        ids = hit[s:s + chunk]
+        a, b = t0[ids], t1[ids]
+        dd = d[ids]
+        C = np.zeros((ids.size, 3))
+        T = np.ones(ids.size)
+        act = np.arange(ids.size)
+        k = 0
+        while act.size:
+            seg0 = a[act] + k * step
+            seg1 = np.minimum(seg0 + step, b[act])
+            live = seg1 > seg0
+            act, seg0, seg1 = act[live], seg0[live], seg1[live]
+            if not act.size:
+                break
+            mid = 0.5 * (seg0 + seg1)
+            p = o + dd[act] * mid[:, None]
+            dens, col = sampler(p)
+            alpha = 1.0 - np.exp(-extinction * dens * (seg1 - seg0))
+            C[act] += col * (alpha * T[act])[:, None]
+            T[act] *= 1.0 - alpha
+            act = act[T[act] >= t_stop]
+            k += 1
+        out_c[ids] = C
+        out_T[ids] = T
+    rgb = out_c + out_T[:, None] * cam.bg.astype(np.float64)[None, :]
+    img = np.concatenate([rgb, (1.0 - out_T)[:, None]], axis=1).T
+    return _f32(img.reshape(4, rows.size, W))
+
+
+def raymarch_volume(vol: np.ndarray, cam: Camera, rows=None) -> np.ndarray:
+    """Target image of the phantom with half-voxel steps."""
+    return raymarch(trilinear_sampler(vol), cam, step=1.0 / vol.shape[0], rows=rows)
