@@ -1,0 +1,216 @@
+/*
+ * gsfit.h - C ABI of the MI355X (gfx950) differentiable Gaussian-splatting fit path.
+ *
+ * The paper (arXiv 2601.22026, Method section, "Periphery Model Training")
+ * fits its peripheral model of anatomy by optimising 3D Gaussians against posed
+ * renderings with a 3D Gaussian Splatting rasterizer and Adam; its continual
+ * refinement restarts the optimiser with reloaded Gaussians and discarded
+ * optimiser state.  This library implements that fit step on one GPU:
+ *
+ *   gsf_forward   Gaussians + cameras -> RGBA images        (projection, key
+ *                 duplication, (tile, depth) sort, per-tile front-to-back
+ *                 alpha compositing)
+ *   gsf_loss_l1   images + targets -> mean L1 loss, dL/dRGBA (optional circular
+ *                 fovea mask per view)
+ *   gsf_backward  dL/dRGBA -> dL/d(parameters)              (adjoint of the above)
+ *   gsf_adam      bias-corrected Adam with per-segment learning rates
+ *   gsf_step_*    the four calls above as one captured HIP graph
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Every pointer is DEVICE memory unless its comment says (host).  The caller
+ *   owns all device buffers (parameters, gradients, optimiser state, images,
+ *   targets, cameras, workspace).  The library owns only the opaque host-side
+ *   context and plan objects and the graphs it instantiates.
+ * - Every call is asynchronous on the context's stream, except gsf_poll,
+ *   gsf_debug_copy and (for plans created with host_sized = 1) gsf_forward,
+ *   which synchronise that stream.
+ * - Errors: every call returns a gsf_status; no exception crosses the ABI.
+ *   Argument errors are detected on the host before anything is enqueued.
+ *   Conditions detected on the device (key overflow, non-finite loss) set sticky
+ *   flags read by gsf_poll.  gsf_last_error() returns a context-owned message
+ *   valid until the next call on that context.
+ * - Parameters: planar float32 [C][n], C = 11 + 3K, K = (sh_degree + 1)^2:
+ *     planes 0..2 mean xyz, 3..5 log-scale xyz, 6..9 rotation quaternion
+ *     (w, x, y, z; normalised inside), 10 opacity logit, 11 + 3k + c SH
+ *     coefficient k (k = l*l + l + m) of colour channel c.
+ *   Gradients use the same layout.
+ * - Images: per view planar float32 [4][H][W] (R, G, B, A), views concatenated
+ *   in plan order.  Targets: per view [3][H][W], concatenated likewise.
+ * - Cameras: a device array of gsf_camera, one per view, in plan order.  They
+ *   live in device memory so captured graphs see updated poses.
+ * - Pixel (i, j) has its centre at (i + 0.5, j + 0.5); camera axes are x right,
+ *   y down, z forward.
+ */
+#ifndef GSFIT_H
+#define GSFIT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GSF_OK = 0,
+    GSF_E_INVALID = 1,     /* bad argument (null pointer, size out of range, bad option) */
+    GSF_E_CAPACITY = 2,    /* key count exceeded the plan's key capacity */
+    GSF_E_HIP = 3,         /* a HIP runtime call failed; see gsf_last_error */
+    GSF_E_STATE = 4,       /* call out of order (no workspace, no forward, no graph) */
+    GSF_E_NONFINITE = 5,   /* non-finite loss detected */
+    GSF_E_UNSUPPORTED = 6  /* option not supported by this build */
+} gsf_status;
+
+/* sticky device flags reported by gsf_poll */
+#define GSF_FLAG_CAPACITY 1u
+#define GSF_FLAG_NONFINITE 2u
+
+typedef struct gsf_ctx gsf_ctx;
+typedef struct gsf_plan gsf_plan;
+
+/* One pinhole camera (128 bytes). */
+typedef struct gsf_camera {
+    float viewmat[12];          /* world -> camera [R | t], row-major 3x4 */
+    float campos[3];            /* camera centre in world (SH view direction) */
+    float fx, fy, cx, cy;       /* focal lengths and principal point, pixels */
+    float tan_half_fov_x;       /* half-FOV tangents: the projection Jacobian is */
+    float tan_half_fov_y;       /*   evaluated at x/z clamped to +-1.3 of these  */
+    float znear;                /* Gaussians with camera depth <= znear are culled */
+    float bg[3];                /* background colour composited behind the Gaussians */
+    int32_t width, height;      /* image size, pixels (1 .. 8192) */
+    int32_t reserved[5];        /* must be zero */
+} gsf_camera;
+
+/* Plan description: everything that fixes workspace sizes and launch shapes. */
+typedef struct gsf_plan_desc {
+    int64_t n_max;              /* maximum Gaussian count per call (>= 1) */
+    int32_t sh_degree;          /* 0 .. 3 */
+    int32_t n_views;            /* 1 .. 64 */
+    const int32_t *widths;      /* (host) [n_views] */
+    const int32_t *heights;     /* (host) [n_views] */
+    int32_t tile;               /* tile edge in pixels: 8, 16 or 32 */
+    int32_t lds_batch;          /* Gaussians staged in LDS per batch: 64, 128 or 256 */
+    int32_t t_mode;             /* backward transmittance: 0 recompute from the final
+                                   transmittance, 1 stored per (key, pixel) */
+    int32_t host_sized;         /* 1: gsf_forward reads the key count back to the host
+                                   and sizes the sort from it (plain path);
+                                   0: the count stays on the device (capturable) */
+    int64_t key_capacity;       /* maximum (tile, Gaussian) keys; 0 = 32 per record + 2^20 */
+} gsf_plan_desc;
+
+/* ---- context ---------------------------------------------------------------- */
+
+/* Create a context on HIP device `device` that enqueues on `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  Returns GSF_E_HIP if the device
+ * cannot be selected. */
+gsf_status gsf_ctx_create(int device, void *hip_stream, gsf_ctx **out);
+gsf_status gsf_ctx_destroy(gsf_ctx *ctx);
+/* Change the stream later calls enqueue on. */
+gsf_status gsf_ctx_set_stream(gsf_ctx *ctx, void *hip_stream);
+/* Last error message of this context (context-owned, never NULL). */
+const char *gsf_last_error(const gsf_ctx *ctx);
+
+/* ---- plans --------------------------------------------------------------------- */
+
+/* Validate `desc` and create a plan.  Widths/heights are copied. */
+gsf_status gsf_plan_create(gsf_ctx *ctx, const gsf_plan_desc *desc, gsf_plan **out);
+/* Bytes of device workspace the plan needs (written to *bytes, host). */
+gsf_status gsf_plan_workspace_bytes(const gsf_plan *plan, size_t *bytes);
+/* Bind caller-owned device workspace of at least gsf_plan_workspace_bytes bytes,
+ * 256-byte aligned.  The state saved by gsf_forward for gsf_backward lives here
+ * and stays valid until the next gsf_forward on the same plan. */
+gsf_status gsf_plan_bind_workspace(gsf_plan *plan, void *dev, size_t bytes);
+/* Totals of the plan (host): tiles over all views, pixels over all views. */
+gsf_status gsf_plan_info(const gsf_plan *plan, int64_t *total_tiles, int64_t *total_pixels);
+gsf_status gsf_plan_destroy(gsf_plan *plan);
+
+/* ---- the fit step --------------------------------------------------------------- */
+
+/* Render all views of the plan.  params: [C][n] (1 <= n <= n_max); cams:
+ * [n_views]; out_rgba: concatenated per-view [4][H][W].  With host_sized = 1
+ * this synchronises the stream once and returns GSF_E_CAPACITY if the key count
+ * exceeded the capacity (the image is then background only). */
+gsf_status gsf_forward(gsf_plan *plan, const float *params, int64_t n, const gsf_camera *cams,
+                       float *out_rgba);
+
+/* Mean absolute error over the masked (view, pixel, RGB channel) entries of
+ * `rgba` against `target_rgb` (concatenated per-view [3][H][W]).  gaze_px:
+ * nullable device [n_views][2] pixel coordinates; when given, only pixels whose
+ * centre lies within mask_radius_frac * width of the gaze point count.  Writes
+ * the loss to loss[0] (device) and dL/dRGBA (sign / count; alpha plane zero) to
+ * dl_drgba (concatenated per-view [4][H][W]).  A non-finite loss sets
+ * GSF_FLAG_NONFINITE. */
+gsf_status gsf_loss_l1(gsf_plan *plan, const float *rgba, const float *target_rgb,
+                       const float *gaze_px, float mask_radius_frac, float *loss,
+                       float *dl_drgba);
+
+/* Gradient of the loss w.r.t. the parameters given dL/dRGBA of the last
+ * gsf_forward on this plan (same params, n and cams).  grads: [C][n], overwritten. */
+gsf_status gsf_backward(gsf_plan *plan, const float *params, int64_t n, const gsf_camera *cams,
+                        const float *dl_drgba, float *grads);
+
+/* One Adam step on n_elems float32 elements: m <- b1 m + (1-b1) g,
+ * v <- b2 v + (1-b2) g^2, p <- p - lr m_hat / (sqrt(v_hat) + eps), with bias
+ * correction by the step number held in step_dev[0] (device int32), which this
+ * call increments first.  Element e uses seg_lr[s] for seg_off[s] <= e <
+ * seg_off[s+1] (host arrays, n_seg in 1..16, seg_off[0] = 0,
+ * seg_off[n_seg] = n_elems).  Resetting m, v and step_dev to zero restarts the
+ * optimiser (continual refinement by restart). */
+gsf_status gsf_adam(gsf_ctx *ctx, float *p, const float *g, float *m, float *v, int64_t n_elems,
+                    const int64_t *seg_off, const float *seg_lr, int32_t n_seg, float beta1,
+                    float beta2, float eps, int32_t *step_dev);
+
+/* Arguments of one full step: forward, loss, backward, Adam on the parameters. */
+typedef struct gsf_step_args {
+    float *params;              /* [C][n]; updated in place by Adam */
+    int64_t n;
+    const gsf_camera *cams;
+    const float *target_rgb;
+    const float *gaze_px;       /* nullable */
+    float mask_radius_frac;
+    float *loss;                /* [1] */
+    float *rgba;                /* image buffer */
+    float *dl_drgba;            /* image-sized gradient buffer */
+    float *grads;               /* [C][n] */
+    float *adam_m, *adam_v;     /* [C][n] each */
+    int32_t *step_dev;          /* [1] */
+    const float *seg_lr;        /* (host) [11 + 3K]: learning rate per parameter plane */
+    float beta1, beta2, eps;
+} gsf_step_args;
+
+/* Enqueue one step eagerly. */
+gsf_status gsf_step(gsf_plan *plan, const gsf_step_args *args);
+/* Capture one step into a HIP graph owned by the plan (replaces any previous
+ * one).  Needs host_sized = 0.  Nothing runs during capture. */
+gsf_status gsf_step_capture(gsf_plan *plan, const gsf_step_args *args);
+/* Launch the captured graph once on the context stream. */
+gsf_status gsf_step_replay(gsf_plan *plan);
+
+/* ---- diagnostics ---------------------------------------------------------------- */
+
+/* Synchronise the stream, return and clear the sticky flags (host *flags), and
+ * report the key count of the last forward (host *m_keys, may be NULL). */
+gsf_status gsf_poll(gsf_plan *plan, uint32_t *flags, int64_t *m_keys);
+
+enum {
+    GSF_DBG_RECT = 0,      /* uint32[2] per record (v*n + i): tile x0 | y0 << 16, x1 | y1 << 16 */
+    GSF_DBG_COUNT = 1,     /* uint32 per record: tiles touched (0 = culled or empty) */
+    GSF_DBG_DEPTH = 2,     /* float per record: camera-space depth */
+    GSF_DBG_KEYS = 3,      /* uint32 per key: global tile id, sorted */
+    GSF_DBG_VALS = 4,      /* uint32 per key: record id, in sorted key order */
+    GSF_DBG_RANGES = 5,    /* uint32[2] per global tile: [start, end) */
+    GSF_DBG_TFINAL = 6,    /* float per pixel (all views concatenated) */
+    GSF_DBG_NCONTRIB = 7,  /* uint32 per pixel: list entries up to the last included */
+    GSF_DBG_G2D = 8,       /* float [9][n_views * n]: per-record screen-space gradient */
+    GSF_DBG_PROJ = 9       /* float [11] per record: mean x, mean y, conic A, B, C, opacity,
+                              red, green, blue, camera depth, valid (1 or 0) */
+};
+/* Synchronise and copy an internal buffer of the last forward/backward to host
+ * memory (at most cap bytes; bytes copied in *written). */
+gsf_status gsf_debug_copy(gsf_plan *plan, int which, void *host_dst, size_t cap, size_t *written);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GSFIT_H */

@@ -1,0 +1,349 @@
+"""MI355X (gfx950) differentiable Gaussian-splatting fit path - Python binding.
+
+The compute path is the HIP library ``libgsfit.so`` behind the C ABI in
+``include/gsfit.h``; this module only marshals arguments (PyTorch supplies
+device memory and streams).  The C functions are re-exported under their own
+names by ``paper_2601_22026_amd._abi``; the classes here wrap them:
+
+* ``Context``   - device + stream (``gsf_ctx_*``)
+* ``Plan``      - view sizes, SH degree, tile/batch, key capacity and the
+                  caller-owned workspace (``gsf_plan_*``)
+* ``rasterize`` - ``torch.autograd.Function`` around ``gsf_forward`` /
+                  ``gsf_backward``
+* ``adam``      - ``gsf_adam`` on a flat parameter buffer
+* ``FitStep``   - one forward + L1 loss + backward + Adam step, either fused
+                  over all views and captured in a HIP graph, or plain (one
+                  host-synchronised plan per view, eager launches)
+"""
+from __future__ import annotations
+
+import ctypes as ct
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _abi
+from ._abi import GsfError, gsf_camera, gsf_plan_desc, gsf_step_args, lib
+
+__all__ = ["GsfError", "Context", "Plan", "rasterize", "adam", "FitStep", "pack_cameras",
+           "cameras_to_device", "n_planes", "lib"]
+
+
+def n_planes(sh_degree: int) -> int:
+    return 11 + 3 * (sh_degree + 1) ** 2
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise GsfError(_abi.GSF_E_INVALID, "tensor must live on the GPU")
+    return ct.c_void_p(t.data_ptr())
+
+
+def _stream_ptr(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ct.c_void_p(s.cuda_stream)
+
+
+def pack_cameras(cams) -> bytes:
+    """gsf_camera records of camera objects with attributes R (3x3), t (3),
+    campos (3), fx, fy, cx, cy, tanx, tany, znear, bg (3), width, height."""
+    arr = (gsf_camera * len(cams))()
+    for k, c in enumerate(cams):
+        R = np.asarray(c.R, np.float32).reshape(3, 3)
+        t = np.asarray(c.t, np.float32).reshape(3)
+        vm = np.concatenate([R, t[:, None]], axis=1).reshape(-1)
+        arr[k].viewmat[:] = [float(x) for x in vm]
+        arr[k].campos[:] = [float(x) for x in np.asarray(c.campos, np.float32)]
+        arr[k].fx, arr[k].fy, arr[k].cx, arr[k].cy = c.fx, c.fy, c.cx, c.cy
+        arr[k].tan_half_fov_x, arr[k].tan_half_fov_y = c.tanx, c.tany
+        arr[k].znear = c.znear
+        arr[k].bg[:] = [float(x) for x in np.asarray(c.bg, np.float32)]
+        arr[k].width, arr[k].height = int(c.width), int(c.height)
+    return bytes(arr)
+
+
+def cameras_to_device(cams, device="cuda") -> torch.Tensor:
+    raw = np.frombuffer(pack_cameras(cams), dtype=np.uint8).copy()
+    return torch.from_numpy(raw).to(device)
+
+
+class Context:
+    """A device and the stream calls are enqueued on (default: torch's current stream)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        self.device = device
+        h = ct.c_void_p()
+        st = lib().gsf_ctx_create(device, _stream_ptr(stream), ct.byref(h))
+        if st != 0:
+            raise GsfError(st, f"gsf_ctx_create(device={device}) failed")
+        self.handle = h
+
+    def check(self, status: int, what: str = ""):
+        if status != 0:
+            msg = lib().gsf_last_error(self.handle).decode()
+            raise GsfError(status, f"{what}: {msg}" if what else msg)
+
+    def use_stream(self, stream=None):
+        self.check(lib().gsf_ctx_set_stream(self.handle, _stream_ptr(stream)), "gsf_ctx_set_stream")
+
+    def close(self):
+        if self.handle:
+            lib().gsf_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Plan:
+    """Plan over fixed view sizes with its own device workspace."""
+
+    def __init__(self, ctx: Context, n_max: int, sizes: Sequence[tuple], sh_degree: int = 0,
+                 tile: int = 16, lds_batch: int = 128, host_sized: bool = False,
+                 key_capacity: int = 0, t_mode: int = 0):
+        self.ctx = ctx
+        self.sizes = [(int(w), int(h)) for w, h in sizes]
+        self.n_max, self.sh_degree, self.tile, self.lds_batch = n_max, sh_degree, tile, lds_batch
+        self.host_sized = bool(host_sized)
+        V = len(self.sizes)
+        self._w = (ct.c_int32 * V)(*[w for w, _ in self.sizes])
+        self._h = (ct.c_int32 * V)(*[h for _, h in self.sizes])
+        d = gsf_plan_desc(n_max=n_max, sh_degree=sh_degree, n_views=V,
+                          widths=ct.cast(self._w, ct.POINTER(ct.c_int32)),
+                          heights=ct.cast(self._h, ct.POINTER(ct.c_int32)), tile=tile,
+                          lds_batch=lds_batch, t_mode=t_mode, host_sized=int(host_sized),
+                          key_capacity=int(key_capacity))
+        h = ct.c_void_p()
+        ctx.check(lib().gsf_plan_create(ctx.handle, ct.byref(d), ct.byref(h)), "gsf_plan_create")
+        self.handle = h
+        nb = ct.c_size_t()
+        ctx.check(lib().gsf_plan_workspace_bytes(h, ct.byref(nb)), "gsf_plan_workspace_bytes")
+        self.workspace = torch.empty(max(int(nb.value), 256), dtype=torch.uint8,
+                                     device=f"cuda:{ctx.device}")
+        ctx.use_stream()
+        ctx.check(lib().gsf_plan_bind_workspace(h, _ptr(self.workspace), nb.value),
+                  "gsf_plan_bind_workspace")
+        tt, tp = ct.c_int64(), ct.c_int64()
+        lib().gsf_plan_info(h, ct.byref(tt), ct.byref(tp))
+        self.total_tiles, self.total_pixels = tt.value, tp.value
+
+    # -- raw calls (tensors in, status checked) ------------------------------------
+    def forward(self, params, n, cams_dev, out_rgba):
+        self.ctx.use_stream()
+        self.ctx.check(lib().gsf_forward(self.handle, _ptr(params), int(n), _ptr(cams_dev),
+                                         _ptr(out_rgba)), "gsf_forward")
+
+    def loss_l1(self, rgba, target, loss, dl, gaze=None, radius_frac=0.0):
+        self.ctx.use_stream()
+        self.ctx.check(lib().gsf_loss_l1(self.handle, _ptr(rgba), _ptr(target), _ptr(gaze),
+                                         float(radius_frac), _ptr(loss), _ptr(dl)), "gsf_loss_l1")
+
+    def backward(self, params, n, cams_dev, dl, grads):
+        self.ctx.use_stream()
+        self.ctx.check(lib().gsf_backward(self.handle, _ptr(params), int(n), _ptr(cams_dev),
+                                          _ptr(dl), _ptr(grads)), "gsf_backward")
+
+    def poll(self):
+        f, m = ct.c_uint32(), ct.c_int64()
+        self.ctx.use_stream()
+        self.ctx.check(lib().gsf_poll(self.handle, ct.byref(f), ct.byref(m)), "gsf_poll")
+        return int(f.value), int(m.value)
+
+    def debug(self, which: int, dtype, count: int) -> np.ndarray:
+        out = np.zeros(max(count, 1), dtype=dtype)
+        written = ct.c_size_t()
+        self.ctx.use_stream()
+        self.ctx.check(lib().gsf_debug_copy(self.handle, which, out.ctypes.data_as(ct.c_void_p),
+                                            out.nbytes, ct.byref(written)), "gsf_debug_copy")
+        return out[: written.value // out.itemsize]
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().gsf_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class _Rasterize(torch.autograd.Function):
+    @staticmethod
+    def forward(fctx, params, plan, cams_dev):
+        params = params.contiguous()
+        n = params.shape[1]
+        out = torch.empty(4 * plan.total_pixels, dtype=torch.float32, device=params.device)
+        plan.forward(params, n, cams_dev, out)
+        fctx.plan, fctx.cams = plan, cams_dev
+        fctx.save_for_backward(params)
+        return out
+
+    @staticmethod
+    def backward(fctx, grad_out):
+        (params,) = fctx.saved_tensors
+        grads = torch.empty_like(params)
+        fctx.plan.backward(params, params.shape[1], fctx.cams, grad_out.contiguous(), grads)
+        return grads, None, None
+
+
+def rasterize(params: torch.Tensor, plan: Plan, cams_dev: torch.Tensor) -> torch.Tensor:
+    """Concatenated per-view [4][H][W] images of planar float32 params [C][n].
+    Differentiable w.r.t. params (gsf_backward).  The state the backward needs
+    lives in the plan, so use one plan per forward in flight."""
+    return _Rasterize.apply(params, plan, cams_dev)
+
+
+def adam(ctx: Context, p, g, m, v, step_dev, seg_off, seg_lr, betas=(0.9, 0.999), eps=1e-15):
+    """gsf_adam over flat float32 buffers with per-segment learning rates."""
+    so = (ct.c_int64 * len(seg_off))(*[int(x) for x in seg_off])
+    sl = (ct.c_float * len(seg_lr))(*[float(x) for x in seg_lr])
+    ctx.use_stream()
+    ctx.check(lib().gsf_adam(ctx.handle, _ptr(p), _ptr(g), _ptr(m), _ptr(v), int(p.numel()), so, sl,
+                             len(seg_lr), float(betas[0]), float(betas[1]), float(eps),
+                             _ptr(step_dev)), "gsf_adam")
+
+
+@dataclass
+class FitConfig:
+    lr: float | Sequence[float] = 1e-3
+    betas: tuple = (0.9, 0.999)
+    eps: float = 1e-15
+    tile: int = 16
+    lds_batch: int = 128
+    radius_frac: float = 0.2
+    key_capacity: int = 0
+
+
+class FitStep:
+    """One fit step (forward, L1 loss, backward, Adam) over all views.
+
+    fused=True: one plan over all views (one launch per stage), key count kept
+    on the device, and ``capture()`` records the whole step in a HIP graph that
+    ``replay()`` launches.  fused=False: the plain path - one host-synchronised
+    plan per view, eager launches, views one after another (the loss of each
+    view is normalised by that view's own masked count).
+    """
+
+    def __init__(self, ctx: Context, params: torch.Tensor, cams, targets: torch.Tensor,
+                 gaze: Optional[torch.Tensor] = None, cfg: FitConfig = FitConfig(),
+                 fused: bool = True):
+        self.ctx, self.cfg, self.fused = ctx, cfg, fused
+        self.params = params
+        self.C, self.n = params.shape
+        self.sh_degree = int(round(((self.C - 11) // 3) ** 0.5)) - 1
+        dev = params.device
+        self.cams = list(cams)
+        self.sizes = [(c.width, c.height) for c in self.cams]
+        self.cams_dev = cameras_to_device(self.cams, dev)
+        self.targets = targets.contiguous()
+        self.gaze = gaze
+        total = sum(w * h for w, h in self.sizes)
+        self.rgba = torch.zeros(4 * total, dtype=torch.float32, device=dev)
+        self.dl = torch.zeros_like(self.rgba)
+        self.grads = torch.zeros_like(params)
+        self.m = torch.zeros_like(params)
+        self.v = torch.zeros_like(params)
+        self.step_dev = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=dev)
+        lr = cfg.lr if isinstance(cfg.lr, (list, tuple)) else [cfg.lr] * self.C
+        self._seg_lr = (ct.c_float * self.C)(*[float(x) for x in lr])
+        if fused:
+            cap = cfg.key_capacity or self._measure_capacity()
+            self.plan = Plan(ctx, self.n, self.sizes, self.sh_degree, cfg.tile, cfg.lds_batch,
+                             host_sized=False, key_capacity=cap)
+            self.args = self._args(self.plan, self.cams_dev, self.targets, self.rgba, self.dl,
+                                   self.gaze)
+        else:
+            self.view_plans = []
+            off = 0
+            for k, (w, h) in enumerate(self.sizes):
+                p = Plan(ctx, self.n, [(w, h)], self.sh_degree, cfg.tile, cfg.lds_batch,
+                         host_sized=True, key_capacity=cfg.key_capacity)
+                sl = slice(off, off + w * h)
+                self.view_plans.append((p, self.cams_dev[128 * k:128 * (k + 1)], sl))
+                off += w * h
+            self.view_grads = torch.zeros_like(params)
+        self.captured = False
+
+    def _measure_capacity(self) -> int:
+        probe = Plan(self.ctx, self.n, self.sizes, self.sh_degree, self.cfg.tile,
+                     self.cfg.lds_batch, host_sized=True, key_capacity=self.cfg.key_capacity)
+        probe.forward(self.params, self.n, self.cams_dev, self.rgba)
+        _, m = probe.poll()
+        probe.close()
+        return int(m * 1.5) + (1 << 16)
+
+    def _args(self, plan, cams_dev, targets, rgba, dl, gaze):
+        return gsf_step_args(
+            params=self.params.data_ptr(), n=self.n, cams=cams_dev.data_ptr(),
+            target_rgb=targets.data_ptr(), gaze_px=gaze.data_ptr() if gaze is not None else None,
+            mask_radius_frac=self.cfg.radius_frac, loss=self.loss.data_ptr(),
+            rgba=rgba.data_ptr(), dl_drgba=dl.data_ptr(), grads=self.grads.data_ptr(),
+            adam_m=self.m.data_ptr(), adam_v=self.v.data_ptr(), step_dev=self.step_dev.data_ptr(),
+            seg_lr=ct.cast(self._seg_lr, ct.POINTER(ct.c_float)), beta1=self.cfg.betas[0],
+            beta2=self.cfg.betas[1], eps=self.cfg.eps)
+
+    def step(self):
+        """One eager step."""
+        self.ctx.use_stream()
+        if self.fused:
+            self.ctx.check(lib().gsf_step(self.plan.handle, ct.byref(self.args)), "gsf_step")
+            return
+        # plain: per view forward + loss + backward, gradients summed, then Adam
+        for k, (p, cam, sl) in enumerate(self.view_plans):
+            rgba = self.rgba[4 * sl.start:4 * sl.stop]
+            dl = self.dl[4 * sl.start:4 * sl.stop]
+            tgt = self.targets[3 * sl.start:3 * sl.stop]
+            gz = self.gaze[k] if self.gaze is not None else None
+            p.forward(self.params, self.n, cam, rgba)
+            p.loss_l1(rgba, tgt, self.loss, dl, gz, self.cfg.radius_frac)
+            p.backward(self.params, self.n, cam, dl, self.grads if k == 0 else self.view_grads)
+            if k > 0:
+                self.grads += self.view_grads
+        seg_off = [c * self.n for c in range(self.C + 1)]
+        lr = list(self._seg_lr)
+        so, sl_ = [0], [lr[0]]
+        for c in range(1, self.C):
+            if lr[c] != sl_[-1]:
+                so.append(seg_off[c])
+                sl_.append(lr[c])
+        so.append(seg_off[self.C])
+        adam(self.ctx, self.params, self.grads, self.m, self.v, self.step_dev, so, sl_,
+             self.cfg.betas, self.cfg.eps)
+
+    def capture(self):
+        if not self.fused:
+            raise GsfError(_abi.GSF_E_STATE, "only the fused step can be captured")
+        self.ctx.use_stream()
+        self.ctx.check(lib().gsf_step_capture(self.plan.handle, ct.byref(self.args)),
+                       "gsf_step_capture")
+        self.captured = True
+
+    def replay(self):
+        self.ctx.use_stream()
+        self.ctx.check(lib().gsf_step_replay(self.plan.handle), "gsf_step_replay")
+
+    def reset_optimizer(self):
+        """Continual refinement restarts Adam: zero m, v and the step counter."""
+        self.m.zero_()
+        self.v.zero_()
+        self.step_dev.zero_()
+
+    def poll(self):
+        if self.fused:
+            return self.plan.poll()
+        flags, m = 0, 0
+        for p, _, _ in self.view_plans:
+            f, mm = p.poll()
+            flags |= f
+            m += mm
+        return flags, m

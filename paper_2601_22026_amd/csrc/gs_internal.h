@@ -1,0 +1,116 @@
+// gs_internal.h - internal types, constants and launchers of the gfx950 fit path.
+// Not part of the ABI (see include/gsfit.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gsfit.h"
+
+namespace gsf {
+
+// Compositing constants of the 3DGS forward model the paper builds on (Related
+// Work "Novel View Synthesis"; Method "Periphery Model Training").
+constexpr float kAlphaMin = 1.0f / 255.0f;   // contributions below are skipped
+constexpr float kAlphaMax = 0.99f;           // alpha clamp
+constexpr float kTStop = 1e-4f;              // stop before T would fall below this
+constexpr float kLowPass = 0.3f;             // px^2 added to the 2D covariance diagonal
+constexpr float kJClamp = 1.3f;              // Jacobian evaluated at x/z within 1.3 tan(fov/2)
+constexpr float kBoxRel = 1e-4f;             // support-box padding, relative
+constexpr float kBoxAbs = 1.0f / 64.0f;      // support-box padding, pixels
+
+constexpr int kMaxViews = 64;
+constexpr int kMaxSeg = 16;
+constexpr int kSortBlock = 256;              // threads per radix-sort block (4 waves)
+constexpr int kSortIpt = 8;                  // keys per thread per tile
+constexpr int kSortTile = kSortBlock * kSortIpt;
+constexpr int kSortMaxGrid = 1024;
+constexpr int kScanBlock = 256;
+constexpr int kScanIpt = 8;
+constexpr int kScanTile = kScanBlock * kScanIpt;
+
+// Per-view launch descriptor (device copy made at plan creation).
+struct ViewDesc {
+    int32_t tile_off;   // first global tile id of the view
+    int32_t tiles_x;
+    int32_t tiles_y;
+    int32_t pix_off;    // first global pixel of the view (images are concatenated)
+    int32_t width;
+    int32_t height;
+    int32_t pad0, pad1;
+};
+
+// Per-record screen-space splat, split so that one gather is two 16-byte and
+// one 4-byte load: a = (mean x, mean y, conic A, conic B), b = (conic C,
+// opacity, red, green), c = blue.
+struct SplatPtrs {
+    float4 *a;
+    float4 *b;
+    float *c;
+};
+
+struct SegTable {
+    int64_t off[kMaxSeg + 1];
+    float lr[kMaxSeg];
+    int32_t n;
+};
+
+// ---- launchers (all asynchronous on `s`) -----------------------------------------
+
+// Projection of n Gaussians into V views: records r = v*n + i.
+void launch_project_fwd(hipStream_t s, const float *P, int n, int nviews, int deg,
+                        const gsf_camera *cams, const ViewDesc *views, int tile, SplatPtrs sp,
+                        uint32_t *depth_key, uint32_t *rec_idx, uint2 *rect, uint32_t *count);
+
+// Parameter gradient from the per-record screen-space gradient g2d [9][V*n].
+void launch_project_bwd(hipStream_t s, const float *P, int n, int nviews, int deg,
+                        const gsf_camera *cams, const float *g2d, float *grads);
+
+// Stable radix sort of (key, value) pairs by their `bits` low key bits.  The
+// count comes from n_dev (device) when non-null, else n_host.  Pass 0 reads
+// (kin, vin) and writes (ka, va); later passes alternate between (ka, va) and
+// (kb, vb), which may alias (kin, vin).  Returns 0 if the result is in
+// (kin, vin) (no pass), 1 for (ka, va), 2 for (kb, vb).
+int launch_radix_sort(hipStream_t s, const uint32_t *kin, const uint32_t *vin, uint32_t *ka,
+                      uint32_t *va, uint32_t *kb, uint32_t *vb, const uint32_t *n_dev,
+                      uint32_t n_host, int bits, int grid, uint32_t *hist, uint32_t *digit_tot);
+int radix_grid_for(int64_t capacity);
+
+// Exclusive scan of count[order[j]] (j < nrec) and duplication of one key per
+// touched tile: keys = global tile id, vals = record id, in depth order.
+// Writes the key count to m_dev (0 and GSF_FLAG_CAPACITY on overflow) and the
+// unclamped total to m_total.
+void launch_scan_duplicate(hipStream_t s, const uint32_t *order, const uint32_t *count,
+                           const uint2 *rect, int nrec, int n, const ViewDesc *views, int nviews,
+                           uint32_t *block_sums, uint32_t *keys, uint32_t *vals, uint32_t *m_dev,
+                           unsigned long long *m_total, uint32_t *flags, int64_t capacity);
+
+// [start, end) of every global tile in the sorted keys.
+void launch_tile_ranges(hipStream_t s, const uint32_t *keys, const uint32_t *m_dev,
+                        uint32_t m_host, int total_tiles, uint2 *ranges);
+
+// Front-to-back compositing of all tiles of all views.
+void launch_render_fwd(hipStream_t s, int tile, int batch, int total_tiles, const uint2 *ranges,
+                       const uint32_t *vals, SplatPtrs sp, const ViewDesc *views, int nviews,
+                       const gsf_camera *cams, float *out_rgba, float *tfinal, uint32_t *ncontrib);
+
+// Back-to-front adjoint of the compositing: accumulates g2d [9][nrec].
+void launch_render_bwd(hipStream_t s, int tile, int batch, int total_tiles, const uint2 *ranges,
+                       const uint32_t *vals, SplatPtrs sp, const ViewDesc *views, int nviews,
+                       const gsf_camera *cams, const float *tfinal, const uint32_t *ncontrib,
+                       const float *dl_drgba, float *g2d, int nrec);
+
+// Masked L1 loss.  partial: scratch of loss_partials(total_pix) floats.
+int loss_partials(int64_t total_pix);
+void launch_loss_l1(hipStream_t s, const float *rgba, const float *target, const float *gaze,
+                    float radius_frac, const ViewDesc *views, int nviews, int64_t total_pix,
+                    float *dl, float *partial, uint32_t *mask_count, float *loss,
+                    uint32_t *flags);
+
+void launch_adam(hipStream_t s, float *p, const float *g, float *m, float *v, int64_t n,
+                 const SegTable &seg, float b1, float b2, float eps, int32_t *step);
+
+void launch_fill_u32(hipStream_t s, uint32_t *p, int64_t n, uint32_t value);
+void launch_fill_f32(hipStream_t s, float *p, int64_t n, float value);
+
+}  // namespace gsf

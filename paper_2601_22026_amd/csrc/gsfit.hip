@@ -1,0 +1,582 @@
+// gsfit.hip - host runtime and C ABI (include/gsfit.h) of the gfx950 fit path.
+//
+// A context pins a device and a stream.  A plan fixes the view sizes, SH
+// degree, tile size, LDS batch and key capacity, carves the caller-owned
+// workspace into the buffers of the pipeline and enqueues the kernels:
+//
+//   forward   project -> depth radix sort -> scan + duplicate -> tile radix sort
+//             -> tile ranges -> composite
+//   loss      masked L1 -> dL/dRGBA
+//   backward  zero screen-space gradient -> composite adjoint -> projection adjoint
+//   adam      step counter + update
+//
+// All views of a plan share one launch per stage: their tiles form one global
+// tile space (per-view offsets) and their records one record space r = v*n + i.
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "gs_internal.h"
+
+using namespace gsf;
+
+struct gsf_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+};
+
+namespace {
+
+struct Buffers {
+    float4 *rec_a = nullptr, *rec_b = nullptr;
+    float *rec_c = nullptr;
+    uint32_t *depth_key = nullptr, *rec_idx = nullptr;   // unsorted, per record
+    uint32_t *dk[2] = {nullptr, nullptr}, *di[2] = {nullptr, nullptr};  // depth sort ping-pong
+    uint2 *rect = nullptr;
+    uint32_t *count = nullptr;
+    uint32_t *block_sums = nullptr;
+    uint32_t *keys[2] = {nullptr, nullptr}, *vals[2] = {nullptr, nullptr};
+    uint2 *ranges = nullptr;
+    float *tfinal = nullptr;
+    uint32_t *ncontrib = nullptr;
+    float *g2d = nullptr;
+    uint32_t *hist = nullptr, *digit_tot = nullptr;
+    uint32_t *m_dev = nullptr, *flags = nullptr, *mask_count = nullptr;
+    unsigned long long *m_total = nullptr;
+    float *loss_partial = nullptr;
+    ViewDesc *views = nullptr;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+struct gsf_plan {
+    gsf_ctx *ctx = nullptr;
+    int64_t n_max = 0;
+    int deg = 0, V = 0, tile = 16, batch = 128, t_mode = 0, host_sized = 0;
+    int64_t cap = 0;
+    std::vector<ViewDesc> views;
+    int64_t total_tiles = 0, total_pix = 0, nrec_max = 0;
+    int tile_bits = 0, grid_depth = 1, grid_tile = 1;
+    size_t ws_bytes = 0;
+    void *ws = nullptr;
+    Buffers b;
+    bool have_forward = false;
+    int64_t fwd_n = 0;
+    uint32_t *order = nullptr, *keys_sorted = nullptr, *vals_sorted = nullptr;
+    unsigned long long *pinned = nullptr;     // host-pinned readback of the key count
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+gsf_status fail(gsf_ctx *ctx, gsf_status st, const std::string &msg) {
+    if (ctx) ctx->err = msg;
+    return st;
+}
+
+#define GSF_HIP(ctx, expr)                                                                   \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail((ctx), GSF_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define GSF_LAUNCHED(ctx)                                                                    \
+    do {                                                                                     \
+        hipError_t e_ = hipGetLastError();                                                   \
+        if (e_ != hipSuccess)                                                                \
+            return fail((ctx), GSF_E_HIP, std::string("kernel launch: ") + hipGetErrorString(e_)); \
+    } while (0)
+
+int planes_of(int deg) { return 11 + 3 * (deg + 1) * (deg + 1); }
+
+// Carve the workspace (base == nullptr: only measure).  Returns the byte count.
+size_t carve(gsf_plan *p, char *base, Buffers *out) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char * {
+        char *ptr = base ? base + off : nullptr;
+        off += align256(bytes);
+        return ptr;
+    };
+    const size_t R = (size_t)p->nrec_max;
+    Buffers b;
+    b.rec_a = (float4 *)take(R * sizeof(float4));
+    b.rec_b = (float4 *)take(R * sizeof(float4));
+    b.rec_c = (float *)take(R * sizeof(float));
+    b.depth_key = (uint32_t *)take(R * 4);
+    b.rec_idx = (uint32_t *)take(R * 4);
+    for (int k = 0; k < 2; k++) {
+        b.dk[k] = (uint32_t *)take(R * 4);
+        b.di[k] = (uint32_t *)take(R * 4);
+    }
+    b.rect = (uint2 *)take(R * sizeof(uint2));
+    b.count = (uint32_t *)take(R * 4);
+    b.block_sums = (uint32_t *)take(((R + kScanTile - 1) / kScanTile + 1) * 4);
+    for (int k = 0; k < 2; k++) {
+        b.keys[k] = (uint32_t *)take((size_t)p->cap * 4);
+        b.vals[k] = (uint32_t *)take((size_t)p->cap * 4);
+    }
+    b.ranges = (uint2 *)take((size_t)p->total_tiles * sizeof(uint2));
+    b.tfinal = (float *)take((size_t)p->total_pix * 4);
+    b.ncontrib = (uint32_t *)take((size_t)p->total_pix * 4);
+    b.g2d = (float *)take(9 * R * 4);
+    b.hist = (uint32_t *)take((size_t)256 * kSortMaxGrid * 4);
+    b.digit_tot = (uint32_t *)take(256 * 4);
+    b.m_dev = (uint32_t *)take(4);
+    b.flags = (uint32_t *)take(4);
+    b.mask_count = (uint32_t *)take(4);
+    b.m_total = (unsigned long long *)take(8);
+    b.loss_partial = (float *)take((size_t)loss_partials(p->total_pix) * 4);
+    b.views = (ViewDesc *)take(p->views.size() * sizeof(ViewDesc));
+    if (out) *out = b;
+    return off;
+}
+
+gsf_status check_ready(gsf_plan *p) {
+    if (!p) return GSF_E_INVALID;
+    if (!p->ws) return fail(p->ctx, GSF_E_STATE, "no workspace bound to the plan");
+    return GSF_OK;
+}
+
+SplatPtrs splats(gsf_plan *p) { return SplatPtrs{p->b.rec_a, p->b.rec_b, p->b.rec_c}; }
+
+gsf_status enqueue_forward(gsf_plan *p, const float *params, int64_t n, const gsf_camera *cams,
+                           float *out_rgba, bool *overflow) {
+    gsf_ctx *ctx = p->ctx;
+    hipStream_t s = ctx->stream;
+    Buffers &b = p->b;
+    const int nrec = (int)(n * p->V);
+    *overflow = false;
+    launch_project_fwd(s, params, (int)n, p->V, p->deg, cams, b.views, p->tile, splats(p),
+                       b.depth_key, b.rec_idx, b.rect, b.count);
+    GSF_LAUNCHED(ctx);
+    // records in (depth, record) order
+    const int where = launch_radix_sort(s, b.depth_key, b.rec_idx, b.dk[0], b.di[0], b.dk[1],
+                                        b.di[1], nullptr, (uint32_t)nrec, 32, p->grid_depth,
+                                        b.hist, b.digit_tot);
+    GSF_LAUNCHED(ctx);
+    p->order = where == 0 ? b.rec_idx : b.di[where - 1];
+    launch_scan_duplicate(s, p->order, b.count, b.rect, nrec, (int)n, b.views, p->V, b.block_sums,
+                          b.keys[0], b.vals[0], b.m_dev, b.m_total, b.flags, p->cap);
+    GSF_LAUNCHED(ctx);
+    int tw;
+    if (p->host_sized) {
+        GSF_HIP(ctx, hipMemcpyAsync(p->pinned, b.m_total, 8, hipMemcpyDeviceToHost, s));
+        GSF_HIP(ctx, hipStreamSynchronize(s));
+        const unsigned long long total = *p->pinned;
+        const uint32_t m = total > (unsigned long long)p->cap ? 0u : (uint32_t)total;
+        *overflow = total > (unsigned long long)p->cap;
+        tw = launch_radix_sort(s, b.keys[0], b.vals[0], b.keys[1], b.vals[1], b.keys[0], b.vals[0],
+                               nullptr, m, p->tile_bits, radix_grid_for(m), b.hist, b.digit_tot);
+        GSF_LAUNCHED(ctx);
+        p->keys_sorted = tw == 1 ? b.keys[1] : b.keys[0];
+        p->vals_sorted = tw == 1 ? b.vals[1] : b.vals[0];
+        launch_tile_ranges(s, p->keys_sorted, nullptr, m, (int)p->total_tiles, b.ranges);
+    } else {
+        tw = launch_radix_sort(s, b.keys[0], b.vals[0], b.keys[1], b.vals[1], b.keys[0], b.vals[0],
+                               b.m_dev, 0u, p->tile_bits, p->grid_tile, b.hist, b.digit_tot);
+        GSF_LAUNCHED(ctx);
+        p->keys_sorted = tw == 1 ? b.keys[1] : b.keys[0];
+        p->vals_sorted = tw == 1 ? b.vals[1] : b.vals[0];
+        launch_tile_ranges(s, p->keys_sorted, b.m_dev, 0u, (int)p->total_tiles, b.ranges);
+    }
+    GSF_LAUNCHED(ctx);
+    launch_render_fwd(s, p->tile, p->batch, (int)p->total_tiles, b.ranges, p->vals_sorted,
+                      splats(p), b.views, p->V, cams, out_rgba, b.tfinal, b.ncontrib);
+    GSF_LAUNCHED(ctx);
+    p->have_forward = true;
+    p->fwd_n = n;
+    return GSF_OK;
+}
+
+gsf_status enqueue_loss(gsf_plan *p, const float *rgba, const float *target, const float *gaze,
+                        float radius_frac, float *loss, float *dl) {
+    launch_loss_l1(p->ctx->stream, rgba, target, gaze, radius_frac, p->b.views, p->V,
+                   p->total_pix, dl, p->b.loss_partial, p->b.mask_count, loss, p->b.flags);
+    GSF_LAUNCHED(p->ctx);
+    return GSF_OK;
+}
+
+gsf_status enqueue_backward(gsf_plan *p, const float *params, int64_t n, const gsf_camera *cams,
+                            const float *dl, float *grads) {
+    hipStream_t s = p->ctx->stream;
+    const int64_t nrec = n * p->V;
+    launch_fill_f32(s, p->b.g2d, 9 * nrec, 0.f);
+    launch_render_bwd(s, p->tile, p->batch, (int)p->total_tiles, p->b.ranges, p->vals_sorted,
+                      splats(p), p->b.views, p->V, cams, p->b.tfinal, p->b.ncontrib, dl, p->b.g2d,
+                      (int)nrec);
+    GSF_LAUNCHED(p->ctx);
+    launch_project_bwd(s, params, (int)n, p->V, p->deg, cams, p->b.g2d, grads);
+    GSF_LAUNCHED(p->ctx);
+    return GSF_OK;
+}
+
+bool aligned16(const void *ptr) { return ((uintptr_t)ptr & 15u) == 0; }
+
+gsf_status make_segments(gsf_ctx *ctx, int64_t n_elems, const int64_t *seg_off, const float *seg_lr,
+                         int32_t n_seg, SegTable *seg) {
+    if (!seg_off || !seg_lr || n_seg < 1 || n_seg > kMaxSeg)
+        return fail(ctx, GSF_E_INVALID, "gsf_adam: need 1..16 segments with host offsets and rates");
+    if (seg_off[0] != 0 || seg_off[n_seg] != n_elems)
+        return fail(ctx, GSF_E_INVALID, "gsf_adam: segments must start at 0 and end at n_elems");
+    std::memset(seg, 0, sizeof *seg);
+    for (int s = 0; s < n_seg; s++) {
+        if (seg_off[s + 1] < seg_off[s])
+            return fail(ctx, GSF_E_INVALID, "gsf_adam: segment offsets must be non-decreasing");
+        seg->off[s] = seg_off[s];
+        seg->lr[s] = seg_lr[s];
+    }
+    seg->off[n_seg] = seg_off[n_seg];
+    seg->n = n_seg;
+    return GSF_OK;
+}
+
+gsf_status check_step(gsf_plan *p, const gsf_step_args *a) {
+    if (!a || !a->params || !a->cams || !a->target_rgb || !a->loss || !a->rgba || !a->dl_drgba ||
+        !a->grads || !a->adam_m || !a->adam_v || !a->step_dev || !a->seg_lr)
+        return fail(p->ctx, GSF_E_INVALID, "gsf_step: null argument");
+    if (a->n < 1 || a->n > p->n_max) return fail(p->ctx, GSF_E_INVALID, "gsf_step: n out of range");
+    if (!aligned16(a->params) || !aligned16(a->grads) || !aligned16(a->adam_m) || !aligned16(a->adam_v))
+        return fail(p->ctx, GSF_E_INVALID, "gsf_step: parameter buffers must be 16-byte aligned");
+    return GSF_OK;
+}
+
+gsf_status enqueue_step(gsf_plan *p, const gsf_step_args *a) {
+    bool overflow = false;
+    gsf_status st = enqueue_forward(p, a->params, a->n, a->cams, a->rgba, &overflow);
+    if (st != GSF_OK) return st;
+    st = enqueue_loss(p, a->rgba, a->target_rgb, a->gaze_px, a->mask_radius_frac, a->loss, a->dl_drgba);
+    if (st != GSF_OK) return st;
+    st = enqueue_backward(p, a->params, a->n, a->cams, a->dl_drgba, a->grads);
+    if (st != GSF_OK) return st;
+    const int C = planes_of(p->deg);
+    std::vector<int64_t> off(C + 1);
+    for (int c = 0; c <= C; c++) off[c] = (int64_t)c * a->n;
+    // merge equal neighbouring planes into segments (at most 16)
+    std::vector<int64_t> so{0};
+    std::vector<float> sl{a->seg_lr[0]};
+    for (int c = 1; c < C; c++) {
+        if (a->seg_lr[c] != sl.back()) {
+            so.push_back(off[c]);
+            sl.push_back(a->seg_lr[c]);
+        }
+    }
+    so.push_back(off[C]);
+    SegTable seg;
+    st = make_segments(p->ctx, off[C], so.data(), sl.data(), (int32_t)sl.size(), &seg);
+    if (st != GSF_OK) return st;
+    launch_adam(p->ctx->stream, a->params, a->grads, a->adam_m, a->adam_v, off[C], seg, a->beta1,
+                a->beta2, a->eps, a->step_dev);
+    GSF_LAUNCHED(p->ctx);
+    return overflow ? fail(p->ctx, GSF_E_CAPACITY, "key capacity exceeded") : GSF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gsf_status gsf_ctx_create(int device, void *hip_stream, gsf_ctx **out) {
+    if (!out) return GSF_E_INVALID;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return GSF_E_HIP;
+    if (hipSetDevice(device) != hipSuccess) return GSF_E_HIP;
+    gsf_ctx *c = new (std::nothrow) gsf_ctx;
+    if (!c) return GSF_E_INVALID;
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    *out = c;
+    return GSF_OK;
+}
+
+gsf_status gsf_ctx_destroy(gsf_ctx *ctx) {
+    delete ctx;
+    return GSF_OK;
+}
+
+gsf_status gsf_ctx_set_stream(gsf_ctx *ctx, void *hip_stream) {
+    if (!ctx) return GSF_E_INVALID;
+    ctx->stream = (hipStream_t)hip_stream;
+    return GSF_OK;
+}
+
+const char *gsf_last_error(const gsf_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+gsf_status gsf_plan_create(gsf_ctx *ctx, const gsf_plan_desc *d, gsf_plan **out) {
+    if (!ctx || !d || !out) return fail(ctx, GSF_E_INVALID, "gsf_plan_create: null argument");
+    *out = nullptr;
+    if (d->n_max < 1) return fail(ctx, GSF_E_INVALID, "n_max must be >= 1");
+    if (d->sh_degree < 0 || d->sh_degree > 3) return fail(ctx, GSF_E_INVALID, "sh_degree must be 0..3");
+    if (d->n_views < 1 || d->n_views > kMaxViews) return fail(ctx, GSF_E_INVALID, "n_views must be 1..64");
+    if (!d->widths || !d->heights) return fail(ctx, GSF_E_INVALID, "widths/heights are null");
+    if (d->tile != 8 && d->tile != 16 && d->tile != 32) return fail(ctx, GSF_E_INVALID, "tile must be 8, 16 or 32");
+    if (d->lds_batch != 64 && d->lds_batch != 128 && d->lds_batch != 256)
+        return fail(ctx, GSF_E_INVALID, "lds_batch must be 64, 128 or 256");
+    if (d->t_mode != 0) return fail(ctx, GSF_E_UNSUPPORTED, "only t_mode 0 (recompute) is built");
+    if (d->host_sized != 0 && d->host_sized != 1) return fail(ctx, GSF_E_INVALID, "host_sized must be 0 or 1");
+    if (d->key_capacity < 0 || d->key_capacity > 0xF0000000ll)
+        return fail(ctx, GSF_E_INVALID, "key_capacity out of range");
+    const int64_t nrec = d->n_max * d->n_views;
+    if (nrec > 0x7FFFFFFFll) return fail(ctx, GSF_E_INVALID, "n_max * n_views must fit in 31 bits");
+    gsf_plan *p = new (std::nothrow) gsf_plan;
+    if (!p) return fail(ctx, GSF_E_INVALID, "out of host memory");
+    p->ctx = ctx;
+    p->n_max = d->n_max;
+    p->deg = d->sh_degree;
+    p->V = d->n_views;
+    p->tile = d->tile;
+    p->batch = d->lds_batch;
+    p->t_mode = d->t_mode;
+    p->host_sized = d->host_sized;
+    p->nrec_max = nrec;
+    int64_t toff = 0, poff = 0;
+    for (int v = 0; v < p->V; v++) {
+        const int W = d->widths[v], H = d->heights[v];
+        if (W < 1 || H < 1 || W > 8192 || H > 8192) {
+            delete p;
+            return fail(ctx, GSF_E_INVALID, "view sizes must be 1..8192");
+        }
+        ViewDesc vd{};
+        vd.tile_off = (int32_t)toff;
+        vd.tiles_x = (W + p->tile - 1) / p->tile;
+        vd.tiles_y = (H + p->tile - 1) / p->tile;
+        vd.pix_off = (int32_t)poff;
+        vd.width = W;
+        vd.height = H;
+        p->views.push_back(vd);
+        toff += (int64_t)vd.tiles_x * vd.tiles_y;
+        poff += (int64_t)W * H;
+    }
+    if (poff > 0x7FFFFFFFll) {
+        delete p;
+        return fail(ctx, GSF_E_INVALID, "total pixels must fit in 31 bits");
+    }
+    p->total_tiles = toff;
+    p->total_pix = poff;
+    p->cap = d->key_capacity > 0 ? d->key_capacity : 32 * nrec + (1 << 20);
+    if (p->cap > 0xF0000000ll) p->cap = 0xF0000000ll;
+    p->tile_bits = 0;
+    while ((int64_t(1) << p->tile_bits) < p->total_tiles) p->tile_bits++;
+    p->grid_depth = radix_grid_for(nrec);
+    p->grid_tile = radix_grid_for(p->cap);
+    p->ws_bytes = carve(p, nullptr, nullptr);
+    if (hipHostMalloc((void **)&p->pinned, sizeof(unsigned long long)) != hipSuccess) {
+        delete p;
+        return fail(ctx, GSF_E_HIP, "hipHostMalloc failed");
+    }
+    *out = p;
+    return GSF_OK;
+}
+
+gsf_status gsf_plan_workspace_bytes(const gsf_plan *p, size_t *bytes) {
+    if (!p || !bytes) return GSF_E_INVALID;
+    *bytes = p->ws_bytes;
+    return GSF_OK;
+}
+
+gsf_status gsf_plan_info(const gsf_plan *p, int64_t *total_tiles, int64_t *total_pixels) {
+    if (!p) return GSF_E_INVALID;
+    if (total_tiles) *total_tiles = p->total_tiles;
+    if (total_pixels) *total_pixels = p->total_pix;
+    return GSF_OK;
+}
+
+gsf_status gsf_plan_bind_workspace(gsf_plan *p, void *dev, size_t bytes) {
+    if (!p || !dev) return fail(p ? p->ctx : nullptr, GSF_E_INVALID, "gsf_plan_bind_workspace: null");
+    if (bytes < p->ws_bytes) return fail(p->ctx, GSF_E_INVALID, "workspace too small");
+    if (((uintptr_t)dev & 255u) != 0) return fail(p->ctx, GSF_E_INVALID, "workspace must be 256-byte aligned");
+    p->ws = dev;
+    carve(p, (char *)dev, &p->b);
+    p->have_forward = false;
+    GSF_HIP(p->ctx, hipMemcpyAsync(p->b.views, p->views.data(), p->views.size() * sizeof(ViewDesc),
+                                   hipMemcpyHostToDevice, p->ctx->stream));
+    launch_fill_u32(p->ctx->stream, p->b.flags, 1, 0u);
+    launch_fill_u32(p->ctx->stream, p->b.m_dev, 1, 0u);
+    GSF_LAUNCHED(p->ctx);
+    GSF_HIP(p->ctx, hipStreamSynchronize(p->ctx->stream));
+    return GSF_OK;
+}
+
+gsf_status gsf_plan_destroy(gsf_plan *p) {
+    if (!p) return GSF_OK;
+    if (p->exec) hipGraphExecDestroy(p->exec);
+    if (p->graph) hipGraphDestroy(p->graph);
+    if (p->pinned) hipHostFree(p->pinned);
+    delete p;
+    return GSF_OK;
+}
+
+gsf_status gsf_forward(gsf_plan *p, const float *params, int64_t n, const gsf_camera *cams,
+                       float *out_rgba) {
+    gsf_status st = check_ready(p);
+    if (st != GSF_OK) return st;
+    if (!params || !cams || !out_rgba) return fail(p->ctx, GSF_E_INVALID, "gsf_forward: null argument");
+    if (n < 1 || n > p->n_max) return fail(p->ctx, GSF_E_INVALID, "gsf_forward: n out of range");
+    bool overflow = false;
+    st = enqueue_forward(p, params, n, cams, out_rgba, &overflow);
+    if (st != GSF_OK) return st;
+    return overflow ? fail(p->ctx, GSF_E_CAPACITY, "key capacity exceeded") : GSF_OK;
+}
+
+gsf_status gsf_loss_l1(gsf_plan *p, const float *rgba, const float *target_rgb, const float *gaze_px,
+                       float mask_radius_frac, float *loss, float *dl_drgba) {
+    gsf_status st = check_ready(p);
+    if (st != GSF_OK) return st;
+    if (!rgba || !target_rgb || !loss || !dl_drgba) return fail(p->ctx, GSF_E_INVALID, "gsf_loss_l1: null argument");
+    if (gaze_px && !(mask_radius_frac >= 0.f)) return fail(p->ctx, GSF_E_INVALID, "gsf_loss_l1: bad radius");
+    return enqueue_loss(p, rgba, target_rgb, gaze_px, mask_radius_frac, loss, dl_drgba);
+}
+
+gsf_status gsf_backward(gsf_plan *p, const float *params, int64_t n, const gsf_camera *cams,
+                        const float *dl_drgba, float *grads) {
+    gsf_status st = check_ready(p);
+    if (st != GSF_OK) return st;
+    if (!params || !cams || !dl_drgba || !grads) return fail(p->ctx, GSF_E_INVALID, "gsf_backward: null argument");
+    if (!p->have_forward) return fail(p->ctx, GSF_E_STATE, "gsf_backward before gsf_forward");
+    if (n != p->fwd_n) return fail(p->ctx, GSF_E_INVALID, "gsf_backward: n differs from the forward");
+    return enqueue_backward(p, params, n, cams, dl_drgba, grads);
+}
+
+gsf_status gsf_adam(gsf_ctx *ctx, float *prm, const float *g, float *m, float *v, int64_t n_elems,
+                    const int64_t *seg_off, const float *seg_lr, int32_t n_seg, float beta1,
+                    float beta2, float eps, int32_t *step_dev) {
+    if (!ctx) return GSF_E_INVALID;
+    if (!prm || !g || !m || !v || !step_dev || n_elems < 1)
+        return fail(ctx, GSF_E_INVALID, "gsf_adam: null argument or empty");
+    if (!aligned16(prm) || !aligned16(g) || !aligned16(m) || !aligned16(v))
+        return fail(ctx, GSF_E_INVALID, "gsf_adam: buffers must be 16-byte aligned");
+    SegTable seg;
+    gsf_status st = make_segments(ctx, n_elems, seg_off, seg_lr, n_seg, &seg);
+    if (st != GSF_OK) return st;
+    launch_adam(ctx->stream, prm, g, m, v, n_elems, seg, beta1, beta2, eps, step_dev);
+    GSF_LAUNCHED(ctx);
+    return GSF_OK;
+}
+
+gsf_status gsf_step(gsf_plan *p, const gsf_step_args *a) {
+    gsf_status st = check_ready(p);
+    if (st != GSF_OK) return st;
+    st = check_step(p, a);
+    if (st != GSF_OK) return st;
+    return enqueue_step(p, a);
+}
+
+gsf_status gsf_step_capture(gsf_plan *p, const gsf_step_args *a) {
+    gsf_status st = check_ready(p);
+    if (st != GSF_OK) return st;
+    if (p->host_sized) return fail(p->ctx, GSF_E_STATE, "capture needs a plan with host_sized = 0");
+    if (!p->ctx->stream) return fail(p->ctx, GSF_E_STATE, "capture needs a non-null stream");
+    st = check_step(p, a);
+    if (st != GSF_OK) return st;
+    if (p->exec) {
+        hipGraphExecDestroy(p->exec);
+        p->exec = nullptr;
+    }
+    if (p->graph) {
+        hipGraphDestroy(p->graph);
+        p->graph = nullptr;
+    }
+    GSF_HIP(p->ctx, hipStreamBeginCapture(p->ctx->stream, hipStreamCaptureModeThreadLocal));
+    gsf_status est = enqueue_step(p, a);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(p->ctx->stream, &g);
+    if (est != GSF_OK) {
+        if (g) hipGraphDestroy(g);
+        return est;
+    }
+    if (e != hipSuccess) return fail(p->ctx, GSF_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    p->graph = g;
+    GSF_HIP(p->ctx, hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
+    return GSF_OK;
+}
+
+gsf_status gsf_step_replay(gsf_plan *p) {
+    if (!p) return GSF_E_INVALID;
+    if (!p->exec) return fail(p->ctx, GSF_E_STATE, "no captured step");
+    GSF_HIP(p->ctx, hipGraphLaunch(p->exec, p->ctx->stream));
+    return GSF_OK;
+}
+
+gsf_status gsf_poll(gsf_plan *p, uint32_t *flags, int64_t *m_keys) {
+    gsf_status st = check_ready(p);
+    if (st != GSF_OK) return st;
+    if (!flags) return fail(p->ctx, GSF_E_INVALID, "gsf_poll: null flags");
+    hipStream_t s = p->ctx->stream;
+    uint32_t f = 0;
+    unsigned long long m = 0;
+    GSF_HIP(p->ctx, hipStreamSynchronize(s));
+    GSF_HIP(p->ctx, hipMemcpy(&f, p->b.flags, 4, hipMemcpyDeviceToHost));
+    GSF_HIP(p->ctx, hipMemcpy(&m, p->b.m_total, 8, hipMemcpyDeviceToHost));
+    launch_fill_u32(s, p->b.flags, 1, 0u);
+    GSF_LAUNCHED(p->ctx);
+    GSF_HIP(p->ctx, hipStreamSynchronize(s));
+    *flags = f;
+    if (m_keys) *m_keys = (int64_t)m;
+    return GSF_OK;
+}
+
+gsf_status gsf_debug_copy(gsf_plan *p, int which, void *host_dst, size_t cap, size_t *written) {
+    gsf_status st = check_ready(p);
+    if (st != GSF_OK) return st;
+    if (!host_dst || !written) return fail(p->ctx, GSF_E_INVALID, "gsf_debug_copy: null argument");
+    GSF_HIP(p->ctx, hipStreamSynchronize(p->ctx->stream));
+    const size_t R = (size_t)(p->fwd_n * p->V);
+    unsigned long long mt = 0;
+    uint32_t md = 0;
+    GSF_HIP(p->ctx, hipMemcpy(&mt, p->b.m_total, 8, hipMemcpyDeviceToHost));
+    GSF_HIP(p->ctx, hipMemcpy(&md, p->b.m_dev, 4, hipMemcpyDeviceToHost));
+    const size_t M = p->host_sized ? (mt > (unsigned long long)p->cap ? 0 : (size_t)mt) : md;
+    const void *src = nullptr;
+    size_t bytes = 0;
+    std::vector<float> proj;
+    switch (which) {
+    case GSF_DBG_RECT: src = p->b.rect; bytes = R * 8; break;
+    case GSF_DBG_COUNT: src = p->b.count; bytes = R * 4; break;
+    case GSF_DBG_DEPTH: src = p->b.depth_key; bytes = R * 4; break;
+    case GSF_DBG_KEYS: src = p->keys_sorted; bytes = M * 4; break;
+    case GSF_DBG_VALS: src = p->vals_sorted; bytes = M * 4; break;
+    case GSF_DBG_RANGES: src = p->b.ranges; bytes = (size_t)p->total_tiles * 8; break;
+    case GSF_DBG_TFINAL: src = p->b.tfinal; bytes = (size_t)p->total_pix * 4; break;
+    case GSF_DBG_NCONTRIB: src = p->b.ncontrib; bytes = (size_t)p->total_pix * 4; break;
+    case GSF_DBG_G2D: src = p->b.g2d; bytes = 9 * R * 4; break;
+    case GSF_DBG_PROJ: {
+        std::vector<float4> a(R), b(R);
+        std::vector<float> c(R);
+        std::vector<uint32_t> dk(R);
+        if (R) {
+            GSF_HIP(p->ctx, hipMemcpy(a.data(), p->b.rec_a, R * 16, hipMemcpyDeviceToHost));
+            GSF_HIP(p->ctx, hipMemcpy(b.data(), p->b.rec_b, R * 16, hipMemcpyDeviceToHost));
+            GSF_HIP(p->ctx, hipMemcpy(c.data(), p->b.rec_c, R * 4, hipMemcpyDeviceToHost));
+            GSF_HIP(p->ctx, hipMemcpy(dk.data(), p->b.depth_key, R * 4, hipMemcpyDeviceToHost));
+        }
+        proj.resize(R * 11);
+        for (size_t r = 0; r < R; r++) {
+            float *o = proj.data() + 11 * r;
+            const bool valid = dk[r] != 0xFFFFFFFFu;
+            float depth;
+            std::memcpy(&depth, &dk[r], 4);
+            const float vals[11] = {a[r].x, a[r].y, a[r].z, a[r].w, b[r].x, b[r].y, b[r].z, b[r].w,
+                                    c[r], valid ? depth : 0.f, valid ? 1.f : 0.f};
+            std::memcpy(o, vals, sizeof vals);
+        }
+        bytes = proj.size() * 4;
+        if (bytes > cap) return fail(p->ctx, GSF_E_INVALID, "gsf_debug_copy: destination too small");
+        std::memcpy(host_dst, proj.data(), bytes);
+        *written = bytes;
+        return GSF_OK;
+    }
+    default: return fail(p->ctx, GSF_E_INVALID, "gsf_debug_copy: unknown buffer");
+    }
+    if (bytes > cap) return fail(p->ctx, GSF_E_INVALID, "gsf_debug_copy: destination too small");
+    if (bytes) GSF_HIP(p->ctx, hipMemcpy(host_dst, src, bytes, hipMemcpyDeviceToHost));
+    *written = bytes;
+    return GSF_OK;
+}
+
+}  // extern "C"
