@@ -91,8 +91,12 @@ typedef struct gsf_plan_desc {
     const int32_t *heights;     /* (host) [n_views] */
     int32_t tile;               /* tile edge in pixels: 8, 16 or 32 */
     int32_t lds_batch;          /* Gaussians staged in LDS per batch: 64, 128 or 256 */
-    int32_t t_mode;             /* backward transmittance: 0 recompute from the final
-                                   transmittance, 1 stored per (key, pixel) */
+    int32_t t_mode;             /* transmittance in the adjoint: 0 recomputed back to
+                                   front from the final transmittance (8 B/pixel saved,
+                                   one workgroup per tile); 1 checkpointed: the forward
+                                   also stores (T, colour) per pixel at every LDS-batch
+                                   boundary (16 B/pixel/boundary) and the adjoint runs
+                                   one workgroup per (tile, batch) */
     int32_t host_sized;         /* 1: gsf_forward reads the key count back to the host
                                    and sizes the sort from it (plain path);
                                    0: the count stays on the device (capturable) */
@@ -188,6 +192,35 @@ gsf_status gsf_step_capture(gsf_plan *plan, const gsf_step_args *args);
 gsf_status gsf_step_replay(gsf_plan *plan);
 
 /* ---- diagnostics ---------------------------------------------------------------- */
+
+/* Per-stage GPU timing of eager calls on a plan (hipEvents recorded around each
+ * stage on the context stream; not available while capturing).  Enabling
+ * resets the accumulators.  Stages holding exactly one kernel: PROJECT,
+ * RENDER, RENDER_BWD, PROJECT_BWD. */
+enum {
+    GSF_STAGE_PROJECT = 0,     /* projection + support boxes (one kernel) */
+    GSF_STAGE_DEPTH_SORT = 1,  /* radix sort of records by depth */
+    GSF_STAGE_DUPLICATE = 2,   /* scan of tile counts + key duplication */
+    GSF_STAGE_TILE_SORT = 3,   /* radix sort of keys by tile */
+    GSF_STAGE_RANGES = 4,      /* per-tile ranges */
+    GSF_STAGE_RENDER = 5,      /* forward compositing (one kernel) */
+    GSF_STAGE_LOSS = 6,        /* masked L1 loss */
+    GSF_STAGE_RENDER_BWD = 7,  /* compositing adjoint (one kernel) */
+    GSF_STAGE_PROJECT_BWD = 8, /* projection adjoint (one kernel) */
+    GSF_STAGE_ADAM = 9,        /* step counter + Adam (inside gsf_step only) */
+    GSF_STAGE_ZERO = 10,       /* clearing the screen-space gradient */
+    GSF_STAGE_COUNT = 11
+};
+gsf_status gsf_plan_set_timing(gsf_plan *plan, int enable);
+/* Work accounting of the last gsf_forward (synchronises): out[0] = (pixel,
+ * splat) pairs the forward compositing visits (up to and including the splat
+ * that stops a pixel, else the whole tile list), out[1] = pairs included in
+ * the image, out[2] = pairs the adjoint visits (up to each pixel's last
+ * included splat).  Runs an extra counting kernel; not part of the fit step. */
+gsf_status gsf_count_pairs(gsf_plan *plan, int64_t *out /* (host) [3] */);
+/* Synchronise and return the accumulated milliseconds and call counts per
+ * stage (host arrays of GSF_STAGE_COUNT entries; either may be NULL). */
+gsf_status gsf_plan_stage_times(gsf_plan *plan, double *total_ms, int64_t *calls);
 
 /* Synchronise the stream, return and clear the sticky flags (host *flags), and
  * report the key count of the last forward (host *m_keys, may be NULL). */

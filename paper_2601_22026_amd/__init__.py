@@ -164,6 +164,23 @@ class Plan:
                                             out.nbytes, ct.byref(written)), "gsf_debug_copy")
         return out[: written.value // out.itemsize]
 
+    def count_pairs(self) -> dict:
+        """Pairs visited / included by the last forward, and visited by its adjoint."""
+        out = (ct.c_int64 * 3)()
+        self.ctx.use_stream()
+        self.ctx.check(lib().gsf_count_pairs(self.handle, out), "gsf_count_pairs")
+        return {"visited_fwd": out[0], "included": out[1], "visited_bwd": out[2]}
+
+    def set_timing(self, enable: bool = True):
+        self.ctx.check(lib().gsf_plan_set_timing(self.handle, int(enable)), "gsf_plan_set_timing")
+
+    def stage_times(self) -> dict:
+        """{stage: (total ms, calls)} of the eager calls since timing was enabled."""
+        n = len(_abi.STAGES)
+        ms, calls = (ct.c_double * n)(), (ct.c_int64 * n)()
+        self.ctx.check(lib().gsf_plan_stage_times(self.handle, ms, calls), "gsf_plan_stage_times")
+        return {name: (ms[k], calls[k]) for k, name in enumerate(_abi.STAGES)}
+
     def close(self):
         if getattr(self, "handle", None):
             lib().gsf_plan_destroy(self.handle)
@@ -221,16 +238,19 @@ class FitConfig:
     lds_batch: int = 128
     radius_frac: float = 0.2
     key_capacity: int = 0
+    t_mode: int = 1          # adjoint transmittance of the fused step: 1 checkpointed, 0 recomputed
 
 
 class FitStep:
     """One fit step (forward, L1 loss, backward, Adam) over all views.
 
     fused=True: one plan over all views (one launch per stage), key count kept
-    on the device, and ``capture()`` records the whole step in a HIP graph that
-    ``replay()`` launches.  fused=False: the plain path - one host-synchronised
-    plan per view, eager launches, views one after another (the loss of each
-    view is normalised by that view's own masked count).
+    on the device, checkpointed transmittance (cfg.t_mode), and ``capture()``
+    records the whole step in a HIP graph that ``replay()`` launches.
+    fused=False: the plain path - one host-synchronised plan per view,
+    transmittance recomputed in the adjoint, eager launches, views one after
+    another (the loss of each view is normalised by that view's own masked
+    count).
     """
 
     def __init__(self, ctx: Context, params: torch.Tensor, cams, targets: torch.Tensor,
@@ -259,7 +279,7 @@ class FitStep:
         if fused:
             cap = cfg.key_capacity or self._measure_capacity()
             self.plan = Plan(ctx, self.n, self.sizes, self.sh_degree, cfg.tile, cfg.lds_batch,
-                             host_sized=False, key_capacity=cap)
+                             host_sized=False, key_capacity=cap, t_mode=cfg.t_mode)
             self.args = self._args(self.plan, self.cams_dev, self.targets, self.rgba, self.dl,
                                    self.gaze)
         else:

@@ -23,7 +23,10 @@ EXPORTED = ["gsf_ctx_create", "gsf_ctx_destroy", "gsf_ctx_set_stream", "gsf_last
             "gsf_plan_create", "gsf_plan_workspace_bytes", "gsf_plan_bind_workspace",
             "gsf_plan_info", "gsf_plan_destroy", "gsf_forward", "gsf_loss_l1", "gsf_backward",
             "gsf_adam", "gsf_step", "gsf_step_capture", "gsf_step_replay", "gsf_poll",
-            "gsf_debug_copy"]
+            "gsf_debug_copy", "gsf_plan_set_timing", "gsf_plan_stage_times",
+            "gsf_count_pairs"]
+STAGES = ["project", "depth_sort", "duplicate", "tile_sort", "ranges", "render", "loss",
+          "render_bwd", "project_bwd", "adam", "zero"]
 
 
 class GsfError(RuntimeError):
@@ -82,6 +85,9 @@ def _declare(L):
         "gsf_step_replay": [vp],
         "gsf_poll": [vp, ct.POINTER(ct.c_uint32), ct.POINTER(ct.c_int64)],
         "gsf_debug_copy": [vp, ct.c_int, vp, ct.c_size_t, ct.POINTER(ct.c_size_t)],
+        "gsf_plan_set_timing": [vp, ct.c_int],
+        "gsf_count_pairs": [vp, ct.POINTER(ct.c_int64)],
+        "gsf_plan_stage_times": [vp, ct.POINTER(ct.c_double), ct.POINTER(ct.c_int64)],
     }
     for name, args in sig.items():
         fn = getattr(L, name)

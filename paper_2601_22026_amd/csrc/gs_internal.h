@@ -89,16 +89,34 @@ void launch_scan_duplicate(hipStream_t s, const uint32_t *order, const uint32_t 
 void launch_tile_ranges(hipStream_t s, const uint32_t *keys, const uint32_t *m_dev,
                         uint32_t m_host, int total_tiles, uint2 *ranges);
 
+// Everything the compositing kernels share.
+struct RenderArgs {
+    int tile = 16, batch = 128, total_tiles = 0, nviews = 1, nrec = 0;
+    int ckpt_mode = 0;                    // 1: checkpoint (T, colour) at every LDS batch boundary
+    int bwd_grid = 1;                     // persistent workgroups of the checkpointed adjoint
+    const uint2 *ranges = nullptr;
+    const uint32_t *vals = nullptr;
+    SplatPtrs sp{};
+    const ViewDesc *views = nullptr;
+    const gsf_camera *cams = nullptr;
+    float *tfinal = nullptr;
+    uint32_t *ncontrib = nullptr;
+    float4 *ckpt = nullptr;               // [key capacity / B + 1][T*T]
+    float4 *fstate = nullptr;             // [pixels]: final (T, colour)
+    const uint32_t *m_dev = nullptr;      // key count on the device, or
+    uint32_t m_host = 0;                  //   on the host when m_dev is null
+};
+
 // Front-to-back compositing of all tiles of all views.
-void launch_render_fwd(hipStream_t s, int tile, int batch, int total_tiles, const uint2 *ranges,
-                       const uint32_t *vals, SplatPtrs sp, const ViewDesc *views, int nviews,
-                       const gsf_camera *cams, float *out_rgba, float *tfinal, uint32_t *ncontrib);
+void launch_render_fwd(hipStream_t s, const RenderArgs &a, float *out_rgba);
 
 // Back-to-front adjoint of the compositing: accumulates g2d [9][nrec].
-void launch_render_bwd(hipStream_t s, int tile, int batch, int total_tiles, const uint2 *ranges,
-                       const uint32_t *vals, SplatPtrs sp, const ViewDesc *views, int nviews,
-                       const gsf_camera *cams, const float *tfinal, const uint32_t *ncontrib,
-                       const float *dl_drgba, float *g2d, int nrec);
+void launch_render_bwd(hipStream_t s, const RenderArgs &a, const float *dl_drgba, float *g2d);
+
+// Pair accounting of the last forward: counters[3] (visited, included, adjoint visited).
+void launch_count_pairs(hipStream_t s, int tile, int total_tiles, const uint2 *ranges,
+                        const uint32_t *vals, SplatPtrs sp, const ViewDesc *views, int nviews,
+                        unsigned long long *counters);
 
 // Masked L1 loss.  partial: scratch of loss_partials(total_pix) floats.
 int loss_partials(int64_t total_pix);

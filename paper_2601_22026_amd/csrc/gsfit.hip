@@ -13,6 +13,7 @@
 // All views of a plan share one launch per stage: their tiles form one global
 // tile space (per-view offsets) and their records one record space r = v*n + i.
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <new>
 #include <string>
@@ -42,10 +43,12 @@ struct Buffers {
     uint2 *ranges = nullptr;
     float *tfinal = nullptr;
     uint32_t *ncontrib = nullptr;
+    float4 *ckpt = nullptr, *fstate = nullptr;   // checkpoint mode only
     float *g2d = nullptr;
     uint32_t *hist = nullptr, *digit_tot = nullptr;
     uint32_t *m_dev = nullptr, *flags = nullptr, *mask_count = nullptr;
     unsigned long long *m_total = nullptr;
+    unsigned long long *counters = nullptr;
     float *loss_partial = nullptr;
     ViewDesc *views = nullptr;
 };
@@ -61,7 +64,8 @@ struct gsf_plan {
     int64_t cap = 0;
     std::vector<ViewDesc> views;
     int64_t total_tiles = 0, total_pix = 0, nrec_max = 0;
-    int tile_bits = 0, grid_depth = 1, grid_tile = 1;
+    int tile_bits = 0, grid_depth = 1, grid_tile = 1, bwd_grid = 1;
+    uint32_t m_host = 0;                      // key count of the last host-sized forward
     size_t ws_bytes = 0;
     void *ws = nullptr;
     Buffers b;
@@ -71,6 +75,16 @@ struct gsf_plan {
     unsigned long long *pinned = nullptr;     // host-pinned readback of the key count
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    // per-stage timing (eager only)
+    bool timing = false;
+    struct Pending {
+        int stage;
+        hipEvent_t a, b;
+    };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> pool;
+    double stage_ms[GSF_STAGE_COUNT] = {};
+    int64_t stage_calls[GSF_STAGE_COUNT] = {};
 };
 
 namespace {
@@ -125,6 +139,10 @@ size_t carve(gsf_plan *p, char *base, Buffers *out) {
     b.ranges = (uint2 *)take((size_t)p->total_tiles * sizeof(uint2));
     b.tfinal = (float *)take((size_t)p->total_pix * 4);
     b.ncontrib = (uint32_t *)take((size_t)p->total_pix * 4);
+    if (p->t_mode == 1) {
+        b.ckpt = (float4 *)take(((size_t)p->cap / p->batch + 1) * p->tile * p->tile * sizeof(float4));
+        b.fstate = (float4 *)take((size_t)p->total_pix * sizeof(float4));
+    }
     b.g2d = (float *)take(9 * R * 4);
     b.hist = (uint32_t *)take((size_t)256 * kSortMaxGrid * 4);
     b.digit_tot = (uint32_t *)take(256 * 4);
@@ -132,6 +150,7 @@ size_t carve(gsf_plan *p, char *base, Buffers *out) {
     b.flags = (uint32_t *)take(4);
     b.mask_count = (uint32_t *)take(4);
     b.m_total = (unsigned long long *)take(8);
+    b.counters = (unsigned long long *)take(3 * 8);
     b.loss_partial = (float *)take((size_t)loss_partials(p->total_pix) * 4);
     b.views = (ViewDesc *)take(p->views.size() * sizeof(ViewDesc));
     if (out) *out = b;
@@ -146,6 +165,71 @@ gsf_status check_ready(gsf_plan *p) {
 
 SplatPtrs splats(gsf_plan *p) { return SplatPtrs{p->b.rec_a, p->b.rec_b, p->b.rec_c}; }
 
+RenderArgs render_args(gsf_plan *p, const gsf_camera *cams, int64_t n) {
+    RenderArgs a;
+    a.tile = p->tile;
+    a.batch = p->batch;
+    a.total_tiles = (int)p->total_tiles;
+    a.nviews = p->V;
+    a.nrec = (int)(n * p->V);
+    a.ckpt_mode = p->t_mode == 1;
+    a.bwd_grid = p->bwd_grid;
+    a.ranges = p->b.ranges;
+    a.vals = p->vals_sorted;
+    a.sp = splats(p);
+    a.views = p->b.views;
+    a.cams = cams;
+    a.tfinal = p->b.tfinal;
+    a.ncontrib = p->b.ncontrib;
+    a.ckpt = p->b.ckpt;
+    a.fstate = p->b.fstate;
+    a.m_dev = p->host_sized ? nullptr : p->b.m_dev;
+    a.m_host = p->m_host;
+    return a;
+}
+
+hipEvent_t take_event(gsf_plan *p) {
+    if (!p->pool.empty()) {
+        hipEvent_t e = p->pool.back();
+        p->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+gsf_status flush_timing(gsf_plan *p) {
+    for (auto &q : p->pending) {
+        float ms = 0.f;
+        GSF_HIP(p->ctx, hipEventSynchronize(q.b));
+        GSF_HIP(p->ctx, hipEventElapsedTime(&ms, q.a, q.b));
+        p->stage_ms[q.stage] += ms;
+        p->stage_calls[q.stage] += 1;
+        p->pool.push_back(q.a);
+        p->pool.push_back(q.b);
+    }
+    p->pending.clear();
+    return GSF_OK;
+}
+
+// Brackets one stage with events when timing is on.
+struct StageTimer {
+    gsf_plan *p;
+    int stage;
+    hipEvent_t a = nullptr;
+    StageTimer(gsf_plan *plan, int st) : p(plan), stage(st) {
+        if (p->timing && (a = take_event(p))) hipEventRecord(a, p->ctx->stream);
+    }
+    ~StageTimer() {
+        if (!a) return;
+        hipEvent_t b = take_event(p);
+        if (!b) return;
+        hipEventRecord(b, p->ctx->stream);
+        p->pending.push_back({stage, a, b});
+    }
+};
+
 gsf_status enqueue_forward(gsf_plan *p, const float *params, int64_t n, const gsf_camera *cams,
                            float *out_rgba, bool *overflow) {
     gsf_ctx *ctx = p->ctx;
@@ -153,17 +237,30 @@ gsf_status enqueue_forward(gsf_plan *p, const float *params, int64_t n, const gs
     Buffers &b = p->b;
     const int nrec = (int)(n * p->V);
     *overflow = false;
-    launch_project_fwd(s, params, (int)n, p->V, p->deg, cams, b.views, p->tile, splats(p),
-                       b.depth_key, b.rec_idx, b.rect, b.count);
+    if (p->timing && p->pending.size() > 512) {
+        gsf_status fs = flush_timing(p);
+        if (fs != GSF_OK) return fs;
+    }
+    {
+        StageTimer t(p, GSF_STAGE_PROJECT);
+        launch_project_fwd(s, params, (int)n, p->V, p->deg, cams, b.views, p->tile, splats(p),
+                           b.depth_key, b.rec_idx, b.rect, b.count);
+    }
     GSF_LAUNCHED(ctx);
     // records in (depth, record) order
-    const int where = launch_radix_sort(s, b.depth_key, b.rec_idx, b.dk[0], b.di[0], b.dk[1],
-                                        b.di[1], nullptr, (uint32_t)nrec, 32, p->grid_depth,
-                                        b.hist, b.digit_tot);
+    int where;
+    {
+        StageTimer t(p, GSF_STAGE_DEPTH_SORT);
+        where = launch_radix_sort(s, b.depth_key, b.rec_idx, b.dk[0], b.di[0], b.dk[1], b.di[1],
+                                  nullptr, (uint32_t)nrec, 32, p->grid_depth, b.hist, b.digit_tot);
+    }
     GSF_LAUNCHED(ctx);
     p->order = where == 0 ? b.rec_idx : b.di[where - 1];
-    launch_scan_duplicate(s, p->order, b.count, b.rect, nrec, (int)n, b.views, p->V, b.block_sums,
-                          b.keys[0], b.vals[0], b.m_dev, b.m_total, b.flags, p->cap);
+    {
+        StageTimer t(p, GSF_STAGE_DUPLICATE);
+        launch_scan_duplicate(s, p->order, b.count, b.rect, nrec, (int)n, b.views, p->V,
+                              b.block_sums, b.keys[0], b.vals[0], b.m_dev, b.m_total, b.flags, p->cap);
+    }
     GSF_LAUNCHED(ctx);
     int tw;
     if (p->host_sized) {
@@ -172,23 +269,36 @@ gsf_status enqueue_forward(gsf_plan *p, const float *params, int64_t n, const gs
         const unsigned long long total = *p->pinned;
         const uint32_t m = total > (unsigned long long)p->cap ? 0u : (uint32_t)total;
         *overflow = total > (unsigned long long)p->cap;
-        tw = launch_radix_sort(s, b.keys[0], b.vals[0], b.keys[1], b.vals[1], b.keys[0], b.vals[0],
-                               nullptr, m, p->tile_bits, radix_grid_for(m), b.hist, b.digit_tot);
+        p->m_host = m;
+        {
+            StageTimer t(p, GSF_STAGE_TILE_SORT);
+            tw = launch_radix_sort(s, b.keys[0], b.vals[0], b.keys[1], b.vals[1], b.keys[0],
+                                   b.vals[0], nullptr, m, p->tile_bits, radix_grid_for(m), b.hist,
+                                   b.digit_tot);
+        }
         GSF_LAUNCHED(ctx);
         p->keys_sorted = tw == 1 ? b.keys[1] : b.keys[0];
         p->vals_sorted = tw == 1 ? b.vals[1] : b.vals[0];
+        StageTimer t(p, GSF_STAGE_RANGES);
         launch_tile_ranges(s, p->keys_sorted, nullptr, m, (int)p->total_tiles, b.ranges);
     } else {
-        tw = launch_radix_sort(s, b.keys[0], b.vals[0], b.keys[1], b.vals[1], b.keys[0], b.vals[0],
-                               b.m_dev, 0u, p->tile_bits, p->grid_tile, b.hist, b.digit_tot);
+        {
+            StageTimer t(p, GSF_STAGE_TILE_SORT);
+            tw = launch_radix_sort(s, b.keys[0], b.vals[0], b.keys[1], b.vals[1], b.keys[0],
+                                   b.vals[0], b.m_dev, 0u, p->tile_bits, p->grid_tile, b.hist,
+                                   b.digit_tot);
+        }
         GSF_LAUNCHED(ctx);
         p->keys_sorted = tw == 1 ? b.keys[1] : b.keys[0];
         p->vals_sorted = tw == 1 ? b.vals[1] : b.vals[0];
+        StageTimer t(p, GSF_STAGE_RANGES);
         launch_tile_ranges(s, p->keys_sorted, b.m_dev, 0u, (int)p->total_tiles, b.ranges);
     }
     GSF_LAUNCHED(ctx);
-    launch_render_fwd(s, p->tile, p->batch, (int)p->total_tiles, b.ranges, p->vals_sorted,
-                      splats(p), b.views, p->V, cams, out_rgba, b.tfinal, b.ncontrib);
+    {
+        StageTimer t(p, GSF_STAGE_RENDER);
+        launch_render_fwd(s, render_args(p, cams, n), out_rgba);
+    }
     GSF_LAUNCHED(ctx);
     p->have_forward = true;
     p->fwd_n = n;
@@ -197,6 +307,7 @@ gsf_status enqueue_forward(gsf_plan *p, const float *params, int64_t n, const gs
 
 gsf_status enqueue_loss(gsf_plan *p, const float *rgba, const float *target, const float *gaze,
                         float radius_frac, float *loss, float *dl) {
+    StageTimer t(p, GSF_STAGE_LOSS);
     launch_loss_l1(p->ctx->stream, rgba, target, gaze, radius_frac, p->b.views, p->V,
                    p->total_pix, dl, p->b.loss_partial, p->b.mask_count, loss, p->b.flags);
     GSF_LAUNCHED(p->ctx);
@@ -207,12 +318,19 @@ gsf_status enqueue_backward(gsf_plan *p, const float *params, int64_t n, const g
                             const float *dl, float *grads) {
     hipStream_t s = p->ctx->stream;
     const int64_t nrec = n * p->V;
-    launch_fill_f32(s, p->b.g2d, 9 * nrec, 0.f);
-    launch_render_bwd(s, p->tile, p->batch, (int)p->total_tiles, p->b.ranges, p->vals_sorted,
-                      splats(p), p->b.views, p->V, cams, p->b.tfinal, p->b.ncontrib, dl, p->b.g2d,
-                      (int)nrec);
+    {
+        StageTimer t(p, GSF_STAGE_ZERO);
+        launch_fill_f32(s, p->b.g2d, 9 * nrec, 0.f);
+    }
+    {
+        StageTimer t(p, GSF_STAGE_RENDER_BWD);
+        launch_render_bwd(s, render_args(p, cams, n), dl, p->b.g2d);
+    }
     GSF_LAUNCHED(p->ctx);
-    launch_project_bwd(s, params, (int)n, p->V, p->deg, cams, p->b.g2d, grads);
+    {
+        StageTimer t(p, GSF_STAGE_PROJECT_BWD);
+        launch_project_bwd(s, params, (int)n, p->V, p->deg, cams, p->b.g2d, grads);
+    }
     GSF_LAUNCHED(p->ctx);
     return GSF_OK;
 }
@@ -271,8 +389,11 @@ gsf_status enqueue_step(gsf_plan *p, const gsf_step_args *a) {
     SegTable seg;
     st = make_segments(p->ctx, off[C], so.data(), sl.data(), (int32_t)sl.size(), &seg);
     if (st != GSF_OK) return st;
-    launch_adam(p->ctx->stream, a->params, a->grads, a->adam_m, a->adam_v, off[C], seg, a->beta1,
-                a->beta2, a->eps, a->step_dev);
+    {
+        StageTimer t(p, GSF_STAGE_ADAM);
+        launch_adam(p->ctx->stream, a->params, a->grads, a->adam_m, a->adam_v, off[C], seg,
+                    a->beta1, a->beta2, a->eps, a->step_dev);
+    }
     GSF_LAUNCHED(p->ctx);
     return overflow ? fail(p->ctx, GSF_E_CAPACITY, "key capacity exceeded") : GSF_OK;
 }
@@ -318,7 +439,7 @@ gsf_status gsf_plan_create(gsf_ctx *ctx, const gsf_plan_desc *d, gsf_plan **out)
     if (d->tile != 8 && d->tile != 16 && d->tile != 32) return fail(ctx, GSF_E_INVALID, "tile must be 8, 16 or 32");
     if (d->lds_batch != 64 && d->lds_batch != 128 && d->lds_batch != 256)
         return fail(ctx, GSF_E_INVALID, "lds_batch must be 64, 128 or 256");
-    if (d->t_mode != 0) return fail(ctx, GSF_E_UNSUPPORTED, "only t_mode 0 (recompute) is built");
+    if (d->t_mode != 0 && d->t_mode != 1) return fail(ctx, GSF_E_INVALID, "t_mode must be 0 or 1");
     if (d->host_sized != 0 && d->host_sized != 1) return fail(ctx, GSF_E_INVALID, "host_sized must be 0 or 1");
     if (d->key_capacity < 0 || d->key_capacity > 0xF0000000ll)
         return fail(ctx, GSF_E_INVALID, "key_capacity out of range");
@@ -365,6 +486,14 @@ gsf_status gsf_plan_create(gsf_ctx *ctx, const gsf_plan_desc *d, gsf_plan **out)
     while ((int64_t(1) << p->tile_bits) < p->total_tiles) p->tile_bits++;
     p->grid_depth = radix_grid_for(nrec);
     p->grid_tile = radix_grid_for(p->cap);
+    {   // persistent workgroups of the checkpointed adjoint: enough to fill every CU
+        int cus = 256;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess || cus < 1)
+            cus = 256;
+        const int64_t units_max = p->cap / p->batch + p->total_tiles;
+        const int64_t per_cu = p->tile == 8 ? 16 : 8;
+        p->bwd_grid = (int)std::max<int64_t>(1, std::min<int64_t>(units_max, per_cu * cus));
+    }
     p->ws_bytes = carve(p, nullptr, nullptr);
     if (hipHostMalloc((void **)&p->pinned, sizeof(unsigned long long)) != hipSuccess) {
         delete p;
@@ -408,6 +537,11 @@ gsf_status gsf_plan_destroy(gsf_plan *p) {
     if (p->exec) hipGraphExecDestroy(p->exec);
     if (p->graph) hipGraphDestroy(p->graph);
     if (p->pinned) hipHostFree(p->pinned);
+    for (auto &q : p->pending) {
+        hipEventDestroy(q.a);
+        hipEventDestroy(q.b);
+    }
+    for (auto e : p->pool) hipEventDestroy(e);
     delete p;
     return GSF_OK;
 }
@@ -472,6 +606,7 @@ gsf_status gsf_step_capture(gsf_plan *p, const gsf_step_args *a) {
     if (st != GSF_OK) return st;
     if (p->host_sized) return fail(p->ctx, GSF_E_STATE, "capture needs a plan with host_sized = 0");
     if (!p->ctx->stream) return fail(p->ctx, GSF_E_STATE, "capture needs a non-null stream");
+    if (p->timing) return fail(p->ctx, GSF_E_STATE, "disable stage timing before capturing");
     st = check_step(p, a);
     if (st != GSF_OK) return st;
     if (p->exec) {
@@ -518,6 +653,44 @@ gsf_status gsf_poll(gsf_plan *p, uint32_t *flags, int64_t *m_keys) {
     GSF_HIP(p->ctx, hipStreamSynchronize(s));
     *flags = f;
     if (m_keys) *m_keys = (int64_t)m;
+    return GSF_OK;
+}
+
+gsf_status gsf_plan_set_timing(gsf_plan *p, int enable) {
+    if (!p) return GSF_E_INVALID;
+    gsf_status st = flush_timing(p);
+    if (st != GSF_OK) return st;
+    p->timing = enable != 0;
+    for (int k = 0; k < GSF_STAGE_COUNT; k++) {
+        p->stage_ms[k] = 0.0;
+        p->stage_calls[k] = 0;
+    }
+    return GSF_OK;
+}
+
+gsf_status gsf_plan_stage_times(gsf_plan *p, double *total_ms, int64_t *calls) {
+    if (!p) return GSF_E_INVALID;
+    gsf_status st = flush_timing(p);
+    if (st != GSF_OK) return st;
+    for (int k = 0; k < GSF_STAGE_COUNT; k++) {
+        if (total_ms) total_ms[k] = p->stage_ms[k];
+        if (calls) calls[k] = p->stage_calls[k];
+    }
+    return GSF_OK;
+}
+
+gsf_status gsf_count_pairs(gsf_plan *p, int64_t *out) {
+    gsf_status st = check_ready(p);
+    if (st != GSF_OK) return st;
+    if (!out) return fail(p->ctx, GSF_E_INVALID, "gsf_count_pairs: null output");
+    if (!p->have_forward) return fail(p->ctx, GSF_E_STATE, "gsf_count_pairs before gsf_forward");
+    launch_count_pairs(p->ctx->stream, p->tile, (int)p->total_tiles, p->b.ranges, p->vals_sorted,
+                       splats(p), p->b.views, p->V, p->b.counters);
+    GSF_LAUNCHED(p->ctx);
+    unsigned long long c[3] = {0, 0, 0};
+    GSF_HIP(p->ctx, hipStreamSynchronize(p->ctx->stream));
+    GSF_HIP(p->ctx, hipMemcpy(c, p->b.counters, sizeof c, hipMemcpyDeviceToHost));
+    for (int k = 0; k < 3; k++) out[k] = (int64_t)c[k];
     return GSF_OK;
 }
 

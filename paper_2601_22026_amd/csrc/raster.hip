@@ -48,17 +48,35 @@ __device__ __forceinline__ int view_of_tile(const ViewDesc *__restrict__ views, 
     return v;
 }
 
-__device__ __forceinline__ float wave_sum(float x) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
+// Sum of x over the 64 lanes of a wave, valid in lane 63: four row shifts
+// (DPP row_shr 1, 2, 4, 8) leave each 16-lane row's total in its lane 15, then
+// row_bcast:15 and row_bcast:31 fold the rows together.  All steps are VALU
+// instructions with DPP operands (no LDS traffic).
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_shift(float x) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL,
+                                                                 ROW_MASK, 0xf, true));
+}
+
+__device__ __forceinline__ float wave_sum_lane63(float x) {
+    x += dpp_shift<0x111, 0xf>(x);   // row_shr:1
+    x += dpp_shift<0x112, 0xf>(x);   // row_shr:2
+    x += dpp_shift<0x114, 0xf>(x);   // row_shr:4
+    x += dpp_shift<0x118, 0xf>(x);   // row_shr:8
+    x += dpp_shift<0x142, 0xa>(x);   // row_bcast:15 into rows 1 and 3
+    x += dpp_shift<0x143, 0xc>(x);   // row_bcast:31 into rows 2 and 3
     return x;
 }
 
-template <int T, int B>
+// CKPT: also store (T, colour) of every pixel after each LDS batch that is not
+// the tile's last (slot = boundary position / B, unique over all tiles) and the
+// final (T, colour), so the adjoint can start at any batch.
+template <int T, int B, bool CKPT>
 __global__ __launch_bounds__(T * T < 256 ? T * T : 256) void k_render_fwd(
     const uint2 *__restrict__ ranges, const uint32_t *__restrict__ vals, SplatPtrs sp,
     const ViewDesc *__restrict__ views, int nviews, const gsf_camera *__restrict__ cams,
-    float *__restrict__ out_rgba, float *__restrict__ tfinal, uint32_t *__restrict__ ncontrib) {
+    float *__restrict__ out_rgba, float *__restrict__ tfinal, uint32_t *__restrict__ ncontrib,
+    float4 *__restrict__ ckpt, float4 *__restrict__ fstate) {
     constexpr int NT = T * T < 256 ? T * T : 256;
     constexpr int PPT = T * T / NT;
     constexpr int ROWS = NT / T;
@@ -124,6 +142,12 @@ __global__ __launch_bounds__(T * T < 256 ? T * T : 256) void k_render_fwd(
                 last[k] = bs + (uint32_t)j - rg.x + 1u;
             }
         }
+        if (CKPT && bs + B < rg.y) {
+            float4 *slot = ckpt + (size_t)((bs + B) / B) * (T * T);
+#pragma unroll
+            for (int k = 0; k < PPT; k++)
+                slot[threadIdx.x + k * NT] = make_float4(Tr[k], cr[k], cg[k], cb[k]);
+        }
         bool all = true;
 #pragma unroll
         for (int k = 0; k < PPT; k++) all &= done[k];
@@ -145,31 +169,31 @@ __global__ __launch_bounds__(T * T < 256 ? T * T : 256) void k_render_fwd(
         img[3 * plane + q] = 1.f - Tr[k];
         tfinal[vd.pix_off + q] = Tr[k];
         ncontrib[vd.pix_off + q] = last[k];
+        if (CKPT) fstate[vd.pix_off + q] = make_float4(Tr[k], cr[k], cg[k], cb[k]);
     }
 }
 
-template <int T, int B>
-__global__ __launch_bounds__(T * T < 256 ? T * T : 256) void k_render_bwd(
-    const uint2 *__restrict__ ranges, const uint32_t *__restrict__ vals, SplatPtrs sp,
-    const ViewDesc *__restrict__ views, int nviews, const gsf_camera *__restrict__ cams,
-    const float *__restrict__ tfinal, const uint32_t *__restrict__ ncontrib,
-    const float *__restrict__ dl, float *__restrict__ g2d, int nrec) {
+// Unit of adjoint work: the entries [us, ue) of tile gt's list.  With
+// checkpoints (CKPT) a unit is one LDS batch of B entries and starts from the
+// state the forward stored at the batch's end; without, a unit is the whole
+// list and starts from the final state.
+template <int T, int B, bool CKPT>
+__device__ __forceinline__ void render_bwd_unit(
+    int gt, uint32_t us, uint32_t ue, bool last_unit, const uint2 &rg,
+    const uint32_t *__restrict__ vals, SplatPtrs sp, const ViewDesc *__restrict__ views,
+    int nviews, const gsf_camera *__restrict__ cams, const float *__restrict__ tfinal,
+    const uint32_t *__restrict__ ncontrib, const float4 *__restrict__ fstate,
+    const float4 *__restrict__ ckpt, const float *__restrict__ dl, float *__restrict__ g2d,
+    int nrec, float4 *s_a, float4 *s_b, float *s_c, uint32_t *s_r,
+    float (*s_g)[9][B], uint32_t *s_nmax) {
     constexpr int NT = T * T < 256 ? T * T : 256;
     constexpr int PPT = T * T / NT;
     constexpr int ROWS = NT / T;
-    __shared__ float4 s_a[B];
-    __shared__ float4 s_b[B];
-    __shared__ float s_c[B];
-    __shared__ uint32_t s_r[B];
-    __shared__ float s_g[B * 9];
-    __shared__ uint32_t s_nmax;
-
-    const int gt = blockIdx.x;
+    constexpr int NW = NT / 64;
     const int v = view_of_tile(views, nviews, gt);
     const ViewDesc vd = views[v];
     const int local = gt - vd.tile_off;
     const int ty = local / vd.tiles_x, tx = local - ty * vd.tiles_x;
-    const uint2 rg = ranges[gt];
     const int lx = threadIdx.x % T, ly = threadIdx.x / T;
     const gsf_camera &cam = cams[v];
     const float bg0 = cam.bg[0], bg1 = cam.bg[1], bg2 = cam.bg[2];
@@ -197,18 +221,29 @@ __global__ __launch_bounds__(T * T < 256 ? T * T : 256) void k_render_bwd(
             nc[k] = 0u;
             g0[k] = g1[k] = g2[k] = gA[k] = 0.f;
         }
-        Tr[k] = Tf[k];
-        gR[k] = Tf[k] * (g0[k] * bg0 + g1[k] * bg1 + g2[k] * bg2);
+        const float gbg = Tf[k] * (g0[k] * bg0 + g1[k] * bg1 + g2[k] * bg2);
+        if (CKPT && !last_unit && rg.x + nc[k] > us) {
+            // colour behind the unit = final colour - colour accumulated at its end
+            const float4 fs = fstate[vd.pix_off + (x < vd.width && y < vd.height ? (size_t)y * vd.width + x : 0)];
+            const float4 cp = ckpt[(size_t)(ue / B) * (T * T) + threadIdx.x + k * NT];
+            Tr[k] = cp.x;
+            gR[k] = gbg + g0[k] * (fs.y - cp.y) + g1[k] * (fs.z - cp.z) + g2[k] * (fs.w - cp.w);
+        } else {
+            Tr[k] = Tf[k];
+            gR[k] = gbg;
+        }
         my_max = max(my_max, nc[k]);
     }
-    if (threadIdx.x == 0) s_nmax = 0u;
     __syncthreads();
-    atomicMax(&s_nmax, my_max);
+    if (threadIdx.x == 0) *s_nmax = 0u;
     __syncthreads();
-    const uint32_t nmax = s_nmax;
+    atomicMax(s_nmax, my_max);
+    __syncthreads();
+    const uint32_t nmax = *s_nmax;
+    const uint32_t top = min(ue, rg.x + nmax);
 
-    for (uint32_t be = rg.x + nmax; be > rg.x;) {
-        const uint32_t bs = be - rg.x > (uint32_t)B ? be - (uint32_t)B : rg.x;
+    for (uint32_t be = top; be > us;) {
+        const uint32_t bs = be - us > (uint32_t)B ? be - (uint32_t)B : us;
         const int nb = (int)(be - bs);
         __syncthreads();
         for (int j = threadIdx.x; j < nb; j += NT) {
@@ -218,7 +253,7 @@ __global__ __launch_bounds__(T * T < 256 ? T * T : 256) void k_render_bwd(
             s_c[j] = sp.c[r];
             s_r[j] = r;
         }
-        for (int e = threadIdx.x; e < nb * 9; e += NT) s_g[e] = 0.f;
+        for (int e = threadIdx.x; e < NW * 9 * B; e += NT) (&s_g[0][0][0])[e] = 0.f;
         __syncthreads();
         for (int j = nb - 1; j >= 0; j--) {
             const uint32_t pos = bs + (uint32_t)j - rg.x;   // list position in the tile
@@ -235,10 +270,10 @@ __global__ __launch_bounds__(T * T < 256 ? T * T : 256) void k_render_bwd(
                 float alpha, ae, ex, dx, dy;
                 if (!splat_alpha(a, b, px[k], py[k], alpha, ae, ex, dx, dy)) continue;
                 any = true;
-                const float oma = 1.f - alpha;
-                const float Tb = Tr[k] / oma;
+                const float inv = __builtin_amdgcn_rcpf(1.f - alpha);   // alpha <= 0.99
+                const float Tb = Tr[k] * inv;
                 const float gc = g0[k] * b.z + g1[k] * b.w + g2[k] * c2;
-                const float dalpha = (Tb * gc - gR[k] / oma) + gA[k] * Tf[k] / oma;
+                const float dalpha = Tb * gc - (gR[k] - gA[k] * Tf[k]) * inv;
                 const float wT = alpha * Tb;
                 acc[6] += wT * g0[k];
                 acc[7] += wT * g1[k];
@@ -255,23 +290,133 @@ __global__ __launch_bounds__(T * T < 256 ? T * T : 256) void k_render_bwd(
                 acc[1] += (a.w * dx + b.x * dy) * dpw;
             }
             if (__any(any)) {
+                const int w = threadIdx.x >> 6;
 #pragma unroll
                 for (int f = 0; f < 9; f++) {
-                    const float sum = wave_sum(acc[f]);
-                    if (__lane_id() == 0 && sum != 0.f) atomicAdd(&s_g[j * 9 + f], sum);
+                    const float sum = wave_sum_lane63(acc[f]);
+                    if (__lane_id() == 63) s_g[w][f][j] = sum;
                 }
             }
         }
         __syncthreads();
         for (int e = threadIdx.x; e < nb * 9; e += NT) {
-            const float val = s_g[e];
-            if (val != 0.f) {
-                const int j = e / 9, f = e - 9 * (e / 9);
-                unsafeAtomicAdd(&g2d[(size_t)f * nrec + s_r[j]], val);
-            }
+            const int f = e / nb, j = e - f * nb;
+            float val = 0.f;
+#pragma unroll
+            for (int w = 0; w < NW; w++) val += s_g[w][f][j];
+            if (val != 0.f) unsafeAtomicAdd(&g2d[(size_t)f * nrec + s_r[j]], val);
         }
         be = bs;
     }
+}
+
+// Recompute mode: one workgroup per tile, the whole list back to front.
+template <int T, int B>
+__global__ __launch_bounds__(T * T < 256 ? T * T : 256) void k_render_bwd(
+    const uint2 *__restrict__ ranges, const uint32_t *__restrict__ vals, SplatPtrs sp,
+    const ViewDesc *__restrict__ views, int nviews, const gsf_camera *__restrict__ cams,
+    const float *__restrict__ tfinal, const uint32_t *__restrict__ ncontrib,
+    const float *__restrict__ dl, float *__restrict__ g2d, int nrec) {
+    constexpr int NT = T * T < 256 ? T * T : 256;
+    __shared__ float4 s_a[B];
+    __shared__ float4 s_b[B];
+    __shared__ float s_c[B];
+    __shared__ uint32_t s_r[B];
+    __shared__ float s_g[NT / 64][9][B];
+    __shared__ uint32_t s_nmax;
+    const uint2 rg = ranges[blockIdx.x];
+    render_bwd_unit<T, B, false>(blockIdx.x, rg.x, rg.y, true, rg, vals, sp, views, nviews, cams,
+                                 tfinal, ncontrib, nullptr, nullptr, dl, g2d, nrec, s_a, s_b, s_c,
+                                 s_r, s_g, &s_nmax);
+}
+
+// Checkpoint mode: persistent workgroups over (tile, batch) units.  Unit u of
+// tile t has id floor(start_t / B) + t + u (strictly increasing, below
+// M / B + tiles); a workgroup maps an id back to its tile by binary search.
+template <int T, int B>
+__global__ __launch_bounds__(T * T < 256 ? T * T : 256) void k_render_bwd_ckpt(
+    const uint2 *__restrict__ ranges, int total_tiles, const uint32_t *__restrict__ m_dev,
+    uint32_t m_host, const uint32_t *__restrict__ vals, SplatPtrs sp,
+    const ViewDesc *__restrict__ views, int nviews, const gsf_camera *__restrict__ cams,
+    const float *__restrict__ tfinal, const uint32_t *__restrict__ ncontrib,
+    const float4 *__restrict__ fstate, const float4 *__restrict__ ckpt,
+    const float *__restrict__ dl, float *__restrict__ g2d, int nrec) {
+    constexpr int NT = T * T < 256 ? T * T : 256;
+    __shared__ float4 s_a[B];
+    __shared__ float4 s_b[B];
+    __shared__ float s_c[B];
+    __shared__ uint32_t s_r[B];
+    __shared__ float s_g[NT / 64][9][B];
+    __shared__ uint32_t s_nmax;
+    const uint32_t m = m_dev ? *m_dev : m_host;
+    const uint32_t n_ids = m / B + (uint32_t)total_tiles;
+    for (uint32_t id = blockIdx.x; id < n_ids; id += gridDim.x) {
+        // largest tile t with first id floor(start_t / B) + t <= id
+        int lo = 0, hi = total_tiles - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (ranges[mid].x / B + (uint32_t)mid <= id) lo = mid; else hi = mid - 1;
+        }
+        const uint2 rg = ranges[lo];
+        const uint32_t u = id - (rg.x / B + (uint32_t)lo);
+        const uint32_t units = (rg.y - rg.x + B - 1) / B;
+        if (u >= units) continue;
+        const uint32_t us = rg.x + u * B;
+        const uint32_t ue = min(rg.y, us + B);
+        render_bwd_unit<T, B, true>(lo, us, ue, u + 1 == units, rg, vals, sp, views, nviews, cams,
+                                    tfinal, ncontrib, fstate, ckpt, dl, g2d, nrec, s_a, s_b, s_c,
+                                    s_r, s_g, &s_nmax);
+    }
+}
+
+// Work accounting: the same per-pixel walk as k_render_fwd, counting instead
+// of compositing.  counters: visited (forward), included, visited (adjoint).
+template <int T>
+__global__ __launch_bounds__(T * T < 256 ? T * T : 256) void k_count_pairs(
+    const uint2 *__restrict__ ranges, const uint32_t *__restrict__ vals, SplatPtrs sp,
+    const ViewDesc *__restrict__ views, int nviews, unsigned long long *__restrict__ counters) {
+    constexpr int NT = T * T < 256 ? T * T : 256;
+    constexpr int PPT = T * T / NT;
+    constexpr int ROWS = NT / T;
+    __shared__ unsigned long long s_cnt[3];
+    if (threadIdx.x < 3) s_cnt[threadIdx.x] = 0ull;
+    __syncthreads();
+    const int gt = blockIdx.x;
+    const int v = view_of_tile(views, nviews, gt);
+    const ViewDesc vd = views[v];
+    const int local = gt - vd.tile_off;
+    const int ty = local / vd.tiles_x, tx = local - ty * vd.tiles_x;
+    const uint2 rg = ranges[gt];
+    unsigned long long visit = 0, incl = 0, visit_bwd = 0;
+#pragma unroll
+    for (int k = 0; k < PPT; k++) {
+        const int x = tx * T + threadIdx.x % T, y = ty * T + threadIdx.x / T + k * ROWS;
+        if (!(x < vd.width && y < vd.height)) continue;
+        const float px = (float)x + 0.5f, py = (float)y + 0.5f;
+        float Tr = 1.f;
+        uint32_t last = 0;
+        for (uint32_t e = rg.x; e < rg.y; e++) {
+            const uint32_t r = vals[e];
+            visit++;
+            float alpha, ae, ex, dx, dy;
+            if (!splat_alpha(sp.a[r], sp.b[r], px, py, alpha, ae, ex, dx, dy)) continue;
+            const float Tn = Tr * (1.f - alpha);
+            if (Tn < kTStop) break;
+            Tr = Tn;
+            incl++;
+            last = e - rg.x + 1u;
+        }
+        visit_bwd += last;
+    }
+    atomicAdd(&s_cnt[0], visit);
+    atomicAdd(&s_cnt[1], incl);
+    atomicAdd(&s_cnt[2], visit_bwd);
+    __syncthreads();
+    if (threadIdx.x < 3) atomicAdd(&counters[threadIdx.x], s_cnt[threadIdx.x]);
+}
+
+__global__ void k_zero_u64(unsigned long long *p, int n) {
+    if ((int)threadIdx.x < n) p[threadIdx.x] = 0ull;
 }
 
 // ---- loss -----------------------------------------------------------------------
@@ -389,55 +534,70 @@ __global__ void k_fill_f32(float *p, int64_t n, float value) {
         p[e] = value;
 }
 
-template <int T>
-void render_fwd_t(hipStream_t s, int batch, int total_tiles, const uint2 *ranges, const uint32_t *vals,
-                  SplatPtrs sp, const ViewDesc *views, int nviews, const gsf_camera *cams,
-                  float *out, float *tfinal, uint32_t *ncontrib) {
+template <int T, int B>
+void render_fwd_tb(hipStream_t s, const RenderArgs &a, float *out) {
     constexpr int NT = T * T < 256 ? T * T : 256;
-    if (batch == 64)
-        k_render_fwd<T, 64><<<total_tiles, NT, 0, s>>>(ranges, vals, sp, views, nviews, cams, out, tfinal, ncontrib);
-    else if (batch == 128)
-        k_render_fwd<T, 128><<<total_tiles, NT, 0, s>>>(ranges, vals, sp, views, nviews, cams, out, tfinal, ncontrib);
+    if (a.ckpt_mode)
+        k_render_fwd<T, B, true><<<a.total_tiles, NT, 0, s>>>(a.ranges, a.vals, a.sp, a.views, a.nviews,
+                                                             a.cams, out, a.tfinal, a.ncontrib, a.ckpt,
+                                                             a.fstate);
     else
-        k_render_fwd<T, 256><<<total_tiles, NT, 0, s>>>(ranges, vals, sp, views, nviews, cams, out, tfinal, ncontrib);
+        k_render_fwd<T, B, false><<<a.total_tiles, NT, 0, s>>>(a.ranges, a.vals, a.sp, a.views, a.nviews,
+                                                              a.cams, out, a.tfinal, a.ncontrib, nullptr,
+                                                              nullptr);
+}
+
+template <int T, int B>
+void render_bwd_tb(hipStream_t s, const RenderArgs &a, const float *dl, float *g2d) {
+    constexpr int NT = T * T < 256 ? T * T : 256;
+    if (a.ckpt_mode)
+        k_render_bwd_ckpt<T, B><<<a.bwd_grid, NT, 0, s>>>(a.ranges, a.total_tiles, a.m_dev, a.m_host,
+                                                         a.vals, a.sp, a.views, a.nviews, a.cams,
+                                                         a.tfinal, a.ncontrib, a.fstate, a.ckpt, dl,
+                                                         g2d, a.nrec);
+    else
+        k_render_bwd<T, B><<<a.total_tiles, NT, 0, s>>>(a.ranges, a.vals, a.sp, a.views, a.nviews,
+                                                       a.cams, a.tfinal, a.ncontrib, dl, g2d, a.nrec);
 }
 
 template <int T>
-void render_bwd_t(hipStream_t s, int batch, int total_tiles, const uint2 *ranges, const uint32_t *vals,
-                  SplatPtrs sp, const ViewDesc *views, int nviews, const gsf_camera *cams,
-                  const float *tfinal, const uint32_t *ncontrib, const float *dl, float *g2d, int nrec) {
-    constexpr int NT = T * T < 256 ? T * T : 256;
-    if (batch == 64)
-        k_render_bwd<T, 64><<<total_tiles, NT, 0, s>>>(ranges, vals, sp, views, nviews, cams, tfinal, ncontrib, dl, g2d, nrec);
-    else if (batch == 128)
-        k_render_bwd<T, 128><<<total_tiles, NT, 0, s>>>(ranges, vals, sp, views, nviews, cams, tfinal, ncontrib, dl, g2d, nrec);
-    else
-        k_render_bwd<T, 256><<<total_tiles, NT, 0, s>>>(ranges, vals, sp, views, nviews, cams, tfinal, ncontrib, dl, g2d, nrec);
+void render_fwd_t(hipStream_t s, const RenderArgs &a, float *out) {
+    if (a.batch == 64) render_fwd_tb<T, 64>(s, a, out);
+    else if (a.batch == 128) render_fwd_tb<T, 128>(s, a, out);
+    else render_fwd_tb<T, 256>(s, a, out);
+}
+
+template <int T>
+void render_bwd_t(hipStream_t s, const RenderArgs &a, const float *dl, float *g2d) {
+    if (a.batch == 64) render_bwd_tb<T, 64>(s, a, dl, g2d);
+    else if (a.batch == 128) render_bwd_tb<T, 128>(s, a, dl, g2d);
+    else render_bwd_tb<T, 256>(s, a, dl, g2d);
 }
 
 }  // namespace
 
-void launch_render_fwd(hipStream_t s, int tile, int batch, int total_tiles, const uint2 *ranges,
-                       const uint32_t *vals, SplatPtrs sp, const ViewDesc *views, int nviews,
-                       const gsf_camera *cams, float *out_rgba, float *tfinal, uint32_t *ncontrib) {
-    if (tile == 8)
-        render_fwd_t<8>(s, batch, total_tiles, ranges, vals, sp, views, nviews, cams, out_rgba, tfinal, ncontrib);
-    else if (tile == 16)
-        render_fwd_t<16>(s, batch, total_tiles, ranges, vals, sp, views, nviews, cams, out_rgba, tfinal, ncontrib);
-    else
-        render_fwd_t<32>(s, batch, total_tiles, ranges, vals, sp, views, nviews, cams, out_rgba, tfinal, ncontrib);
+void launch_render_fwd(hipStream_t s, const RenderArgs &a, float *out_rgba) {
+    if (a.tile == 8) render_fwd_t<8>(s, a, out_rgba);
+    else if (a.tile == 16) render_fwd_t<16>(s, a, out_rgba);
+    else render_fwd_t<32>(s, a, out_rgba);
 }
 
-void launch_render_bwd(hipStream_t s, int tile, int batch, int total_tiles, const uint2 *ranges,
-                       const uint32_t *vals, SplatPtrs sp, const ViewDesc *views, int nviews,
-                       const gsf_camera *cams, const float *tfinal, const uint32_t *ncontrib,
-                       const float *dl_drgba, float *g2d, int nrec) {
+void launch_render_bwd(hipStream_t s, const RenderArgs &a, const float *dl_drgba, float *g2d) {
+    if (a.tile == 8) render_bwd_t<8>(s, a, dl_drgba, g2d);
+    else if (a.tile == 16) render_bwd_t<16>(s, a, dl_drgba, g2d);
+    else render_bwd_t<32>(s, a, dl_drgba, g2d);
+}
+
+void launch_count_pairs(hipStream_t s, int tile, int total_tiles, const uint2 *ranges,
+                        const uint32_t *vals, SplatPtrs sp, const ViewDesc *views, int nviews,
+                        unsigned long long *counters) {
+    k_zero_u64<<<1, 64, 0, s>>>(counters, 3);
     if (tile == 8)
-        render_bwd_t<8>(s, batch, total_tiles, ranges, vals, sp, views, nviews, cams, tfinal, ncontrib, dl_drgba, g2d, nrec);
+        k_count_pairs<8><<<total_tiles, 64, 0, s>>>(ranges, vals, sp, views, nviews, counters);
     else if (tile == 16)
-        render_bwd_t<16>(s, batch, total_tiles, ranges, vals, sp, views, nviews, cams, tfinal, ncontrib, dl_drgba, g2d, nrec);
+        k_count_pairs<16><<<total_tiles, 256, 0, s>>>(ranges, vals, sp, views, nviews, counters);
     else
-        render_bwd_t<32>(s, batch, total_tiles, ranges, vals, sp, views, nviews, cams, tfinal, ncontrib, dl_drgba, g2d, nrec);
+        k_count_pairs<32><<<total_tiles, 256, 0, s>>>(ranges, vals, sp, views, nviews, counters);
 }
 
 int loss_partials(int64_t total_pix) { return (int)((total_pix + kLossBlock - 1) / kLossBlock); }

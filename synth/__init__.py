@@ -294,7 +294,22 @@ def seed_from_volume(vol: np.ndarray, threshold: float = TF_THRESHOLD, cap: int 
 
 def trilinear_sampler(vol: np.ndarray):
     """Sampler returning (density t in [0,1], rgb) at world points, trilinear in
-    the raw values with zero outside the grid."""
+    the raw values with zero outside the grid (scipy's C interpolator)."""
+    from scipy.ndimage import map_coordinates
+    n = vol.shape[0]
+    v = vol.astype(np.float64)
+
+    def sample(p):
+        u = (p + 1.0) * (n / 2.0) - 0.5
+        acc = map_coordinates(v, u.T, order=1, mode="grid-constant", cval=0.0, prefilter=False)
+        t = tf_density(acc)
+        return t, tf_colour(t)
+
+    return sample
+
+
+def trilinear_sampler_reference(vol: np.ndarray):
+    """Explicit eight-corner form of ``trilinear_sampler`` (for checking it)."""
     n = vol.shape[0]
     v = vol.astype(np.float64)
 
@@ -380,6 +395,50 @@ def raymarch(sampler, cam: Camera, step: float, extinction: float = EXTINCTION,
     return _f32(img.reshape(4, rows.size, W))
 
 
-def raymarch_volume(vol: np.ndarray, cam: Camera, rows=None) -> np.ndarray:
-    """Target image of the phantom with half-voxel steps."""
-    return raymarch(trilinear_sampler(vol), cam, step=1.0 / vol.shape[0], rows=rows)
+_RM_SRC = __import__("os").path.join(__import__("os").path.dirname(__file__), "raymarch.c")
+_RM_LIB = _RM_SRC[:-2] + ".so"
+_rm = None
+
+
+def _raymarch_lib():
+    """ctypes handle of raymarch.c (built with gcc on first use)."""
+    global _rm
+    import ctypes as ct
+    import os
+    import subprocess
+    if _rm is None:
+        if not os.path.exists(_RM_LIB) or os.path.getmtime(_RM_LIB) < os.path.getmtime(_RM_SRC):
+            tmp = _RM_LIB + f".tmp{os.getpid()}"
+            subprocess.run(["gcc", "-O2", "-fPIC", "-shared", "-fopenmp", "-o", tmp, _RM_SRC, "-lm"],
+                           check=True)
+            os.replace(tmp, _RM_LIB)
+        L = ct.CDLL(_RM_LIB)
+        dp = ct.POINTER(ct.c_double)
+        L.syn_raymarch.argtypes = [ct.c_void_p, ct.c_int, dp, ct.POINTER(ct.c_int64), ct.c_int64,
+                                   ct.c_double, ct.c_double, ct.c_double, dp, dp, ct.c_double,
+                                   ct.c_double, ct.c_void_p]
+        L.syn_raymarch.restype = None
+        _rm = L
+    return _rm
+
+
+def raymarch_volume(vol: np.ndarray, cam: Camera, rows=None, t_stop: float = 1e-4) -> np.ndarray:
+    """Target image of the phantom with half-voxel steps (C implementation of
+    ``raymarch`` with ``trilinear_sampler``)."""
+    import ctypes as ct
+    L = _raymarch_lib()
+    n = vol.shape[0]
+    v = np.ascontiguousarray(vol, np.uint16)
+    rows = np.arange(cam.height) if rows is None else np.asarray(rows)
+    rows = np.ascontiguousarray(rows, np.int64)
+    c = np.ascontiguousarray(np.concatenate([cam.R.reshape(-1), cam.campos,
+                                             [cam.fx, cam.fy, cam.cx, cam.cy], cam.bg,
+                                             [cam.width, cam.height]]).astype(np.float64))
+    out = np.zeros((4, rows.size, cam.width), np.float32)
+    lo, hi = np.ascontiguousarray(TF_LO, np.float64), np.ascontiguousarray(TF_HI, np.float64)
+    dp = ct.POINTER(ct.c_double)
+    L.syn_raymarch(v.ctypes.data_as(ct.c_void_p), n, c.ctypes.data_as(dp),
+                   rows.ctypes.data_as(ct.POINTER(ct.c_int64)), rows.size, 1.0 / n, EXTINCTION,
+                   t_stop, lo.ctypes.data_as(dp), hi.ctypes.data_as(dp), TF_THRESHOLD, TF_RANGE,
+                   out.ctypes.data_as(ct.c_void_p))
+    return out

@@ -20,7 +20,8 @@ def log(msg):
 class GpuScene:
     """Device copies of a parameter set and cameras plus one plan."""
 
-    def __init__(self, ctx, P, cams, tile=16, batch=128, host_sized=True, key_capacity=0):
+    def __init__(self, ctx, P, cams, tile=16, batch=128, host_sized=True, key_capacity=0,
+                 t_mode=0):
         self.P = P
         self.cams = list(cams)
         self.deg = oracle.sh_degree_of(P)
@@ -28,7 +29,8 @@ class GpuScene:
         self.params = torch.from_numpy(np.ascontiguousarray(P, np.float32)).to(DEV)
         self.cams_dev = gs.cameras_to_device(self.cams, DEV)
         self.plan = gs.Plan(ctx, self.n, [(c.width, c.height) for c in self.cams], self.deg,
-                            tile, batch, host_sized=host_sized, key_capacity=key_capacity)
+                            tile, batch, host_sized=host_sized, key_capacity=key_capacity,
+                            t_mode=t_mode)
         self.npix = [c.width * c.height for c in self.cams]
         self.rgba = torch.zeros(4 * sum(self.npix), dtype=torch.float32, device=DEV)
 
@@ -73,11 +75,15 @@ def grads_close(gpu, ref, rtol=1e-3, floor_frac=1e-2, atol_frac=1e-5):
     groups = {"mean": slice(0, 3), "logscale": slice(3, 6), "quat": slice(6, 10),
               "opacity": slice(10, 11), "sh": slice(11, gpu.shape[0])}
     report = []
+    overall = np.abs(ref).max()
     for name, sl in groups.items():
         g, r = gpu[sl], ref[sl]
         mx = np.abs(r).max()
-        if mx == 0:
-            report.append((name, int((g != 0).sum()), float(np.abs(g).max())))
+        if mx < 1e-4 * overall:
+            # a group that is zero in exact arithmetic (e.g. rotations of isotropic
+            # Gaussians): float32 cancellation noise against the largest gradient
+            err = np.abs(g - r)
+            report.append((name, int((err > atol_frac * overall).sum()), float(err.max() / overall)))
             continue
         big = np.abs(r) >= floor_frac * mx
         err = np.abs(g - r)

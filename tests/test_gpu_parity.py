@@ -95,13 +95,13 @@ def test_image_matches_oracle_cfg1(ctx):
     np.testing.assert_array_equal(last_gpu[ok], ref.last[ok])
 
 
-@pytest.mark.parametrize("deg", [0, 3])
-def test_multiview_image_and_gradient(ctx, deg):
+@pytest.mark.parametrize("deg,t_mode,batch", [(0, 0, 128), (3, 0, 128), (0, 1, 64), (3, 1, 128)])
+def test_multiview_image_and_gradient(ctx, deg, t_mode, batch):
     P = synth.random_gaussians(400, seed=5, sh_degree=deg)
     cams = [synth.look_at_camera([0.3, -0.2, -3.0], width=96, height=80, bg=(0.1, 0.2, 0.3)),
             synth.look_at_camera([2.5, 1.0, 1.0], width=61, height=47)]
-    log(f"[parity] 2 views, SH degree {deg}: image + gradient")
-    sc = GpuScene(ctx, P, cams)
+    log(f"[parity] 2 views, SH degree {deg}, t_mode {t_mode}, batch {batch}: image + gradient")
+    sc = GpuScene(ctx, P, cams, batch=batch, t_mode=t_mode)
     imgs = sc.forward()
     refs = [oracle.render(P, c) for c in cams]
     for img, ref in zip(imgs, refs):
@@ -147,3 +147,22 @@ def test_loss_and_dl_match_oracle(ctx):
     L, dls = oracle.loss_l1([img.astype(np.float64)], [target.astype(np.float64)], [cam])
     assert abs(loss.item() - L) <= 1e-5 * L
     np.testing.assert_allclose(dl.cpu().numpy().reshape(4, -1), dls[0], rtol=1e-6, atol=0)
+
+
+@pytest.mark.parametrize("tile,batch", [(8, 64), (16, 64), (16, 128), (32, 64)])
+def test_checkpointed_adjoint_matches_recompute(ctx, tile, batch):
+    """Same image bits; gradients equal within tolerance (the checkpointed
+    adjoint starts every LDS batch from stored state)."""
+    P = synth.random_gaussians(1500, seed=8)
+    cam = synth.look_at_camera([0.2, 0.4, -3.0], width=112, height=90, bg=(0.3, 0.1, 0.2))
+    a = GpuScene(ctx, P, [cam], tile=tile, batch=batch, t_mode=0)
+    b = GpuScene(ctx, P, [cam], tile=tile, batch=batch, t_mode=1)
+    ia, ib = a.forward()[0], b.forward()[0]
+    np.testing.assert_array_equal(ia.view(np.uint32), ib.view(np.uint32))
+    dl = [np.random.default_rng(2).normal(size=(4, cam.npix))]
+    ga, gb = a.backward(dl), b.backward(dl)
+    rep = grads_close(gb, ga.astype(np.float64))
+    log(f"[parity] tile {tile} batch {batch}: ckpt vs recompute {rep}")
+    assert all(nb == 0 for _, nb, _ in rep), rep
+    ranges = a.debug(_abi.GSF_DBG_RANGES, np.uint32, 2 * a.plan.total_tiles).reshape(-1, 2)
+    assert (ranges[:, 1] - ranges[:, 0]).max() > 2 * batch   # several batches per tile exercised

@@ -1,0 +1,268 @@
+"""GPU tests of the whole step: Adam, graph replay, multi-step fit, autograd,
+failure paths, edge cases and the full-size workload (sampled against the
+oracle)."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from paper_2601_22026_amd import _abi
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+from gpu_common import DEV, GpuScene, grads_close, image_close, log  # noqa: E402
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def gs():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2601_22026_amd
+    return paper_2601_22026_amd
+
+
+@pytest.fixture(scope="module")
+def ctx(gs):
+    return gs.Context(0)
+
+
+def _cfg1_target():
+    return np.load(os.path.join(GOLDEN, "cfg1_target_128.npy"))[:3]
+
+
+def test_adam_matches_oracle_given_identical_inputs(gs, ctx):
+    rng = np.random.default_rng(0)
+    n = 1003                                   # not a multiple of 4: exercises the tail
+    p = rng.normal(size=n).astype(np.float32)
+    m = np.zeros(n, np.float32)
+    v = np.zeros(n, np.float32)
+    seg_off = [0, 300, 301, 1003]
+    seg_lr = [1e-3, 2.5e-3, 1.5e-3]
+    lr_el = np.repeat(seg_lr, np.diff(seg_off))
+    tp, tm, tv = (torch.from_numpy(a.copy()).to(DEV) for a in (p, m, v))
+    step = torch.zeros(1, dtype=torch.int32, device=DEV)
+    pd, md, vd = p.astype(np.float64), m.astype(np.float64), v.astype(np.float64)
+    for t in range(1, 4):
+        g = rng.normal(size=n).astype(np.float32)
+        # both sides start each step from the same float32 state
+        pd, md, vd = (tp.cpu().numpy().astype(np.float64), tm.cpu().numpy().astype(np.float64),
+                      tv.cpu().numpy().astype(np.float64))
+        gs.adam(ctx, tp, torch.from_numpy(g).to(DEV), tm, tv, step, seg_off, seg_lr)
+        torch.cuda.synchronize()
+        # identical inputs: the kernel receives the hyper-parameters as float32
+        f32 = lambda x: float(np.float32(x))  # noqa: E731
+        oracle.adam(pd, g.astype(np.float64), md, vd, t,
+                    lr=np.asarray([f32(x) for x in lr_el]), betas=(f32(0.9), f32(0.999)),
+                    eps=f32(1e-15))
+        np.testing.assert_allclose(tm.cpu().numpy(), md, rtol=1e-6, atol=1e-7)
+        np.testing.assert_allclose(tv.cpu().numpy(), vd, rtol=1e-6, atol=1e-9)
+        np.testing.assert_allclose(tp.cpu().numpy(), pd, rtol=1e-6, atol=1e-7)
+    assert int(step.item()) == 3
+
+
+def test_graph_replay_equals_eager(gs, ctx):
+    """Every replay of the captured step gives the eager image bits and
+    gradients within tolerance (lr = 0 keeps the parameters fixed); eager work
+    and synchronisations run between the replays."""
+    P = synth.random_gaussians(1000, seed=0)
+    cam = synth.axis_camera(128, 128)
+    tgt = torch.from_numpy(_cfg1_target().reshape(-1).copy()).to(DEV)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        cfg = gs.FitConfig(lr=0.0)
+        eager = gs.FitStep(ctx, torch.from_numpy(P).to(DEV), [cam], tgt, cfg=cfg)
+        eager.step()
+        torch.cuda.synchronize()
+        img0, g0, l0 = eager.rgba.cpu().numpy(), eager.grads.cpu().numpy(), eager.loss.item()
+        cap = gs.FitStep(ctx, torch.from_numpy(P).to(DEV), [cam], tgt, cfg=cfg)
+        cap.capture()
+        for k in range(4):
+            cap.rgba.zero_()
+            cap.grads.zero_()
+            cap.replay()
+            torch.cuda.synchronize()
+            _ = (eager.params * 2).sum().item()           # unrelated eager work in between
+            np.testing.assert_array_equal(cap.rgba.cpu().numpy().view(np.uint32), img0.view(np.uint32))
+            assert cap.loss.item() == l0
+            rep = grads_close(cap.grads.cpu().numpy(), g0.astype(np.float64))
+            assert all(nb == 0 for _, nb, _ in rep), (k, rep)
+        assert int(cap.step_dev.item()) == 4
+        flags, m = cap.poll()
+        assert flags == 0 and m > 0
+
+
+def test_fit_loss_curve_matches_oracle(gs, ctx):
+    """Ten fit steps of the 1,000-Gaussian single-view workload: the GPU loss
+    curve follows the FP64 oracle's within 1e-3 relative."""
+    P = synth.random_gaussians(1000, seed=0)
+    cam = synth.axis_camera(128, 128)
+    target = _cfg1_target()
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        fs = gs.FitStep(ctx, torch.from_numpy(P).to(DEV), [cam],
+                        torch.from_numpy(target.reshape(-1).copy()).to(DEV),
+                        cfg=gs.FitConfig(lr=1e-3))
+        gpu_losses = []
+        for _ in range(10):
+            fs.step()
+            gpu_losses.append(fs.loss.item())
+    Pd = P.astype(np.float64)
+    m, v = np.zeros_like(Pd), np.zeros_like(Pd)
+    ref = [oracle.fit_step(Pd, m, v, t, [cam], [target.reshape(3, -1).astype(np.float64)])
+           for t in range(1, 11)]
+    log(f"[step] losses gpu {np.round(gpu_losses, 6)} oracle {np.round(ref, 6)}")
+    np.testing.assert_allclose(gpu_losses, ref, rtol=1e-3)
+    assert ref[-1] < ref[0]
+
+
+def test_autograd_function_matches_direct_call_and_fd(gs, ctx):
+    P = synth.random_gaussians(60, seed=4, logscale_mean=-2.2)
+    cam = synth.look_at_camera([0.5, -0.3, -3.0], width=48, height=40, bg=(0.2, 0.2, 0.2))
+    plan = gs.Plan(ctx, P.shape[1], [(cam.width, cam.height)], 0, 16, 64, host_sized=True)
+    cams = gs.cameras_to_device([cam], DEV)
+    w = torch.from_numpy(np.random.default_rng(1).normal(size=4 * cam.npix).astype(np.float32)).to(DEV)
+    prm = torch.from_numpy(P).to(DEV).requires_grad_(True)
+    img = gs.rasterize(prm, plan, cams)
+    (img * w).sum().backward()
+    G = prm.grad.cpu().numpy()
+    ref = oracle.render(P, cam)
+    assert image_close(img.detach().cpu().numpy().reshape(4, -1), ref.rgba, ref.flags)[0] == 0
+    Gref = oracle.backward(P, cam, w.cpu().numpy().astype(np.float64).reshape(4, -1))
+    rep = grads_close(G, Gref)
+    assert all(nb == 0 for _, nb, _ in rep), rep
+    # float32 central differences through the same autograd op.  Only colour
+    # coefficients: they enter the image linearly, whereas moving geometry or
+    # opacity by a finite step also moves pixels across the 1/255 cutoff, a
+    # jump the exact derivative excludes by definition (geometry is pinned by
+    # the oracle comparison above and the oracle's own FP64 differences).
+    rng = np.random.default_rng(5)
+    checked = 0
+    with torch.no_grad():
+        for _ in range(24):
+            c, i = int(rng.integers(11, 14)), int(rng.integers(0, P.shape[1]))
+            if abs(G[c, i]) < 1e-2 * np.abs(G[c]).max():
+                continue
+            h = 2e-3 * max(1.0, abs(float(P[c, i])))
+            pp, pm = prm.detach().clone(), prm.detach().clone()
+            pp[c, i] += h
+            pm[c, i] -= h
+            fd = ((gs.rasterize(pp, plan, cams) * w).sum() - (gs.rasterize(pm, plan, cams) * w).sum()).item() / (2 * h)
+            assert abs(fd - G[c, i]) <= 0.01 * abs(G[c, i]) + 1e-3 * np.abs(G[c]).max(), (c, i, fd, G[c, i])
+            checked += 1
+    assert checked >= 8
+
+
+def test_key_capacity_overflow_is_reported(gs, ctx):
+    P = synth.random_gaussians(500, seed=1)
+    cam = synth.axis_camera(64, 64)
+    sc = GpuScene(ctx, P, [cam], key_capacity=100, host_sized=True)
+    with pytest.raises(gs.GsfError) as e:
+        sc.plan.forward(sc.params, sc.n, sc.cams_dev, sc.rgba)
+    assert e.value.status == _abi.GSF_E_CAPACITY
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(sc.rgba.cpu().numpy().reshape(4, -1)[3], 0.0)   # background only
+    flags, m = sc.plan.poll()
+    assert flags & _abi.GSF_FLAG_CAPACITY and m > 100
+    dev_sized = GpuScene(ctx, P, [cam], key_capacity=100, host_sized=False)
+    dev_sized.forward()
+    flags, _ = dev_sized.plan.poll()
+    assert flags & _abi.GSF_FLAG_CAPACITY
+    assert dev_sized.plan.poll()[0] == 0      # flags are cleared by the poll
+
+
+def test_nonfinite_loss_is_flagged(gs, ctx):
+    P = synth.random_gaussians(200, seed=2)
+    cam = synth.axis_camera(32, 32)
+    sc = GpuScene(ctx, P, [cam])
+    sc.forward()
+    tgt = np.zeros((3, cam.npix), np.float32)
+    tgt[1, 17] = np.nan
+    loss = torch.zeros(1, device=DEV)
+    dl = torch.zeros(4 * cam.npix, device=DEV)
+    sc.plan.loss_l1(sc.rgba, torch.from_numpy(tgt.reshape(-1)).to(DEV), loss, dl)
+    flags, _ = sc.plan.poll()
+    assert flags & _abi.GSF_FLAG_NONFINITE
+
+
+def test_invalid_arguments_are_rejected(gs, ctx):
+    P = synth.random_gaussians(10, seed=2)
+    cam = synth.axis_camera(16, 16)
+    with pytest.raises(gs.GsfError) as e:
+        gs.Plan(ctx, 10, [(16, 16)], 0, tile=12)
+    assert e.value.status == _abi.GSF_E_INVALID
+    with pytest.raises(gs.GsfError):
+        gs.Plan(ctx, 10, [(16, 16)], 4)
+    sc = GpuScene(ctx, P, [cam])
+    with pytest.raises(gs.GsfError) as e:
+        sc.plan.backward(sc.params, 10, sc.cams_dev, torch.zeros(4 * 256, device=DEV),
+                         torch.zeros_like(sc.params))
+    assert e.value.status == _abi.GSF_E_STATE
+    with pytest.raises(gs.GsfError) as e:
+        sc.plan.forward(sc.params, 11, sc.cams_dev, sc.rgba)
+    assert e.value.status == _abi.GSF_E_INVALID
+
+
+def test_edge_cases(gs, ctx):
+    # one Gaussian; one pixel; everything behind the camera; a huge Gaussian
+    one = synth.random_gaussians(1, seed=3, logscale_mean=-1.0)
+    one[0:3, 0] = 0.0
+    for cam in (synth.axis_camera(1, 1), synth.axis_camera(37, 29, bg=(0.5, 0.25, 0.125))):
+        sc = GpuScene(ctx, one, [cam])
+        img = sc.forward()[0]
+        ref = oracle.render(one, cam)
+        assert image_close(img, ref.rgba, ref.flags)[0] == 0
+    behind = synth.random_gaussians(50, seed=4)
+    behind[2] = -4.0                                  # camera at z = -3 looks along +z
+    cam = synth.axis_camera(40, 24, bg=(0.1, 0.2, 0.3))
+    sc = GpuScene(ctx, behind, [cam])
+    img = sc.forward()[0]
+    np.testing.assert_array_equal(img[:3], np.repeat(cam.bg[:, None], cam.npix, 1))
+    np.testing.assert_array_equal(img[3], 0.0)
+    assert sc.debug(_abi.GSF_DBG_KEYS, np.uint32, 16).size == 0
+    g = sc.backward([np.ones((4, cam.npix))])
+    np.testing.assert_array_equal(g, 0.0)
+    huge = synth.random_gaussians(3, seed=5, logscale_mean=0.5)
+    cam = synth.axis_camera(96, 64)
+    for t_mode in (0, 1):
+        sc = GpuScene(ctx, huge, [cam], t_mode=t_mode, batch=64)
+        img = sc.forward()[0]
+        ref = oracle.render(huge, cam)
+        assert image_close(img, ref.rgba, ref.flags)[0] == 0
+        dl = np.random.default_rng(0).normal(size=(4, cam.npix))
+        dl[:, ref.flags != 0] = 0
+        rep = grads_close(sc.backward([dl]), oracle.backward(huge, cam, dl.astype(np.float32).astype(np.float64)))
+        assert all(nb == 0 for _, nb, _ in rep), rep
+
+
+def test_full_size_workload_sampled_against_oracle(gs, ctx):
+    """The 50,000-Gaussian 1024x1024 phantom workload in the launch
+    configuration the benchmark times (fused plan, device-sized, checkpointed
+    adjoint, tile 16, LDS batch 128): 512 sampled pixels of the image and the
+    gradient of a loss living on those pixels, against the oracle."""
+    import bench
+    P, cam, target = bench.build_workload()
+    log(f"[full] {P.shape[1]} Gaussians {cam.width}x{cam.height}")
+    sc = GpuScene(ctx, P, [cam], tile=16, batch=128, host_sized=False, t_mode=1)
+    img = sc.forward()[0]
+    rng = np.random.default_rng(11)
+    alpha_px = np.nonzero(img[3] > 0.05)[0]
+    pix = np.sort(np.concatenate([rng.choice(alpha_px, 384, replace=False),
+                                  rng.choice(cam.npix, 128, replace=False)]))
+    ref = oracle.render(P, cam, pixels=pix)
+    nbad, worst, nflag = image_close(img[:, pix], ref.rgba, ref.flags)
+    log(f"[full] image: worst {worst:.2e}, flagged {nflag}")
+    assert nbad == 0, worst
+    keep = pix[ref.flags == 0]
+    dl_sub = rng.normal(size=(4, keep.size))
+    dl_full = np.zeros((4, cam.npix))
+    dl_full[:, keep] = dl_sub
+    g = sc.backward([dl_full])
+    G = oracle.backward(P, cam, dl_sub.astype(np.float32).astype(np.float64), pixels=keep)
+    rep = grads_close(g, G)
+    log(f"[full] gradient groups {rep}")
+    assert all(nb == 0 for _, nb, _ in rep), rep

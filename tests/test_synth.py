@@ -68,3 +68,23 @@ def test_raymarch_constant_slab_closed_form():
     L = np.clip(np.min(np.maximum(ta, tb), 1) - np.max(np.minimum(ta, tb), 1), 0, None)
     np.testing.assert_allclose(img[3].reshape(-1), 1 - np.exp(-4.0 * dens * L), atol=1e-12)
     assert L.max() > 1.5
+
+
+def test_trilinear_sampler_matches_eight_corner_form():
+    vol = synth.phantom(16, seed=3)
+    p = np.random.default_rng(0).uniform(-1.1, 1.1, size=(2000, 3))
+    a, ca = synth.trilinear_sampler(vol)(p)
+    b, cb = synth.trilinear_sampler_reference(vol)(p)
+    np.testing.assert_allclose(a, b, atol=1e-12)
+    np.testing.assert_allclose(ca, cb, atol=1e-12)
+
+
+def test_c_raymarch_matches_numpy_definition():
+    vol = synth.phantom(24, seed=3)
+    cam = synth.look_at_camera([0.4, -2.5, 1.6], width=40, height=30, bg=(0.1, 0.0, 0.2))
+    ref = synth.raymarch(synth.trilinear_sampler_reference(vol), cam, step=1.0 / 24)
+    got = synth.raymarch_volume(vol, cam)
+    assert ref[3].max() > 0.3
+    np.testing.assert_allclose(got, ref, atol=2e-6)
+    rows = np.array([3, 17, 29])
+    np.testing.assert_array_equal(synth.raymarch_volume(vol, cam, rows=rows), got[:, rows])
