@@ -125,6 +125,8 @@ def main():
     ap.add_argument("--lds-batch", type=int, default=128)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use --tile/--lds-batch instead of sweeping tile x LDS batch")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -152,6 +154,15 @@ def main():
     out = {}
     with torch.cuda.stream(stream):
         ctx = gs.Context(0)
+
+        tune = None
+        if not args.no_autotune:
+            best, sweep = gs.autotune(ctx, torch.from_numpy(P).to(dev), [cam], tgt_dev, cfg=cfg,
+                                      stream=stream)
+            tune = {"best": list(best), "us_per_step": {f"{t}x{b}": round(ms * 1e3, 1)
+                                                        for (t, b), ms in sorted(sweep.items())}}
+            cfg = gs.FitConfig(lr=1e-3, tile=best[0], lds_batch=best[1])
+            log(f"[bench] autotune: best tile {best[0]} batch {best[1]}; {tune['us_per_step']}")
 
         # fused, captured
         fused = gs.FitStep(ctx, torch.from_numpy(P).to(dev), [cam], tgt_dev, cfg=cfg, fused=True)
@@ -243,7 +254,7 @@ def main():
         "config": {"workload": "phantom-seeded fit: 128^3 phantom, 50,000 Gaussians (SH0), "
                                "one 1024x1024 view, L1 vs ray-marched target, Adam lr 1e-3",
                    "gaussians": N, "views": 1, "width": cam.width, "height": cam.height,
-                   "tile": args.tile, "lds_batch": args.lds_batch, "keys_per_step": M,
+                   "tile": cfg.tile, "lds_batch": cfg.lds_batch, "keys_per_step": M,
                    "form": "fused, hipGraph-captured"},
         "mpix_per_s": round(npix * steps_per_s / 1e6, 1),
         "ms_per_100_step_fit": round(100 * ms_fused, 2),
@@ -251,6 +262,7 @@ def main():
         "plain_steps_per_s": round(1000.0 / ms_plain, 2) if ms_plain else None,
         "vs_plain": round(ms_plain / ms_fused, 3) if ms_plain else None,
         "loss_after_timed_steps": round(loss_fused, 6),
+        "autotune": tune,
         "stages": stage_roof,
         "roofline": roof,
     }

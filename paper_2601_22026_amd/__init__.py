@@ -27,8 +27,8 @@ import torch
 from . import _abi
 from ._abi import GsfError, gsf_camera, gsf_plan_desc, gsf_step_args, lib
 
-__all__ = ["GsfError", "Context", "Plan", "rasterize", "adam", "FitStep", "pack_cameras",
-           "cameras_to_device", "n_planes", "lib"]
+__all__ = ["GsfError", "Context", "Plan", "rasterize", "adam", "FitStep", "FitConfig", "autotune",
+           "pack_cameras", "cameras_to_device", "n_planes", "lib"]
 
 
 def n_planes(sh_degree: int) -> int:
@@ -367,3 +367,42 @@ class FitStep:
             flags |= f
             m += mm
         return flags, m
+
+
+_TUNE_CACHE: dict = {}
+
+
+def autotune(ctx: Context, params: torch.Tensor, cams, targets: torch.Tensor,
+             gaze: Optional[torch.Tensor] = None, cfg: FitConfig = FitConfig(),
+             tiles=(8, 16, 32), batches=(64, 128, 256), warmup: int = 3, reps: int = 10,
+             stream=None):
+    """Pick the tile size and LDS batch that make the captured fused step
+    fastest on this input shape.  Each candidate is captured once and timed
+    with HIP events over ``reps`` replays (Adam disabled so every candidate
+    sees the same parameters).  Results are cached per (n, SH degree, view
+    sizes, t_mode).  Returns (best (tile, batch), {(tile, batch): ms/step})."""
+    import dataclasses
+    key = (params.shape[1], params.shape[0], tuple((c.width, c.height) for c in cams), cfg.t_mode,
+           tuple(tiles), tuple(batches))
+    if key in _TUNE_CACHE:
+        return _TUNE_CACHE[key]
+    stream = stream or torch.cuda.current_stream()
+    times = {}
+    for t in tiles:
+        for b in batches:
+            c = dataclasses.replace(cfg, tile=t, lds_batch=b, lr=0.0)
+            fs = FitStep(ctx, params.detach().clone(), cams, targets, gaze, c, fused=True)
+            fs.capture()
+            for _ in range(warmup):
+                fs.replay()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                fs.replay()
+            e1.record(stream)
+            e1.synchronize()
+            times[(t, b)] = e0.elapsed_time(e1) / reps
+            fs.plan.close()
+    best = min(times, key=times.get)
+    _TUNE_CACHE[key] = (best, times)
+    return best, times

@@ -5,6 +5,8 @@
 // Gaussians and discarded optimiser state (Method, "Periphery Model
 // Training"); zeroing m, v and the step counter is that restart.  The step
 // counter lives in device memory so a captured step graph can be replayed.
+// In the fused step the loss reduction advances it; a standalone call
+// advances it with a one-thread kernel first.
 #include "gs_internal.h"
 
 namespace gsf {
@@ -68,8 +70,8 @@ __global__ __launch_bounds__(256) void k_adam(float *__restrict__ p, const float
 }  // namespace
 
 void launch_adam(hipStream_t s, float *p, const float *g, float *m, float *v, int64_t n,
-                 const SegTable &seg, float b1, float b2, float eps, int32_t *step) {
-    k_step_inc<<<1, 64, 0, s>>>(step);
+                 const SegTable &seg, float b1, float b2, float eps, int32_t *step, bool advance) {
+    if (advance) k_step_inc<<<1, 64, 0, s>>>(step);
     int64_t blocks = (n / 4 + 255) / 256;
     if (blocks < 1) blocks = 1;
     if (blocks > 8192) blocks = 8192;

@@ -41,13 +41,17 @@ struct ViewDesc {
 };
 
 // Per-record screen-space splat, split so that one gather is two 16-byte and
-// one 4-byte load: a = (mean x, mean y, conic A, conic B), b = (conic C,
-// opacity, red, green), c = blue.
+// one 8-byte load: a = (mean x, mean y, A2, B2), b = (C2, opacity, red, green),
+// c = (blue, tau).  The conic is stored pre-scaled so that
+// power2 = A2 dx^2 + C2 dy^2 + B2 dx dy = log2(e) * power, i.e. A2 = -log2(e) A / 2,
+// B2 = -log2(e) B, C2 = -log2(e) C / 2, and tau = log2(1 / (255 opacity)) is
+// the power2 below which alpha < 1/255.
 struct SplatPtrs {
     float4 *a;
     float4 *b;
-    float *c;
+    float2 *c;
 };
+constexpr float kLog2e = 1.4426950408889634f;
 
 struct SegTable {
     int64_t off[kMaxSeg + 1];
@@ -57,10 +61,13 @@ struct SegTable {
 
 // ---- launchers (all asynchronous on `s`) -----------------------------------------
 
-// Projection of n Gaussians into V views: records r = v*n + i.
+// Projection of n Gaussians into V views: records r = v*n + i.  Also clears
+// the record's nine screen-space gradient entries g2d[f * V*n + r] when g2d
+// is non-null.
 void launch_project_fwd(hipStream_t s, const float *P, int n, int nviews, int deg,
                         const gsf_camera *cams, const ViewDesc *views, int tile, SplatPtrs sp,
-                        uint32_t *depth_key, uint32_t *rec_idx, uint2 *rect, uint32_t *count);
+                        uint32_t *depth_key, uint32_t *rec_idx, uint2 *rect, uint32_t *count,
+                        float *g2d);
 
 // Parameter gradient from the per-record screen-space gradient g2d [9][V*n].
 void launch_project_bwd(hipStream_t s, const float *P, int n, int nviews, int deg,
@@ -120,13 +127,16 @@ void launch_count_pairs(hipStream_t s, int tile, int total_tiles, const uint2 *r
 
 // Masked L1 loss.  partial: scratch of loss_partials(total_pix) floats.
 int loss_partials(int64_t total_pix);
+// step_inc (nullable): step counter the final reduction advances by one.
 void launch_loss_l1(hipStream_t s, const float *rgba, const float *target, const float *gaze,
                     float radius_frac, const ViewDesc *views, int nviews, int64_t total_pix,
-                    float *dl, float *partial, uint32_t *mask_count, float *loss,
-                    uint32_t *flags);
+                    float *dl, float *partial, uint32_t *mask_count, float *loss, uint32_t *flags,
+                    int32_t *step_inc);
 
+// Adam with bias correction for step step[0]; when advance is true a one-thread
+// kernel first advances step[0] by one.
 void launch_adam(hipStream_t s, float *p, const float *g, float *m, float *v, int64_t n,
-                 const SegTable &seg, float b1, float b2, float eps, int32_t *step);
+                 const SegTable &seg, float b1, float b2, float eps, int32_t *step, bool advance);
 
 void launch_fill_u32(hipStream_t s, uint32_t *p, int64_t n, uint32_t value);
 void launch_fill_f32(hipStream_t s, float *p, int64_t n, float value);

@@ -33,7 +33,7 @@ namespace {
 
 struct Buffers {
     float4 *rec_a = nullptr, *rec_b = nullptr;
-    float *rec_c = nullptr;
+    float2 *rec_c = nullptr;
     uint32_t *depth_key = nullptr, *rec_idx = nullptr;   // unsorted, per record
     uint32_t *dk[2] = {nullptr, nullptr}, *di[2] = {nullptr, nullptr};  // depth sort ping-pong
     uint2 *rect = nullptr;
@@ -70,6 +70,7 @@ struct gsf_plan {
     void *ws = nullptr;
     Buffers b;
     bool have_forward = false;
+    bool g2d_clean = false;                   // the last forward cleared the screen gradient
     int64_t fwd_n = 0;
     uint32_t *order = nullptr, *keys_sorted = nullptr, *vals_sorted = nullptr;
     unsigned long long *pinned = nullptr;     // host-pinned readback of the key count
@@ -122,7 +123,7 @@ size_t carve(gsf_plan *p, char *base, Buffers *out) {
     Buffers b;
     b.rec_a = (float4 *)take(R * sizeof(float4));
     b.rec_b = (float4 *)take(R * sizeof(float4));
-    b.rec_c = (float *)take(R * sizeof(float));
+    b.rec_c = (float2 *)take(R * sizeof(float2));
     b.depth_key = (uint32_t *)take(R * 4);
     b.rec_idx = (uint32_t *)take(R * 4);
     for (int k = 0; k < 2; k++) {
@@ -244,8 +245,9 @@ gsf_status enqueue_forward(gsf_plan *p, const float *params, int64_t n, const gs
     {
         StageTimer t(p, GSF_STAGE_PROJECT);
         launch_project_fwd(s, params, (int)n, p->V, p->deg, cams, b.views, p->tile, splats(p),
-                           b.depth_key, b.rec_idx, b.rect, b.count);
+                           b.depth_key, b.rec_idx, b.rect, b.count, b.g2d);
     }
+    p->g2d_clean = true;
     GSF_LAUNCHED(ctx);
     // records in (depth, record) order
     int where;
@@ -306,10 +308,11 @@ gsf_status enqueue_forward(gsf_plan *p, const float *params, int64_t n, const gs
 }
 
 gsf_status enqueue_loss(gsf_plan *p, const float *rgba, const float *target, const float *gaze,
-                        float radius_frac, float *loss, float *dl) {
+                        float radius_frac, float *loss, float *dl, int32_t *step_inc) {
     StageTimer t(p, GSF_STAGE_LOSS);
     launch_loss_l1(p->ctx->stream, rgba, target, gaze, radius_frac, p->b.views, p->V,
-                   p->total_pix, dl, p->b.loss_partial, p->b.mask_count, loss, p->b.flags);
+                   p->total_pix, dl, p->b.loss_partial, p->b.mask_count, loss, p->b.flags,
+                   step_inc);
     GSF_LAUNCHED(p->ctx);
     return GSF_OK;
 }
@@ -318,7 +321,7 @@ gsf_status enqueue_backward(gsf_plan *p, const float *params, int64_t n, const g
                             const float *dl, float *grads) {
     hipStream_t s = p->ctx->stream;
     const int64_t nrec = n * p->V;
-    {
+    if (!p->g2d_clean) {   // a second adjoint of the same forward: clear the accumulator
         StageTimer t(p, GSF_STAGE_ZERO);
         launch_fill_f32(s, p->b.g2d, 9 * nrec, 0.f);
     }
@@ -326,6 +329,7 @@ gsf_status enqueue_backward(gsf_plan *p, const float *params, int64_t n, const g
         StageTimer t(p, GSF_STAGE_RENDER_BWD);
         launch_render_bwd(s, render_args(p, cams, n), dl, p->b.g2d);
     }
+    p->g2d_clean = false;
     GSF_LAUNCHED(p->ctx);
     {
         StageTimer t(p, GSF_STAGE_PROJECT_BWD);
@@ -369,7 +373,9 @@ gsf_status enqueue_step(gsf_plan *p, const gsf_step_args *a) {
     bool overflow = false;
     gsf_status st = enqueue_forward(p, a->params, a->n, a->cams, a->rgba, &overflow);
     if (st != GSF_OK) return st;
-    st = enqueue_loss(p, a->rgba, a->target_rgb, a->gaze_px, a->mask_radius_frac, a->loss, a->dl_drgba);
+    // the loss reduction also advances the Adam step counter of this step
+    st = enqueue_loss(p, a->rgba, a->target_rgb, a->gaze_px, a->mask_radius_frac, a->loss,
+                      a->dl_drgba, a->step_dev);
     if (st != GSF_OK) return st;
     st = enqueue_backward(p, a->params, a->n, a->cams, a->dl_drgba, a->grads);
     if (st != GSF_OK) return st;
@@ -392,7 +398,7 @@ gsf_status enqueue_step(gsf_plan *p, const gsf_step_args *a) {
     {
         StageTimer t(p, GSF_STAGE_ADAM);
         launch_adam(p->ctx->stream, a->params, a->grads, a->adam_m, a->adam_v, off[C], seg,
-                    a->beta1, a->beta2, a->eps, a->step_dev);
+                    a->beta1, a->beta2, a->eps, a->step_dev, false);
     }
     GSF_LAUNCHED(p->ctx);
     return overflow ? fail(p->ctx, GSF_E_CAPACITY, "key capacity exceeded") : GSF_OK;
@@ -564,7 +570,7 @@ gsf_status gsf_loss_l1(gsf_plan *p, const float *rgba, const float *target_rgb, 
     if (st != GSF_OK) return st;
     if (!rgba || !target_rgb || !loss || !dl_drgba) return fail(p->ctx, GSF_E_INVALID, "gsf_loss_l1: null argument");
     if (gaze_px && !(mask_radius_frac >= 0.f)) return fail(p->ctx, GSF_E_INVALID, "gsf_loss_l1: bad radius");
-    return enqueue_loss(p, rgba, target_rgb, gaze_px, mask_radius_frac, loss, dl_drgba);
+    return enqueue_loss(p, rgba, target_rgb, gaze_px, mask_radius_frac, loss, dl_drgba, nullptr);
 }
 
 gsf_status gsf_backward(gsf_plan *p, const float *params, int64_t n, const gsf_camera *cams,
@@ -588,7 +594,7 @@ gsf_status gsf_adam(gsf_ctx *ctx, float *prm, const float *g, float *m, float *v
     SegTable seg;
     gsf_status st = make_segments(ctx, n_elems, seg_off, seg_lr, n_seg, &seg);
     if (st != GSF_OK) return st;
-    launch_adam(ctx->stream, prm, g, m, v, n_elems, seg, beta1, beta2, eps, step_dev);
+    launch_adam(ctx->stream, prm, g, m, v, n_elems, seg, beta1, beta2, eps, step_dev, true);
     GSF_LAUNCHED(ctx);
     return GSF_OK;
 }
@@ -720,22 +726,25 @@ gsf_status gsf_debug_copy(gsf_plan *p, int which, void *host_dst, size_t cap, si
     case GSF_DBG_G2D: src = p->b.g2d; bytes = 9 * R * 4; break;
     case GSF_DBG_PROJ: {
         std::vector<float4> a(R), b(R);
-        std::vector<float> c(R);
+        std::vector<float2> c(R);
         std::vector<uint32_t> dk(R);
         if (R) {
             GSF_HIP(p->ctx, hipMemcpy(a.data(), p->b.rec_a, R * 16, hipMemcpyDeviceToHost));
             GSF_HIP(p->ctx, hipMemcpy(b.data(), p->b.rec_b, R * 16, hipMemcpyDeviceToHost));
-            GSF_HIP(p->ctx, hipMemcpy(c.data(), p->b.rec_c, R * 4, hipMemcpyDeviceToHost));
+            GSF_HIP(p->ctx, hipMemcpy(c.data(), p->b.rec_c, R * 8, hipMemcpyDeviceToHost));
             GSF_HIP(p->ctx, hipMemcpy(dk.data(), p->b.depth_key, R * 4, hipMemcpyDeviceToHost));
         }
         proj.resize(R * 11);
+        // the stored conic is pre-scaled by -log2(e)/2 (A, C) and -log2(e) (B)
+        const double half = -0.5 * 1.4426950408889634, full = -1.4426950408889634;
         for (size_t r = 0; r < R; r++) {
             float *o = proj.data() + 11 * r;
             const bool valid = dk[r] != 0xFFFFFFFFu;
             float depth;
             std::memcpy(&depth, &dk[r], 4);
-            const float vals[11] = {a[r].x, a[r].y, a[r].z, a[r].w, b[r].x, b[r].y, b[r].z, b[r].w,
-                                    c[r], valid ? depth : 0.f, valid ? 1.f : 0.f};
+            const float vals[11] = {a[r].x, a[r].y, (float)(a[r].z / half), (float)(a[r].w / full),
+                                    (float)(b[r].x / half), b[r].y, b[r].z, b[r].w, c[r].x,
+                                    valid ? depth : 0.f, valid ? 1.f : 0.f};
             std::memcpy(o, vals, sizeof vals);
         }
         bytes = proj.size() * 4;

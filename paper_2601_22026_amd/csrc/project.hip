@@ -229,13 +229,18 @@ __global__ __launch_bounds__(256) void k_project_fwd(const float *__restrict__ P
                                                      SplatPtrs sp, uint32_t *__restrict__ depth_key,
                                                      uint32_t *__restrict__ rec_idx,
                                                      uint2 *__restrict__ rect,
-                                                     uint32_t *__restrict__ count) {
+                                                     uint32_t *__restrict__ count,
+                                                     float *__restrict__ g2d) {
     constexpr int K = (DEG + 1) * (DEG + 1);
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= nrec) return;
     const int v = r / n;
     const int i = r - v * n;
     rec_idx[r] = (uint32_t)r;
+    if (g2d) {
+#pragma unroll
+        for (int f = 0; f < 9; f++) g2d[(size_t)f * nrec + r] = 0.f;
+    }
     const gsf_camera &cam = cams[v];
     Gauss g;
     load_gauss(P, n, i, g);
@@ -260,9 +265,10 @@ __global__ __launch_bounds__(256) void k_project_fwd(const float *__restrict__ P
         for (int k = 0; k < K; k++) acc = fmaf(P[(size_t)(11 + 3 * k + ch) * n + i], Y[k], acc);
         col[ch] = fmaxf(acc + 0.5f, 0.f);
     }
-    sp.a[r] = make_float4(p.mx, p.my, p.A, p.B);
-    sp.b[r] = make_float4(p.C, g.o, col[0], col[1]);
-    sp.c[r] = col[2];
+    // conic pre-scaled for a base-2 exponent, and the power2 at which alpha = 1/255
+    sp.a[r] = make_float4(p.mx, p.my, (-0.5f * kLog2e) * p.A, -kLog2e * p.B);
+    sp.b[r] = make_float4((-0.5f * kLog2e) * p.C, g.o, col[0], col[1]);
+    sp.c[r] = make_float2(col[2], -log2f(255.f * g.o));
     depth_key[r] = __float_as_uint(p.t[2]);
     // support box: AABB of the ellipse where o e^power >= 1/255, padded
     const float k2 = 2.f * logf(255.f * g.o);
@@ -452,14 +458,15 @@ __global__ __launch_bounds__(128) void k_project_bwd(const float *__restrict__ P
 
 void launch_project_fwd(hipStream_t s, const float *P, int n, int nviews, int deg,
                         const gsf_camera *cams, const ViewDesc *views, int tile, SplatPtrs sp,
-                        uint32_t *depth_key, uint32_t *rec_idx, uint2 *rect, uint32_t *count) {
+                        uint32_t *depth_key, uint32_t *rec_idx, uint2 *rect, uint32_t *count,
+                        float *g2d) {
     const int nrec = n * nviews;
     const dim3 grid((nrec + 255) / 256), block(256);
     switch (deg) {
-    case 0: k_project_fwd<0><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rec_idx, rect, count); break;
-    case 1: k_project_fwd<1><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rec_idx, rect, count); break;
-    case 2: k_project_fwd<2><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rec_idx, rect, count); break;
-    default: k_project_fwd<3><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rec_idx, rect, count); break;
+    case 0: k_project_fwd<0><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rec_idx, rect, count, g2d); break;
+    case 1: k_project_fwd<1><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rec_idx, rect, count, g2d); break;
+    case 2: k_project_fwd<2><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rec_idx, rect, count, g2d); break;
+    default: k_project_fwd<3><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rec_idx, rect, count, g2d); break;
     }
 }
 

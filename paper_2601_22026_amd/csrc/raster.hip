@@ -4,42 +4,48 @@
 // One workgroup per screen tile (T x T pixels, T in {8, 16, 32}); one thread
 // per pixel (T = 32: four pixels per thread).  The tile's depth-ordered list of
 // splats is staged through LDS in batches of B records (B in {64, 128, 256})
-// that every wave then reads by broadcast.  Per pixel and splat:
-//   power = -(A dx^2 + C dy^2) / 2 - B dx dy, skip if power > 0;
-//   alpha = min(0.99, o e^power), skip if alpha < 1/255;
+// that every wave then reads by broadcast.  Per pixel and splat, with the
+// projection's conic pre-scaled by log2(e) so that power2 = log2(e) * power:
+//   skip if power2 > 0 or power2 < tau, tau = log2(1 / (255 o))
+//        (the second test is o e^power < 1/255 without the exponential);
+//   alpha = min(0.99, o 2^power2);
 //   stop before the splat if T (1 - alpha) < 1e-4;
 //   C += colour alpha T;  T *= 1 - alpha.
-// A wave leaves the batch loop once all its pixels have stopped and the
-// workgroup leaves the tile once all waves have.  Because a pixel's arithmetic
-// sequence does not depend on T, B or the tile's other pixels, images are
-// bitwise independent of the tile size and the batch size.
+// A wave leaves the batch once all its pixels have stopped (checked every four
+// splats) and the workgroup leaves the tile once all waves have.  A pixel's
+// arithmetic sequence does not depend on T, B or the tile's other pixels, so
+// images are bitwise independent of the tile size and the batch size.
 //
 // The adjoint walks the same list back to front from each pixel's last
 // included splat, rebuilding the transmittance in front of each splat as
-// T_i = T_{i+1} / (1 - alpha_i) from the stored final transmittance.  The nine
-// per-splat screen-space gradient terms of a wave are summed across lanes,
-// added into an LDS accumulator per batch entry, and flushed with one global
-// atomic per (tile, splat, field).
+// T_i = T_{i+1} / (1 - alpha_i).  It either starts from the final state
+// (recompute mode, one workgroup per tile) or from (T, colour) checkpoints the
+// forward stored at every LDS-batch boundary (checkpoint mode, persistent
+// workgroups over (tile, batch) units).  The nine per-splat screen-space
+// gradient terms of a wave are summed across its lanes with DPP row
+// operations, kept per wave in LDS, and flushed with one global atomic per
+// (unit, splat, field).
 #include "gs_internal.h"
 
 namespace gsf {
 namespace {
 
-constexpr float kLog2e = 1.4426950408889634f;
+constexpr float kLn2 = 0.69314718055994531f;
 
-// Shared by the forward and backward kernels so both take identical decisions.
-__device__ __forceinline__ bool splat_alpha(const float4 &a, const float4 &b, float px, float py,
-                                            float &alpha, float &ae, float &ex, float &dx,
-                                            float &dy) {
+// Shared by every kernel that walks a tile list so all take identical decisions.
+// a = (mean x, mean y, A2, B2), b = (C2, opacity, red, green), c = (blue, tau)
+// with A2 = -log2(e) A / 2, B2 = -log2(e) B, C2 = -log2(e) C / 2.
+__device__ __forceinline__ bool splat_alpha(const float4 &a, const float4 &b, const float2 &c,
+                                            float px, float py, float &alpha, float &ae, float &ex,
+                                            float &dx, float &dy) {
     dx = px - a.x;
     dy = py - a.y;
-    const float q = fmaf(a.z * dx, dx, (b.x * dy) * dy);
-    const float power = fmaf(-0.5f, q, -((a.w * dx) * dy));
-    if (power > 0.f) return false;
-    ex = __builtin_amdgcn_exp2f(power * kLog2e);
+    const float power2 = fmaf(a.z * dx, dx, fmaf(b.x * dy, dy, (a.w * dx) * dy));
+    if (power2 > 0.f || power2 < c.y) return false;
+    ex = __builtin_amdgcn_exp2f(power2);
     ae = b.y * ex;
     alpha = fminf(kAlphaMax, ae);
-    return alpha >= kAlphaMin;
+    return true;
 }
 
 __device__ __forceinline__ int view_of_tile(const ViewDesc *__restrict__ views, int nviews, int gt) {
@@ -80,9 +86,10 @@ __global__ __launch_bounds__(T * T < 256 ? T * T : 256) void k_render_fwd(
     constexpr int NT = T * T < 256 ? T * T : 256;
     constexpr int PPT = T * T / NT;
     constexpr int ROWS = NT / T;
+    constexpr int U = 4;   // splats between wave-level completion checks
     __shared__ float4 s_a[B];
     __shared__ float4 s_b[B];
-    __shared__ float s_c[B];
+    __shared__ float2 s_c[B];
 
     const int gt = blockIdx.x;
     const int v = view_of_tile(views, nviews, gt);
@@ -116,30 +123,53 @@ __global__ __launch_bounds__(T * T < 256 ? T * T : 256) void k_render_fwd(
             s_c[j] = sp.c[r];
         }
         __syncthreads();
-        for (int j = 0; j < nb; j++) {
+        for (int j0 = 0; j0 < nb; j0 += U) {
             bool all = true;
 #pragma unroll
             for (int k = 0; k < PPT; k++) all &= done[k];
             if (__all(all)) break;
-            const float4 a = s_a[j];
-            const float4 b = s_b[j];
-            const float c2 = s_c[j];
+            const int nu = min(U, nb - j0);
+            // Phase 1: the U splats' alphas are independent of each other and of
+            // the pixel state; computed without branches (out-of-range or
+            // skipped splats get valid = false).
+            float4 a[U], b[U];
+            float2 c[U];
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                const int j = u < nu ? j0 + u : j0;
+                a[u] = s_a[j];
+                b[u] = s_b[j];
+                c[u] = s_c[j];
+            }
 #pragma unroll
             for (int k = 0; k < PPT; k++) {
-                if (done[k]) continue;
-                float alpha, ae, ex, dx, dy;
-                if (!splat_alpha(a, b, px[k], py[k], alpha, ae, ex, dx, dy)) continue;
-                const float Tn = Tr[k] * (1.f - alpha);
-                if (Tn < kTStop) {
-                    done[k] = true;
-                    continue;
+                float alpha[U];
+                bool valid[U];
+#pragma unroll
+                for (int u = 0; u < U; u++) {
+                    const float dx = px[k] - a[u].x, dy = py[k] - a[u].y;
+                    const float power2 =
+                        fmaf(a[u].z * dx, dx, fmaf(b[u].x * dy, dy, (a[u].w * dx) * dy));
+                    valid[u] = u < nu && !(power2 > 0.f) && !(power2 < c[u].y);
+                    alpha[u] = fminf(kAlphaMax, b[u].y * __builtin_amdgcn_exp2f(power2));
                 }
-                const float w = alpha * Tr[k];
-                cr[k] = fmaf(b.z, w, cr[k]);
-                cg[k] = fmaf(b.w, w, cg[k]);
-                cb[k] = fmaf(c2, w, cb[k]);
-                Tr[k] = Tn;
-                last[k] = bs + (uint32_t)j - rg.x + 1u;
+                // Phase 2: the sequential front-to-back update, with selects.
+                // An included splat performs exactly the float operations of the
+                // definition (Tn = T (1 - alpha), w = alpha T, C += colour w).
+#pragma unroll
+                for (int u = 0; u < U; u++) {
+                    const float Tn = Tr[k] * (1.f - alpha[u]);
+                    const bool take = valid[u] && !done[k];
+                    const bool stop = take && Tn < kTStop;
+                    const bool inc = take && !stop;
+                    const float w = alpha[u] * Tr[k];
+                    cr[k] = inc ? fmaf(b[u].z, w, cr[k]) : cr[k];
+                    cg[k] = inc ? fmaf(b[u].w, w, cg[k]) : cg[k];
+                    cb[k] = inc ? fmaf(c[u].x, w, cb[k]) : cb[k];
+                    Tr[k] = inc ? Tn : Tr[k];
+                    last[k] = inc ? bs + (uint32_t)(j0 + u) - rg.x + 1u : last[k];
+                    done[k] = done[k] || stop;
+                }
             }
         }
         if (CKPT && bs + B < rg.y) {
@@ -184,8 +214,8 @@ __device__ __forceinline__ void render_bwd_unit(
     int nviews, const gsf_camera *__restrict__ cams, const float *__restrict__ tfinal,
     const uint32_t *__restrict__ ncontrib, const float4 *__restrict__ fstate,
     const float4 *__restrict__ ckpt, const float *__restrict__ dl, float *__restrict__ g2d,
-    int nrec, float4 *s_a, float4 *s_b, float *s_c, uint32_t *s_r,
-    float (*s_g)[9][B], uint32_t *s_nmax) {
+    int nrec, float4 *s_a, float4 *s_b, float2 *s_c, uint32_t *s_r, float (*s_g)[9][B],
+    uint32_t *s_nmax) {
     constexpr int NT = T * T < 256 ? T * T : 256;
     constexpr int PPT = T * T / NT;
     constexpr int ROWS = NT / T;
@@ -206,10 +236,11 @@ __device__ __forceinline__ void render_bwd_unit(
 #pragma unroll
     for (int k = 0; k < PPT; k++) {
         const int x = tx * T + lx, y = ty * T + ly + k * ROWS;
+        const bool inside = x < vd.width && y < vd.height;
+        const size_t q = inside ? (size_t)y * vd.width + x : 0;
         px[k] = (float)x + 0.5f;
         py[k] = (float)y + 0.5f;
-        if (x < vd.width && y < vd.height) {
-            const size_t q = (size_t)y * vd.width + x;
+        if (inside) {
             Tf[k] = tfinal[vd.pix_off + q];
             nc[k] = ncontrib[vd.pix_off + q];
             g0[k] = dimg[q];
@@ -224,7 +255,7 @@ __device__ __forceinline__ void render_bwd_unit(
         const float gbg = Tf[k] * (g0[k] * bg0 + g1[k] * bg1 + g2[k] * bg2);
         if (CKPT && !last_unit && rg.x + nc[k] > us) {
             // colour behind the unit = final colour - colour accumulated at its end
-            const float4 fs = fstate[vd.pix_off + (x < vd.width && y < vd.height ? (size_t)y * vd.width + x : 0)];
+            const float4 fs = fstate[vd.pix_off + q];
             const float4 cp = ckpt[(size_t)(ue / B) * (T * T) + threadIdx.x + k * NT];
             Tr[k] = cp.x;
             gR[k] = gbg + g0[k] * (fs.y - cp.y) + g1[k] * (fs.z - cp.z) + g2[k] * (fs.w - cp.w);
@@ -259,7 +290,7 @@ __device__ __forceinline__ void render_bwd_unit(
             const uint32_t pos = bs + (uint32_t)j - rg.x;   // list position in the tile
             const float4 a = s_a[j];
             const float4 b = s_b[j];
-            const float c2 = s_c[j];
+            const float2 c = s_c[j];
             float acc[9];
 #pragma unroll
             for (int f = 0; f < 9; f++) acc[f] = 0.f;
@@ -268,11 +299,11 @@ __device__ __forceinline__ void render_bwd_unit(
             for (int k = 0; k < PPT; k++) {
                 if (pos >= nc[k]) continue;
                 float alpha, ae, ex, dx, dy;
-                if (!splat_alpha(a, b, px[k], py[k], alpha, ae, ex, dx, dy)) continue;
+                if (!splat_alpha(a, b, c, px[k], py[k], alpha, ae, ex, dx, dy)) continue;
                 any = true;
                 const float inv = __builtin_amdgcn_rcpf(1.f - alpha);   // alpha <= 0.99
                 const float Tb = Tr[k] * inv;
-                const float gc = g0[k] * b.z + g1[k] * b.w + g2[k] * c2;
+                const float gc = g0[k] * b.z + g1[k] * b.w + g2[k] * c.x;
                 const float dalpha = Tb * gc - (gR[k] - gA[k] * Tf[k]) * inv;
                 const float wT = alpha * Tb;
                 acc[6] += wT * g0[k];
@@ -281,13 +312,15 @@ __device__ __forceinline__ void render_bwd_unit(
                 gR[k] = fmaf(gc, wT, gR[k]);
                 Tr[k] = Tb;
                 if (ae > kAlphaMax) continue;      // clamped alpha: no gradient to o, power
-                const float dpw = ae * dalpha;
+                const float dpw = ae * dalpha;     // d loss / d power (natural units)
                 acc[5] += ex * dalpha;
                 acc[2] += -0.5f * dx * dx * dpw;
                 acc[3] += -dx * dy * dpw;
                 acc[4] += -0.5f * dy * dy * dpw;
-                acc[0] += (a.z * dx + a.w * dy) * dpw;
-                acc[1] += (a.w * dx + b.x * dy) * dpw;
+                // d power / d mean = (A dx + B dy, B dx + C dy) = -ln2 (2 A2 dx + B2 dy, ...)
+                const float s2 = -kLn2 * dpw;
+                acc[0] += (2.f * a.z * dx + a.w * dy) * s2;
+                acc[1] += (a.w * dx + 2.f * b.x * dy) * s2;
             }
             if (__any(any)) {
                 const int w = threadIdx.x >> 6;
@@ -320,7 +353,7 @@ __global__ __launch_bounds__(T * T < 256 ? T * T : 256) void k_render_bwd(
     constexpr int NT = T * T < 256 ? T * T : 256;
     __shared__ float4 s_a[B];
     __shared__ float4 s_b[B];
-    __shared__ float s_c[B];
+    __shared__ float2 s_c[B];
     __shared__ uint32_t s_r[B];
     __shared__ float s_g[NT / 64][9][B];
     __shared__ uint32_t s_nmax;
@@ -344,7 +377,7 @@ __global__ __launch_bounds__(T * T < 256 ? T * T : 256) void k_render_bwd_ckpt(
     constexpr int NT = T * T < 256 ? T * T : 256;
     __shared__ float4 s_a[B];
     __shared__ float4 s_b[B];
-    __shared__ float s_c[B];
+    __shared__ float2 s_c[B];
     __shared__ uint32_t s_r[B];
     __shared__ float s_g[NT / 64][9][B];
     __shared__ uint32_t s_nmax;
@@ -399,7 +432,7 @@ __global__ __launch_bounds__(T * T < 256 ? T * T : 256) void k_count_pairs(
             const uint32_t r = vals[e];
             visit++;
             float alpha, ae, ex, dx, dy;
-            if (!splat_alpha(sp.a[r], sp.b[r], px, py, alpha, ae, ex, dx, dy)) continue;
+            if (!splat_alpha(sp.a[r], sp.b[r], sp.c[r], px, py, alpha, ae, ex, dx, dy)) continue;
             const float Tn = Tr * (1.f - alpha);
             if (Tn < kTStop) break;
             Tr = Tn;
@@ -456,16 +489,18 @@ __global__ __launch_bounds__(kLossBlock) void k_loss_count(const float *__restri
     if (threadIdx.x == 0 && s_cnt) atomicAdd(mask_count, s_cnt);
 }
 
-__global__ __launch_bounds__(kLossBlock) void k_loss_l1(const float *__restrict__ rgba,
-                                                        const float *__restrict__ target,
-                                                        const float *__restrict__ gaze,
-                                                        float radius_frac,
-                                                        const ViewDesc *__restrict__ views,
-                                                        int nviews, int64_t total_pix,
-                                                        const uint32_t *__restrict__ mask_count,
-                                                        float *__restrict__ dl,
-                                                        float *__restrict__ partial) {
-    __shared__ float s_wave[kLossBlock / 64];
+// Per-pixel L1 terms and sign gradient, and one partial sum per workgroup.
+// The count of masked entries comes from mask_count (device) or count_host.
+// (A last-workgroup-done reduction would need an agent-scope release fence per
+// workgroup, which writes back the L2 just filled with dL/dRGBA; a second
+// one-workgroup kernel is cheaper.)
+__global__ __launch_bounds__(kLossBlock) void k_loss_l1(
+    const float *__restrict__ rgba, const float *__restrict__ target, const float *__restrict__ gaze,
+    float radius_frac, const ViewDesc *__restrict__ views, int nviews, int64_t total_pix,
+    const uint32_t *__restrict__ mask_count, uint32_t count_host, float *__restrict__ dl,
+    float *__restrict__ partial) {
+    __shared__ float s_red[kLossBlock];
+    const uint32_t cnt = mask_count ? *mask_count : count_host;
     const int64_t p = (int64_t)blockIdx.x * kLossBlock + threadIdx.x;
     float s = 0.f;
     if (p < total_pix) {
@@ -478,7 +513,7 @@ __global__ __launch_bounds__(kLossBlock) void k_loss_l1(const float *__restrict_
         const float *tgt = target + 3 * (size_t)vd.pix_off;
         float *g = dl + 4 * (size_t)vd.pix_off;
         const bool in = in_fovea(gaze, v, x, y, radius_frac * (float)vd.width);
-        const float inv = 1.f / (float)max(*mask_count, 1u);
+        const float inv = 1.f / (float)max(cnt, 1u);
 #pragma unroll
         for (int c = 0; c < 3; c++) {
             const float d = img[c * plane + q] - tgt[c * plane + q];
@@ -491,34 +526,37 @@ __global__ __launch_bounds__(kLossBlock) void k_loss_l1(const float *__restrict_
         }
         g[3 * plane + q] = 0.f;
     }
-    // deterministic block reduction
-    for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
-    if (__lane_id() == 0) s_wave[threadIdx.x >> 6] = s;
+    s_red[threadIdx.x] = s;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        float t = 0.f;
-        for (int w = 0; w < kLossBlock / 64; w++) t += s_wave[w];
-        partial[blockIdx.x] = t;
+    for (int o = kLossBlock / 2; o >= 1; o >>= 1) {
+        if ((int)threadIdx.x < o) s_red[threadIdx.x] += s_red[threadIdx.x + o];
+        __syncthreads();
     }
+    if (threadIdx.x == 0) partial[blockIdx.x] = s_red[0];
 }
 
+// Sum of the partials in a fixed order (deterministic) -> loss; optionally
+// advances the optimiser step counter (the fit step's Adam runs after it).
 __global__ __launch_bounds__(1024) void k_loss_final(const float *__restrict__ partial, int nparts,
                                                      const uint32_t *__restrict__ mask_count,
-                                                     float *__restrict__ loss,
-                                                     uint32_t *__restrict__ flags) {
+                                                     uint32_t count_host, float *__restrict__ loss,
+                                                     uint32_t *__restrict__ flags,
+                                                     int32_t *__restrict__ step_inc) {
     __shared__ float s_part[1024];
     float s = 0.f;
     for (int k = threadIdx.x; k < nparts; k += 1024) s += partial[k];
     s_part[threadIdx.x] = s;
     __syncthreads();
     for (int o = 512; o >= 1; o >>= 1) {
-        if (threadIdx.x < o) s_part[threadIdx.x] += s_part[threadIdx.x + o];
+        if ((int)threadIdx.x < o) s_part[threadIdx.x] += s_part[threadIdx.x + o];
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        const float L = s_part[0] / (float)max(*mask_count, 1u);
+        const uint32_t cnt = mask_count ? *mask_count : count_host;
+        const float L = s_part[0] / (float)max(cnt, 1u);
         loss[0] = L;
         if (!isfinite(L)) atomicOr(flags, GSF_FLAG_NONFINITE);
+        if (step_inc) step_inc[0] = step_inc[0] + 1;
     }
 }
 
@@ -604,17 +642,18 @@ int loss_partials(int64_t total_pix) { return (int)((total_pix + kLossBlock - 1)
 
 void launch_loss_l1(hipStream_t s, const float *rgba, const float *target, const float *gaze,
                     float radius_frac, const ViewDesc *views, int nviews, int64_t total_pix,
-                    float *dl, float *partial, uint32_t *mask_count, float *loss, uint32_t *flags) {
+                    float *dl, float *partial, uint32_t *mask_count, float *loss, uint32_t *flags,
+                    int32_t *step_inc) {
     const int nb = loss_partials(total_pix);
     if (gaze) {
         k_fill_u32<<<1, 64, 0, s>>>(mask_count, 1, 0u);
         k_loss_count<<<nb, kLossBlock, 0, s>>>(gaze, radius_frac, views, nviews, total_pix, mask_count);
-    } else {
-        k_fill_u32<<<1, 64, 0, s>>>(mask_count, 1, (uint32_t)(3 * total_pix));
     }
-    k_loss_l1<<<nb, kLossBlock, 0, s>>>(rgba, target, gaze, radius_frac, views, nviews, total_pix,
-                                        mask_count, dl, partial);
-    k_loss_final<<<1, 1024, 0, s>>>(partial, nb, mask_count, loss, flags);
+    const uint32_t *mc = gaze ? mask_count : nullptr;
+    const uint32_t cnt = (uint32_t)(3 * total_pix);
+    k_loss_l1<<<nb, kLossBlock, 0, s>>>(rgba, target, gaze, radius_frac, views, nviews, total_pix, mc,
+                                        cnt, dl, partial);
+    k_loss_final<<<1, 1024, 0, s>>>(partial, nb, mc, cnt, loss, flags, step_inc);
 }
 
 void launch_fill_u32(hipStream_t s, uint32_t *p, int64_t n, uint32_t value) {
