@@ -70,14 +70,16 @@ def time_steps(fn, steps, stream):
     return e0.elapsed_time(e1) / steps
 
 
-def hbm_bytes_per_launch(stage, N, M, npix, planes, depth_passes, tile_passes):
+def hbm_bytes_per_launch(stage, N, M, npix, planes, tiles):
     """Algorithmic HBM bytes one launch of a stage must move."""
     rec = N  # one view
+    passes = (max(1, (tiles - 1).bit_length()) + 7) // 8
     return {
-        "project": planes * 4 * N + 52 * rec,                  # params in; records out
-        "depth_sort": depth_passes * 20 * rec,                  # hist read + key/val read/write
-        "duplicate": 16 * rec + 8 * M,                          # order/count/rect in; keys out
-        "tile_sort": tile_passes * 20 * M,
+        "project": planes * 4 * N + 92 * rec,                # params in; splat, key, box, count, g2d clear
+        "duplicate": 16 * rec + 8 * M + 8 * tiles,           # counts (twice), boxes in; pairs out; ranges cleared
+        "tile_sort": passes * 20 * M,                        # per pass: key histogram, pair in, pair out
+        "ranges": 4 * M + 8 * tiles,                         # sorted tile ids in; ranges out
+        "depth_sort": 12 * M,                                # record ids in, depth gather, record ids out
         "loss": 40 * npix,
         "project_bwd": planes * 4 * N + 36 * rec + planes * 4 * N,
         "adam": 28 * planes * N,
@@ -127,7 +129,20 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use --tile/--lds-batch instead of sweeping tile x LDS batch")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only copy a 256 MiB device buffer 5 times (reference for HBM byte "
+                         "counters) and exit")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        x = torch.ones(64 << 20, dtype=torch.float32, device="cuda:0")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read_per_launch": x.numel() * 4,
+                          "copy_bytes_written_per_launch": x.numel() * 4, "launches": 5}))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
               "sharding of this path is described in DESIGN.md but not built.", file=sys.stderr)
@@ -207,9 +222,7 @@ def main():
 
     # roofline of the dominant kernel
     dom = max(stages, key=stages.get)
-    depth_passes = 4
-    tile_bits = max(1, int(np.ceil(np.log2(fused.plan.total_tiles))))
-    tile_passes = (tile_bits + 7) // 8
+    tiles = fused.plan.total_tiles
     if dom in ("render", "render_bwd"):
         if dom == "render":
             flops = FLOPS_ALPHA * pairs["visited_fwd"] + FLOPS_FWD_INCLUDED * pairs["included"]
@@ -220,7 +233,7 @@ def main():
                 "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_TFLOPS, 4), "traffic": None,
                 "work": {"flops_per_launch": int(flops), **pairs}}
     else:
-        byt = hbm_bytes_per_launch(dom, N, M, npix, planes, depth_passes, tile_passes)
+        byt = hbm_bytes_per_launch(dom, N, M, npix, planes, tiles)
         ach = byt / (stages[dom] * 1e-3) / 1e9
         roof = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS,
                 "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": None}
@@ -232,7 +245,7 @@ def main():
                   FLOPS_ALPHA * pairs["visited_bwd"] + FLOPS_BWD_INCLUDED * pairs["included"])
             stage_roof[k] = {"us": round(ms * 1e3, 2), "tflops": round(fl / (ms * 1e-3) / 1e12, 3)}
         else:
-            byt = hbm_bytes_per_launch(k, N, M, npix, planes, depth_passes, tile_passes)
+            byt = hbm_bytes_per_launch(k, N, M, npix, planes, tiles)
             stage_roof[k] = {"us": round(ms * 1e3, 2)}
             if byt:
                 stage_roof[k]["gbs"] = round(byt / (ms * 1e-3) / 1e9, 1)

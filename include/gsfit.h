@@ -196,13 +196,13 @@ gsf_status gsf_step_replay(gsf_plan *plan);
 /* Per-stage GPU timing of eager calls on a plan (hipEvents recorded around each
  * stage on the context stream; not available while capturing).  Enabling
  * resets the accumulators.  Stages holding exactly one kernel: PROJECT,
- * RENDER, RENDER_BWD, PROJECT_BWD. */
+ * RANGES, DEPTH_SORT, RENDER, RENDER_BWD, PROJECT_BWD. */
 enum {
     GSF_STAGE_PROJECT = 0,     /* projection + support boxes (one kernel) */
-    GSF_STAGE_DEPTH_SORT = 1,  /* radix sort of records by depth */
-    GSF_STAGE_DUPLICATE = 2,   /* scan of tile counts + key duplication */
-    GSF_STAGE_TILE_SORT = 3,   /* radix sort of keys by tile */
-    GSF_STAGE_RANGES = 4,      /* per-tile ranges */
+    GSF_STAGE_DUPLICATE = 1,   /* scan of the per-record tile counts + key emission */
+    GSF_STAGE_TILE_SORT = 2,   /* stable radix sort of the keys by tile */
+    GSF_STAGE_RANGES = 3,      /* per-tile ranges from the key boundaries (one kernel) */
+    GSF_STAGE_DEPTH_SORT = 4,  /* per-tile stable LDS radix sort by depth (one kernel) */
     GSF_STAGE_RENDER = 5,      /* forward compositing (one kernel) */
     GSF_STAGE_LOSS = 6,        /* masked L1 loss */
     GSF_STAGE_RENDER_BWD = 7,  /* compositing adjoint (one kernel) */

@@ -25,7 +25,7 @@ EXPORTED = ["gsf_ctx_create", "gsf_ctx_destroy", "gsf_ctx_set_stream", "gsf_last
             "gsf_adam", "gsf_step", "gsf_step_capture", "gsf_step_replay", "gsf_poll",
             "gsf_debug_copy", "gsf_plan_set_timing", "gsf_plan_stage_times",
             "gsf_count_pairs"]
-STAGES = ["project", "depth_sort", "duplicate", "tile_sort", "ranges", "render", "loss",
+STAGES = ["project", "duplicate", "tile_sort", "ranges", "depth_sort", "render", "loss",
           "render_bwd", "project_bwd", "adam", "zero"]
 
 

@@ -21,13 +21,6 @@ constexpr float kBoxAbs = 1.0f / 64.0f;      // support-box padding, pixels
 
 constexpr int kMaxViews = 64;
 constexpr int kMaxSeg = 16;
-constexpr int kSortBlock = 256;              // threads per radix-sort block (4 waves)
-constexpr int kSortIpt = 8;                  // keys per thread per tile
-constexpr int kSortTile = kSortBlock * kSortIpt;
-constexpr int kSortMaxGrid = 1024;
-constexpr int kScanBlock = 256;
-constexpr int kScanIpt = 8;
-constexpr int kScanTile = kScanBlock * kScanIpt;
 
 // Per-view launch descriptor (device copy made at plan creation).
 struct ViewDesc {
@@ -61,40 +54,47 @@ struct SegTable {
 
 // ---- launchers (all asynchronous on `s`) -----------------------------------------
 
-// Projection of n Gaussians into V views: records r = v*n + i.  Also clears
-// the record's nine screen-space gradient entries g2d[f * V*n + r] when g2d
-// is non-null.
+// Projection of n Gaussians into V views: records r = v*n + i.  Writes the
+// splat, the depth key (float32 bits of the camera depth, 0xFFFFFFFF when
+// culled), the touched tile rectangle and its tile count, and clears the
+// record's nine screen-space gradient entries g2d[f * V*n + r] when g2d is
+// non-null.
 void launch_project_fwd(hipStream_t s, const float *P, int n, int nviews, int deg,
                         const gsf_camera *cams, const ViewDesc *views, int tile, SplatPtrs sp,
-                        uint32_t *depth_key, uint32_t *rec_idx, uint2 *rect, uint32_t *count,
-                        float *g2d);
+                        uint32_t *depth_key, uint2 *rect, uint32_t *count, float *g2d);
 
 // Parameter gradient from the per-record screen-space gradient g2d [9][V*n].
 void launch_project_bwd(hipStream_t s, const float *P, int n, int nviews, int deg,
                         const gsf_camera *cams, const float *g2d, float *grads);
 
-// Stable radix sort of (key, value) pairs by their `bits` low key bits.  The
-// count comes from n_dev (device) when non-null, else n_host.  Pass 0 reads
-// (kin, vin) and writes (ka, va); later passes alternate between (ka, va) and
-// (kb, vb), which may alias (kin, vin).  Returns 0 if the result is in
-// (kin, vin) (no pass), 1 for (ka, va), 2 for (kb, vb).
+// Exclusive scan of the per-record tile counts and key emission in record
+// order (key = global tile id, value = record id).  Writes the key total to
+// m_total and (0 on overflow, with GSF_FLAG_CAPACITY) to m_dev; emits nothing on
+// overflow.  Clears ranges[total_tiles].  block_sums: scan_blocks(nrec) words.
+void launch_scan_duplicate(hipStream_t s, const uint32_t *count, const uint2 *rect, int nrec, int n,
+                           const ViewDesc *views, uint32_t *block_sums, uint32_t *keys,
+                           uint32_t *vals, uint32_t *m_dev, unsigned long long *m_total,
+                           uint32_t *flags, int64_t capacity, uint2 *ranges, int total_tiles);
+int scan_blocks(int64_t nrec);
+
+// Stable LSD radix sort of (key, value) pairs by the low `bits` key bits; the
+// count is read from n_dev (or n_host when n_dev is null).  Passes write a, b,
+// a, ... (b may alias the input); returns 1 when the result is in (ka, va), 2
+// when in (kb, vb).  hist: 256 * grid words; digit_tot: 256 words.
 int launch_radix_sort(hipStream_t s, const uint32_t *kin, const uint32_t *vin, uint32_t *ka,
                       uint32_t *va, uint32_t *kb, uint32_t *vb, const uint32_t *n_dev,
                       uint32_t n_host, int bits, int grid, uint32_t *hist, uint32_t *digit_tot);
 int radix_grid_for(int64_t capacity);
 
-// Exclusive scan of count[order[j]] (j < nrec) and duplication of one key per
-// touched tile: keys = global tile id, vals = record id, in depth order.
-// Writes the key count to m_dev (0 and GSF_FLAG_CAPACITY on overflow) and the
-// unclamped total to m_total.
-void launch_scan_duplicate(hipStream_t s, const uint32_t *order, const uint32_t *count,
-                           const uint2 *rect, int nrec, int n, const ViewDesc *views, int nviews,
-                           uint32_t *block_sums, uint32_t *keys, uint32_t *vals, uint32_t *m_dev,
-                           unsigned long long *m_total, uint32_t *flags, int64_t capacity);
+// ranges[t] = [lower_bound(t), lower_bound(t + 1)) in the sorted keys for every
+// tile (ranges cleared beforehand).
+void launch_tile_bounds(hipStream_t s, const uint32_t *keys, const uint32_t *m_dev, uint32_t m_host,
+                        int64_t capacity, int total_tiles, uint2 *ranges);
 
-// [start, end) of every global tile in the sorted keys.
-void launch_tile_ranges(hipStream_t s, const uint32_t *keys, const uint32_t *m_dev,
-                        uint32_t m_host, int total_tiles, uint2 *ranges);
+// Stable per-tile sort of vals by depth_key[val]; gk0, gk1, gv1: key-capacity
+// scratch for lists longer than the LDS capacity.
+void launch_tile_sort(hipStream_t s, const uint2 *ranges, int total_tiles, const uint32_t *depth_key,
+                      uint32_t *vals, uint32_t *gk0, uint32_t *gk1, uint32_t *gv1);
 
 // Everything the compositing kernels share.
 struct RenderArgs {

@@ -4,8 +4,8 @@
 // degree, tile size, LDS batch and key capacity, carves the caller-owned
 // workspace into the buffers of the pipeline and enqueues the kernels:
 //
-//   forward   project -> depth radix sort -> scan + duplicate -> tile radix sort
-//             -> tile ranges -> composite
+//   forward   project (+ per-tile key counts) -> scan of the tile counts (ranges)
+//             -> place keys in their tile ranges -> per-tile sort by depth -> composite
 //   loss      masked L1 -> dL/dRGBA
 //   backward  zero screen-space gradient -> composite adjoint -> projection adjoint
 //   adam      step counter + update
@@ -32,20 +32,27 @@ struct gsf_ctx {
 namespace {
 
 struct Buffers {
+    // per record (view v, Gaussian i)
     float4 *rec_a = nullptr, *rec_b = nullptr;
     float2 *rec_c = nullptr;
-    uint32_t *depth_key = nullptr, *rec_idx = nullptr;   // unsorted, per record
-    uint32_t *dk[2] = {nullptr, nullptr}, *di[2] = {nullptr, nullptr};  // depth sort ping-pong
-    uint2 *rect = nullptr;
-    uint32_t *count = nullptr;
-    uint32_t *block_sums = nullptr;
-    uint32_t *keys[2] = {nullptr, nullptr}, *vals[2] = {nullptr, nullptr};
+    uint32_t *depth_key = nullptr;               // float32 depth bits; 0xFFFFFFFF = culled
+    uint2 *rect = nullptr;                       // touched tile rectangle
+    uint32_t *count = nullptr;                   // touched tiles
+    uint32_t *block_sums = nullptr;              // scan of the per-record tile counts
+    // per global tile
     uint2 *ranges = nullptr;
+    // per key (key capacity): two (tile id, record id) buffers for the radix
+    // sort.  After the sort, `vals` is the sorted record-id list the compositing
+    // reads; the rest is scratch for per-tile lists longer than the LDS sort holds.
+    uint32_t *k0 = nullptr, *v0 = nullptr, *k1 = nullptr, *v1 = nullptr;
+    uint32_t *keys = nullptr, *vals = nullptr;   // sorted pair (aliases k0/v0 or k1/v1)
+    uint32_t *ok = nullptr, *ov = nullptr;       // the other pair
+    uint32_t *hist = nullptr, *digit_tot = nullptr;   // radix-sort histograms
+    // per pixel
     float *tfinal = nullptr;
     uint32_t *ncontrib = nullptr;
     float4 *ckpt = nullptr, *fstate = nullptr;   // checkpoint mode only
     float *g2d = nullptr;
-    uint32_t *hist = nullptr, *digit_tot = nullptr;
     uint32_t *m_dev = nullptr, *flags = nullptr, *mask_count = nullptr;
     unsigned long long *m_total = nullptr;
     unsigned long long *counters = nullptr;
@@ -64,7 +71,7 @@ struct gsf_plan {
     int64_t cap = 0;
     std::vector<ViewDesc> views;
     int64_t total_tiles = 0, total_pix = 0, nrec_max = 0;
-    int tile_bits = 0, grid_depth = 1, grid_tile = 1, bwd_grid = 1;
+    int tile_bits = 0, radix_grid = 1, bwd_grid = 1;
     uint32_t m_host = 0;                      // key count of the last host-sized forward
     size_t ws_bytes = 0;
     void *ws = nullptr;
@@ -72,7 +79,6 @@ struct gsf_plan {
     bool have_forward = false;
     bool g2d_clean = false;                   // the last forward cleared the screen gradient
     int64_t fwd_n = 0;
-    uint32_t *order = nullptr, *keys_sorted = nullptr, *vals_sorted = nullptr;
     unsigned long long *pinned = nullptr;     // host-pinned readback of the key count
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -125,19 +131,23 @@ size_t carve(gsf_plan *p, char *base, Buffers *out) {
     b.rec_b = (float4 *)take(R * sizeof(float4));
     b.rec_c = (float2 *)take(R * sizeof(float2));
     b.depth_key = (uint32_t *)take(R * 4);
-    b.rec_idx = (uint32_t *)take(R * 4);
-    for (int k = 0; k < 2; k++) {
-        b.dk[k] = (uint32_t *)take(R * 4);
-        b.di[k] = (uint32_t *)take(R * 4);
-    }
     b.rect = (uint2 *)take(R * sizeof(uint2));
     b.count = (uint32_t *)take(R * 4);
-    b.block_sums = (uint32_t *)take(((R + kScanTile - 1) / kScanTile + 1) * 4);
-    for (int k = 0; k < 2; k++) {
-        b.keys[k] = (uint32_t *)take((size_t)p->cap * 4);
-        b.vals[k] = (uint32_t *)take((size_t)p->cap * 4);
-    }
-    b.ranges = (uint2 *)take((size_t)p->total_tiles * sizeof(uint2));
+    const size_t T = (size_t)p->total_tiles;
+    b.block_sums = (uint32_t *)take((size_t)scan_blocks(p->nrec_max) * 4);
+    b.ranges = (uint2 *)take(T * sizeof(uint2));
+    b.k0 = (uint32_t *)take((size_t)p->cap * 4);
+    b.v0 = (uint32_t *)take((size_t)p->cap * 4);
+    b.k1 = (uint32_t *)take((size_t)p->cap * 4);
+    b.v1 = (uint32_t *)take((size_t)p->cap * 4);
+    // passes write (k1, v1), (k0, v0), ...: an odd pass count ends in (k1, v1)
+    const bool odd = ((p->tile_bits + 7) / 8) % 2 == 1;
+    b.keys = odd ? b.k1 : b.k0;
+    b.vals = odd ? b.v1 : b.v0;
+    b.ok = odd ? b.k0 : b.k1;
+    b.ov = odd ? b.v0 : b.v1;
+    b.hist = (uint32_t *)take((size_t)256 * p->radix_grid * 4);
+    b.digit_tot = (uint32_t *)take(256 * 4);
     b.tfinal = (float *)take((size_t)p->total_pix * 4);
     b.ncontrib = (uint32_t *)take((size_t)p->total_pix * 4);
     if (p->t_mode == 1) {
@@ -145,8 +155,6 @@ size_t carve(gsf_plan *p, char *base, Buffers *out) {
         b.fstate = (float4 *)take((size_t)p->total_pix * sizeof(float4));
     }
     b.g2d = (float *)take(9 * R * 4);
-    b.hist = (uint32_t *)take((size_t)256 * kSortMaxGrid * 4);
-    b.digit_tot = (uint32_t *)take(256 * 4);
     b.m_dev = (uint32_t *)take(4);
     b.flags = (uint32_t *)take(4);
     b.mask_count = (uint32_t *)take(4);
@@ -176,7 +184,7 @@ RenderArgs render_args(gsf_plan *p, const gsf_camera *cams, int64_t n) {
     a.ckpt_mode = p->t_mode == 1;
     a.bwd_grid = p->bwd_grid;
     a.ranges = p->b.ranges;
-    a.vals = p->vals_sorted;
+    a.vals = p->b.vals;
     a.sp = splats(p);
     a.views = p->b.views;
     a.cams = cams;
@@ -242,59 +250,42 @@ gsf_status enqueue_forward(gsf_plan *p, const float *params, int64_t n, const gs
         gsf_status fs = flush_timing(p);
         if (fs != GSF_OK) return fs;
     }
-    {
+    {   // splats, support boxes, depth keys; clears the screen gradient
         StageTimer t(p, GSF_STAGE_PROJECT);
         launch_project_fwd(s, params, (int)n, p->V, p->deg, cams, b.views, p->tile, splats(p),
-                           b.depth_key, b.rec_idx, b.rect, b.count, b.g2d);
+                           b.depth_key, b.rect, b.count, b.g2d);
     }
     p->g2d_clean = true;
     GSF_LAUNCHED(ctx);
-    // records in (depth, record) order
-    int where;
-    {
-        StageTimer t(p, GSF_STAGE_DEPTH_SORT);
-        where = launch_radix_sort(s, b.depth_key, b.rec_idx, b.dk[0], b.di[0], b.dk[1], b.di[1],
-                                  nullptr, (uint32_t)nrec, 32, p->grid_depth, b.hist, b.digit_tot);
-    }
-    GSF_LAUNCHED(ctx);
-    p->order = where == 0 ? b.rec_idx : b.di[where - 1];
-    {
+    {   // one key per touched tile in record order; key total + capacity check on the device
         StageTimer t(p, GSF_STAGE_DUPLICATE);
-        launch_scan_duplicate(s, p->order, b.count, b.rect, nrec, (int)n, b.views, p->V,
-                              b.block_sums, b.keys[0], b.vals[0], b.m_dev, b.m_total, b.flags, p->cap);
+        launch_scan_duplicate(s, b.count, b.rect, nrec, (int)n, b.views, b.block_sums, b.k0, b.v0,
+                              b.m_dev, b.m_total, b.flags, p->cap, b.ranges, (int)p->total_tiles);
     }
     GSF_LAUNCHED(ctx);
-    int tw;
-    if (p->host_sized) {
+    if (p->host_sized) {   // plain path: one host synchronisation per forward
         GSF_HIP(ctx, hipMemcpyAsync(p->pinned, b.m_total, 8, hipMemcpyDeviceToHost, s));
         GSF_HIP(ctx, hipStreamSynchronize(s));
         const unsigned long long total = *p->pinned;
-        const uint32_t m = total > (unsigned long long)p->cap ? 0u : (uint32_t)total;
         *overflow = total > (unsigned long long)p->cap;
-        p->m_host = m;
-        {
-            StageTimer t(p, GSF_STAGE_TILE_SORT);
-            tw = launch_radix_sort(s, b.keys[0], b.vals[0], b.keys[1], b.vals[1], b.keys[0],
-                                   b.vals[0], nullptr, m, p->tile_bits, radix_grid_for(m), b.hist,
-                                   b.digit_tot);
-        }
-        GSF_LAUNCHED(ctx);
-        p->keys_sorted = tw == 1 ? b.keys[1] : b.keys[0];
-        p->vals_sorted = tw == 1 ? b.vals[1] : b.vals[0];
+        p->m_host = *overflow ? 0u : (uint32_t)total;
+    }
+    const uint32_t *m_dev = p->host_sized ? nullptr : b.m_dev;
+    {   // stable by tile: each tile's keys stay in record order
+        StageTimer t(p, GSF_STAGE_TILE_SORT);
+        const int grid = p->host_sized ? radix_grid_for(p->m_host) : p->radix_grid;
+        launch_radix_sort(s, b.k0, b.v0, b.k1, b.v1, b.k0, b.v0, m_dev, p->m_host, p->tile_bits,
+                          grid, b.hist, b.digit_tot);
+    }
+    GSF_LAUNCHED(ctx);
+    {
         StageTimer t(p, GSF_STAGE_RANGES);
-        launch_tile_ranges(s, p->keys_sorted, nullptr, m, (int)p->total_tiles, b.ranges);
-    } else {
-        {
-            StageTimer t(p, GSF_STAGE_TILE_SORT);
-            tw = launch_radix_sort(s, b.keys[0], b.vals[0], b.keys[1], b.vals[1], b.keys[0],
-                                   b.vals[0], b.m_dev, 0u, p->tile_bits, p->grid_tile, b.hist,
-                                   b.digit_tot);
-        }
-        GSF_LAUNCHED(ctx);
-        p->keys_sorted = tw == 1 ? b.keys[1] : b.keys[0];
-        p->vals_sorted = tw == 1 ? b.vals[1] : b.vals[0];
-        StageTimer t(p, GSF_STAGE_RANGES);
-        launch_tile_ranges(s, p->keys_sorted, b.m_dev, 0u, (int)p->total_tiles, b.ranges);
+        launch_tile_bounds(s, b.keys, m_dev, p->m_host, p->cap, (int)p->total_tiles, b.ranges);
+    }
+    GSF_LAUNCHED(ctx);
+    {   // each tile's list by (depth, record); the sorted tile ids are free scratch now
+        StageTimer t(p, GSF_STAGE_DEPTH_SORT);
+        launch_tile_sort(s, b.ranges, (int)p->total_tiles, b.depth_key, b.vals, b.keys, b.ok, b.ov);
     }
     GSF_LAUNCHED(ctx);
     {
@@ -488,10 +479,9 @@ gsf_status gsf_plan_create(gsf_ctx *ctx, const gsf_plan_desc *d, gsf_plan **out)
     p->total_pix = poff;
     p->cap = d->key_capacity > 0 ? d->key_capacity : 32 * nrec + (1 << 20);
     if (p->cap > 0xF0000000ll) p->cap = 0xF0000000ll;
-    p->tile_bits = 0;
+    p->tile_bits = 0;                         // bits of the largest global tile id
     while ((int64_t(1) << p->tile_bits) < p->total_tiles) p->tile_bits++;
-    p->grid_depth = radix_grid_for(nrec);
-    p->grid_tile = radix_grid_for(p->cap);
+    p->radix_grid = radix_grid_for(p->cap);
     {   // persistent workgroups of the checkpointed adjoint: enough to fill every CU
         int cus = 256;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess || cus < 1)
@@ -690,7 +680,7 @@ gsf_status gsf_count_pairs(gsf_plan *p, int64_t *out) {
     if (st != GSF_OK) return st;
     if (!out) return fail(p->ctx, GSF_E_INVALID, "gsf_count_pairs: null output");
     if (!p->have_forward) return fail(p->ctx, GSF_E_STATE, "gsf_count_pairs before gsf_forward");
-    launch_count_pairs(p->ctx->stream, p->tile, (int)p->total_tiles, p->b.ranges, p->vals_sorted,
+    launch_count_pairs(p->ctx->stream, p->tile, (int)p->total_tiles, p->b.ranges, p->b.vals,
                        splats(p), p->b.views, p->V, p->b.counters);
     GSF_LAUNCHED(p->ctx);
     unsigned long long c[3] = {0, 0, 0};
@@ -718,8 +708,20 @@ gsf_status gsf_debug_copy(gsf_plan *p, int which, void *host_dst, size_t cap, si
     case GSF_DBG_RECT: src = p->b.rect; bytes = R * 8; break;
     case GSF_DBG_COUNT: src = p->b.count; bytes = R * 4; break;
     case GSF_DBG_DEPTH: src = p->b.depth_key; bytes = R * 4; break;
-    case GSF_DBG_KEYS: src = p->keys_sorted; bytes = M * 4; break;
-    case GSF_DBG_VALS: src = p->vals_sorted; bytes = M * 4; break;
+    case GSF_DBG_KEYS: {   // the tile id of every key position, from the ranges
+        std::vector<uint2> rg((size_t)p->total_tiles);
+        if (!rg.empty())
+            GSF_HIP(p->ctx, hipMemcpy(rg.data(), p->b.ranges, rg.size() * 8, hipMemcpyDeviceToHost));
+        std::vector<uint32_t> keys(M);
+        for (size_t t = 0; t < rg.size(); t++)
+            for (uint32_t k = rg[t].x; k < rg[t].y && k < M; k++) keys[k] = (uint32_t)t;
+        bytes = M * 4;
+        if (bytes > cap) return fail(p->ctx, GSF_E_INVALID, "gsf_debug_copy: destination too small");
+        if (bytes) std::memcpy(host_dst, keys.data(), bytes);
+        *written = bytes;
+        return GSF_OK;
+    }
+    case GSF_DBG_VALS: src = p->b.vals; bytes = M * 4; break;
     case GSF_DBG_RANGES: src = p->b.ranges; bytes = (size_t)p->total_tiles * 8; break;
     case GSF_DBG_TFINAL: src = p->b.tfinal; bytes = (size_t)p->total_pix * 4; break;
     case GSF_DBG_NCONTRIB: src = p->b.ncontrib; bytes = (size_t)p->total_pix * 4; break;

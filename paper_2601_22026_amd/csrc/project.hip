@@ -227,7 +227,6 @@ __global__ __launch_bounds__(256) void k_project_fwd(const float *__restrict__ P
                                                      const gsf_camera *__restrict__ cams,
                                                      const ViewDesc *__restrict__ views, int tile,
                                                      SplatPtrs sp, uint32_t *__restrict__ depth_key,
-                                                     uint32_t *__restrict__ rec_idx,
                                                      uint2 *__restrict__ rect,
                                                      uint32_t *__restrict__ count,
                                                      float *__restrict__ g2d) {
@@ -236,7 +235,6 @@ __global__ __launch_bounds__(256) void k_project_fwd(const float *__restrict__ P
     if (r >= nrec) return;
     const int v = r / n;
     const int i = r - v * n;
-    rec_idx[r] = (uint32_t)r;
     if (g2d) {
 #pragma unroll
         for (int f = 0; f < 9; f++) g2d[(size_t)f * nrec + r] = 0.f;
@@ -458,15 +456,15 @@ __global__ __launch_bounds__(128) void k_project_bwd(const float *__restrict__ P
 
 void launch_project_fwd(hipStream_t s, const float *P, int n, int nviews, int deg,
                         const gsf_camera *cams, const ViewDesc *views, int tile, SplatPtrs sp,
-                        uint32_t *depth_key, uint32_t *rec_idx, uint2 *rect, uint32_t *count,
+                        uint32_t *depth_key, uint2 *rect, uint32_t *count,
                         float *g2d) {
     const int nrec = n * nviews;
     const dim3 grid((nrec + 255) / 256), block(256);
     switch (deg) {
-    case 0: k_project_fwd<0><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rec_idx, rect, count, g2d); break;
-    case 1: k_project_fwd<1><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rec_idx, rect, count, g2d); break;
-    case 2: k_project_fwd<2><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rec_idx, rect, count, g2d); break;
-    default: k_project_fwd<3><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rec_idx, rect, count, g2d); break;
+    case 0: k_project_fwd<0><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rect, count, g2d); break;
+    case 1: k_project_fwd<1><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rect, count, g2d); break;
+    case 2: k_project_fwd<2><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rect, count, g2d); break;
+    default: k_project_fwd<3><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rect, count, g2d); break;
     }
 }
 

@@ -1,28 +1,40 @@
-// sort.hip - the discrete stage of tile-based splatting: per-record tile counts
-// scanned in depth order, one (tile, record) key per touched tile, a stable
-// radix sort of those keys by tile, and per-tile [start, end) ranges.
+// sort.hip - the discrete stage of tile-based splatting: one key per
+// (tile, record) pair whose support box touches the tile, ordered by
+// (global tile, camera depth, record), and per-tile [start, end) ranges.
 //
-// The order that compositing needs is (global tile, depth, record).  It is
-// reached with two stable sorts: records are first sorted by their float32
-// depth bits (stable, so ties keep the record order), the duplication then
-// emits keys in that order, and a stable sort by tile id alone finishes the job.
-// The tile sort thus needs only ceil(log2(tiles)) key bits instead of tile bits
-// plus 32 depth bits.
-//
-// Radix sort: least-significant-digit first, 8-bit digits, reduce-then-scan
-// with a fixed grid of G workgroups, each owning one contiguous chunk of the
-// input whose size is derived from the key count read on the device, so the
-// launches do not depend on a host-side count (graph capture).  Per pass:
-//   hist    per-workgroup digit histogram (per-wave LDS sub-histograms)
-//   colscan one workgroup per digit scans that digit's G counts
-//   scatter each workgroup re-reads its chunk in 2048-key tiles; a wave ranks
-//           its 64 keys per round by matching digits with 8 ballots (peer
-//           masks), keeps per-wave running digit counts in LDS, and the tile's
-//           waves are combined in digit order, which keeps the sort stable.
+//   1. scan + duplicate: an exclusive scan of the records' touched-tile counts
+//      (record order) places every record's keys; key = global tile id,
+//      value = record id.  The total is checked against the key capacity on the
+//      device.  No global atomics: counters with thousands of writers serialise
+//      badly across the XCDs of this chip.
+//   2. a stable least-significant-digit radix sort of the keys by tile id
+//      (8-bit digits, ceil(log2(tiles)) bits): a fixed grid of G workgroups,
+//      each owning one contiguous chunk whose size follows from the key count
+//      read on the device (graph capture).  Per pass: per-workgroup digit
+//      histograms (per-wave LDS sub-histograms), a column scan per digit, and a
+//      scatter that ranks each wave's 64 keys with 8 ballots (peer masks) and
+//      combines the waves in order (stable);
+//   3. tile ranges from the boundaries of the sorted keys;
+//   4. one workgroup per tile sorts its list by the float32 depth bits with the
+//      same stable LDS ranking (4 passes, skipped when a digit is uniform); the
+//      list is in record order on entry, so equal depths stay in record order.
+//      Lists longer than the LDS capacity run the passes on global scratch.
+// Depth bits of positive floats order like the floats, so the result is the
+// (tile, depth, record) order.
 #include "gs_internal.h"
 
 namespace gsf {
 namespace {
+
+constexpr int kSortBlock = 256;              // threads per radix-sort workgroup (4 waves)
+constexpr int kSortIpt = 8;                  // keys per thread per chunk tile
+constexpr int kSortTile = kSortBlock * kSortIpt;
+constexpr int kSortMaxGrid = 1024;
+constexpr int kScanBlock = 256;
+constexpr int kScanIpt = 8;
+constexpr int kScanTile = kScanBlock * kScanIpt;
+constexpr int kTileSortBlock = 256;
+constexpr int kTileSortLds = 2048;           // list length sorted in LDS; longer lists use global scratch
 
 __device__ __forceinline__ uint32_t chunk_size(uint32_t n, int G) {
     const uint32_t per = (n + (uint32_t)G - 1u) / (uint32_t)G;
@@ -57,6 +69,8 @@ __device__ __forceinline__ uint32_t block_excl_scan_256(uint32_t x, uint32_t *s_
     __syncthreads();
     return base + inc - x;
 }
+
+// ---- 2. stable radix sort by tile id ------------------------------------------
 
 __global__ __launch_bounds__(kSortBlock) void k_radix_hist(const uint32_t *__restrict__ keys,
                                                            const uint32_t *__restrict__ n_dev,
@@ -177,17 +191,16 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(
     }
 }
 
-// ---- scan of tile counts in depth order + key duplication -------------------------
+// ---- 1. scan of the touched-tile counts + key duplication (record order) -------
 
-__global__ __launch_bounds__(kScanBlock) void k_scan_reduce(const uint32_t *__restrict__ order,
-                                                            const uint32_t *__restrict__ count,
+__global__ __launch_bounds__(kScanBlock) void k_scan_reduce(const uint32_t *__restrict__ count,
                                                             int nrec, uint32_t *__restrict__ block_sums) {
     __shared__ uint32_t s_wave[4];
     const int base = blockIdx.x * kScanTile + threadIdx.x * kScanIpt;
     uint32_t sum = 0;
 #pragma unroll
     for (int k = 0; k < kScanIpt; k++)
-        if (base + k < nrec) sum += count[order[base + k]];
+        if (base + k < nrec) sum += count[base + k];
     uint32_t total;
     block_excl_scan_256(sum, s_wave, total);
     if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
@@ -207,7 +220,7 @@ __global__ __launch_bounds__(1024) void k_scan_top(uint32_t *__restrict__ block_
     __syncthreads();
     // Hillis-Steele inclusive scan of the 1024 partial sums
     for (int o = 1; o < 1024; o <<= 1) {
-        const unsigned long long y = threadIdx.x >= o ? s_part[threadIdx.x - o] : 0ull;
+        const unsigned long long y = threadIdx.x >= (unsigned)o ? s_part[threadIdx.x - o] : 0ull;
         __syncthreads();
         s_part[threadIdx.x] += y;
         __syncthreads();
@@ -231,20 +244,23 @@ __global__ __launch_bounds__(1024) void k_scan_top(uint32_t *__restrict__ block_
     }
 }
 
+// Keys of each record (one per touched tile) at its scanned offset; also
+// clears the tile ranges (grid-stride) before the boundary pass fills them.
 __global__ __launch_bounds__(kScanBlock) void k_scan_dup(
-    const uint32_t *__restrict__ order, const uint32_t *__restrict__ count,
-    const uint2 *__restrict__ rect, int nrec, int n, const ViewDesc *__restrict__ views,
-    const uint32_t *__restrict__ block_prefix, const unsigned long long *__restrict__ m_total,
-    int64_t capacity, uint32_t *__restrict__ keys, uint32_t *__restrict__ vals) {
+    const uint32_t *__restrict__ count, const uint2 *__restrict__ rect, int nrec, int n,
+    const ViewDesc *__restrict__ views, const uint32_t *__restrict__ block_prefix,
+    const unsigned long long *__restrict__ m_total, int64_t capacity, uint32_t *__restrict__ keys,
+    uint32_t *__restrict__ vals, uint2 *__restrict__ ranges, int total_tiles) {
     __shared__ uint32_t s_wave[4];
+    for (int t = blockIdx.x * kScanBlock + threadIdx.x; t < total_tiles; t += gridDim.x * kScanBlock)
+        ranges[t] = make_uint2(0u, 0u);
     if (*m_total > (unsigned long long)capacity) return;    // overflow: emit nothing
     const int base = blockIdx.x * kScanTile + threadIdx.x * kScanIpt;
-    uint32_t rec[kScanIpt], cnt[kScanIpt];
+    uint32_t cnt[kScanIpt];
     uint32_t sum = 0;
 #pragma unroll
     for (int k = 0; k < kScanIpt; k++) {
-        rec[k] = base + k < nrec ? order[base + k] : 0u;
-        cnt[k] = base + k < nrec ? count[rec[k]] : 0u;
+        cnt[k] = base + k < nrec ? count[base + k] : 0u;
         sum += cnt[k];
     }
     uint32_t total;
@@ -252,9 +268,8 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_dup(
 #pragma unroll
     for (int k = 0; k < kScanIpt; k++) {
         if (cnt[k] == 0u) continue;
-        const uint32_t r = rec[k];
-        const int v = (int)(r / (uint32_t)n);
-        const ViewDesc vd = views[v];
+        const uint32_t r = (uint32_t)(base + k);
+        const ViewDesc vd = views[r / (uint32_t)n];
         const uint2 rc = rect[r];
         const uint32_t x0 = rc.x & 0xFFFFu, y0 = rc.x >> 16, x1 = rc.y & 0xFFFFu, y1 = rc.y >> 16;
         uint32_t o = off;
@@ -270,26 +285,168 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_dup(
     }
 }
 
-__global__ __launch_bounds__(256) void k_tile_ranges(const uint32_t *__restrict__ keys,
+// ---- 3. tile ranges from the boundaries of the sorted keys -----------------------
+
+// ranges[t] = [lower_bound(t), lower_bound(t + 1)) over the sorted keys, for every
+// tile: an empty tile gets the position where its keys would be, so starts are
+// non-decreasing in t (the checkpointed adjoint numbers its work units by them).
+// A lane at a boundary owns the run of empty tiles before its key (and the last
+// key the run after it); a run can be a thousand tiles long, so each wave writes
+// its lanes' runs together, 64 tiles per store.  Tiles before the first key keep
+// the (0, 0) the duplicate pass wrote.
+__device__ __forceinline__ void fill_runs(uint2 *ranges, uint32_t lo, uint32_t hi, uint32_t value) {
+    const int lane = __lane_id();
+    uint64_t todo = __ballot(hi > lo);
+    while (todo) {
+        const int src = __builtin_ctzll(todo);
+        const uint32_t a = __shfl(lo, src, 64), b = __shfl(hi, src, 64), v = __shfl(value, src, 64);
+        for (uint32_t e = a + (uint32_t)lane; e < b; e += 64u) ranges[e] = make_uint2(v, v);
+        todo &= todo - 1u;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_tile_bounds(const uint32_t *__restrict__ keys,
                                                      const uint32_t *__restrict__ m_dev,
                                                      uint32_t m_host, int total_tiles,
                                                      uint2 *__restrict__ ranges) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= total_tiles) return;
     const uint32_t m = m_dev ? *m_dev : m_host;
-    // lower bounds of t and t + 1
-    uint32_t lo = 0, hi = m;
-    while (lo < hi) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (keys[mid] < (uint32_t)t) lo = mid + 1; else hi = mid;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    // wave-uniform trip count: every lane takes part in the run fills
+    for (uint32_t base = blockIdx.x * blockDim.x; base < m; base += stride) {
+        const uint32_t k = base + threadIdx.x;
+        uint32_t lo = 0, hi = 0, lo2 = 0, hi2 = 0;
+        if (k < m) {
+            const uint32_t t = keys[k];
+            if (k == 0 || keys[k - 1] != t) {
+                lo = k == 0 ? t : keys[k - 1] + 1u;   // empty tiles before t
+                hi = t;
+                ranges[t].x = k;
+            }
+            if (k + 1 == m) {
+                ranges[t].y = m;
+                lo2 = t + 1u;                         // empty tiles after the last key
+                hi2 = (uint32_t)total_tiles;
+            } else if (keys[k + 1] != t) {
+                ranges[t].y = k + 1;
+            }
+        }
+        fill_runs(ranges, lo, hi, k);
+        fill_runs(ranges, lo2, hi2, m);
     }
-    const uint32_t a = lo;
-    hi = m;
-    while (lo < hi) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (keys[mid] < (uint32_t)t + 1u) lo = mid + 1; else hi = mid;
+}
+
+// ---- 4. per-tile sort by depth ----------------------------------------------------
+
+struct SortShared {
+    uint32_t hist[4][256];   // per-wave digit counts
+    uint32_t base[256];      // running output offset per digit
+    uint32_t tot[256];
+    uint32_t wave[4];
+    uint32_t skip;
+};
+
+// One stable pass by the 8-bit digit (k >> shift) & 0xFF.  Returns false (and
+// moves nothing) when every key has the same digit.  Generic pointers: called
+// on LDS arrays or on global scratch.
+__device__ __forceinline__ bool sort_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout,
+                                          uint32_t *vout, int n, int shift, SortShared &sh) {
+    const int t = threadIdx.x, w = t >> 6, lane = __lane_id();
+    for (int e = t; e < 4 * 256; e += kTileSortBlock) (&sh.hist[0][0])[e] = 0u;
+    if (t == 0) sh.skip = 0u;
+    __syncthreads();
+    for (int i = t; i < n; i += kTileSortBlock) {
+        const uint32_t d = (kin[i] >> shift) & 0xFFu;
+        atomicAdd(&sh.hist[w][d], 1u);
     }
-    ranges[t] = make_uint2(a, lo);
+    __syncthreads();
+    const uint32_t cnt = sh.hist[0][t] + sh.hist[1][t] + sh.hist[2][t] + sh.hist[3][t];
+    if (cnt == (uint32_t)n) sh.skip = 1u;
+    uint32_t all;
+    sh.base[t] = block_excl_scan_256(cnt, sh.wave, all);   // (has barriers)
+    const bool skip = sh.skip != 0u;
+    __syncthreads();                       // all have read skip before a later pass resets it
+    if (skip) return false;
+    for (int c0 = 0; c0 < n; c0 += kTileSortBlock) {
+        for (int e = t; e < 4 * 256; e += kTileSortBlock) (&sh.hist[0][0])[e] = 0u;
+        __syncthreads();
+        const int i = c0 + w * 64 + lane;
+        const bool valid = i < n;
+        const uint32_t k = valid ? kin[i] : 0u, v = valid ? vin[i] : 0u;
+        const uint32_t d = (k >> shift) & 0xFFu;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; b++) {
+            const uint64_t bal = __ballot((d >> b) & 1u);
+            peers &= ((d >> b) & 1u) ? bal : ~bal;
+        }
+        const uint32_t below = lanes_below(peers);
+        if (valid && below == 0u) sh.hist[w][d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        {   // earlier waves of this chunk, per digit
+            uint32_t run = 0;
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const uint32_t c = sh.hist[q][t];
+                sh.hist[q][t] = run;
+                run += c;
+            }
+            sh.tot[t] = run;
+        }
+        __syncthreads();
+        if (valid) {
+            const uint32_t pos = sh.base[d] + sh.hist[w][d] + below;
+            kout[pos] = k;
+            vout[pos] = v;
+        }
+        __syncthreads();
+        sh.base[t] += sh.tot[t];
+    }
+    __syncthreads();
+    return true;
+}
+
+// Four stable passes over the 32 depth bits.  The list arrives in record order
+// (stable tile sort of keys emitted in record order), so equal depths keep it.
+__device__ __forceinline__ void sort_list(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
+                                          int n, SortShared &sh, bool &in_second) {
+    bool second = false;
+    for (int p = 0; p < 4; p++) {
+        const bool moved = second ? sort_pass(k1, v1, k0, v0, n, 8 * p, sh)
+                                  : sort_pass(k0, v0, k1, v1, n, 8 * p, sh);
+        if (moved) second = !second;
+    }
+    in_second = second;
+}
+
+__global__ __launch_bounds__(kTileSortBlock) void k_tile_sort(
+    const uint2 *__restrict__ ranges, const uint32_t *__restrict__ depth_key,
+    uint32_t *__restrict__ vals, uint32_t *__restrict__ gk0, uint32_t *__restrict__ gk1,
+    uint32_t *__restrict__ gv1) {
+    __shared__ SortShared sh;
+    __shared__ uint32_t s_k0[kTileSortLds], s_v0[kTileSortLds], s_k1[kTileSortLds], s_v1[kTileSortLds];
+    const uint2 rg = ranges[blockIdx.x];
+    const int n = (int)(rg.y - rg.x);
+    if (n <= 1) return;
+    uint32_t *lv = vals + rg.x;
+    bool second;
+    if (n <= kTileSortLds) {
+        for (int i = threadIdx.x; i < n; i += kTileSortBlock) {
+            const uint32_t r = lv[i];
+            s_v0[i] = r;
+            s_k0[i] = depth_key[r];
+        }
+        __syncthreads();
+        sort_list(s_k0, s_v0, s_k1, s_v1, n, sh, second);
+        const uint32_t *res = second ? s_v1 : s_v0;
+        for (int i = threadIdx.x; i < n; i += kTileSortBlock) lv[i] = res[i];
+    } else {
+        uint32_t *k0 = gk0 + rg.x, *k1 = gk1 + rg.x, *v1 = gv1 + rg.x;
+        for (int i = threadIdx.x; i < n; i += kTileSortBlock) k0[i] = depth_key[lv[i]];
+        __syncthreads();
+        sort_list(k0, lv, k1, v1, n, sh, second);
+        if (second)
+            for (int i = threadIdx.x; i < n; i += kTileSortBlock) lv[i] = v1[i];
+    }
 }
 
 }  // namespace
@@ -320,21 +477,30 @@ int launch_radix_sort(hipStream_t s, const uint32_t *kin, const uint32_t *vin, u
     return where;
 }
 
-void launch_scan_duplicate(hipStream_t s, const uint32_t *order, const uint32_t *count,
-                           const uint2 *rect, int nrec, int n, const ViewDesc *views, int nviews,
-                           uint32_t *block_sums, uint32_t *keys, uint32_t *vals, uint32_t *m_dev,
-                           unsigned long long *m_total, uint32_t *flags, int64_t capacity) {
-    (void)nviews;
+int scan_blocks(int64_t nrec) { return (int)((nrec + kScanTile - 1) / kScanTile) + 1; }
+
+void launch_scan_duplicate(hipStream_t s, const uint32_t *count, const uint2 *rect, int nrec, int n,
+                           const ViewDesc *views, uint32_t *block_sums, uint32_t *keys,
+                           uint32_t *vals, uint32_t *m_dev, unsigned long long *m_total,
+                           uint32_t *flags, int64_t capacity, uint2 *ranges, int total_tiles) {
     const int nb = (nrec + kScanTile - 1) / kScanTile;
-    k_scan_reduce<<<nb, kScanBlock, 0, s>>>(order, count, nrec, block_sums);
+    k_scan_reduce<<<nb, kScanBlock, 0, s>>>(count, nrec, block_sums);
     k_scan_top<<<1, 1024, 0, s>>>(block_sums, nb, m_dev, m_total, flags, capacity);
-    k_scan_dup<<<nb, kScanBlock, 0, s>>>(order, count, rect, nrec, n, views, block_sums, m_total,
-                                         capacity, keys, vals);
+    k_scan_dup<<<nb, kScanBlock, 0, s>>>(count, rect, nrec, n, views, block_sums, m_total, capacity,
+                                         keys, vals, ranges, total_tiles);
 }
 
-void launch_tile_ranges(hipStream_t s, const uint32_t *keys, const uint32_t *m_dev, uint32_t m_host,
-                        int total_tiles, uint2 *ranges) {
-    k_tile_ranges<<<(total_tiles + 255) / 256, 256, 0, s>>>(keys, m_dev, m_host, total_tiles, ranges);
+void launch_tile_bounds(hipStream_t s, const uint32_t *keys, const uint32_t *m_dev, uint32_t m_host,
+                        int64_t capacity, int total_tiles, uint2 *ranges) {
+    int64_t g = (capacity + 255) / 256;
+    if (g > 2048) g = 2048;
+    if (g < 1) g = 1;
+    k_tile_bounds<<<(int)g, 256, 0, s>>>(keys, m_dev, m_host, total_tiles, ranges);
+}
+
+void launch_tile_sort(hipStream_t s, const uint2 *ranges, int total_tiles, const uint32_t *depth_key,
+                      uint32_t *vals, uint32_t *gk0, uint32_t *gk1, uint32_t *gv1) {
+    k_tile_sort<<<total_tiles, kTileSortBlock, 0, s>>>(ranges, depth_key, vals, gk0, gk1, gv1);
 }
 
 }  // namespace gsf

@@ -67,8 +67,10 @@ def test_discrete_stage_bit_exact(ctx, tile):
     if flagged.size == 0:
         assert keys.size == M
         np.testing.assert_array_equal(ranges.astype(np.int64), d.ranges)
-    # sort properties on the GPU output itself
+    # sort properties on the GPU output itself; range starts never decrease,
+    # empty tiles included (the checkpointed adjoint numbers its units by them)
     assert (np.diff(keys) >= 0).all()
+    assert (np.diff(ranges[:, 0].astype(np.int64)) >= 0).all()
     count = sc.debug(_abi.GSF_DBG_COUNT, np.uint32, R)
     assert keys.size == int(count.sum())
     log(f"[parity]   keys {M}, flagged records {flagged.size}")
@@ -166,3 +168,34 @@ def test_checkpointed_adjoint_matches_recompute(ctx, tile, batch):
     assert all(nb == 0 for _, nb, _ in rep), rep
     ranges = a.debug(_abi.GSF_DBG_RANGES, np.uint32, 2 * a.plan.total_tiles).reshape(-1, 2)
     assert (ranges[:, 1] - ranges[:, 0]).max() > 2 * batch   # several batches per tile exercised
+
+
+def test_checkpointed_adjoint_with_empty_tiles(ctx):
+    """A dense cluster plus a few scattered Gaussians in two views: most tiles
+    hold no key, empty and full tiles interleave, some tiles span several LDS
+    batches, and the checkpointed adjoint must still find every unit."""
+    P = np.concatenate([synth.random_gaussians(300, seed=12, mean_range=0.12, logscale_mean=-4.0),
+                        synth.random_gaussians(30, seed=13, logscale_mean=-4.0)], axis=1)
+    cams = [synth.look_at_camera([0.2, 0.4, -3.0], width=320, height=256),
+            synth.look_at_camera([2.5, 1.0, 1.0], width=192, height=144)]
+    a = GpuScene(ctx, P, cams, tile=16, batch=64, t_mode=0)
+    b = GpuScene(ctx, P, cams, tile=16, batch=64, t_mode=1)
+    ia, ib = a.forward(), b.forward()
+    for x, y in zip(ia, ib):
+        np.testing.assert_array_equal(x.view(np.uint32), y.view(np.uint32))
+    ranges = b.debug(_abi.GSF_DBG_RANGES, np.uint32, 2 * b.plan.total_tiles).reshape(-1, 2)
+    empty = ranges[:, 1] == ranges[:, 0]
+    assert empty.sum() > ranges.shape[0] // 2 and (~empty[:-1] & empty[1:]).any()
+    assert (ranges[:, 1] - ranges[:, 0]).max() > 2 * 64
+    rng = np.random.default_rng(4)
+    dls = [rng.normal(size=(4, c.npix)) for c in cams]
+    ga, gb = a.backward(dls), b.backward(dls)
+    rep = grads_close(gb, ga.astype(np.float64))
+    log(f"[parity] sparse scene ckpt vs recompute {rep}")
+    assert all(nb == 0 for _, nb, _ in rep), rep
+    refs = [oracle.render(P, c) for c in cams]
+    for dl, ref in zip(dls, refs):
+        dl[:, ref.flags != 0] = 0.0
+    G = sum(oracle.backward(P, c, dl.astype(np.float32).astype(np.float64)) for c, dl in zip(cams, dls))
+    rep = grads_close(b.backward(dls), G)
+    assert all(nb == 0 for _, nb, _ in rep), rep
