@@ -87,6 +87,27 @@ def hbm_bytes_per_launch(stage, N, M, npix, planes, tiles):
     }.get(stage)
 
 
+def profiled_traffic(kernel, tile, batch):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summaries (FETCH_SIZE and WRITE_SIZE, scaled by a copy-kernel calibration),
+    or None when no summary matches this kernel, tile and LDS batch, or the
+    compositing source has changed since the counters were taken."""
+    import glob
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    src = os.path.join(here, "paper_2601_22026_amd", "csrc", "raster.hip")
+    h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    for path in sorted(glob.glob(os.path.join(here, "profiles", "*.md"))):
+        for line in open(path):
+            if not line.startswith("traffic:"):
+                continue
+            kv = dict(f.split("=", 1) for f in line.split()[1:])
+            if (kv.get("kernel") == kernel and int(kv.get("tile", 0)) == tile
+                    and int(kv.get("lds_batch", 0)) == batch and kv.get("raster_sha256") == h):
+                return int(kv["bytes_per_launch"])
+    return None
+
+
 def cpu_baseline(P, cam, target, budget_s=15.0):
     """FP64 oracle fit step on a bounded sample of image rows, extrapolated
     linearly in rows to the full image."""
@@ -230,13 +251,15 @@ def main():
             flops = FLOPS_ALPHA * pairs["visited_bwd"] + FLOPS_BWD_INCLUDED * pairs["included"]
         ach = flops / (stages[dom] * 1e-3) / 1e12
         roof = {"kernel": dom, "bound": "alu", "achieved": round(ach, 3), "peak": PEAK_FP32_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_TFLOPS, 4),
+                "traffic": profiled_traffic(dom, cfg.tile, cfg.lds_batch),
                 "work": {"flops_per_launch": int(flops), **pairs}}
     else:
         byt = hbm_bytes_per_launch(dom, N, M, npix, planes, tiles)
         ach = byt / (stages[dom] * 1e-3) / 1e9
         roof = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS,
-                "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": None}
+                "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBS, 4),
+                "traffic": profiled_traffic(dom, cfg.tile, cfg.lds_batch)}
     stage_roof = {}
     for k, ms in stages.items():
         if k in ("render", "render_bwd"):
