@@ -1,28 +1,37 @@
 #!/usr/bin/env python3
 """Fit-step benchmark of the MI355X Gaussian-splatting fit path.
 
-Workload (phantom-seeded fit): a 128^3 uint16 CT-like phantom (20 random
-ellipsoids, HU-like values, noise sigma 20, seed 3); one Gaussian per voxel
-above 1200 capped at 50,000 (seed 4), isotropic one-voxel scale, opacity 0.1,
-linear transfer-function colour (SH degree 0); one 1024x1024 view, 60 degree
-FOV, on the radius-3 sphere (pose seed 2); L1 loss against an emission-
-absorption ray march of the same volume; Adam lr 1e-3.  All inputs are seeded
-and synthetic (the paper's CT datasets are not available).
+Default workload (phantom-seeded fit): a 128^3 uint16 CT-like phantom (20
+random ellipsoids, HU-like values, noise sigma 20, seed 3); one Gaussian per
+voxel above 1200 capped at 50,000 (seed 4), isotropic one-voxel scale,
+opacity 0.1, linear transfer-function colour (SH degree 0); one 1024x1024
+view, 60 degree FOV, on the radius-3 sphere (pose seed 2); L1 loss against an
+emission-absorption ray march of the same volume; Adam lr 1e-3.  All inputs
+are seeded and synthetic (the paper's CT datasets are not available).
 
-A "step" is one forward + loss + backward + Adam pass over the view.  The
-timed path is the fused step captured in a HIP graph (one launch per stage,
-key count on the device), replayed K times after W warm-up replays, bracketed
-by stream synchronisation and timed with HIP events.  Alongside: the plain
-path (host-synchronised, eager launches), the eager fused path, per-stage
-kernel times (HIP events in the library, on the stream the kernels run on),
-the roofline of the dominant kernel and the FP64 CPU oracle on a bounded
-sample of rows.
+Other workloads (--workload): small (1,000 random Gaussians, one 128^2 view,
+target rendered by the oracle), batched (200,000 SH3 Gaussians, 8 views of
+uneven resolution), foveal (500,000 Gaussians seeded from a 256^3 phantom, 16
+views of 1920^2, loss masked to a fovea of radius 0.2 W at a random gaze point,
+ms per 300-step regeneration), stereo (1,000,000 SH3 Gaussians, two eyes of
+2064x2208, recomputed / checkpointed / stored transmittance compared).
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1]
+A "step" is one forward + loss + backward + Adam pass over all views.  The
+timed path is the fused step captured in a HIP graph (one launch per stage
+for all views, key count on the device), replayed K times after W warm-up
+replays, bracketed by stream synchronisation and timed with HIP events.
+Alongside: the plain path (one host-synchronised plan per view, eager), the
+eager fused path, per-stage kernel times (HIP events recorded by the library
+on the stream the kernels run on, over the same step indices as the timed
+replays), the roofline of the dominant kernel and the FP64 CPU oracle on a
+bounded sample of rows.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload NAME]
 """
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -48,14 +57,115 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def build_workload(n_vol=128, cap=50_000, size=1024):
+@dataclasses.dataclass
+class Workload:
+    name: str
+    description: str
+    data: str
+    P: object                       # planar float32 [C][n]
+    cams: list
+    targets: object = None          # float32, per view [3][H][W], views concatenated (flat)
+    gaze: object = None             # float32 [V][2] or None
+    target_params: object = None    # Gaussian set whose render is the target
+    volume: object = None
+
+
+def _phantom_fit(n_vol, cap, cams, gaze=None):
+    import numpy as np
+
     import synth
     vol = synth.phantom(n_vol, seed=synth.SEED_VOLUME)
     P = synth.seed_from_volume(vol, cap=cap, seed=synth.SEED_CAP_SUBSET)
-    d = synth.sphere_directions(1, seed=synth.SEED_POSES)[0]
-    cam = synth.look_at_camera(3.0 * d, width=size, height=size, fov_x_deg=60.0)
-    target = synth.raymarch_volume(vol, cam)[:3]
-    return P, cam, target
+    tg = []
+    for k, c in enumerate(cams):
+        if gaze is None:
+            tg.append(synth.raymarch_volume(vol, c)[:3])
+            continue
+        # only rows that meet the fovea carry loss; the others stay zero
+        r = 0.2 * c.width
+        y0 = max(0, int(np.floor(gaze[k][1] - r - 1)))
+        y1 = min(c.height, int(np.ceil(gaze[k][1] + r + 1)))
+        img = np.zeros((3, c.height, c.width), np.float32)
+        img[:, y0:y1] = synth.raymarch_volume(vol, c, rows=np.arange(y0, y1))[:3]
+        tg.append(img)
+    targets = np.concatenate([t.reshape(-1) for t in tg])
+    return P, targets, vol
+
+
+def build_workload(name="phantom"):
+    import numpy as np
+
+    import synth
+    if name == "small":
+        P = synth.random_gaussians(1000, seed=synth.SEED_GAUSSIANS)
+        cam = synth.axis_camera(128, 128)
+        tgt = np.load(os.path.join(ROOT, "tests", "golden", "cfg1_target_128.npy"))[:3]
+        return Workload(name, "plain single view: 1,000 random Gaussians (SH0), one 128x128 view, "
+                              "L1 vs the seed-1 set rendered by the oracle, Adam lr 1e-3",
+                        "synthetic: seeded random Gaussians; target from the FP64 oracle",
+                        P, [cam], targets=np.ascontiguousarray(tgt.reshape(-1)))
+    if name == "phantom":
+        d = synth.sphere_directions(1, seed=synth.SEED_POSES)[0]
+        cam = synth.look_at_camera(3.0 * d, width=1024, height=1024, fov_x_deg=60.0)
+        P, targets, vol = _phantom_fit(128, 50_000, [cam])
+        return Workload(name, "phantom-seeded fit: 128^3 phantom, 50,000 Gaussians (SH0), one "
+                              "1024x1024 view, L1 vs ray-marched target, Adam lr 1e-3",
+                        "synthetic: seeded CT-like phantom, voxel-seeded Gaussians, ray-marched target",
+                        P, [cam], targets=targets, volume=vol)
+    if name == "batched":
+        n = 200_000
+        mu = synth.scaled_logscale_mean(n)
+        P = synth.random_gaussians(n, seed=synth.SEED_GAUSSIANS, sh_degree=3, logscale_mean=mu)
+        Pt = synth.random_gaussians(n, seed=synth.SEED_TARGET_SET, sh_degree=3, logscale_mean=mu)
+        cams = synth.sphere_cameras(synth.draw_resolutions(8, seed=synth.SEED_RESOLUTIONS),
+                                    radius=3.0, seed=synth.SEED_POSES)
+        return Workload(name, "batched uneven views: 200,000 random Gaussians (SH3), 8 views with "
+                              "resolutions drawn from {512^2, 768x1024, 1024^2, 1536^2, 2048^2}, "
+                              "L1 vs the seed-1 set, Adam lr 1e-3",
+                        "synthetic: seeded random Gaussians; target = the seed-1 set rendered by "
+                        "this library's forward", P, cams, target_params=Pt)
+    if name == "foveal":
+        dirs = synth.sphere_directions(16, seed=synth.SEED_POSES)
+        cams = [synth.look_at_camera(3.0 * d, width=1920, height=1920, fov_x_deg=60.0) for d in dirs]
+        gaze = synth.gaze_points(cams, seed=synth.SEED_GAZE)
+        P, targets, vol = _phantom_fit(256, 500_000, cams, gaze)
+        return Workload(name, "foveal refinement: 256^3 phantom, 500,000 Gaussians (SH0), 16 views "
+                              "of 1920x1920, L1 masked to a fovea of radius 0.2 W at a random gaze "
+                              "point per view, ray-marched targets, Adam lr 1e-3",
+                        "synthetic: seeded CT-like phantom, voxel-seeded Gaussians, ray-marched target",
+                        P, cams, targets=targets, gaze=gaze, volume=vol)
+    if name == "stereo":
+        n = 1_000_000
+        mu = synth.scaled_logscale_mean(n)
+        P = synth.random_gaussians(n, seed=synth.SEED_GAUSSIANS, sh_degree=3, logscale_mean=mu)
+        Pt = synth.random_gaussians(n, seed=synth.SEED_TARGET_SET, sh_degree=3, logscale_mean=mu)
+        cams = synth.stereo_cameras(2064, 2208, radius=3.0, baseline=0.064, seed=synth.SEED_POSES)
+        return Workload(name, "stereo HMD: 1,000,000 random Gaussians (SH3), two eyes of 2064x2208 "
+                              "with a 64 mm baseline, L1 vs the seed-1 set, Adam lr 1e-3",
+                        "synthetic: seeded random Gaussians; target = the seed-1 set rendered by "
+                        "this library's forward", P, cams, target_params=Pt)
+    raise SystemExit(f"unknown workload {name!r}")
+
+
+def render_targets(ctx, wl, dev):
+    """RGB of the target Gaussian set through the library's forward (a plain
+    host-sized plan with recomputed transmittance)."""
+    import numpy as np
+    import torch
+
+    import paper_2601_22026_amd as gs
+    Pt = torch.from_numpy(np.ascontiguousarray(wl.target_params)).to(dev)
+    deg = int(round(((Pt.shape[0] - 11) // 3) ** 0.5)) - 1
+    sizes = [(c.width, c.height) for c in wl.cams]
+    plan = gs.Plan(ctx, Pt.shape[1], sizes, deg, 16, 128, host_sized=True)
+    rgba = torch.zeros(4 * sum(w * h for w, h in sizes), dtype=torch.float32, device=dev)
+    plan.forward(Pt, Pt.shape[1], gs.cameras_to_device(wl.cams, dev), rgba)
+    out, off = [], 0
+    for w, h in sizes:
+        out.append(rgba[4 * off:4 * off + 3 * w * h])
+        off += w * h
+    plan.close()
+    return torch.cat(out).contiguous()
 
 
 def time_steps(fn, steps, stream):
@@ -70,73 +180,86 @@ def time_steps(fn, steps, stream):
     return e0.elapsed_time(e1) / steps
 
 
-def hbm_bytes_per_launch(stage, N, M, npix, planes, tiles):
-    """Algorithmic HBM bytes one launch of a stage must move."""
-    rec = N  # one view
+def hbm_bytes_per_launch(stage, N, R, M, npix, planes, tiles):
+    """Algorithmic HBM bytes one launch of a stage must move: N Gaussians,
+    R = N * views records, M keys, npix pixels, `planes` floats per Gaussian."""
     passes = (max(1, (tiles - 1).bit_length()) + 7) // 8
     return {
-        "project": planes * 4 * N + 92 * rec,                # params in; splat, key, box, count, g2d clear
-        "duplicate": 16 * rec + 8 * M + 8 * tiles,           # counts (twice), boxes in; pairs out; ranges cleared
-        "tile_sort": passes * 20 * M,                        # per pass: key histogram, pair in, pair out
-        "ranges": 4 * M + 8 * tiles,                         # sorted tile ids in; ranges out
-        "depth_sort": 12 * M,                                # record ids in, depth gather, record ids out
-        "loss": 40 * npix,
-        "project_bwd": planes * 4 * N + 36 * rec + planes * 4 * N,
+        "project": planes * 4 * N + 92 * R,                   # params in; splat, key, box, count, g2d clear
+        "duplicate": 16 * R + 8 * M + 8 * tiles,              # counts (twice), boxes in; pairs out; ranges cleared
+        "tile_sort": passes * 20 * M,                         # per pass: key histogram, pair in, pair out
+        "ranges": 4 * M + 8 * tiles,                          # sorted tile ids in; ranges out
+        "depth_sort": 12 * M,                                 # record ids in, depth gather, record ids out
+        "render": 40 * M + 24 * npix,                         # splat gather per key; RGBA, T, count out
+        "loss": 40 * npix,                                    # RGBA, target in; dL/dRGBA out
+        "render_bwd": 40 * M + 24 * npix + 36 * R,            # splat gather; pixel state in; g2d out
+        "project_bwd": planes * 4 * N + 36 * R + planes * 4 * N,
         "adam": 28 * planes * N,
-        "zero": 36 * rec,
+        "zero": 36 * R,
     }.get(stage)
 
 
-def profiled_traffic(kernel, tile, batch):
+def profiled_traffic(workload, kernel, tile, batch):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summaries (FETCH_SIZE and WRITE_SIZE, scaled by a copy-kernel calibration),
-    or None when no summary matches this kernel, tile and LDS batch, or the
-    compositing source has changed since the counters were taken."""
+    or None when no summary matches this workload, kernel, tile and LDS batch,
+    or the compositing source has changed since the counters were taken."""
     import glob
     import hashlib
-    here = os.path.dirname(os.path.abspath(__file__))
-    src = os.path.join(here, "paper_2601_22026_amd", "csrc", "raster.hip")
+    src = os.path.join(ROOT, "paper_2601_22026_amd", "csrc", "raster.hip")
     h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    for path in sorted(glob.glob(os.path.join(here, "profiles", "*.md"))):
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
         for line in open(path):
             if not line.startswith("traffic:"):
                 continue
             kv = dict(f.split("=", 1) for f in line.split()[1:])
-            if (kv.get("kernel") == kernel and int(kv.get("tile", 0)) == tile
-                    and int(kv.get("lds_batch", 0)) == batch and kv.get("raster_sha256") == h):
+            if (kv.get("workload") == workload and kv.get("kernel") == kernel
+                    and int(kv.get("tile", 0)) == tile and int(kv.get("lds_batch", 0)) == batch
+                    and kv.get("raster_sha256") == h):
                 return int(kv["bytes_per_launch"])
     return None
 
 
-def cpu_baseline(P, cam, target, budget_s=15.0):
-    """FP64 oracle fit step on a bounded sample of image rows, extrapolated
-    linearly in rows to the full image."""
+def cpu_baseline(wl, targets_np, budget_s=15.0):
+    """FP64 oracle fit step (render, L1 sign, adjoint, Adam) on a bounded sample
+    of image rows of every view, extrapolated linearly in rows per view."""
     import numpy as np
 
     import oracle
-    H, W = cam.height, cam.width
-    Pd = P.astype(np.float64)
+    Pd = wl.P.astype(np.float64)
     m, v = np.zeros_like(Pd), np.zeros_like(Pd)
+    offs = np.cumsum([0] + [c.width * c.height for c in wl.cams])
 
-    def run(nrows):
-        rows = np.linspace(0, H - 1, nrows).astype(np.int64)
-        pix = (rows[:, None] * W + np.arange(W)[None, :]).reshape(-1)
+    def run(rows_per_view):
+        est, used = 0.0, 0
+        G = np.zeros_like(Pd)
+        t_start = time.perf_counter()
+        for k, cam in enumerate(wl.cams):
+            H, W = cam.height, cam.width
+            nrows = min(H, rows_per_view)
+            rows = np.linspace(0, H - 1, nrows).astype(np.int64)
+            pix = (rows[:, None] * W + np.arange(W)[None, :]).reshape(-1)
+            t0 = time.perf_counter()
+            r = oracle.render(Pd, cam, pixels=pix)
+            tgt = targets_np[3 * offs[k]:3 * offs[k + 1]].reshape(3, -1)[:, pix]
+            s, cnt, dl = oracle.loss_l1_view(r.rgba, tgt, type("c", (), {"width": W, "height": nrows})())
+            G += oracle.backward(Pd, cam, dl / max(cnt, 1), pixels=pix)
+            est += (time.perf_counter() - t0) * H / nrows
+            used += nrows
         t0 = time.perf_counter()
-        r = oracle.render(Pd, cam, pixels=pix)
-        tgt = target.reshape(3, -1)[:, pix]
-        s, cnt, dl = oracle.loss_l1_view(r.rgba, tgt, type("c", (), {"width": W, "height": nrows})())
-        G = oracle.backward(Pd, cam, dl / max(cnt, 1), pixels=pix)
         oracle.adam(Pd.copy(), G, m.copy(), v.copy(), 1)
-        return time.perf_counter() - t0
+        est += time.perf_counter() - t0
+        return est, used, time.perf_counter() - t_start
 
-    t_small = run(4)
-    nrows = int(min(H, max(8, 4 * budget_s / max(t_small, 1e-3))))
-    t = run(nrows)
-    full = t * H / nrows
+    _, _, t_probe = run(2)
+    rows = max(2, int(2 * budget_s / max(t_probe, 1e-3)))
+    full, used, spent = run(rows)
+    tot_rows = sum(c.height for c in wl.cams)
     return {"value": 1.0 / full, "unit": "fit-steps/s", "cores": oracle.num_threads(),
             "kind": "oracle",
-            "sample": f"{nrows} of {H} rows ({nrows * W} px) of one step, {t:.1f} s, "
-                      f"extrapolated x{H / nrows:.1f} in rows (all {P.shape[1]} Gaussians per pixel)"}
+            "sample": f"{used} of {tot_rows} rows over {len(wl.cams)} view(s) of one step, "
+                      f"{spent:.1f} s, extrapolated per view in rows (all {wl.P.shape[1]} Gaussians "
+                      f"per pixel)"}
 
 
 def main():
@@ -144,12 +267,21 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="phantom",
+                    choices=["small", "phantom", "batched", "foveal", "stereo"])
     ap.add_argument("--tile", type=int, default=16)
     ap.add_argument("--lds-batch", type=int, default=128)
+    ap.add_argument("--t-mode", type=int, default=1, choices=[0, 1, 2],
+                    help="transmittance of the timed step: 0 recomputed, 1 checkpointed, 2 stored")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use --tile/--lds-batch instead of sweeping tile x LDS batch")
+    ap.add_argument("--compare-t-modes", action="store_true",
+                    help="also time the captured step and record peak device memory with each "
+                         "transmittance mode (always on for --workload stereo)")
+    ap.add_argument("--regen-steps", type=int, default=300,
+                    help="steps of one regeneration (foveal workload)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 256 MiB device buffer 5 times (reference for HBM byte "
                          "counters) and exit")
@@ -175,33 +307,39 @@ def main():
     import paper_2601_22026_amd as gs
 
     t0 = time.perf_counter()
-    P, cam, target = build_workload()
-    N = P.shape[1]
-    planes = P.shape[0]
-    npix = cam.npix
-    log(f"[bench] workload: {N} Gaussians, {cam.width}x{cam.height}, built in "
+    wl = build_workload(args.workload)
+    P, cams = wl.P, wl.cams
+    N, planes, V = P.shape[1], P.shape[0], len(cams)
+    npix = sum(c.width * c.height for c in cams)
+    log(f"[bench] workload {wl.name}: {N} Gaussians, {V} view(s), {npix} px, built in "
         f"{time.perf_counter() - t0:.1f} s")
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.Stream(dev)
-    tgt_dev = torch.from_numpy(np.ascontiguousarray(target.reshape(-1))).to(dev)
-    cfg = gs.FitConfig(lr=1e-3, tile=args.tile, lds_batch=args.lds_batch)
-    out = {}
+    cfg = gs.FitConfig(lr=1e-3, tile=args.tile, lds_batch=args.lds_batch, t_mode=args.t_mode)
     with torch.cuda.stream(stream):
         ctx = gs.Context(0)
+        if wl.targets is None:
+            tgt_dev = render_targets(ctx, wl, dev)
+        else:
+            tgt_dev = torch.from_numpy(np.ascontiguousarray(wl.targets)).to(dev)
+        gaze_dev = None if wl.gaze is None else torch.from_numpy(np.ascontiguousarray(wl.gaze)).to(dev)
+        P_dev = torch.from_numpy(np.ascontiguousarray(P)).to(dev)
+
+        def fit(c, fused=True):
+            return gs.FitStep(ctx, P_dev.clone(), cams, tgt_dev, gaze_dev, cfg=c, fused=fused)
 
         tune = None
         if not args.no_autotune:
-            best, sweep = gs.autotune(ctx, torch.from_numpy(P).to(dev), [cam], tgt_dev, cfg=cfg,
-                                      stream=stream)
+            best, sweep = gs.autotune(ctx, P_dev, cams, tgt_dev, gaze_dev, cfg=cfg, stream=stream)
             tune = {"best": list(best), "us_per_step": {f"{t}x{b}": round(ms * 1e3, 1)
                                                         for (t, b), ms in sorted(sweep.items())}}
-            cfg = gs.FitConfig(lr=1e-3, tile=best[0], lds_batch=best[1])
+            cfg = dataclasses.replace(cfg, tile=best[0], lds_batch=best[1])
             log(f"[bench] autotune: best tile {best[0]} batch {best[1]}; {tune['us_per_step']}")
 
-        # fused, captured
-        fused = gs.FitStep(ctx, torch.from_numpy(P).to(dev), [cam], tgt_dev, cfg=cfg, fused=True)
+        # fused, captured: the timed path
+        fused = fit(cfg)
         fused.capture()
         for _ in range(args.warmup):
             fused.replay()
@@ -210,40 +348,104 @@ def main():
         loss_fused = float(fused.loss.item())
         log(f"[bench] fused+captured: {ms_fused * 1e3:.1f} us/step, keys {M}, flags {flags}, "
             f"loss {loss_fused:.5f}")
+        ws_fused = fused.plan.workspace_bytes
+        total_tiles = fused.plan.total_tiles
+        fused.plan.close()
+        del fused
+
+        regen = None
+        if wl.name == "foveal":
+            runs = []
+            for _ in range(3):
+                rf = fit(cfg)
+                rf.capture()
+                runs.append(time_steps(rf.replay, args.regen_steps, stream) * args.regen_steps)
+                rf.plan.close()
+                del rf
+            regen = {"ms_per_regeneration": round(sorted(runs)[1], 2), "steps": args.regen_steps,
+                     "runs_ms": [round(r, 2) for r in runs],
+                     "includes": "the captured fit steps only (seeding and the target ray march "
+                                 "run on the host and are excluded)"}
+            log(f"[bench] regeneration ({args.regen_steps} steps): {regen['ms_per_regeneration']} ms")
 
         # fused, eager (same plan shape, no graph)
-        eager = gs.FitStep(ctx, torch.from_numpy(P).to(dev), [cam], tgt_dev, cfg=cfg, fused=True)
+        eager = fit(cfg)
         for _ in range(args.warmup):
             eager.step()
         ms_eager = time_steps(eager.step, args.steps, stream)
+        eager.plan.close()
+        del eager
         log(f"[bench] fused eager: {ms_eager * 1e3:.1f} us/step")
 
-        # per-stage kernel times on the eager fused step (HIP events in the library)
-        eager.plan.set_timing(True)
-        n_prof = max(10, min(args.steps, 50))
-        for _ in range(n_prof):
-            eager.step()
-        st = eager.plan.stage_times()
-        eager.plan.set_timing(False)
+        # per-stage kernel times: a fresh eager fused step taken through the same
+        # step indices as the timed replays (W warm-up, then K), with HIP events
+        # recorded by the library around each stage on the stream it launches on
+        staged = fit(cfg)
+        for _ in range(args.warmup):
+            staged.step()
+        staged.plan.set_timing(True)
+        for _ in range(args.steps):
+            staged.step()
+        st = staged.plan.stage_times()
+        staged.plan.set_timing(False)
+        staged.plan.close()
+        del staged
         stages = {k: (ms / max(c, 1)) for k, (ms, c) in st.items() if c}
-        eager.plan.forward(eager.params, N, eager.cams_dev, eager.rgba)
-        pairs = eager.plan.count_pairs()
         log("[bench] stage us/launch: " + ", ".join(f"{k} {v * 1e3:.1f}" for k, v in stages.items()))
-        log(f"[bench] pairs: {pairs}")
+        # pair counts of the same K steps (a separate run: counting synchronises)
+        counted = fit(cfg)
+        for _ in range(args.warmup):
+            counted.step()
+        pairs = {}
+        for _ in range(args.steps):
+            counted.step()
+            for k, v in counted.plan.count_pairs().items():
+                pairs[k] = pairs.get(k, 0) + v / args.steps
+        counted.plan.close()
+        del counted
+        pairs = {k: int(round(v)) for k, v in pairs.items()}
+        log(f"[bench] pairs per step (mean of the K steps): {pairs}")
 
-        # plain path: host-synchronised, eager
+        # plain path: one host-synchronised plan per view, eager
         ms_plain = None
         if not args.no_plain:
-            plain = gs.FitStep(ctx, torch.from_numpy(P).to(dev), [cam], tgt_dev, cfg=cfg, fused=False)
+            plain = fit(cfg, fused=False)
             for _ in range(args.warmup):
                 plain.step()
             ms_plain = time_steps(plain.step, args.steps, stream)
+            for p, _, _ in plain.view_plans:
+                p.close()
+            del plain
             log(f"[bench] plain: {ms_plain * 1e3:.1f} us/step")
+
+        # transmittance modes: step time and peak device memory
+        modes = None
+        if args.compare_t_modes or wl.name == "stereo":
+            modes = {}
+            for m, label in enumerate(["recompute", "checkpointed", "stored"]):
+                torch.cuda.synchronize()
+                torch.cuda.empty_cache()
+                torch.cuda.reset_peak_memory_stats(dev)
+                base = torch.cuda.memory_allocated(dev)
+                fm = fit(dataclasses.replace(cfg, t_mode=m))
+                fm.capture()
+                for _ in range(args.warmup):
+                    fm.replay()
+                ms_m = time_steps(fm.replay, args.steps, stream)
+                peak = torch.cuda.max_memory_allocated(dev)
+                modes[label] = {"ms_per_step": round(ms_m, 4),
+                                "workspace_bytes": fm.plan.workspace_bytes,
+                                "peak_device_bytes_above_inputs": int(peak - base)}
+                fm.plan.close()
+                del fm
+                log(f"[bench] t_mode {m} ({label}): {ms_m * 1e3:.1f} us/step, workspace "
+                    f"{modes[label]['workspace_bytes'] / 2**30:.2f} GiB")
     torch.cuda.synchronize()
 
     # roofline of the dominant kernel
+    R = N * V
     dom = max(stages, key=stages.get)
-    tiles = fused.plan.total_tiles
+    traffic = profiled_traffic(wl.name, dom, cfg.tile, cfg.lds_batch)
     if dom in ("render", "render_bwd"):
         if dom == "render":
             flops = FLOPS_ALPHA * pairs["visited_fwd"] + FLOPS_FWD_INCLUDED * pairs["included"]
@@ -251,27 +453,23 @@ def main():
             flops = FLOPS_ALPHA * pairs["visited_bwd"] + FLOPS_BWD_INCLUDED * pairs["included"]
         ach = flops / (stages[dom] * 1e-3) / 1e12
         roof = {"kernel": dom, "bound": "alu", "achieved": round(ach, 3), "peak": PEAK_FP32_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_TFLOPS, 4),
-                "traffic": profiled_traffic(dom, cfg.tile, cfg.lds_batch),
+                "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
                 "work": {"flops_per_launch": int(flops), **pairs}}
     else:
-        byt = hbm_bytes_per_launch(dom, N, M, npix, planes, tiles)
+        byt = hbm_bytes_per_launch(dom, N, R, M, npix, planes, total_tiles)
         ach = byt / (stages[dom] * 1e-3) / 1e9
         roof = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS,
-                "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBS, 4),
-                "traffic": profiled_traffic(dom, cfg.tile, cfg.lds_batch)}
+                "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": traffic}
     stage_roof = {}
     for k, ms in stages.items():
+        byt = hbm_bytes_per_launch(k, N, R, M, npix, planes, total_tiles)
+        stage_roof[k] = {"us": round(ms * 1e3, 2), "gbs": round(byt / (ms * 1e-3) / 1e9, 1)}
         if k in ("render", "render_bwd"):
             fl = (FLOPS_ALPHA * pairs["visited_fwd"] + FLOPS_FWD_INCLUDED * pairs["included"]
                   if k == "render" else
                   FLOPS_ALPHA * pairs["visited_bwd"] + FLOPS_BWD_INCLUDED * pairs["included"])
-            stage_roof[k] = {"us": round(ms * 1e3, 2), "tflops": round(fl / (ms * 1e-3) / 1e12, 3)}
-        else:
-            byt = hbm_bytes_per_launch(k, N, M, npix, planes, tiles)
-            stage_roof[k] = {"us": round(ms * 1e3, 2)}
-            if byt:
-                stage_roof[k]["gbs"] = round(byt / (ms * 1e-3) / 1e9, 1)
+            stage_roof[k]["tflops"] = round(fl / (ms * 1e-3) / 1e12, 3)
+    step_bytes = sum(hbm_bytes_per_launch(k, N, R, M, npix, planes, total_tiles) for k in stages)
 
     steps_per_s = 1000.0 / ms_fused
     res = {
@@ -286,25 +484,33 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
-        "data": "synthetic: seeded CT-like phantom, voxel-seeded Gaussians, ray-marched target",
-        "config": {"workload": "phantom-seeded fit: 128^3 phantom, 50,000 Gaussians (SH0), "
-                               "one 1024x1024 view, L1 vs ray-marched target, Adam lr 1e-3",
-                   "gaussians": N, "views": 1, "width": cam.width, "height": cam.height,
-                   "tile": cfg.tile, "lds_batch": cfg.lds_batch, "keys_per_step": M,
-                   "form": "fused, hipGraph-captured"},
+        "data": wl.data,
+        "config": {"workload": wl.description, "name": wl.name, "gaussians": N, "views": V,
+                   "sizes": [[c.width, c.height] for c in cams], "pixels": npix,
+                   "sh_degree": int(round(((planes - 11) // 3) ** 0.5)) - 1,
+                   "tile": cfg.tile, "lds_batch": cfg.lds_batch, "t_mode": cfg.t_mode,
+                   "keys_per_step": M, "form": "fused, hipGraph-captured"},
         "mpix_per_s": round(npix * steps_per_s / 1e6, 1),
         "ms_per_100_step_fit": round(100 * ms_fused, 2),
         "eager_fused_steps_per_s": round(1000.0 / ms_eager, 2),
         "plain_steps_per_s": round(1000.0 / ms_plain, 2) if ms_plain else None,
         "vs_plain": round(ms_plain / ms_fused, 3) if ms_plain else None,
         "loss_after_timed_steps": round(loss_fused, 6),
+        "workspace_bytes": ws_fused,
+        "step_hbm": {"algorithmic_bytes": int(step_bytes),
+                     "gbs": round(step_bytes / (ms_fused * 1e-3) / 1e9, 1),
+                     "frac_of_peak": round(step_bytes / (ms_fused * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)},
         "autotune": tune,
         "stages": stage_roof,
         "roofline": roof,
     }
+    if regen:
+        res["regeneration"] = regen
+    if modes:
+        res["transmittance_modes"] = modes
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline ...")
-        res["cpu_baseline"] = cpu_baseline(P, cam, target)
+        res["cpu_baseline"] = cpu_baseline(wl, tgt_dev.detach().cpu().numpy())
     else:
         res["cpu_baseline"] = None
     print(json.dumps(res), flush=True)

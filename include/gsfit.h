@@ -91,12 +91,17 @@ typedef struct gsf_plan_desc {
     const int32_t *heights;     /* (host) [n_views] */
     int32_t tile;               /* tile edge in pixels: 8, 16 or 32 */
     int32_t lds_batch;          /* Gaussians staged in LDS per batch: 64, 128 or 256 */
-    int32_t t_mode;             /* transmittance in the adjoint: 0 recomputed back to
-                                   front from the final transmittance (8 B/pixel saved,
-                                   one workgroup per tile); 1 checkpointed: the forward
-                                   also stores (T, colour) per pixel at every LDS-batch
-                                   boundary (16 B/pixel/boundary) and the adjoint runs
-                                   one workgroup per (tile, batch) */
+    int32_t t_mode;             /* transmittance in the adjoint:
+                                   0 recomputed back to front from the final
+                                     transmittance (8 B/pixel saved; one workgroup
+                                     per tile);
+                                   1 checkpointed: the forward also stores (T, colour)
+                                     per pixel at every LDS-batch boundary
+                                     (16 B/pixel/boundary) and the adjoint runs one
+                                     workgroup per (tile, batch);
+                                   2 stored: the forward stores T in front of every
+                                     included (Gaussian, pixel) pair, key capacity x
+                                     tile^2 x 4 B; one workgroup per tile */
     int32_t host_sized;         /* 1: gsf_forward reads the key count back to the host
                                    and sizes the sort from it (plain path);
                                    0: the count stays on the device (capturable) */

@@ -185,6 +185,11 @@ class Plan:
         if getattr(self, "handle", None):
             lib().gsf_plan_destroy(self.handle)
             self.handle = None
+        self.workspace = None
+
+    @property
+    def workspace_bytes(self) -> int:
+        return 0 if self.workspace is None else int(self.workspace.numel())
 
     def __del__(self):
         try:
@@ -238,7 +243,7 @@ class FitConfig:
     lds_batch: int = 128
     radius_frac: float = 0.2
     key_capacity: int = 0
-    t_mode: int = 1          # adjoint transmittance of the fused step: 1 checkpointed, 0 recomputed
+    t_mode: int = 1          # adjoint transmittance of the fused step: 0 recomputed, 1 checkpointed, 2 stored
 
 
 class FitStep:

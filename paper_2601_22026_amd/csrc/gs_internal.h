@@ -33,16 +33,22 @@ struct ViewDesc {
     int32_t pad0, pad1;
 };
 
-// Per-record screen-space splat, split so that one gather is two 16-byte and
-// one 8-byte load: a = (mean x, mean y, A2, B2), b = (C2, opacity, red, green),
-// c = (blue, tau).  The conic is stored pre-scaled so that
-// power2 = A2 dx^2 + C2 dy^2 + B2 dx dy = log2(e) * power, i.e. A2 = -log2(e) A / 2,
-// B2 = -log2(e) B, C2 = -log2(e) C / 2, and tau = log2(1 / (255 opacity)) is
-// the power2 below which alpha < 1/255.
+// Per-record screen-space splat, three 16-byte loads per gather:
+//   a = (hx, hy, A2, B2), b = (C2, opacity, red, green), c = (blue, tau, ix, iy).
+// The pixel mean mu' is computed in double precision and split into an integer
+// pixel (ix, iy; exact floats) and the offset of mu' from that pixel's centre,
+// hx = ix + 1/2 - mu'_x (likewise hy), so that the offset of pixel (x, y) from
+// the mean, dx = (x - ix) + hx, is exact up to one float32 rounding of the
+// result: the gradient with respect to the mean sums +dx and -dx terms from
+// both sides of a small footprint, and float32 rounding of mu' itself (about
+// 3e-5 px at 1000 px) would otherwise dominate it.  The conic is stored
+// pre-scaled so that power2 = A2 dx^2 + C2 dy^2 + B2 dx dy = log2(e) * power,
+// i.e. A2 = -log2(e) A / 2, B2 = -log2(e) B, C2 = -log2(e) C / 2, and tau =
+// log2(1 / (255 opacity)) is the power2 below which alpha < 1/255.
 struct SplatPtrs {
     float4 *a;
     float4 *b;
-    float2 *c;
+    float4 *c;
 };
 constexpr float kLog2e = 1.4426950408889634f;
 
@@ -99,7 +105,7 @@ void launch_tile_sort(hipStream_t s, const uint2 *ranges, int total_tiles, const
 // Everything the compositing kernels share.
 struct RenderArgs {
     int tile = 16, batch = 128, total_tiles = 0, nviews = 1, nrec = 0;
-    int ckpt_mode = 0;                    // 1: checkpoint (T, colour) at every LDS batch boundary
+    int t_mode = 0;                       // 0 recompute, 1 checkpointed, 2 stored transmittance
     int bwd_grid = 1;                     // persistent workgroups of the checkpointed adjoint
     const uint2 *ranges = nullptr;
     const uint32_t *vals = nullptr;
@@ -110,6 +116,7 @@ struct RenderArgs {
     uint32_t *ncontrib = nullptr;
     float4 *ckpt = nullptr;               // [key capacity / B + 1][T*T]
     float4 *fstate = nullptr;             // [pixels]: final (T, colour)
+    float *tstore = nullptr;              // [key capacity][T*T]: T in front of each included pair
     const uint32_t *m_dev = nullptr;      // key count on the device, or
     uint32_t m_host = 0;                  //   on the host when m_dev is null
 };

@@ -34,7 +34,7 @@ namespace {
 struct Buffers {
     // per record (view v, Gaussian i)
     float4 *rec_a = nullptr, *rec_b = nullptr;
-    float2 *rec_c = nullptr;
+    float4 *rec_c = nullptr;
     uint32_t *depth_key = nullptr;               // float32 depth bits; 0xFFFFFFFF = culled
     uint2 *rect = nullptr;                       // touched tile rectangle
     uint32_t *count = nullptr;                   // touched tiles
@@ -51,7 +51,8 @@ struct Buffers {
     // per pixel
     float *tfinal = nullptr;
     uint32_t *ncontrib = nullptr;
-    float4 *ckpt = nullptr, *fstate = nullptr;   // checkpoint mode only
+    float4 *ckpt = nullptr, *fstate = nullptr;   // checkpointed mode only
+    float *tstore = nullptr;                     // stored mode only
     float *g2d = nullptr;
     uint32_t *m_dev = nullptr, *flags = nullptr, *mask_count = nullptr;
     unsigned long long *m_total = nullptr;
@@ -129,7 +130,7 @@ size_t carve(gsf_plan *p, char *base, Buffers *out) {
     Buffers b;
     b.rec_a = (float4 *)take(R * sizeof(float4));
     b.rec_b = (float4 *)take(R * sizeof(float4));
-    b.rec_c = (float2 *)take(R * sizeof(float2));
+    b.rec_c = (float4 *)take(R * sizeof(float4));
     b.depth_key = (uint32_t *)take(R * 4);
     b.rect = (uint2 *)take(R * sizeof(uint2));
     b.count = (uint32_t *)take(R * 4);
@@ -154,6 +155,7 @@ size_t carve(gsf_plan *p, char *base, Buffers *out) {
         b.ckpt = (float4 *)take(((size_t)p->cap / p->batch + 1) * p->tile * p->tile * sizeof(float4));
         b.fstate = (float4 *)take((size_t)p->total_pix * sizeof(float4));
     }
+    if (p->t_mode == 2) b.tstore = (float *)take((size_t)p->cap * p->tile * p->tile * sizeof(float));
     b.g2d = (float *)take(9 * R * 4);
     b.m_dev = (uint32_t *)take(4);
     b.flags = (uint32_t *)take(4);
@@ -181,7 +183,7 @@ RenderArgs render_args(gsf_plan *p, const gsf_camera *cams, int64_t n) {
     a.total_tiles = (int)p->total_tiles;
     a.nviews = p->V;
     a.nrec = (int)(n * p->V);
-    a.ckpt_mode = p->t_mode == 1;
+    a.t_mode = p->t_mode;
     a.bwd_grid = p->bwd_grid;
     a.ranges = p->b.ranges;
     a.vals = p->b.vals;
@@ -192,6 +194,7 @@ RenderArgs render_args(gsf_plan *p, const gsf_camera *cams, int64_t n) {
     a.ncontrib = p->b.ncontrib;
     a.ckpt = p->b.ckpt;
     a.fstate = p->b.fstate;
+    a.tstore = p->b.tstore;
     a.m_dev = p->host_sized ? nullptr : p->b.m_dev;
     a.m_host = p->m_host;
     return a;
@@ -436,7 +439,7 @@ gsf_status gsf_plan_create(gsf_ctx *ctx, const gsf_plan_desc *d, gsf_plan **out)
     if (d->tile != 8 && d->tile != 16 && d->tile != 32) return fail(ctx, GSF_E_INVALID, "tile must be 8, 16 or 32");
     if (d->lds_batch != 64 && d->lds_batch != 128 && d->lds_batch != 256)
         return fail(ctx, GSF_E_INVALID, "lds_batch must be 64, 128 or 256");
-    if (d->t_mode != 0 && d->t_mode != 1) return fail(ctx, GSF_E_INVALID, "t_mode must be 0 or 1");
+    if (d->t_mode < 0 || d->t_mode > 2) return fail(ctx, GSF_E_INVALID, "t_mode must be 0, 1 or 2");
     if (d->host_sized != 0 && d->host_sized != 1) return fail(ctx, GSF_E_INVALID, "host_sized must be 0 or 1");
     if (d->key_capacity < 0 || d->key_capacity > 0xF0000000ll)
         return fail(ctx, GSF_E_INVALID, "key_capacity out of range");
@@ -728,12 +731,12 @@ gsf_status gsf_debug_copy(gsf_plan *p, int which, void *host_dst, size_t cap, si
     case GSF_DBG_G2D: src = p->b.g2d; bytes = 9 * R * 4; break;
     case GSF_DBG_PROJ: {
         std::vector<float4> a(R), b(R);
-        std::vector<float2> c(R);
+        std::vector<float4> c(R);
         std::vector<uint32_t> dk(R);
         if (R) {
             GSF_HIP(p->ctx, hipMemcpy(a.data(), p->b.rec_a, R * 16, hipMemcpyDeviceToHost));
             GSF_HIP(p->ctx, hipMemcpy(b.data(), p->b.rec_b, R * 16, hipMemcpyDeviceToHost));
-            GSF_HIP(p->ctx, hipMemcpy(c.data(), p->b.rec_c, R * 8, hipMemcpyDeviceToHost));
+            GSF_HIP(p->ctx, hipMemcpy(c.data(), p->b.rec_c, R * 16, hipMemcpyDeviceToHost));
             GSF_HIP(p->ctx, hipMemcpy(dk.data(), p->b.depth_key, R * 4, hipMemcpyDeviceToHost));
         }
         proj.resize(R * 11);
@@ -744,7 +747,10 @@ gsf_status gsf_debug_copy(gsf_plan *p, int which, void *host_dst, size_t cap, si
             const bool valid = dk[r] != 0xFFFFFFFFu;
             float depth;
             std::memcpy(&depth, &dk[r], 4);
-            const float vals[11] = {a[r].x, a[r].y, (float)(a[r].z / half), (float)(a[r].w / full),
+            // the mean is stored as an integer pixel plus the offset of the mean from its centre
+            const float mx = (float)((double)c[r].z + 0.5 - (double)a[r].x);
+            const float my = (float)((double)c[r].w + 0.5 - (double)a[r].y);
+            const float vals[11] = {mx, my, (float)(a[r].z / half), (float)(a[r].w / full),
                                     (float)(b[r].x / half), b[r].y, b[r].z, b[r].w, c[r].x,
                                     valid ? depth : 0.f, valid ? 1.f : 0.f};
             std::memcpy(o, vals, sizeof vals);

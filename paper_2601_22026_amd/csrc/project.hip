@@ -263,20 +263,32 @@ __global__ __launch_bounds__(256) void k_project_fwd(const float *__restrict__ P
         for (int k = 0; k < K; k++) acc = fmaf(P[(size_t)(11 + 3 * k + ch) * n + i], Y[k], acc);
         col[ch] = fmaxf(acc + 0.5f, 0.f);
     }
+    // pixel mean in double precision (camera transform included), stored as an
+    // integer pixel plus the offset of the mean from that pixel's centre
+    double td[3];
+#pragma unroll
+    for (int q = 0; q < 3; q++)
+        td[q] = fma((double)cam.viewmat[4 * q], (double)g.mu[0],
+                    fma((double)cam.viewmat[4 * q + 1], (double)g.mu[1],
+                        fma((double)cam.viewmat[4 * q + 2], (double)g.mu[2], (double)cam.viewmat[4 * q + 3])));
+    const double mxd = fma((double)cam.fx, td[0] / td[2], (double)cam.cx);
+    const double myd = fma((double)cam.fy, td[1] / td[2], (double)cam.cy);
+    const double ixd = floor(mxd), iyd = floor(myd);
     // conic pre-scaled for a base-2 exponent, and the power2 at which alpha = 1/255
-    sp.a[r] = make_float4(p.mx, p.my, (-0.5f * kLog2e) * p.A, -kLog2e * p.B);
+    sp.a[r] = make_float4((float)(ixd + 0.5 - mxd), (float)(iyd + 0.5 - myd), (-0.5f * kLog2e) * p.A,
+                          -kLog2e * p.B);
     sp.b[r] = make_float4((-0.5f * kLog2e) * p.C, g.o, col[0], col[1]);
-    sp.c[r] = make_float2(col[2], -log2f(255.f * g.o));
+    sp.c[r] = make_float4(col[2], -log2f(255.f * g.o), (float)ixd, (float)iyd);
     depth_key[r] = __float_as_uint(p.t[2]);
     // support box: AABB of the ellipse where o e^power >= 1/255, padded
     const float k2 = 2.f * logf(255.f * g.o);
     const float hx = fmaf(sqrtf(k2 * p.a), 1.f + kBoxRel, kBoxAbs);
     const float hy = fmaf(sqrtf(k2 * p.c), 1.f + kBoxRel, kBoxAbs);
     const ViewDesc vd = views[v];
-    const float x0 = fmaxf(ceilf(p.mx - hx - 0.5f), 0.f);
-    const float x1 = fminf(floorf(p.mx + hx - 0.5f), (float)(vd.width - 1));
-    const float y0 = fmaxf(ceilf(p.my - hy - 0.5f), 0.f);
-    const float y1 = fminf(floorf(p.my + hy - 0.5f), (float)(vd.height - 1));
+    const float x0 = fmaxf(ceilf((float)(mxd - hx - 0.5)), 0.f);
+    const float x1 = fminf(floorf((float)(mxd + hx - 0.5)), (float)(vd.width - 1));
+    const float y0 = fmaxf(ceilf((float)(myd - hy - 0.5)), 0.f);
+    const float y1 = fminf(floorf((float)(myd + hy - 0.5)), (float)(vd.height - 1));
     if (!(x0 <= x1) || !(y0 <= y1)) {
         rect[r] = make_uint2(0u, 0u);
         count[r] = 0u;

@@ -17,11 +17,13 @@
 // images are bitwise independent of the tile size and the batch size.
 //
 // The adjoint walks the same list back to front from each pixel's last
-// included splat, rebuilding the transmittance in front of each splat as
-// T_i = T_{i+1} / (1 - alpha_i).  It either starts from the final state
-// (recompute mode, one workgroup per tile) or from (T, colour) checkpoints the
-// forward stored at every LDS-batch boundary (checkpoint mode, persistent
-// workgroups over (tile, batch) units).  The nine per-splat screen-space
+// included splat.  Transmittance modes: recompute (the transmittance in front
+// of each splat is rebuilt as T_i = T_{i+1} / (1 - alpha_i) from the final
+// state; one workgroup per tile), checkpointed ((T, colour) stored by the
+// forward at every LDS-batch boundary; persistent workgroups over (tile, batch)
+// units, each rebuilding T within its batch) and stored (the forward stores
+// T_i of every included (splat, pixel) pair at [key position][pixel of tile];
+// the adjoint reads it; one workgroup per tile).  The nine per-splat screen-space
 // gradient terms of a wave are summed across its lanes with DPP row
 // operations, kept per wave in LDS, and flushed with one global atomic per
 // (unit, splat, field).
@@ -33,13 +35,16 @@ namespace {
 constexpr float kLn2 = 0.69314718055994531f;
 
 // Shared by every kernel that walks a tile list so all take identical decisions.
-// a = (mean x, mean y, A2, B2), b = (C2, opacity, red, green), c = (blue, tau)
-// with A2 = -log2(e) A / 2, B2 = -log2(e) B, C2 = -log2(e) C / 2.
-__device__ __forceinline__ bool splat_alpha(const float4 &a, const float4 &b, const float2 &c,
-                                            float px, float py, float &alpha, float &ae, float &ex,
+// a = (hx, hy, A2, B2), b = (C2, opacity, red, green), c = (blue, tau, ix, iy)
+// with A2 = -log2(e) A / 2, B2 = -log2(e) B, C2 = -log2(e) C / 2; (x, y) is
+// the integer pixel (as float) and (dx, dy) its centre's offset from the mean.
+__device__ __forceinline__ float splat_dx(float x, float ix, float hx) { return (x - ix) + hx; }
+
+__device__ __forceinline__ bool splat_alpha(const float4 &a, const float4 &b, const float4 &c,
+                                            float x, float y, float &alpha, float &ae, float &ex,
                                             float &dx, float &dy) {
-    dx = px - a.x;
-    dy = py - a.y;
+    dx = splat_dx(x, c.z, a.x);
+    dy = splat_dx(y, c.w, a.y);
     const float power2 = fmaf(a.z * dx, dx, fmaf(b.x * dy, dy, (a.w * dx) * dy));
     if (power2 > 0.f || power2 < c.y) return false;
     ex = __builtin_amdgcn_exp2f(power2);
@@ -74,22 +79,25 @@ __device__ __forceinline__ float wave_sum_lane63(float x) {
     return x;
 }
 
-// CKPT: also store (T, colour) of every pixel after each LDS batch that is not
-// the tile's last (slot = boundary position / B, unique over all tiles) and the
-// final (T, colour), so the adjoint can start at any batch.
-template <int T, int B, bool CKPT>
+// MODE 1 (checkpointed): also store (T, colour) of every pixel after each LDS
+// batch that is not the tile's last (slot = boundary position / B, unique over
+// all tiles) and the final (T, colour), so the adjoint can start at any batch.
+// MODE 2 (stored): also store T in front of every included pair at
+// tstore[key position * T*T + pixel of tile].
+template <int T, int B, int MODE>
 __global__ __launch_bounds__(T * T < 256 ? T * T : 256) void k_render_fwd(
     const uint2 *__restrict__ ranges, const uint32_t *__restrict__ vals, SplatPtrs sp,
     const ViewDesc *__restrict__ views, int nviews, const gsf_camera *__restrict__ cams,
     float *__restrict__ out_rgba, float *__restrict__ tfinal, uint32_t *__restrict__ ncontrib,
-    float4 *__restrict__ ckpt, float4 *__restrict__ fstate) {
+    float4 *__restrict__ ckpt, float4 *__restrict__ fstate, float *__restrict__ tstore) {
+    constexpr bool CKPT = MODE == 1;
     constexpr int NT = T * T < 256 ? T * T : 256;
     constexpr int PPT = T * T / NT;
     constexpr int ROWS = NT / T;
     constexpr int U = 4;   // splats between wave-level completion checks
     __shared__ float4 s_a[B];
     __shared__ float4 s_b[B];
-    __shared__ float2 s_c[B];
+    __shared__ float4 s_c[B];
 
     const int gt = blockIdx.x;
     const int v = view_of_tile(views, nviews, gt);
@@ -106,8 +114,8 @@ __global__ __launch_bounds__(T * T < 256 ? T * T : 256) void k_render_fwd(
     for (int k = 0; k < PPT; k++) {
         const int x = tx * T + lx, y = ty * T + ly + k * ROWS;
         done[k] = !(x < vd.width && y < vd.height);
-        px[k] = (float)x + 0.5f;
-        py[k] = (float)y + 0.5f;
+        px[k] = (float)x;   // integer pixel; its centre's offset from a mean is splat_dx
+        py[k] = (float)y;
         Tr[k] = 1.f;
         cr[k] = cg[k] = cb[k] = 0.f;
         last[k] = 0u;
@@ -133,7 +141,7 @@ __global__ __launch_bounds__(T * T < 256 ? T * T : 256) void k_render_fwd(
             // the pixel state; computed without branches (out-of-range or
             // skipped splats get valid = false).
             float4 a[U], b[U];
-            float2 c[U];
+            float4 c[U];
 #pragma unroll
             for (int u = 0; u < U; u++) {
                 const int j = u < nu ? j0 + u : j0;
@@ -147,7 +155,8 @@ __global__ __launch_bounds__(T * T < 256 ? T * T : 256) void k_render_fwd(
                 bool valid[U];
 #pragma unroll
                 for (int u = 0; u < U; u++) {
-                    const float dx = px[k] - a[u].x, dy = py[k] - a[u].y;
+                    const float dx = splat_dx(px[k], c[u].z, a[u].x);
+                    const float dy = splat_dx(py[k], c[u].w, a[u].y);
                     const float power2 =
                         fmaf(a[u].z * dx, dx, fmaf(b[u].x * dy, dy, (a[u].w * dx) * dy));
                     valid[u] = u < nu && !(power2 > 0.f) && !(power2 < c[u].y);
@@ -162,6 +171,8 @@ __global__ __launch_bounds__(T * T < 256 ? T * T : 256) void k_render_fwd(
                     const bool take = valid[u] && !done[k];
                     const bool stop = take && Tn < kTStop;
                     const bool inc = take && !stop;
+                    if (MODE == 2 && inc)
+                        tstore[(size_t)(bs + (uint32_t)(j0 + u)) * (T * T) + threadIdx.x + k * NT] = Tr[k];
                     const float w = alpha[u] * Tr[k];
                     cr[k] = inc ? fmaf(b[u].z, w, cr[k]) : cr[k];
                     cg[k] = inc ? fmaf(b[u].w, w, cg[k]) : cg[k];
@@ -204,18 +215,20 @@ __global__ __launch_bounds__(T * T < 256 ? T * T : 256) void k_render_fwd(
 }
 
 // Unit of adjoint work: the entries [us, ue) of tile gt's list.  With
-// checkpoints (CKPT) a unit is one LDS batch of B entries and starts from the
-// state the forward stored at the batch's end; without, a unit is the whole
-// list and starts from the final state.
-template <int T, int B, bool CKPT>
+// checkpoints (MODE 1) a unit is one LDS batch of B entries and starts from the
+// state the forward stored at the batch's end; otherwise a unit is the whole
+// list and starts from the final state.  MODE 2 reads each included pair's
+// transmittance from tstore instead of dividing.
+template <int T, int B, int MODE>
 __device__ __forceinline__ void render_bwd_unit(
     int gt, uint32_t us, uint32_t ue, bool last_unit, const uint2 &rg,
     const uint32_t *__restrict__ vals, SplatPtrs sp, const ViewDesc *__restrict__ views,
     int nviews, const gsf_camera *__restrict__ cams, const float *__restrict__ tfinal,
     const uint32_t *__restrict__ ncontrib, const float4 *__restrict__ fstate,
-    const float4 *__restrict__ ckpt, const float *__restrict__ dl, float *__restrict__ g2d,
-    int nrec, float4 *s_a, float4 *s_b, float2 *s_c, uint32_t *s_r, float (*s_g)[9][B],
-    uint32_t *s_nmax) {
+    const float4 *__restrict__ ckpt, const float *__restrict__ tstore, const float *__restrict__ dl,
+    float *__restrict__ g2d, int nrec, float4 *s_a, float4 *s_b, float4 *s_c, uint32_t *s_r,
+    float (*s_g)[9][B], uint32_t *s_nmax) {
+    constexpr bool CKPT = MODE == 1;
     constexpr int NT = T * T < 256 ? T * T : 256;
     constexpr int PPT = T * T / NT;
     constexpr int ROWS = NT / T;
@@ -238,8 +251,8 @@ __device__ __forceinline__ void render_bwd_unit(
         const int x = tx * T + lx, y = ty * T + ly + k * ROWS;
         const bool inside = x < vd.width && y < vd.height;
         const size_t q = inside ? (size_t)y * vd.width + x : 0;
-        px[k] = (float)x + 0.5f;
-        py[k] = (float)y + 0.5f;
+        px[k] = (float)x;   // integer pixel; its centre's offset from a mean is splat_dx
+        py[k] = (float)y;
         if (inside) {
             Tf[k] = tfinal[vd.pix_off + q];
             nc[k] = ncontrib[vd.pix_off + q];
@@ -290,7 +303,7 @@ __device__ __forceinline__ void render_bwd_unit(
             const uint32_t pos = bs + (uint32_t)j - rg.x;   // list position in the tile
             const float4 a = s_a[j];
             const float4 b = s_b[j];
-            const float2 c = s_c[j];
+            const float4 c = s_c[j];
             float acc[9];
 #pragma unroll
             for (int f = 0; f < 9; f++) acc[f] = 0.f;
@@ -302,7 +315,8 @@ __device__ __forceinline__ void render_bwd_unit(
                 if (!splat_alpha(a, b, c, px[k], py[k], alpha, ae, ex, dx, dy)) continue;
                 any = true;
                 const float inv = __builtin_amdgcn_rcpf(1.f - alpha);   // alpha <= 0.99
-                const float Tb = Tr[k] * inv;
+                const float Tb = MODE == 2 ? tstore[(size_t)(bs + (uint32_t)j) * (T * T) + threadIdx.x + k * NT]
+                                           : Tr[k] * inv;
                 const float gc = g0[k] * b.z + g1[k] * b.w + g2[k] * c.x;
                 const float dalpha = Tb * gc - (gR[k] - gA[k] * Tf[k]) * inv;
                 const float wT = alpha * Tb;
@@ -343,24 +357,26 @@ __device__ __forceinline__ void render_bwd_unit(
     }
 }
 
-// Recompute mode: one workgroup per tile, the whole list back to front.
-template <int T, int B>
+// Recompute (MODE 0) and stored (MODE 2) modes: one workgroup per tile, the
+// whole list back to front.
+template <int T, int B, int MODE>
 __global__ __launch_bounds__(T * T < 256 ? T * T : 256) void k_render_bwd(
     const uint2 *__restrict__ ranges, const uint32_t *__restrict__ vals, SplatPtrs sp,
     const ViewDesc *__restrict__ views, int nviews, const gsf_camera *__restrict__ cams,
     const float *__restrict__ tfinal, const uint32_t *__restrict__ ncontrib,
-    const float *__restrict__ dl, float *__restrict__ g2d, int nrec) {
+    const float *__restrict__ tstore, const float *__restrict__ dl, float *__restrict__ g2d,
+    int nrec) {
     constexpr int NT = T * T < 256 ? T * T : 256;
     __shared__ float4 s_a[B];
     __shared__ float4 s_b[B];
-    __shared__ float2 s_c[B];
+    __shared__ float4 s_c[B];
     __shared__ uint32_t s_r[B];
     __shared__ float s_g[NT / 64][9][B];
     __shared__ uint32_t s_nmax;
     const uint2 rg = ranges[blockIdx.x];
-    render_bwd_unit<T, B, false>(blockIdx.x, rg.x, rg.y, true, rg, vals, sp, views, nviews, cams,
-                                 tfinal, ncontrib, nullptr, nullptr, dl, g2d, nrec, s_a, s_b, s_c,
-                                 s_r, s_g, &s_nmax);
+    render_bwd_unit<T, B, MODE>(blockIdx.x, rg.x, rg.y, true, rg, vals, sp, views, nviews, cams,
+                                tfinal, ncontrib, nullptr, nullptr, tstore, dl, g2d, nrec, s_a, s_b,
+                                s_c, s_r, s_g, &s_nmax);
 }
 
 // Checkpoint mode: persistent workgroups over (tile, batch) units.  Unit u of
@@ -377,7 +393,7 @@ __global__ __launch_bounds__(T * T < 256 ? T * T : 256) void k_render_bwd_ckpt(
     constexpr int NT = T * T < 256 ? T * T : 256;
     __shared__ float4 s_a[B];
     __shared__ float4 s_b[B];
-    __shared__ float2 s_c[B];
+    __shared__ float4 s_c[B];
     __shared__ uint32_t s_r[B];
     __shared__ float s_g[NT / 64][9][B];
     __shared__ uint32_t s_nmax;
@@ -396,9 +412,9 @@ __global__ __launch_bounds__(T * T < 256 ? T * T : 256) void k_render_bwd_ckpt(
         if (u >= units) continue;
         const uint32_t us = rg.x + u * B;
         const uint32_t ue = min(rg.y, us + B);
-        render_bwd_unit<T, B, true>(lo, us, ue, u + 1 == units, rg, vals, sp, views, nviews, cams,
-                                    tfinal, ncontrib, fstate, ckpt, dl, g2d, nrec, s_a, s_b, s_c,
-                                    s_r, s_g, &s_nmax);
+        render_bwd_unit<T, B, 1>(lo, us, ue, u + 1 == units, rg, vals, sp, views, nviews, cams,
+                                 tfinal, ncontrib, fstate, ckpt, nullptr, dl, g2d, nrec, s_a, s_b,
+                                 s_c, s_r, s_g, &s_nmax);
     }
 }
 
@@ -425,7 +441,7 @@ __global__ __launch_bounds__(T * T < 256 ? T * T : 256) void k_count_pairs(
     for (int k = 0; k < PPT; k++) {
         const int x = tx * T + threadIdx.x % T, y = ty * T + threadIdx.x / T + k * ROWS;
         if (!(x < vd.width && y < vd.height)) continue;
-        const float px = (float)x + 0.5f, py = (float)y + 0.5f;
+        const float px = (float)x, py = (float)y;
         float Tr = 1.f;
         uint32_t last = 0;
         for (uint32_t e = rg.x; e < rg.y; e++) {
@@ -575,27 +591,36 @@ __global__ void k_fill_f32(float *p, int64_t n, float value) {
 template <int T, int B>
 void render_fwd_tb(hipStream_t s, const RenderArgs &a, float *out) {
     constexpr int NT = T * T < 256 ? T * T : 256;
-    if (a.ckpt_mode)
-        k_render_fwd<T, B, true><<<a.total_tiles, NT, 0, s>>>(a.ranges, a.vals, a.sp, a.views, a.nviews,
-                                                             a.cams, out, a.tfinal, a.ncontrib, a.ckpt,
-                                                             a.fstate);
+    if (a.t_mode == 1)
+        k_render_fwd<T, B, 1><<<a.total_tiles, NT, 0, s>>>(a.ranges, a.vals, a.sp, a.views, a.nviews,
+                                                          a.cams, out, a.tfinal, a.ncontrib, a.ckpt,
+                                                          a.fstate, nullptr);
+    else if (a.t_mode == 2)
+        k_render_fwd<T, B, 2><<<a.total_tiles, NT, 0, s>>>(a.ranges, a.vals, a.sp, a.views, a.nviews,
+                                                          a.cams, out, a.tfinal, a.ncontrib, nullptr,
+                                                          nullptr, a.tstore);
     else
-        k_render_fwd<T, B, false><<<a.total_tiles, NT, 0, s>>>(a.ranges, a.vals, a.sp, a.views, a.nviews,
-                                                              a.cams, out, a.tfinal, a.ncontrib, nullptr,
-                                                              nullptr);
+        k_render_fwd<T, B, 0><<<a.total_tiles, NT, 0, s>>>(a.ranges, a.vals, a.sp, a.views, a.nviews,
+                                                          a.cams, out, a.tfinal, a.ncontrib, nullptr,
+                                                          nullptr, nullptr);
 }
 
 template <int T, int B>
 void render_bwd_tb(hipStream_t s, const RenderArgs &a, const float *dl, float *g2d) {
     constexpr int NT = T * T < 256 ? T * T : 256;
-    if (a.ckpt_mode)
+    if (a.t_mode == 1)
         k_render_bwd_ckpt<T, B><<<a.bwd_grid, NT, 0, s>>>(a.ranges, a.total_tiles, a.m_dev, a.m_host,
                                                          a.vals, a.sp, a.views, a.nviews, a.cams,
                                                          a.tfinal, a.ncontrib, a.fstate, a.ckpt, dl,
                                                          g2d, a.nrec);
+    else if (a.t_mode == 2)
+        k_render_bwd<T, B, 2><<<a.total_tiles, NT, 0, s>>>(a.ranges, a.vals, a.sp, a.views, a.nviews,
+                                                          a.cams, a.tfinal, a.ncontrib, a.tstore, dl,
+                                                          g2d, a.nrec);
     else
-        k_render_bwd<T, B><<<a.total_tiles, NT, 0, s>>>(a.ranges, a.vals, a.sp, a.views, a.nviews,
-                                                       a.cams, a.tfinal, a.ncontrib, dl, g2d, a.nrec);
+        k_render_bwd<T, B, 0><<<a.total_tiles, NT, 0, s>>>(a.ranges, a.vals, a.sp, a.views, a.nviews,
+                                                          a.cams, a.tfinal, a.ncontrib, nullptr, dl,
+                                                          g2d, a.nrec);
 }
 
 template <int T>

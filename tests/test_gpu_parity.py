@@ -97,7 +97,8 @@ def test_image_matches_oracle_cfg1(ctx):
     np.testing.assert_array_equal(last_gpu[ok], ref.last[ok])
 
 
-@pytest.mark.parametrize("deg,t_mode,batch", [(0, 0, 128), (3, 0, 128), (0, 1, 64), (3, 1, 128)])
+@pytest.mark.parametrize("deg,t_mode,batch", [(0, 0, 128), (3, 0, 128), (0, 1, 64), (3, 1, 128),
+                                               (0, 2, 64), (3, 2, 256)])
 def test_multiview_image_and_gradient(ctx, deg, t_mode, batch):
     P = synth.random_gaussians(400, seed=5, sh_degree=deg)
     cams = [synth.look_at_camera([0.3, -0.2, -3.0], width=96, height=80, bg=(0.1, 0.2, 0.3)),
@@ -152,20 +153,22 @@ def test_loss_and_dl_match_oracle(ctx):
 
 
 @pytest.mark.parametrize("tile,batch", [(8, 64), (16, 64), (16, 128), (32, 64)])
-def test_checkpointed_adjoint_matches_recompute(ctx, tile, batch):
-    """Same image bits; gradients equal within tolerance (the checkpointed
-    adjoint starts every LDS batch from stored state)."""
+def test_transmittance_modes_agree(ctx, tile, batch):
+    """Recomputed, checkpointed and stored transmittance: same image bits,
+    gradients equal within tolerance."""
     P = synth.random_gaussians(1500, seed=8)
     cam = synth.look_at_camera([0.2, 0.4, -3.0], width=112, height=90, bg=(0.3, 0.1, 0.2))
-    a = GpuScene(ctx, P, [cam], tile=tile, batch=batch, t_mode=0)
-    b = GpuScene(ctx, P, [cam], tile=tile, batch=batch, t_mode=1)
-    ia, ib = a.forward()[0], b.forward()[0]
-    np.testing.assert_array_equal(ia.view(np.uint32), ib.view(np.uint32))
+    scenes = [GpuScene(ctx, P, [cam], tile=tile, batch=batch, t_mode=m) for m in (0, 1, 2)]
+    imgs = [sc.forward()[0] for sc in scenes]
+    for img in imgs[1:]:
+        np.testing.assert_array_equal(imgs[0].view(np.uint32), img.view(np.uint32))
     dl = [np.random.default_rng(2).normal(size=(4, cam.npix))]
-    ga, gb = a.backward(dl), b.backward(dl)
-    rep = grads_close(gb, ga.astype(np.float64))
-    log(f"[parity] tile {tile} batch {batch}: ckpt vs recompute {rep}")
-    assert all(nb == 0 for _, nb, _ in rep), rep
+    grads = [sc.backward(dl) for sc in scenes]
+    for m in (1, 2):
+        rep = grads_close(grads[m], grads[0].astype(np.float64))
+        log(f"[parity] tile {tile} batch {batch}: t_mode {m} vs recompute {rep}")
+        assert all(nb == 0 for _, nb, _ in rep), rep
+    a = scenes[0]
     ranges = a.debug(_abi.GSF_DBG_RANGES, np.uint32, 2 * a.plan.total_tiles).reshape(-1, 2)
     assert (ranges[:, 1] - ranges[:, 0]).max() > 2 * batch   # several batches per tile exercised
 
@@ -180,19 +183,22 @@ def test_checkpointed_adjoint_with_empty_tiles(ctx):
             synth.look_at_camera([2.5, 1.0, 1.0], width=192, height=144)]
     a = GpuScene(ctx, P, cams, tile=16, batch=64, t_mode=0)
     b = GpuScene(ctx, P, cams, tile=16, batch=64, t_mode=1)
-    ia, ib = a.forward(), b.forward()
-    for x, y in zip(ia, ib):
+    c = GpuScene(ctx, P, cams, tile=16, batch=64, t_mode=2)
+    ia, ib, ic = a.forward(), b.forward(), c.forward()
+    for x, y, z in zip(ia, ib, ic):
         np.testing.assert_array_equal(x.view(np.uint32), y.view(np.uint32))
+        np.testing.assert_array_equal(x.view(np.uint32), z.view(np.uint32))
     ranges = b.debug(_abi.GSF_DBG_RANGES, np.uint32, 2 * b.plan.total_tiles).reshape(-1, 2)
     empty = ranges[:, 1] == ranges[:, 0]
     assert empty.sum() > ranges.shape[0] // 2 and (~empty[:-1] & empty[1:]).any()
     assert (ranges[:, 1] - ranges[:, 0]).max() > 2 * 64
     rng = np.random.default_rng(4)
     dls = [rng.normal(size=(4, c.npix)) for c in cams]
-    ga, gb = a.backward(dls), b.backward(dls)
-    rep = grads_close(gb, ga.astype(np.float64))
-    log(f"[parity] sparse scene ckpt vs recompute {rep}")
-    assert all(nb == 0 for _, nb, _ in rep), rep
+    ga, gb, gc = a.backward(dls), b.backward(dls), c.backward(dls)
+    for g in (gb, gc):
+        rep = grads_close(g, ga.astype(np.float64))
+        log(f"[parity] sparse scene mode vs recompute {rep}")
+        assert all(nb == 0 for _, nb, _ in rep), rep
     refs = [oracle.render(P, c) for c in cams]
     for dl, ref in zip(dls, refs):
         dl[:, ref.flags != 0] = 0.0
