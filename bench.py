@@ -276,7 +276,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
-                    help="use --tile/--lds-batch instead of sweeping tile x LDS batch")
+                    help="use --tile/--lds-batch/--t-mode instead of sweeping tile x LDS batch x "
+                         "transmittance mode (recomputed, checkpointed)")
     ap.add_argument("--compare-t-modes", action="store_true",
                     help="also time the captured step and record peak device memory with each "
                          "transmittance mode (always on for --workload stereo)")
@@ -332,11 +333,13 @@ def main():
 
         tune = None
         if not args.no_autotune:
-            best, sweep = gs.autotune(ctx, P_dev, cams, tgt_dev, gaze_dev, cfg=cfg, stream=stream)
-            tune = {"best": list(best), "us_per_step": {f"{t}x{b}": round(ms * 1e3, 1)
-                                                        for (t, b), ms in sorted(sweep.items())}}
-            cfg = dataclasses.replace(cfg, tile=best[0], lds_batch=best[1])
-            log(f"[bench] autotune: best tile {best[0]} batch {best[1]}; {tune['us_per_step']}")
+            best, sweep = gs.autotune(ctx, P_dev, cams, tgt_dev, gaze_dev, cfg=cfg, t_modes=(0, 1),
+                                      stream=stream)
+            tune = {"best": list(best), "us_per_step": {f"{t}x{b}/t{m}": round(ms * 1e3, 1)
+                                                        for (t, b, m), ms in sorted(sweep.items())}}
+            cfg = dataclasses.replace(cfg, tile=best[0], lds_batch=best[1], t_mode=best[2])
+            log(f"[bench] autotune: best tile {best[0]} batch {best[1]} t_mode {best[2]}; "
+                f"{tune['us_per_step']}")
 
         # fused, captured: the timed path
         fused = fit(cfg)

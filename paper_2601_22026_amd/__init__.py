@@ -252,8 +252,8 @@ class FitStep:
     fused=True: one plan over all views (one launch per stage), key count kept
     on the device, checkpointed transmittance (cfg.t_mode), and ``capture()``
     records the whole step in a HIP graph that ``replay()`` launches.
-    fused=False: the plain path - one host-synchronised plan per view,
-    transmittance recomputed in the adjoint, eager launches, views one after
+    fused=False: the plain path - one host-synchronised plan per view (same
+    tile, LDS batch and transmittance mode), eager launches, views one after
     another (the loss of each view is normalised by that view's own masked
     count).
     """
@@ -292,7 +292,7 @@ class FitStep:
             off = 0
             for k, (w, h) in enumerate(self.sizes):
                 p = Plan(ctx, self.n, [(w, h)], self.sh_degree, cfg.tile, cfg.lds_batch,
-                         host_sized=True, key_capacity=cfg.key_capacity)
+                         host_sized=True, key_capacity=cfg.key_capacity, t_mode=cfg.t_mode)
                 sl = slice(off, off + w * h)
                 self.view_plans.append((p, self.cams_dev[128 * k:128 * (k + 1)], sl))
                 off += w * h
@@ -379,35 +379,43 @@ _TUNE_CACHE: dict = {}
 
 def autotune(ctx: Context, params: torch.Tensor, cams, targets: torch.Tensor,
              gaze: Optional[torch.Tensor] = None, cfg: FitConfig = FitConfig(),
-             tiles=(8, 16, 32), batches=(64, 128, 256), warmup: int = 3, reps: int = 10,
-             stream=None):
-    """Pick the tile size and LDS batch that make the captured fused step
-    fastest on this input shape.  Each candidate is captured once and timed
-    with HIP events over ``reps`` replays (Adam disabled so every candidate
-    sees the same parameters).  Results are cached per (n, SH degree, view
-    sizes, t_mode).  Returns (best (tile, batch), {(tile, batch): ms/step})."""
+             tiles=(8, 16, 32), batches=(64, 128, 256), t_modes=None, warmup: int = 3,
+             reps: int = 10, stream=None):
+    """Pick the tile size, LDS batch and (optionally) adjoint transmittance mode
+    that make the captured fused step fastest on this input shape.  Each
+    candidate is captured once and timed with HIP events over ``reps`` replays
+    (Adam disabled so every candidate sees the same parameters).  ``t_modes``
+    defaults to ``(cfg.t_mode,)``.  Results are cached per (n, SH degree, view
+    sizes, candidates).  Returns (best (tile, batch, t_mode),
+    {(tile, batch, t_mode): ms/step})."""
     import dataclasses
-    key = (params.shape[1], params.shape[0], tuple((c.width, c.height) for c in cams), cfg.t_mode,
-           tuple(tiles), tuple(batches))
+    t_modes = tuple(t_modes) if t_modes is not None else (cfg.t_mode,)
+    key = (params.shape[1], params.shape[0], tuple((c.width, c.height) for c in cams),
+           tuple(tiles), tuple(batches), t_modes)
     if key in _TUNE_CACHE:
         return _TUNE_CACHE[key]
     stream = stream or torch.cuda.current_stream()
+    if stream.cuda_stream == 0:          # graphs cannot be captured on the null stream
+        stream = torch.cuda.Stream()
     times = {}
-    for t in tiles:
-        for b in batches:
-            c = dataclasses.replace(cfg, tile=t, lds_batch=b, lr=0.0)
-            fs = FitStep(ctx, params.detach().clone(), cams, targets, gaze, c, fused=True)
-            fs.capture()
-            for _ in range(warmup):
-                fs.replay()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            for _ in range(reps):
-                fs.replay()
-            e1.record(stream)
-            e1.synchronize()
-            times[(t, b)] = e0.elapsed_time(e1) / reps
-            fs.plan.close()
+    with torch.cuda.stream(stream):
+        for t in tiles:
+            for b in batches:
+                for m in t_modes:
+                    c = dataclasses.replace(cfg, tile=t, lds_batch=b, t_mode=m, lr=0.0)
+                    fs = FitStep(ctx, params.detach().clone(), cams, targets, gaze, c, fused=True)
+                    fs.capture()
+                    for _ in range(warmup):
+                        fs.replay()
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
+                    for _ in range(reps):
+                        fs.replay()
+                    e1.record(stream)
+                    e1.synchronize()
+                    times[(t, b, m)] = e0.elapsed_time(e1) / reps
+                    fs.plan.close()
     best = min(times, key=times.get)
     _TUNE_CACHE[key] = (best, times)
     return best, times

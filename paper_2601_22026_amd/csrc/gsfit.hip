@@ -490,7 +490,7 @@ gsf_status gsf_plan_create(gsf_ctx *ctx, const gsf_plan_desc *d, gsf_plan **out)
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess || cus < 1)
             cus = 256;
         const int64_t units_max = p->cap / p->batch + p->total_tiles;
-        const int64_t per_cu = p->tile == 8 ? 16 : 8;
+        const int64_t per_cu = p->tile == 32 ? 16 : 32;   // one- or two-wave workgroups
         p->bwd_grid = (int)std::max<int64_t>(1, std::min<int64_t>(units_max, per_cu * cus));
     }
     p->ws_bytes = carve(p, nullptr, nullptr);

@@ -53,6 +53,13 @@ __device__ __forceinline__ bool splat_alpha(const float4 &a, const float4 &b, co
     return true;
 }
 
+// Threads of an adjoint workgroup: one wave per 8x8 or 16x16 tile (1 or 4 pixels
+// per lane), two waves per 32x32 tile (8 pixels per lane).  Each lane first sums
+// its own pixels' contributions, so the per-splat cross-lane reductions, the
+// bulk of the adjoint's VALU work, are shared by more pixels.
+template <int T>
+constexpr int bwd_threads() { return T == 32 ? 128 : 64; }
+
 __device__ __forceinline__ int view_of_tile(const ViewDesc *__restrict__ views, int nviews, int gt) {
     int v = 0;
     while (v + 1 < nviews && gt >= views[v + 1].tile_off) v++;
@@ -229,7 +236,7 @@ __device__ __forceinline__ void render_bwd_unit(
     float *__restrict__ g2d, int nrec, float4 *s_a, float4 *s_b, float4 *s_c, uint32_t *s_r,
     float (*s_g)[9][B], uint32_t *s_nmax) {
     constexpr bool CKPT = MODE == 1;
-    constexpr int NT = T * T < 256 ? T * T : 256;
+    constexpr int NT = bwd_threads<T>();
     constexpr int PPT = T * T / NT;
     constexpr int ROWS = NT / T;
     constexpr int NW = NT / 64;
@@ -269,6 +276,8 @@ __device__ __forceinline__ void render_bwd_unit(
         if (CKPT && !last_unit && rg.x + nc[k] > us) {
             // colour behind the unit = final colour - colour accumulated at its end
             const float4 fs = fstate[vd.pix_off + q];
+            // threadIdx.x + k * NT is the pixel's row-major index in the tile, the
+            // index the forward wrote with its own thread count
             const float4 cp = ckpt[(size_t)(ue / B) * (T * T) + threadIdx.x + k * NT];
             Tr[k] = cp.x;
             gR[k] = gbg + g0[k] * (fs.y - cp.y) + g1[k] * (fs.z - cp.z) + g2[k] * (fs.w - cp.w);
@@ -360,13 +369,13 @@ __device__ __forceinline__ void render_bwd_unit(
 // Recompute (MODE 0) and stored (MODE 2) modes: one workgroup per tile, the
 // whole list back to front.
 template <int T, int B, int MODE>
-__global__ __launch_bounds__(T * T < 256 ? T * T : 256) void k_render_bwd(
+__global__ __launch_bounds__(bwd_threads<T>()) void k_render_bwd(
     const uint2 *__restrict__ ranges, const uint32_t *__restrict__ vals, SplatPtrs sp,
     const ViewDesc *__restrict__ views, int nviews, const gsf_camera *__restrict__ cams,
     const float *__restrict__ tfinal, const uint32_t *__restrict__ ncontrib,
     const float *__restrict__ tstore, const float *__restrict__ dl, float *__restrict__ g2d,
     int nrec) {
-    constexpr int NT = T * T < 256 ? T * T : 256;
+    constexpr int NT = bwd_threads<T>();
     __shared__ float4 s_a[B];
     __shared__ float4 s_b[B];
     __shared__ float4 s_c[B];
@@ -383,14 +392,14 @@ __global__ __launch_bounds__(T * T < 256 ? T * T : 256) void k_render_bwd(
 // tile t has id floor(start_t / B) + t + u (strictly increasing, below
 // M / B + tiles); a workgroup maps an id back to its tile by binary search.
 template <int T, int B>
-__global__ __launch_bounds__(T * T < 256 ? T * T : 256) void k_render_bwd_ckpt(
+__global__ __launch_bounds__(bwd_threads<T>()) void k_render_bwd_ckpt(
     const uint2 *__restrict__ ranges, int total_tiles, const uint32_t *__restrict__ m_dev,
     uint32_t m_host, const uint32_t *__restrict__ vals, SplatPtrs sp,
     const ViewDesc *__restrict__ views, int nviews, const gsf_camera *__restrict__ cams,
     const float *__restrict__ tfinal, const uint32_t *__restrict__ ncontrib,
     const float4 *__restrict__ fstate, const float4 *__restrict__ ckpt,
     const float *__restrict__ dl, float *__restrict__ g2d, int nrec) {
-    constexpr int NT = T * T < 256 ? T * T : 256;
+    constexpr int NT = bwd_threads<T>();
     __shared__ float4 s_a[B];
     __shared__ float4 s_b[B];
     __shared__ float4 s_c[B];
@@ -607,7 +616,7 @@ void render_fwd_tb(hipStream_t s, const RenderArgs &a, float *out) {
 
 template <int T, int B>
 void render_bwd_tb(hipStream_t s, const RenderArgs &a, const float *dl, float *g2d) {
-    constexpr int NT = T * T < 256 ? T * T : 256;
+    constexpr int NT = bwd_threads<T>();
     if (a.t_mode == 1)
         k_render_bwd_ckpt<T, B><<<a.bwd_grid, NT, 0, s>>>(a.ranges, a.total_tiles, a.m_dev, a.m_host,
                                                          a.vals, a.sp, a.views, a.nviews, a.cams,

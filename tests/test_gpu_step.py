@@ -1,6 +1,5 @@
 """GPU tests of the whole step: Adam, graph replay, multi-step fit, autograd,
-failure paths, edge cases and the full-size workload (sampled against the
-oracle)."""
+autotuning, failure paths and edge cases."""
 import os
 
 import numpy as np
@@ -237,3 +236,27 @@ def test_edge_cases(gs, ctx):
         dl[:, ref.flags != 0] = 0
         rep = grads_close(sc.backward([dl]), oracle.backward(huge, cam, dl.astype(np.float32).astype(np.float64)))
         assert all(nb == 0 for _, nb, _ in rep), rep
+
+
+def test_autotune_sweeps_and_candidates_render_identically(gs, ctx):
+    """The autotuner times every (tile, LDS batch, transmittance mode)
+    candidate of the captured step and returns the fastest; every candidate
+    renders the same image bits (the per-pixel arithmetic does not depend on
+    them) and is a valid plan."""
+    P = synth.random_gaussians(1000, seed=0)
+    cam = synth.axis_camera(128, 128)
+    tgt = torch.from_numpy(np.ascontiguousarray(_cfg1_target().reshape(-1))).to(DEV)
+    Pd = torch.from_numpy(P).to(DEV)
+    best, times = gs.autotune(ctx, Pd, [cam], tgt, tiles=(8, 16, 32), batches=(64, 256),
+                              t_modes=(0, 1, 2), warmup=1, reps=2)
+    assert set(times) == {(t, b, m) for t in (8, 16, 32) for b in (64, 256) for m in (0, 1, 2)}
+    assert best == min(times, key=times.get) and all(v > 0 for v in times.values())
+    imgs = []
+    for (t, b, m) in [best, (8, 64, 2), (32, 256, 1)]:
+        fs = gs.FitStep(ctx, Pd.clone(), [cam], tgt, cfg=gs.FitConfig(tile=t, lds_batch=b, t_mode=m))
+        fs.plan.forward(fs.params, fs.n, fs.cams_dev, fs.rgba)
+        torch.cuda.synchronize()
+        imgs.append(fs.rgba.cpu().numpy())
+        fs.plan.close()
+    for img in imgs[1:]:
+        np.testing.assert_array_equal(imgs[0].view(np.uint32), img.view(np.uint32))
