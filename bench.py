@@ -188,7 +188,7 @@ def hbm_bytes_per_launch(stage, N, R, M, npix, planes, tiles):
         "project": planes * 4 * N + 92 * R,                   # params in; splat, key, box, count, g2d clear
         "duplicate": 16 * R + 8 * M + 8 * tiles,              # counts (twice), boxes in; pairs out; ranges cleared
         "tile_sort": passes * 20 * M,                         # per pass: key histogram, pair in, pair out
-        "ranges": 4 * M + 8 * tiles,                          # sorted tile ids in; ranges out
+        "ranges": 4 * M + 28 * tiles,                         # sorted tile ids in; ranges out; order
         "depth_sort": 12 * M,                                 # record ids in, depth gather, record ids out
         "render": 40 * M + 24 * npix,                         # splat gather per key; RGBA, T, count out
         "loss": 40 * npix,                                    # RGBA, target in; dL/dRGBA out

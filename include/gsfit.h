@@ -201,12 +201,12 @@ gsf_status gsf_step_replay(gsf_plan *plan);
 /* Per-stage GPU timing of eager calls on a plan (hipEvents recorded around each
  * stage on the context stream; not available while capturing).  Enabling
  * resets the accumulators.  Stages holding exactly one kernel: PROJECT,
- * RANGES, DEPTH_SORT, RENDER, RENDER_BWD, PROJECT_BWD. */
+ * DEPTH_SORT, RENDER, RENDER_BWD, PROJECT_BWD. */
 enum {
     GSF_STAGE_PROJECT = 0,     /* projection + support boxes (one kernel) */
     GSF_STAGE_DUPLICATE = 1,   /* scan of the per-record tile counts + key emission */
     GSF_STAGE_TILE_SORT = 2,   /* stable radix sort of the keys by tile */
-    GSF_STAGE_RANGES = 3,      /* per-tile ranges from the key boundaries (one kernel) */
+    GSF_STAGE_RANGES = 3,      /* per-tile ranges from the key boundaries + compositing order */
     GSF_STAGE_DEPTH_SORT = 4,  /* per-tile stable LDS radix sort by depth (one kernel) */
     GSF_STAGE_RENDER = 5,      /* forward compositing (one kernel) */
     GSF_STAGE_LOSS = 6,        /* masked L1 loss */
@@ -241,8 +241,10 @@ enum {
     GSF_DBG_TFINAL = 6,    /* float per pixel (all views concatenated) */
     GSF_DBG_NCONTRIB = 7,  /* uint32 per pixel: list entries up to the last included */
     GSF_DBG_G2D = 8,       /* float [9][n_views * n]: per-record screen-space gradient */
-    GSF_DBG_PROJ = 9       /* float [11] per record: mean x, mean y, conic A, B, C, opacity,
+    GSF_DBG_PROJ = 9,      /* float [11] per record: mean x, mean y, conic A, B, C, opacity,
                               red, green, blue, camera depth, valid (1 or 0) */
+    GSF_DBG_ORDER = 10     /* uint32 per global tile: compositing order of the tiles (a
+                              permutation; tiles with more keys first) */
 };
 /* Synchronise and copy an internal buffer of the last forward/backward to host
  * memory (at most cap bytes; bytes copied in *written). */

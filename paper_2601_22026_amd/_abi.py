@@ -17,7 +17,7 @@ STATUS_NAMES = {0: "GSF_OK", 1: "GSF_E_INVALID", 2: "GSF_E_CAPACITY", 3: "GSF_E_
 GSF_FLAG_CAPACITY = 1
 GSF_FLAG_NONFINITE = 2
 (GSF_DBG_RECT, GSF_DBG_COUNT, GSF_DBG_DEPTH, GSF_DBG_KEYS, GSF_DBG_VALS, GSF_DBG_RANGES,
- GSF_DBG_TFINAL, GSF_DBG_NCONTRIB, GSF_DBG_G2D, GSF_DBG_PROJ) = range(10)
+ GSF_DBG_TFINAL, GSF_DBG_NCONTRIB, GSF_DBG_G2D, GSF_DBG_PROJ, GSF_DBG_ORDER) = range(11)
 
 EXPORTED = ["gsf_ctx_create", "gsf_ctx_destroy", "gsf_ctx_set_stream", "gsf_last_error",
             "gsf_plan_create", "gsf_plan_workspace_bytes", "gsf_plan_bind_workspace",

@@ -97,6 +97,13 @@ int radix_grid_for(int64_t capacity);
 void launch_tile_bounds(hipStream_t s, const uint32_t *keys, const uint32_t *m_dev, uint32_t m_host,
                         int64_t capacity, int total_tiles, uint2 *ranges);
 
+// order = all tile ids, tiles with more keys first (by floor(log2(key count)),
+// empty tiles last; order within a class unspecified).  counts: scratch of
+// 33 * order_groups(total_tiles) words.
+void launch_tile_order(hipStream_t s, const uint2 *ranges, int total_tiles, uint32_t *order,
+                       uint32_t *counts);
+int order_groups(int64_t total_tiles);
+
 // Stable per-tile sort of vals by depth_key[val]; gk0, gk1, gv1: key-capacity
 // scratch for lists longer than the LDS capacity.
 void launch_tile_sort(hipStream_t s, const uint2 *ranges, int total_tiles, const uint32_t *depth_key,
@@ -106,7 +113,8 @@ void launch_tile_sort(hipStream_t s, const uint2 *ranges, int total_tiles, const
 struct RenderArgs {
     int tile = 16, batch = 128, total_tiles = 0, nviews = 1, nrec = 0;
     int t_mode = 0;                       // 0 recompute, 1 checkpointed, 2 stored transmittance
-    int bwd_grid = 1;                     // persistent workgroups of the checkpointed adjoint
+    int bwd_grid = 1;                     // workgroups of the checkpointed adjoint (unit ids)
+    const uint32_t *order = nullptr;      // tile ids, heavy tiles first
     const uint2 *ranges = nullptr;
     const uint32_t *vals = nullptr;
     SplatPtrs sp{};

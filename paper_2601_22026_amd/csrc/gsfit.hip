@@ -41,6 +41,8 @@ struct Buffers {
     uint32_t *block_sums = nullptr;              // scan of the per-record tile counts
     // per global tile
     uint2 *ranges = nullptr;
+    uint32_t *order = nullptr;                   // compositing order of the tiles
+    uint32_t *order_counts = nullptr;            // per-workgroup class counts of that order
     // per key (key capacity): two (tile id, record id) buffers for the radix
     // sort.  After the sort, `vals` is the sorted record-id list the compositing
     // reads; the rest is scratch for per-tile lists longer than the LDS sort holds.
@@ -137,6 +139,8 @@ size_t carve(gsf_plan *p, char *base, Buffers *out) {
     const size_t T = (size_t)p->total_tiles;
     b.block_sums = (uint32_t *)take((size_t)scan_blocks(p->nrec_max) * 4);
     b.ranges = (uint2 *)take(T * sizeof(uint2));
+    b.order = (uint32_t *)take(T * 4);
+    b.order_counts = (uint32_t *)take((size_t)33 * order_groups(p->total_tiles) * 4);
     b.k0 = (uint32_t *)take((size_t)p->cap * 4);
     b.v0 = (uint32_t *)take((size_t)p->cap * 4);
     b.k1 = (uint32_t *)take((size_t)p->cap * 4);
@@ -184,6 +188,7 @@ RenderArgs render_args(gsf_plan *p, const gsf_camera *cams, int64_t n) {
     a.nviews = p->V;
     a.nrec = (int)(n * p->V);
     a.t_mode = p->t_mode;
+    a.order = p->b.order;
     a.bwd_grid = p->bwd_grid;
     a.ranges = p->b.ranges;
     a.vals = p->b.vals;
@@ -284,6 +289,7 @@ gsf_status enqueue_forward(gsf_plan *p, const float *params, int64_t n, const gs
     {
         StageTimer t(p, GSF_STAGE_RANGES);
         launch_tile_bounds(s, b.keys, m_dev, p->m_host, p->cap, (int)p->total_tiles, b.ranges);
+        launch_tile_order(s, b.ranges, (int)p->total_tiles, b.order, b.order_counts);
     }
     GSF_LAUNCHED(ctx);
     {   // each tile's list by (depth, record); the sorted tile ids are free scratch now
@@ -485,14 +491,9 @@ gsf_status gsf_plan_create(gsf_ctx *ctx, const gsf_plan_desc *d, gsf_plan **out)
     p->tile_bits = 0;                         // bits of the largest global tile id
     while ((int64_t(1) << p->tile_bits) < p->total_tiles) p->tile_bits++;
     p->radix_grid = radix_grid_for(p->cap);
-    {   // persistent workgroups of the checkpointed adjoint: enough to fill every CU
-        int cus = 256;
-        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess || cus < 1)
-            cus = 256;
-        const int64_t units_max = p->cap / p->batch + p->total_tiles;
-        const int64_t per_cu = p->tile == 32 ? 16 : 32;   // one- or two-wave workgroups
-        p->bwd_grid = (int)std::max<int64_t>(1, std::min<int64_t>(units_max, per_cu * cus));
-    }
+    // checkpointed adjoint: one workgroup per possible (tile, batch) unit id
+    p->bwd_grid = (int)std::max<int64_t>(1, std::min<int64_t>(p->cap / p->batch + p->total_tiles,
+                                                               0x7FFFFFFFll));
     p->ws_bytes = carve(p, nullptr, nullptr);
     if (hipHostMalloc((void **)&p->pinned, sizeof(unsigned long long)) != hipSuccess) {
         delete p;
@@ -726,6 +727,7 @@ gsf_status gsf_debug_copy(gsf_plan *p, int which, void *host_dst, size_t cap, si
     }
     case GSF_DBG_VALS: src = p->b.vals; bytes = M * 4; break;
     case GSF_DBG_RANGES: src = p->b.ranges; bytes = (size_t)p->total_tiles * 8; break;
+    case GSF_DBG_ORDER: src = p->b.order; bytes = (size_t)p->total_tiles * 4; break;
     case GSF_DBG_TFINAL: src = p->b.tfinal; bytes = (size_t)p->total_pix * 4; break;
     case GSF_DBG_NCONTRIB: src = p->b.ncontrib; bytes = (size_t)p->total_pix * 4; break;
     case GSF_DBG_G2D: src = p->b.g2d; bytes = 9 * R * 4; break;

@@ -91,8 +91,13 @@ __device__ __forceinline__ float wave_sum_lane63(float x) {
 // all tiles) and the final (T, colour), so the adjoint can start at any batch.
 // MODE 2 (stored): also store T in front of every included pair at
 // tstore[key position * T*T + pixel of tile].
+// One workgroup per tile, workgroup i taking tile order[i]: the order lists
+// tiles with more keys first, so the dispatcher starts the heavy tiles on
+// different CUs at once and fills in with light ones as slots free up, however
+// the keys cluster on screen.
 template <int T, int B, int MODE>
 __global__ __launch_bounds__(T * T < 256 ? T * T : 256) void k_render_fwd(
+    const uint32_t *__restrict__ order,
     const uint2 *__restrict__ ranges, const uint32_t *__restrict__ vals, SplatPtrs sp,
     const ViewDesc *__restrict__ views, int nviews, const gsf_camera *__restrict__ cams,
     float *__restrict__ out_rgba, float *__restrict__ tfinal, uint32_t *__restrict__ ncontrib,
@@ -106,7 +111,7 @@ __global__ __launch_bounds__(T * T < 256 ? T * T : 256) void k_render_fwd(
     __shared__ float4 s_b[B];
     __shared__ float4 s_c[B];
 
-    const int gt = blockIdx.x;
+    const int gt = (int)order[blockIdx.x];
     const int v = view_of_tile(views, nviews, gt);
     const ViewDesc vd = views[v];
     const int local = gt - vd.tile_off;
@@ -367,9 +372,10 @@ __device__ __forceinline__ void render_bwd_unit(
 }
 
 // Recompute (MODE 0) and stored (MODE 2) modes: one workgroup per tile, the
-// whole list back to front.
+// whole list back to front; workgroup i takes tile order[i] like the forward.
 template <int T, int B, int MODE>
 __global__ __launch_bounds__(bwd_threads<T>()) void k_render_bwd(
+    const uint32_t *__restrict__ order,
     const uint2 *__restrict__ ranges, const uint32_t *__restrict__ vals, SplatPtrs sp,
     const ViewDesc *__restrict__ views, int nviews, const gsf_camera *__restrict__ cams,
     const float *__restrict__ tfinal, const uint32_t *__restrict__ ncontrib,
@@ -382,15 +388,18 @@ __global__ __launch_bounds__(bwd_threads<T>()) void k_render_bwd(
     __shared__ uint32_t s_r[B];
     __shared__ float s_g[NT / 64][9][B];
     __shared__ uint32_t s_nmax;
-    const uint2 rg = ranges[blockIdx.x];
-    render_bwd_unit<T, B, MODE>(blockIdx.x, rg.x, rg.y, true, rg, vals, sp, views, nviews, cams,
-                                tfinal, ncontrib, nullptr, nullptr, tstore, dl, g2d, nrec, s_a, s_b,
-                                s_c, s_r, s_g, &s_nmax);
+    const int gt = (int)order[blockIdx.x];
+    const uint2 rg = ranges[gt];
+    render_bwd_unit<T, B, MODE>(gt, rg.x, rg.y, true, rg, vals, sp, views, nviews, cams, tfinal,
+                                ncontrib, nullptr, nullptr, tstore, dl, g2d, nrec, s_a, s_b, s_c, s_r,
+                                s_g, &s_nmax);
 }
 
-// Checkpoint mode: persistent workgroups over (tile, batch) units.  Unit u of
-// tile t has id floor(start_t / B) + t + u (strictly increasing, below
-// M / B + tiles); a workgroup maps an id back to its tile by binary search.
+// Checkpoint mode: one workgroup per (tile, batch) unit id.  Unit u of tile t
+// has id floor(start_t / B) + t + u (strictly increasing, below M / B + tiles);
+// a workgroup maps its id back to its tile by binary search.  The grid covers
+// the key capacity; ids at or above M / B + tiles (M read on the device) and
+// ids that fall in no tile's units exit at once.
 template <int T, int B>
 __global__ __launch_bounds__(bwd_threads<T>()) void k_render_bwd_ckpt(
     const uint2 *__restrict__ ranges, int total_tiles, const uint32_t *__restrict__ m_dev,
@@ -408,7 +417,7 @@ __global__ __launch_bounds__(bwd_threads<T>()) void k_render_bwd_ckpt(
     __shared__ uint32_t s_nmax;
     const uint32_t m = m_dev ? *m_dev : m_host;
     const uint32_t n_ids = m / B + (uint32_t)total_tiles;
-    for (uint32_t id = blockIdx.x; id < n_ids; id += gridDim.x) {
+    for (uint32_t id = blockIdx.x; id < n_ids; id += gridDim.x) {   // one trip when the grid covers n_ids
         // largest tile t with first id floor(start_t / B) + t <= id
         int lo = 0, hi = total_tiles - 1;
         while (lo < hi) {
@@ -600,18 +609,19 @@ __global__ void k_fill_f32(float *p, int64_t n, float value) {
 template <int T, int B>
 void render_fwd_tb(hipStream_t s, const RenderArgs &a, float *out) {
     constexpr int NT = T * T < 256 ? T * T : 256;
+    const int g = a.total_tiles;
     if (a.t_mode == 1)
-        k_render_fwd<T, B, 1><<<a.total_tiles, NT, 0, s>>>(a.ranges, a.vals, a.sp, a.views, a.nviews,
-                                                          a.cams, out, a.tfinal, a.ncontrib, a.ckpt,
-                                                          a.fstate, nullptr);
+        k_render_fwd<T, B, 1><<<g, NT, 0, s>>>(a.order, a.ranges, a.vals, a.sp, a.views,
+                                              a.nviews, a.cams, out, a.tfinal, a.ncontrib, a.ckpt,
+                                              a.fstate, nullptr);
     else if (a.t_mode == 2)
-        k_render_fwd<T, B, 2><<<a.total_tiles, NT, 0, s>>>(a.ranges, a.vals, a.sp, a.views, a.nviews,
-                                                          a.cams, out, a.tfinal, a.ncontrib, nullptr,
-                                                          nullptr, a.tstore);
+        k_render_fwd<T, B, 2><<<g, NT, 0, s>>>(a.order, a.ranges, a.vals, a.sp, a.views,
+                                              a.nviews, a.cams, out, a.tfinal, a.ncontrib, nullptr,
+                                              nullptr, a.tstore);
     else
-        k_render_fwd<T, B, 0><<<a.total_tiles, NT, 0, s>>>(a.ranges, a.vals, a.sp, a.views, a.nviews,
-                                                          a.cams, out, a.tfinal, a.ncontrib, nullptr,
-                                                          nullptr, nullptr);
+        k_render_fwd<T, B, 0><<<g, NT, 0, s>>>(a.order, a.ranges, a.vals, a.sp, a.views,
+                                              a.nviews, a.cams, out, a.tfinal, a.ncontrib, nullptr,
+                                              nullptr, nullptr);
 }
 
 template <int T, int B>
@@ -623,13 +633,13 @@ void render_bwd_tb(hipStream_t s, const RenderArgs &a, const float *dl, float *g
                                                          a.tfinal, a.ncontrib, a.fstate, a.ckpt, dl,
                                                          g2d, a.nrec);
     else if (a.t_mode == 2)
-        k_render_bwd<T, B, 2><<<a.total_tiles, NT, 0, s>>>(a.ranges, a.vals, a.sp, a.views, a.nviews,
-                                                          a.cams, a.tfinal, a.ncontrib, a.tstore, dl,
-                                                          g2d, a.nrec);
+        k_render_bwd<T, B, 2><<<a.total_tiles, NT, 0, s>>>(a.order, a.ranges, a.vals, a.sp,
+                                                        a.views, a.nviews, a.cams, a.tfinal,
+                                                        a.ncontrib, a.tstore, dl, g2d, a.nrec);
     else
-        k_render_bwd<T, B, 0><<<a.total_tiles, NT, 0, s>>>(a.ranges, a.vals, a.sp, a.views, a.nviews,
-                                                          a.cams, a.tfinal, a.ncontrib, nullptr, dl,
-                                                          g2d, a.nrec);
+        k_render_bwd<T, B, 0><<<a.total_tiles, NT, 0, s>>>(a.order, a.ranges, a.vals, a.sp,
+                                                        a.views, a.nviews, a.cams, a.tfinal,
+                                                        a.ncontrib, nullptr, dl, g2d, a.nrec);
 }
 
 template <int T>

@@ -335,6 +335,145 @@ __global__ __launch_bounds__(256) void k_tile_bounds(const uint32_t *__restrict_
     }
 }
 
+// ---- 3b. compositing order: tiles with more keys first ----------------------------
+
+// Key-count class of a tile: 0 for an empty tile, else 1 + floor(log2(count)).
+__device__ __forceinline__ uint32_t tile_class(const uint2 *__restrict__ ranges, int i) {
+    const uint2 rg = ranges[i];
+    const uint32_t len = rg.y - rg.x;
+    return len ? 32u - (uint32_t)__clz(len) : 0u;
+}
+
+// Lanes of the wave with the same 6-bit class (valid lanes only).
+__device__ __forceinline__ uint64_t class_peers(uint32_t c, bool valid) {
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int k = 0; k < 6; k++) {
+        const uint64_t bal = __ballot((c >> k) & 1u);
+        peers &= ((c >> k) & 1u) ? bal : ~bal;
+    }
+    return peers;
+}
+
+// One workgroup: a counting sort of the tile ids by descending class, each
+// wave aggregating its lanes per class before touching the LDS counters.  The
+// ranges of OU rounds of 1024 tiles are loaded before any is used, so the loop
+// is not a chain of dependent global loads.
+constexpr int kOrderU = 8;
+
+__global__ __launch_bounds__(1024) void k_tile_order(const uint2 *__restrict__ ranges, int total_tiles,
+                                                     uint32_t *__restrict__ order) {
+    __shared__ uint32_t s_cnt[33];
+    const int t = threadIdx.x;
+    if (t < 33) s_cnt[t] = 0u;
+    __syncthreads();
+    for (int base = 0; base < total_tiles; base += 1024 * kOrderU) {   // uniform trip count
+        uint32_t c[kOrderU];
+#pragma unroll
+        for (int u = 0; u < kOrderU; u++) {
+            const int i = base + u * 1024 + t;
+            c[u] = i < total_tiles ? tile_class(ranges, i) : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < kOrderU; u++) {
+            const bool valid = base + u * 1024 + t < total_tiles;
+            const uint64_t peers = class_peers(c[u], valid);
+            if (valid && lanes_below(peers) == 0u) atomicAdd(&s_cnt[c[u]], (uint32_t)__popcll(peers));
+        }
+    }
+    __syncthreads();
+    if (t == 0) {   // class 32 first
+        uint32_t run = 0;
+        for (int k = 32; k >= 0; k--) {
+            const uint32_t n = s_cnt[k];
+            s_cnt[k] = run;
+            run += n;
+        }
+    }
+    __syncthreads();
+    for (int base = 0; base < total_tiles; base += 1024 * kOrderU) {
+        uint32_t c[kOrderU];
+#pragma unroll
+        for (int u = 0; u < kOrderU; u++) {
+            const int i = base + u * 1024 + t;
+            c[u] = i < total_tiles ? tile_class(ranges, i) : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < kOrderU; u++) {
+            const int i = base + u * 1024 + t;
+            const bool valid = i < total_tiles;
+            const uint64_t peers = class_peers(c[u], valid);
+            const uint32_t below = lanes_below(peers);
+            uint32_t start = 0u;
+            if (valid && below == 0u) start = atomicAdd(&s_cnt[c[u]], (uint32_t)__popcll(peers));
+            const int leader = peers ? __builtin_ctzll(peers) : __lane_id();
+            start = __shfl(start, leader, 64);
+            if (valid) order[start + below] = (uint32_t)i;
+        }
+    }
+}
+
+// Many tiles: the same counting sort over kOrderTiles tiles per workgroup.
+// k_order_count writes each workgroup's class counts; k_order_place turns them
+// into the workgroup's first slot per class (classes descending, workgroups in
+// order) and places its tiles.
+constexpr int kOrderTiles = 4096;
+
+__device__ __forceinline__ void order_walk(const uint2 *__restrict__ ranges, int total_tiles,
+                                           uint32_t *s_cnt, uint32_t *__restrict__ order) {
+    const int t0 = blockIdx.x * kOrderTiles;
+    const int t1 = min(total_tiles, t0 + kOrderTiles);
+    for (int base = t0; base < t1; base += 256) {   // workgroup-uniform trip count
+        const int i = base + (int)threadIdx.x;
+        const bool valid = i < t1;
+        const uint32_t c = valid ? tile_class(ranges, i) : 0u;
+        const uint64_t peers = class_peers(c, valid);
+        const uint32_t below = lanes_below(peers);
+        uint32_t start = 0u;
+        if (valid && below == 0u) start = atomicAdd(&s_cnt[c], (uint32_t)__popcll(peers));
+        if (order) {
+            const int leader = peers ? __builtin_ctzll(peers) : __lane_id();
+            start = __shfl(start, leader, 64);
+            if (valid) order[start + below] = (uint32_t)i;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_order_count(const uint2 *__restrict__ ranges, int total_tiles,
+                                                     uint32_t *__restrict__ counts) {
+    __shared__ uint32_t s_cnt[33];
+    if (threadIdx.x < 33) s_cnt[threadIdx.x] = 0u;
+    __syncthreads();
+    order_walk(ranges, total_tiles, s_cnt, nullptr);
+    __syncthreads();
+    if (threadIdx.x < 33) counts[(size_t)blockIdx.x * 33 + threadIdx.x] = s_cnt[threadIdx.x];
+}
+
+__global__ __launch_bounds__(256) void k_order_place(const uint2 *__restrict__ ranges, int total_tiles,
+                                                     const uint32_t *__restrict__ counts, int groups,
+                                                     uint32_t *__restrict__ order) {
+    __shared__ uint32_t s_tot[33], s_cnt[33];
+    const int c = threadIdx.x;
+    if (c < 33) {
+        uint32_t tot = 0, before = 0;
+        for (int w = 0; w < groups; w++) {
+            const uint32_t n = counts[(size_t)w * 33 + c];
+            tot += n;
+            if (w < (int)blockIdx.x) before += n;
+        }
+        s_tot[c] = tot;
+        s_cnt[c] = before;
+    }
+    __syncthreads();
+    if (c < 33) {
+        uint32_t above = 0;
+        for (int k = c + 1; k <= 32; k++) above += s_tot[k];
+        s_cnt[c] += above;
+    }
+    __syncthreads();
+    order_walk(ranges, total_tiles, s_cnt, order);
+}
+
 // ---- 4. per-tile sort by depth ----------------------------------------------------
 
 struct SortShared {
@@ -496,6 +635,19 @@ void launch_tile_bounds(hipStream_t s, const uint32_t *keys, const uint32_t *m_d
     if (g > 2048) g = 2048;
     if (g < 1) g = 1;
     k_tile_bounds<<<(int)g, 256, 0, s>>>(keys, m_dev, m_host, total_tiles, ranges);
+}
+
+int order_groups(int64_t total_tiles) { return (int)((total_tiles + kOrderTiles - 1) / kOrderTiles); }
+
+void launch_tile_order(hipStream_t s, const uint2 *ranges, int total_tiles, uint32_t *order,
+                       uint32_t *counts) {
+    if (total_tiles <= 4 * kOrderTiles) {
+        k_tile_order<<<1, 1024, 0, s>>>(ranges, total_tiles, order);
+        return;
+    }
+    const int g = order_groups(total_tiles);
+    k_order_count<<<g, 256, 0, s>>>(ranges, total_tiles, counts);
+    k_order_place<<<g, 256, 0, s>>>(ranges, total_tiles, counts, g, order);
 }
 
 void launch_tile_sort(hipStream_t s, const uint2 *ranges, int total_tiles, const uint32_t *depth_key,

@@ -67,7 +67,8 @@ def test_phantom_workload(ctx, t_mode):
     import bench
     wl = bench.build_workload("phantom")
     log(f"[full] phantom: {wl.P.shape[1]} Gaussians, 1024x1024, t_mode {t_mode}")
-    _sampled_parity(ctx, wl.P, wl.cams, t_mode, per_view=512, seed=11)
+    sc = _sampled_parity(ctx, wl.P, wl.cams, t_mode, per_view=512, seed=11)
+    _check_order(sc)
 
 
 def test_batched_uneven_workload(ctx):
@@ -76,12 +77,25 @@ def test_batched_uneven_workload(ctx):
     log(f"[full] batched: {wl.P.shape[1]} SH3 Gaussians, views "
         f"{[(c.width, c.height) for c in wl.cams]}")
     sc = _sampled_parity(ctx, wl.P, wl.cams, 1, per_view=64, seed=12)
-    ranges = sc.debug(_abi.GSF_DBG_RANGES, np.uint32, 2 * sc.plan.total_tiles).reshape(-1, 2)
-    assert (np.diff(ranges[:, 0].astype(np.int64)) >= 0).all()
+    _check_order(sc)
+
+
+def _check_order(sc):
+    """The compositing order is a permutation of the tiles, heavier key-count
+    classes (floor(log2(count)), empty last) before lighter ones."""
+    T = sc.plan.total_tiles
+    ranges = sc.debug(_abi.GSF_DBG_RANGES, np.uint32, 2 * T).reshape(-1, 2).astype(np.int64)
+    assert (np.diff(ranges[:, 0]) >= 0).all()
+    order = sc.debug(_abi.GSF_DBG_ORDER, np.uint32, T).astype(np.int64)
+    np.testing.assert_array_equal(np.sort(order), np.arange(T))
+    n = ranges[:, 1] - ranges[:, 0]
+    cls = np.where(n > 0, np.floor(np.log2(np.maximum(n, 1))).astype(np.int64) + 1, 0)
+    assert (np.diff(cls[order]) <= 0).all()
 
 
 def test_stereo_workload(ctx):
     import bench
     wl = bench.build_workload("stereo")
     log(f"[full] stereo: {wl.P.shape[1]} SH3 Gaussians, two eyes 2064x2208")
-    _sampled_parity(ctx, wl.P, wl.cams, 1, per_view=96, seed=13)
+    sc = _sampled_parity(ctx, wl.P, wl.cams, 1, per_view=96, seed=13)
+    _check_order(sc)
