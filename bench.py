@@ -281,6 +281,8 @@ def main():
     ap.add_argument("--compare-t-modes", action="store_true",
                     help="also time the captured step and record peak device memory with each "
                          "transmittance mode (always on for --workload stereo)")
+    ap.add_argument("--no-fovea-cull", action="store_true",
+                    help="composite full frames even when the loss is masked to a fovea")
     ap.add_argument("--regen-steps", type=int, default=300,
                     help="steps of one regeneration (foveal workload)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -318,7 +320,9 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.Stream(dev)
-    cfg = gs.FitConfig(lr=1e-3, tile=args.tile, lds_batch=args.lds_batch, t_mode=args.t_mode)
+    # a masked loss lets the fused step composite only the tiles that meet each fovea
+    cfg = gs.FitConfig(lr=1e-3, tile=args.tile, lds_batch=args.lds_batch, t_mode=args.t_mode,
+                       fovea_cull=wl.gaze is not None and not args.no_fovea_cull)
     with torch.cuda.stream(stream):
         ctx = gs.Context(0)
         if wl.targets is None:
@@ -409,7 +413,7 @@ def main():
         pairs = {k: int(round(v)) for k, v in pairs.items()}
         log(f"[bench] pairs per step (mean of the K steps): {pairs}")
 
-        # plain path: one host-synchronised plan per view, eager
+        # plain path: one host-synchronised plan per view, eager, full frames
         ms_plain = None
         if not args.no_plain:
             plain = fit(cfg, fused=False)
@@ -492,6 +496,7 @@ def main():
                    "sizes": [[c.width, c.height] for c in cams], "pixels": npix,
                    "sh_degree": int(round(((planes - 11) // 3) ** 0.5)) - 1,
                    "tile": cfg.tile, "lds_batch": cfg.lds_batch, "t_mode": cfg.t_mode,
+                   "fovea_cull": bool(cfg.fovea_cull),
                    "keys_per_step": M, "form": "fused, hipGraph-captured"},
         "mpix_per_s": round(npix * steps_per_s / 1e6, 1),
         "ms_per_100_step_fit": round(100 * ms_fused, 2),

@@ -186,6 +186,12 @@ typedef struct gsf_step_args {
     int32_t *step_dev;          /* [1] */
     const float *seg_lr;        /* (host) [11 + 3K]: learning rate per parameter plane */
     float beta1, beta2, eps;
+    int32_t fovea_cull;         /* 1: with gaze_px, composite and back-propagate only the
+                                   tiles that meet each view's fovea box (the pixels whose
+                                   centre can lie within the mask radius, plus one pixel);
+                                   loss and gradients are those of the full frame (other
+                                   pixels carry no loss); rgba and dl_drgba outside those
+                                   tiles are left as they were.  0: full frames. */
 } gsf_step_args;
 
 /* Enqueue one step eagerly. */

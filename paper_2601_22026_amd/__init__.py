@@ -244,6 +244,7 @@ class FitConfig:
     radius_frac: float = 0.2
     key_capacity: int = 0
     t_mode: int = 1          # adjoint transmittance of the fused step: 0 recomputed, 1 checkpointed, 2 stored
+    fovea_cull: bool = False  # fused step with a gaze: composite only the tiles that meet the fovea
 
 
 class FitStep:
@@ -315,7 +316,8 @@ class FitStep:
             rgba=rgba.data_ptr(), dl_drgba=dl.data_ptr(), grads=self.grads.data_ptr(),
             adam_m=self.m.data_ptr(), adam_v=self.v.data_ptr(), step_dev=self.step_dev.data_ptr(),
             seg_lr=ct.cast(self._seg_lr, ct.POINTER(ct.c_float)), beta1=self.cfg.betas[0],
-            beta2=self.cfg.betas[1], eps=self.cfg.eps)
+            beta2=self.cfg.betas[1], eps=self.cfg.eps,
+            fovea_cull=int(bool(self.cfg.fovea_cull and gaze is not None)))
 
     def step(self):
         """One eager step."""

@@ -57,7 +57,7 @@ class gsf_step_args(ct.Structure):
                 ("dl_drgba", ct.c_void_p), ("grads", ct.c_void_p), ("adam_m", ct.c_void_p),
                 ("adam_v", ct.c_void_p), ("step_dev", ct.c_void_p),
                 ("seg_lr", ct.POINTER(ct.c_float)), ("beta1", ct.c_float), ("beta2", ct.c_float),
-                ("eps", ct.c_float)]
+                ("eps", ct.c_float), ("fovea_cull", ct.c_int32)]
 
 
 assert ct.sizeof(gsf_camera) == 128

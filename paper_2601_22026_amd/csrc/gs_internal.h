@@ -58,16 +58,39 @@ struct SegTable {
     int32_t n;
 };
 
+// Tiles [tx0, tx1] x [ty0, ty1] of a view that meet its fovea: the pixels whose
+// centre can lie within radius_frac * width of the gaze point, with one pixel of
+// slack (the mask test itself is done per pixel by the loss).  Empty when
+// tx0 > tx1.
+struct FoveaTiles {
+    int tx0, tx1, ty0, ty1;
+};
+
+__device__ __forceinline__ FoveaTiles fovea_tiles(const float *__restrict__ gaze, int v,
+                                                  float radius_frac, int width, int height, int tile) {
+    const float r = radius_frac * (float)width;
+    const float gx = gaze[2 * v], gy = gaze[2 * v + 1];
+    const float x0 = fmaxf(floorf(gx - r - 0.5f) - 1.f, 0.f);
+    const float x1 = fminf(ceilf(gx + r - 0.5f) + 1.f, (float)(width - 1));
+    const float y0 = fmaxf(floorf(gy - r - 0.5f) - 1.f, 0.f);
+    const float y1 = fminf(ceilf(gy + r - 0.5f) + 1.f, (float)(height - 1));
+    FoveaTiles f{1, 0, 1, 0};
+    if (x0 <= x1 && y0 <= y1) f = FoveaTiles{(int)x0 / tile, (int)x1 / tile, (int)y0 / tile, (int)y1 / tile};
+    return f;
+}
+
 // ---- launchers (all asynchronous on `s`) -----------------------------------------
 
 // Projection of n Gaussians into V views: records r = v*n + i.  Writes the
 // splat, the depth key (float32 bits of the camera depth, 0xFFFFFFFF when
 // culled), the touched tile rectangle and its tile count, and clears the
 // record's nine screen-space gradient entries g2d[f * V*n + r] when g2d is
-// non-null.
+// non-null.  With cull_gaze (nullable) the rectangle is clipped to the view's
+// fovea tiles (fovea_tiles with cull_radius).
 void launch_project_fwd(hipStream_t s, const float *P, int n, int nviews, int deg,
                         const gsf_camera *cams, const ViewDesc *views, int tile, SplatPtrs sp,
-                        uint32_t *depth_key, uint2 *rect, uint32_t *count, float *g2d);
+                        uint32_t *depth_key, uint2 *rect, uint32_t *count, float *g2d,
+                        const float *cull_gaze, float cull_radius);
 
 // Parameter gradient from the per-record screen-space gradient g2d [9][V*n].
 void launch_project_bwd(hipStream_t s, const float *P, int n, int nviews, int deg,
@@ -115,6 +138,8 @@ struct RenderArgs {
     int t_mode = 0;                       // 0 recompute, 1 checkpointed, 2 stored transmittance
     int bwd_grid = 1;                     // workgroups of the checkpointed adjoint (unit ids)
     const uint32_t *order = nullptr;      // tile ids, heavy tiles first
+    const float *cull_gaze = nullptr;     // fovea culling: only tiles meeting the fovea are composited
+    float cull_radius = 0.f;
     const uint2 *ranges = nullptr;
     const uint32_t *vals = nullptr;
     SplatPtrs sp{};
@@ -143,10 +168,13 @@ void launch_count_pairs(hipStream_t s, int tile, int total_tiles, const uint2 *r
 // Masked L1 loss.  partial: scratch of loss_partials(total_pix) floats.
 int loss_partials(int64_t total_pix);
 // step_inc (nullable): step counter the final reduction advances by one.
+// box > 0 (fovea culling, gaze required): only the box x box pixel window of each
+// view starting at its first fovea tile is visited (every pixel of the tiles
+// that meet the fovea; nviews * box^2 <= total_pix); dl elsewhere is not written.
 void launch_loss_l1(hipStream_t s, const float *rgba, const float *target, const float *gaze,
                     float radius_frac, const ViewDesc *views, int nviews, int64_t total_pix,
                     float *dl, float *partial, uint32_t *mask_count, float *loss, uint32_t *flags,
-                    int32_t *step_inc);
+                    int32_t *step_inc, int box, int tile);
 
 // Adam with bias correction for step step[0]; when advance is true a one-thread
 // kernel first advances step[0] by one.

@@ -17,6 +17,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <cmath>
 #include <vector>
 
 #include "gs_internal.h"
@@ -247,8 +248,10 @@ struct StageTimer {
     }
 };
 
+// cull_gaze (nullable): fovea culling with radius fraction cull_radius.
 gsf_status enqueue_forward(gsf_plan *p, const float *params, int64_t n, const gsf_camera *cams,
-                           float *out_rgba, bool *overflow) {
+                           float *out_rgba, bool *overflow, const float *cull_gaze = nullptr,
+                           float cull_radius = 0.f) {
     gsf_ctx *ctx = p->ctx;
     hipStream_t s = ctx->stream;
     Buffers &b = p->b;
@@ -261,7 +264,7 @@ gsf_status enqueue_forward(gsf_plan *p, const float *params, int64_t n, const gs
     {   // splats, support boxes, depth keys; clears the screen gradient
         StageTimer t(p, GSF_STAGE_PROJECT);
         launch_project_fwd(s, params, (int)n, p->V, p->deg, cams, b.views, p->tile, splats(p),
-                           b.depth_key, b.rect, b.count, b.g2d);
+                           b.depth_key, b.rect, b.count, b.g2d, cull_gaze, cull_radius);
     }
     p->g2d_clean = true;
     GSF_LAUNCHED(ctx);
@@ -299,7 +302,10 @@ gsf_status enqueue_forward(gsf_plan *p, const float *params, int64_t n, const gs
     GSF_LAUNCHED(ctx);
     {
         StageTimer t(p, GSF_STAGE_RENDER);
-        launch_render_fwd(s, render_args(p, cams, n), out_rgba);
+        RenderArgs ra = render_args(p, cams, n);
+        ra.cull_gaze = cull_gaze;
+        ra.cull_radius = cull_radius;
+        launch_render_fwd(s, ra, out_rgba);
     }
     GSF_LAUNCHED(ctx);
     p->have_forward = true;
@@ -307,12 +313,24 @@ gsf_status enqueue_forward(gsf_plan *p, const float *params, int64_t n, const gs
     return GSF_OK;
 }
 
+// cull: visit only the pixels of the tiles that meet each view's fovea (gaze
+// required) - a window of box x box pixels per view, when that is smaller.
 gsf_status enqueue_loss(gsf_plan *p, const float *rgba, const float *target, const float *gaze,
-                        float radius_frac, float *loss, float *dl, int32_t *step_inc) {
+                        float radius_frac, float *loss, float *dl, int32_t *step_inc,
+                        bool cull = false) {
+    int box = 0;
+    if (cull && gaze) {
+        int wmax = 1;
+        for (const ViewDesc &vd : p->views) wmax = std::max(wmax, (int)vd.width);
+        const double r = (double)radius_frac * wmax;
+        const int64_t tiles = (int64_t)std::ceil((2.0 * r + 4.0) / p->tile) + 1;
+        const int64_t side = tiles * p->tile;
+        if (side > 0 && (int64_t)p->V * side * side <= p->total_pix) box = (int)side;
+    }
     StageTimer t(p, GSF_STAGE_LOSS);
     launch_loss_l1(p->ctx->stream, rgba, target, gaze, radius_frac, p->b.views, p->V,
                    p->total_pix, dl, p->b.loss_partial, p->b.mask_count, loss, p->b.flags,
-                   step_inc);
+                   step_inc, box, p->tile);
     GSF_LAUNCHED(p->ctx);
     return GSF_OK;
 }
@@ -366,16 +384,24 @@ gsf_status check_step(gsf_plan *p, const gsf_step_args *a) {
     if (a->n < 1 || a->n > p->n_max) return fail(p->ctx, GSF_E_INVALID, "gsf_step: n out of range");
     if (!aligned16(a->params) || !aligned16(a->grads) || !aligned16(a->adam_m) || !aligned16(a->adam_v))
         return fail(p->ctx, GSF_E_INVALID, "gsf_step: parameter buffers must be 16-byte aligned");
+    if (a->fovea_cull != 0 && a->fovea_cull != 1)
+        return fail(p->ctx, GSF_E_INVALID, "gsf_step: fovea_cull must be 0 or 1");
+    if (a->fovea_cull && !a->gaze_px)
+        return fail(p->ctx, GSF_E_INVALID, "gsf_step: fovea_cull needs gaze_px");
+    if (a->fovea_cull && !(a->mask_radius_frac >= 0.f && a->mask_radius_frac <= 4.f))
+        return fail(p->ctx, GSF_E_INVALID, "gsf_step: mask_radius_frac must lie in [0, 4]");
     return GSF_OK;
 }
 
 gsf_status enqueue_step(gsf_plan *p, const gsf_step_args *a) {
     bool overflow = false;
-    gsf_status st = enqueue_forward(p, a->params, a->n, a->cams, a->rgba, &overflow);
+    const bool cull = a->fovea_cull != 0;
+    gsf_status st = enqueue_forward(p, a->params, a->n, a->cams, a->rgba, &overflow,
+                                    cull ? a->gaze_px : nullptr, a->mask_radius_frac);
     if (st != GSF_OK) return st;
     // the loss reduction also advances the Adam step counter of this step
     st = enqueue_loss(p, a->rgba, a->target_rgb, a->gaze_px, a->mask_radius_frac, a->loss,
-                      a->dl_drgba, a->step_dev);
+                      a->dl_drgba, a->step_dev, cull);
     if (st != GSF_OK) return st;
     st = enqueue_backward(p, a->params, a->n, a->cams, a->dl_drgba, a->grads);
     if (st != GSF_OK) return st;

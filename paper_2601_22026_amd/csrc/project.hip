@@ -229,7 +229,9 @@ __global__ __launch_bounds__(256) void k_project_fwd(const float *__restrict__ P
                                                      SplatPtrs sp, uint32_t *__restrict__ depth_key,
                                                      uint2 *__restrict__ rect,
                                                      uint32_t *__restrict__ count,
-                                                     float *__restrict__ g2d) {
+                                                     float *__restrict__ g2d,
+                                                     const float *__restrict__ cull_gaze,
+                                                     float cull_radius) {
     constexpr int K = (DEG + 1) * (DEG + 1);
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= nrec) return;
@@ -294,8 +296,20 @@ __global__ __launch_bounds__(256) void k_project_fwd(const float *__restrict__ P
         count[r] = 0u;
         return;
     }
-    const uint32_t tx0 = (uint32_t)x0 / tile, tx1 = (uint32_t)x1 / tile;
-    const uint32_t ty0 = (uint32_t)y0 / tile, ty1 = (uint32_t)y1 / tile;
+    uint32_t tx0 = (uint32_t)x0 / tile, tx1 = (uint32_t)x1 / tile;
+    uint32_t ty0 = (uint32_t)y0 / tile, ty1 = (uint32_t)y1 / tile;
+    if (cull_gaze) {   // only the tiles that meet the fovea are composited
+        const FoveaTiles f = fovea_tiles(cull_gaze, v, cull_radius, vd.width, vd.height, tile);
+        if (f.tx0 > f.tx1 || (int)tx1 < f.tx0 || (int)tx0 > f.tx1 || (int)ty1 < f.ty0 || (int)ty0 > f.ty1) {
+            rect[r] = make_uint2(0u, 0u);
+            count[r] = 0u;
+            return;
+        }
+        tx0 = max(tx0, (uint32_t)f.tx0);
+        tx1 = min(tx1, (uint32_t)f.tx1);
+        ty0 = max(ty0, (uint32_t)f.ty0);
+        ty1 = min(ty1, (uint32_t)f.ty1);
+    }
     rect[r] = make_uint2(tx0 | (ty0 << 16), tx1 | (ty1 << 16));
     count[r] = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
 }
@@ -469,14 +483,14 @@ __global__ __launch_bounds__(128) void k_project_bwd(const float *__restrict__ P
 void launch_project_fwd(hipStream_t s, const float *P, int n, int nviews, int deg,
                         const gsf_camera *cams, const ViewDesc *views, int tile, SplatPtrs sp,
                         uint32_t *depth_key, uint2 *rect, uint32_t *count,
-                        float *g2d) {
+                        float *g2d, const float *cull_gaze, float cull_radius) {
     const int nrec = n * nviews;
     const dim3 grid((nrec + 255) / 256), block(256);
     switch (deg) {
-    case 0: k_project_fwd<0><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rect, count, g2d); break;
-    case 1: k_project_fwd<1><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rect, count, g2d); break;
-    case 2: k_project_fwd<2><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rect, count, g2d); break;
-    default: k_project_fwd<3><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rect, count, g2d); break;
+    case 0: k_project_fwd<0><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rect, count, g2d, cull_gaze, cull_radius); break;
+    case 1: k_project_fwd<1><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rect, count, g2d, cull_gaze, cull_radius); break;
+    case 2: k_project_fwd<2><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rect, count, g2d, cull_gaze, cull_radius); break;
+    default: k_project_fwd<3><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rect, count, g2d, cull_gaze, cull_radius); break;
     }
 }
 

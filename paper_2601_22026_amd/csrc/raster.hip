@@ -101,7 +101,8 @@ __global__ __launch_bounds__(T * T < 256 ? T * T : 256) void k_render_fwd(
     const uint2 *__restrict__ ranges, const uint32_t *__restrict__ vals, SplatPtrs sp,
     const ViewDesc *__restrict__ views, int nviews, const gsf_camera *__restrict__ cams,
     float *__restrict__ out_rgba, float *__restrict__ tfinal, uint32_t *__restrict__ ncontrib,
-    float4 *__restrict__ ckpt, float4 *__restrict__ fstate, float *__restrict__ tstore) {
+    float4 *__restrict__ ckpt, float4 *__restrict__ fstate, float *__restrict__ tstore,
+    const float *__restrict__ cull_gaze, float cull_radius) {
     constexpr bool CKPT = MODE == 1;
     constexpr int NT = T * T < 256 ? T * T : 256;
     constexpr int PPT = T * T / NT;
@@ -116,6 +117,10 @@ __global__ __launch_bounds__(T * T < 256 ? T * T : 256) void k_render_fwd(
     const ViewDesc vd = views[v];
     const int local = gt - vd.tile_off;
     const int ty = local / vd.tiles_x, tx = local - ty * vd.tiles_x;
+    if (cull_gaze) {   // fovea culling: tiles away from the fovea are not composited
+        const FoveaTiles f = fovea_tiles(cull_gaze, v, cull_radius, vd.width, vd.height, T);
+        if (tx < f.tx0 || tx > f.tx1 || ty < f.ty0 || ty > f.ty1) return;
+    }
     const uint2 rg = ranges[gt];
     const int lx = threadIdx.x % T, ly = threadIdx.x / T;
 
@@ -503,20 +508,48 @@ __device__ __forceinline__ bool in_fovea(const float *__restrict__ gaze, int v, 
     return dx * dx + dy * dy <= radius * radius;
 }
 
+// Pixel p of a loss launch: every pixel of every view (box == 0), or pixel p of
+// view p / box^2's box x box window that starts at its first fovea tile
+// (fovea culling; false for window pixels outside the view or past its last
+// fovea tile).
+__device__ __forceinline__ bool loss_pixel(int64_t p, int64_t total_pix, int box, int tile,
+                                           const float *__restrict__ gaze, float radius_frac,
+                                           const ViewDesc *__restrict__ views, int nviews, int &v,
+                                           int &x, int &y) {
+    if (box == 0) {
+        if (p >= total_pix) return false;
+        v = view_of_pixel(views, nviews, p);
+        const ViewDesc vd = views[v];
+        const int q = (int)(p - vd.pix_off);
+        y = q / vd.width;
+        x = q - y * vd.width;
+        return true;
+    }
+    const int64_t area = (int64_t)box * box;
+    v = (int)(p / area);
+    if (v >= nviews) return false;
+    const int l = (int)(p - (int64_t)v * area);
+    const ViewDesc vd = views[v];
+    const FoveaTiles f = fovea_tiles(gaze, v, radius_frac, vd.width, vd.height, tile);
+    if (f.tx0 > f.tx1) return false;
+    x = f.tx0 * tile + l % box;
+    y = f.ty0 * tile + l / box;
+    return x < vd.width && y < vd.height && x < (f.tx1 + 1) * tile && y < (f.ty1 + 1) * tile;
+}
+
 __global__ __launch_bounds__(kLossBlock) void k_loss_count(const float *__restrict__ gaze,
                                                            float radius_frac,
                                                            const ViewDesc *__restrict__ views,
-                                                           int nviews, int64_t total_pix,
+                                                           int nviews, int64_t total_pix, int box,
+                                                           int tile,
                                                            uint32_t *__restrict__ mask_count) {
     __shared__ uint32_t s_cnt;
     if (threadIdx.x == 0) s_cnt = 0u;
     __syncthreads();
     const int64_t p = (int64_t)blockIdx.x * kLossBlock + threadIdx.x;
-    if (p < total_pix) {
-        const int v = view_of_pixel(views, nviews, p);
+    int v, x, y;
+    if (loss_pixel(p, total_pix, box, tile, gaze, radius_frac, views, nviews, v, x, y)) {
         const ViewDesc vd = views[v];
-        const int q = (int)(p - vd.pix_off);
-        const int y = q / vd.width, x = q - y * vd.width;
         if (in_fovea(gaze, v, x, y, radius_frac * (float)vd.width)) atomicAdd(&s_cnt, 3u);
     }
     __syncthreads();
@@ -530,18 +563,17 @@ __global__ __launch_bounds__(kLossBlock) void k_loss_count(const float *__restri
 // one-workgroup kernel is cheaper.)
 __global__ __launch_bounds__(kLossBlock) void k_loss_l1(
     const float *__restrict__ rgba, const float *__restrict__ target, const float *__restrict__ gaze,
-    float radius_frac, const ViewDesc *__restrict__ views, int nviews, int64_t total_pix,
-    const uint32_t *__restrict__ mask_count, uint32_t count_host, float *__restrict__ dl,
+    float radius_frac, const ViewDesc *__restrict__ views, int nviews, int64_t total_pix, int box,
+    int tile, const uint32_t *__restrict__ mask_count, uint32_t count_host, float *__restrict__ dl,
     float *__restrict__ partial) {
     __shared__ float s_red[kLossBlock];
     const uint32_t cnt = mask_count ? *mask_count : count_host;
     const int64_t p = (int64_t)blockIdx.x * kLossBlock + threadIdx.x;
     float s = 0.f;
-    if (p < total_pix) {
-        const int v = view_of_pixel(views, nviews, p);
+    int v, x, y;
+    if (loss_pixel(p, total_pix, box, tile, gaze, radius_frac, views, nviews, v, x, y)) {
         const ViewDesc vd = views[v];
-        const int q = (int)(p - vd.pix_off);
-        const int y = q / vd.width, x = q - y * vd.width;
+        const int q = y * vd.width + x;
         const size_t plane = (size_t)vd.width * vd.height;
         const float *img = rgba + 4 * (size_t)vd.pix_off;
         const float *tgt = target + 3 * (size_t)vd.pix_off;
@@ -613,15 +645,15 @@ void render_fwd_tb(hipStream_t s, const RenderArgs &a, float *out) {
     if (a.t_mode == 1)
         k_render_fwd<T, B, 1><<<g, NT, 0, s>>>(a.order, a.ranges, a.vals, a.sp, a.views,
                                               a.nviews, a.cams, out, a.tfinal, a.ncontrib, a.ckpt,
-                                              a.fstate, nullptr);
+                                              a.fstate, nullptr, a.cull_gaze, a.cull_radius);
     else if (a.t_mode == 2)
         k_render_fwd<T, B, 2><<<g, NT, 0, s>>>(a.order, a.ranges, a.vals, a.sp, a.views,
                                               a.nviews, a.cams, out, a.tfinal, a.ncontrib, nullptr,
-                                              nullptr, a.tstore);
+                                              nullptr, a.tstore, a.cull_gaze, a.cull_radius);
     else
         k_render_fwd<T, B, 0><<<g, NT, 0, s>>>(a.order, a.ranges, a.vals, a.sp, a.views,
                                               a.nviews, a.cams, out, a.tfinal, a.ncontrib, nullptr,
-                                              nullptr, nullptr);
+                                              nullptr, nullptr, a.cull_gaze, a.cull_radius);
 }
 
 template <int T, int B>
@@ -687,16 +719,18 @@ int loss_partials(int64_t total_pix) { return (int)((total_pix + kLossBlock - 1)
 void launch_loss_l1(hipStream_t s, const float *rgba, const float *target, const float *gaze,
                     float radius_frac, const ViewDesc *views, int nviews, int64_t total_pix,
                     float *dl, float *partial, uint32_t *mask_count, float *loss, uint32_t *flags,
-                    int32_t *step_inc) {
-    const int nb = loss_partials(total_pix);
+                    int32_t *step_inc, int box, int tile) {
+    if (!gaze) box = 0;
+    const int nb = loss_partials(box ? (int64_t)nviews * box * box : total_pix);
     if (gaze) {
         k_fill_u32<<<1, 64, 0, s>>>(mask_count, 1, 0u);
-        k_loss_count<<<nb, kLossBlock, 0, s>>>(gaze, radius_frac, views, nviews, total_pix, mask_count);
+        k_loss_count<<<nb, kLossBlock, 0, s>>>(gaze, radius_frac, views, nviews, total_pix, box, tile,
+                                               mask_count);
     }
     const uint32_t *mc = gaze ? mask_count : nullptr;
     const uint32_t cnt = (uint32_t)(3 * total_pix);
-    k_loss_l1<<<nb, kLossBlock, 0, s>>>(rgba, target, gaze, radius_frac, views, nviews, total_pix, mc,
-                                        cnt, dl, partial);
+    k_loss_l1<<<nb, kLossBlock, 0, s>>>(rgba, target, gaze, radius_frac, views, nviews, total_pix, box,
+                                        tile, mc, cnt, dl, partial);
     k_loss_final<<<1, 1024, 0, s>>>(partial, nb, mc, cnt, loss, flags, step_inc);
 }
 

@@ -46,6 +46,36 @@ def test_struct_layouts():
     assert ct.sizeof(_abi.gsf_plan_desc) == 56
 
 
+def test_struct_layouts_match_the_c_header(tmp_path):
+    """sizeof / offsetof of every ABI struct field, as a C compiler lays out
+    include/gsfit.h, equal the ctypes mirrors of the binding."""
+    import shutil
+    import subprocess
+    from paper_2601_22026_amd import _abi
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"gsf_camera": _abi.gsf_camera, "gsf_plan_desc": _abi.gsf_plan_desc,
+               "gsf_step_args": _abi.gsf_step_args}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "gsfit.h"', 'int main(void) {']
+    for name, cls in structs.items():
+        lines.append(f'printf("{name} size %zu\\n", sizeof({name}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'printf("{name} {fname} %zu\\n", offsetof({name}, {fname}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for name, cls in structs.items():
+        assert got[(name, "size")] == ct.sizeof(cls), name
+        for fname, _ in cls._fields_:
+            assert got[(name, fname)] == getattr(cls, fname).offset, (name, fname)
+
+
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     from paper_2601_22026_amd import _abi
     monkeypatch.setattr(_abi, "LIB_PATH", str(tmp_path / "absent.so"))

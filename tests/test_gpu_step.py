@@ -260,3 +260,49 @@ def test_autotune_sweeps_and_candidates_render_identically(gs, ctx):
         fs.plan.close()
     for img in imgs[1:]:
         np.testing.assert_array_equal(imgs[0].view(np.uint32), img.view(np.uint32))
+
+
+def test_fovea_culling_matches_full_frame(gs, ctx):
+    """Fovea culling composites only the tiles that meet each view's fovea:
+    in-mask pixels keep their bits, the masked loss and the gradient equal the
+    full-frame step's, with fewer keys; the loss also equals the oracle's on
+    the same image."""
+    P = synth.random_gaussians(3000, seed=21)
+    cams = [synth.look_at_camera([0.3, -0.2, -3.0], width=224, height=160),
+            synth.look_at_camera([2.5, 1.0, 1.0], width=160, height=208)]
+    gaze = synth.gaze_points(cams, seed=6)
+    rng = np.random.default_rng(5)
+    tgt = np.concatenate([rng.uniform(0, 1, size=3 * c.npix) for c in cams]).astype(np.float32)
+    tgt_dev = torch.from_numpy(tgt).to(DEV)
+    gz = torch.from_numpy(np.ascontiguousarray(gaze)).to(DEV)
+    runs = {}
+    for cull in (False, True):
+        cfg = gs.FitConfig(lr=0.0, tile=16, lds_batch=64, fovea_cull=cull)
+        fs = gs.FitStep(ctx, torch.from_numpy(P).to(DEV), cams, tgt_dev, gz, cfg=cfg, fused=True)
+        fs.step()
+        torch.cuda.synchronize()
+        runs[cull] = (fs.loss.item(), fs.rgba.cpu().numpy(), fs.grads.cpu().numpy(), fs.poll()[1])
+        fs.plan.close()
+    (l0, img0, g0, m0), (l1, img1, g1, m1) = runs[False], runs[True]
+    log(f"[cull] loss {l0:.7f} vs {l1:.7f}, keys {m0} -> {m1}")
+    assert m1 < m0
+    assert abs(l1 - l0) <= 1e-6 * abs(l0)
+    off = 0
+    imgs = []
+    for v, c in enumerate(cams):
+        a = img0[4 * off:4 * (off + c.npix)].reshape(4, c.npix)
+        b = img1[4 * off:4 * (off + c.npix)].reshape(4, c.npix)
+        ys, xs = np.divmod(np.arange(c.npix), c.width)
+        inside = (xs + 0.5 - gaze[v][0]) ** 2 + (ys + 0.5 - gaze[v][1]) ** 2 <= (0.2 * c.width) ** 2
+        assert inside.sum() > 100
+        np.testing.assert_array_equal(a[:, inside].view(np.uint32), b[:, inside].view(np.uint32))
+        imgs.append(a.astype(np.float64))
+        off += c.npix
+    rep = grads_close(g1, g0.astype(np.float64))
+    assert all(nb == 0 for _, nb, _ in rep), rep
+    tg, off = [], 0
+    for c in cams:
+        tg.append(tgt[3 * off:3 * (off + c.npix)].astype(np.float64))
+        off += c.npix
+    L, _ = oracle.loss_l1(imgs, tg, cams, gazes=gaze.astype(np.float64), radius_frac=0.2)
+    assert abs(l1 - L) <= 1e-5 * L
