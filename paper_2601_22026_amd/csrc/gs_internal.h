@@ -34,7 +34,9 @@ struct ViewDesc {
 };
 
 // Per-record screen-space splat, three 16-byte loads per gather:
-//   a = (hx, hy, A2, B2), b = (C2, opacity, red, green), c = (blue, tau, ix, iy).
+//   a = (hx, hy, A2, B2), b = (C2, opacity, red, green), c = (blue, h, ix, iy),
+// h being the padded half height in pixel rows of the support box (the region
+// where o e^power >= 1/255 can hold).
 // The pixel mean mu' is computed in double precision and split into an integer
 // pixel (ix, iy; exact floats) and the offset of mu' from that pixel's centre,
 // hx = ix + 1/2 - mu'_x (likewise hy), so that the offset of pixel (x, y) from
@@ -43,8 +45,9 @@ struct ViewDesc {
 // both sides of a small footprint, and float32 rounding of mu' itself (about
 // 3e-5 px at 1000 px) would otherwise dominate it.  The conic is stored
 // pre-scaled so that power2 = A2 dx^2 + C2 dy^2 + B2 dx dy = log2(e) * power,
-// i.e. A2 = -log2(e) A / 2, B2 = -log2(e) B, C2 = -log2(e) C / 2, and tau =
-// log2(1 / (255 opacity)) is the power2 below which alpha < 1/255.
+// i.e. A2 = -log2(e) A / 2, B2 = -log2(e) B, C2 = -log2(e) C / 2; the
+// compositing kernels compare power2 with tau = log2(1 / (255 opacity)), below
+// which alpha < 1/255.
 struct SplatPtrs {
     float4 *a;
     float4 *b;

@@ -36,6 +36,7 @@ constexpr float kLn2 = 0.69314718055994531f;
 
 // Shared by every kernel that walks a tile list so all take identical decisions.
 // a = (hx, hy, A2, B2), b = (C2, opacity, red, green), c = (blue, tau, ix, iy)
+// (c as staged: the record holds the support half height in place of tau)
 // with A2 = -log2(e) A / 2, B2 = -log2(e) B, C2 = -log2(e) C / 2; (x, y) is
 // the integer pixel (as float) and (dx, dy) its centre's offset from the mean.
 __device__ __forceinline__ float splat_dx(float x, float ix, float hx) { return (x - ix) + hx; }
@@ -59,6 +60,20 @@ __device__ __forceinline__ bool splat_alpha(const float4 &a, const float4 &b, co
 // bulk of the adjoint's VALU work, are shared by more pixels.
 template <int T>
 constexpr int bwd_threads() { return T == 32 ? 128 : 64; }
+
+// A record's c = (blue, hy, ix, iy) holds the padded half height hy of the
+// splat's support box (where o e^power >= 1/255 can hold; the bound the tile
+// lists are built with).  Staged into LDS as c = (blue, tau, ix, iy) plus hy
+// apart, tau derived from the opacity by the one expression every kernel uses.
+__device__ __forceinline__ float splat_tau(const float4 &b) { return -log2f(255.f * b.y); }
+
+// Whether rows with offsets [lo, lo + span] from a splat's mean can meet its
+// support of half height h (NaN-safe: only a definite miss returns false).
+// Rows farther away are skipped as a block: the per-pixel test would skip
+// every pair there.
+__device__ __forceinline__ bool rows_meet(float lo, float span, float h) {
+    return !(lo > h) && !(lo + span < -h);
+}
 
 __device__ __forceinline__ int view_of_tile(const ViewDesc *__restrict__ views, int nviews, int gt) {
     int v = 0;
@@ -143,9 +158,10 @@ __global__ __launch_bounds__(T * T < 256 ? T * T : 256) void k_render_fwd(
         __syncthreads();
         for (int j = threadIdx.x; j < nb; j += NT) {
             const uint32_t r = vals[bs + j];
-            s_a[j] = sp.a[r];
-            s_b[j] = sp.b[r];
-            s_c[j] = sp.c[r];
+            const float4 ra = sp.a[r], rb = sp.b[r], rc = sp.c[r];
+            s_a[j] = ra;
+            s_b[j] = rb;
+            s_c[j] = make_float4(rc.x, splat_tau(rb), rc.z, rc.w);
         }
         __syncthreads();
         for (int j0 = 0; j0 < nb; j0 += U) {
@@ -244,7 +260,7 @@ __device__ __forceinline__ void render_bwd_unit(
     const uint32_t *__restrict__ ncontrib, const float4 *__restrict__ fstate,
     const float4 *__restrict__ ckpt, const float *__restrict__ tstore, const float *__restrict__ dl,
     float *__restrict__ g2d, int nrec, float4 *s_a, float4 *s_b, float4 *s_c, uint32_t *s_r,
-    float (*s_g)[9][B], uint32_t *s_nmax) {
+    float (*s_g)[9][B], float *s_h, uint32_t *s_nmax) {
     constexpr bool CKPT = MODE == 1;
     constexpr int NT = bwd_threads<T>();
     constexpr int PPT = T * T / NT;
@@ -311,10 +327,12 @@ __device__ __forceinline__ void render_bwd_unit(
         __syncthreads();
         for (int j = threadIdx.x; j < nb; j += NT) {
             const uint32_t r = vals[bs + j];
-            s_a[j] = sp.a[r];
-            s_b[j] = sp.b[r];
-            s_c[j] = sp.c[r];
+            const float4 ra = sp.a[r], rb = sp.b[r], rc = sp.c[r];
+            s_a[j] = ra;
+            s_b[j] = rb;
+            s_c[j] = make_float4(rc.x, splat_tau(rb), rc.z, rc.w);
             s_r[j] = r;
+            s_h[j] = rc.y;
         }
         for (int e = threadIdx.x; e < NW * 9 * B; e += NT) (&s_g[0][0][0])[e] = 0.f;
         __syncthreads();
@@ -323,12 +341,19 @@ __device__ __forceinline__ void render_bwd_unit(
             const float4 a = s_a[j];
             const float4 b = s_b[j];
             const float4 c = s_c[j];
+            const float hy = s_h[j];
+            // row offset of the tile's first row from the mean; block k adds k ROWS
+            const float dy0 = splat_dx((float)(ty * T), c.w, a.y);
+            // per lane sums: dpw dx, dpw dy, dpw dx^2, dpw dx dy, dpw dy^2 (dpw = dL/dpower),
+            // dL/do, dL/dcolour; the conic factors of the mean gradient are applied once
+            // per splat when the sums are flushed
             float acc[9];
 #pragma unroll
             for (int f = 0; f < 9; f++) acc[f] = 0.f;
             bool any = false;
 #pragma unroll
             for (int k = 0; k < PPT; k++) {
+                if (!rows_meet(dy0 + (float)(k * ROWS), (float)(ROWS - 1), hy)) continue;   // wave-uniform
                 if (pos >= nc[k]) continue;
                 float alpha, ae, ex, dx, dy;
                 if (!splat_alpha(a, b, c, px[k], py[k], alpha, ae, ex, dx, dy)) continue;
@@ -347,13 +372,12 @@ __device__ __forceinline__ void render_bwd_unit(
                 if (ae > kAlphaMax) continue;      // clamped alpha: no gradient to o, power
                 const float dpw = ae * dalpha;     // d loss / d power (natural units)
                 acc[5] += ex * dalpha;
-                acc[2] += -0.5f * dx * dx * dpw;
-                acc[3] += -dx * dy * dpw;
-                acc[4] += -0.5f * dy * dy * dpw;
-                // d power / d mean = (A dx + B dy, B dx + C dy) = -ln2 (2 A2 dx + B2 dy, ...)
-                const float s2 = -kLn2 * dpw;
-                acc[0] += (2.f * a.z * dx + a.w * dy) * s2;
-                acc[1] += (a.w * dx + 2.f * b.x * dy) * s2;
+                const float ux = dpw * dx, uy = dpw * dy;
+                acc[0] += ux;
+                acc[1] += uy;
+                acc[2] = fmaf(ux, dx, acc[2]);
+                acc[3] = fmaf(ux, dy, acc[3]);
+                acc[4] = fmaf(uy, dy, acc[4]);
             }
             if (__any(any)) {
                 const int w = threadIdx.x >> 6;
@@ -367,9 +391,19 @@ __device__ __forceinline__ void render_bwd_unit(
         __syncthreads();
         for (int e = threadIdx.x; e < nb * 9; e += NT) {
             const int f = e / nb, j = e - f * nb;
-            float val = 0.f;
+            float S[2] = {0.f, 0.f};
+            const int f0 = f < 2 ? 0 : f, nf = f < 2 ? 2 : 1;
+            for (int q = 0; q < nf; q++)
 #pragma unroll
-            for (int w = 0; w < NW; w++) val += s_g[w][f][j];
+                for (int w = 0; w < NW; w++) S[q] += s_g[w][f0 + q][j];
+            float val;
+            // dpower/dmean = (A dx + B dy, B dx + C dy) = -ln2 (2 A2 dx + B2 dy, B2 dx + 2 C2 dy);
+            // dpower/d(A, B, C) = (-dx^2 / 2, -dx dy, -dy^2 / 2)
+            if (f == 0) val = -kLn2 * (2.f * s_a[j].z * S[0] + s_a[j].w * S[1]);
+            else if (f == 1) val = -kLn2 * (s_a[j].w * S[0] + 2.f * s_b[j].x * S[1]);
+            else if (f == 2 || f == 4) val = -0.5f * S[0];
+            else if (f == 3) val = -S[0];
+            else val = S[0];
             if (val != 0.f) unsafeAtomicAdd(&g2d[(size_t)f * nrec + s_r[j]], val);
         }
         be = bs;
@@ -392,12 +426,13 @@ __global__ __launch_bounds__(bwd_threads<T>()) void k_render_bwd(
     __shared__ float4 s_c[B];
     __shared__ uint32_t s_r[B];
     __shared__ float s_g[NT / 64][9][B];
+    __shared__ float s_h[B];
     __shared__ uint32_t s_nmax;
     const int gt = (int)order[blockIdx.x];
     const uint2 rg = ranges[gt];
     render_bwd_unit<T, B, MODE>(gt, rg.x, rg.y, true, rg, vals, sp, views, nviews, cams, tfinal,
                                 ncontrib, nullptr, nullptr, tstore, dl, g2d, nrec, s_a, s_b, s_c, s_r,
-                                s_g, &s_nmax);
+                                s_g, s_h, &s_nmax);
 }
 
 // Checkpoint mode: one workgroup per (tile, batch) unit id.  Unit u of tile t
@@ -419,6 +454,7 @@ __global__ __launch_bounds__(bwd_threads<T>()) void k_render_bwd_ckpt(
     __shared__ float4 s_c[B];
     __shared__ uint32_t s_r[B];
     __shared__ float s_g[NT / 64][9][B];
+    __shared__ float s_h[B];
     __shared__ uint32_t s_nmax;
     const uint32_t m = m_dev ? *m_dev : m_host;
     const uint32_t n_ids = m / B + (uint32_t)total_tiles;
@@ -437,7 +473,7 @@ __global__ __launch_bounds__(bwd_threads<T>()) void k_render_bwd_ckpt(
         const uint32_t ue = min(rg.y, us + B);
         render_bwd_unit<T, B, 1>(lo, us, ue, u + 1 == units, rg, vals, sp, views, nviews, cams,
                                  tfinal, ncontrib, fstate, ckpt, nullptr, dl, g2d, nrec, s_a, s_b,
-                                 s_c, s_r, s_g, &s_nmax);
+                                 s_c, s_r, s_g, s_h, &s_nmax);
     }
 }
 
@@ -471,7 +507,9 @@ __global__ __launch_bounds__(T * T < 256 ? T * T : 256) void k_count_pairs(
             const uint32_t r = vals[e];
             visit++;
             float alpha, ae, ex, dx, dy;
-            if (!splat_alpha(sp.a[r], sp.b[r], sp.c[r], px, py, alpha, ae, ex, dx, dy)) continue;
+            const float4 ra = sp.a[r], rb = sp.b[r], rc = sp.c[r];
+            const float4 c = make_float4(rc.x, splat_tau(rb), rc.z, rc.w);
+            if (!splat_alpha(ra, rb, c, px, py, alpha, ae, ex, dx, dy)) continue;
             const float Tn = Tr * (1.f - alpha);
             if (Tn < kTStop) break;
             Tr = Tn;
