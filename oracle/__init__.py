@@ -59,6 +59,9 @@ def lib():
                                    ct.c_int64, i64p, i64p, i32p]
         L.orc_loss_l1.argtypes = [dp, dp, ct.c_int64, ct.c_int64, dp, ct.c_double, dp, i64p]
         L.orc_loss_l1.restype = ct.c_double
+        L.orc_loss_l1_rgba.argtypes = [dp, dp, dp, ct.c_int64, ct.c_int64, dp, ct.c_double, ct.c_int,
+                                       dp, i64p]
+        L.orc_loss_l1_rgba.restype = ct.c_double
         L.orc_adam.argtypes = [dp, dp, dp, dp, ct.c_int64, ct.c_double, ct.c_double, ct.c_double,
                                ct.c_double, ct.c_int64]
         L.orc_adam.restype = None
@@ -206,6 +209,55 @@ def loss_l1(rgbas, targets, cams, gazes=None, radius_frac=0.2):
         dls.append(dl)
     denom = max(cnts, 1)
     return sums / denom, [d / denom for d in dls]
+
+
+def loss_l1_rgba(rgbas, targets, cams, bgs=None, alpha=True, gazes=None, radius_frac=0.2):
+    """Alpha training over backgrounds: mean |prediction - target| over all
+    masked (view, pixel, channel) entries, the RGBA target composited over the
+    view's background bgs[v] (None: black), channels R, G, B and (alpha) A.
+    Returns (loss, [dL/dRGBA per view])."""
+    sums, cnts, dls = 0.0, 0, []
+    for v, cam in enumerate(cams):
+        rgba = _d(rgbas[v]).reshape(4, -1)
+        tgt = np.ascontiguousarray(_d(targets[v]).reshape(4, -1))
+        dl = np.zeros_like(rgba)
+        cnt = np.zeros(1, np.int64)
+        g = None if gazes is None else _d(gazes[v])
+        bg = None if bgs is None else _d(bgs[v])
+        sums += lib().orc_loss_l1_rgba(_p(rgba), _p(tgt), _p(bg), cam.width, cam.height, _p(g),
+                                       float(radius_frac * cam.width), int(bool(alpha)), _p(dl),
+                                       _p(cnt, ct.c_int64))
+        cnts += int(cnt[0])
+        dls.append(dl)
+    denom = max(cnts, 1)
+    return sums / denom, [d / denom for d in dls]
+
+
+_M64 = (1 << 64) - 1
+
+
+def splitmix64(seed: int, k: int) -> int:
+    """k-th output (k >= 1) of the SplitMix64 generator (Steele, Lea and Flood,
+    "Fast splittable pseudorandom number generators", OOPSLA 2014) started from
+    state ``seed``: the state advances by the golden-ratio increment and each
+    output is the state passed through the published 64-bit finaliser."""
+    z = (seed + k * 0x9E3779B97F4A7C15) & _M64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _M64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _M64
+    return z ^ (z >> 31)
+
+
+def background_draw(seed: int, step: int, nviews: int, max_views: int = 64) -> np.ndarray:
+    """Random background of every view for fit step ``step`` (0-based): channel
+    c of view v is the top 24 bits of output 1 + (step * max_views + v) * 4 + c
+    of SplitMix64(seed), scaled to [0, 1).  [nviews][3] float64 (exact float32
+    values)."""
+    out = np.zeros((nviews, 3))
+    for v in range(nviews):
+        for c in range(3):
+            z = splitmix64(seed, 1 + (step * max_views + v) * 4 + c)
+            out[v, c] = (z >> 40) * 2.0 ** -24
+    return out
 
 
 def adam(p, g, m, v, t, lr=1e-3, betas=(0.9, 0.999), eps=1e-15):

@@ -791,6 +791,44 @@ double orc_loss_l1(const double *rgba, const double *target, int64_t w, int64_t 
     return sum;
 }
 
+/* Alpha training with a background (Method, "Periphery Model Training": the
+ * peripheral model is trained on alpha as well as colour, over randomised
+ * backgrounds).  Reading: the target is RGBA, its colour premultiplied (an
+ * emission-absorption render over black); prediction and target are both
+ * composited over the view's background bg, i.e. the target becomes
+ * target_rgb + (1 - target_alpha) bg while the prediction was rendered with
+ * bg; the L1 covers R, G, B and, with alpha != 0, A.  Returns the sum of the
+ * masked terms; *count = the number of masked entries; dl = their signs. */
+double orc_loss_l1_rgba(const double *rgba, const double *target_rgba, const double *bg, int64_t w,
+                        int64_t h, const double *gaze, double radius, int alpha, double *dl,
+                        int64_t *count) {
+    const int64_t npix = w * h;
+    double sum = 0;
+    int64_t cnt = 0;
+    for (int64_t k = 0; k < npix; k++) {
+        int in = 1;
+        if (gaze) {
+            const double dx = (double)(k % w) + 0.5 - gaze[0], dy = (double)(k / w) + 0.5 - gaze[1];
+            in = dx * dx + dy * dy <= radius * radius;
+        }
+        const double ta = target_rgba[3 * npix + k];
+        for (int c = 0; c < 4; c++) {
+            double t = target_rgba[c * npix + k];
+            if (c < 3 && bg) t += (1.0 - ta) * bg[c];
+            const double d = rgba[c * npix + k] - t;
+            if (in && (c < 3 || alpha)) {
+                sum += fabs(d);
+                cnt++;
+                dl[c * npix + k] = d > 0 ? 1.0 : (d < 0 ? -1.0 : 0.0);
+            } else {
+                dl[c * npix + k] = 0;
+            }
+        }
+    }
+    *count = cnt;
+    return sum;
+}
+
 /* One Adam step (t = step number, >= 1) on n elements, in place. */
 void orc_adam(double *p, const double *g, double *m, double *v, int64_t n, double lr, double b1,
               double b2, double eps, int64_t t) {

@@ -517,6 +517,51 @@ def test_l1_loss_and_sign_gradient():
     assert (dlm[0][:, ~m] == 0).all()
 
 
+def test_rgba_loss_reduces_to_rgb_loss_and_hand_values():
+    rng = np.random.default_rng(3)
+    cam = synth.axis_camera(12, 9)
+    rgba = rng.uniform(size=(4, cam.npix))
+    tgt = rng.uniform(size=(4, cam.npix))
+    # black background, no alpha term: the RGB loss
+    L0, d0 = oracle.loss_l1([rgba], [tgt[:3]], [cam])
+    L1, d1 = oracle.loss_l1_rgba([rgba], [tgt], [cam], bgs=None, alpha=False)
+    assert abs(L0 - L1) < 1e-15
+    np.testing.assert_array_equal(d0[0], d1[0])
+    # one pixel by hand: target (0.3, 0.1, 0.2, A 0.5) over bg (1, 0.5, 0) is
+    # (0.8, 0.35, 0.2); prediction (0.5, 0.2, 0.9, 0.6)
+    one = synth.axis_camera(1, 1)
+    L, d = oracle.loss_l1_rgba([np.array([0.5, 0.2, 0.9, 0.6])], [np.array([0.3, 0.1, 0.2, 0.5])],
+                               [one], bgs=[np.array([1.0, 0.5, 0.0])], alpha=True)
+    assert abs(L - (0.3 + 0.15 + 0.7 + 0.1) / 4) < 1e-15
+    np.testing.assert_array_equal(d[0][:, 0], np.array([-1.0, -1.0, 1.0, 1.0]) / 4)
+
+
+def test_target_over_background_is_the_renderers_own_compositing():
+    """Rendering a scene over bg equals its render over black composited as
+    target_rgb + (1 - target_alpha) bg - the rule the RGBA loss applies to
+    the target - so a model that reproduces the target over black reproduces
+    it over every background."""
+    P = synth.random_gaussians(40, seed=4)
+    bg = (0.7, 0.2, 0.4)
+    black = synth.axis_camera(24, 20)
+    coloured = synth.axis_camera(24, 20, bg=bg)
+    r0 = oracle.render(P, black)
+    r1 = oracle.render(P, coloured)
+    over = r0.rgba[:3] + (1.0 - r0.rgba[3]) * coloured.bg.astype(np.float64)[:, None]
+    np.testing.assert_allclose(r1.rgba[:3], over, rtol=0, atol=1e-12)
+    L, _ = oracle.loss_l1_rgba([r1.rgba], [r0.rgba], [coloured], bgs=[coloured.bg], alpha=True)
+    assert L < 1e-12
+
+
+def test_splitmix64_published_first_output_and_background_range():
+    # first output of SplitMix64 from state 0, as published with the generator
+    assert oracle.splitmix64(0, 1) == 0xE220A8397B1DCDAF
+    bg = oracle.background_draw(7, 3, 5)
+    assert bg.shape == (5, 3) and (bg >= 0).all() and (bg < 1).all()
+    assert (bg.astype(np.float32).astype(np.float64) == bg).all()
+    assert not np.array_equal(bg, oracle.background_draw(7, 4, 5))
+
+
 def test_adam_first_step_closed_form():
     rng = np.random.default_rng(0)
     p = rng.normal(size=100)
