@@ -192,7 +192,29 @@ typedef struct gsf_step_args {
                                    loss and gradients are those of the full frame (other
                                    pixels carry no loss); rgba and dl_drgba outside those
                                    tiles are left as they were.  0: full frames. */
+    int32_t alpha_loss;         /* 1: target_rgb is RGBA per view ([4][H][W], colour
+                                   premultiplied) and the L1 also covers alpha (alpha
+                                   training, Method "Periphery Model Training") */
+    int32_t random_bg;          /* 1 (needs alpha_loss): every step draws one background
+                                   colour per view (SplitMix64 from bg_seed, output
+                                   1 + (step * 64 + v) * 4 + c, top 24 bits scaled to
+                                   [0, 1), step = *step_dev before the step) and renders,
+                                   differentiates and compares over it; the target is
+                                   composited over it as rgb + (1 - alpha) bg.  The
+                                   cameras' bg is not used then.  0: the cameras' bg. */
+    uint64_t bg_seed;
 } gsf_step_args;
+
+/* L1 of an RGBA prediction against RGBA targets (alpha training): the target
+ * colour is premultiplied and composited over bg (device [n_views][3], NULL =
+ * black) as rgb + (1 - alpha) bg; the mean runs over R, G, B and, with
+ * alpha != 0, A of every masked pixel (mask as in gsf_loss_l1).  rgba as
+ * produced by gsf_forward with the same bg in the cameras; dl_drgba receives
+ * the sign gradient of all four planes.  Same ownership and errors as
+ * gsf_loss_l1. */
+gsf_status gsf_loss_l1_rgba(gsf_plan *plan, const float *rgba, const float *target_rgba,
+                            const float *bg, int32_t alpha, const float *gaze_px,
+                            float mask_radius_frac, float *loss, float *dl_drgba);
 
 /* Enqueue one step eagerly. */
 gsf_status gsf_step(gsf_plan *plan, const gsf_step_args *args);
@@ -249,8 +271,9 @@ enum {
     GSF_DBG_G2D = 8,       /* float [9][n_views * n]: per-record screen-space gradient */
     GSF_DBG_PROJ = 9,      /* float [11] per record: mean x, mean y, conic A, B, C, opacity,
                               red, green, blue, camera depth, valid (1 or 0) */
-    GSF_DBG_ORDER = 10     /* uint32 per global tile: compositing order of the tiles (a
+    GSF_DBG_ORDER = 10,    /* uint32 per global tile: compositing order of the tiles (a
                               permutation; tiles with more keys first) */
+    GSF_DBG_BG = 11        /* float [n_views][3]: backgrounds drawn by the last random_bg step */
 };
 /* Synchronise and copy an internal buffer of the last forward/backward to host
  * memory (at most cap bytes; bytes copied in *written). */

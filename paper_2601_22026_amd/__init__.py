@@ -145,6 +145,15 @@ class Plan:
         self.ctx.check(lib().gsf_loss_l1(self.handle, _ptr(rgba), _ptr(target), _ptr(gaze),
                                          float(radius_frac), _ptr(loss), _ptr(dl)), "gsf_loss_l1")
 
+    def loss_l1_rgba(self, rgba, target_rgba, loss, dl, bg=None, alpha=True, gaze=None,
+                     radius_frac=0.0):
+        """Alpha-training L1 against RGBA targets composited over bg ([V][3] device
+        tensor or None for black)."""
+        self.ctx.use_stream()
+        self.ctx.check(lib().gsf_loss_l1_rgba(self.handle, _ptr(rgba), _ptr(target_rgba), _ptr(bg),
+                                              int(bool(alpha)), _ptr(gaze), float(radius_frac),
+                                              _ptr(loss), _ptr(dl)), "gsf_loss_l1_rgba")
+
     def backward(self, params, n, cams_dev, dl, grads):
         self.ctx.use_stream()
         self.ctx.check(lib().gsf_backward(self.handle, _ptr(params), int(n), _ptr(cams_dev),
@@ -245,6 +254,9 @@ class FitConfig:
     key_capacity: int = 0
     t_mode: int = 1          # adjoint transmittance of the fused step: 0 recomputed, 1 checkpointed, 2 stored
     fovea_cull: bool = False  # fused step with a gaze: composite only the tiles that meet the fovea
+    alpha_loss: bool = False  # targets are RGBA ([4][H][W] per view) and the L1 covers alpha
+    random_bg: bool = False   # fused step: a new background per view each step (needs alpha_loss)
+    bg_seed: int = 0
 
 
 class FitStep:
@@ -282,6 +294,10 @@ class FitStep:
         self.loss = torch.zeros(1, dtype=torch.float32, device=dev)
         lr = cfg.lr if isinstance(cfg.lr, (list, tuple)) else [cfg.lr] * self.C
         self._seg_lr = (ct.c_float * self.C)(*[float(x) for x in lr])
+        if cfg.random_bg and not cfg.alpha_loss:
+            raise ValueError("random_bg needs alpha_loss (RGBA targets)")
+        if not fused and (cfg.alpha_loss or cfg.random_bg):
+            raise ValueError("alpha training and random backgrounds are fused-step options")
         if fused:
             cap = cfg.key_capacity or self._measure_capacity()
             self.plan = Plan(ctx, self.n, self.sizes, self.sh_degree, cfg.tile, cfg.lds_batch,
@@ -317,7 +333,9 @@ class FitStep:
             adam_m=self.m.data_ptr(), adam_v=self.v.data_ptr(), step_dev=self.step_dev.data_ptr(),
             seg_lr=ct.cast(self._seg_lr, ct.POINTER(ct.c_float)), beta1=self.cfg.betas[0],
             beta2=self.cfg.betas[1], eps=self.cfg.eps,
-            fovea_cull=int(bool(self.cfg.fovea_cull and gaze is not None)))
+            fovea_cull=int(bool(self.cfg.fovea_cull and gaze is not None)),
+            alpha_loss=int(bool(self.cfg.alpha_loss)), random_bg=int(bool(self.cfg.random_bg)),
+            bg_seed=int(self.cfg.bg_seed) & ((1 << 64) - 1))
 
     def step(self):
         """One eager step."""
@@ -358,6 +376,12 @@ class FitStep:
     def replay(self):
         self.ctx.use_stream()
         self.ctx.check(lib().gsf_step_replay(self.plan.handle), "gsf_step_replay")
+
+    def backgrounds(self):
+        """The per-view backgrounds [V][3] drawn by the last random_bg step."""
+        if not (self.fused and self.cfg.random_bg):
+            raise GsfError(_abi.GSF_E_STATE, "no random backgrounds in this step")
+        return self.plan.debug(_abi.GSF_DBG_BG, np.float32, 3 * len(self.cams)).reshape(-1, 3)
 
     def reset_optimizer(self):
         """Continual refinement restarts Adam: zero m, v and the step counter."""

@@ -17,14 +17,14 @@ STATUS_NAMES = {0: "GSF_OK", 1: "GSF_E_INVALID", 2: "GSF_E_CAPACITY", 3: "GSF_E_
 GSF_FLAG_CAPACITY = 1
 GSF_FLAG_NONFINITE = 2
 (GSF_DBG_RECT, GSF_DBG_COUNT, GSF_DBG_DEPTH, GSF_DBG_KEYS, GSF_DBG_VALS, GSF_DBG_RANGES,
- GSF_DBG_TFINAL, GSF_DBG_NCONTRIB, GSF_DBG_G2D, GSF_DBG_PROJ, GSF_DBG_ORDER) = range(11)
+ GSF_DBG_TFINAL, GSF_DBG_NCONTRIB, GSF_DBG_G2D, GSF_DBG_PROJ, GSF_DBG_ORDER, GSF_DBG_BG) = range(12)
 
 EXPORTED = ["gsf_ctx_create", "gsf_ctx_destroy", "gsf_ctx_set_stream", "gsf_last_error",
             "gsf_plan_create", "gsf_plan_workspace_bytes", "gsf_plan_bind_workspace",
             "gsf_plan_info", "gsf_plan_destroy", "gsf_forward", "gsf_loss_l1", "gsf_backward",
             "gsf_adam", "gsf_step", "gsf_step_capture", "gsf_step_replay", "gsf_poll",
             "gsf_debug_copy", "gsf_plan_set_timing", "gsf_plan_stage_times",
-            "gsf_count_pairs"]
+            "gsf_count_pairs", "gsf_loss_l1_rgba"]
 STAGES = ["project", "duplicate", "tile_sort", "ranges", "depth_sort", "render", "loss",
           "render_bwd", "project_bwd", "adam", "zero"]
 
@@ -57,7 +57,8 @@ class gsf_step_args(ct.Structure):
                 ("dl_drgba", ct.c_void_p), ("grads", ct.c_void_p), ("adam_m", ct.c_void_p),
                 ("adam_v", ct.c_void_p), ("step_dev", ct.c_void_p),
                 ("seg_lr", ct.POINTER(ct.c_float)), ("beta1", ct.c_float), ("beta2", ct.c_float),
-                ("eps", ct.c_float), ("fovea_cull", ct.c_int32)]
+                ("eps", ct.c_float), ("fovea_cull", ct.c_int32), ("alpha_loss", ct.c_int32),
+                ("random_bg", ct.c_int32), ("bg_seed", ct.c_uint64)]
 
 
 assert ct.sizeof(gsf_camera) == 128
@@ -77,6 +78,7 @@ def _declare(L):
         "gsf_plan_destroy": [vp],
         "gsf_forward": [vp, vp, i64, vp, vp],
         "gsf_loss_l1": [vp, vp, vp, vp, f32, vp, vp],
+        "gsf_loss_l1_rgba": [vp, vp, vp, vp, i32, vp, f32, vp, vp],
         "gsf_backward": [vp, vp, i64, vp, vp, vp],
         "gsf_adam": [vp, vp, vp, vp, vp, i64, ct.POINTER(ct.c_int64), ct.POINTER(ct.c_float), i32,
                      f32, f32, f32, vp],

@@ -141,6 +141,7 @@ struct RenderArgs {
     int t_mode = 0;                       // 0 recompute, 1 checkpointed, 2 stored transmittance
     int bwd_grid = 1;                     // workgroups of the checkpointed adjoint (unit ids)
     const uint32_t *order = nullptr;      // tile ids, heavy tiles first
+    const float *bg = nullptr;            // per-view background [V][3] replacing the cameras' bg
     const float *cull_gaze = nullptr;     // fovea culling: only tiles meeting the fovea are composited
     float cull_radius = 0.f;
     const uint2 *ranges = nullptr;
@@ -174,10 +175,17 @@ int loss_partials(int64_t total_pix);
 // box > 0 (fovea culling, gaze required): only the box x box pixel window of each
 // view starting at its first fovea tile is visited (every pixel of the tiles
 // that meet the fovea; nviews * box^2 <= total_pix); dl elsewhere is not written.
+// RGBA targets (tgt_planes 4): the target colour is composited over bg
+// ([V][3], nullable = black) and, with alpha_term, alpha is a fourth L1 channel.
 void launch_loss_l1(hipStream_t s, const float *rgba, const float *target, const float *gaze,
                     float radius_frac, const ViewDesc *views, int nviews, int64_t total_pix,
                     float *dl, float *partial, uint32_t *mask_count, float *loss, uint32_t *flags,
-                    int32_t *step_inc, int box, int tile);
+                    int32_t *step_inc, int box, int tile, int tgt_planes, bool alpha_term,
+                    const float *bg);
+
+// bg[v][c] = top 24 bits of output 1 + (step[0] * kMaxViews + v) * 4 + c of
+// SplitMix64(seed), scaled to [0, 1).
+void launch_draw_bg(hipStream_t s, uint64_t seed, const int32_t *step, int nviews, float *bg);
 
 // Adam with bias correction for step step[0]; when advance is true a one-thread
 // kernel first advances step[0] by one.

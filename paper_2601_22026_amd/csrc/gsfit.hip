@@ -61,6 +61,7 @@ struct Buffers {
     unsigned long long *m_total = nullptr;
     unsigned long long *counters = nullptr;
     float *loss_partial = nullptr;
+    float *bg = nullptr;                         // per-view random background of the step [V][3]
     ViewDesc *views = nullptr;
 };
 
@@ -168,6 +169,7 @@ size_t carve(gsf_plan *p, char *base, Buffers *out) {
     b.m_total = (unsigned long long *)take(8);
     b.counters = (unsigned long long *)take(3 * 8);
     b.loss_partial = (float *)take((size_t)loss_partials(p->total_pix) * 4);
+    b.bg = (float *)take(p->views.size() * 3 * sizeof(float));
     b.views = (ViewDesc *)take(p->views.size() * sizeof(ViewDesc));
     if (out) *out = b;
     return off;
@@ -251,7 +253,7 @@ struct StageTimer {
 // cull_gaze (nullable): fovea culling with radius fraction cull_radius.
 gsf_status enqueue_forward(gsf_plan *p, const float *params, int64_t n, const gsf_camera *cams,
                            float *out_rgba, bool *overflow, const float *cull_gaze = nullptr,
-                           float cull_radius = 0.f) {
+                           float cull_radius = 0.f, const float *bg = nullptr) {
     gsf_ctx *ctx = p->ctx;
     hipStream_t s = ctx->stream;
     Buffers &b = p->b;
@@ -305,6 +307,7 @@ gsf_status enqueue_forward(gsf_plan *p, const float *params, int64_t n, const gs
         RenderArgs ra = render_args(p, cams, n);
         ra.cull_gaze = cull_gaze;
         ra.cull_radius = cull_radius;
+        ra.bg = bg;
         launch_render_fwd(s, ra, out_rgba);
     }
     GSF_LAUNCHED(ctx);
@@ -315,9 +318,12 @@ gsf_status enqueue_forward(gsf_plan *p, const float *params, int64_t n, const gs
 
 // cull: visit only the pixels of the tiles that meet each view's fovea (gaze
 // required) - a window of box x box pixels per view, when that is smaller.
+// tgt_planes 4: RGBA targets composited over bg (nullable) with an alpha term
+// when alpha_term.
 gsf_status enqueue_loss(gsf_plan *p, const float *rgba, const float *target, const float *gaze,
                         float radius_frac, float *loss, float *dl, int32_t *step_inc,
-                        bool cull = false) {
+                        bool cull = false, int tgt_planes = 3, bool alpha_term = false,
+                        const float *bg = nullptr) {
     int box = 0;
     if (cull && gaze) {
         int wmax = 1;
@@ -330,13 +336,13 @@ gsf_status enqueue_loss(gsf_plan *p, const float *rgba, const float *target, con
     StageTimer t(p, GSF_STAGE_LOSS);
     launch_loss_l1(p->ctx->stream, rgba, target, gaze, radius_frac, p->b.views, p->V,
                    p->total_pix, dl, p->b.loss_partial, p->b.mask_count, loss, p->b.flags,
-                   step_inc, box, p->tile);
+                   step_inc, box, p->tile, tgt_planes, alpha_term, bg);
     GSF_LAUNCHED(p->ctx);
     return GSF_OK;
 }
 
 gsf_status enqueue_backward(gsf_plan *p, const float *params, int64_t n, const gsf_camera *cams,
-                            const float *dl, float *grads) {
+                            const float *dl, float *grads, const float *bg = nullptr) {
     hipStream_t s = p->ctx->stream;
     const int64_t nrec = n * p->V;
     if (!p->g2d_clean) {   // a second adjoint of the same forward: clear the accumulator
@@ -345,7 +351,9 @@ gsf_status enqueue_backward(gsf_plan *p, const float *params, int64_t n, const g
     }
     {
         StageTimer t(p, GSF_STAGE_RENDER_BWD);
-        launch_render_bwd(s, render_args(p, cams, n), dl, p->b.g2d);
+        RenderArgs ra = render_args(p, cams, n);
+        ra.bg = bg;
+        launch_render_bwd(s, ra, dl, p->b.g2d);
     }
     p->g2d_clean = false;
     GSF_LAUNCHED(p->ctx);
@@ -390,20 +398,30 @@ gsf_status check_step(gsf_plan *p, const gsf_step_args *a) {
         return fail(p->ctx, GSF_E_INVALID, "gsf_step: fovea_cull needs gaze_px");
     if (a->fovea_cull && !(a->mask_radius_frac >= 0.f && a->mask_radius_frac <= 4.f))
         return fail(p->ctx, GSF_E_INVALID, "gsf_step: mask_radius_frac must lie in [0, 4]");
+    if ((a->alpha_loss != 0 && a->alpha_loss != 1) || (a->random_bg != 0 && a->random_bg != 1))
+        return fail(p->ctx, GSF_E_INVALID, "gsf_step: alpha_loss and random_bg must be 0 or 1");
+    if (a->random_bg && !a->alpha_loss)
+        return fail(p->ctx, GSF_E_INVALID, "gsf_step: random_bg needs alpha_loss (RGBA targets)");
     return GSF_OK;
 }
 
 gsf_status enqueue_step(gsf_plan *p, const gsf_step_args *a) {
     bool overflow = false;
     const bool cull = a->fovea_cull != 0;
+    const float *bg = nullptr;
+    if (a->random_bg) {   // this step's backgrounds, from the step counter on the device
+        launch_draw_bg(p->ctx->stream, a->bg_seed, a->step_dev, p->V, p->b.bg);
+        GSF_LAUNCHED(p->ctx);
+        bg = p->b.bg;
+    }
     gsf_status st = enqueue_forward(p, a->params, a->n, a->cams, a->rgba, &overflow,
-                                    cull ? a->gaze_px : nullptr, a->mask_radius_frac);
+                                    cull ? a->gaze_px : nullptr, a->mask_radius_frac, bg);
     if (st != GSF_OK) return st;
     // the loss reduction also advances the Adam step counter of this step
     st = enqueue_loss(p, a->rgba, a->target_rgb, a->gaze_px, a->mask_radius_frac, a->loss,
-                      a->dl_drgba, a->step_dev, cull);
+                      a->dl_drgba, a->step_dev, cull, a->alpha_loss ? 4 : 3, a->alpha_loss != 0, bg);
     if (st != GSF_OK) return st;
-    st = enqueue_backward(p, a->params, a->n, a->cams, a->dl_drgba, a->grads);
+    st = enqueue_backward(p, a->params, a->n, a->cams, a->dl_drgba, a->grads, bg);
     if (st != GSF_OK) return st;
     const int C = planes_of(p->deg);
     std::vector<int64_t> off(C + 1);
@@ -593,6 +611,20 @@ gsf_status gsf_loss_l1(gsf_plan *p, const float *rgba, const float *target_rgb, 
     return enqueue_loss(p, rgba, target_rgb, gaze_px, mask_radius_frac, loss, dl_drgba, nullptr);
 }
 
+gsf_status gsf_loss_l1_rgba(gsf_plan *p, const float *rgba, const float *target_rgba,
+                            const float *bg, int32_t alpha, const float *gaze_px,
+                            float mask_radius_frac, float *loss, float *dl_drgba) {
+    gsf_status st = check_ready(p);
+    if (st != GSF_OK) return st;
+    if (!rgba || !target_rgba || !loss || !dl_drgba)
+        return fail(p->ctx, GSF_E_INVALID, "gsf_loss_l1_rgba: null argument");
+    if (alpha != 0 && alpha != 1) return fail(p->ctx, GSF_E_INVALID, "gsf_loss_l1_rgba: alpha must be 0 or 1");
+    if (gaze_px && !(mask_radius_frac >= 0.f))
+        return fail(p->ctx, GSF_E_INVALID, "gsf_loss_l1_rgba: bad radius");
+    return enqueue_loss(p, rgba, target_rgba, gaze_px, mask_radius_frac, loss, dl_drgba, nullptr,
+                        false, 4, alpha != 0, bg);
+}
+
 gsf_status gsf_backward(gsf_plan *p, const float *params, int64_t n, const gsf_camera *cams,
                         const float *dl_drgba, float *grads) {
     gsf_status st = check_ready(p);
@@ -754,6 +786,7 @@ gsf_status gsf_debug_copy(gsf_plan *p, int which, void *host_dst, size_t cap, si
     case GSF_DBG_VALS: src = p->b.vals; bytes = M * 4; break;
     case GSF_DBG_RANGES: src = p->b.ranges; bytes = (size_t)p->total_tiles * 8; break;
     case GSF_DBG_ORDER: src = p->b.order; bytes = (size_t)p->total_tiles * 4; break;
+    case GSF_DBG_BG: src = p->b.bg; bytes = p->views.size() * 3 * sizeof(float); break;
     case GSF_DBG_TFINAL: src = p->b.tfinal; bytes = (size_t)p->total_pix * 4; break;
     case GSF_DBG_NCONTRIB: src = p->b.ncontrib; bytes = (size_t)p->total_pix * 4; break;
     case GSF_DBG_G2D: src = p->b.g2d; bytes = 9 * R * 4; break;

@@ -117,7 +117,7 @@ __global__ __launch_bounds__(T * T < 256 ? T * T : 256) void k_render_fwd(
     const ViewDesc *__restrict__ views, int nviews, const gsf_camera *__restrict__ cams,
     float *__restrict__ out_rgba, float *__restrict__ tfinal, uint32_t *__restrict__ ncontrib,
     float4 *__restrict__ ckpt, float4 *__restrict__ fstate, float *__restrict__ tstore,
-    const float *__restrict__ cull_gaze, float cull_radius) {
+    const float *__restrict__ bg, const float *__restrict__ cull_gaze, float cull_radius) {
     constexpr bool CKPT = MODE == 1;
     constexpr int NT = T * T < 256 ? T * T : 256;
     constexpr int PPT = T * T / NT;
@@ -228,8 +228,8 @@ __global__ __launch_bounds__(T * T < 256 ? T * T : 256) void k_render_fwd(
         if (__syncthreads_and(all)) break;
     }
 
-    const gsf_camera &cam = cams[v];
-    const float bg0 = cam.bg[0], bg1 = cam.bg[1], bg2 = cam.bg[2];
+    const float *bgv = bg ? bg + 3 * v : cams[v].bg;
+    const float bg0 = bgv[0], bg1 = bgv[1], bg2 = bgv[2];
     const size_t plane = (size_t)vd.width * vd.height;
     float *img = out_rgba + 4 * (size_t)vd.pix_off;
 #pragma unroll
@@ -258,9 +258,9 @@ __device__ __forceinline__ void render_bwd_unit(
     const uint32_t *__restrict__ vals, SplatPtrs sp, const ViewDesc *__restrict__ views,
     int nviews, const gsf_camera *__restrict__ cams, const float *__restrict__ tfinal,
     const uint32_t *__restrict__ ncontrib, const float4 *__restrict__ fstate,
-    const float4 *__restrict__ ckpt, const float *__restrict__ tstore, const float *__restrict__ dl,
-    float *__restrict__ g2d, int nrec, float4 *s_a, float4 *s_b, float4 *s_c, uint32_t *s_r,
-    float (*s_g)[9][B], float *s_h, uint32_t *s_nmax) {
+    const float4 *__restrict__ ckpt, const float *__restrict__ tstore, const float *__restrict__ bg,
+    const float *__restrict__ dl, float *__restrict__ g2d, int nrec, float4 *s_a, float4 *s_b,
+    float4 *s_c, uint32_t *s_r, float (*s_g)[9][B], float *s_h, uint32_t *s_nmax) {
     constexpr bool CKPT = MODE == 1;
     constexpr int NT = bwd_threads<T>();
     constexpr int PPT = T * T / NT;
@@ -271,8 +271,8 @@ __device__ __forceinline__ void render_bwd_unit(
     const int local = gt - vd.tile_off;
     const int ty = local / vd.tiles_x, tx = local - ty * vd.tiles_x;
     const int lx = threadIdx.x % T, ly = threadIdx.x / T;
-    const gsf_camera &cam = cams[v];
-    const float bg0 = cam.bg[0], bg1 = cam.bg[1], bg2 = cam.bg[2];
+    const float *bgv = bg ? bg + 3 * v : cams[v].bg;
+    const float bg0 = bgv[0], bg1 = bgv[1], bg2 = bgv[2];
     const size_t plane = (size_t)vd.width * vd.height;
     const float *dimg = dl + 4 * (size_t)vd.pix_off;
 
@@ -418,8 +418,8 @@ __global__ __launch_bounds__(bwd_threads<T>()) void k_render_bwd(
     const uint2 *__restrict__ ranges, const uint32_t *__restrict__ vals, SplatPtrs sp,
     const ViewDesc *__restrict__ views, int nviews, const gsf_camera *__restrict__ cams,
     const float *__restrict__ tfinal, const uint32_t *__restrict__ ncontrib,
-    const float *__restrict__ tstore, const float *__restrict__ dl, float *__restrict__ g2d,
-    int nrec) {
+    const float *__restrict__ tstore, const float *__restrict__ bg, const float *__restrict__ dl,
+    float *__restrict__ g2d, int nrec) {
     constexpr int NT = bwd_threads<T>();
     __shared__ float4 s_a[B];
     __shared__ float4 s_b[B];
@@ -431,8 +431,8 @@ __global__ __launch_bounds__(bwd_threads<T>()) void k_render_bwd(
     const int gt = (int)order[blockIdx.x];
     const uint2 rg = ranges[gt];
     render_bwd_unit<T, B, MODE>(gt, rg.x, rg.y, true, rg, vals, sp, views, nviews, cams, tfinal,
-                                ncontrib, nullptr, nullptr, tstore, dl, g2d, nrec, s_a, s_b, s_c, s_r,
-                                s_g, s_h, &s_nmax);
+                                ncontrib, nullptr, nullptr, tstore, bg, dl, g2d, nrec, s_a, s_b, s_c,
+                                s_r, s_g, s_h, &s_nmax);
 }
 
 // Checkpoint mode: one workgroup per (tile, batch) unit id.  Unit u of tile t
@@ -447,7 +447,7 @@ __global__ __launch_bounds__(bwd_threads<T>()) void k_render_bwd_ckpt(
     const ViewDesc *__restrict__ views, int nviews, const gsf_camera *__restrict__ cams,
     const float *__restrict__ tfinal, const uint32_t *__restrict__ ncontrib,
     const float4 *__restrict__ fstate, const float4 *__restrict__ ckpt,
-    const float *__restrict__ dl, float *__restrict__ g2d, int nrec) {
+    const float *__restrict__ bg, const float *__restrict__ dl, float *__restrict__ g2d, int nrec) {
     constexpr int NT = bwd_threads<T>();
     __shared__ float4 s_a[B];
     __shared__ float4 s_b[B];
@@ -472,8 +472,8 @@ __global__ __launch_bounds__(bwd_threads<T>()) void k_render_bwd_ckpt(
         const uint32_t us = rg.x + u * B;
         const uint32_t ue = min(rg.y, us + B);
         render_bwd_unit<T, B, 1>(lo, us, ue, u + 1 == units, rg, vals, sp, views, nviews, cams,
-                                 tfinal, ncontrib, fstate, ckpt, nullptr, dl, g2d, nrec, s_a, s_b,
-                                 s_c, s_r, s_g, s_h, &s_nmax);
+                                 tfinal, ncontrib, fstate, ckpt, nullptr, bg, dl, g2d, nrec, s_a,
+                                 s_b, s_c, s_r, s_g, s_h, &s_nmax);
     }
 }
 
@@ -579,7 +579,7 @@ __global__ __launch_bounds__(kLossBlock) void k_loss_count(const float *__restri
                                                            float radius_frac,
                                                            const ViewDesc *__restrict__ views,
                                                            int nviews, int64_t total_pix, int box,
-                                                           int tile,
+                                                           int tile, uint32_t channels,
                                                            uint32_t *__restrict__ mask_count) {
     __shared__ uint32_t s_cnt;
     if (threadIdx.x == 0) s_cnt = 0u;
@@ -588,7 +588,7 @@ __global__ __launch_bounds__(kLossBlock) void k_loss_count(const float *__restri
     int v, x, y;
     if (loss_pixel(p, total_pix, box, tile, gaze, radius_frac, views, nviews, v, x, y)) {
         const ViewDesc vd = views[v];
-        if (in_fovea(gaze, v, x, y, radius_frac * (float)vd.width)) atomicAdd(&s_cnt, 3u);
+        if (in_fovea(gaze, v, x, y, radius_frac * (float)vd.width)) atomicAdd(&s_cnt, channels);
     }
     __syncthreads();
     if (threadIdx.x == 0 && s_cnt) atomicAdd(mask_count, s_cnt);
@@ -602,7 +602,8 @@ __global__ __launch_bounds__(kLossBlock) void k_loss_count(const float *__restri
 __global__ __launch_bounds__(kLossBlock) void k_loss_l1(
     const float *__restrict__ rgba, const float *__restrict__ target, const float *__restrict__ gaze,
     float radius_frac, const ViewDesc *__restrict__ views, int nviews, int64_t total_pix, int box,
-    int tile, const uint32_t *__restrict__ mask_count, uint32_t count_host, float *__restrict__ dl,
+    int tile, int tgt_planes, bool alpha_term, const float *__restrict__ bg,
+    const uint32_t *__restrict__ mask_count, uint32_t count_host, float *__restrict__ dl,
     float *__restrict__ partial) {
     __shared__ float s_red[kLossBlock];
     const uint32_t cnt = mask_count ? *mask_count : count_host;
@@ -614,13 +615,21 @@ __global__ __launch_bounds__(kLossBlock) void k_loss_l1(
         const int q = y * vd.width + x;
         const size_t plane = (size_t)vd.width * vd.height;
         const float *img = rgba + 4 * (size_t)vd.pix_off;
-        const float *tgt = target + 3 * (size_t)vd.pix_off;
+        const float *tgt = target + (size_t)tgt_planes * vd.pix_off;
         float *g = dl + 4 * (size_t)vd.pix_off;
         const bool in = in_fovea(gaze, v, x, y, radius_frac * (float)vd.width);
         const float inv = 1.f / (float)max(cnt, 1u);
+        // RGBA targets: colour premultiplied, composited over the view background
+        const float ta = tgt_planes == 4 ? tgt[3 * plane + q] : 1.f;
 #pragma unroll
-        for (int c = 0; c < 3; c++) {
-            const float d = img[c * plane + q] - tgt[c * plane + q];
+        for (int c = 0; c < 4; c++) {
+            if (c == 3 && !alpha_term) {
+                g[3 * plane + q] = 0.f;
+                continue;
+            }
+            float t = tgt[c * plane + q];
+            if (c < 3 && bg) t = fmaf(1.f - ta, bg[3 * v + c], t);
+            const float d = img[c * plane + q] - t;
             float gv = 0.f;
             if (in) {
                 s += fabsf(d);
@@ -628,7 +637,6 @@ __global__ __launch_bounds__(kLossBlock) void k_loss_l1(
             }
             g[c * plane + q] = gv;
         }
-        g[3 * plane + q] = 0.f;
     }
     s_red[threadIdx.x] = s;
     __syncthreads();
@@ -664,6 +672,23 @@ __global__ __launch_bounds__(1024) void k_loss_final(const float *__restrict__ p
     }
 }
 
+// Per-view random background: SplitMix64 (Steele, Lea and Flood, OOPSLA 2014)
+// output k = 1 + (step * kMaxViews + v) * 4 + c from state seed, i.e. the
+// state seed + k * golden-ratio increment passed through the published
+// finaliser; the top 24 bits scaled to [0, 1) (exact in float).
+__global__ void k_draw_bg(uint64_t seed, const int32_t *__restrict__ step, int nviews,
+                          float *__restrict__ bg) {
+    const int e = threadIdx.x;
+    if (e >= 3 * nviews) return;
+    const int v = e / 3, c = e - 3 * v;
+    const uint64_t k = 1ull + ((uint64_t)step[0] * kMaxViews + (uint64_t)v) * 4ull + (uint64_t)c;
+    uint64_t z = seed + k * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    bg[e] = (float)(uint32_t)(z >> 40) * (1.f / 16777216.f);
+}
+
 __global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t value) {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
          e += (int64_t)gridDim.x * blockDim.x)
@@ -683,15 +708,15 @@ void render_fwd_tb(hipStream_t s, const RenderArgs &a, float *out) {
     if (a.t_mode == 1)
         k_render_fwd<T, B, 1><<<g, NT, 0, s>>>(a.order, a.ranges, a.vals, a.sp, a.views,
                                               a.nviews, a.cams, out, a.tfinal, a.ncontrib, a.ckpt,
-                                              a.fstate, nullptr, a.cull_gaze, a.cull_radius);
+                                              a.fstate, nullptr, a.bg, a.cull_gaze, a.cull_radius);
     else if (a.t_mode == 2)
         k_render_fwd<T, B, 2><<<g, NT, 0, s>>>(a.order, a.ranges, a.vals, a.sp, a.views,
                                               a.nviews, a.cams, out, a.tfinal, a.ncontrib, nullptr,
-                                              nullptr, a.tstore, a.cull_gaze, a.cull_radius);
+                                              nullptr, a.tstore, a.bg, a.cull_gaze, a.cull_radius);
     else
         k_render_fwd<T, B, 0><<<g, NT, 0, s>>>(a.order, a.ranges, a.vals, a.sp, a.views,
                                               a.nviews, a.cams, out, a.tfinal, a.ncontrib, nullptr,
-                                              nullptr, nullptr, a.cull_gaze, a.cull_radius);
+                                              nullptr, nullptr, a.bg, a.cull_gaze, a.cull_radius);
 }
 
 template <int T, int B>
@@ -700,16 +725,16 @@ void render_bwd_tb(hipStream_t s, const RenderArgs &a, const float *dl, float *g
     if (a.t_mode == 1)
         k_render_bwd_ckpt<T, B><<<a.bwd_grid, NT, 0, s>>>(a.ranges, a.total_tiles, a.m_dev, a.m_host,
                                                          a.vals, a.sp, a.views, a.nviews, a.cams,
-                                                         a.tfinal, a.ncontrib, a.fstate, a.ckpt, dl,
-                                                         g2d, a.nrec);
+                                                         a.tfinal, a.ncontrib, a.fstate, a.ckpt, a.bg,
+                                                         dl, g2d, a.nrec);
     else if (a.t_mode == 2)
         k_render_bwd<T, B, 2><<<a.total_tiles, NT, 0, s>>>(a.order, a.ranges, a.vals, a.sp,
                                                         a.views, a.nviews, a.cams, a.tfinal,
-                                                        a.ncontrib, a.tstore, dl, g2d, a.nrec);
+                                                        a.ncontrib, a.tstore, a.bg, dl, g2d, a.nrec);
     else
         k_render_bwd<T, B, 0><<<a.total_tiles, NT, 0, s>>>(a.order, a.ranges, a.vals, a.sp,
                                                         a.views, a.nviews, a.cams, a.tfinal,
-                                                        a.ncontrib, nullptr, dl, g2d, a.nrec);
+                                                        a.ncontrib, nullptr, a.bg, dl, g2d, a.nrec);
 }
 
 template <int T>
@@ -757,19 +782,25 @@ int loss_partials(int64_t total_pix) { return (int)((total_pix + kLossBlock - 1)
 void launch_loss_l1(hipStream_t s, const float *rgba, const float *target, const float *gaze,
                     float radius_frac, const ViewDesc *views, int nviews, int64_t total_pix,
                     float *dl, float *partial, uint32_t *mask_count, float *loss, uint32_t *flags,
-                    int32_t *step_inc, int box, int tile) {
+                    int32_t *step_inc, int box, int tile, int tgt_planes, bool alpha_term,
+                    const float *bg) {
     if (!gaze) box = 0;
+    const uint32_t channels = alpha_term ? 4u : 3u;
     const int nb = loss_partials(box ? (int64_t)nviews * box * box : total_pix);
     if (gaze) {
         k_fill_u32<<<1, 64, 0, s>>>(mask_count, 1, 0u);
         k_loss_count<<<nb, kLossBlock, 0, s>>>(gaze, radius_frac, views, nviews, total_pix, box, tile,
-                                               mask_count);
+                                               channels, mask_count);
     }
     const uint32_t *mc = gaze ? mask_count : nullptr;
-    const uint32_t cnt = (uint32_t)(3 * total_pix);
+    const uint32_t cnt = (uint32_t)(channels * total_pix);
     k_loss_l1<<<nb, kLossBlock, 0, s>>>(rgba, target, gaze, radius_frac, views, nviews, total_pix, box,
-                                        tile, mc, cnt, dl, partial);
+                                        tile, tgt_planes, alpha_term, bg, mc, cnt, dl, partial);
     k_loss_final<<<1, 1024, 0, s>>>(partial, nb, mc, cnt, loss, flags, step_inc);
+}
+
+void launch_draw_bg(hipStream_t s, uint64_t seed, const int32_t *step, int nviews, float *bg) {
+    k_draw_bg<<<1, 3 * kMaxViews, 0, s>>>(seed, step, nviews, bg);
 }
 
 void launch_fill_u32(hipStream_t s, uint32_t *p, int64_t n, uint32_t value) {

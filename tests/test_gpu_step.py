@@ -306,3 +306,80 @@ def test_fovea_culling_matches_full_frame(gs, ctx):
         off += c.npix
     L, _ = oracle.loss_l1(imgs, tg, cams, gazes=gaze.astype(np.float64), radius_frac=0.2)
     assert abs(l1 - L) <= 1e-5 * L
+
+
+def _rgba_targets(cams):
+    Pt = synth.random_gaussians(300, seed=synth.SEED_TARGET_SET)
+    return [oracle.render(Pt, c).rgba for c in cams]
+
+
+def test_rgba_loss_over_background_matches_oracle(gs, ctx):
+    P = synth.random_gaussians(300, seed=31)
+    cams = [synth.look_at_camera([0.3, -0.2, -3.0], width=80, height=64),
+            synth.look_at_camera([2.0, 1.0, 1.5], width=56, height=72)]
+    sc = GpuScene(ctx, P, cams)
+    imgs = sc.forward()
+    tg = _rgba_targets(cams)
+    bg = np.array([[0.9, 0.1, 0.4], [0.2, 0.7, 0.5]], np.float32)
+    gaze = synth.gaze_points(cams, seed=6)
+    for alpha in (True, False):
+        for gz in (None, gaze):
+            loss = torch.zeros(1, device=DEV)
+            dl = torch.zeros(4 * sum(c.npix for c in cams), device=DEV)
+            t = torch.from_numpy(np.concatenate([x.astype(np.float32).reshape(-1) for x in tg])).to(DEV)
+            sc.plan.loss_l1_rgba(sc.rgba, t, loss, dl, bg=torch.from_numpy(bg).to(DEV), alpha=alpha,
+                                 gaze=None if gz is None else torch.from_numpy(gz).to(DEV),
+                                 radius_frac=0.2 if gz is not None else 0.0)
+            torch.cuda.synchronize()
+            L, dls = oracle.loss_l1_rgba([i.astype(np.float64) for i in imgs],
+                                         [x.astype(np.float32).astype(np.float64) for x in tg], cams,
+                                         bgs=bg.astype(np.float64), alpha=alpha,
+                                         gazes=None if gz is None else gz.astype(np.float64),
+                                         radius_frac=0.2)
+            assert abs(loss.item() - L) <= 1e-5 * L
+            np.testing.assert_allclose(dl.cpu().numpy(), np.concatenate([d.reshape(-1) for d in dls]),
+                                       rtol=1e-6, atol=0)
+
+
+def test_alpha_training_with_random_backgrounds(gs, ctx):
+    """The fused step with alpha training over random backgrounds: the drawn
+    backgrounds are the SplitMix64 values of the step number, and loss and
+    gradient equal the oracle's for the scene rendered over them; captured
+    replays draw each step's own backgrounds."""
+    P = synth.random_gaussians(400, seed=32)
+    P[10] -= 1.0      # lower opacities: no pixel near a threshold (checked below), so every
+    #                   pixel's sign gradient can be compared as is
+    cams = [synth.look_at_camera([0.3, -0.2, -3.0], width=96, height=80),
+            synth.look_at_camera([2.5, 1.0, 1.0], width=64, height=48)]
+    tg = _rgba_targets(cams)
+    tgt = torch.from_numpy(np.concatenate([x.astype(np.float32).reshape(-1) for x in tg])).to(DEV)
+    seed = 0x5EED1234ABCD
+    cfg = gs.FitConfig(lr=0.0, tile=16, lds_batch=64, alpha_loss=True, random_bg=True, bg_seed=seed)
+    fs = gs.FitStep(ctx, torch.from_numpy(P).to(DEV), cams, tgt, cfg=cfg, fused=True)
+    for step in range(2):
+        fs.step()
+        torch.cuda.synchronize()
+        bg = fs.backgrounds()
+        expect = oracle.background_draw(seed, step, len(cams))
+        np.testing.assert_array_equal(bg.astype(np.float64), expect)
+        ocams = [synth.Camera(**{**c.__dict__, "bg": expect[v].astype(np.float32)})
+                 for v, c in enumerate(cams)]
+        refs = [oracle.render(P, c) for c in ocams]
+        L, dls = oracle.loss_l1_rgba([r.rgba for r in refs],
+                                     [x.astype(np.float32).astype(np.float64) for x in tg], ocams,
+                                     bgs=expect, alpha=True)
+        log(f"[alpha] step {step}: bg {bg.tolist()}, loss {fs.loss.item():.6f} vs {L:.6f}")
+        assert abs(fs.loss.item() - L) <= 1e-5 * L
+        assert all((r.flags == 0).all() for r in refs)
+        G = sum(oracle.backward(P, c, d) for c, d in zip(ocams, dls))
+        rep = grads_close(fs.grads.cpu().numpy(), G)
+        assert all(nb == 0 for _, nb, _ in rep), rep
+    # captured (on a stream of its own): each replay draws its own step's backgrounds
+    with torch.cuda.stream(torch.cuda.Stream()):
+        fs.capture()
+        for step in range(2, 5):
+            fs.replay()
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(fs.backgrounds().astype(np.float64),
+                                          oracle.background_draw(seed, step, len(cams)))
+    fs.plan.close()
