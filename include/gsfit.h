@@ -224,6 +224,40 @@ gsf_status gsf_step_capture(gsf_plan *plan, const gsf_step_args *args);
 /* Launch the captured graph once on the context stream. */
 gsf_status gsf_step_replay(gsf_plan *plan);
 
+/* ---- the CT volume on the device --------------------------------------------------- */
+
+/* Seeding (Method, "Periphery Model Training": the model starts from Gaussians
+ * placed on the volume's structures).  vol: device uint16 [n][n][n] (C order,
+ * spanning [-1, 1]^3, voxel centres at (idx + 1/2) 2/n - 1).  One Gaussian per
+ * voxel with value > threshold, in raster order; above cap candidates, the cap
+ * with the smallest priority are kept (priority of flat index idx: SplitMix64
+ * output idx + 1 from state seed with its low b bits replaced by idx, b = bits
+ * of n^3 - 1), still in raster order.  Each: mean = voxel centre, log-scale
+ * ln(2/n) on all axes, rotation (1, 0, 0, 0), opacity logit ln(o / (1 - o)),
+ * degree-0 SH (col - 1/2) / Y00 with col = lo (1 - t) + hi t, t = clamp((v -
+ * threshold) / range, 0, 1); computed in double, rounded once to float.
+ * params: device float with room for 14 * cap values, written planar [14][m];
+ * *count (host) = m = min(candidates, cap).  scratch: device memory of
+ * gsf_seed_scratch_bytes(n) bytes.  Synchronises the context stream. */
+gsf_status gsf_seed_scratch_bytes(int32_t n, size_t *bytes);
+gsf_status gsf_seed_volume(gsf_ctx *ctx, const uint16_t *vol, int32_t n, double threshold,
+                           double range, const double *lo, const double *hi, double opacity,
+                           int64_t cap, uint64_t seed, float *params, int64_t *count,
+                           void *scratch, size_t scratch_bytes);
+
+/* Emission-absorption ray march of the volume for n_views cameras (Method,
+ * "Volumetric Path Tracing"; the fit's target images): float32, segments of
+ * `step` world units from the entry into [-1, 1]^3 (the last shortened), the
+ * trilinear sample (zero outside the grid) at each midpoint, density t as in
+ * gsf_seed_volume, colour lo (1 - t) + hi t (host float[3]), alpha = 1 -
+ * exp(-extinction t length), stopping once T < t_stop.  out: device RGBA per
+ * view [4][H][W] (views concatenated) = C + T bg, 1 - T.  widths/heights
+ * (host) must match the cameras.  Asynchronous on the context stream. */
+gsf_status gsf_raymarch(gsf_ctx *ctx, const uint16_t *vol, int32_t n, const gsf_camera *cams,
+                        int32_t n_views, const int32_t *widths, const int32_t *heights, float step,
+                        float extinction, float t_stop, float threshold, float range,
+                        const float *lo, const float *hi, float *out_rgba);
+
 /* ---- diagnostics ---------------------------------------------------------------- */
 
 /* Per-stage GPU timing of eager calls on a plan (hipEvents recorded around each

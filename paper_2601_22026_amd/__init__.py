@@ -400,6 +400,51 @@ class FitStep:
         return flags, m
 
 
+def seed_volume(ctx: Context, vol: torch.Tensor, cap: int, seed: int, threshold: float = 1200.0,
+                range_: float = 1800.0, lo=(0.8, 0.3, 0.2), hi=(1.0, 0.95, 0.9),
+                opacity: float = 0.1) -> torch.Tensor:
+    """Gaussians seeded on the device from a uint16 volume [n][n][n] (one per
+    voxel above the threshold, capped by a seeded priority subset): planar
+    float32 [14][m] (see gsf_seed_volume).  Synchronises."""
+    n = int(vol.shape[0])
+    assert vol.dtype == torch.int16 or vol.dtype == torch.uint16 or vol.element_size() == 2
+    nb = ct.c_size_t()
+    ctx.check(lib().gsf_seed_scratch_bytes(n, ct.byref(nb)), "gsf_seed_scratch_bytes")
+    scratch = torch.empty(max(int(nb.value), 256), dtype=torch.uint8, device=vol.device)
+    out = torch.empty(14 * int(cap), dtype=torch.float32, device=vol.device)
+    m = ct.c_int64()
+    lo_a, hi_a = (ct.c_double * 3)(*lo), (ct.c_double * 3)(*hi)
+    ctx.use_stream()
+    ctx.check(lib().gsf_seed_volume(ctx.handle, _ptr(vol), n, float(threshold), float(range_), lo_a,
+                                    hi_a, float(opacity), int(cap), int(seed) & ((1 << 64) - 1),
+                                    _ptr(out), ct.byref(m), _ptr(scratch), nb.value),
+              "gsf_seed_volume")
+    return out[:14 * m.value].view(14, m.value)
+
+
+def raymarch(ctx: Context, vol: torch.Tensor, cams, step: Optional[float] = None,
+             extinction: float = 40.0, t_stop: float = 1e-4, threshold: float = 1200.0,
+             range_: float = 1800.0, lo=(0.8, 0.3, 0.2), hi=(1.0, 0.95, 0.9),
+             out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Emission-absorption RGBA of the volume for each camera (float32 [4][H][W]
+    per view, concatenated); step defaults to half a voxel (1/n)."""
+    n = int(vol.shape[0])
+    cams = list(cams)
+    sizes = [(c.width, c.height) for c in cams]
+    if out is None:
+        out = torch.empty(4 * sum(w * h for w, h in sizes), dtype=torch.float32, device=vol.device)
+    cams_dev = cameras_to_device(cams, vol.device)
+    w = (ct.c_int32 * len(cams))(*[a for a, _ in sizes])
+    h = (ct.c_int32 * len(cams))(*[b for _, b in sizes])
+    ctx.use_stream()
+    ctx.check(lib().gsf_raymarch(ctx.handle, _ptr(vol), n, _ptr(cams_dev), len(cams), w, h,
+                                 float(step if step is not None else 1.0 / n), float(extinction),
+                                 float(t_stop), float(threshold), float(range_),
+                                 (ct.c_float * 3)(*lo), (ct.c_float * 3)(*hi), _ptr(out)),
+              "gsf_raymarch")
+    return out
+
+
 _TUNE_CACHE: dict = {}
 
 

@@ -24,7 +24,8 @@ EXPORTED = ["gsf_ctx_create", "gsf_ctx_destroy", "gsf_ctx_set_stream", "gsf_last
             "gsf_plan_info", "gsf_plan_destroy", "gsf_forward", "gsf_loss_l1", "gsf_backward",
             "gsf_adam", "gsf_step", "gsf_step_capture", "gsf_step_replay", "gsf_poll",
             "gsf_debug_copy", "gsf_plan_set_timing", "gsf_plan_stage_times",
-            "gsf_count_pairs", "gsf_loss_l1_rgba"]
+            "gsf_count_pairs", "gsf_loss_l1_rgba", "gsf_seed_scratch_bytes",
+            "gsf_seed_volume", "gsf_raymarch"]
 STAGES = ["project", "duplicate", "tile_sort", "ranges", "depth_sort", "render", "loss",
           "render_bwd", "project_bwd", "adam", "zero"]
 
@@ -90,6 +91,12 @@ def _declare(L):
         "gsf_plan_set_timing": [vp, ct.c_int],
         "gsf_count_pairs": [vp, ct.POINTER(ct.c_int64)],
         "gsf_plan_stage_times": [vp, ct.POINTER(ct.c_double), ct.POINTER(ct.c_int64)],
+        "gsf_seed_scratch_bytes": [i32, ct.POINTER(ct.c_size_t)],
+        "gsf_seed_volume": [vp, vp, i32, ct.c_double, ct.c_double, ct.POINTER(ct.c_double),
+                            ct.POINTER(ct.c_double), ct.c_double, i64, ct.c_uint64, vp,
+                            ct.POINTER(ct.c_int64), vp, ct.c_size_t],
+        "gsf_raymarch": [vp, vp, i32, vp, i32, ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int32), f32,
+                         f32, f32, f32, f32, ct.POINTER(ct.c_float), ct.POINTER(ct.c_float), vp],
     }
     for name, args in sig.items():
         fn = getattr(L, name)

@@ -192,6 +192,17 @@ void launch_draw_bg(hipStream_t s, uint64_t seed, const int32_t *step, int nview
 void launch_adam(hipStream_t s, float *p, const float *g, float *m, float *v, int64_t n,
                  const SegTable &seg, float b1, float b2, float eps, int32_t *step, bool advance);
 
+// Seeding from a device volume (synchronises); scratch: seed_scratch_bytes(n^3).
+hipError_t run_seed(hipStream_t s, const uint16_t *vol, int n, double thr, double range,
+                    const double *lo, const double *hi, double opacity, int64_t cap, uint64_t seed,
+                    float *params, int64_t *count, void *scratch);
+size_t seed_scratch_bytes(int64_t nvox);
+// Emission-absorption targets of n_views cameras (asynchronous).
+hipError_t run_raymarch(hipStream_t s, const uint16_t *vol, int n, const gsf_camera *cams, int nviews,
+                        const int32_t *widths, const int32_t *heights, float step, float extinction,
+                        float t_stop, float thr, float range, const float *lo, const float *hi,
+                        float *out);
+
 void launch_fill_u32(hipStream_t s, uint32_t *p, int64_t n, uint32_t value);
 void launch_fill_f32(hipStream_t s, float *p, int64_t n, float value);
 

@@ -635,6 +635,49 @@ gsf_status gsf_backward(gsf_plan *p, const float *params, int64_t n, const gsf_c
     return enqueue_backward(p, params, n, cams, dl_drgba, grads);
 }
 
+gsf_status gsf_seed_scratch_bytes(int32_t n, size_t *bytes) {
+    if (!bytes || n < 1 || n > 2048) return GSF_E_INVALID;
+    *bytes = seed_scratch_bytes((int64_t)n * n * n);
+    return GSF_OK;
+}
+
+gsf_status gsf_seed_volume(gsf_ctx *ctx, const uint16_t *vol, int32_t n, double threshold,
+                           double range, const double *lo, const double *hi, double opacity,
+                           int64_t cap, uint64_t seed, float *params, int64_t *count,
+                           void *scratch, size_t scratch_bytes) {
+    if (!ctx) return GSF_E_INVALID;
+    if (!vol || !lo || !hi || !params || !count || !scratch)
+        return fail(ctx, GSF_E_INVALID, "gsf_seed_volume: null argument");
+    if (n < 1 || n > 2048) return fail(ctx, GSF_E_INVALID, "gsf_seed_volume: n must lie in [1, 2048]");
+    if (cap < 1) return fail(ctx, GSF_E_INVALID, "gsf_seed_volume: cap must be positive");
+    if (!(range > 0.0)) return fail(ctx, GSF_E_INVALID, "gsf_seed_volume: range must be positive");
+    if (!(opacity > 0.0 && opacity < 1.0)) return fail(ctx, GSF_E_INVALID, "gsf_seed_volume: opacity must lie in (0, 1)");
+    if (scratch_bytes < seed_scratch_bytes((int64_t)n * n * n))
+        return fail(ctx, GSF_E_INVALID, "gsf_seed_volume: scratch too small");
+    GSF_HIP(ctx, run_seed(ctx->stream, vol, n, threshold, range, lo, hi, opacity, cap, seed, params,
+                          count, scratch));
+    return GSF_OK;
+}
+
+gsf_status gsf_raymarch(gsf_ctx *ctx, const uint16_t *vol, int32_t n, const gsf_camera *cams,
+                        int32_t n_views, const int32_t *widths, const int32_t *heights, float step,
+                        float extinction, float t_stop, float threshold, float range,
+                        const float *lo, const float *hi, float *out_rgba) {
+    if (!ctx) return GSF_E_INVALID;
+    if (!vol || !cams || !widths || !heights || !lo || !hi || !out_rgba)
+        return fail(ctx, GSF_E_INVALID, "gsf_raymarch: null argument");
+    if (n < 1 || n > 2048 || n_views < 1 || n_views > kMaxViews)
+        return fail(ctx, GSF_E_INVALID, "gsf_raymarch: n or n_views out of range");
+    for (int v = 0; v < n_views; v++)
+        if (widths[v] < 1 || heights[v] < 1 || widths[v] > 8192 || heights[v] > 8192)
+            return fail(ctx, GSF_E_INVALID, "gsf_raymarch: image size out of range");
+    if (!(step > 0.f) || !(range > 0.f) || !(t_stop >= 0.f) || !(extinction >= 0.f))
+        return fail(ctx, GSF_E_INVALID, "gsf_raymarch: step, range, extinction or t_stop invalid");
+    GSF_HIP(ctx, run_raymarch(ctx->stream, vol, n, cams, n_views, widths, heights, step, extinction,
+                              t_stop, threshold, range, lo, hi, out_rgba));
+    return GSF_OK;
+}
+
 gsf_status gsf_adam(gsf_ctx *ctx, float *prm, const float *g, float *m, float *v, int64_t n_elems,
                     const int64_t *seg_off, const float *seg_lr, int32_t n_seg, float beta1,
                     float beta2, float eps, int32_t *step_dev) {

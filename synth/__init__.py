@@ -263,18 +263,41 @@ def tf_colour(t):
     return TF_LO * (1.0 - t) + TF_HI * t
 
 
+def _splitmix64(state: int, k: np.ndarray) -> np.ndarray:
+    """Outputs k (uint64 array, k >= 1) of SplitMix64 (Steele, Lea and Flood,
+    OOPSLA 2014) from state ``state``: state + k * golden-ratio increment
+    through the published finaliser (uint64 arithmetic wraps)."""
+    z = np.uint64(state) + k.astype(np.uint64) * np.uint64(0x9E3779B97F4A7C15)
+    z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+    z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+    return z ^ (z >> np.uint64(31))
+
+
+def cap_priority(idx: np.ndarray, seed: int, nvox: int) -> np.ndarray:
+    """Priority of voxel ``idx`` for the seeding cap: SplitMix64 output idx + 1
+    from state ``seed`` with its low b bits replaced by idx (b = bits of
+    nvox - 1), so priorities are distinct; the cap smallest are kept."""
+    b = np.uint64(max(1, int(nvox - 1).bit_length()))
+    idx = np.asarray(idx, np.uint64)
+    with np.errstate(over="ignore"):
+        h = _splitmix64(seed, idx + np.uint64(1))
+    return ((h >> b) << b) | idx
+
+
 def seed_from_volume(vol: np.ndarray, threshold: float = TF_THRESHOLD, cap: int = 50_000,
                      seed: int = SEED_CAP_SUBSET, opacity: float = 0.1) -> np.ndarray:
     """One Gaussian per voxel above ``threshold`` (raster order), capped by a
-    seeded uniform subset without replacement (kept in raster order).  Mean at
+    seeded uniform subset without replacement (the candidates of smallest
+    ``cap_priority``, kept in raster order).  Mean at
     the voxel centre, isotropic scale of one voxel, identity rotation, the
     given initial opacity and the transfer-function colour as degree-0 SH."""
     n = vol.shape[0]
     flat = vol.reshape(-1)
     idx = np.nonzero(flat > threshold)[0]
     if idx.size > cap:
-        pick = _rng(seed).choice(idx.size, size=cap, replace=False)
-        idx = idx[np.sort(pick)]
+        # the cap candidates of smallest priority (a seeded uniform subset)
+        pri = cap_priority(idx, seed, flat.size)
+        idx = np.sort(idx[np.argsort(pri, kind="stable")[:cap]])
     ix, iy, iz = np.unravel_index(idx, vol.shape)
     c = voxel_centres(n)
     m = idx.size

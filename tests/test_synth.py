@@ -46,6 +46,30 @@ def test_phantom_and_seeding():
     assert np.all(np.abs(P[0:3]) < 1)
 
 
+def test_cap_subset_is_the_smallest_splitmix_priorities():
+    """The seeding cap keeps the candidates of smallest priority: SplitMix64
+    outputs (first output from state 0 as published: 0xE220A8397B1DCDAF) with
+    the low bits replaced by the voxel index - distinct, so the kept set is
+    exactly determined - in raster order."""
+    pri = synth.cap_priority(np.array([0]), 0, 2)
+    assert int(pri[0]) == 0xE220A8397B1DCDAF & ~1
+    vol = synth.phantom(24, seed=3)
+    flat = vol.reshape(-1)
+    cand = np.nonzero(flat > synth.TF_THRESHOLD)[0]
+    cap = cand.size // 3
+    P = synth.seed_from_volume(vol, cap=cap, seed=9)
+    pr = synth.cap_priority(cand, 9, flat.size)
+    assert np.unique(pr).size == pr.size
+    keep = np.sort(cand[np.argsort(pr)[:cap]])
+    c = synth.voxel_centres(24)
+    ix, iy, iz = np.unravel_index(keep, vol.shape)
+    np.testing.assert_array_equal(P[0], c[ix].astype(np.float32))
+    np.testing.assert_array_equal(P[1], c[iy].astype(np.float32))
+    np.testing.assert_array_equal(P[2], c[iz].astype(np.float32))
+    # a cap above the candidate count keeps them all
+    assert synth.seed_from_volume(vol, cap=cand.size + 5, seed=9).shape[1] == cand.size
+
+
 def test_raymarch_constant_slab_closed_form():
     """Constant density in the box: A = 1 - exp(-sigma * L) with L the chord length
     (the midpoint rule is exact for a piecewise-constant medium)."""
