@@ -372,14 +372,15 @@ def main():
                 t_start = time.perf_counter()
                 Ps = gs.seed_volume(ctx, vol_dev, cap=N, seed=synth.SEED_CAP_SUBSET)
                 t_seeded = time.perf_counter()
-                rf = gs.FitStep(ctx, Ps.contiguous(), cams, tgt_dev, gaze_dev, cfg=cfg, fused=True)
+                if not runs:   # the device seeding reproduces the workload's Gaussians
+                    same = bool(torch.equal(Ps.cpu(), torch.from_numpy(P)))
+                rf = gs.FitStep(ctx, Ps, cams, tgt_dev, gaze_dev, cfg=cfg, fused=True)
                 rf.capture()
                 for _ in range(args.regen_steps):
                     rf.replay()
                 torch.cuda.synchronize()
                 runs.append((time.perf_counter() - t_start) * 1e3)
                 seeds.append((t_seeded - t_start) * 1e3)
-                same = bool(torch.equal(Ps.cpu(), torch.from_numpy(P)))
                 rf.plan.close()
                 del rf
             # the targets' ray march on the device, reported apart (S24)
