@@ -7,12 +7,14 @@ Functions follow the plain definitions written out in ``gsorc.c`` (projection by
 the local affine approximation of the pinhole map, brute-force front-to-back
 compositing over all Gaussians in depth order, the exact adjoint, the
 (tile, depth) discrete stage by nested loops and a comparison sort, L1 loss,
-bias-corrected Adam).  Inputs are the float32 arrays produced by ``synth``,
+bias-corrected Adam) and, in Python, the refinement loop's Eq. (1) view
+selection, Gaussian visibility and visibility-masked Adam.  Inputs are the float32 arrays produced by ``synth``,
 widened to float64.
 """
 from __future__ import annotations
 
 import ctypes as ct
+import math
 import os
 import subprocess
 from dataclasses import dataclass
@@ -280,16 +282,89 @@ def adam(p, g, m, v, t, lr=1e-3, betas=(0.9, 0.999), eps=1e-15):
 
 
 def fit_step(params, m, v, t, cams, targets, gazes=None, radius_frac=0.2, lr=1e-3,
-             betas=(0.9, 0.999), eps=1e-15):
+             betas=(0.9, 0.999), eps=1e-15, masked=False, tile=16):
     """One full oracle step (render, L1 loss, adjoint, Adam) on float64 state.
-    Returns the loss; params, m, v are updated in place."""
+    Returns the loss; params, m, v are updated in place.  masked: the
+    visibility-masked Adam of ``adam_masked`` with ``visibility(params, cams,
+    tile)`` taken before the update."""
     rgbas = [render(params, c).rgba for c in cams]
     loss, dls = loss_l1(rgbas, targets, cams, gazes, radius_frac)
     G = np.zeros_like(params)
     for cam, dl in zip(cams, dls):
         G += backward(params, cam, dl)
-    adam(params, G, m, v, t, lr, betas, eps)
+    if masked:
+        adam_masked(params, G, m, v, t, visibility(params, cams, tile), lr, betas, eps)
+    else:
+        adam(params, G, m, v, t, lr, betas, eps)
     return loss
+
+
+# ------------------------------------------------------------ continual refinement
+# Method, "Periphery Model Training": the refinement keeps a set of training
+# views, admits a new foveal view only when Eq. (1) finds it novel against every
+# view already kept, and restarts optimisation from the current Gaussians with
+# the optimiser state discarded (m = v = 0, t = 0).  The visibility-masked
+# update is the sparse Adam of Taming 3DGS, which the paper's optimiser builds on.
+
+def view_pose(cam):
+    """Camera centre and unit viewing direction in world coordinates (FP64).  The
+    viewing direction is the camera's +z axis: the third row of the world-to-
+    camera rotation, normalised."""
+    c = [float(x) for x in np.asarray(cam.campos, np.float64)]
+    d = [float(x) for x in np.asarray(cam.R, np.float64)[2]]
+    norm = math.sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2])
+    return c, [x / norm for x in d]
+
+
+def view_is_novel(pose, kept_poses, delta_pos=0.05, theta_view_deg=5.0) -> bool:
+    """Eq. (1): for every kept view i, the centres lie more than delta_pos apart
+    or the viewing directions' dot product is below cos(theta_view)."""
+    (p, d), cos_t = pose, math.cos(math.radians(theta_view_deg))
+    for q, e in kept_poses:
+        dist = math.sqrt(sum((p[k] - q[k]) ** 2 for k in range(3)))
+        dot = sum(d[k] * e[k] for k in range(3))
+        if not (dist > delta_pos or dot < cos_t):
+            return False
+    return True
+
+
+def select_views(kept, candidates, delta_pos=0.05, theta_view_deg=5.0):
+    """Candidates offered one after another to the kept set (cameras): each one
+    that Eq. (1) finds novel joins the set before the next is tested.  Returns
+    one bool per candidate."""
+    poses = [view_pose(c) for c in kept]
+    out = []
+    for cam in candidates:
+        pose = view_pose(cam)
+        novel = view_is_novel(pose, poses, delta_pos, theta_view_deg)
+        if novel:
+            poses.append(pose)
+        out.append(novel)
+    return out
+
+
+def visibility(params, cams, tile: int = 16) -> np.ndarray:
+    """Gaussians that emit at least one (tile, depth) key in some view: bool [n]."""
+    n = params.shape[1]
+    d = discrete(params, cams, tile)
+    vis = np.zeros(n, bool)
+    vis[d.vals % n] = True
+    return vis
+
+
+def adam_masked(p, g, m, v, t, visible, lr=1e-3, betas=(0.9, 0.999), eps=1e-15):
+    """Visibility-masked Adam on planar float64 state [C][n]: the columns of the
+    visible Gaussians take one bias-corrected Adam step at step number t; the
+    others keep p, m and v.  ``lr``: scalar or per-plane [C]."""
+    C, n = p.shape
+    sel = np.nonzero(np.asarray(visible, bool))[0]
+    if sel.size == 0:
+        return
+    lr_planes = np.broadcast_to(np.asarray(lr, np.float64).reshape(-1, 1), (C, 1))
+    cols = [np.ascontiguousarray(a[:, sel]) for a in (p, g, m, v)]
+    adam(*cols, t, lr=np.ascontiguousarray(np.broadcast_to(lr_planes, cols[0].shape)),
+         betas=betas, eps=eps)
+    p[:, sel], m[:, sel], v[:, sel] = cols[0], cols[2], cols[3]
 
 
 def sh_basis(deg, dirs):
