@@ -15,6 +15,11 @@
  *   gsf_backward  dL/dRGBA -> dL/d(parameters)              (adjoint of the above)
  *   gsf_adam      bias-corrected Adam with per-segment learning rates
  *   gsf_step_*    the four calls above as one captured HIP graph
+ *   continual refinement: gsf_view_select (Eq. (1), host), gsf_adam_reset
+ *                 (restart with discarded optimiser state), gsf_adam_masked
+ *                 and gsf_step_args.masked_adam (visibility-masked update)
+ *   seeding: gsf_seed_volume (Gaussians from a CT volume), gsf_raymarch
+ *                 (emission-absorption target images)
  *
  * Conventions shared by every call
  * --------------------------------
@@ -23,8 +28,9 @@
  *   targets, cameras, workspace).  The library owns only the opaque host-side
  *   context and plan objects and the graphs it instantiates.
  * - Every call is asynchronous on the context's stream, except gsf_poll,
- *   gsf_debug_copy and (for plans created with host_sized = 1) gsf_forward,
- *   which synchronise that stream.
+ *   gsf_debug_copy, gsf_seed_volume and (for plans created with
+ *   host_sized = 1) gsf_forward, which synchronise that stream, and
+ *   gsf_view_select, which runs on the host only.
  * - Errors: every call returns a gsf_status; no exception crosses the ABI.
  *   Argument errors are detected on the host before anything is enqueued.
  *   Conditions detected on the device (key overflow, non-finite loss) set sticky
@@ -170,6 +176,44 @@ gsf_status gsf_adam(gsf_ctx *ctx, float *p, const float *g, float *m, float *v, 
                     const int64_t *seg_off, const float *seg_lr, int32_t n_seg, float beta1,
                     float beta2, float eps, int32_t *step_dev);
 
+/* Visibility-masked Adam on planar [planes][n] float32 state (p, g, m, v device
+ * arrays, planes in 1..64): for every Gaussian i with visible[i] != 0 (device
+ * uint8 [n]) each plane c takes the Adam step of gsf_adam at plane_lr[c] (host
+ * [planes]); Gaussians with visible[i] == 0 keep p, m and v unchanged (they are
+ * not read or written).  step_dev[0] is incremented first and its new value is
+ * the step number of the bias correction for every Gaussian.  This is the sparse
+ * Adam of Taming 3DGS, which the paper's optimiser adopts (Method, "Periphery
+ * Model Training").  GSF_E_INVALID for null pointers, n < 1, planes out of
+ * range or a non-finite learning rate. */
+gsf_status gsf_adam_masked(gsf_ctx *ctx, float *p, const float *g, float *m, float *v, int64_t n,
+                           int32_t planes, const float *plane_lr, const uint8_t *visible,
+                           float beta1, float beta2, float eps, int32_t *step_dev);
+
+/* Optimiser restart of the continual refinement (Method, "Periphery Model
+ * Training": optimisation restarts from the current Gaussians with the
+ * optimiser state discarded): m[0..n_elems) = v[0..n_elems) = 0 and
+ * step_dev[0] = 0, written by a kernel on the context stream (no memset, so a
+ * captured graph may hold it).  m and v: device, 16-byte aligned. */
+gsf_status gsf_adam_reset(gsf_ctx *ctx, float *m, float *v, int64_t n_elems, int32_t *step_dev);
+
+/* Training-view selection of the continual refinement (Method, "Periphery Model
+ * Training", Eq. (1)).  The candidates are offered in order; candidate j is kept
+ * (keep[j] = 1, else 0) when for every view of the set - the n_set views of
+ * `set`, then the candidates kept before j - the camera centres (campos) lie
+ * more than delta_pos apart or the unit viewing directions d satisfy
+ * d_j . d_i < cos(theta_view_deg).  d is the camera's +z axis in world
+ * coordinates: the third row of viewmat's rotation, normalised.  An empty set
+ * keeps the first candidate.  The paper sets delta_pos = 0.05 (scene units) and
+ * theta_view = 5 degrees.  All arrays are host memory (set may be NULL when
+ * n_set = 0); evaluated on the host in double precision; no context, no device
+ * work.  *n_kept: the number of kept candidates.  GSF_E_INVALID for null
+ * pointers, negative counts, delta_pos < 0 or non-finite, theta outside
+ * [0, 180], or a camera with a zero or non-finite direction or centre (then
+ * nothing is written to keep). */
+gsf_status gsf_view_select(const gsf_camera *set, int32_t n_set, const gsf_camera *cand,
+                           int32_t n_cand, float delta_pos, float theta_view_deg, int32_t *keep,
+                           int32_t *n_kept);
+
 /* Arguments of one full step: forward, loss, backward, Adam on the parameters. */
 typedef struct gsf_step_args {
     float *params;              /* [C][n]; updated in place by Adam */
@@ -203,6 +247,13 @@ typedef struct gsf_step_args {
                                    composited over it as rgb + (1 - alpha) bg.  The
                                    cameras' bg is not used then.  0: the cameras' bg. */
     uint64_t bg_seed;
+    int32_t masked_adam;        /* 1: visibility-masked Adam (the sparse Adam of Taming
+                                   3DGS, on which the paper's optimiser builds): only the
+                                   Gaussians that touched at least one tile in some view
+                                   of this step (with fovea_cull: one of the composited
+                                   tiles) take the Adam update; the others keep their
+                                   parameters, m and v.  Bias correction still uses the
+                                   shared step counter.  0: every Gaussian is updated. */
 } gsf_step_args;
 
 /* L1 of an RGBA prediction against RGBA targets (alpha training): the target
@@ -307,7 +358,8 @@ enum {
                               red, green, blue, camera depth, valid (1 or 0) */
     GSF_DBG_ORDER = 10,    /* uint32 per global tile: compositing order of the tiles (a
                               permutation; tiles with more keys first) */
-    GSF_DBG_BG = 11        /* float [n_views][3]: backgrounds drawn by the last random_bg step */
+    GSF_DBG_BG = 11,       /* float [n_views][3]: backgrounds drawn by the last random_bg step */
+    GSF_DBG_VIS = 12       /* uint8 [n]: Gaussian visibility of the last masked_adam step */
 };
 /* Synchronise and copy an internal buffer of the last forward/backward to host
  * memory (at most cap bytes; bytes copied in *written). */

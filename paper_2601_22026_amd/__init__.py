@@ -27,8 +27,9 @@ import torch
 from . import _abi
 from ._abi import GsfError, gsf_camera, gsf_plan_desc, gsf_step_args, lib
 
-__all__ = ["GsfError", "Context", "Plan", "rasterize", "adam", "FitStep", "FitConfig", "autotune",
-           "pack_cameras", "cameras_to_device", "n_planes", "lib"]
+__all__ = ["GsfError", "Context", "Plan", "rasterize", "adam", "adam_masked", "adam_reset",
+           "FitStep", "FitConfig", "autotune", "select_views", "plane_learning_rates", "Refiner",
+           "seed_volume", "raymarch", "pack_cameras", "cameras_to_device", "n_planes", "lib"]
 
 
 def n_planes(sh_degree: int) -> int:
@@ -243,6 +244,60 @@ def adam(ctx: Context, p, g, m, v, step_dev, seg_off, seg_lr, betas=(0.9, 0.999)
                              _ptr(step_dev)), "gsf_adam")
 
 
+def adam_masked(ctx: Context, p, g, m, v, step_dev, plane_lr, visible, betas=(0.9, 0.999),
+                eps=1e-15):
+    """gsf_adam_masked over planar float32 state [C][n]: only the Gaussians with
+    visible[i] != 0 (device uint8 [n]) are updated; plane c at plane_lr[c]."""
+    C, n = p.shape
+    assert visible.dtype == torch.uint8 and visible.numel() == n
+    lr = (ct.c_float * C)(*[float(x) for x in plane_lr])
+    ctx.use_stream()
+    ctx.check(lib().gsf_adam_masked(ctx.handle, _ptr(p), _ptr(g), _ptr(m), _ptr(v), int(n), int(C),
+                                    lr, _ptr(visible), float(betas[0]), float(betas[1]),
+                                    float(eps), _ptr(step_dev)), "gsf_adam_masked")
+
+
+def adam_reset(ctx: Context, m, v, step_dev):
+    """gsf_adam_reset: m = v = 0 and the step counter = 0 (optimiser restart)."""
+    ctx.use_stream()
+    ctx.check(lib().gsf_adam_reset(ctx.handle, _ptr(m), _ptr(v), int(m.numel()), _ptr(step_dev)),
+              "gsf_adam_reset")
+
+
+def select_views(kept, candidates, delta_pos: float = 0.05, theta_view_deg: float = 5.0):
+    """gsf_view_select (Eq. (1), host only): which candidate cameras join the
+    kept set when offered in order.  Returns one bool per candidate."""
+    kept, candidates = list(kept), list(candidates)
+    if not candidates:
+        return []
+    ks = (gsf_camera * max(len(kept), 1)).from_buffer_copy(
+        pack_cameras(kept) if kept else bytes(ct.sizeof(gsf_camera)))
+    cs = (gsf_camera * len(candidates)).from_buffer_copy(pack_cameras(candidates))
+    keep = (ct.c_int32 * len(candidates))()
+    nk = ct.c_int32()
+    st = lib().gsf_view_select(ks, len(kept), cs, len(candidates), float(delta_pos),
+                               float(theta_view_deg), keep, ct.byref(nk))
+    if st != _abi.GSF_OK:
+        raise GsfError(st, "gsf_view_select: invalid argument")
+    return [bool(x) for x in keep]
+
+
+# Planes whose learning rate the initial fit raises: log-scale (3..5), opacity
+# (10) and colour (11 onwards); the paper raises them by about 50 % (Method,
+# "Periphery Model Training").
+REFINE_LR_BOOST = 1.5
+
+
+def plane_learning_rates(sh_degree: int, lr=1e-3, boost: float = 1.0):
+    """Learning rate per parameter plane: ``lr`` (scalar or per plane), times
+    ``boost`` on the scale, opacity and colour planes."""
+    C = n_planes(sh_degree)
+    base = [float(x) for x in lr] if isinstance(lr, (list, tuple, np.ndarray)) else [float(lr)] * C
+    if len(base) != C:
+        raise ValueError(f"need {C} learning rates, got {len(base)}")
+    return [b * boost if (3 <= c <= 5 or c >= 10) else b for c, b in enumerate(base)]
+
+
 @dataclass
 class FitConfig:
     lr: float | Sequence[float] = 1e-3
@@ -257,6 +312,8 @@ class FitConfig:
     alpha_loss: bool = False  # targets are RGBA ([4][H][W] per view) and the L1 covers alpha
     random_bg: bool = False   # fused step: a new background per view each step (needs alpha_loss)
     bg_seed: int = 0
+    masked_adam: bool = False  # fused step: Adam only for Gaussians that touched a tile this step
+    lr_boost: float = 1.0     # factor on the scale, opacity and colour planes' learning rates
 
 
 class FitStep:
@@ -292,12 +349,13 @@ class FitStep:
         self.v = torch.zeros_like(params)
         self.step_dev = torch.zeros(1, dtype=torch.int32, device=dev)
         self.loss = torch.zeros(1, dtype=torch.float32, device=dev)
-        lr = cfg.lr if isinstance(cfg.lr, (list, tuple)) else [cfg.lr] * self.C
+        lr = plane_learning_rates(self.sh_degree, cfg.lr, cfg.lr_boost)
         self._seg_lr = (ct.c_float * self.C)(*[float(x) for x in lr])
         if cfg.random_bg and not cfg.alpha_loss:
             raise ValueError("random_bg needs alpha_loss (RGBA targets)")
-        if not fused and (cfg.alpha_loss or cfg.random_bg):
-            raise ValueError("alpha training and random backgrounds are fused-step options")
+        if not fused and (cfg.alpha_loss or cfg.random_bg or cfg.masked_adam):
+            raise ValueError("alpha training, random backgrounds and the masked Adam are "
+                             "fused-step options")
         if fused:
             cap = cfg.key_capacity or self._measure_capacity()
             self.plan = Plan(ctx, self.n, self.sizes, self.sh_degree, cfg.tile, cfg.lds_batch,
@@ -335,7 +393,8 @@ class FitStep:
             beta2=self.cfg.betas[1], eps=self.cfg.eps,
             fovea_cull=int(bool(self.cfg.fovea_cull and gaze is not None)),
             alpha_loss=int(bool(self.cfg.alpha_loss)), random_bg=int(bool(self.cfg.random_bg)),
-            bg_seed=int(self.cfg.bg_seed) & ((1 << 64) - 1))
+            bg_seed=int(self.cfg.bg_seed) & ((1 << 64) - 1),
+            masked_adam=int(bool(self.cfg.masked_adam)))
 
     def step(self):
         """One eager step."""
@@ -384,10 +443,26 @@ class FitStep:
         return self.plan.debug(_abi.GSF_DBG_BG, np.float32, 3 * len(self.cams)).reshape(-1, 3)
 
     def reset_optimizer(self):
-        """Continual refinement restarts Adam: zero m, v and the step counter."""
-        self.m.zero_()
-        self.v.zero_()
-        self.step_dev.zero_()
+        """Continual refinement restarts Adam: zero m, v and the step counter
+        (gsf_adam_reset)."""
+        adam_reset(self.ctx, self.m, self.v, self.step_dev)
+
+    def restart(self, params: Optional[torch.Tensor] = None):
+        """Restart optimisation: reload ``params`` (same shape) as the Gaussians,
+        if given, and discard the optimiser state.  A captured graph stays valid
+        (same buffers)."""
+        if params is not None:
+            if tuple(params.shape) != tuple(self.params.shape):
+                raise ValueError("restart: the Gaussian count is fixed by the plan")
+            self.ctx.use_stream()
+            self.params.copy_(params)
+        self.reset_optimizer()
+
+    def visibility(self):
+        """Per-Gaussian visibility (uint8 [n]) of the last masked_adam step."""
+        if not (self.fused and self.cfg.masked_adam):
+            raise GsfError(_abi.GSF_E_STATE, "no masked Adam in this step")
+        return self.plan.debug(_abi.GSF_DBG_VIS, np.uint8, self.n)
 
     def poll(self):
         if self.fused:
@@ -398,6 +473,69 @@ class FitStep:
             flags |= f
             m += mm
         return flags, m
+
+
+class Refiner:
+    """Continual refinement by restart (Method, "Periphery Model Training").
+
+    Holds the training views (cameras, per-view targets, optional gaze points).
+    ``offer`` admits a new view only when Eq. (1) finds it novel against every
+    kept view (gsf_view_select).  ``restart`` builds the fused, captured step
+    over all kept views (at most 64), starting from the current Gaussians with
+    the optimiser state discarded; ``run`` replays it.  Either every view has a
+    gaze point (fovea-masked loss) or none has.
+    """
+
+    def __init__(self, ctx: Context, params: torch.Tensor, cams, targets, gazes=None,
+                 cfg: FitConfig = FitConfig(), delta_pos: float = 0.05,
+                 theta_view_deg: float = 5.0):
+        self.ctx, self.cfg = ctx, cfg
+        self.params = params
+        self.delta_pos, self.theta_view_deg = float(delta_pos), float(theta_view_deg)
+        self.cams = list(cams)
+        self.targets = [t.reshape(-1) for t in targets]
+        if len(self.targets) != len(self.cams):
+            raise ValueError("one target per camera")
+        self.gazes = None if gazes is None else [np.asarray(g, np.float32).reshape(2) for g in gazes]
+        self.fit: Optional[FitStep] = None
+        self.pending = 0          # views admitted since the last restart
+
+    def offer(self, cam, target: torch.Tensor, gaze=None) -> bool:
+        """Eq. (1): keep the view if it is novel against every kept view."""
+        if (gaze is None) != (self.gazes is None):
+            raise ValueError("either every view has a gaze point or none has")
+        if not select_views(self.cams, [cam], self.delta_pos, self.theta_view_deg)[0]:
+            return False
+        self.cams.append(cam)
+        self.targets.append(target.reshape(-1))
+        if gaze is not None:
+            self.gazes.append(np.asarray(gaze, np.float32).reshape(2))
+        self.pending += 1
+        return True
+
+    def restart(self) -> FitStep:
+        """Fused step over every kept view from the current Gaussians, Adam state
+        discarded (new zero moments and step counter), captured in a graph."""
+        if len(self.cams) > 64:
+            raise GsfError(_abi.GSF_E_INVALID, "at most 64 views per fused step")
+        if self.fit is not None:
+            self.fit.plan.close()
+        dev = self.params.device
+        tgt = torch.cat(self.targets)
+        gz = None
+        if self.gazes is not None:
+            gz = torch.from_numpy(np.stack(self.gazes)).to(dev)
+        self.fit = FitStep(self.ctx, self.params, self.cams, tgt, gz, cfg=self.cfg, fused=True)
+        self.fit.reset_optimizer()
+        self.fit.capture()
+        self.pending = 0
+        return self.fit
+
+    def run(self, steps: int):
+        if self.fit is None:
+            raise GsfError(_abi.GSF_E_STATE, "restart() first")
+        for _ in range(int(steps)):
+            self.fit.replay()
 
 
 def seed_volume(ctx: Context, vol: torch.Tensor, cap: int, seed: int, threshold: float = 1200.0,

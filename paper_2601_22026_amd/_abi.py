@@ -17,7 +17,8 @@ STATUS_NAMES = {0: "GSF_OK", 1: "GSF_E_INVALID", 2: "GSF_E_CAPACITY", 3: "GSF_E_
 GSF_FLAG_CAPACITY = 1
 GSF_FLAG_NONFINITE = 2
 (GSF_DBG_RECT, GSF_DBG_COUNT, GSF_DBG_DEPTH, GSF_DBG_KEYS, GSF_DBG_VALS, GSF_DBG_RANGES,
- GSF_DBG_TFINAL, GSF_DBG_NCONTRIB, GSF_DBG_G2D, GSF_DBG_PROJ, GSF_DBG_ORDER, GSF_DBG_BG) = range(12)
+ GSF_DBG_TFINAL, GSF_DBG_NCONTRIB, GSF_DBG_G2D, GSF_DBG_PROJ, GSF_DBG_ORDER, GSF_DBG_BG,
+ GSF_DBG_VIS) = range(13)
 
 EXPORTED = ["gsf_ctx_create", "gsf_ctx_destroy", "gsf_ctx_set_stream", "gsf_last_error",
             "gsf_plan_create", "gsf_plan_workspace_bytes", "gsf_plan_bind_workspace",
@@ -25,7 +26,8 @@ EXPORTED = ["gsf_ctx_create", "gsf_ctx_destroy", "gsf_ctx_set_stream", "gsf_last
             "gsf_adam", "gsf_step", "gsf_step_capture", "gsf_step_replay", "gsf_poll",
             "gsf_debug_copy", "gsf_plan_set_timing", "gsf_plan_stage_times",
             "gsf_count_pairs", "gsf_loss_l1_rgba", "gsf_seed_scratch_bytes",
-            "gsf_seed_volume", "gsf_raymarch"]
+            "gsf_seed_volume", "gsf_raymarch", "gsf_adam_masked", "gsf_adam_reset",
+            "gsf_view_select"]
 STAGES = ["project", "duplicate", "tile_sort", "ranges", "depth_sort", "render", "loss",
           "render_bwd", "project_bwd", "adam", "zero"]
 
@@ -59,7 +61,7 @@ class gsf_step_args(ct.Structure):
                 ("adam_v", ct.c_void_p), ("step_dev", ct.c_void_p),
                 ("seg_lr", ct.POINTER(ct.c_float)), ("beta1", ct.c_float), ("beta2", ct.c_float),
                 ("eps", ct.c_float), ("fovea_cull", ct.c_int32), ("alpha_loss", ct.c_int32),
-                ("random_bg", ct.c_int32), ("bg_seed", ct.c_uint64)]
+                ("random_bg", ct.c_int32), ("bg_seed", ct.c_uint64), ("masked_adam", ct.c_int32)]
 
 
 assert ct.sizeof(gsf_camera) == 128
@@ -83,6 +85,11 @@ def _declare(L):
         "gsf_backward": [vp, vp, i64, vp, vp, vp],
         "gsf_adam": [vp, vp, vp, vp, vp, i64, ct.POINTER(ct.c_int64), ct.POINTER(ct.c_float), i32,
                      f32, f32, f32, vp],
+        "gsf_adam_masked": [vp, vp, vp, vp, vp, i64, i32, ct.POINTER(ct.c_float), vp, f32, f32,
+                            f32, vp],
+        "gsf_adam_reset": [vp, vp, vp, i64, vp],
+        "gsf_view_select": [ct.POINTER(gsf_camera), i32, ct.POINTER(gsf_camera), i32, f32, f32,
+                            ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int32)],
         "gsf_step": [vp, ct.POINTER(gsf_step_args)],
         "gsf_step_capture": [vp, ct.POINTER(gsf_step_args)],
         "gsf_step_replay": [vp],

@@ -61,6 +61,12 @@ struct SegTable {
     int32_t n;
 };
 
+// Learning rate per parameter plane (11 + 3 * 16 planes at SH degree 3).
+constexpr int kMaxPlanes = 64;
+struct PlaneLr {
+    float lr[kMaxPlanes];
+};
+
 // Tiles [tx0, tx1] x [ty0, ty1] of a view that meet its fovea: the pixels whose
 // centre can lie within radius_frac * width of the gaze point, with one pixel of
 // slack (the mask test itself is done per pixel by the loss).  Empty when
@@ -191,6 +197,18 @@ void launch_draw_bg(hipStream_t s, uint64_t seed, const int32_t *step, int nview
 // kernel first advances step[0] by one.
 void launch_adam(hipStream_t s, float *p, const float *g, float *m, float *v, int64_t n,
                  const SegTable &seg, float b1, float b2, float eps, int32_t *step, bool advance);
+
+// vis[i] = 1 when a record of Gaussian i (count[v * n + i], v < nviews) touched a tile.
+void launch_visible(hipStream_t s, const uint32_t *count, int n, int nviews, uint8_t *vis);
+
+// Adam on planar [planes][n] state for the Gaussians with vis[i] != 0 only
+// (others untouched), plane c at lr.lr[c]; advance as in launch_adam.
+void launch_adam_masked(hipStream_t s, float *p, const float *g, float *m, float *v, int64_t n,
+                        int planes, const PlaneLr &lr, const uint8_t *vis, float b1, float b2,
+                        float eps, int32_t *step, bool advance);
+
+// m[0..n) = v[0..n) = 0 and step[0] = 0, by a kernel (graph-capturable).
+void launch_adam_reset(hipStream_t s, float *m, float *v, int64_t n, int32_t *step);
 
 // Seeding from a device volume (synchronises); scratch: seed_scratch_bytes(n^3).
 hipError_t run_seed(hipStream_t s, const uint16_t *vol, int n, double thr, double range,

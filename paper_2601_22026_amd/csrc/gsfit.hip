@@ -63,6 +63,7 @@ struct Buffers {
     float *loss_partial = nullptr;
     float *bg = nullptr;                         // per-view random background of the step [V][3]
     ViewDesc *views = nullptr;
+    uint8_t *vis = nullptr;                      // per-Gaussian visibility of the masked Adam [n_max]
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -171,6 +172,7 @@ size_t carve(gsf_plan *p, char *base, Buffers *out) {
     b.loss_partial = (float *)take((size_t)loss_partials(p->total_pix) * 4);
     b.bg = (float *)take(p->views.size() * 3 * sizeof(float));
     b.views = (ViewDesc *)take(p->views.size() * sizeof(ViewDesc));
+    b.vis = (uint8_t *)take((size_t)p->n_max);
     if (out) *out = b;
     return off;
 }
@@ -402,6 +404,8 @@ gsf_status check_step(gsf_plan *p, const gsf_step_args *a) {
         return fail(p->ctx, GSF_E_INVALID, "gsf_step: alpha_loss and random_bg must be 0 or 1");
     if (a->random_bg && !a->alpha_loss)
         return fail(p->ctx, GSF_E_INVALID, "gsf_step: random_bg needs alpha_loss (RGBA targets)");
+    if (a->masked_adam != 0 && a->masked_adam != 1)
+        return fail(p->ctx, GSF_E_INVALID, "gsf_step: masked_adam must be 0 or 1");
     return GSF_OK;
 }
 
@@ -439,7 +443,14 @@ gsf_status enqueue_step(gsf_plan *p, const gsf_step_args *a) {
     SegTable seg;
     st = make_segments(p->ctx, off[C], so.data(), sl.data(), (int32_t)sl.size(), &seg);
     if (st != GSF_OK) return st;
-    {
+    if (a->masked_adam) {   // only the Gaussians that touched a tile in some view
+        StageTimer t(p, GSF_STAGE_ADAM);
+        PlaneLr lr{};
+        for (int c = 0; c < C; c++) lr.lr[c] = a->seg_lr[c];
+        launch_visible(p->ctx->stream, p->b.count, (int)a->n, p->V, p->b.vis);
+        launch_adam_masked(p->ctx->stream, a->params, a->grads, a->adam_m, a->adam_v, a->n, C, lr,
+                           p->b.vis, a->beta1, a->beta2, a->eps, a->step_dev, false);
+    } else {
         StageTimer t(p, GSF_STAGE_ADAM);
         launch_adam(p->ctx->stream, a->params, a->grads, a->adam_m, a->adam_v, off[C], seg,
                     a->beta1, a->beta2, a->eps, a->step_dev, false);
@@ -694,6 +705,38 @@ gsf_status gsf_adam(gsf_ctx *ctx, float *prm, const float *g, float *m, float *v
     return GSF_OK;
 }
 
+gsf_status gsf_adam_masked(gsf_ctx *ctx, float *prm, const float *g, float *m, float *v,
+                           int64_t n, int32_t planes, const float *plane_lr,
+                           const uint8_t *visible, float beta1, float beta2, float eps,
+                           int32_t *step_dev) {
+    if (!ctx) return GSF_E_INVALID;
+    if (!prm || !g || !m || !v || !plane_lr || !visible || !step_dev)
+        return fail(ctx, GSF_E_INVALID, "gsf_adam_masked: null argument");
+    if (n < 1 || planes < 1 || planes > kMaxPlanes || n > (int64_t)1 << 40)
+        return fail(ctx, GSF_E_INVALID, "gsf_adam_masked: n or planes out of range");
+    PlaneLr lr{};
+    for (int c = 0; c < planes; c++) {
+        if (!std::isfinite(plane_lr[c]))
+            return fail(ctx, GSF_E_INVALID, "gsf_adam_masked: non-finite learning rate");
+        lr.lr[c] = plane_lr[c];
+    }
+    launch_adam_masked(ctx->stream, prm, g, m, v, n, planes, lr, visible, beta1, beta2, eps,
+                       step_dev, true);
+    GSF_LAUNCHED(ctx);
+    return GSF_OK;
+}
+
+gsf_status gsf_adam_reset(gsf_ctx *ctx, float *m, float *v, int64_t n_elems, int32_t *step_dev) {
+    if (!ctx) return GSF_E_INVALID;
+    if (!m || !v || !step_dev || n_elems < 1)
+        return fail(ctx, GSF_E_INVALID, "gsf_adam_reset: null argument or empty");
+    if (!aligned16(m) || !aligned16(v))
+        return fail(ctx, GSF_E_INVALID, "gsf_adam_reset: buffers must be 16-byte aligned");
+    launch_adam_reset(ctx->stream, m, v, n_elems, step_dev);
+    GSF_LAUNCHED(ctx);
+    return GSF_OK;
+}
+
 gsf_status gsf_step(gsf_plan *p, const gsf_step_args *a) {
     gsf_status st = check_ready(p);
     if (st != GSF_OK) return st;
@@ -830,6 +873,7 @@ gsf_status gsf_debug_copy(gsf_plan *p, int which, void *host_dst, size_t cap, si
     case GSF_DBG_RANGES: src = p->b.ranges; bytes = (size_t)p->total_tiles * 8; break;
     case GSF_DBG_ORDER: src = p->b.order; bytes = (size_t)p->total_tiles * 4; break;
     case GSF_DBG_BG: src = p->b.bg; bytes = p->views.size() * 3 * sizeof(float); break;
+    case GSF_DBG_VIS: src = p->b.vis; bytes = (size_t)p->fwd_n; break;
     case GSF_DBG_TFINAL: src = p->b.tfinal; bytes = (size_t)p->total_pix * 4; break;
     case GSF_DBG_NCONTRIB: src = p->b.ncontrib; bytes = (size_t)p->total_pix * 4; break;
     case GSF_DBG_G2D: src = p->b.g2d; bytes = 9 * R * 4; break;

@@ -43,6 +43,7 @@ SEED_VOLUME = 3
 SEED_CAP_SUBSET = 4
 SEED_RESOLUTIONS = 5
 SEED_GAZE = 6
+SEED_VIEW_STREAM = 7
 
 RESOLUTION_CHOICES = [(512, 512), (768, 1024), (1024, 1024), (1536, 1536), (2048, 2048)]
 
@@ -197,6 +198,25 @@ def stereo_cameras(width: int = 2064, height: int = 2208, radius: float = 3.0,
         t = -(head.R.astype(np.float64) @ c)
         cams.append(Camera(R=head.R, t=t, campos=c, width=width, height=height,
                            **_intrinsics(width, height, fov_x_deg)))
+    return cams
+
+
+def view_stream(count: int, radius: float = 3.0, seed: int = SEED_VIEW_STREAM,
+                step: float = 0.04, jitter: float = 0.15, width: int = 128, height: int = 128,
+                fov_x_deg: float = 20.0):
+    """Foveal views along a wandering head path, as offered to the refinement's
+    view selection: camera centres on a random walk (isotropic steps of about
+    ``step`` scene units) starting on the sphere of the given radius, each
+    looking at a point drawn around the origin (standard deviation ``jitter``
+    per axis), so consecutive directions differ by a few degrees; narrow field of
+    view."""
+    rng = _rng(seed)
+    c = radius * sphere_directions(1, seed)[0]
+    cams = []
+    for _ in range(count):
+        c = c + rng.normal(scale=step / math.sqrt(3.0), size=3)
+        target = rng.normal(scale=jitter, size=3)
+        cams.append(look_at_camera(c, target, width, height, fov_x_deg))
     return cams
 
 
