@@ -91,13 +91,12 @@ __device__ __forceinline__ float dpp_shift(float x) {
                                                                  ROW_MASK, 0xf, true));
 }
 
-__device__ __forceinline__ float wave_sum_lane63(float x) {
+// Sum over each 16-lane row, left in the row's last lane (15, 31, 47, 63).
+__device__ __forceinline__ float row_sum_lane15(float x) {
     x += dpp_shift<0x111, 0xf>(x);   // row_shr:1
     x += dpp_shift<0x112, 0xf>(x);   // row_shr:2
     x += dpp_shift<0x114, 0xf>(x);   // row_shr:4
     x += dpp_shift<0x118, 0xf>(x);   // row_shr:8
-    x += dpp_shift<0x142, 0xa>(x);   // row_bcast:15 into rows 1 and 3
-    x += dpp_shift<0x143, 0xc>(x);   // row_bcast:31 into rows 2 and 3
     return x;
 }
 
@@ -139,48 +138,54 @@ __global__ __launch_bounds__(T * T < 256 ? T * T : 256) void k_render_fwd(
     const uint2 rg = ranges[gt];
     const int lx = threadIdx.x % T, ly = threadIdx.x / T;
 
+    // Tr[k] is the pixel's transmittance while it composites; a pixel that has
+    // stopped (or lies outside the image) holds -T instead, so one compare
+    // gives its state and no flag is carried from splat to splat.
     float px[PPT], py[PPT], Tr[PPT], cr[PPT], cg[PPT], cb[PPT];
     uint32_t last[PPT];
-    bool done[PPT];
 #pragma unroll
     for (int k = 0; k < PPT; k++) {
         const int x = tx * T + lx, y = ty * T + ly + k * ROWS;
-        done[k] = !(x < vd.width && y < vd.height);
         px[k] = (float)x;   // integer pixel; its centre's offset from a mean is splat_dx
         py[k] = (float)y;
-        Tr[k] = 1.f;
+        Tr[k] = x < vd.width && y < vd.height ? 1.f : -1.f;
         cr[k] = cg[k] = cb[k] = 0.f;
         last[k] = 0u;
     }
 
     for (uint32_t bs = rg.x; bs < rg.y; bs += B) {
         const int nb = (int)min((uint32_t)B, rg.y - bs);
+        const int nbu = (nb + U - 1) / U * U;   // padded with inert splats to whole groups
         __syncthreads();
-        for (int j = threadIdx.x; j < nb; j += NT) {
-            const uint32_t r = vals[bs + j];
-            const float4 ra = sp.a[r], rb = sp.b[r], rc = sp.c[r];
-            s_a[j] = ra;
-            s_b[j] = rb;
-            s_c[j] = make_float4(rc.x, splat_tau(rb), rc.z, rc.w);
+        for (int j = threadIdx.x; j < nbu; j += NT) {
+            if (j < nb) {
+                const uint32_t r = vals[bs + j];
+                const float4 ra = sp.a[r], rb = sp.b[r], rc = sp.c[r];
+                s_a[j] = ra;
+                s_b[j] = rb;
+                s_c[j] = make_float4(rc.x, splat_tau(rb), rc.z, rc.w);
+            } else {   // power2 = 0 < tau = +inf: never included
+                s_a[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+                s_b[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+                s_c[j] = make_float4(0.f, __builtin_inff(), 0.f, 0.f);
+            }
         }
         __syncthreads();
-        for (int j0 = 0; j0 < nb; j0 += U) {
+        for (int j0 = 0; j0 < nbu; j0 += U) {
             bool all = true;
 #pragma unroll
-            for (int k = 0; k < PPT; k++) all &= done[k];
+            for (int k = 0; k < PPT; k++) all &= !(Tr[k] > 0.f);
             if (__all(all)) break;
-            const int nu = min(U, nb - j0);
             // Phase 1: the U splats' alphas are independent of each other and of
-            // the pixel state; computed without branches (out-of-range or
-            // skipped splats get valid = false).
+            // the pixel state; computed without branches (skipped splats get
+            // valid = false; every operand is read whatever the outcome).
             float4 a[U], b[U];
             float4 c[U];
 #pragma unroll
             for (int u = 0; u < U; u++) {
-                const int j = u < nu ? j0 + u : j0;
-                a[u] = s_a[j];
-                b[u] = s_b[j];
-                c[u] = s_c[j];
+                a[u] = s_a[j0 + u];
+                b[u] = s_b[j0 + u];
+                c[u] = s_c[j0 + u];
             }
 #pragma unroll
             for (int k = 0; k < PPT; k++) {
@@ -192,27 +197,28 @@ __global__ __launch_bounds__(T * T < 256 ? T * T : 256) void k_render_fwd(
                     const float dy = splat_dx(py[k], c[u].w, a[u].y);
                     const float power2 =
                         fmaf(a[u].z * dx, dx, fmaf(b[u].x * dy, dy, (a[u].w * dx) * dy));
-                    valid[u] = u < nu && !(power2 > 0.f) && !(power2 < c[u].y);
+                    valid[u] = !(power2 > 0.f) & !(power2 < c[u].y);
                     alpha[u] = fminf(kAlphaMax, b[u].y * __builtin_amdgcn_exp2f(power2));
                 }
-                // Phase 2: the sequential front-to-back update, with selects.
-                // An included splat performs exactly the float operations of the
-                // definition (Tn = T (1 - alpha), w = alpha T, C += colour w).
+                // Phase 2: the sequential front-to-back update.  An included
+                // splat performs exactly the float operations of the definition
+                // (Tn = T (1 - alpha), w = alpha T, C += colour w); any other
+                // gets w = 0, which leaves the (non-negative) colour sums as
+                // they are bit for bit.
 #pragma unroll
                 for (int u = 0; u < U; u++) {
                     const float Tn = Tr[k] * (1.f - alpha[u]);
-                    const bool take = valid[u] && !done[k];
+                    const bool take = valid[u] && Tr[k] > 0.f;
                     const bool stop = take && Tn < kTStop;
                     const bool inc = take && !stop;
                     if (MODE == 2 && inc)
                         tstore[(size_t)(bs + (uint32_t)(j0 + u)) * (T * T) + threadIdx.x + k * NT] = Tr[k];
-                    const float w = alpha[u] * Tr[k];
-                    cr[k] = inc ? fmaf(b[u].z, w, cr[k]) : cr[k];
-                    cg[k] = inc ? fmaf(b[u].w, w, cg[k]) : cg[k];
-                    cb[k] = inc ? fmaf(c[u].x, w, cb[k]) : cb[k];
-                    Tr[k] = inc ? Tn : Tr[k];
+                    const float w = (inc ? alpha[u] : 0.f) * Tr[k];
+                    cr[k] = fmaf(b[u].z, w, cr[k]);
+                    cg[k] = fmaf(b[u].w, w, cg[k]);
+                    cb[k] = fmaf(c[u].x, w, cb[k]);
+                    Tr[k] = inc ? Tn : (stop ? -Tr[k] : Tr[k]);
                     last[k] = inc ? bs + (uint32_t)(j0 + u) - rg.x + 1u : last[k];
-                    done[k] = done[k] || stop;
                 }
             }
         }
@@ -220,13 +226,15 @@ __global__ __launch_bounds__(T * T < 256 ? T * T : 256) void k_render_fwd(
             float4 *slot = ckpt + (size_t)((bs + B) / B) * (T * T);
 #pragma unroll
             for (int k = 0; k < PPT; k++)
-                slot[threadIdx.x + k * NT] = make_float4(Tr[k], cr[k], cg[k], cb[k]);
+                slot[threadIdx.x + k * NT] = make_float4(fabsf(Tr[k]), cr[k], cg[k], cb[k]);
         }
         bool all = true;
 #pragma unroll
-        for (int k = 0; k < PPT; k++) all &= done[k];
+        for (int k = 0; k < PPT; k++) all &= !(Tr[k] > 0.f);
         if (__syncthreads_and(all)) break;
     }
+#pragma unroll
+    for (int k = 0; k < PPT; k++) Tr[k] = fabsf(Tr[k]);
 
     const float *bgv = bg ? bg + 3 * v : cams[v].bg;
     const float bg0 = bgv[0], bg1 = bgv[1], bg2 = bgv[2];
@@ -347,31 +355,44 @@ __device__ __forceinline__ void render_bwd_unit(
             // per lane sums: dpw dx, dpw dy, dpw dx^2, dpw dx dy, dpw dy^2 (dpw = dL/dpower),
             // dL/do, dL/dcolour; the conic factors of the mean gradient are applied once
             // per splat when the sums are flushed
+            // (-0 is the exact identity of addition, so the first term needs no add)
             float acc[9];
 #pragma unroll
-            for (int f = 0; f < 9; f++) acc[f] = 0.f;
+            for (int f = 0; f < 9; f++) acc[f] = -0.f;
             bool any = false;
 #pragma unroll
             for (int k = 0; k < PPT; k++) {
                 if (!rows_meet(dy0 + (float)(k * ROWS), (float)(ROWS - 1), hy)) continue;   // wave-uniform
-                if (pos >= nc[k]) continue;
-                float alpha, ae, ex, dx, dy;
-                if (!splat_alpha(a, b, c, px[k], py[k], alpha, ae, ex, dx, dy)) continue;
-                any = true;
+                // Branch-free per lane: every value is computed and a pixel the
+                // splat does not reach (behind its last contributor, or alpha
+                // below 1/255) adds exact zeros and keeps its state.  An
+                // included pixel does exactly the float operations of the adjoint.
+                const float dx = splat_dx(px[k], c.z, a.x);
+                const float dy = splat_dx(py[k], c.w, a.y);
+                const float power2 = fmaf(a.z * dx, dx, fmaf(b.x * dy, dy, (a.w * dx) * dy));
+                const bool inc = (pos < nc[k]) & !(power2 > 0.f) & !(power2 < c.y);
+                const float ex = __builtin_amdgcn_exp2f(power2);
+                const float ae = b.y * ex;
+                const float alpha = fminf(kAlphaMax, ae);
+                any |= inc;
                 const float inv = __builtin_amdgcn_rcpf(1.f - alpha);   // alpha <= 0.99
-                const float Tb = MODE == 2 ? tstore[(size_t)(bs + (uint32_t)j) * (T * T) + threadIdx.x + k * NT]
-                                           : Tr[k] * inv;
+                float Tb;
+                if (MODE == 2)
+                    Tb = inc ? tstore[(size_t)(bs + (uint32_t)j) * (T * T) + threadIdx.x + k * NT] : 0.f;
+                else
+                    Tb = Tr[k] * inv;
                 const float gc = g0[k] * b.z + g1[k] * b.w + g2[k] * c.x;
                 const float dalpha = Tb * gc - (gR[k] - gA[k] * Tf[k]) * inv;
-                const float wT = alpha * Tb;
+                const float wT = inc ? alpha * Tb : 0.f;
                 acc[6] += wT * g0[k];
                 acc[7] += wT * g1[k];
                 acc[8] += wT * g2[k];
                 gR[k] = fmaf(gc, wT, gR[k]);
-                Tr[k] = Tb;
-                if (ae > kAlphaMax) continue;      // clamped alpha: no gradient to o, power
-                const float dpw = ae * dalpha;     // d loss / d power (natural units)
-                acc[5] += ex * dalpha;
+                Tr[k] = inc ? Tb : Tr[k];
+                // a clamped alpha passes no gradient to the opacity or the power
+                const bool open = inc & !(ae > kAlphaMax);
+                const float dpw = open ? ae * dalpha : 0.f;   // d loss / d power (natural units)
+                acc[5] += open ? ex * dalpha : 0.f;
                 const float ux = dpw * dx, uy = dpw * dy;
                 acc[0] += ux;
                 acc[1] += uy;
@@ -379,12 +400,14 @@ __device__ __forceinline__ void render_bwd_unit(
                 acc[3] = fmaf(ux, dy, acc[3]);
                 acc[4] = fmaf(uy, dy, acc[4]);
             }
-            if (__any(any)) {
+            if (__any(any)) {   // row sums, the four rows added into LDS
                 const int w = threadIdx.x >> 6;
+                float sum[9];
 #pragma unroll
-                for (int f = 0; f < 9; f++) {
-                    const float sum = wave_sum_lane63(acc[f]);
-                    if (__lane_id() == 63) s_g[w][f][j] = sum;
+                for (int f = 0; f < 9; f++) sum[f] = row_sum_lane15(acc[f]);
+                if ((__lane_id() & 15) == 15) {
+#pragma unroll
+                    for (int f = 0; f < 9; f++) atomicAdd(&s_g[w][f][j], sum[f]);
                 }
             }
         }
