@@ -136,10 +136,12 @@ void launch_tile_order(hipStream_t s, const uint2 *ranges, int total_tiles, uint
                        uint32_t *counts);
 int order_groups(int64_t total_tiles);
 
-// Stable per-tile sort of vals by depth_key[val]; gk0, gk1, gv1: key-capacity
-// scratch for lists longer than the LDS capacity.
-void launch_tile_sort(hipStream_t s, const uint2 *ranges, int total_tiles, const uint32_t *depth_key,
-                      uint32_t *vals, uint32_t *gk0, uint32_t *gk1, uint32_t *gv1);
+// Stable per-tile sort of vals by depth_key[val], one workgroup per tile in the
+// compositing order (order: a permutation of the tiles); gk0, gk1, gv1:
+// key-capacity scratch for lists longer than the LDS capacity.
+void launch_tile_sort(hipStream_t s, const uint32_t *order, const uint2 *ranges, int total_tiles,
+                      const uint32_t *depth_key, uint32_t *vals, uint32_t *gk0, uint32_t *gk1,
+                      uint32_t *gv1);
 
 // Everything the compositing kernels share.
 struct RenderArgs {

@@ -301,7 +301,8 @@ gsf_status enqueue_forward(gsf_plan *p, const float *params, int64_t n, const gs
     GSF_LAUNCHED(ctx);
     {   // each tile's list by (depth, record); the sorted tile ids are free scratch now
         StageTimer t(p, GSF_STAGE_DEPTH_SORT);
-        launch_tile_sort(s, b.ranges, (int)p->total_tiles, b.depth_key, b.vals, b.keys, b.ok, b.ov);
+        launch_tile_sort(s, b.order, b.ranges, (int)p->total_tiles, b.depth_key, b.vals, b.keys, b.ok,
+                         b.ov);
     }
     GSF_LAUNCHED(ctx);
     {

@@ -31,7 +31,7 @@ constexpr int kSortIpt = 8;                  // keys per thread per chunk tile
 constexpr int kSortTile = kSortBlock * kSortIpt;
 constexpr int kSortMaxGrid = 1024;
 constexpr int kScanBlock = 256;
-constexpr int kScanIpt = 8;
+constexpr int kScanIpt = 1;                  // 256 records per block: 50k records fill 196 blocks
 constexpr int kScanTile = kScanBlock * kScanIpt;
 constexpr int kTileSortBlock = 256;
 constexpr int kTileSortLds = 2048;           // list length sorted in LDS; longer lists use global scratch
@@ -246,16 +246,24 @@ __global__ __launch_bounds__(1024) void k_scan_top(uint32_t *__restrict__ block_
 
 // Keys of each record (one per touched tile) at its scanned offset; also
 // clears the tile ranges (grid-stride) before the boundary pass fills them.
+// The block's keys are written by all its threads together, key q of the block
+// by thread q mod 256: the record owning q is found by binary search over the
+// block's offsets in LDS, so one record's many keys are spread over the block
+// and consecutive threads write consecutive addresses.
 __global__ __launch_bounds__(kScanBlock) void k_scan_dup(
     const uint32_t *__restrict__ count, const uint2 *__restrict__ rect, int nrec, int n,
     const ViewDesc *__restrict__ views, const uint32_t *__restrict__ block_prefix,
     const unsigned long long *__restrict__ m_total, int64_t capacity, uint32_t *__restrict__ keys,
     uint32_t *__restrict__ vals, uint2 *__restrict__ ranges, int total_tiles) {
     __shared__ uint32_t s_wave[4];
+    __shared__ uint32_t s_off[kScanTile];    // block-local exclusive key offset per record
+    __shared__ uint32_t s_base[kScanTile];   // global tile id of the record's first tile
+    __shared__ uint32_t s_w[kScanTile];      // rect width (low 16 bits), view tiles_x (high 16)
     for (int t = blockIdx.x * kScanBlock + threadIdx.x; t < total_tiles; t += gridDim.x * kScanBlock)
         ranges[t] = make_uint2(0u, 0u);
     if (*m_total > (unsigned long long)capacity) return;    // overflow: emit nothing
-    const int base = blockIdx.x * kScanTile + threadIdx.x * kScanIpt;
+    const int rec0 = blockIdx.x * kScanTile;
+    const int base = rec0 + threadIdx.x * kScanIpt;
     uint32_t cnt[kScanIpt];
     uint32_t sum = 0;
 #pragma unroll
@@ -264,24 +272,40 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_dup(
         sum += cnt[k];
     }
     uint32_t total;
-    uint32_t off = block_prefix[blockIdx.x] + block_excl_scan_256(sum, s_wave, total);
+    uint32_t off = block_excl_scan_256(sum, s_wave, total);
 #pragma unroll
     for (int k = 0; k < kScanIpt; k++) {
-        if (cnt[k] == 0u) continue;
-        const uint32_t r = (uint32_t)(base + k);
-        const ViewDesc vd = views[r / (uint32_t)n];
-        const uint2 rc = rect[r];
-        const uint32_t x0 = rc.x & 0xFFFFu, y0 = rc.x >> 16, x1 = rc.y & 0xFFFFu, y1 = rc.y >> 16;
-        uint32_t o = off;
-        for (uint32_t ty = y0; ty <= y1; ty++) {
-            const uint32_t row = (uint32_t)vd.tile_off + ty * (uint32_t)vd.tiles_x;
-            for (uint32_t tx = x0; tx <= x1; tx++) {
-                keys[o] = row + tx;
-                vals[o] = r;
-                o++;
-            }
+        const int i = threadIdx.x * kScanIpt + k;
+        s_off[i] = off;
+        if (cnt[k] != 0u) {
+            const uint32_t r = (uint32_t)(base + k);
+            const ViewDesc vd = views[r / (uint32_t)n];
+            const uint2 rc = rect[r];
+            const uint32_t x0 = rc.x & 0xFFFFu, y0 = rc.x >> 16, x1 = rc.y & 0xFFFFu;
+            s_base[i] = (uint32_t)vd.tile_off + y0 * (uint32_t)vd.tiles_x + x0;
+            s_w[i] = (x1 - x0 + 1u) | ((uint32_t)vd.tiles_x << 16);
         }
         off += cnt[k];
+    }
+    __syncthreads();
+    const uint32_t gbase = block_prefix[blockIdx.x];
+    for (uint32_t q = threadIdx.x; q < total; q += kScanBlock) {
+        // the last record whose offset is <= q (records without keys share the
+        // offset of the next record, so the last one is the owner)
+        int lo = 0, hi = kScanTile - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_off[mid] <= q) lo = mid; else hi = mid - 1;
+        }
+        const uint32_t li = q - s_off[lo];        // index of the key within its record
+        const uint32_t wv = s_w[lo];
+        const uint32_t w = wv & 0xFFFFu, tiles_x = wv >> 16;
+        // li / w via a float reciprocal, then exact by one correction each way
+        uint32_t row = (uint32_t)((float)li * __builtin_amdgcn_rcpf((float)w));
+        if (row * w > li) row--;
+        if ((row + 1u) * w <= li) row++;
+        keys[gbase + q] = s_base[lo] + row * tiles_x + (li - row * w);
+        vals[gbase + q] = (uint32_t)(rec0 + lo);
     }
 }
 
@@ -558,12 +582,13 @@ __device__ __forceinline__ void sort_list(uint32_t *k0, uint32_t *v0, uint32_t *
 }
 
 __global__ __launch_bounds__(kTileSortBlock) void k_tile_sort(
-    const uint2 *__restrict__ ranges, const uint32_t *__restrict__ depth_key,
+    const uint32_t *__restrict__ order, const uint2 *__restrict__ ranges,
+    const uint32_t *__restrict__ depth_key,
     uint32_t *__restrict__ vals, uint32_t *__restrict__ gk0, uint32_t *__restrict__ gk1,
     uint32_t *__restrict__ gv1) {
     __shared__ SortShared sh;
     __shared__ uint32_t s_k0[kTileSortLds], s_v0[kTileSortLds], s_k1[kTileSortLds], s_v1[kTileSortLds];
-    const uint2 rg = ranges[blockIdx.x];
+    const uint2 rg = ranges[order[blockIdx.x]];   // tiles with the longest lists first
     const int n = (int)(rg.y - rg.x);
     if (n <= 1) return;
     uint32_t *lv = vals + rg.x;
@@ -650,9 +675,10 @@ void launch_tile_order(hipStream_t s, const uint2 *ranges, int total_tiles, uint
     k_order_place<<<g, 256, 0, s>>>(ranges, total_tiles, counts, g, order);
 }
 
-void launch_tile_sort(hipStream_t s, const uint2 *ranges, int total_tiles, const uint32_t *depth_key,
-                      uint32_t *vals, uint32_t *gk0, uint32_t *gk1, uint32_t *gv1) {
-    k_tile_sort<<<total_tiles, kTileSortBlock, 0, s>>>(ranges, depth_key, vals, gk0, gk1, gv1);
+void launch_tile_sort(hipStream_t s, const uint32_t *order, const uint2 *ranges, int total_tiles,
+                      const uint32_t *depth_key, uint32_t *vals, uint32_t *gk0, uint32_t *gk1,
+                      uint32_t *gv1) {
+    k_tile_sort<<<total_tiles, kTileSortBlock, 0, s>>>(order, ranges, depth_key, vals, gk0, gk1, gv1);
 }
 
 }  // namespace gsf
