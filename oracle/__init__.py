@@ -372,3 +372,87 @@ def sh_basis(deg, dirs):
     out = np.zeros((d.shape[0], 16))
     lib().orc_sh_basis(deg, _p(d), d.shape[0], _p(out))
     return out[:, :(deg + 1) ** 2]
+
+
+# ------------------------------------------------------------ depth-guided reprojection
+# Method, "Real-time Viewer", Eqs. (2)-(4): a pixel with texture coordinate uv
+# and first-hit distance d is lifted to the world point at distance d from the
+# old camera centre along the ray through the far-plane point that
+# (P_old V_old)^-1 maps (2 uv - 1, 1, 1) to, and projected with P_new V_new.
+
+def reproject(depth, P_old, V_old, pos_old, P_new, V_new):
+    """Eqs. (2)-(4) per pixel in FP64: clip coordinates [H][W][4] of the world
+    points; pixel (i, j) has uv = ((i + 0.5) / W, (j + 0.5) / H).  Pixels whose
+    depth is not finite and positive get NaN."""
+    d = np.asarray(depth, np.float64)
+    H, W = d.shape
+    inv_old = np.linalg.inv(np.asarray(P_old, np.float64) @ np.asarray(V_old, np.float64))
+    u = (np.arange(W) + 0.5) / W
+    v = (np.arange(H) + 0.5) / H
+    ndc = np.stack(np.broadcast_arrays((2.0 * u - 1.0)[None, :], (2.0 * v - 1.0)[:, None],
+                                       np.ones((H, W)), np.ones((H, W))), -1)
+    far = ndc @ inv_old.T                                   # Eq. (2), before the divide
+    p_far = far[..., :3] / far[..., 3:4]
+    c = np.asarray(pos_old, np.float64)
+    ray = p_far - c
+    with np.errstate(invalid="ignore", over="ignore"):
+        p_world = c + ray / np.linalg.norm(ray, axis=-1, keepdims=True) * d[..., None]   # Eq. (3)
+    hom = np.concatenate([p_world, np.ones((H, W, 1))], -1)
+    with np.errstate(invalid="ignore", over="ignore"):
+        clip = hom @ (np.asarray(P_new, np.float64) @ np.asarray(V_new, np.float64)).T    # Eq. (4)
+    clip[~(np.isfinite(d) & (d > 0))] = np.nan
+    return clip
+
+
+def reproject_warp(rgba, depth, P_old, V_old, pos_old, P_new, V_new, out_w, out_h, eps=1e-4):
+    """The foveal image moved to the new view: every pixel with a depth lands on
+    the output pixel containing its reprojected position (NDC x, y in [-1, 1)
+    mapped to [0, W') x [0, H'), clip w > 0, NDC z in [-1, 1]); where several
+    land, the smallest clip w (nearest to the new camera) wins, ties to the
+    lower source index.  Returns (out_rgba [4][H'][W'], src [H'][W'] with -1
+    where nothing lands, flags [H'][W']).  flags marks output pixels whose
+    winner FP32 rounding could change: a candidate within eps of a pixel edge,
+    or the two nearest candidates within 1e-5 relative in w."""
+    rgba = np.asarray(rgba, np.float64).reshape(4, -1)
+    clip = reproject(depth, P_old, V_old, pos_old, P_new, V_new).reshape(-1, 4)
+    n = clip.shape[0]
+    w = clip[:, 3]
+    with np.errstate(invalid="ignore", divide="ignore"):
+        ndc = clip[:, :3] / w[:, None]
+        x = (ndc[:, 0] + 1.0) * 0.5 * out_w
+        y = (ndc[:, 1] + 1.0) * 0.5 * out_h
+        ok = np.isfinite(w) & (w > 0) & (np.abs(ndc[:, 2]) <= 1.0) & (x >= 0) & (x < out_w) & \
+            (y >= 0) & (y < out_h)
+    src = np.nonzero(ok)[0]
+    tx, ty = np.floor(x[src]).astype(np.int64), np.floor(y[src]).astype(np.int64)
+    tgt = ty * out_w + tx
+    edge = (np.abs(x[src] - np.round(x[src])) < eps) | (np.abs(y[src] - np.round(y[src])) < eps)
+    order = np.lexsort((src, w[src], tgt))                 # by target, then w, then index
+    out = np.zeros((4, out_h * out_w))
+    who = np.full(out_h * out_w, -1, np.int64)
+    flags = np.zeros(out_h * out_w, bool)
+    first = np.ones(order.size, bool)
+    first[1:] = tgt[order][1:] != tgt[order][:-1]
+    for k in np.nonzero(first)[0]:
+        t = tgt[order[k]]
+        win = order[k]
+        who[t] = src[win]
+        out[:, t] = rgba[:, src[win]]
+        group = [order[k]]
+        q = k + 1
+        while q < order.size and tgt[order[q]] == t:
+            group.append(order[q])
+            q += 1
+        if edge[group].any():
+            flags[t] = True
+        if len(group) > 1 and w[src[group[1]]] - w[src[group[0]]] <= 1e-5 * w[src[group[0]]]:
+            flags[t] = True
+    # a candidate near an edge may belong to a neighbouring output pixel instead
+    for s_, t in zip(np.nonzero(edge)[0], tgt[edge]):
+        ty_, tx_ = divmod(int(t), out_w)
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                yy, xx = ty_ + dy, tx_ + dx
+                if 0 <= yy < out_h and 0 <= xx < out_w:
+                    flags[yy * out_w + xx] = True
+    return out.reshape(4, out_h, out_w), who.reshape(out_h, out_w), flags.reshape(out_h, out_w)

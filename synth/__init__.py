@@ -220,6 +220,41 @@ def view_stream(count: int, radius: float = 3.0, seed: int = SEED_VIEW_STREAM,
     return cams
 
 
+def clip_matrices(cam: Camera, near: float = 0.1, far: float = 100.0):
+    """Projection P and view V (float32 4x4, row-major) of a pinhole camera for
+    column vectors: V = [R | t; 0 0 0 1]; P maps camera space (x right, y
+    down, z forward) to clip space with NDC x = 2 px / W - 1, y = 2 py / H - 1
+    (px, py the pixel coordinates, pixel i covering [i, i + 1)), NDC z = -1 at
+    the near and +1 at the far plane, and clip w = camera z."""
+    W, H = float(cam.width), float(cam.height)
+    P = np.zeros((4, 4))
+    P[0, 0], P[0, 2] = 2.0 * cam.fx / W, 2.0 * cam.cx / W - 1.0
+    P[1, 1], P[1, 2] = 2.0 * cam.fy / H, 2.0 * cam.cy / H - 1.0
+    P[2, 2], P[2, 3] = (far + near) / (far - near), -2.0 * far * near / (far - near)
+    P[3, 2] = 1.0
+    V = np.eye(4)
+    V[:3, :3] = cam.R
+    V[:3, 3] = cam.t
+    return _f32(P), _f32(V)
+
+
+def sphere_depth(cam: Camera, radius: float = 1.0, center=(0.0, 0.0, 0.0)) -> np.ndarray:
+    """First-hit distance along each pixel-centre ray to a sphere (float32
+    [H][W]; 0 where the ray misses): the depth a path tracer's first hits give
+    for a round object, standing in for the paper's foveal depth images."""
+    j, i = np.meshgrid(np.arange(cam.height), np.arange(cam.width), indexing="ij")
+    xc = (i + 0.5 - cam.cx) / cam.fx
+    yc = (j + 0.5 - cam.cy) / cam.fy
+    d_cam = np.stack([xc, yc, np.ones_like(xc)], -1)
+    d = d_cam @ cam.R.astype(np.float64)          # camera -> world direction (R^T d)
+    d /= np.linalg.norm(d, axis=-1, keepdims=True)
+    o = cam.campos.astype(np.float64) - np.asarray(center, np.float64)
+    b = d @ o
+    disc = b * b - (o @ o - radius * radius)
+    t = -b - np.sqrt(np.maximum(disc, 0.0))
+    return _f32(np.where((disc > 0) & (t > 0), t, 0.0))
+
+
 def gaze_points(cams, seed: int = SEED_GAZE) -> np.ndarray:
     rng = _rng(seed)
     g = [(rng.uniform(0.2 * c.width, 0.8 * c.width), rng.uniform(0.2 * c.height, 0.8 * c.height))
