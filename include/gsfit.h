@@ -20,6 +20,8 @@
  *                 and gsf_step_args.masked_adam (visibility-masked update)
  *   seeding: gsf_seed_volume (Gaussians from a CT volume), gsf_raymarch
  *                 (emission-absorption target images)
+ *   viewer: gsf_reproject, gsf_reproject_warp (depth-guided reprojection of
+ *                 the foveal image)
  *
  * Conventions shared by every call
  * --------------------------------
@@ -213,6 +215,40 @@ gsf_status gsf_adam_reset(gsf_ctx *ctx, float *m, float *v, int64_t n_elems, int
 gsf_status gsf_view_select(const gsf_camera *set, int32_t n_set, const gsf_camera *cand,
                            int32_t n_cand, float delta_pos, float theta_view_deg, int32_t *keep,
                            int32_t *n_kept);
+
+/* Depth-guided reprojection of a foveal image (Method, "Real-time Viewer",
+ * Eqs. (2)-(4)).  Pixel (i, j) of a width x height image has texture
+ * coordinate uv = ((i + 0.5) / width, (j + 0.5) / height) and first-hit
+ * distance depth[j * width + i] (device float32, world units).  Its far-plane
+ * point is p_far = (h.x, h.y, h.z) / h.w with h = (P_old V_old)^-1 (2u - 1,
+ * 2v - 1, 1, 1); its world point is pos_old + depth (p_far - pos_old) /
+ * |p_far - pos_old|; clip = P_new V_new (p_world, 1).  Matrices: host float32
+ * [16], row-major, for column vectors (clip = M x); pos_old: host float32 [3].
+ * P V products and the inverse are formed on the host in double, the per-pixel
+ * work on the device in float32.  clip: device float32 [4][height][width]
+ * (x, y, z, w planes), NaN where the depth is not finite and positive.
+ * GSF_E_INVALID for null pointers, sizes outside 1..16384, a singular
+ * P_old V_old or a non-finite matrix entry. */
+gsf_status gsf_reproject(gsf_ctx *ctx, const float *depth, int32_t width, int32_t height,
+                         const float *p_old, const float *v_old, const float *pos_old,
+                         const float *p_new, const float *v_new, float *clip);
+
+/* The foveal image moved to the new view by its reprojected points (the
+ * viewer's depth-deformed image, Method "Real-time Viewer", drawn as points):
+ * every pixel with a depth lands on the output pixel (floor(x), floor(y)) with
+ * x = (ndc_x + 1) / 2 * out_width, y = (ndc_y + 1) / 2 * out_height, if clip
+ * w > 0, ndc_z in [-1, 1] and (x, y) inside; where several land the smallest
+ * clip w wins, ties to the lower source index j * width + i.  rgba: device
+ * [4][height][width]; zbuf: device scratch of out_width * out_height uint64
+ * (8-byte aligned, overwritten); out_rgba: device [4][out_height][out_width],
+ * the winner's four values, zero where nothing lands; out_src: device int32
+ * [out_height][out_width], the winner's source index or -1.  The gaps are the
+ * disocclusions the peripheral model fills.  Errors as gsf_reproject. */
+gsf_status gsf_reproject_warp(gsf_ctx *ctx, const float *rgba, const float *depth, int32_t width,
+                              int32_t height, const float *p_old, const float *v_old,
+                              const float *pos_old, const float *p_new, const float *v_new,
+                              int32_t out_width, int32_t out_height, uint64_t *zbuf,
+                              float *out_rgba, int32_t *out_src);
 
 /* Arguments of one full step: forward, loss, backward, Adam on the parameters. */
 typedef struct gsf_step_args {

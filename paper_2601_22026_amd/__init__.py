@@ -29,7 +29,7 @@ from ._abi import GsfError, gsf_camera, gsf_plan_desc, gsf_step_args, lib
 
 __all__ = ["GsfError", "Context", "Plan", "rasterize", "adam", "adam_masked", "adam_reset",
            "FitStep", "FitConfig", "autotune", "select_views", "plane_learning_rates", "Refiner",
-           "seed_volume", "raymarch", "pack_cameras", "cameras_to_device", "n_planes", "lib"]
+           "seed_volume", "raymarch", "reproject", "reproject_warp", "pack_cameras", "cameras_to_device", "n_planes", "lib"]
 
 
 def n_planes(sh_degree: int) -> int:
@@ -536,6 +536,46 @@ class Refiner:
             raise GsfError(_abi.GSF_E_STATE, "restart() first")
         for _ in range(int(steps)):
             self.fit.replay()
+
+
+def _mat16(m):
+    a = np.ascontiguousarray(np.asarray(m, np.float32).reshape(16))
+    return (ct.c_float * 16)(*[float(x) for x in a])
+
+
+def _vec3(v):
+    return (ct.c_float * 3)(*[float(x) for x in np.asarray(v, np.float32).reshape(3)])
+
+
+def reproject(ctx: Context, depth: torch.Tensor, P_old, V_old, pos_old, P_new, V_new) -> torch.Tensor:
+    """gsf_reproject (Eqs. (2)-(4)): clip coordinates [4][H][W] of every pixel
+    of a depth image [H][W] (NaN where the depth is missing).  Matrices: 4x4
+    row-major, column-vector convention."""
+    H, W = depth.shape
+    clip = torch.empty((4, H, W), dtype=torch.float32, device=depth.device)
+    ctx.use_stream()
+    ctx.check(lib().gsf_reproject(ctx.handle, _ptr(depth), int(W), int(H), _mat16(P_old),
+                                  _mat16(V_old), _vec3(pos_old), _mat16(P_new), _mat16(V_new),
+                                  _ptr(clip)), "gsf_reproject")
+    return clip
+
+
+def reproject_warp(ctx: Context, rgba: torch.Tensor, depth: torch.Tensor, P_old, V_old, pos_old,
+                   P_new, V_new, out_w: int, out_h: int, zbuf: Optional[torch.Tensor] = None):
+    """gsf_reproject_warp: the image [4][H][W] moved to the new view by its
+    depth, as (out_rgba [4][out_h][out_w], src int32 [out_h][out_w])."""
+    H, W = depth.shape
+    dev = depth.device
+    if zbuf is None:
+        zbuf = torch.empty(int(out_w) * int(out_h), dtype=torch.int64, device=dev)
+    out = torch.empty((4, out_h, out_w), dtype=torch.float32, device=dev)
+    src = torch.empty((out_h, out_w), dtype=torch.int32, device=dev)
+    ctx.use_stream()
+    ctx.check(lib().gsf_reproject_warp(ctx.handle, _ptr(rgba), _ptr(depth), int(W), int(H),
+                                       _mat16(P_old), _mat16(V_old), _vec3(pos_old),
+                                       _mat16(P_new), _mat16(V_new), int(out_w), int(out_h),
+                                       _ptr(zbuf), _ptr(out), _ptr(src)), "gsf_reproject_warp")
+    return out, src
 
 
 def seed_volume(ctx: Context, vol: torch.Tensor, cap: int, seed: int, threshold: float = 1200.0,

@@ -27,7 +27,7 @@ EXPORTED = ["gsf_ctx_create", "gsf_ctx_destroy", "gsf_ctx_set_stream", "gsf_last
             "gsf_debug_copy", "gsf_plan_set_timing", "gsf_plan_stage_times",
             "gsf_count_pairs", "gsf_loss_l1_rgba", "gsf_seed_scratch_bytes",
             "gsf_seed_volume", "gsf_raymarch", "gsf_adam_masked", "gsf_adam_reset",
-            "gsf_view_select"]
+            "gsf_view_select", "gsf_reproject", "gsf_reproject_warp"]
 STAGES = ["project", "duplicate", "tile_sort", "ranges", "depth_sort", "render", "loss",
           "render_bwd", "project_bwd", "adam", "zero"]
 
@@ -69,6 +69,7 @@ assert ct.sizeof(gsf_camera) == 128
 
 def _declare(L):
     vp, i64, i32, f32 = ct.c_void_p, ct.c_int64, ct.c_int32, ct.c_float
+    pf = ct.POINTER(ct.c_float)
     pvp = ct.POINTER(ct.c_void_p)
     sig = {
         "gsf_ctx_create": [ct.c_int, vp, pvp],
@@ -90,6 +91,8 @@ def _declare(L):
         "gsf_adam_reset": [vp, vp, vp, i64, vp],
         "gsf_view_select": [ct.POINTER(gsf_camera), i32, ct.POINTER(gsf_camera), i32, f32, f32,
                             ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int32)],
+        "gsf_reproject": [vp, vp, i32, i32, pf, pf, pf, pf, pf, vp],
+        "gsf_reproject_warp": [vp, vp, vp, i32, i32, pf, pf, pf, pf, pf, i32, i32, vp, vp, vp],
         "gsf_step": [vp, ct.POINTER(gsf_step_args)],
         "gsf_step_capture": [vp, ct.POINTER(gsf_step_args)],
         "gsf_step_replay": [vp],

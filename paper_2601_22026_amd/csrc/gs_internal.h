@@ -212,6 +212,21 @@ void launch_adam_masked(hipStream_t s, float *p, const float *g, float *m, float
 // m[0..n) = v[0..n) = 0 and step[0] = 0, by a kernel (graph-capturable).
 void launch_adam_reset(hipStream_t s, float *m, float *v, int64_t n, int32_t *step);
 
+// Depth-guided reprojection constants (matrices composed and inverted on the
+// host in double, stored as float), opaque outside reproject.hip.
+struct ReprojConstOpaque {
+    alignas(16) unsigned char bytes[160];
+};
+// False when P_old V_old is singular or a value is not finite.
+bool make_reproj(const float *p_old, const float *v_old, const float *pos_old, const float *p_new,
+                 const float *v_new, int width, int height, ReprojConstOpaque *out);
+// clip [4][H][W] of every pixel (NaN where the depth is not finite and positive).
+void launch_reproject(hipStream_t s, const ReprojConstOpaque &k, const float *depth, float *clip);
+// Forward warp of rgba [4][H][W] to [4][out_h][out_w] (zbuf: out_w * out_h words).
+void launch_reproject_warp(hipStream_t s, const ReprojConstOpaque &k, const float *rgba,
+                           const float *depth, int out_w, int out_h, unsigned long long *zbuf,
+                           float *out_rgba, int32_t *src);
+
 // Seeding from a device volume (synchronises); scratch: seed_scratch_bytes(n^3).
 hipError_t run_seed(hipStream_t s, const uint16_t *vol, int n, double thr, double range,
                     const double *lo, const double *hi, double opacity, int64_t cap, uint64_t seed,

@@ -738,6 +738,46 @@ gsf_status gsf_adam_reset(gsf_ctx *ctx, float *m, float *v, int64_t n_elems, int
     return GSF_OK;
 }
 
+gsf_status gsf_reproject(gsf_ctx *ctx, const float *depth, int32_t width, int32_t height,
+                         const float *p_old, const float *v_old, const float *pos_old,
+                         const float *p_new, const float *v_new, float *clip) {
+    if (!ctx) return GSF_E_INVALID;
+    if (!depth || !p_old || !v_old || !pos_old || !p_new || !v_new || !clip)
+        return fail(ctx, GSF_E_INVALID, "gsf_reproject: null argument");
+    if (width < 1 || height < 1 || width > 16384 || height > 16384)
+        return fail(ctx, GSF_E_INVALID, "gsf_reproject: image size out of range");
+    ReprojConstOpaque k;
+    if (!make_reproj(p_old, v_old, pos_old, p_new, v_new, width, height, &k))
+        return fail(ctx, GSF_E_INVALID, "gsf_reproject: singular P_old V_old or a non-finite value");
+    launch_reproject(ctx->stream, k, depth, clip);
+    GSF_LAUNCHED(ctx);
+    return GSF_OK;
+}
+
+gsf_status gsf_reproject_warp(gsf_ctx *ctx, const float *rgba, const float *depth, int32_t width,
+                              int32_t height, const float *p_old, const float *v_old,
+                              const float *pos_old, const float *p_new, const float *v_new,
+                              int32_t out_width, int32_t out_height, uint64_t *zbuf,
+                              float *out_rgba, int32_t *out_src) {
+    if (!ctx) return GSF_E_INVALID;
+    if (!rgba || !depth || !p_old || !v_old || !pos_old || !p_new || !v_new || !zbuf || !out_rgba ||
+        !out_src)
+        return fail(ctx, GSF_E_INVALID, "gsf_reproject_warp: null argument");
+    if (width < 1 || height < 1 || width > 16384 || height > 16384 || out_width < 1 ||
+        out_height < 1 || out_width > 16384 || out_height > 16384)
+        return fail(ctx, GSF_E_INVALID, "gsf_reproject_warp: image size out of range");
+    if (((uintptr_t)zbuf & 7u) != 0)
+        return fail(ctx, GSF_E_INVALID, "gsf_reproject_warp: zbuf must be 8-byte aligned");
+    ReprojConstOpaque k;
+    if (!make_reproj(p_old, v_old, pos_old, p_new, v_new, width, height, &k))
+        return fail(ctx, GSF_E_INVALID,
+                    "gsf_reproject_warp: singular P_old V_old or a non-finite value");
+    launch_reproject_warp(ctx->stream, k, rgba, depth, out_width, out_height,
+                          (unsigned long long *)zbuf, out_rgba, out_src);
+    GSF_LAUNCHED(ctx);
+    return GSF_OK;
+}
+
 gsf_status gsf_step(gsf_plan *p, const gsf_step_args *a) {
     gsf_status st = check_ready(p);
     if (st != GSF_OK) return st;
