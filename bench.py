@@ -262,13 +262,101 @@ def cpu_baseline(wl, targets_np, budget_s=15.0):
                       f"per pixel)"}
 
 
+def bench_reproject(args):
+    """Viewer-side workload: the depth-guided reprojection warp of one eye's
+    foveal image (2064 x 2208, the stereo rig's eye resolution; the paper's
+    512 x 512 foveal size is timed too) to the head pose a frame later."""
+    import numpy as np
+    import torch
+
+    import paper_2601_22026_amd as gs
+    import synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.Stream(dev)
+    sizes = [(2064, 2208), (512, 512)]
+    out = {}
+    with torch.cuda.stream(stream):
+        ctx = gs.Context(0)
+        for (w, h) in sizes:
+            old = synth.look_at_camera([0.2, -0.1, -2.5], [0.0, 0.0, 0.0], w, h, 60.0)
+            new = synth.look_at_camera([0.23, -0.09, -2.52], [0.03, 0.02, 0.0], w, h, 60.0)
+            depth = synth.sphere_depth(old, radius=1.0)
+            rgba = np.random.default_rng(synth.SEED_GAUSSIANS).uniform(size=(4, h, w)).astype(np.float32)
+            P0, V0 = synth.clip_matrices(old)
+            P1, V1 = synth.clip_matrices(new)
+            d_dev = torch.from_numpy(depth).to(dev)
+            c_dev = torch.from_numpy(rgba).to(dev)
+            zbuf = torch.empty(w * h, dtype=torch.int64, device=dev)
+            res = {}
+
+            def warp():
+                res["o"] = gs.reproject_warp(ctx, c_dev, d_dev, P0, V0, old.campos, P1, V1, w, h,
+                                             zbuf=zbuf)
+            warp()
+            torch.cuda.synchronize()
+            # the three launches captured once and replayed, so host call overhead
+            # stays out of the timed region
+            graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(graph, stream=stream):
+                warp()
+            for _ in range(args.warmup):
+                graph.replay()
+            ms = time_steps(graph.replay, args.steps, stream)
+            landed = int((res["o"][1] >= 0).sum().item())
+            # algorithmic bytes: depth and colour in, z-buffer cleared, one 64-bit
+            # atomic per landing point, resolve reads the z-buffer and the winner's
+            # colour and writes colour and source index
+            bytes_ = 4 * w * h + 8 * w * h + 16 * landed + 8 * w * h + 16 * landed + 20 * w * h
+            out[(w, h)] = {"ms": ms, "mpix_per_s": w * h / (ms * 1e-3) / 1e6, "bytes": bytes_,
+                           "landed": landed}
+            log(f"[bench] reproject {w}x{h}: {ms * 1e3:.1f} us per warp, landed {landed}, "
+                f"{bytes_ / (ms * 1e-3) / 1e9:.0f} GB/s")
+    main_w, main_h = sizes[0]
+    r = out[sizes[0]]
+    gbs = r["bytes"] / (r["ms"] * 1e-3) / 1e9
+    res = {
+        "metric": METRIC, "value": round(r["mpix_per_s"], 1), "unit": "Mpix/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(r["ms"], 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic: unit-sphere first-hit depth, seeded colours, 3 cm / 1 degree head motion",
+        "config": {"workload": f"depth-guided reprojection warp of a {main_w}x{main_h} foveal image "
+                               "to the next head pose (Eqs. (2)-(4), nearest-wins forward warp)",
+                   "name": "reproject", "width": main_w, "height": main_h},
+        "paper_foveal_512": {"us_per_warp": round(out[(512, 512)]["ms"] * 1e3, 2),
+                             "mpix_per_s": round(out[(512, 512)]["mpix_per_s"], 1)},
+        "roofline": {"kernel": "reproject_warp (clear, splat, resolve)", "bound": "hbm",
+                     "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": None},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        w, h = 512, 512
+        old = synth.look_at_camera([0.2, -0.1, -2.5], [0.0, 0.0, 0.0], w, h, 60.0)
+        new = synth.look_at_camera([0.23, -0.09, -2.52], [0.03, 0.02, 0.0], w, h, 60.0)
+        depth = synth.sphere_depth(old, radius=1.0)
+        rgba = np.random.default_rng(synth.SEED_GAUSSIANS).uniform(size=(4, h, w))
+        P0, V0 = synth.clip_matrices(old)
+        P1, V1 = synth.clip_matrices(new)
+        t0 = time.perf_counter()
+        oracle.reproject_warp(rgba, depth, P0, V0, old.campos, P1, V1, w, h)
+        dt = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": round(w * h / dt / 1e6, 4), "unit": "Mpix/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"one 512x512 warp in {dt:.2f} s (numpy, one thread)"}
+    else:
+        res["cpu_baseline"] = None
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="phantom",
-                    choices=["small", "phantom", "batched", "foveal", "stereo"])
+                    choices=["small", "phantom", "batched", "foveal", "stereo", "reproject"])
     ap.add_argument("--tile", type=int, default=16)
     ap.add_argument("--lds-batch", type=int, default=128)
     ap.add_argument("--t-mode", type=int, default=1, choices=[0, 1, 2],
@@ -303,6 +391,10 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
               "sharding of this path is described in DESIGN.md but not built.", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "reproject":
+        bench_reproject(args)
+        return
 
     import numpy as np
     import torch
