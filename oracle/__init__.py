@@ -68,6 +68,9 @@ def lib():
                                ct.c_double, ct.c_int64]
         L.orc_adam.restype = None
         L.orc_sh_basis.argtypes = [ct.c_int, dp, ct.c_int64, dp]
+        L.orc_first_hits.argtypes = [ct.c_void_p, ct.c_int, dp, ct.c_int, ct.c_double, ct.c_double,
+                                     ct.c_double, ct.c_double, dp, dp, ct.c_double, ct.c_int, i32p,
+                                     dp, dp, dp]
         L.orc_num_threads.restype = ct.c_int
         _lib = L
     return _lib
@@ -456,3 +459,59 @@ def reproject_warp(rgba, depth, P_old, V_old, pos_old, P_new, V_new, out_w, out_
                 if 0 <= yy < out_h and 0 <= xx < out_w:
                     flags[yy * out_w + xx] = True
     return out.reshape(4, out_h, out_w), who.reshape(out_h, out_w), flags.reshape(out_h, out_w)
+
+
+# ------------------------------------------------------------ first-hit point cloud
+def first_hits(vol, cams, step, extinction, threshold, range_, lo, hi, hit_alpha=0.5,
+               color_steps=8):
+    """Per pixel-centre ray of every camera (rays in view, row, column order):
+    dict(hit bool [R], pos [R][3], col [R][3], margin [R]) as defined in
+    orc_first_hits."""
+    vol = np.ascontiguousarray(vol, np.uint16)
+    n = vol.shape[0]
+    C = _d(np.concatenate([cam_array(c) for c in cams]))
+    R = sum(c.width * c.height for c in cams)
+    hit = np.zeros(R, np.int32)
+    pos = np.zeros((R, 3))
+    col = np.zeros((R, 3))
+    margin = np.zeros(R)
+    lib().orc_first_hits(vol.ctypes.data_as(ct.c_void_p), n, _p(C), len(cams), float(step),
+                         float(extinction), float(threshold), float(range_), _p(_d(lo)), _p(_d(hi)),
+                         float(hit_alpha), int(color_steps), _p(hit, ct.c_int32), _p(pos), _p(col),
+                         _p(margin))
+    return {"hit": hit.astype(bool), "pos": pos, "col": col, "margin": margin}
+
+
+def ray_priority(idx, seed: int, n_rays: int) -> np.ndarray:
+    """Cap priority of ray idx: SplitMix64 output idx + 1 from state seed with
+    its low b bits (b = bits of n_rays - 1) replaced by idx (distinct)."""
+    b = max(1, int(n_rays - 1).bit_length())
+    out = np.zeros(len(idx), np.uint64)
+    for q, r in enumerate(np.asarray(idx, np.int64)):
+        h = splitmix64(seed, int(r) + 1)
+        out[q] = np.uint64(((h >> b) << b) | int(r))
+    return out
+
+
+def seed_first_hits(vol, cams, cap, seed, step, extinction, threshold, range_, lo, hi,
+                    hit_alpha=0.5, color_steps=8, opacity=0.1, flag_margin=1e-4):
+    """Gaussians at the first significant hits (Method, "Volumetric Path
+    Tracing"): one per hit ray, capped to the `cap` rays of smallest
+    ray_priority, in ray order; mean at the hit, isotropic scale of one voxel,
+    identity rotation, the given opacity, the hit colour as degree-0 SH.
+    Returns (params [14][m] float64, ray ids [m], flagged ray ids): a ray is
+    flagged when its hit decision lies within flag_margin of the threshold."""
+    n = np.asarray(vol).shape[0]
+    h = first_hits(vol, cams, step, extinction, threshold, range_, lo, hi, hit_alpha, color_steps)
+    R = h["hit"].size
+    idx = np.nonzero(h["hit"])[0]
+    if idx.size > cap:
+        pri = ray_priority(idx, seed, R)
+        idx = np.sort(idx[np.argsort(pri, kind="stable")[:cap]])
+    P = np.zeros((14, idx.size))
+    P[0:3] = h["pos"][idx].T
+    P[3:6] = math.log(2.0 / n)
+    P[6] = 1.0
+    P[10] = math.log(opacity / (1.0 - opacity))
+    P[11:14] = ((h["col"][idx] - 0.5) / (0.5 / math.sqrt(math.pi))).T
+    return P, idx, np.nonzero(h["margin"] < flag_margin)[0]

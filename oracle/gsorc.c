@@ -841,6 +841,120 @@ void orc_adam(double *p, const double *g, double *m, double *v, int64_t n, doubl
     }
 }
 
+/* ------------------------------------------------------- first-hit point cloud */
+/* Initial point cloud (Method, "Volumetric Path Tracing"): rays are cast at the
+ * volume from several viewpoints, the first significant hit of each ray is
+ * kept and coloured.  Each pixel-centre ray of each camera is marched through
+ * the volume box [-1, 1]^3 in segments of length `step` from the box entry
+ * (the last one shortened to the exit), each sampled at its midpoint: raw
+ * value v trilinear in the grid (voxel centres at (idx + 1/2) 2/n - 1, zero
+ * outside), density t = clamp((v - thr) / range, 0, 1), segment opacity
+ * 1 - exp(-extinction t length).  The hit is the midpoint of the first
+ * segment after which the accumulated opacity 1 - T reaches hit_alpha.  Its
+ * colour is the emission-absorption colour (lo (1 - t) + hi t) of that
+ * segment and the next color_steps - 1 segments (or up to the exit), composited
+ * from opacity zero, divided by their accumulated opacity.
+ * hit [R]: 1 / 0; pos [R][3]; col [R][3]; margin [R]: the smallest
+ * |1 - T - hit_alpha| after any segment up to the decision (the whole ray
+ * when there is no hit).  R = sum over views of width * height, rays in view,
+ * row, column order. */
+static double vol_sample(const uint16_t *vol, int n, const double p[3]) {
+    double u[3], f[3];
+    int64_t i0[3];
+    for (int a = 0; a < 3; a++) {
+        u[a] = (p[a] + 1.0) * 0.5 * n - 0.5;
+        const double fl = floor(u[a]);
+        i0[a] = (int64_t)fl;
+        f[a] = u[a] - fl;
+    }
+    double acc = 0.0;
+    for (int c = 0; c < 8; c++) {
+        const int64_t i = i0[0] + (c >> 2 & 1), j = i0[1] + (c >> 1 & 1), k = i0[2] + (c & 1);
+        if (i < 0 || i >= n || j < 0 || j >= n || k < 0 || k >= n) continue;
+        const double w = ((c >> 2 & 1) ? f[0] : 1.0 - f[0]) * ((c >> 1 & 1) ? f[1] : 1.0 - f[1]) *
+                         ((c & 1) ? f[2] : 1.0 - f[2]);
+        acc += w * (double)vol[(i * n + j) * n + k];
+    }
+    return acc;
+}
+
+int orc_first_hits(const uint16_t *vol, int n, const double *cams, int nviews, double step,
+                   double extinction, double thr, double range, const double *lo, const double *hi,
+                   double hit_alpha, int color_steps, int32_t *hit, double *pos, double *col,
+                   double *margin) {
+    int64_t base = 0;
+    for (int v = 0; v < nviews; v++) {
+        const double *cam = cams + 27 * v;
+        const int64_t W = (int64_t)cam[C_W], H = (int64_t)cam[C_H];
+#pragma omp parallel for schedule(dynamic, 4)
+        for (int64_t j = 0; j < H; j++)
+            for (int64_t i = 0; i < W; i++) {
+                const int64_t r = base + j * W + i;
+                const double dc[3] = {((double)i + 0.5 - cam[C_CX]) / cam[C_FX],
+                                      ((double)j + 0.5 - cam[C_CY]) / cam[C_FY], 1.0};
+                double d[3], o[3], nn = 0.0;
+                for (int a = 0; a < 3; a++) {   /* world direction R^T dc */
+                    d[a] = cam[C_R + a] * dc[0] + cam[C_R + 3 + a] * dc[1] + cam[C_R + 6 + a] * dc[2];
+                    nn += d[a] * d[a];
+                    o[a] = cam[C_CAMPOS + a];
+                }
+                nn = sqrt(nn);
+                double t0 = -INFINITY, t1 = INFINITY;
+                for (int a = 0; a < 3; a++) {
+                    d[a] /= nn;
+                    double ta = (-1.0 - o[a]) / d[a], tb = (1.0 - o[a]) / d[a];
+                    if (ta > tb) { const double x = ta; ta = tb; tb = x; }
+                    if (ta > t0) t0 = ta;
+                    if (tb < t1) t1 = tb;
+                }
+                if (t0 < 0.0) t0 = 0.0;
+                hit[r] = 0;
+                margin[r] = INFINITY;
+                for (int a = 0; a < 3; a++) pos[3 * r + a] = col[3 * r + a] = 0.0;
+                if (!(t1 > t0)) continue;
+                double T = 1.0;
+                int64_t khit = -1;
+                for (int64_t k = 0;; k++) {
+                    const double s0 = t0 + (double)k * step;
+                    double s1 = s0 + step;
+                    if (s1 > t1) s1 = t1;
+                    if (!(s1 > s0)) break;
+                    const double mid = 0.5 * (s0 + s1), p[3] = {o[0] + d[0] * mid, o[1] + d[1] * mid,
+                                                                o[2] + d[2] * mid};
+                    double t = (vol_sample(vol, n, p) - thr) / range;
+                    t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+                    T *= exp(-extinction * t * (s1 - s0));
+                    const double gap = fabs(1.0 - T - hit_alpha);
+                    if (gap < margin[r]) margin[r] = gap;
+                    if (1.0 - T >= hit_alpha) {
+                        khit = k;
+                        for (int a = 0; a < 3; a++) pos[3 * r + a] = p[a];
+                        break;
+                    }
+                }
+                if (khit < 0) continue;
+                hit[r] = 1;
+                double C[3] = {0.0, 0.0, 0.0}, Ts = 1.0;
+                for (int64_t k = khit; k < khit + color_steps; k++) {
+                    const double s0 = t0 + (double)k * step;
+                    double s1 = s0 + step;
+                    if (s1 > t1) s1 = t1;
+                    if (!(s1 > s0)) break;
+                    const double mid = 0.5 * (s0 + s1), p[3] = {o[0] + d[0] * mid, o[1] + d[1] * mid,
+                                                                o[2] + d[2] * mid};
+                    double t = (vol_sample(vol, n, p) - thr) / range;
+                    t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+                    const double alpha = 1.0 - exp(-extinction * t * (s1 - s0));
+                    for (int a = 0; a < 3; a++) C[a] += (lo[a] * (1.0 - t) + hi[a] * t) * alpha * Ts;
+                    Ts *= 1.0 - alpha;
+                }
+                for (int a = 0; a < 3; a++) col[3 * r + a] = C[a] / (1.0 - Ts);
+            }
+        base += W * H;
+    }
+    return 0;
+}
+
 int orc_num_threads(void) {
 #ifdef _OPENMP
     return omp_get_max_threads();
