@@ -18,7 +18,9 @@
  *   continual refinement: gsf_view_select (Eq. (1), host), gsf_adam_reset
  *                 (restart with discarded optimiser state), gsf_adam_masked
  *                 and gsf_step_args.masked_adam (visibility-masked update)
- *   seeding: gsf_seed_volume (Gaussians from a CT volume), gsf_raymarch
+ *   seeding: gsf_seed_volume (Gaussians from a CT volume's voxels),
+ *                 gsf_seed_first_hits (Gaussians at the first significant hits
+ *                 of rays from several viewpoints), gsf_raymarch
  *                 (emission-absorption target images)
  *   viewer: gsf_reproject, gsf_reproject_warp (depth-guided reprojection of
  *                 the foveal image)
@@ -30,8 +32,8 @@
  *   targets, cameras, workspace).  The library owns only the opaque host-side
  *   context and plan objects and the graphs it instantiates.
  * - Every call is asynchronous on the context's stream, except gsf_poll,
- *   gsf_debug_copy, gsf_seed_volume and (for plans created with
- *   host_sized = 1) gsf_forward, which synchronise that stream, and
+ *   gsf_debug_copy, gsf_seed_volume, gsf_seed_first_hits and (for plans
+ *   created with host_sized = 1) gsf_forward, which synchronise that stream, and
  *   gsf_view_select, which runs on the host only.
  * - Errors: every call returns a gsf_status; no exception crosses the ABI.
  *   Argument errors are detected on the host before anything is enqueued.
@@ -327,6 +329,37 @@ gsf_status gsf_step_replay(gsf_plan *plan);
  * *count (host) = m = min(candidates, cap).  scratch: device memory of
  * gsf_seed_scratch_bytes(n) bytes.  Synchronises the context stream. */
 gsf_status gsf_seed_scratch_bytes(int32_t n, size_t *bytes);
+
+/* First-hit point cloud (Method, "Volumetric Path Tracing": rays cast at the
+ * volume from viewpoints around it; the first significant hit of each ray
+ * becomes a point, coloured by marching on from it).  Every pixel-centre ray of
+ * the n_views cameras (device gsf_camera array; widths, heights: host, must
+ * equal the cameras' sizes; rays numbered in view, row, column order) is
+ * marched through [-1, 1]^3 as gsf_raymarch does (segments of `step` from the
+ * box entry, midpoint samples, t = clamp((v - threshold) / range, 0, 1),
+ * segment opacity 1 - exp(-extinction t length)).  The hit is the midpoint of
+ * the first segment after which the accumulated opacity reaches hit_alpha
+ * (in (0, 1)); its colour is the emission-absorption colour lo (1 - t) + hi t
+ * (lo, hi: host [3]) of that segment and the next color_steps - 1 (or up to the
+ * exit) composited from zero opacity, divided by their accumulated opacity.
+ * Above cap hits, the cap rays with the smallest priority are kept (ray r:
+ * SplitMix64 output r + 1 from state seed with its low b bits replaced by r,
+ * b = bits of (rays - 1)), in ray order.  Each point becomes a Gaussian: mean at
+ * the hit, log-scale ln(2/n), rotation (1, 0, 0, 0), opacity logit
+ * ln(o / (1 - o)), degree-0 SH (colour - 1/2) / Y00; the march runs in float.
+ * params: device float with room for 14 * cap values, written planar [14][m];
+ * ray_ids: nullable device int32 [cap], the ray of each Gaussian; *count (host)
+ * = m.  scratch: device memory of gsf_first_hit_scratch_bytes(rays) bytes,
+ * 256-byte aligned.  Synchronises the context stream.  GSF_E_INVALID for null
+ * pointers, sizes or parameters out of range or a short scratch. */
+gsf_status gsf_first_hit_scratch_bytes(int64_t n_rays, size_t *bytes);
+gsf_status gsf_seed_first_hits(gsf_ctx *ctx, const uint16_t *vol, int32_t n, const gsf_camera *cams,
+                               int32_t n_views, const int32_t *widths, const int32_t *heights,
+                               float step, float extinction, float threshold, float range,
+                               const float *lo, const float *hi, float hit_alpha,
+                               int32_t color_steps, double opacity, int64_t cap, uint64_t seed,
+                               float *params, int32_t *ray_ids, int64_t *count, void *scratch,
+                               size_t scratch_bytes);
 gsf_status gsf_seed_volume(gsf_ctx *ctx, const uint16_t *vol, int32_t n, double threshold,
                            double range, const double *lo, const double *hi, double opacity,
                            int64_t cap, uint64_t seed, float *params, int64_t *count,

@@ -29,7 +29,8 @@ from ._abi import GsfError, gsf_camera, gsf_plan_desc, gsf_step_args, lib
 
 __all__ = ["GsfError", "Context", "Plan", "rasterize", "adam", "adam_masked", "adam_reset",
            "FitStep", "FitConfig", "autotune", "select_views", "plane_learning_rates", "Refiner",
-           "seed_volume", "raymarch", "reproject", "reproject_warp", "pack_cameras", "cameras_to_device", "n_planes", "lib"]
+           "seed_volume", "seed_first_hits", "raymarch", "reproject", "reproject_warp",
+           "pack_cameras", "cameras_to_device", "n_planes", "lib"]
 
 
 def n_planes(sh_degree: int) -> int:
@@ -536,6 +537,42 @@ class Refiner:
             raise GsfError(_abi.GSF_E_STATE, "restart() first")
         for _ in range(int(steps)):
             self.fit.replay()
+
+
+def seed_first_hits(ctx: Context, vol: torch.Tensor, cams, cap: int, seed: int, step: float,
+                    extinction: float = 40.0, threshold: float = 1200.0, range_: float = 1800.0,
+                    lo=(0.8, 0.3, 0.2), hi=(1.0, 0.95, 0.9), hit_alpha: float = 0.5,
+                    color_steps: int = 8, opacity: float = 0.1):
+    """gsf_seed_first_hits: Gaussians at the first significant hits of every
+    pixel ray of `cams` (planar float32 [14][m]) and the ray of each (int32 [m]).
+    Synchronises."""
+    n = int(vol.shape[0])
+    cams = list(cams)
+    dev = vol.device
+    cams_dev = cameras_to_device(cams, dev)
+    ws = (ct.c_int32 * len(cams))(*[c.width for c in cams])
+    hs = (ct.c_int32 * len(cams))(*[c.height for c in cams])
+    nrays = sum(c.width * c.height for c in cams)
+    nb = ct.c_size_t()
+    ctx.check(lib().gsf_first_hit_scratch_bytes(nrays, ct.byref(nb)), "gsf_first_hit_scratch_bytes")
+    scratch = torch.empty(int(nb.value) + 256, dtype=torch.uint8, device=dev)
+    base = scratch.data_ptr()
+    aligned = (base + 255) & ~255
+    out = torch.empty(14 * int(cap), dtype=torch.float32, device=dev)
+    ids = torch.empty(int(cap), dtype=torch.int32, device=dev)
+    m = ct.c_int64()
+    lo_a = (ct.c_float * 3)(*[float(x) for x in lo])
+    hi_a = (ct.c_float * 3)(*[float(x) for x in hi])
+    ctx.use_stream()
+    ctx.check(lib().gsf_seed_first_hits(ctx.handle, _ptr(vol), n, _ptr(cams_dev), len(cams), ws, hs,
+                                        float(step), float(extinction), float(threshold),
+                                        float(range_), lo_a, hi_a, float(hit_alpha),
+                                        int(color_steps), float(opacity), int(cap),
+                                        int(seed) & ((1 << 64) - 1), _ptr(out), _ptr(ids),
+                                        ct.byref(m), ct.c_void_p(aligned), nb.value),
+              "gsf_seed_first_hits")
+    k = int(m.value)
+    return out[:14 * k].view(14, k), ids[:k]
 
 
 def _mat16(m):

@@ -27,7 +27,8 @@ EXPORTED = ["gsf_ctx_create", "gsf_ctx_destroy", "gsf_ctx_set_stream", "gsf_last
             "gsf_debug_copy", "gsf_plan_set_timing", "gsf_plan_stage_times",
             "gsf_count_pairs", "gsf_loss_l1_rgba", "gsf_seed_scratch_bytes",
             "gsf_seed_volume", "gsf_raymarch", "gsf_adam_masked", "gsf_adam_reset",
-            "gsf_view_select", "gsf_reproject", "gsf_reproject_warp"]
+            "gsf_view_select", "gsf_reproject", "gsf_reproject_warp",
+            "gsf_first_hit_scratch_bytes", "gsf_seed_first_hits"]
 STAGES = ["project", "duplicate", "tile_sort", "ranges", "depth_sort", "render", "loss",
           "render_bwd", "project_bwd", "adam", "zero"]
 
@@ -92,6 +93,10 @@ def _declare(L):
         "gsf_view_select": [ct.POINTER(gsf_camera), i32, ct.POINTER(gsf_camera), i32, f32, f32,
                             ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int32)],
         "gsf_reproject": [vp, vp, i32, i32, pf, pf, pf, pf, pf, vp],
+        "gsf_first_hit_scratch_bytes": [i64, ct.POINTER(ct.c_size_t)],
+        "gsf_seed_first_hits": [vp, vp, i32, vp, i32, ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int32),
+                                f32, f32, f32, f32, pf, pf, f32, i32, ct.c_double, i64, ct.c_uint64,
+                                vp, vp, ct.POINTER(ct.c_int64), vp, ct.c_size_t],
         "gsf_reproject_warp": [vp, vp, vp, i32, i32, pf, pf, pf, pf, pf, i32, i32, vp, vp, vp],
         "gsf_step": [vp, ct.POINTER(gsf_step_args)],
         "gsf_step_capture": [vp, ct.POINTER(gsf_step_args)],

@@ -227,6 +227,17 @@ void launch_reproject_warp(hipStream_t s, const ReprojConstOpaque &k, const floa
                            const float *depth, int out_w, int out_h, unsigned long long *zbuf,
                            float *out_rgba, int32_t *src);
 
+// First-hit point cloud (synchronises): Gaussians at the first significant hit
+// of every pixel ray of the cameras, capped by ray priority; scratch:
+// first_hit_scratch_bytes(total rays).
+size_t first_hit_scratch_bytes(int64_t nrays);
+hipError_t run_first_hits(hipStream_t s, const uint16_t *vol, int n, const gsf_camera *cams,
+                          int nviews, const int32_t *widths, const int32_t *heights, float step,
+                          float extinction, float thr, float range, const float *lo, const float *hi,
+                          float hit_alpha, int color_steps, double opacity, int64_t cap,
+                          uint64_t seed, float *params, int64_t *count, int32_t *ray_ids,
+                          void *scratch);
+
 // Seeding from a device volume (synchronises); scratch: seed_scratch_bytes(n^3).
 hipError_t run_seed(hipStream_t s, const uint16_t *vol, int n, double thr, double range,
                     const double *lo, const double *hi, double opacity, int64_t cap, uint64_t seed,

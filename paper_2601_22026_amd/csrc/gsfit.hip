@@ -738,6 +738,47 @@ gsf_status gsf_adam_reset(gsf_ctx *ctx, float *m, float *v, int64_t n_elems, int
     return GSF_OK;
 }
 
+gsf_status gsf_first_hit_scratch_bytes(int64_t n_rays, size_t *bytes) {
+    if (!bytes || n_rays < 1 || n_rays > 0x7FFFFFFFll) return GSF_E_INVALID;
+    *bytes = first_hit_scratch_bytes(n_rays);
+    return GSF_OK;
+}
+
+gsf_status gsf_seed_first_hits(gsf_ctx *ctx, const uint16_t *vol, int32_t n, const gsf_camera *cams,
+                               int32_t n_views, const int32_t *widths, const int32_t *heights,
+                               float step, float extinction, float threshold, float range,
+                               const float *lo, const float *hi, float hit_alpha,
+                               int32_t color_steps, double opacity, int64_t cap, uint64_t seed,
+                               float *params, int32_t *ray_ids, int64_t *count, void *scratch,
+                               size_t scratch_bytes) {
+    if (!ctx) return GSF_E_INVALID;
+    if (!vol || !cams || !widths || !heights || !lo || !hi || !params || !count || !scratch)
+        return fail(ctx, GSF_E_INVALID, "gsf_seed_first_hits: null argument");
+    if (n < 1 || n > 2048 || n_views < 1 || n_views > kMaxViews || cap < 1)
+        return fail(ctx, GSF_E_INVALID, "gsf_seed_first_hits: n, n_views or cap out of range");
+    int64_t nrays = 0;
+    for (int v = 0; v < n_views; v++) {
+        if (widths[v] < 1 || heights[v] < 1 || widths[v] > 8192 || heights[v] > 8192)
+            return fail(ctx, GSF_E_INVALID, "gsf_seed_first_hits: image size out of range");
+        nrays += (int64_t)widths[v] * heights[v];
+    }
+    if (nrays > 0x7FFFFFFFll)
+        return fail(ctx, GSF_E_INVALID, "gsf_seed_first_hits: more than 2^31 - 1 rays");
+    if (!(step > 0.f) || !(range > 0.f) || !(extinction >= 0.f) || !(hit_alpha > 0.f) ||
+        !(hit_alpha < 1.f) || color_steps < 1 || !(opacity > 0.0) || !(opacity < 1.0))
+        return fail(ctx, GSF_E_INVALID,
+                    "gsf_seed_first_hits: step, range, extinction, hit_alpha, color_steps or "
+                    "opacity invalid");
+    if (scratch_bytes < first_hit_scratch_bytes(nrays))
+        return fail(ctx, GSF_E_INVALID, "gsf_seed_first_hits: scratch too small");
+    if (((uintptr_t)scratch & 255u) != 0)
+        return fail(ctx, GSF_E_INVALID, "gsf_seed_first_hits: scratch must be 256-byte aligned");
+    GSF_HIP(ctx, run_first_hits(ctx->stream, vol, n, cams, n_views, widths, heights, step,
+                                extinction, threshold, range, lo, hi, hit_alpha, color_steps,
+                                opacity, cap, seed, params, count, ray_ids, scratch));
+    return GSF_OK;
+}
+
 gsf_status gsf_reproject(gsf_ctx *ctx, const float *depth, int32_t width, int32_t height,
                          const float *p_old, const float *v_old, const float *pos_old,
                          const float *p_new, const float *v_new, float *clip) {
