@@ -284,6 +284,8 @@ __device__ __forceinline__ void render_bwd_unit(
     const size_t plane = (size_t)vd.width * vd.height;
     const float *dimg = dl + 4 * (size_t)vd.pix_off;
 
+    // gR: dL/dC-weighted colour behind the current splat, less gA Tf (the alpha
+    // plane's share), carried as one value since only that difference is used
     float px[PPT], py[PPT], Tr[PPT], Tf[PPT], gR[PPT], g0[PPT], g1[PPT], g2[PPT], gA[PPT];
     uint32_t nc[PPT];
     uint32_t my_max = 0;
@@ -319,6 +321,7 @@ __device__ __forceinline__ void render_bwd_unit(
             Tr[k] = Tf[k];
             gR[k] = gbg;
         }
+        gR[k] -= gA[k] * Tf[k];
         my_max = max(my_max, nc[k]);
     }
     __syncthreads();
@@ -381,18 +384,18 @@ __device__ __forceinline__ void render_bwd_unit(
                     Tb = inc ? tstore[(size_t)(bs + (uint32_t)j) * (T * T) + threadIdx.x + k * NT] : 0.f;
                 else
                     Tb = Tr[k] * inv;
-                const float gc = g0[k] * b.z + g1[k] * b.w + g2[k] * c.x;
-                const float dalpha = Tb * gc - (gR[k] - gA[k] * Tf[k]) * inv;
+                const float gc = fmaf(g2[k], c.x, fmaf(g1[k], b.w, g0[k] * b.z));
+                const float dalpha = fmaf(Tb, gc, -(gR[k] * inv));
                 const float wT = inc ? alpha * Tb : 0.f;
-                acc[6] += wT * g0[k];
-                acc[7] += wT * g1[k];
-                acc[8] += wT * g2[k];
+                acc[6] = fmaf(wT, g0[k], acc[6]);
+                acc[7] = fmaf(wT, g1[k], acc[7]);
+                acc[8] = fmaf(wT, g2[k], acc[8]);
                 gR[k] = fmaf(gc, wT, gR[k]);
                 Tr[k] = inc ? Tb : Tr[k];
                 // a clamped alpha passes no gradient to the opacity or the power
                 const bool open = inc & !(ae > kAlphaMax);
-                const float dpw = open ? ae * dalpha : 0.f;   // d loss / d power (natural units)
-                acc[5] += open ? ex * dalpha : 0.f;
+                const float dpw = (open ? ae : 0.f) * dalpha;   // d loss / d power (natural units)
+                acc[5] = fmaf(open ? ex : 0.f, dalpha, acc[5]);
                 const float ux = dpw * dx, uy = dpw * dy;
                 acc[0] += ux;
                 acc[1] += uy;
