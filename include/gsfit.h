@@ -305,7 +305,12 @@ gsf_status gsf_loss_l1_rgba(gsf_plan *plan, const float *rgba, const float *targ
                             const float *bg, int32_t alpha, const float *gaze_px,
                             float mask_radius_frac, float *loss, float *dl_drgba);
 
-/* Enqueue one step eagerly. */
+/* Enqueue one step eagerly.  With host_sized = 0 the key count stays on the
+ * device: if it exceeds the plan's capacity the step sets GSF_FLAG_CAPACITY
+ * and leaves parameters, m, v and *step_dev untouched (its image, loss and
+ * gradients are undefined); every later step does the same until gsf_poll
+ * clears the flag, so after a re-plan with more capacity the same step can be
+ * run again. */
 gsf_status gsf_step(gsf_plan *plan, const gsf_step_args *args);
 /* Capture one step into a HIP graph owned by the plan (replaces any previous
  * one).  Needs host_sized = 0.  Nothing runs during capture. */

@@ -19,7 +19,8 @@
  *     out by the chain rule), with zero derivative through discrete decisions
  *     and active clamps;
  *   - the discrete stage (tile ids, sort order, ranges) is a nested loop plus
- *     qsort over (tile, fp32 depth bits, record) tuples;
+ *     qsort over (tile, fp32 depth bits, record) tuples; a record lists the
+ *     tiles of each row of its box that its padded support ellipse reaches;
  *   - Adam is the bias-corrected form (the paper's continual refinement restarts
  *     it by discarding its state, Method section, last paragraph of
  *     "Periphery Model Training").
@@ -77,6 +78,9 @@ static const double LOWPASS = 0.3;
 static const double JCLAMP = 1.3;
 static const double BOX_REL = 1e-4;
 static const double BOX_ABS = 1.0 / 64.0;
+/* boxes of at most this many tile rows list only the tiles their support
+ * ellipse reaches in each row; taller boxes list every tile of the box */
+#define SPAN_ROWS 32
 
 static int n_coeffs(int deg) { return (deg + 1) * (deg + 1); }
 
@@ -690,6 +694,44 @@ static int tile_rect(double e0, double e1, int64_t size, int tile, int64_t *t0, 
     return 1;
 }
 
+/* Tile columns [*c0, *c1] of tile row ty that the padded support ellipse
+ * reaches, or 0 when none.  The ellipse is q(d) = d^T Sigma'^-1 d <= Kp with
+ * Kp = 2 ln(255 o) (1 + BOX_REL)^2, d the offset of a pixel centre from the
+ * mean.  Over the row's pixel-centre band (rows ty T .. min(ty T + T, H) - 1)
+ * its x extent is taken where the ellipse's boundary is rightmost (leftmost)
+ * within the band, widened by BOX_ABS; the pixel columns whose centres lie in
+ * that extent, clamped to the image and to the record's tile rectangle
+ * [x0, x1], give the tiles.  `shift` moves both extents outward (> 0) or inward
+ * (< 0), for the rounding flags. */
+static int row_span(const double *r, int64_t ty, int tile, int64_t W, int64_t H, int64_t x0,
+                    int64_t x1, double shift, int64_t *c0, int64_t *c1) {
+    const double sa = r[R_SA], sb = r[R_SB], sc = r[R_SC];
+    const double Kp = 2.0 * log(255.0 * r[R_O]) * (1.0 + BOX_REL) * (1.0 + BOX_REL);
+    const int64_t ja = ty * tile, jb = (ty * tile + tile < H ? ty * tile + tile : H) - 1;
+    const double ya = (double)ja + 0.5 - r[R_MY], yb = (double)jb + 0.5 - r[R_MY];
+    const double ey = sqrt(Kp * sc);
+    double lo = ya > -ey ? ya : -ey, hi = yb < ey ? yb : ey;
+    if (lo > hi) lo = hi = (ya > ey ? ey : -ey);          /* band beside the ellipse: its tip */
+    const double slope = sb / sc, wid = sa - sb * sb / sc;
+    const double dyr = sb * sqrt(Kp / sa);                /* rows of the right- and leftmost points */
+    const double d1 = dyr < lo ? lo : (dyr > hi ? hi : dyr);
+    const double d2 = -dyr < lo ? lo : (-dyr > hi ? hi : -dyr);
+    const double h1 = Kp - d1 * d1 / sc, h2 = Kp - d2 * d2 / sc;
+    const double xr = slope * d1 + sqrt((h1 > 0 ? h1 : 0.0) * wid) + BOX_ABS + shift;
+    const double xl = slope * d2 - sqrt((h2 > 0 ? h2 : 0.0) * wid) - BOX_ABS - shift;
+    double a = ceil(r[R_MX] + xl - 0.5), b = floor(r[R_MX] + xr - 0.5);
+    if (a < 0) a = 0;
+    if (b > (double)(W - 1)) b = (double)(W - 1);
+    if (a > b) return 0;
+    int64_t t0 = (int64_t)a / tile, t1 = (int64_t)b / tile;
+    if (t0 < x0) t0 = x0;
+    if (t1 > x1) t1 = x1;
+    if (t0 > t1) return 0;
+    *c0 = t0;
+    *c1 = t1;
+    return 1;
+}
+
 /* Keys/values of all views ordered by (global tile, fp32 depth bits, record)
  * and the per-tile [start, end) ranges.  Records are r = v*n + i.  Returns the
  * key count in *m_out (keys beyond cap are counted but not written).
@@ -725,14 +767,34 @@ int orc_discrete(const double *P, int64_t n, int deg, const double *cams, int nv
                 int64_t x0, x1, y0, y1;
                 if (tile_rect(r[R_EX0], r[R_EX1], W, tile, &x0, &x1)
                     && tile_rect(r[R_EY0], r[R_EY1], H, tile, &y0, &y1)) {
-                    for (int64_t ty = y0; ty <= y1; ty++)
-                        for (int64_t tx = x0; tx <= x1; tx++) {
+                    const int spans = y1 - y0 + 1 <= SPAN_ROWS;   /* else the whole box */
+                    for (int64_t ty = y0; ty <= y1; ty++) {
+                        /* the tiles of this row the support ellipse reaches */
+                        int64_t s0 = x0, s1 = x1, p0, p1, q0, q1;
+                        if (!spans) {
+                            for (int64_t tx = s0; tx <= s1; tx++) {
+                                if (count == alloc) { alloc *= 2; list = realloc(list, sizeof(tkey) * alloc); }
+                                list[count].tile = total_tiles + ty * tw + tx;
+                                list[count].dbits = f32bits(r[R_TZ]);
+                                list[count].rec = (int64_t)v * n + i;
+                                count++;
+                            }
+                            continue;
+                        }
+                        const double m = 2e-4 + 4e-6 * (fabs(r[R_MX]) + fabs(r[R_EX1] - r[R_EX0]));
+                        const int in = row_span(r, ty, tile, W, H, x0, x1, 0.0, &s0, &s1);
+                        const int out = row_span(r, ty, tile, W, H, x0, x1, m, &p0, &p1);
+                        const int inw = row_span(r, ty, tile, W, H, x0, x1, -m, &q0, &q1);
+                        if (out != inw || (out && (p0 != q0 || p1 != q1))) fl |= F_NEAR_BOX;
+                        if (!in) continue;
+                        for (int64_t tx = s0; tx <= s1; tx++) {
                             if (count == alloc) { alloc *= 2; list = realloc(list, sizeof(tkey) * alloc); }
                             list[count].tile = total_tiles + ty * tw + tx;
                             list[count].dbits = f32bits(r[R_TZ]);
                             list[count].rec = (int64_t)v * n + i;
                             count++;
                         }
+                    }
                 }
             }
             rflags[(int64_t)v * n + i] = fl;

@@ -358,11 +358,8 @@ class FitStep:
             raise ValueError("alpha training, random backgrounds and the masked Adam are "
                              "fused-step options")
         if fused:
-            cap = cfg.key_capacity or self._measure_capacity()
-            self.plan = Plan(ctx, self.n, self.sizes, self.sh_degree, cfg.tile, cfg.lds_batch,
-                             host_sized=False, key_capacity=cap, t_mode=cfg.t_mode)
-            self.args = self._args(self.plan, self.cams_dev, self.targets, self.rgba, self.dl,
-                                   self.gaze)
+            self.key_capacity = cfg.key_capacity or self._measure_capacity()
+            self._make_plan()
         else:
             self.view_plans = []
             off = 0
@@ -374,6 +371,33 @@ class FitStep:
                 off += w * h
             self.view_grads = torch.zeros_like(params)
         self.captured = False
+
+    def _make_plan(self):
+        self.plan = Plan(self.ctx, self.n, self.sizes, self.sh_degree, self.cfg.tile,
+                         self.cfg.lds_batch, host_sized=False, key_capacity=self.key_capacity,
+                         t_mode=self.cfg.t_mode)
+        self.args = self._args(self.plan, self.cams_dev, self.targets, self.rgba, self.dl,
+                               self.gaze)
+
+    def ensure_capacity(self) -> bool:
+        """Poll the fused step's flags (synchronises).  After a key-capacity
+        overflow (the overflowing steps left parameters, moments and the step
+        counter as they were) re-plan with room for 1.5 times the keys needed
+        (at least twice the old capacity), recapture if captured, and return
+        True: the caller repeats the step.  Raises on a non-finite loss."""
+        if not self.fused:
+            raise GsfError(_abi.GSF_E_STATE, "the plain path reports overflow on each forward")
+        flags, m = self.plan.poll()
+        if flags & _abi.GSF_FLAG_NONFINITE:
+            raise GsfError(_abi.GSF_E_NONFINITE, "non-finite loss")
+        if not flags & _abi.GSF_FLAG_CAPACITY:
+            return False
+        self.plan.close()
+        self.key_capacity = max(2 * self.key_capacity, int(m * 1.5) + (1 << 16))
+        self._make_plan()
+        if self.captured:
+            self.capture()
+        return True
 
     def _measure_capacity(self) -> int:
         probe = Plan(self.ctx, self.n, self.sizes, self.sh_degree, self.cfg.tile,

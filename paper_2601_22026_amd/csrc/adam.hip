@@ -36,7 +36,9 @@ __device__ __forceinline__ void adam_one(float &p, float g, float &m, float &v, 
 __global__ __launch_bounds__(256) void k_adam(float *__restrict__ p, const float *__restrict__ g,
                                               float *__restrict__ m, float *__restrict__ v, int64_t n,
                                               SegTable seg, float b1, float b2, float eps,
-                                              const int32_t *__restrict__ step) {
+                                              const int32_t *__restrict__ step,
+                                              const uint32_t *__restrict__ skip) {
+    if (skip && (*skip & GSF_FLAG_CAPACITY)) return;   // the step's keys overflowed
     const float t = (float)step[0];
     const float ibc1 = 1.f / (1.f - powf(b1, t));
     const float ibc2 = 1.f / (1.f - powf(b2, t));
@@ -87,7 +89,9 @@ __global__ __launch_bounds__(256) void k_adam_masked(float *__restrict__ p,
                                                      int64_t n, PlaneLr lr,
                                                      const uint8_t *__restrict__ vis, float b1,
                                                      float b2, float eps,
-                                                     const int32_t *__restrict__ step) {
+                                                     const int32_t *__restrict__ step,
+                                                     const uint32_t *__restrict__ skip) {
+    if (skip && (*skip & GSF_FLAG_CAPACITY)) return;   // the step's keys overflowed
     const float t = (float)step[0];
     const float ibc1 = 1.f / (1.f - powf(b1, t));
     const float ibc2 = 1.f / (1.f - powf(b2, t));
@@ -132,12 +136,12 @@ void launch_visible(hipStream_t s, const uint32_t *count, int n, int nviews, uin
 
 void launch_adam_masked(hipStream_t s, float *p, const float *g, float *m, float *v, int64_t n,
                         int planes, const PlaneLr &lr, const uint8_t *vis, float b1, float b2,
-                        float eps, int32_t *step, bool advance) {
+                        float eps, int32_t *step, bool advance, const uint32_t *skip) {
     if (advance) k_step_inc<<<1, 64, 0, s>>>(step);
     int64_t bx = (n + 255) / 256;
     if (bx > 4096) bx = 4096;
     k_adam_masked<<<dim3((unsigned)bx, (unsigned)planes), 256, 0, s>>>(p, g, m, v, n, lr, vis, b1,
-                                                                        b2, eps, step);
+                                                                        b2, eps, step, skip);
 }
 
 void launch_adam_reset(hipStream_t s, float *m, float *v, int64_t n, int32_t *step) {
@@ -148,12 +152,13 @@ void launch_adam_reset(hipStream_t s, float *m, float *v, int64_t n, int32_t *st
 }
 
 void launch_adam(hipStream_t s, float *p, const float *g, float *m, float *v, int64_t n,
-                 const SegTable &seg, float b1, float b2, float eps, int32_t *step, bool advance) {
+                 const SegTable &seg, float b1, float b2, float eps, int32_t *step, bool advance,
+                 const uint32_t *skip) {
     if (advance) k_step_inc<<<1, 64, 0, s>>>(step);
     int64_t blocks = (n / 4 + 255) / 256;
     if (blocks < 1) blocks = 1;
     if (blocks > 8192) blocks = 8192;
-    k_adam<<<(int)blocks, 256, 0, s>>>(p, g, m, v, n, seg, b1, b2, eps, step);
+    k_adam<<<(int)blocks, 256, 0, s>>>(p, g, m, v, n, seg, b1, b2, eps, step, skip);
 }
 
 }  // namespace gsf

@@ -67,6 +67,60 @@ struct PlaneLr {
     float lr[kMaxPlanes];
 };
 
+// Support ellipse of a record for the tile lists, as the constants of its
+// row-wise x extent: for a row offset d from the mean the ellipse (quadratic
+// form <= Kp = 2 ln(255 o) (1 + kBoxRel)^2, covariance Sigma' = [sa sb; sb sc])
+// spans x in slope d +- sqrt(kw - ws d^2), with slope = sb / sc,
+// kw = Kp (sa - sb^2 / sc), ws = (sa - sb^2 / sc) / sc; its rightmost point
+// lies at row offset dyr = sb sqrt(Kp / sa) and its rows within +-ey,
+// ey = sqrt(Kp sc).  Plus the split-form mean (integer pixel ix, iy; offsets
+// hxo, hyo of that pixel's centre from the mean).
+struct Ellipse {
+    float slope, kw, ws, dyr, ey;
+    float hxo, hyo;
+    int ix, iy;
+};
+__device__ __forceinline__ float4 ellipse_pack(float sa, float sb, float sc, float Kp, float &ey) {
+    const float slope = sb / sc, wid = sa - sb * (sb / sc);
+    ey = sqrtf(Kp * sc);
+    return make_float4(slope, Kp * wid, wid / sc, sb * sqrtf(Kp / sa));
+}
+// Boxes of at most kSpanRows tile rows list only the tiles their ellipse
+// reaches in each row; taller boxes list every tile of the box.
+constexpr int kSpanRows = 32;
+// Boxes of at most kPackRows tile rows and kPackCols tile columns carry their
+// row spans packed (per row: first column - x0 in the low byte, tile count in
+// the high byte of a 16-bit field), so the duplicate pass needs no arithmetic.
+constexpr int kPackRows = 4;
+constexpr int kPackCols = 255;
+
+// Tile columns [c0, c1] of tile row ty that the padded support ellipse
+// reaches (false: none).  Over the row's band of pixel centres (rows ty T ..
+// min(ty T + T, H) - 1) the ellipse's x extent is taken where its boundary is
+// right- (left-)most within the band, widened by kBoxAbs; the pixel columns
+// whose centres lie in it, clamped to the image width W and to the box's tile
+// columns [x0, x1], give the tiles.  Every pixel with alpha >= 1/255 lies in
+// such a tile.
+// tile = 1 << tile_log2.  The square roots are the hardware's (within an ulp):
+// the same code counts the tiles in the projection and emits them in the
+// duplicate pass, so both agree exactly.
+__device__ __forceinline__ bool row_span(const Ellipse &e, int ty, int tile_log2, int W, int H,
+                                         int x0, int x1, int &c0, int &c1) {
+    const int ja = ty << tile_log2, jb = min((ty + 1) << tile_log2, H) - 1;
+    const float ya = (float)(ja - e.iy) + e.hyo, yb = (float)(jb - e.iy) + e.hyo;
+    float lo = fmaxf(ya, -e.ey), hi = fminf(yb, e.ey);
+    if (lo > hi) lo = hi = ya > e.ey ? e.ey : -e.ey;   // band beside the ellipse: its tip
+    const float d1 = fminf(fmaxf(e.dyr, lo), hi), d2 = fminf(fmaxf(-e.dyr, lo), hi);
+    const float xr = e.slope * d1 + __builtin_amdgcn_sqrtf(fmaxf(e.kw - e.ws * (d1 * d1), 0.f)) + kBoxAbs;
+    const float xl = e.slope * d2 - __builtin_amdgcn_sqrtf(fmaxf(e.kw - e.ws * (d2 * d2), 0.f)) - kBoxAbs;
+    const int a = max(e.ix + (int)ceilf(xl - e.hxo), 0);
+    const int b = min(e.ix + (int)floorf(xr - e.hxo), W - 1);
+    if (a > b) return false;
+    c0 = max(a >> tile_log2, x0);
+    c1 = min(b >> tile_log2, x1);
+    return c0 <= c1;
+}
+
 // Tiles [tx0, tx1] x [ty0, ty1] of a view that meet its fovea: the pixels whose
 // centre can lie within radius_frac * width of the gaze point, with one pixel of
 // slack (the mask test itself is done per pixel by the loss).  Empty when
@@ -92,14 +146,16 @@ __device__ __forceinline__ FoveaTiles fovea_tiles(const float *__restrict__ gaze
 
 // Projection of n Gaussians into V views: records r = v*n + i.  Writes the
 // splat, the depth key (float32 bits of the camera depth, 0xFFFFFFFF when
-// culled), the touched tile rectangle and its tile count, and clears the
+// culled), the tile rectangle of the support box, the number of its tiles the
+// support ellipse reaches (row_span), the ellipse constants (slope, kw, ws,
+// dyr; ey follows as sqrt(kw / ws)), and clears the
 // record's nine screen-space gradient entries g2d[f * V*n + r] when g2d is
 // non-null.  With cull_gaze (nullable) the rectangle is clipped to the view's
 // fovea tiles (fovea_tiles with cull_radius).
 void launch_project_fwd(hipStream_t s, const float *P, int n, int nviews, int deg,
                         const gsf_camera *cams, const ViewDesc *views, int tile, SplatPtrs sp,
-                        uint32_t *depth_key, uint2 *rect, uint32_t *count, float *g2d,
-                        const float *cull_gaze, float cull_radius);
+                        uint32_t *depth_key, uint2 *rect, uint32_t *count, float4 *ell,
+                        uint2 *rspan, float *g2d, const float *cull_gaze, float cull_radius);
 
 // Parameter gradient from the per-record screen-space gradient g2d [9][V*n].
 void launch_project_bwd(hipStream_t s, const float *P, int n, int nviews, int deg,
@@ -109,7 +165,9 @@ void launch_project_bwd(hipStream_t s, const float *P, int n, int nviews, int de
 // order (key = global tile id, value = record id).  Writes the key total to
 // m_total and (0 on overflow, with GSF_FLAG_CAPACITY) to m_dev; emits nothing on
 // overflow.  Clears ranges[total_tiles].  block_sums: scan_blocks(nrec) words.
-void launch_scan_duplicate(hipStream_t s, const uint32_t *count, const uint2 *rect, int nrec, int n,
+void launch_scan_duplicate(hipStream_t s, const uint32_t *count, const uint2 *rect,
+                           const float4 *ell, const uint2 *rspan, SplatPtrs sp, int nrec, int n,
+                           int tile,
                            const ViewDesc *views, uint32_t *block_sums, uint32_t *keys,
                            uint32_t *vals, uint32_t *m_dev, unsigned long long *m_total,
                            uint32_t *flags, int64_t capacity, uint2 *ranges, int total_tiles);
@@ -196,9 +254,11 @@ void launch_loss_l1(hipStream_t s, const float *rgba, const float *target, const
 void launch_draw_bg(hipStream_t s, uint64_t seed, const int32_t *step, int nviews, float *bg);
 
 // Adam with bias correction for step step[0]; when advance is true a one-thread
-// kernel first advances step[0] by one.
+// kernel first advances step[0] by one.  skip (nullable): device flags; the
+// update is skipped while GSF_FLAG_CAPACITY is set.
 void launch_adam(hipStream_t s, float *p, const float *g, float *m, float *v, int64_t n,
-                 const SegTable &seg, float b1, float b2, float eps, int32_t *step, bool advance);
+                 const SegTable &seg, float b1, float b2, float eps, int32_t *step, bool advance,
+                 const uint32_t *skip = nullptr);
 
 // vis[i] = 1 when a record of Gaussian i (count[v * n + i], v < nviews) touched a tile.
 void launch_visible(hipStream_t s, const uint32_t *count, int n, int nviews, uint8_t *vis);
@@ -207,7 +267,7 @@ void launch_visible(hipStream_t s, const uint32_t *count, int n, int nviews, uin
 // (others untouched), plane c at lr.lr[c]; advance as in launch_adam.
 void launch_adam_masked(hipStream_t s, float *p, const float *g, float *m, float *v, int64_t n,
                         int planes, const PlaneLr &lr, const uint8_t *vis, float b1, float b2,
-                        float eps, int32_t *step, bool advance);
+                        float eps, int32_t *step, bool advance, const uint32_t *skip = nullptr);
 
 // m[0..n) = v[0..n) = 0 and step[0] = 0, by a kernel (graph-capturable).
 void launch_adam_reset(hipStream_t s, float *m, float *v, int64_t n, int32_t *step);

@@ -38,7 +38,9 @@ struct Buffers {
     float4 *rec_c = nullptr;
     uint32_t *depth_key = nullptr;               // float32 depth bits; 0xFFFFFFFF = culled
     uint2 *rect = nullptr;                       // touched tile rectangle
-    uint32_t *count = nullptr;                   // touched tiles
+    uint32_t *count = nullptr;                   // listed tiles
+    float4 *ell = nullptr;                       // support ellipse constants (Ellipse)
+    uint2 *rspan = nullptr;                      // packed row spans of short boxes
     uint32_t *block_sums = nullptr;              // scan of the per-record tile counts
     // per global tile
     uint2 *ranges = nullptr;
@@ -139,6 +141,8 @@ size_t carve(gsf_plan *p, char *base, Buffers *out) {
     b.depth_key = (uint32_t *)take(R * 4);
     b.rect = (uint2 *)take(R * sizeof(uint2));
     b.count = (uint32_t *)take(R * 4);
+    b.ell = (float4 *)take(R * sizeof(float4));
+    b.rspan = (uint2 *)take(R * sizeof(uint2));
     const size_t T = (size_t)p->total_tiles;
     b.block_sums = (uint32_t *)take((size_t)scan_blocks(p->nrec_max) * 4);
     b.ranges = (uint2 *)take(T * sizeof(uint2));
@@ -268,14 +272,16 @@ gsf_status enqueue_forward(gsf_plan *p, const float *params, int64_t n, const gs
     {   // splats, support boxes, depth keys; clears the screen gradient
         StageTimer t(p, GSF_STAGE_PROJECT);
         launch_project_fwd(s, params, (int)n, p->V, p->deg, cams, b.views, p->tile, splats(p),
-                           b.depth_key, b.rect, b.count, b.g2d, cull_gaze, cull_radius);
+                           b.depth_key, b.rect, b.count, b.ell, b.rspan, b.g2d, cull_gaze,
+                           cull_radius);
     }
     p->g2d_clean = true;
     GSF_LAUNCHED(ctx);
     {   // one key per touched tile in record order; key total + capacity check on the device
         StageTimer t(p, GSF_STAGE_DUPLICATE);
-        launch_scan_duplicate(s, b.count, b.rect, nrec, (int)n, b.views, b.block_sums, b.k0, b.v0,
-                              b.m_dev, b.m_total, b.flags, p->cap, b.ranges, (int)p->total_tiles);
+        launch_scan_duplicate(s, b.count, b.rect, b.ell, b.rspan, splats(p), nrec, (int)n, p->tile,
+                              b.views, b.block_sums, b.k0, b.v0, b.m_dev, b.m_total, b.flags,
+                              p->cap, b.ranges, (int)p->total_tiles);
     }
     GSF_LAUNCHED(ctx);
     if (p->host_sized) {   // plain path: one host synchronisation per forward
@@ -450,11 +456,11 @@ gsf_status enqueue_step(gsf_plan *p, const gsf_step_args *a) {
         for (int c = 0; c < C; c++) lr.lr[c] = a->seg_lr[c];
         launch_visible(p->ctx->stream, p->b.count, (int)a->n, p->V, p->b.vis);
         launch_adam_masked(p->ctx->stream, a->params, a->grads, a->adam_m, a->adam_v, a->n, C, lr,
-                           p->b.vis, a->beta1, a->beta2, a->eps, a->step_dev, false);
+                           p->b.vis, a->beta1, a->beta2, a->eps, a->step_dev, false, p->b.flags);
     } else {
         StageTimer t(p, GSF_STAGE_ADAM);
         launch_adam(p->ctx->stream, a->params, a->grads, a->adam_m, a->adam_v, off[C], seg,
-                    a->beta1, a->beta2, a->eps, a->step_dev, false);
+                    a->beta1, a->beta2, a->eps, a->step_dev, false, p->b.flags);
     }
     GSF_LAUNCHED(p->ctx);
     return overflow ? fail(p->ctx, GSF_E_CAPACITY, "key capacity exceeded") : GSF_OK;

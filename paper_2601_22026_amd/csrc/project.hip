@@ -229,6 +229,8 @@ __global__ __launch_bounds__(256) void k_project_fwd(const float *__restrict__ P
                                                      SplatPtrs sp, uint32_t *__restrict__ depth_key,
                                                      uint2 *__restrict__ rect,
                                                      uint32_t *__restrict__ count,
+                                                     float4 *__restrict__ ell,
+                                                     uint2 *__restrict__ rspan,
                                                      float *__restrict__ g2d,
                                                      const float *__restrict__ cull_gaze,
                                                      float cull_radius) {
@@ -313,7 +315,34 @@ __global__ __launch_bounds__(256) void k_project_fwd(const float *__restrict__ P
         ty1 = min(ty1, (uint32_t)f.ty1);
     }
     rect[r] = make_uint2(tx0 | (ty0 << 16), tx1 | (ty1 << 16));
-    count[r] = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
+    // the tiles of each box row that the support ellipse reaches
+    const float Kp = k2 * ((1.f + kBoxRel) * (1.f + kBoxRel));
+    float ey;
+    const float4 ep = ellipse_pack(p.a, p.b, p.c, Kp, ey);
+    ell[r] = ep;
+    uint32_t cnt = 0;
+    if (ty1 - ty0 + 1 > (uint32_t)kSpanRows) {
+        cnt = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
+    } else {
+        const Ellipse e{ep.x, ep.y, ep.z, ep.w, sqrtf(ep.y / ep.z), (float)(ixd + 0.5 - mxd),
+                        (float)(iyd + 0.5 - myd), (int)ixd, (int)iyd};
+        const int tl = 31 - __clz(tile);
+        const bool pack = ty1 - ty0 + 1 <= (uint32_t)kPackRows && tx1 - tx0 + 1 <= (uint32_t)kPackCols;
+        uint32_t packed[2] = {0u, 0u};
+        for (uint32_t ty = ty0; ty <= ty1; ty++) {
+            int c0, c1;
+            if (row_span(e, (int)ty, tl, vd.width, vd.height, (int)tx0, (int)tx1, c0, c1)) {
+                const uint32_t w = (uint32_t)(c1 - c0 + 1);
+                cnt += w;
+                if (pack) {
+                    const uint32_t k = ty - ty0;
+                    packed[k >> 1] |= (((uint32_t)c0 - tx0) | (w << 8)) << (16 * (k & 1));
+                }
+            }
+        }
+        rspan[r] = make_uint2(packed[0], packed[1]);
+    }
+    count[r] = cnt;
 }
 
 // d(quaternion)/... from d(R) for the rotation of a unit quaternion (w, x, y, z).
@@ -484,15 +513,15 @@ __global__ __launch_bounds__(128) void k_project_bwd(const float *__restrict__ P
 
 void launch_project_fwd(hipStream_t s, const float *P, int n, int nviews, int deg,
                         const gsf_camera *cams, const ViewDesc *views, int tile, SplatPtrs sp,
-                        uint32_t *depth_key, uint2 *rect, uint32_t *count,
-                        float *g2d, const float *cull_gaze, float cull_radius) {
+                        uint32_t *depth_key, uint2 *rect, uint32_t *count, float4 *ell,
+                        uint2 *rspan, float *g2d, const float *cull_gaze, float cull_radius) {
     const int nrec = n * nviews;
     const dim3 grid((nrec + 255) / 256), block(256);
     switch (deg) {
-    case 0: k_project_fwd<0><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rect, count, g2d, cull_gaze, cull_radius); break;
-    case 1: k_project_fwd<1><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rect, count, g2d, cull_gaze, cull_radius); break;
-    case 2: k_project_fwd<2><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rect, count, g2d, cull_gaze, cull_radius); break;
-    default: k_project_fwd<3><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rect, count, g2d, cull_gaze, cull_radius); break;
+    case 0: k_project_fwd<0><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rect, count, ell, rspan, g2d, cull_gaze, cull_radius); break;
+    case 1: k_project_fwd<1><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rect, count, ell, rspan, g2d, cull_gaze, cull_radius); break;
+    case 2: k_project_fwd<2><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rect, count, ell, rspan, g2d, cull_gaze, cull_radius); break;
+    default: k_project_fwd<3><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rect, count, ell, rspan, g2d, cull_gaze, cull_radius); break;
     }
 }
 

@@ -694,7 +694,9 @@ __global__ __launch_bounds__(1024) void k_loss_final(const float *__restrict__ p
         const float L = s_part[0] / (float)max(cnt, 1u);
         loss[0] = L;
         if (!isfinite(L)) atomicOr(flags, GSF_FLAG_NONFINITE);
-        if (step_inc) step_inc[0] = step_inc[0] + 1;
+        // a step whose keys overflowed the capacity is not counted (its Adam
+        // update is skipped too, so it can be repeated after a re-plan)
+        if (step_inc && !(*flags & GSF_FLAG_CAPACITY)) step_inc[0] = step_inc[0] + 1;
     }
 }
 

@@ -34,7 +34,7 @@ constexpr int kScanBlock = 256;
 constexpr int kScanIpt = 1;                  // 256 records per block: 50k records fill 196 blocks
 constexpr int kScanTile = kScanBlock * kScanIpt;
 constexpr int kTileSortBlock = 256;
-constexpr int kTileSortLds = 2048;           // list length sorted in LDS; longer lists use global scratch
+constexpr int kTileSortLds = 1024;           // list length sorted in LDS (22 KB: 7 workgroups per CU); longer lists use global scratch
 
 __device__ __forceinline__ uint32_t chunk_size(uint32_t n, int G) {
     const uint32_t per = (n + (uint32_t)G - 1u) / (uint32_t)G;
@@ -244,21 +244,29 @@ __global__ __launch_bounds__(1024) void k_scan_top(uint32_t *__restrict__ block_
     }
 }
 
-// Keys of each record (one per touched tile) at its scanned offset; also
+// Keys of each record (one per listed tile) at its scanned offset; also
 // clears the tile ranges (grid-stride) before the boundary pass fills them.
 // The block's keys are written by all its threads together, key q of the block
 // by thread q mod 256: the record owning q is found by binary search over the
 // block's offsets in LDS, so one record's many keys are spread over the block
-// and consecutive threads write consecutive addresses.
+// and consecutive threads write consecutive addresses.  Within a record the
+// keys run over the box rows, each row's tiles being those its support
+// ellipse reaches (row_span, the rule the projection counted with).
 __global__ __launch_bounds__(kScanBlock) void k_scan_dup(
-    const uint32_t *__restrict__ count, const uint2 *__restrict__ rect, int nrec, int n,
+    const uint32_t *__restrict__ count, const uint2 *__restrict__ rect,
+    const float4 *__restrict__ ell, const uint2 *__restrict__ rspan, SplatPtrs sp, int nrec, int n,
+    int tile,
     const ViewDesc *__restrict__ views, const uint32_t *__restrict__ block_prefix,
     const unsigned long long *__restrict__ m_total, int64_t capacity, uint32_t *__restrict__ keys,
     uint32_t *__restrict__ vals, uint2 *__restrict__ ranges, int total_tiles) {
     __shared__ uint32_t s_wave[4];
-    __shared__ uint32_t s_off[kScanTile];    // block-local exclusive key offset per record
-    __shared__ uint32_t s_base[kScanTile];   // global tile id of the record's first tile
-    __shared__ uint32_t s_w[kScanTile];      // rect width (low 16 bits), view tiles_x (high 16)
+    __shared__ uint32_t s_off[kScanTile];   // block-local exclusive key offset per record
+    __shared__ uint2 s_rect[kScanTile];
+    __shared__ int s_view[kScanTile];
+    __shared__ float4 s_e0[kScanTile];        // ellipse: slope, kw, ws, dyr
+    __shared__ float4 s_e1[kScanTile];        // ey, hxo, hyo, -
+    __shared__ int2 s_ixy[kScanTile];
+    __shared__ uint2 s_pack[kScanTile];       // packed row spans (kPackRows rows or fewer)
     for (int t = blockIdx.x * kScanBlock + threadIdx.x; t < total_tiles; t += gridDim.x * kScanBlock)
         ranges[t] = make_uint2(0u, 0u);
     if (*m_total > (unsigned long long)capacity) return;    // overflow: emit nothing
@@ -279,11 +287,19 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_dup(
         s_off[i] = off;
         if (cnt[k] != 0u) {
             const uint32_t r = (uint32_t)(base + k);
-            const ViewDesc vd = views[r / (uint32_t)n];
             const uint2 rc = rect[r];
-            const uint32_t x0 = rc.x & 0xFFFFu, y0 = rc.x >> 16, x1 = rc.y & 0xFFFFu;
-            s_base[i] = (uint32_t)vd.tile_off + y0 * (uint32_t)vd.tiles_x + x0;
-            s_w[i] = (x1 - x0 + 1u) | ((uint32_t)vd.tiles_x << 16);
+            s_rect[i] = rc;
+            s_view[i] = (int)(r / (uint32_t)n);
+            const int rows = (int)(rc.y >> 16) - (int)(rc.x >> 16) + 1;
+            const int cols = (int)(rc.y & 0xFFFFu) - (int)(rc.x & 0xFFFFu) + 1;
+            if (rows <= kPackRows && cols <= kPackCols) {
+                s_pack[i] = rspan[r];
+            } else if (rows <= kSpanRows) {
+                const float4 ea = ell[r], a = sp.a[r], c = sp.c[r];
+                s_e0[i] = ea;
+                s_e1[i] = make_float4(sqrtf(ea.y / ea.z), a.x, a.y, 0.f);
+                s_ixy[i] = make_int2((int)c.z, (int)c.w);
+            }
         }
         off += cnt[k];
     }
@@ -297,15 +313,48 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_dup(
             const int mid = (lo + hi + 1) >> 1;
             if (s_off[mid] <= q) lo = mid; else hi = mid - 1;
         }
-        const uint32_t li = q - s_off[lo];        // index of the key within its record
-        const uint32_t wv = s_w[lo];
-        const uint32_t w = wv & 0xFFFFu, tiles_x = wv >> 16;
-        // li / w via a float reciprocal, then exact by one correction each way
-        uint32_t row = (uint32_t)((float)li * __builtin_amdgcn_rcpf((float)w));
-        if (row * w > li) row--;
-        if ((row + 1u) * w <= li) row++;
-        keys[gbase + q] = s_base[lo] + row * tiles_x + (li - row * w);
-        vals[gbase + q] = (uint32_t)(rec0 + lo);
+        uint32_t li = q - s_off[lo];              // index of the key within its record
+        const uint32_t r = (uint32_t)(rec0 + lo);
+        const uint2 rc = s_rect[lo];
+        const int x0 = (int)(rc.x & 0xFFFFu), y0 = (int)(rc.x >> 16);
+        const int x1 = (int)(rc.y & 0xFFFFu), y1 = (int)(rc.y >> 16);
+        const ViewDesc vd = views[s_view[lo]];
+        uint32_t key = 0u;
+        if (y1 - y0 + 1 <= kPackRows && x1 - x0 + 1 <= kPackCols) {   // packed spans
+            const uint2 pk = s_pack[lo];
+            for (int k = 0; k < kPackRows; k++) {
+                const uint32_t f = ((k < 2 ? pk.x : pk.y) >> (16 * (k & 1))) & 0xFFFFu;
+                const uint32_t w = f >> 8;
+                if (li < w) {
+                    key = (uint32_t)vd.tile_off + (uint32_t)(y0 + k) * (uint32_t)vd.tiles_x +
+                          (uint32_t)x0 + (f & 0xFFu) + li;
+                    break;
+                }
+                li -= w;
+            }
+        } else if (y1 - y0 + 1 > kSpanRows) {     // the whole box, row by row
+            const uint32_t w = (uint32_t)(x1 - x0 + 1);
+            const uint32_t row = li / w;
+            key = (uint32_t)vd.tile_off + ((uint32_t)y0 + row) * (uint32_t)vd.tiles_x + (uint32_t)x0 +
+                  (li - row * w);
+        } else {
+            const float4 e0 = s_e0[lo], e1 = s_e1[lo];
+            const int2 ixy = s_ixy[lo];
+            const Ellipse e{e0.x, e0.y, e0.z, e0.w, e1.x, e1.y, e1.z, ixy.x, ixy.y};
+            const int tl = 31 - __clz(tile);
+            for (int ty = y0; ty <= y1; ty++) {
+                int c0, c1;
+                if (!row_span(e, ty, tl, vd.width, vd.height, x0, x1, c0, c1)) continue;
+                const uint32_t w = (uint32_t)(c1 - c0 + 1);
+                if (li < w) {
+                    key = (uint32_t)vd.tile_off + (uint32_t)ty * (uint32_t)vd.tiles_x + (uint32_t)c0 + li;
+                    break;
+                }
+                li -= w;
+            }
+        }
+        keys[gbase + q] = key;
+        vals[gbase + q] = r;
     }
 }
 
@@ -643,15 +692,18 @@ int launch_radix_sort(hipStream_t s, const uint32_t *kin, const uint32_t *vin, u
 
 int scan_blocks(int64_t nrec) { return (int)((nrec + kScanTile - 1) / kScanTile) + 1; }
 
-void launch_scan_duplicate(hipStream_t s, const uint32_t *count, const uint2 *rect, int nrec, int n,
+void launch_scan_duplicate(hipStream_t s, const uint32_t *count, const uint2 *rect,
+                           const float4 *ell, const uint2 *rspan, SplatPtrs sp, int nrec, int n,
+                           int tile,
                            const ViewDesc *views, uint32_t *block_sums, uint32_t *keys,
                            uint32_t *vals, uint32_t *m_dev, unsigned long long *m_total,
                            uint32_t *flags, int64_t capacity, uint2 *ranges, int total_tiles) {
     const int nb = (nrec + kScanTile - 1) / kScanTile;
     k_scan_reduce<<<nb, kScanBlock, 0, s>>>(count, nrec, block_sums);
     k_scan_top<<<1, 1024, 0, s>>>(block_sums, nb, m_dev, m_total, flags, capacity);
-    k_scan_dup<<<nb, kScanBlock, 0, s>>>(count, rect, nrec, n, views, block_sums, m_total, capacity,
-                                         keys, vals, ranges, total_tiles);
+    k_scan_dup<<<nb, kScanBlock, 0, s>>>(count, rect, ell, rspan, sp, nrec, n, tile, views,
+                                         block_sums, m_total, capacity, keys, vals, ranges,
+                                         total_tiles);
 }
 
 void launch_tile_bounds(hipStream_t s, const uint32_t *keys, const uint32_t *m_dev, uint32_t m_host,

@@ -383,3 +383,34 @@ def test_alpha_training_with_random_backgrounds(gs, ctx):
             np.testing.assert_array_equal(fs.backgrounds().astype(np.float64),
                                           oracle.background_draw(seed, step, len(cams)))
     fs.plan.close()
+
+
+def test_capacity_overflow_skips_the_update_and_replans(gs, ctx):
+    """A captured step whose keys overflow the capacity leaves parameters, Adam
+    moments and the step counter untouched; ensure_capacity re-plans, recaptures
+    and the repeated step matches a step planned with room from the start."""
+    P = synth.random_gaussians(1000, seed=0)
+    cam = synth.axis_camera(128, 128)
+    tgt = torch.from_numpy(_cfg1_target().reshape(-1).copy()).to(DEV)
+    with torch.cuda.stream(torch.cuda.Stream()):
+        fs = gs.FitStep(ctx, torch.from_numpy(P).to(DEV), [cam], tgt,
+                        cfg=gs.FitConfig(lr=1e-2, key_capacity=100))
+        fs.capture()
+        p0 = fs.params.clone()
+        fs.replay()
+        fs.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(fs.params, p0)
+        assert int(fs.step_dev.item()) == 0 and not fs.m.any().item() and not fs.v.any().item()
+        assert fs.ensure_capacity() is True
+        assert fs.key_capacity >= 200
+        fs.replay()
+        assert fs.ensure_capacity() is False
+        assert int(fs.step_dev.item()) == 1 and not torch.equal(fs.params, p0)
+        ref = gs.FitStep(ctx, torch.from_numpy(P).to(DEV), [cam], tgt, cfg=gs.FitConfig(lr=1e-2))
+        ref.step()
+        torch.cuda.synchronize()
+        assert abs(fs.loss.item() - ref.loss.item()) <= 1e-6 * ref.loss.item()
+        rep = grads_close(fs.grads.cpu().numpy(), ref.grads.cpu().numpy().astype(np.float64),
+                          rtol=1e-5)
+        assert all(nb == 0 for _, nb, _ in rep), rep

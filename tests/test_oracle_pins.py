@@ -596,3 +596,33 @@ def test_adam_per_segment_learning_rate():
     p0 = p.copy()
     oracle.adam(p, g, m, v, 1, lr=lr)
     np.testing.assert_allclose(p - p0, -lr * np.sign(g), rtol=1e-12)
+
+
+def test_discrete_stage_lists_only_tiles_the_ellipse_reaches():
+    """A thin splat along the image diagonal: its box spans many tiles, but only
+    the tiles near the diagonal are listed, and each listed tile's band of pixel
+    centres (widened by one pixel) meets the padded support ellipse."""
+    P = synth.random_gaussians(1, seed=3).astype(np.float64)
+    P[0:3, 0] = [0.0, 0.0, 0.0]
+    P[3:6, 0] = [np.log(0.6), np.log(0.01), np.log(0.01)]       # long along x
+    c, s = np.cos(np.pi / 8), np.sin(np.pi / 8)                   # 45 degrees about z
+    P[6:10, 0] = [c, 0.0, 0.0, s]
+    P[10, 0] = 3.0
+    cam = synth.axis_camera(128, 128)
+    T = 8
+    d = oracle.discrete(P, [cam], T)
+    rec = oracle.project(P, cam)
+    assert rec["valid"][0] and d.rflags[0] == 0
+    tw = 128 // T
+    x0, x1 = int(max(0, np.ceil(rec["ex0"][0]))) // T, int(min(127, np.floor(rec["ex1"][0]))) // T
+    y0, y1 = int(max(0, np.ceil(rec["ey0"][0]))) // T, int(min(127, np.floor(rec["ey1"][0]))) // T
+    area = (x1 - x0 + 1) * (y1 - y0 + 1)
+    assert d.m < 0.5 * area, (d.m, area)
+    Kp = 2 * np.log(255 * rec["o"][0]) * (1 + 1e-4) ** 2
+    for t in d.keys:
+        ty, tx = divmod(int(t), tw)
+        xs = np.linspace(tx * T - 1.0, tx * T + T, 64) + 0.5 - rec["mx"][0]
+        ys = np.linspace(ty * T, ty * T + T - 1, 32) + 0.5 - rec["my"][0]
+        X, Y = np.meshgrid(xs, ys)
+        q = rec["A"][0] * X * X + 2 * rec["B"][0] * X * Y + rec["C"][0] * Y * Y
+        assert q.min() <= Kp, (tx, ty)
