@@ -185,17 +185,17 @@ def hbm_bytes_per_launch(stage, N, R, M, npix, planes, tiles):
     R = N * views records, M keys, npix pixels, `planes` floats per Gaussian."""
     passes = (max(1, (tiles - 1).bit_length()) + 7) // 8
     return {
-        "project": planes * 4 * N + 92 * R,                   # params in; splat, key, box, count, g2d clear
-        "duplicate": 16 * R + 8 * M + 8 * tiles,              # counts (twice), boxes in; pairs out; ranges cleared
+        "project": planes * 4 * N + 88 * R,                   # params in; splat, key, box, count, ellipse, spans
+        "duplicate": 20 * R + 8 * M + 8 * tiles,              # counts (twice), boxes in; first-key offset, pairs out; ranges cleared
         "tile_sort": passes * 20 * M,                         # per pass: key histogram, pair in, pair out
         "ranges": 4 * M + 28 * tiles,                         # sorted tile ids in; ranges out; order
         "depth_sort": 12 * M,                                 # record ids in, depth gather, record ids out
         "render": 40 * M + 24 * npix,                         # splat gather per key; RGBA, T, count out
         "loss": 40 * npix,                                    # RGBA, target in; dL/dRGBA out
-        "render_bwd": 40 * M + 24 * npix + 36 * R,            # splat gather; pixel state in; g2d out
+        "render_bwd": 76 * M + 24 * npix,                     # splat gather; pixel state in; per-key gradient out
         "project_bwd": planes * 4 * N + 36 * R + planes * 4 * N,
         "adam": 28 * planes * N,
-        "zero": 36 * R,
+        "grad_sum": 36 * M + 44 * R,                          # per-key gradient, count, offset in; g2d out
     }.get(stage)
 
 

@@ -388,7 +388,7 @@ gsf_status gsf_raymarch(gsf_ctx *ctx, const uint16_t *vol, int32_t n, const gsf_
 /* Per-stage GPU timing of eager calls on a plan (hipEvents recorded around each
  * stage on the context stream; not available while capturing).  Enabling
  * resets the accumulators.  Stages holding exactly one kernel: PROJECT,
- * DEPTH_SORT, RENDER, RENDER_BWD, PROJECT_BWD. */
+ * DEPTH_SORT, RENDER, RENDER_BWD, PROJECT_BWD, GRAD_SUM. */
 enum {
     GSF_STAGE_PROJECT = 0,     /* projection + support boxes (one kernel) */
     GSF_STAGE_DUPLICATE = 1,   /* scan of the per-record tile counts + key emission */
@@ -400,7 +400,7 @@ enum {
     GSF_STAGE_RENDER_BWD = 7,  /* compositing adjoint (one kernel) */
     GSF_STAGE_PROJECT_BWD = 8, /* projection adjoint (one kernel) */
     GSF_STAGE_ADAM = 9,        /* step counter + Adam (inside gsf_step only) */
-    GSF_STAGE_ZERO = 10,       /* clearing the screen-space gradient */
+    GSF_STAGE_GRAD_SUM = 10,   /* per-record sum of the per-key screen-space gradients (one kernel) */
     GSF_STAGE_COUNT = 11
 };
 gsf_status gsf_plan_set_timing(gsf_plan *plan, int enable);

@@ -30,7 +30,7 @@ EXPORTED = ["gsf_ctx_create", "gsf_ctx_destroy", "gsf_ctx_set_stream", "gsf_last
             "gsf_view_select", "gsf_reproject", "gsf_reproject_warp",
             "gsf_first_hit_scratch_bytes", "gsf_seed_first_hits"]
 STAGES = ["project", "duplicate", "tile_sort", "ranges", "depth_sort", "render", "loss",
-          "render_bwd", "project_bwd", "adam", "zero"]
+          "render_bwd", "project_bwd", "adam", "grad_sum"]
 
 
 class GsfError(RuntimeError):

@@ -121,6 +121,53 @@ __device__ __forceinline__ bool row_span(const Ellipse &e, int ty, int tile_log2
     return c0 <= c1;
 }
 
+// Where the adjoint puts each key's screen-space gradient: the duplicate pass
+// writes a record's count[r] keys at consecutive positions (its first at
+// koff[r]), box rows top to bottom and each row's listed tiles left to right;
+// the adjoint writes key (r, tile) at that position of pa / pb / pc (fields
+// 0-3, 4-7, 8, plain stores), and one pass per record sums its positions into
+// g2d.  After a key overflow (m_total > capacity) nothing was listed and g2d
+// is zero.
+struct KeyPlace {
+    const uint32_t *koff = nullptr, *count = nullptr;
+    const uint2 *rect = nullptr, *rspan = nullptr;
+    const float4 *ell = nullptr;
+    float4 *pa = nullptr, *pb = nullptr;
+    float *pc = nullptr;
+    const unsigned long long *m_total = nullptr;
+    int64_t capacity = 0;
+};
+
+// Position of the key of record r in tile (ty, tx) of its view (W x H,
+// tile = 1 << tile_log2): koff[r] plus the tile's rank among the record's
+// listed tiles, found from the packed row spans, the box, or the row spans.
+__device__ __forceinline__ uint32_t key_slot(const KeyPlace &kp, SplatPtrs sp, uint32_t r, int ty,
+                                             int tx, int tile_log2, int W, int H) {
+    const uint2 rc = kp.rect[r];
+    const int x0 = (int)(rc.x & 0xFFFFu), y0 = (int)(rc.x >> 16);
+    const int x1 = (int)(rc.y & 0xFFFFu), y1 = (int)(rc.y >> 16);
+    const int rows = y1 - y0 + 1, cols = x1 - x0 + 1;
+    uint32_t rank = 0;
+    if (rows <= kPackRows && cols <= kPackCols) {
+        const uint2 pk = kp.rspan[r];
+        const int kr = ty - y0;
+        for (int k = 0; k < kr; k++) rank += (((k < 2 ? pk.x : pk.y) >> (16 * (k & 1))) >> 8) & 0xFFu;
+        const uint32_t f = ((kr < 2 ? pk.x : pk.y) >> (16 * (kr & 1))) & 0xFFFFu;
+        rank += (uint32_t)(tx - x0) - (f & 0xFFu);
+    } else if (rows > kSpanRows) {
+        rank = (uint32_t)((ty - y0) * cols + (tx - x0));
+    } else {
+        const float4 e0 = kp.ell[r], a = sp.a[r], c = sp.c[r];
+        const Ellipse e{e0.x, e0.y, e0.z, e0.w, sqrtf(e0.y / e0.z), a.x, a.y, (int)c.z, (int)c.w};
+        int c0, c1;
+        for (int y = y0; y < ty; y++)
+            if (row_span(e, y, tile_log2, W, H, x0, x1, c0, c1)) rank += (uint32_t)(c1 - c0 + 1);
+        row_span(e, ty, tile_log2, W, H, x0, x1, c0, c1);
+        rank += (uint32_t)(tx - c0);
+    }
+    return kp.koff[r] + rank;
+}
+
 // Tiles [tx0, tx1] x [ty0, ty1] of a view that meet its fovea: the pixels whose
 // centre can lie within radius_frac * width of the gaze point, with one pixel of
 // slack (the mask test itself is done per pixel by the loss).  Empty when
@@ -148,14 +195,13 @@ __device__ __forceinline__ FoveaTiles fovea_tiles(const float *__restrict__ gaze
 // splat, the depth key (float32 bits of the camera depth, 0xFFFFFFFF when
 // culled), the tile rectangle of the support box, the number of its tiles the
 // support ellipse reaches (row_span), the ellipse constants (slope, kw, ws,
-// dyr; ey follows as sqrt(kw / ws)), and clears the
-// record's nine screen-space gradient entries g2d[f * V*n + r] when g2d is
-// non-null.  With cull_gaze (nullable) the rectangle is clipped to the view's
+// dyr; ey follows as sqrt(kw / ws)) and the packed row spans of short boxes.
+// With cull_gaze (nullable) the rectangle is clipped to the view's
 // fovea tiles (fovea_tiles with cull_radius).
 void launch_project_fwd(hipStream_t s, const float *P, int n, int nviews, int deg,
                         const gsf_camera *cams, const ViewDesc *views, int tile, SplatPtrs sp,
                         uint32_t *depth_key, uint2 *rect, uint32_t *count, float4 *ell,
-                        uint2 *rspan, float *g2d, const float *cull_gaze, float cull_radius);
+                        uint2 *rspan, const float *cull_gaze, float cull_radius);
 
 // Parameter gradient from the per-record screen-space gradient g2d [9][V*n].
 void launch_project_bwd(hipStream_t s, const float *P, int n, int nviews, int deg,
@@ -166,8 +212,8 @@ void launch_project_bwd(hipStream_t s, const float *P, int n, int nviews, int de
 // m_total and (0 on overflow, with GSF_FLAG_CAPACITY) to m_dev; emits nothing on
 // overflow.  Clears ranges[total_tiles].  block_sums: scan_blocks(nrec) words.
 void launch_scan_duplicate(hipStream_t s, const uint32_t *count, const uint2 *rect,
-                           const float4 *ell, const uint2 *rspan, SplatPtrs sp, int nrec, int n,
-                           int tile,
+                           const float4 *ell, const uint2 *rspan, SplatPtrs sp, uint32_t *koff,
+                           int nrec, int n, int tile,
                            const ViewDesc *views, uint32_t *block_sums, uint32_t *keys,
                            uint32_t *vals, uint32_t *m_dev, unsigned long long *m_total,
                            uint32_t *flags, int64_t capacity, uint2 *ranges, int total_tiles);
@@ -222,13 +268,17 @@ struct RenderArgs {
     float *tstore = nullptr;              // [key capacity][T*T]: T in front of each included pair
     const uint32_t *m_dev = nullptr;      // key count on the device, or
     uint32_t m_host = 0;                  //   on the host when m_dev is null
+    KeyPlace kp{};                        // where the adjoint writes each key's gradient
 };
 
 // Front-to-back compositing of all tiles of all views.
 void launch_render_fwd(hipStream_t s, const RenderArgs &a, float *out_rgba);
 
-// Back-to-front adjoint of the compositing: accumulates g2d [9][nrec].
-void launch_render_bwd(hipStream_t s, const RenderArgs &a, const float *dl_drgba, float *g2d);
+// Back-to-front adjoint of the compositing: every key's screen-space gradient
+// into a.kp (zeros for keys it does not reach).
+void launch_render_bwd(hipStream_t s, const RenderArgs &a, const float *dl_drgba);
+// Their sum per record into g2d [9][nrec] (every entry written).
+void launch_grad_sum(hipStream_t s, const KeyPlace &kp, int nrec, float *g2d);
 
 // Pair accounting of the last forward: counters[3] (visited, included, adjoint visited).
 void launch_count_pairs(hipStream_t s, int tile, int total_tiles, const uint2 *ranges,

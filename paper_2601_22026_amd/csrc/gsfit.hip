@@ -41,6 +41,7 @@ struct Buffers {
     uint32_t *count = nullptr;                   // listed tiles
     float4 *ell = nullptr;                       // support ellipse constants (Ellipse)
     uint2 *rspan = nullptr;                      // packed row spans of short boxes
+    uint32_t *koff = nullptr;                    // position of the record's first key
     uint32_t *block_sums = nullptr;              // scan of the per-record tile counts
     // per global tile
     uint2 *ranges = nullptr;
@@ -53,6 +54,10 @@ struct Buffers {
     uint32_t *keys = nullptr, *vals = nullptr;   // sorted pair (aliases k0/v0 or k1/v1)
     uint32_t *ok = nullptr, *ov = nullptr;       // the other pair
     uint32_t *hist = nullptr, *digit_tot = nullptr;   // radix-sort histograms
+    // per key, at its position in the duplicate pass's order: the adjoint's
+    // screen-space gradient (fields 0-3, 4-7, 8)
+    float4 *pa = nullptr, *pb = nullptr;
+    float *pc = nullptr;
     // per pixel
     float *tfinal = nullptr;
     uint32_t *ncontrib = nullptr;
@@ -85,7 +90,6 @@ struct gsf_plan {
     void *ws = nullptr;
     Buffers b;
     bool have_forward = false;
-    bool g2d_clean = false;                   // the last forward cleared the screen gradient
     int64_t fwd_n = 0;
     unsigned long long *pinned = nullptr;     // host-pinned readback of the key count
     hipGraph_t graph = nullptr;
@@ -143,6 +147,7 @@ size_t carve(gsf_plan *p, char *base, Buffers *out) {
     b.count = (uint32_t *)take(R * 4);
     b.ell = (float4 *)take(R * sizeof(float4));
     b.rspan = (uint2 *)take(R * sizeof(uint2));
+    b.koff = (uint32_t *)take(R * 4);
     const size_t T = (size_t)p->total_tiles;
     b.block_sums = (uint32_t *)take((size_t)scan_blocks(p->nrec_max) * 4);
     b.ranges = (uint2 *)take(T * sizeof(uint2));
@@ -160,6 +165,9 @@ size_t carve(gsf_plan *p, char *base, Buffers *out) {
     b.ov = odd ? b.v0 : b.v1;
     b.hist = (uint32_t *)take((size_t)256 * p->radix_grid * 4);
     b.digit_tot = (uint32_t *)take(256 * 4);
+    b.pa = (float4 *)take((size_t)p->cap * sizeof(float4));
+    b.pb = (float4 *)take((size_t)p->cap * sizeof(float4));
+    b.pc = (float *)take((size_t)p->cap * 4);
     b.tfinal = (float *)take((size_t)p->total_pix * 4);
     b.ncontrib = (uint32_t *)take((size_t)p->total_pix * 4);
     if (p->t_mode == 1) {
@@ -211,6 +219,16 @@ RenderArgs render_args(gsf_plan *p, const gsf_camera *cams, int64_t n) {
     a.tstore = p->b.tstore;
     a.m_dev = p->host_sized ? nullptr : p->b.m_dev;
     a.m_host = p->m_host;
+    a.kp.koff = p->b.koff;
+    a.kp.count = p->b.count;
+    a.kp.rect = p->b.rect;
+    a.kp.rspan = p->b.rspan;
+    a.kp.ell = p->b.ell;
+    a.kp.pa = p->b.pa;
+    a.kp.pb = p->b.pb;
+    a.kp.pc = p->b.pc;
+    a.kp.m_total = p->b.m_total;
+    a.kp.capacity = p->cap;
     return a;
 }
 
@@ -269,17 +287,16 @@ gsf_status enqueue_forward(gsf_plan *p, const float *params, int64_t n, const gs
         gsf_status fs = flush_timing(p);
         if (fs != GSF_OK) return fs;
     }
-    {   // splats, support boxes, depth keys; clears the screen gradient
+    {   // splats, support boxes and their tile counts, depth keys
         StageTimer t(p, GSF_STAGE_PROJECT);
         launch_project_fwd(s, params, (int)n, p->V, p->deg, cams, b.views, p->tile, splats(p),
-                           b.depth_key, b.rect, b.count, b.ell, b.rspan, b.g2d, cull_gaze,
-                           cull_radius);
+                           b.depth_key, b.rect, b.count, b.ell, b.rspan, cull_gaze, cull_radius);
     }
-    p->g2d_clean = true;
     GSF_LAUNCHED(ctx);
     {   // one key per touched tile in record order; key total + capacity check on the device
         StageTimer t(p, GSF_STAGE_DUPLICATE);
-        launch_scan_duplicate(s, b.count, b.rect, b.ell, b.rspan, splats(p), nrec, (int)n, p->tile,
+        launch_scan_duplicate(s, b.count, b.rect, b.ell, b.rspan, splats(p), b.koff, nrec, (int)n,
+                              p->tile,
                               b.views, b.block_sums, b.k0, b.v0, b.m_dev, b.m_total, b.flags,
                               p->cap, b.ranges, (int)p->total_tiles);
     }
@@ -353,18 +370,17 @@ gsf_status enqueue_loss(gsf_plan *p, const float *rgba, const float *target, con
 gsf_status enqueue_backward(gsf_plan *p, const float *params, int64_t n, const gsf_camera *cams,
                             const float *dl, float *grads, const float *bg = nullptr) {
     hipStream_t s = p->ctx->stream;
-    const int64_t nrec = n * p->V;
-    if (!p->g2d_clean) {   // a second adjoint of the same forward: clear the accumulator
-        StageTimer t(p, GSF_STAGE_ZERO);
-        launch_fill_f32(s, p->b.g2d, 9 * nrec, 0.f);
-    }
-    {
+    RenderArgs ra = render_args(p, cams, n);
+    ra.bg = bg;
+    {   // per-key screen-space gradients
         StageTimer t(p, GSF_STAGE_RENDER_BWD);
-        RenderArgs ra = render_args(p, cams, n);
-        ra.bg = bg;
-        launch_render_bwd(s, ra, dl, p->b.g2d);
+        launch_render_bwd(s, ra, dl);
     }
-    p->g2d_clean = false;
+    GSF_LAUNCHED(p->ctx);
+    {   // their per-record sums (every entry of g2d written)
+        StageTimer t(p, GSF_STAGE_GRAD_SUM);
+        launch_grad_sum(s, ra.kp, (int)(n * p->V), p->b.g2d);
+    }
     GSF_LAUNCHED(p->ctx);
     {
         StageTimer t(p, GSF_STAGE_PROJECT_BWD);

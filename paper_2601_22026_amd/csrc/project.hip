@@ -231,7 +231,6 @@ __global__ __launch_bounds__(256) void k_project_fwd(const float *__restrict__ P
                                                      uint32_t *__restrict__ count,
                                                      float4 *__restrict__ ell,
                                                      uint2 *__restrict__ rspan,
-                                                     float *__restrict__ g2d,
                                                      const float *__restrict__ cull_gaze,
                                                      float cull_radius) {
     constexpr int K = (DEG + 1) * (DEG + 1);
@@ -239,10 +238,6 @@ __global__ __launch_bounds__(256) void k_project_fwd(const float *__restrict__ P
     if (r >= nrec) return;
     const int v = r / n;
     const int i = r - v * n;
-    if (g2d) {
-#pragma unroll
-        for (int f = 0; f < 9; f++) g2d[(size_t)f * nrec + r] = 0.f;
-    }
     const gsf_camera &cam = cams[v];
     Gauss g;
     load_gauss(P, n, i, g);
@@ -514,14 +509,14 @@ __global__ __launch_bounds__(128) void k_project_bwd(const float *__restrict__ P
 void launch_project_fwd(hipStream_t s, const float *P, int n, int nviews, int deg,
                         const gsf_camera *cams, const ViewDesc *views, int tile, SplatPtrs sp,
                         uint32_t *depth_key, uint2 *rect, uint32_t *count, float4 *ell,
-                        uint2 *rspan, float *g2d, const float *cull_gaze, float cull_radius) {
+                        uint2 *rspan, const float *cull_gaze, float cull_radius) {
     const int nrec = n * nviews;
     const dim3 grid((nrec + 255) / 256), block(256);
     switch (deg) {
-    case 0: k_project_fwd<0><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rect, count, ell, rspan, g2d, cull_gaze, cull_radius); break;
-    case 1: k_project_fwd<1><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rect, count, ell, rspan, g2d, cull_gaze, cull_radius); break;
-    case 2: k_project_fwd<2><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rect, count, ell, rspan, g2d, cull_gaze, cull_radius); break;
-    default: k_project_fwd<3><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rect, count, ell, rspan, g2d, cull_gaze, cull_radius); break;
+    case 0: k_project_fwd<0><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rect, count, ell, rspan, cull_gaze, cull_radius); break;
+    case 1: k_project_fwd<1><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rect, count, ell, rspan, cull_gaze, cull_radius); break;
+    case 2: k_project_fwd<2><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rect, count, ell, rspan, cull_gaze, cull_radius); break;
+    default: k_project_fwd<3><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rect, count, ell, rspan, cull_gaze, cull_radius); break;
     }
 }
 

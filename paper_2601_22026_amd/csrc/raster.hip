@@ -267,9 +267,10 @@ __device__ __forceinline__ void render_bwd_unit(
     int nviews, const gsf_camera *__restrict__ cams, const float *__restrict__ tfinal,
     const uint32_t *__restrict__ ncontrib, const float4 *__restrict__ fstate,
     const float4 *__restrict__ ckpt, const float *__restrict__ tstore, const float *__restrict__ bg,
-    const float *__restrict__ dl, float *__restrict__ g2d, int nrec, float4 *s_a, float4 *s_b,
-    float4 *s_c, uint32_t *s_r, float (*s_g)[9][B], float *s_h, uint32_t *s_nmax) {
+    const float *__restrict__ dl, const KeyPlace &kp, float4 *s_a, float4 *s_b, float4 *s_c,
+    uint32_t *s_q, float (*s_g)[9][B], float *s_h, uint32_t *s_nmax) {
     constexpr bool CKPT = MODE == 1;
+    constexpr int TL = T == 8 ? 3 : T == 16 ? 4 : 5;
     constexpr int NT = bwd_threads<T>();
     constexpr int PPT = T * T / NT;
     constexpr int ROWS = NT / T;
@@ -342,7 +343,7 @@ __device__ __forceinline__ void render_bwd_unit(
             s_a[j] = ra;
             s_b[j] = rb;
             s_c[j] = make_float4(rc.x, splat_tau(rb), rc.z, rc.w);
-            s_r[j] = r;
+            s_q[j] = key_slot(kp, sp, r, ty, tx, TL, vd.width, vd.height);
             s_h[j] = rc.y;
         }
         for (int e = threadIdx.x; e < NW * 9 * B; e += NT) (&s_g[0][0][0])[e] = 0.f;
@@ -415,24 +416,33 @@ __device__ __forceinline__ void render_bwd_unit(
             }
         }
         __syncthreads();
-        for (int e = threadIdx.x; e < nb * 9; e += NT) {
-            const int f = e / nb, j = e - f * nb;
-            float S[2] = {0.f, 0.f};
-            const int f0 = f < 2 ? 0 : f, nf = f < 2 ? 2 : 1;
-            for (int q = 0; q < nf; q++)
+        // one thread per key: the waves' sums, the conic factors applied, stored
+        // at the key's own position (no other workgroup writes it)
+        for (int j = threadIdx.x; j < nb; j += NT) {
+            float S[9];
 #pragma unroll
-                for (int w = 0; w < NW; w++) S[q] += s_g[w][f0 + q][j];
-            float val;
+            for (int f = 0; f < 9; f++) {
+                S[f] = 0.f;
+#pragma unroll
+                for (int w = 0; w < NW; w++) S[f] += s_g[w][f][j];
+            }
+            const float A2 = s_a[j].z, B2 = s_a[j].w, C2 = s_b[j].x;
+            const uint32_t q = s_q[j];
             // dpower/dmean = (A dx + B dy, B dx + C dy) = -ln2 (2 A2 dx + B2 dy, B2 dx + 2 C2 dy);
             // dpower/d(A, B, C) = (-dx^2 / 2, -dx dy, -dy^2 / 2)
-            if (f == 0) val = -kLn2 * (2.f * s_a[j].z * S[0] + s_a[j].w * S[1]);
-            else if (f == 1) val = -kLn2 * (s_a[j].w * S[0] + 2.f * s_b[j].x * S[1]);
-            else if (f == 2 || f == 4) val = -0.5f * S[0];
-            else if (f == 3) val = -S[0];
-            else val = S[0];
-            if (val != 0.f) unsafeAtomicAdd(&g2d[(size_t)f * nrec + s_r[j]], val);
+            kp.pa[q] = make_float4(-kLn2 * (2.f * A2 * S[0] + B2 * S[1]),
+                                   -kLn2 * (B2 * S[0] + 2.f * C2 * S[1]), -0.5f * S[2], -S[3]);
+            kp.pb[q] = make_float4(-0.5f * S[4], S[5], S[6], S[7]);
+            kp.pc[q] = S[8];
         }
         be = bs;
+    }
+    // keys behind every pixel's last included splat pass no gradient
+    for (uint32_t e = max(top, us) + threadIdx.x; e < ue; e += NT) {
+        const uint32_t q = key_slot(kp, sp, vals[e], ty, tx, TL, vd.width, vd.height);
+        kp.pa[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+        kp.pb[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+        kp.pc[q] = 0.f;
     }
 }
 
@@ -445,20 +455,20 @@ __global__ __launch_bounds__(bwd_threads<T>()) void k_render_bwd(
     const ViewDesc *__restrict__ views, int nviews, const gsf_camera *__restrict__ cams,
     const float *__restrict__ tfinal, const uint32_t *__restrict__ ncontrib,
     const float *__restrict__ tstore, const float *__restrict__ bg, const float *__restrict__ dl,
-    float *__restrict__ g2d, int nrec) {
+    KeyPlace kp) {
     constexpr int NT = bwd_threads<T>();
     __shared__ float4 s_a[B];
     __shared__ float4 s_b[B];
     __shared__ float4 s_c[B];
-    __shared__ uint32_t s_r[B];
+    __shared__ uint32_t s_q[B];
     __shared__ float s_g[NT / 64][9][B];
     __shared__ float s_h[B];
     __shared__ uint32_t s_nmax;
     const int gt = (int)order[blockIdx.x];
     const uint2 rg = ranges[gt];
     render_bwd_unit<T, B, MODE>(gt, rg.x, rg.y, true, rg, vals, sp, views, nviews, cams, tfinal,
-                                ncontrib, nullptr, nullptr, tstore, bg, dl, g2d, nrec, s_a, s_b, s_c,
-                                s_r, s_g, s_h, &s_nmax);
+                                ncontrib, nullptr, nullptr, tstore, bg, dl, kp, s_a, s_b, s_c, s_q,
+                                s_g, s_h, &s_nmax);
 }
 
 // Checkpoint mode: one workgroup per (tile, batch) unit id.  Unit u of tile t
@@ -473,12 +483,12 @@ __global__ __launch_bounds__(bwd_threads<T>()) void k_render_bwd_ckpt(
     const ViewDesc *__restrict__ views, int nviews, const gsf_camera *__restrict__ cams,
     const float *__restrict__ tfinal, const uint32_t *__restrict__ ncontrib,
     const float4 *__restrict__ fstate, const float4 *__restrict__ ckpt,
-    const float *__restrict__ bg, const float *__restrict__ dl, float *__restrict__ g2d, int nrec) {
+    const float *__restrict__ bg, const float *__restrict__ dl, KeyPlace kp) {
     constexpr int NT = bwd_threads<T>();
     __shared__ float4 s_a[B];
     __shared__ float4 s_b[B];
     __shared__ float4 s_c[B];
-    __shared__ uint32_t s_r[B];
+    __shared__ uint32_t s_q[B];
     __shared__ float s_g[NT / 64][9][B];
     __shared__ float s_h[B];
     __shared__ uint32_t s_nmax;
@@ -498,8 +508,68 @@ __global__ __launch_bounds__(bwd_threads<T>()) void k_render_bwd_ckpt(
         const uint32_t us = rg.x + u * B;
         const uint32_t ue = min(rg.y, us + B);
         render_bwd_unit<T, B, 1>(lo, us, ue, u + 1 == units, rg, vals, sp, views, nviews, cams,
-                                 tfinal, ncontrib, fstate, ckpt, nullptr, bg, dl, g2d, nrec, s_a,
-                                 s_b, s_c, s_r, s_g, s_h, &s_nmax);
+                                 tfinal, ncontrib, fstate, ckpt, nullptr, bg, dl, kp, s_a, s_b,
+                                 s_c, s_q, s_g, s_h, &s_nmax);
+    }
+}
+
+// Per-record sum of the per-key screen-space gradients into g2d [9][nrec]:
+// record r's keys sit at koff[r] .. koff[r] + count[r] - 1.  A lane sums its
+// own record's keys when it has at most kSumLane of them; larger records are
+// summed by the whole wave, one after the other, 64 keys a step.  After a key
+// overflow nothing was listed and g2d is written as zeros.
+constexpr uint32_t kSumLane = 32;
+
+__device__ __forceinline__ void add_key(const KeyPlace &kp, uint32_t q, float (&S)[9]) {
+    const float4 a = kp.pa[q], b = kp.pb[q];
+    S[0] += a.x;
+    S[1] += a.y;
+    S[2] += a.z;
+    S[3] += a.w;
+    S[4] += b.x;
+    S[5] += b.y;
+    S[6] += b.z;
+    S[7] += b.w;
+    S[8] += kp.pc[q];
+}
+
+__global__ __launch_bounds__(256) void k_grad_sum(KeyPlace kp, int nrec, float *__restrict__ g2d) {
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    const bool over = *kp.m_total > (unsigned long long)kp.capacity;
+    uint32_t cnt = 0u, base = 0u;
+    if (r < nrec && !over) {
+        cnt = kp.count[r];
+        if (cnt != 0u) base = kp.koff[r];
+    }
+    float S[9];
+#pragma unroll
+    for (int f = 0; f < 9; f++) S[f] = 0.f;
+    const bool own = cnt <= kSumLane;
+    if (own)
+        for (uint32_t i = 0; i < cnt; i++) add_key(kp, base + i, S);
+    const int lane = __lane_id();
+    uint64_t big = __ballot(!own);
+    while (big) {   // wave-uniform
+        const int src = __builtin_ctzll(big);
+        const uint32_t b0 = __shfl(base, src, 64), n0 = __shfl(cnt, src, 64);
+        float W[9];
+#pragma unroll
+        for (int f = 0; f < 9; f++) W[f] = 0.f;
+        for (uint32_t i = (uint32_t)lane; i < n0; i += 64u) add_key(kp, b0 + i, W);
+#pragma unroll
+        for (int f = 0; f < 9; f++) {
+#pragma unroll
+            for (int m = 32; m >= 1; m >>= 1) W[f] += __shfl_xor(W[f], m, 64);
+        }
+        if (lane == src) {
+#pragma unroll
+            for (int f = 0; f < 9; f++) S[f] = W[f];
+        }
+        big &= big - 1u;
+    }
+    if (r < nrec) {
+#pragma unroll
+        for (int f = 0; f < 9; f++) g2d[(size_t)f * nrec + r] = S[f];
     }
 }
 
@@ -748,21 +818,21 @@ void render_fwd_tb(hipStream_t s, const RenderArgs &a, float *out) {
 }
 
 template <int T, int B>
-void render_bwd_tb(hipStream_t s, const RenderArgs &a, const float *dl, float *g2d) {
+void render_bwd_tb(hipStream_t s, const RenderArgs &a, const float *dl) {
     constexpr int NT = bwd_threads<T>();
     if (a.t_mode == 1)
         k_render_bwd_ckpt<T, B><<<a.bwd_grid, NT, 0, s>>>(a.ranges, a.total_tiles, a.m_dev, a.m_host,
                                                          a.vals, a.sp, a.views, a.nviews, a.cams,
                                                          a.tfinal, a.ncontrib, a.fstate, a.ckpt, a.bg,
-                                                         dl, g2d, a.nrec);
+                                                         dl, a.kp);
     else if (a.t_mode == 2)
         k_render_bwd<T, B, 2><<<a.total_tiles, NT, 0, s>>>(a.order, a.ranges, a.vals, a.sp,
                                                         a.views, a.nviews, a.cams, a.tfinal,
-                                                        a.ncontrib, a.tstore, a.bg, dl, g2d, a.nrec);
+                                                        a.ncontrib, a.tstore, a.bg, dl, a.kp);
     else
         k_render_bwd<T, B, 0><<<a.total_tiles, NT, 0, s>>>(a.order, a.ranges, a.vals, a.sp,
                                                         a.views, a.nviews, a.cams, a.tfinal,
-                                                        a.ncontrib, nullptr, a.bg, dl, g2d, a.nrec);
+                                                        a.ncontrib, nullptr, a.bg, dl, a.kp);
 }
 
 template <int T>
@@ -773,10 +843,10 @@ void render_fwd_t(hipStream_t s, const RenderArgs &a, float *out) {
 }
 
 template <int T>
-void render_bwd_t(hipStream_t s, const RenderArgs &a, const float *dl, float *g2d) {
-    if (a.batch == 64) render_bwd_tb<T, 64>(s, a, dl, g2d);
-    else if (a.batch == 128) render_bwd_tb<T, 128>(s, a, dl, g2d);
-    else render_bwd_tb<T, 256>(s, a, dl, g2d);
+void render_bwd_t(hipStream_t s, const RenderArgs &a, const float *dl) {
+    if (a.batch == 64) render_bwd_tb<T, 64>(s, a, dl);
+    else if (a.batch == 128) render_bwd_tb<T, 128>(s, a, dl);
+    else render_bwd_tb<T, 256>(s, a, dl);
 }
 
 }  // namespace
@@ -787,10 +857,15 @@ void launch_render_fwd(hipStream_t s, const RenderArgs &a, float *out_rgba) {
     else render_fwd_t<32>(s, a, out_rgba);
 }
 
-void launch_render_bwd(hipStream_t s, const RenderArgs &a, const float *dl_drgba, float *g2d) {
-    if (a.tile == 8) render_bwd_t<8>(s, a, dl_drgba, g2d);
-    else if (a.tile == 16) render_bwd_t<16>(s, a, dl_drgba, g2d);
-    else render_bwd_t<32>(s, a, dl_drgba, g2d);
+void launch_render_bwd(hipStream_t s, const RenderArgs &a, const float *dl_drgba) {
+    if (a.tile == 8) render_bwd_t<8>(s, a, dl_drgba);
+    else if (a.tile == 16) render_bwd_t<16>(s, a, dl_drgba);
+    else render_bwd_t<32>(s, a, dl_drgba);
+}
+
+void launch_grad_sum(hipStream_t s, const KeyPlace &kp, int nrec, float *g2d) {
+    if (nrec <= 0) return;
+    k_grad_sum<<<(nrec + 255) / 256, 256, 0, s>>>(kp, nrec, g2d);
 }
 
 void launch_count_pairs(hipStream_t s, int tile, int total_tiles, const uint2 *ranges,

@@ -254,8 +254,8 @@ __global__ __launch_bounds__(1024) void k_scan_top(uint32_t *__restrict__ block_
 // ellipse reaches (row_span, the rule the projection counted with).
 __global__ __launch_bounds__(kScanBlock) void k_scan_dup(
     const uint32_t *__restrict__ count, const uint2 *__restrict__ rect,
-    const float4 *__restrict__ ell, const uint2 *__restrict__ rspan, SplatPtrs sp, int nrec, int n,
-    int tile,
+    const float4 *__restrict__ ell, const uint2 *__restrict__ rspan, SplatPtrs sp,
+    uint32_t *__restrict__ koff, int nrec, int n, int tile,
     const ViewDesc *__restrict__ views, const uint32_t *__restrict__ block_prefix,
     const unsigned long long *__restrict__ m_total, int64_t capacity, uint32_t *__restrict__ keys,
     uint32_t *__restrict__ vals, uint2 *__restrict__ ranges, int total_tiles) {
@@ -281,12 +281,14 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_dup(
     }
     uint32_t total;
     uint32_t off = block_excl_scan_256(sum, s_wave, total);
+    const uint32_t gbase = block_prefix[blockIdx.x];
 #pragma unroll
     for (int k = 0; k < kScanIpt; k++) {
         const int i = threadIdx.x * kScanIpt + k;
         s_off[i] = off;
         if (cnt[k] != 0u) {
             const uint32_t r = (uint32_t)(base + k);
+            koff[r] = gbase + off;             // the record's first key
             const uint2 rc = rect[r];
             s_rect[i] = rc;
             s_view[i] = (int)(r / (uint32_t)n);
@@ -304,7 +306,6 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_dup(
         off += cnt[k];
     }
     __syncthreads();
-    const uint32_t gbase = block_prefix[blockIdx.x];
     for (uint32_t q = threadIdx.x; q < total; q += kScanBlock) {
         // the last record whose offset is <= q (records without keys share the
         // offset of the next record, so the last one is the owner)
@@ -693,15 +694,15 @@ int launch_radix_sort(hipStream_t s, const uint32_t *kin, const uint32_t *vin, u
 int scan_blocks(int64_t nrec) { return (int)((nrec + kScanTile - 1) / kScanTile) + 1; }
 
 void launch_scan_duplicate(hipStream_t s, const uint32_t *count, const uint2 *rect,
-                           const float4 *ell, const uint2 *rspan, SplatPtrs sp, int nrec, int n,
-                           int tile,
+                           const float4 *ell, const uint2 *rspan, SplatPtrs sp, uint32_t *koff,
+                           int nrec, int n, int tile,
                            const ViewDesc *views, uint32_t *block_sums, uint32_t *keys,
                            uint32_t *vals, uint32_t *m_dev, unsigned long long *m_total,
                            uint32_t *flags, int64_t capacity, uint2 *ranges, int total_tiles) {
     const int nb = (nrec + kScanTile - 1) / kScanTile;
     k_scan_reduce<<<nb, kScanBlock, 0, s>>>(count, nrec, block_sums);
     k_scan_top<<<1, 1024, 0, s>>>(block_sums, nb, m_dev, m_total, flags, capacity);
-    k_scan_dup<<<nb, kScanBlock, 0, s>>>(count, rect, ell, rspan, sp, nrec, n, tile, views,
+    k_scan_dup<<<nb, kScanBlock, 0, s>>>(count, rect, ell, rspan, sp, koff, nrec, n, tile, views,
                                          block_sums, m_total, capacity, keys, vals, ranges,
                                          total_tiles);
 }
