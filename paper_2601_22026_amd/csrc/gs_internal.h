@@ -104,21 +104,48 @@ constexpr int kPackCols = 255;
 // tile = 1 << tile_log2.  The square roots are the hardware's (within an ulp):
 // the same code counts the tiles in the projection and emits them in the
 // duplicate pass, so both agree exactly.
-__device__ __forceinline__ bool row_span(const Ellipse &e, int ty, int tile_log2, int W, int H,
-                                         int x0, int x1, int &c0, int &c1) {
-    const int ja = ty << tile_log2, jb = min((ty + 1) << tile_log2, H) - 1;
+// Pixel columns [a, b] (not clamped to the image) whose centres lie in the
+// padded ellipse's x extent over the band of pixel rows ja..jb.
+__device__ __forceinline__ void ellipse_cols(const Ellipse &e, int ja, int jb, int &a, int &b) {
     const float ya = (float)(ja - e.iy) + e.hyo, yb = (float)(jb - e.iy) + e.hyo;
     float lo = fmaxf(ya, -e.ey), hi = fminf(yb, e.ey);
     if (lo > hi) lo = hi = ya > e.ey ? e.ey : -e.ey;   // band beside the ellipse: its tip
     const float d1 = fminf(fmaxf(e.dyr, lo), hi), d2 = fminf(fmaxf(-e.dyr, lo), hi);
     const float xr = e.slope * d1 + __builtin_amdgcn_sqrtf(fmaxf(e.kw - e.ws * (d1 * d1), 0.f)) + kBoxAbs;
     const float xl = e.slope * d2 - __builtin_amdgcn_sqrtf(fmaxf(e.kw - e.ws * (d2 * d2), 0.f)) - kBoxAbs;
-    const int a = max(e.ix + (int)ceilf(xl - e.hxo), 0);
-    const int b = min(e.ix + (int)floorf(xr - e.hxo), W - 1);
+    a = e.ix + (int)ceilf(xl - e.hxo);
+    b = e.ix + (int)floorf(xr - e.hxo);
+}
+
+__device__ __forceinline__ bool row_span(const Ellipse &e, int ty, int tile_log2, int W, int H,
+                                         int x0, int x1, int &c0, int &c1) {
+    const int ja = ty << tile_log2, jb = min((ty + 1) << tile_log2, H) - 1;
+    int a, b;
+    ellipse_cols(e, ja, jb, a, b);
+    a = max(a, 0);
+    b = min(b, W - 1);
     if (a > b) return false;
     c0 = max(a >> tile_log2, x0);
     c1 = min(b >> tile_log2, x1);
     return c0 <= c1;
+}
+
+// The compositing kernels of 16-pixel tiles give each wave one 8 x 8 quadrant
+// (q = 0..3: column half q & 1, row half q >> 1) and skip the splats whose
+// padded ellipse reaches no pixel centre of it: bit q of the mask is set when
+// the ellipse's x extent over the quadrant's rows meets its columns.  The same
+// bound as the tile lists, so every pixel with alpha >= 1/255 lies in a
+// quadrant whose bit is set.  (x0, y0): the tile's first pixel.
+__device__ __forceinline__ uint32_t quadrant_mask(const Ellipse &e, int x0, int y0) {
+    uint32_t m = 0u;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        const int xa = x0 + (q & 1) * 8, ya = y0 + (q >> 1) * 8;
+        int a, b;
+        ellipse_cols(e, ya, ya + 7, a, b);
+        if (max(a, xa) <= min(b, xa + 7)) m |= 1u << q;
+    }
+    return m;
 }
 
 // Where the adjoint puts each key's screen-space gradient: the duplicate pass

@@ -116,15 +116,20 @@ __global__ __launch_bounds__(T * T < 256 ? T * T : 256) void k_render_fwd(
     const ViewDesc *__restrict__ views, int nviews, const gsf_camera *__restrict__ cams,
     float *__restrict__ out_rgba, float *__restrict__ tfinal, uint32_t *__restrict__ ncontrib,
     float4 *__restrict__ ckpt, float4 *__restrict__ fstate, float *__restrict__ tstore,
-    const float *__restrict__ bg, const float *__restrict__ cull_gaze, float cull_radius) {
+    const float *__restrict__ bg, const float *__restrict__ cull_gaze, float cull_radius,
+    const float4 *__restrict__ ell) {
     constexpr bool CKPT = MODE == 1;
     constexpr int NT = T * T < 256 ? T * T : 256;
     constexpr int PPT = T * T / NT;
     constexpr int ROWS = NT / T;
+    constexpr bool QUAD = T == 16;   // wave w composites quadrant w (8 x 8 pixels)
     constexpr int U = 4;   // splats between wave-level completion checks
-    __shared__ float4 s_a[B];
-    __shared__ float4 s_b[B];
-    __shared__ float4 s_c[B];
+    // slot B: an inert splat (power2 = 0 < tau = +inf: never included) that
+    // pads a wave's last group of U
+    __shared__ float4 s_a[B + 1];
+    __shared__ float4 s_b[B + 1];
+    __shared__ float4 s_c[B + 1];
+    __shared__ uint8_t s_m[QUAD ? B : 1];   // quadrants each splat reaches
 
     const int gt = (int)order[blockIdx.x];
     const int v = view_of_tile(views, nviews, gt);
@@ -136,18 +141,27 @@ __global__ __launch_bounds__(T * T < 256 ? T * T : 256) void k_render_fwd(
         if (tx < f.tx0 || tx > f.tx1 || ty < f.ty0 || ty > f.ty1) return;
     }
     const uint2 rg = ranges[gt];
-    const int lx = threadIdx.x % T, ly = threadIdx.x / T;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int lx = QUAD ? (wave & 1) * 8 + (lane & 7) : threadIdx.x % T;
+    const int ly = QUAD ? (wave >> 1) * 8 + (lane >> 3) : threadIdx.x / T;
+    if (threadIdx.x == 0) {
+        s_a[B] = make_float4(0.f, 0.f, 0.f, 0.f);
+        s_b[B] = make_float4(0.f, 0.f, 0.f, 0.f);
+        s_c[B] = make_float4(0.f, __builtin_inff(), 0.f, 0.f);
+    }
 
     // Tr[k] is the pixel's transmittance while it composites; a pixel that has
     // stopped (or lies outside the image) holds -T instead, so one compare
     // gives its state and no flag is carried from splat to splat.
     float px[PPT], py[PPT], Tr[PPT], cr[PPT], cg[PPT], cb[PPT];
     uint32_t last[PPT];
+    int pix[PPT];   // the pixel's row-major index in the tile
 #pragma unroll
     for (int k = 0; k < PPT; k++) {
         const int x = tx * T + lx, y = ty * T + ly + k * ROWS;
         px[k] = (float)x;   // integer pixel; its centre's offset from a mean is splat_dx
         py[k] = (float)y;
+        pix[k] = (ly + k * ROWS) * T + lx;
         Tr[k] = x < vd.width && y < vd.height ? 1.f : -1.f;
         cr[k] = cg[k] = cb[k] = 0.f;
         last[k] = 0u;
@@ -155,70 +169,84 @@ __global__ __launch_bounds__(T * T < 256 ? T * T : 256) void k_render_fwd(
 
     for (uint32_t bs = rg.x; bs < rg.y; bs += B) {
         const int nb = (int)min((uint32_t)B, rg.y - bs);
-        const int nbu = (nb + U - 1) / U * U;   // padded with inert splats to whole groups
         __syncthreads();
-        for (int j = threadIdx.x; j < nbu; j += NT) {
-            if (j < nb) {
-                const uint32_t r = vals[bs + j];
-                const float4 ra = sp.a[r], rb = sp.b[r], rc = sp.c[r];
-                s_a[j] = ra;
-                s_b[j] = rb;
-                s_c[j] = make_float4(rc.x, splat_tau(rb), rc.z, rc.w);
-            } else {   // power2 = 0 < tau = +inf: never included
-                s_a[j] = make_float4(0.f, 0.f, 0.f, 0.f);
-                s_b[j] = make_float4(0.f, 0.f, 0.f, 0.f);
-                s_c[j] = make_float4(0.f, __builtin_inff(), 0.f, 0.f);
+        for (int j = threadIdx.x; j < nb; j += NT) {
+            const uint32_t r = vals[bs + j];
+            const float4 ra = sp.a[r], rb = sp.b[r], rc = sp.c[r];
+            s_a[j] = ra;
+            s_b[j] = rb;
+            s_c[j] = make_float4(rc.x, splat_tau(rb), rc.z, rc.w);
+            if (QUAD) {
+                const float4 e0 = ell[r];
+                const Ellipse e{e0.x, e0.y, e0.z, e0.w, sqrtf(e0.y / e0.z), ra.x, ra.y, (int)rc.z, (int)rc.w};
+                s_m[j] = (uint8_t)quadrant_mask(e, tx * T, ty * T);
             }
         }
         __syncthreads();
-        for (int j0 = 0; j0 < nbu; j0 += U) {
-            bool all = true;
+        bool done = false;
+        // the batch 64 splats at a time: the wave's splats are the set bits of m
+        for (int cb0 = 0; cb0 < nb && !done; cb0 += 64) {
+            const int jl = cb0 + lane;
+            uint64_t m = __ballot(jl < nb && (!QUAD || ((s_m[QUAD ? jl : 0] >> wave) & 1u)));
+            while (m != 0ull) {
+                bool all = true;
 #pragma unroll
-            for (int k = 0; k < PPT; k++) all &= !(Tr[k] > 0.f);
-            if (__all(all)) break;
-            // Phase 1: the U splats' alphas are independent of each other and of
-            // the pixel state; computed without branches (skipped splats get
-            // valid = false; every operand is read whatever the outcome).
-            float4 a[U], b[U];
-            float4 c[U];
-#pragma unroll
-            for (int u = 0; u < U; u++) {
-                a[u] = s_a[j0 + u];
-                b[u] = s_b[j0 + u];
-                c[u] = s_c[j0 + u];
-            }
-#pragma unroll
-            for (int k = 0; k < PPT; k++) {
-                float alpha[U];
-                bool valid[U];
-#pragma unroll
-                for (int u = 0; u < U; u++) {
-                    const float dx = splat_dx(px[k], c[u].z, a[u].x);
-                    const float dy = splat_dx(py[k], c[u].w, a[u].y);
-                    const float power2 =
-                        fmaf(a[u].z * dx, dx, fmaf(b[u].x * dy, dy, (a[u].w * dx) * dy));
-                    valid[u] = !(power2 > 0.f) & !(power2 < c[u].y);
-                    alpha[u] = fminf(kAlphaMax, b[u].y * __builtin_amdgcn_exp2f(power2));
+                for (int k = 0; k < PPT; k++) all &= !(Tr[k] > 0.f);
+                if (__all(all)) {
+                    done = true;
+                    break;
                 }
-                // Phase 2: the sequential front-to-back update.  An included
-                // splat performs exactly the float operations of the definition
-                // (Tn = T (1 - alpha), w = alpha T, C += colour w); any other
-                // gets w = 0, which leaves the (non-negative) colour sums as
-                // they are bit for bit.
+                // the next U splats of the wave (the inert slot when m runs out)
+                int jj[U];
 #pragma unroll
                 for (int u = 0; u < U; u++) {
-                    const float Tn = Tr[k] * (1.f - alpha[u]);
-                    const bool take = valid[u] && Tr[k] > 0.f;
-                    const bool stop = take && Tn < kTStop;
-                    const bool inc = take && !stop;
-                    if (MODE == 2 && inc)
-                        tstore[(size_t)(bs + (uint32_t)(j0 + u)) * (T * T) + threadIdx.x + k * NT] = Tr[k];
-                    const float w = (inc ? alpha[u] : 0.f) * Tr[k];
-                    cr[k] = fmaf(b[u].z, w, cr[k]);
-                    cg[k] = fmaf(b[u].w, w, cg[k]);
-                    cb[k] = fmaf(c[u].x, w, cb[k]);
-                    Tr[k] = inc ? Tn : (stop ? -Tr[k] : Tr[k]);
-                    last[k] = inc ? bs + (uint32_t)(j0 + u) - rg.x + 1u : last[k];
+                    jj[u] = m != 0ull ? cb0 + __builtin_ctzll(m) : B;
+                    m &= m - 1ull;
+                }
+                // Phase 1: the U splats' alphas are independent of each other and of
+                // the pixel state; computed without branches (skipped splats get
+                // valid = false; every operand is read whatever the outcome).
+                float4 a[U], b[U];
+                float4 c[U];
+#pragma unroll
+                for (int u = 0; u < U; u++) {
+                    a[u] = s_a[jj[u]];
+                    b[u] = s_b[jj[u]];
+                    c[u] = s_c[jj[u]];
+                }
+#pragma unroll
+                for (int k = 0; k < PPT; k++) {
+                    float alpha[U];
+                    bool valid[U];
+#pragma unroll
+                    for (int u = 0; u < U; u++) {
+                        const float dx = splat_dx(px[k], c[u].z, a[u].x);
+                        const float dy = splat_dx(py[k], c[u].w, a[u].y);
+                        const float power2 =
+                            fmaf(a[u].z * dx, dx, fmaf(b[u].x * dy, dy, (a[u].w * dx) * dy));
+                        valid[u] = !(power2 > 0.f) & !(power2 < c[u].y);
+                        alpha[u] = fminf(kAlphaMax, b[u].y * __builtin_amdgcn_exp2f(power2));
+                    }
+                    // Phase 2: the sequential front-to-back update.  An included
+                    // splat performs exactly the float operations of the definition
+                    // (Tn = T (1 - alpha), w = alpha T, C += colour w); any other
+                    // gets w = 0, which leaves the (non-negative) colour sums as
+                    // they are bit for bit.
+#pragma unroll
+                    for (int u = 0; u < U; u++) {
+                        const float Tn = Tr[k] * (1.f - alpha[u]);
+                        const bool take = valid[u] && Tr[k] > 0.f;
+                        const bool stop = take && Tn < kTStop;
+                        const bool inc = take && !stop;
+                        if (MODE == 2 && inc)
+                            tstore[(size_t)(bs + (uint32_t)jj[u]) * (T * T) + pix[k]] = Tr[k];
+                        const float w = (inc ? alpha[u] : 0.f) * Tr[k];
+                        cr[k] = fmaf(b[u].z, w, cr[k]);
+                        cg[k] = fmaf(b[u].w, w, cg[k]);
+                        cb[k] = fmaf(c[u].x, w, cb[k]);
+                        Tr[k] = inc ? Tn : (stop ? -Tr[k] : Tr[k]);
+                        last[k] = inc ? bs + (uint32_t)jj[u] - rg.x + 1u : last[k];
+                    }
                 }
             }
         }
@@ -226,7 +254,7 @@ __global__ __launch_bounds__(T * T < 256 ? T * T : 256) void k_render_fwd(
             float4 *slot = ckpt + (size_t)((bs + B) / B) * (T * T);
 #pragma unroll
             for (int k = 0; k < PPT; k++)
-                slot[threadIdx.x + k * NT] = make_float4(fabsf(Tr[k]), cr[k], cg[k], cb[k]);
+                slot[pix[k]] = make_float4(fabsf(Tr[k]), cr[k], cg[k], cb[k]);
         }
         bool all = true;
 #pragma unroll
@@ -268,18 +296,22 @@ __device__ __forceinline__ void render_bwd_unit(
     const uint32_t *__restrict__ ncontrib, const float4 *__restrict__ fstate,
     const float4 *__restrict__ ckpt, const float *__restrict__ tstore, const float *__restrict__ bg,
     const float *__restrict__ dl, const KeyPlace &kp, float4 *s_a, float4 *s_b, float4 *s_c,
-    uint32_t *s_q, float (*s_g)[9][B], float *s_h, uint32_t *s_nmax) {
+    uint32_t *s_q, uint8_t *s_m, float (*s_g)[9][B], float *s_h, uint32_t *s_nmax) {
     constexpr bool CKPT = MODE == 1;
     constexpr int TL = T == 8 ? 3 : T == 16 ? 4 : 5;
     constexpr int NT = bwd_threads<T>();
     constexpr int PPT = T * T / NT;
     constexpr int ROWS = NT / T;
     constexpr int NW = NT / 64;
+    // 16-pixel tiles: one wave, pixel block k = quadrant k of the tile (8 x 8),
+    // and a splat skips the quadrants its padded ellipse does not reach
+    constexpr bool QUAD = T == 16;
+    static_assert(!QUAD || (NT == 64 && PPT == 4), "quadrant layout: one wave, four blocks");
     const int v = view_of_tile(views, nviews, gt);
     const ViewDesc vd = views[v];
     const int local = gt - vd.tile_off;
     const int ty = local / vd.tiles_x, tx = local - ty * vd.tiles_x;
-    const int lx = threadIdx.x % T, ly = threadIdx.x / T;
+    const int lane = threadIdx.x & 63;
     const float *bgv = bg ? bg + 3 * v : cams[v].bg;
     const float bg0 = bgv[0], bg1 = bgv[1], bg2 = bgv[2];
     const size_t plane = (size_t)vd.width * vd.height;
@@ -289,10 +321,14 @@ __device__ __forceinline__ void render_bwd_unit(
     // plane's share), carried as one value since only that difference is used
     float px[PPT], py[PPT], Tr[PPT], Tf[PPT], gR[PPT], g0[PPT], g1[PPT], g2[PPT], gA[PPT];
     uint32_t nc[PPT];
+    int pix[PPT];   // the pixel's row-major index in the tile
     uint32_t my_max = 0;
 #pragma unroll
     for (int k = 0; k < PPT; k++) {
-        const int x = tx * T + lx, y = ty * T + ly + k * ROWS;
+        const int lx = QUAD ? (k & 1) * 8 + (lane & 7) : threadIdx.x % T;
+        const int ly = QUAD ? (k >> 1) * 8 + (lane >> 3) : threadIdx.x / T + k * ROWS;
+        pix[k] = ly * T + lx;
+        const int x = tx * T + lx, y = ty * T + ly;
         const bool inside = x < vd.width && y < vd.height;
         const size_t q = inside ? (size_t)y * vd.width + x : 0;
         px[k] = (float)x;   // integer pixel; its centre's offset from a mean is splat_dx
@@ -313,9 +349,7 @@ __device__ __forceinline__ void render_bwd_unit(
         if (CKPT && !last_unit && rg.x + nc[k] > us) {
             // colour behind the unit = final colour - colour accumulated at its end
             const float4 fs = fstate[vd.pix_off + q];
-            // threadIdx.x + k * NT is the pixel's row-major index in the tile, the
-            // index the forward wrote with its own thread count
-            const float4 cp = ckpt[(size_t)(ue / B) * (T * T) + threadIdx.x + k * NT];
+            const float4 cp = ckpt[(size_t)(ue / B) * (T * T) + pix[k]];
             Tr[k] = cp.x;
             gR[k] = gbg + g0[k] * (fs.y - cp.y) + g1[k] * (fs.z - cp.z) + g2[k] * (fs.w - cp.w);
         } else {
@@ -345,6 +379,11 @@ __device__ __forceinline__ void render_bwd_unit(
             s_c[j] = make_float4(rc.x, splat_tau(rb), rc.z, rc.w);
             s_q[j] = key_slot(kp, sp, r, ty, tx, TL, vd.width, vd.height);
             s_h[j] = rc.y;
+            if (QUAD) {
+                const float4 e0 = kp.ell[r];
+                const Ellipse e{e0.x, e0.y, e0.z, e0.w, sqrtf(e0.y / e0.z), ra.x, ra.y, (int)rc.z, (int)rc.w};
+                s_m[j] = (uint8_t)quadrant_mask(e, tx * T, ty * T);
+            }
         }
         for (int e = threadIdx.x; e < NW * 9 * B; e += NT) (&s_g[0][0][0])[e] = 0.f;
         __syncthreads();
@@ -354,6 +393,7 @@ __device__ __forceinline__ void render_bwd_unit(
             const float4 b = s_b[j];
             const float4 c = s_c[j];
             const float hy = s_h[j];
+            const uint32_t qm = QUAD ? s_m[j] : 0u;
             // row offset of the tile's first row from the mean; block k adds k ROWS
             const float dy0 = splat_dx((float)(ty * T), c.w, a.y);
             // per lane sums: dpw dx, dpw dy, dpw dx^2, dpw dx dy, dpw dy^2 (dpw = dL/dpower),
@@ -366,7 +406,8 @@ __device__ __forceinline__ void render_bwd_unit(
             bool any = false;
 #pragma unroll
             for (int k = 0; k < PPT; k++) {
-                if (!rows_meet(dy0 + (float)(k * ROWS), (float)(ROWS - 1), hy)) continue;   // wave-uniform
+                if (QUAD ? !((qm >> k) & 1u)                                        // wave-uniform
+                         : !rows_meet(dy0 + (float)(k * ROWS), (float)(ROWS - 1), hy)) continue;
                 // Branch-free per lane: every value is computed and a pixel the
                 // splat does not reach (behind its last contributor, or alpha
                 // below 1/255) adds exact zeros and keeps its state.  An
@@ -382,7 +423,7 @@ __device__ __forceinline__ void render_bwd_unit(
                 const float inv = __builtin_amdgcn_rcpf(1.f - alpha);   // alpha <= 0.99
                 float Tb;
                 if (MODE == 2)
-                    Tb = inc ? tstore[(size_t)(bs + (uint32_t)j) * (T * T) + threadIdx.x + k * NT] : 0.f;
+                    Tb = inc ? tstore[(size_t)(bs + (uint32_t)j) * (T * T) + pix[k]] : 0.f;
                 else
                     Tb = Tr[k] * inv;
                 const float gc = fmaf(g2[k], c.x, fmaf(g1[k], b.w, g0[k] * b.z));
@@ -461,6 +502,7 @@ __global__ __launch_bounds__(bwd_threads<T>()) void k_render_bwd(
     __shared__ float4 s_b[B];
     __shared__ float4 s_c[B];
     __shared__ uint32_t s_q[B];
+    __shared__ uint8_t s_m[B];
     __shared__ float s_g[NT / 64][9][B];
     __shared__ float s_h[B];
     __shared__ uint32_t s_nmax;
@@ -468,7 +510,7 @@ __global__ __launch_bounds__(bwd_threads<T>()) void k_render_bwd(
     const uint2 rg = ranges[gt];
     render_bwd_unit<T, B, MODE>(gt, rg.x, rg.y, true, rg, vals, sp, views, nviews, cams, tfinal,
                                 ncontrib, nullptr, nullptr, tstore, bg, dl, kp, s_a, s_b, s_c, s_q,
-                                s_g, s_h, &s_nmax);
+                                s_m, s_g, s_h, &s_nmax);
 }
 
 // Checkpoint mode: one workgroup per (tile, batch) unit id.  Unit u of tile t
@@ -489,6 +531,7 @@ __global__ __launch_bounds__(bwd_threads<T>()) void k_render_bwd_ckpt(
     __shared__ float4 s_b[B];
     __shared__ float4 s_c[B];
     __shared__ uint32_t s_q[B];
+    __shared__ uint8_t s_m[B];
     __shared__ float s_g[NT / 64][9][B];
     __shared__ float s_h[B];
     __shared__ uint32_t s_nmax;
@@ -509,7 +552,7 @@ __global__ __launch_bounds__(bwd_threads<T>()) void k_render_bwd_ckpt(
         const uint32_t ue = min(rg.y, us + B);
         render_bwd_unit<T, B, 1>(lo, us, ue, u + 1 == units, rg, vals, sp, views, nviews, cams,
                                  tfinal, ncontrib, fstate, ckpt, nullptr, bg, dl, kp, s_a, s_b,
-                                 s_c, s_q, s_g, s_h, &s_nmax);
+                                 s_c, s_q, s_m, s_g, s_h, &s_nmax);
     }
 }
 
@@ -854,15 +897,15 @@ void render_fwd_tb(hipStream_t s, const RenderArgs &a, float *out) {
     if (a.t_mode == 1)
         k_render_fwd<T, B, 1><<<g, NT, 0, s>>>(a.order, a.ranges, a.vals, a.sp, a.views,
                                               a.nviews, a.cams, out, a.tfinal, a.ncontrib, a.ckpt,
-                                              a.fstate, nullptr, a.bg, a.cull_gaze, a.cull_radius);
+                                              a.fstate, nullptr, a.bg, a.cull_gaze, a.cull_radius, a.kp.ell);
     else if (a.t_mode == 2)
         k_render_fwd<T, B, 2><<<g, NT, 0, s>>>(a.order, a.ranges, a.vals, a.sp, a.views,
                                               a.nviews, a.cams, out, a.tfinal, a.ncontrib, nullptr,
-                                              nullptr, a.tstore, a.bg, a.cull_gaze, a.cull_radius);
+                                              nullptr, a.tstore, a.bg, a.cull_gaze, a.cull_radius, a.kp.ell);
     else
         k_render_fwd<T, B, 0><<<g, NT, 0, s>>>(a.order, a.ranges, a.vals, a.sp, a.views,
                                               a.nviews, a.cams, out, a.tfinal, a.ncontrib, nullptr,
-                                              nullptr, nullptr, a.bg, a.cull_gaze, a.cull_radius);
+                                              nullptr, nullptr, a.bg, a.cull_gaze, a.cull_radius, a.kp.ell);
 }
 
 template <int T, int B>
