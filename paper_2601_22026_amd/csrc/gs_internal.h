@@ -136,15 +136,16 @@ __device__ __forceinline__ bool row_span(const Ellipse &e, int ty, int tile_log2
 // the ellipse's x extent over the quadrant's rows meets its columns.  The same
 // bound as the tile lists, so every pixel with alpha >= 1/255 lies in a
 // quadrant whose bit is set.  (x0, y0): the tile's first pixel.
+__device__ __forceinline__ bool quad_meets(const Ellipse &e, int xa, int ya) {
+    int a, b;
+    ellipse_cols(e, ya, ya + 7, a, b);
+    return max(a, xa) <= min(b, xa + 7);
+}
 __device__ __forceinline__ uint32_t quadrant_mask(const Ellipse &e, int x0, int y0) {
     uint32_t m = 0u;
 #pragma unroll
-    for (int q = 0; q < 4; q++) {
-        const int xa = x0 + (q & 1) * 8, ya = y0 + (q >> 1) * 8;
-        int a, b;
-        ellipse_cols(e, ya, ya + 7, a, b);
-        if (max(a, xa) <= min(b, xa + 7)) m |= 1u << q;
-    }
+    for (int q = 0; q < 4; q++)
+        if (quad_meets(e, x0 + (q & 1) * 8, y0 + (q >> 1) * 8)) m |= 1u << q;
     return m;
 }
 
@@ -279,6 +280,7 @@ struct RenderArgs {
     int tile = 16, batch = 128, total_tiles = 0, nviews = 1, nrec = 0;
     int t_mode = 0;                       // 0 recompute, 1 checkpointed, 2 stored transmittance
     int bwd_grid = 1;                     // workgroups of the checkpointed adjoint (unit ids)
+    int cus = 256;                        // compute units of the device
     const uint32_t *order = nullptr;      // tile ids, heavy tiles first
     const float *bg = nullptr;            // per-view background [V][3] replacing the cameras' bg
     const float *cull_gaze = nullptr;     // fovea culling: only tiles meeting the fovea are composited

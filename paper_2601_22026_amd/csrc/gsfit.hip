@@ -26,6 +26,7 @@ using namespace gsf;
 
 struct gsf_ctx {
     int device = 0;
+    int cus = 256;                             // compute units of the device
     hipStream_t stream = nullptr;
     std::string err;
 };
@@ -219,6 +220,7 @@ RenderArgs render_args(gsf_plan *p, const gsf_camera *cams, int64_t n) {
     a.tstore = p->b.tstore;
     a.m_dev = p->host_sized ? nullptr : p->b.m_dev;
     a.m_host = p->m_host;
+    a.cus = p->ctx->cus;
     a.kp.koff = p->b.koff;
     a.kp.count = p->b.count;
     a.kp.rect = p->b.rect;
@@ -496,6 +498,9 @@ gsf_status gsf_ctx_create(int device, void *hip_stream, gsf_ctx **out) {
     if (!c) return GSF_E_INVALID;
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
+        c->cus = cus;
     *out = c;
     return GSF_OK;
 }

@@ -277,13 +277,12 @@ __global__ __launch_bounds__(256) void k_project_fwd(const float *__restrict__ P
     const float k2 = 2.f * logf(255.f * g.o);
     const float hx = fmaf(sqrtf(k2 * p.a), 1.f + kBoxRel, kBoxAbs);
     const float hy = fmaf(sqrtf(k2 * p.c), 1.f + kBoxRel, kBoxAbs);
-    // conic pre-scaled for a base-2 exponent; the box half height goes with the
-    // splat (the compositing kernels skip rows beyond it and derive the alpha
-    // threshold tau = -log2(255 o) from the opacity)
+    // conic pre-scaled for a base-2 exponent, and the alpha threshold of the
+    // same exponent: o 2^power2 >= 1/255 where power2 >= tau = -log2(255 o)
     sp.a[r] = make_float4((float)(ixd + 0.5 - mxd), (float)(iyd + 0.5 - myd), (-0.5f * kLog2e) * p.A,
                           -kLog2e * p.B);
     sp.b[r] = make_float4((-0.5f * kLog2e) * p.C, g.o, col[0], col[1]);
-    sp.c[r] = make_float4(col[2], hy, (float)ixd, (float)iyd);
+    sp.c[r] = make_float4(col[2], -log2f(255.f * g.o), (float)ixd, (float)iyd);
     depth_key[r] = __float_as_uint(p.t[2]);
     const ViewDesc vd = views[v];
     const float x0 = fmaxf(ceilf((float)(mxd - hx - 0.5)), 0.f);

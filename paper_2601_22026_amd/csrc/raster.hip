@@ -61,11 +61,16 @@ __device__ __forceinline__ bool splat_alpha(const float4 &a, const float4 &b, co
 template <int T>
 constexpr int bwd_threads() { return T == 32 ? 128 : 64; }
 
-// A record's c = (blue, hy, ix, iy) holds the padded half height hy of the
-// splat's support box (where o e^power >= 1/255 can hold; the bound the tile
-// lists are built with).  Staged into LDS as c = (blue, tau, ix, iy) plus hy
-// apart, tau derived from the opacity by the one expression every kernel uses.
-__device__ __forceinline__ float splat_tau(const float4 &b) { return -log2f(255.f * b.y); }
+// A record's c = (blue, tau, ix, iy): tau = -log2(255 o) is the alpha
+// threshold of the base-2 exponent, computed once by the projection.  The
+// padded half height of the support (where o e^power >= 1/255 can hold) is
+// the ellipse's y extent plus the absolute padding.
+__device__ __forceinline__ float support_half_height(const float4 &e0) {
+    return sqrtf(e0.y / e0.z) + kBoxAbs;
+}
+
+typedef __attribute__((address_space(3))) void *lds_void_ptr;
+__device__ __forceinline__ lds_void_ptr lds_ptr(void *p) { return (lds_void_ptr)p; }
 
 // Whether rows with offsets [lo, lo + span] from a splat's mean can meet its
 // support of half height h (NaN-safe: only a definite miss returns false).
@@ -124,12 +129,26 @@ __global__ __launch_bounds__(T * T < 256 ? T * T : 256) void k_render_fwd(
     constexpr int ROWS = NT / T;
     constexpr bool QUAD = T == 16;   // wave w composites quadrant w (8 x 8 pixels)
     constexpr int U = 4;   // splats between wave-level completion checks
-    // slot B: an inert splat (power2 = 0 < tau = +inf: never included) that
-    // pads a wave's last group of U
-    __shared__ float4 s_a[B + 1];
-    __shared__ float4 s_b[B + 1];
-    __shared__ float4 s_c[B + 1];
-    __shared__ uint8_t s_m[QUAD ? B : 1];   // quadrants each splat reaches
+    // PREF (a batch no larger than the workgroup): two LDS buffers; the
+    // records of the next batch are copied from global memory straight into
+    // the other buffer (global_load_lds, no registers; wave w copies entries
+    // 64 w .. 64 w + 63) while the current batch composites, the record ids
+    // being read one batch further ahead.
+    constexpr bool PREF = B <= NT;
+    // A buffer holds the batch's records a, b, c and support ellipses
+    // (slope, kw, ws, dyr) at sections 0, 1, 2, 3 of B + 1 entries.  Buffers
+    // 0 and 1 are separate arrays, so the compiler sees that reads of one do
+    // not wait for copies into the other.  Entry B of a, b, c: an inert splat
+    // (power2 = 0 < tau = +inf: never included) that pads a wave's last
+    // group of U.
+    // (Entry 0 of each array is unused: a copy addressed at an array's very
+    // start loses the alias information that lets reads of the other buffer
+    // proceed while it is in flight.)
+    constexpr int SEC = B + 1;
+    __shared__ float4 s_buf0_[1 + 4 * SEC];
+    __shared__ float4 s_buf1_[PREF ? 1 + 4 * SEC : 1];
+    float4 *const s_buf0 = s_buf0_ + 1;
+    float4 *const s_buf1 = s_buf1_ + 1;
 
     const int gt = (int)order[blockIdx.x];
     const int v = view_of_tile(views, nviews, gt);
@@ -145,9 +164,14 @@ __global__ __launch_bounds__(T * T < 256 ? T * T : 256) void k_render_fwd(
     const int lx = QUAD ? (wave & 1) * 8 + (lane & 7) : threadIdx.x % T;
     const int ly = QUAD ? (wave >> 1) * 8 + (lane >> 3) : threadIdx.x / T;
     if (threadIdx.x == 0) {
-        s_a[B] = make_float4(0.f, 0.f, 0.f, 0.f);
-        s_b[B] = make_float4(0.f, 0.f, 0.f, 0.f);
-        s_c[B] = make_float4(0.f, __builtin_inff(), 0.f, 0.f);
+        s_buf0[B] = make_float4(0.f, 0.f, 0.f, 0.f);
+        s_buf0[SEC + B] = make_float4(0.f, 0.f, 0.f, 0.f);
+        s_buf0[2 * SEC + B] = make_float4(0.f, __builtin_inff(), 0.f, 0.f);
+        if constexpr (PREF) {
+            s_buf1[B] = make_float4(0.f, 0.f, 0.f, 0.f);
+            s_buf1[SEC + B] = make_float4(0.f, 0.f, 0.f, 0.f);
+            s_buf1[2 * SEC + B] = make_float4(0.f, __builtin_inff(), 0.f, 0.f);
+        }
     }
 
     // Tr[k] is the pixel's transmittance while it composites; a pixel that has
@@ -167,27 +191,24 @@ __global__ __launch_bounds__(T * T < 256 ? T * T : 256) void k_render_fwd(
         last[k] = 0u;
     }
 
-    for (uint32_t bs = rg.x; bs < rg.y; bs += B) {
+    // Composite the batch at bs from one LDS buffer; true once every pixel of
+    // the tile has stopped.  Ends with a barrier, after which the buffer is free.
+    auto composite = [&](uint32_t bs, const float4 *buf) -> bool {
+        const float4 *SA = buf, *SB = buf + SEC, *SC = buf + 2 * SEC, *SE = buf + 3 * SEC;
         const int nb = (int)min((uint32_t)B, rg.y - bs);
-        __syncthreads();
-        for (int j = threadIdx.x; j < nb; j += NT) {
-            const uint32_t r = vals[bs + j];
-            const float4 ra = sp.a[r], rb = sp.b[r], rc = sp.c[r];
-            s_a[j] = ra;
-            s_b[j] = rb;
-            s_c[j] = make_float4(rc.x, splat_tau(rb), rc.z, rc.w);
-            if (QUAD) {
-                const float4 e0 = ell[r];
-                const Ellipse e{e0.x, e0.y, e0.z, e0.w, sqrtf(e0.y / e0.z), ra.x, ra.y, (int)rc.z, (int)rc.w};
-                s_m[j] = (uint8_t)quadrant_mask(e, tx * T, ty * T);
-            }
-        }
-        __syncthreads();
         bool done = false;
-        // the batch 64 splats at a time: the wave's splats are the set bits of m
+        // the batch 64 splats at a time: the wave's splats are the set bits of
+        // m (with 16-pixel tiles, those whose padded ellipse reaches the wave's
+        // quadrant)
         for (int cb0 = 0; cb0 < nb && !done; cb0 += 64) {
             const int jl = cb0 + lane;
-            uint64_t m = __ballot(jl < nb && (!QUAD || ((s_m[QUAD ? jl : 0] >> wave) & 1u)));
+            bool meet = jl < nb;
+            if (QUAD && meet) {
+                const float4 e0 = SE[jl], a0 = SA[jl], c0 = SC[jl];
+                const Ellipse e{e0.x, e0.y, e0.z, e0.w, sqrtf(e0.y / e0.z), a0.x, a0.y, (int)c0.z, (int)c0.w};
+                meet = quad_meets(e, tx * T + (wave & 1) * 8, ty * T + (wave >> 1) * 8);
+            }
+            uint64_t m = __ballot(meet);
             while (m != 0ull) {
                 bool all = true;
 #pragma unroll
@@ -210,9 +231,9 @@ __global__ __launch_bounds__(T * T < 256 ? T * T : 256) void k_render_fwd(
                 float4 c[U];
 #pragma unroll
                 for (int u = 0; u < U; u++) {
-                    a[u] = s_a[jj[u]];
-                    b[u] = s_b[jj[u]];
-                    c[u] = s_c[jj[u]];
+                    a[u] = SA[jj[u]];
+                    b[u] = SB[jj[u]];
+                    c[u] = SC[jj[u]];
                 }
 #pragma unroll
                 for (int k = 0; k < PPT; k++) {
@@ -259,7 +280,52 @@ __global__ __launch_bounds__(T * T < 256 ? T * T : 256) void k_render_fwd(
         bool all = true;
 #pragma unroll
         for (int k = 0; k < PPT; k++) all &= !(Tr[k] > 0.f);
-        if (__syncthreads_and(all)) break;
+        return __syncthreads_and(all);
+    };
+
+    if constexpr (PREF) {
+        // copy record r of entry threadIdx.x into a buffer (this wave's 64 slots)
+        auto stage = [&](float4 *buf, uint32_t r) {
+            float4 *d = buf + (threadIdx.x & ~63u);
+            __builtin_amdgcn_global_load_lds((const void *)(sp.a + r), lds_ptr(d), 16, 0, 0);
+            __builtin_amdgcn_global_load_lds((const void *)(sp.b + r), lds_ptr(d + SEC), 16, 0, 0);
+            __builtin_amdgcn_global_load_lds((const void *)(sp.c + r), lds_ptr(d + 2 * SEC), 16, 0, 0);
+            if constexpr (QUAD)
+                __builtin_amdgcn_global_load_lds((const void *)(ell + r), lds_ptr(d + 3 * SEC), 16, 0, 0);
+        };
+        const uint32_t j = threadIdx.x;
+        uint32_t rnext = 0u;
+        if (j < (uint32_t)B && rg.x + j < rg.y) stage(s_buf0, vals[rg.x + j]);
+        if (j < (uint32_t)B && rg.x + B + j < rg.y) rnext = vals[rg.x + B + j];
+        __syncthreads();   // the inert slots and the first batch
+        // Batches alternate between the buffers.  A batch has arrived before
+        // the barrier that ended the previous one, after which the other
+        // buffer is free: the next batch is copied there while this one
+        // composites.
+        for (uint32_t bs = rg.x; bs < rg.y;) {
+            if (j < (uint32_t)B && bs + B + j < rg.y) stage(s_buf1, rnext);
+            if (j < (uint32_t)B && bs + 2 * B + j < rg.y) rnext = vals[bs + 2 * B + j];
+            if (composite(bs, s_buf0)) break;
+            if ((bs += B) >= rg.y) break;
+            if (j < (uint32_t)B && bs + B + j < rg.y) stage(s_buf0, rnext);
+            if (j < (uint32_t)B && bs + 2 * B + j < rg.y) rnext = vals[bs + 2 * B + j];
+            if (composite(bs, s_buf1)) break;
+            bs += B;
+        }
+    } else {
+        __syncthreads();   // the inert slots
+        for (uint32_t bs = rg.x; bs < rg.y; bs += B) {
+            const int nb = (int)min((uint32_t)B, rg.y - bs);
+            for (int j = threadIdx.x; j < nb; j += NT) {
+                const uint32_t r = vals[bs + j];
+                s_buf0[j] = sp.a[r];
+                s_buf0[SEC + j] = sp.b[r];
+                s_buf0[2 * SEC + j] = sp.c[r];
+                if constexpr (QUAD) s_buf0[3 * SEC + j] = ell[r];
+            }
+            __syncthreads();
+            if (composite(bs, s_buf0)) break;
+        }
     }
 #pragma unroll
     for (int k = 0; k < PPT; k++) Tr[k] = fabsf(Tr[k]);
@@ -373,16 +439,16 @@ __device__ __forceinline__ void render_bwd_unit(
         __syncthreads();
         for (int j = threadIdx.x; j < nb; j += NT) {
             const uint32_t r = vals[bs + j];
-            const float4 ra = sp.a[r], rb = sp.b[r], rc = sp.c[r];
+            const float4 ra = sp.a[r], rb = sp.b[r], rc = sp.c[r], e0 = kp.ell[r];
             s_a[j] = ra;
             s_b[j] = rb;
-            s_c[j] = make_float4(rc.x, splat_tau(rb), rc.z, rc.w);
+            s_c[j] = rc;
             s_q[j] = key_slot(kp, sp, r, ty, tx, TL, vd.width, vd.height);
-            s_h[j] = rc.y;
             if (QUAD) {
-                const float4 e0 = kp.ell[r];
                 const Ellipse e{e0.x, e0.y, e0.z, e0.w, sqrtf(e0.y / e0.z), ra.x, ra.y, (int)rc.z, (int)rc.w};
                 s_m[j] = (uint8_t)quadrant_mask(e, tx * T, ty * T);
+            } else {
+                s_h[j] = support_half_height(e0);
             }
         }
         for (int e = threadIdx.x; e < NW * 9 * B; e += NT) (&s_g[0][0][0])[e] = 0.f;
@@ -392,7 +458,7 @@ __device__ __forceinline__ void render_bwd_unit(
             const float4 a = s_a[j];
             const float4 b = s_b[j];
             const float4 c = s_c[j];
-            const float hy = s_h[j];
+            const float hy = QUAD ? 0.f : s_h[j];
             const uint32_t qm = QUAD ? s_m[j] : 0u;
             // row offset of the tile's first row from the mean; block k adds k ROWS
             const float dy0 = splat_dx((float)(ty * T), c.w, a.y);
@@ -694,8 +760,7 @@ __global__ __launch_bounds__(T * T < 256 ? T * T : 256) void k_count_pairs(
             const uint32_t r = vals[e];
             visit++;
             float alpha, ae, ex, dx, dy;
-            const float4 ra = sp.a[r], rb = sp.b[r], rc = sp.c[r];
-            const float4 c = make_float4(rc.x, splat_tau(rb), rc.z, rc.w);
+            const float4 ra = sp.a[r], rb = sp.b[r], c = sp.c[r];
             if (!splat_alpha(ra, rb, c, px, py, alpha, ae, ex, dx, dy)) continue;
             const float Tn = Tr * (1.f - alpha);
             if (Tn < kTStop) break;
