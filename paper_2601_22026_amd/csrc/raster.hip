@@ -25,8 +25,10 @@
 // T_i of every included (splat, pixel) pair at [key position][pixel of tile];
 // the adjoint reads it; one workgroup per tile).  The nine per-splat screen-space
 // gradient terms of a wave are summed across its lanes with DPP row
-// operations, kept per wave in LDS, and flushed with one global atomic per
-// (unit, splat, field).
+// operations, kept per row in LDS, and stored once per (key, field) at the
+// key's own position; a separate pass sums each record's keys (no atomics).
+// With 16-pixel tiles each wave covers an 8x8 quadrant of the tile and skips
+// the splats whose padded support ellipse misses it.
 #include "gs_internal.h"
 
 namespace gsf {
@@ -36,7 +38,6 @@ constexpr float kLn2 = 0.69314718055994531f;
 
 // Shared by every kernel that walks a tile list so all take identical decisions.
 // a = (hx, hy, A2, B2), b = (C2, opacity, red, green), c = (blue, tau, ix, iy)
-// (c as staged: the record holds the support half height in place of tau)
 // with A2 = -log2(e) A / 2, B2 = -log2(e) B, C2 = -log2(e) C / 2; (x, y) is
 // the integer pixel (as float) and (dx, dy) its centre's offset from the mean.
 __device__ __forceinline__ float splat_dx(float x, float ix, float hx) { return (x - ix) + hx; }
@@ -349,6 +350,17 @@ __global__ __launch_bounds__(T * T < 256 ? T * T : 256) void k_render_fwd(
     }
 }
 
+// Per-splat gradient sums of one 16-lane row of the adjoint's lanes, for a
+// block of R consecutive splats (stored as soon as a block is done): nine
+// fields of R splats, plus one word so that the four rows of a wave fall in
+// different LDS banks.  Checkpointed units (one LDS batch, few per CU on
+// light scenes) store once per unit (R = 64); the whole-tile modes, whose
+// many one-wave workgroups need the occupancy, keep the slots small (R = 16).
+template <int MODE>
+constexpr int kRing = MODE == 1 ? 32 : 16;
+template <int MODE>
+constexpr int kGradSlot = 9 * kRing<MODE> + 1;
+
 // Unit of adjoint work: the entries [us, ue) of tile gt's list.  With
 // checkpoints (MODE 1) a unit is one LDS batch of B entries and starts from the
 // state the forward stored at the batch's end; otherwise a unit is the whole
@@ -362,9 +374,10 @@ __device__ __forceinline__ void render_bwd_unit(
     const uint32_t *__restrict__ ncontrib, const float4 *__restrict__ fstate,
     const float4 *__restrict__ ckpt, const float *__restrict__ tstore, const float *__restrict__ bg,
     const float *__restrict__ dl, const KeyPlace &kp, float4 *s_a, float4 *s_b, float4 *s_c,
-    uint32_t *s_q, uint8_t *s_m, float (*s_g)[9][B], float *s_h, uint32_t *s_nmax) {
+    uint32_t *s_q, uint8_t *s_m, float *s_g, uint64_t *s_hit, float *s_h, uint32_t *s_nmax) {
     constexpr bool CKPT = MODE == 1;
     constexpr int TL = T == 8 ? 3 : T == 16 ? 4 : 5;
+    constexpr int R = kRing<MODE>, GS = kGradSlot<MODE>;
     constexpr int NT = bwd_threads<T>();
     constexpr int PPT = T * T / NT;
     constexpr int ROWS = NT / T;
@@ -451,8 +464,8 @@ __device__ __forceinline__ void render_bwd_unit(
                 s_h[j] = support_half_height(e0);
             }
         }
-        for (int e = threadIdx.x; e < NW * 9 * B; e += NT) (&s_g[0][0][0])[e] = 0.f;
         __syncthreads();
+        uint64_t hit = 0ull;   // splats of the current block of R some pixel of the wave took
         for (int j = nb - 1; j >= 0; j--) {
             const uint32_t pos = bs + (uint32_t)j - rg.x;   // list position in the tile
             const float4 a = s_a[j];
@@ -511,36 +524,54 @@ __device__ __forceinline__ void render_bwd_unit(
                 acc[3] = fmaf(ux, dy, acc[3]);
                 acc[4] = fmaf(uy, dy, acc[4]);
             }
-            if (__any(any)) {   // row sums, the four rows added into LDS
-                const int w = threadIdx.x >> 6;
+            // row sums; the last lane of each 16-lane row stores its row's into
+            // the row's own slot, and the wave notes the splat in its hit mask
+            // (a splat no pixel of the wave took leaves its slots unwritten)
+            if (__any(any)) {
                 float sum[9];
 #pragma unroll
                 for (int f = 0; f < 9; f++) sum[f] = row_sum_lane15(acc[f]);
                 if ((__lane_id() & 15) == 15) {
+                    float *g = s_g + ((threadIdx.x >> 6) * 4 + ((threadIdx.x >> 4) & 3)) * GS + (j & (R - 1));
 #pragma unroll
-                    for (int f = 0; f < 9; f++) atomicAdd(&s_g[w][f][j], sum[f]);
+                    for (int f = 0; f < 9; f++) g[f * R] = sum[f];
                 }
+                hit |= 1ull << (j & (R - 1));
             }
-        }
-        __syncthreads();
-        // one thread per key: the waves' sums, the conic factors applied, stored
-        // at the key's own position (no other workgroup writes it)
-        for (int j = threadIdx.x; j < nb; j += NT) {
-            float S[9];
+            if ((j & (R - 1)) == 0) {
+                // splats j .. j + R - 1 are done: one lane per splat adds the
+                // rows' (and waves') sums, applies the conic factors and stores
+                // them at the key's own position (no other workgroup writes it)
+                if (NW > 1) {
+                    if (__lane_id() == 0) s_hit[threadIdx.x >> 6] = hit;
+                    __syncthreads();
+                }
+                const int t = (int)threadIdx.x, jj = j + t;
+                if (t < R && jj < nb) {
+                    float S[9];
 #pragma unroll
-            for (int f = 0; f < 9; f++) {
-                S[f] = 0.f;
+                    for (int f = 0; f < 9; f++) S[f] = 0.f;
 #pragma unroll
-                for (int w = 0; w < NW; w++) S[f] += s_g[w][f][j];
+                    for (int w = 0; w < NW; w++) {
+                        const uint64_t hw = NW > 1 ? s_hit[w] : hit;
+                        if (!((hw >> t) & 1ull)) continue;
+#pragma unroll
+                        for (int f = 0; f < 9; f++)
+#pragma unroll
+                            for (int r = 0; r < 4; r++) S[f] += s_g[(4 * w + r) * GS + f * R + t];
+                    }
+                    const float A2 = s_a[jj].z, B2 = s_a[jj].w, C2 = s_b[jj].x;
+                    const uint32_t q = s_q[jj];
+                    // dpower/dmean = (A dx + B dy, B dx + C dy) = -ln2 (2 A2 dx + B2 dy, B2 dx + 2 C2 dy);
+                    // dpower/d(A, B, C) = (-dx^2 / 2, -dx dy, -dy^2 / 2)
+                    kp.pa[q] = make_float4(-kLn2 * (2.f * A2 * S[0] + B2 * S[1]),
+                                           -kLn2 * (B2 * S[0] + 2.f * C2 * S[1]), -0.5f * S[2], -S[3]);
+                    kp.pb[q] = make_float4(-0.5f * S[4], S[5], S[6], S[7]);
+                    kp.pc[q] = S[8];
+                }
+                if (NW > 1) __syncthreads();   // the slots are free again
+                hit = 0ull;
             }
-            const float A2 = s_a[j].z, B2 = s_a[j].w, C2 = s_b[j].x;
-            const uint32_t q = s_q[j];
-            // dpower/dmean = (A dx + B dy, B dx + C dy) = -ln2 (2 A2 dx + B2 dy, B2 dx + 2 C2 dy);
-            // dpower/d(A, B, C) = (-dx^2 / 2, -dx dy, -dy^2 / 2)
-            kp.pa[q] = make_float4(-kLn2 * (2.f * A2 * S[0] + B2 * S[1]),
-                                   -kLn2 * (B2 * S[0] + 2.f * C2 * S[1]), -0.5f * S[2], -S[3]);
-            kp.pb[q] = make_float4(-0.5f * S[4], S[5], S[6], S[7]);
-            kp.pc[q] = S[8];
         }
         be = bs;
     }
@@ -569,14 +600,15 @@ __global__ __launch_bounds__(bwd_threads<T>()) void k_render_bwd(
     __shared__ float4 s_c[B];
     __shared__ uint32_t s_q[B];
     __shared__ uint8_t s_m[B];
-    __shared__ float s_g[NT / 64][9][B];
+    __shared__ float s_g[NT / 16 * kGradSlot<MODE>];
+    __shared__ uint64_t s_hit[NT / 64];
     __shared__ float s_h[B];
     __shared__ uint32_t s_nmax;
     const int gt = (int)order[blockIdx.x];
     const uint2 rg = ranges[gt];
     render_bwd_unit<T, B, MODE>(gt, rg.x, rg.y, true, rg, vals, sp, views, nviews, cams, tfinal,
                                 ncontrib, nullptr, nullptr, tstore, bg, dl, kp, s_a, s_b, s_c, s_q,
-                                s_m, s_g, s_h, &s_nmax);
+                                s_m, s_g, s_hit, s_h, &s_nmax);
 }
 
 // Checkpoint mode: one workgroup per (tile, batch) unit id.  Unit u of tile t
@@ -598,7 +630,8 @@ __global__ __launch_bounds__(bwd_threads<T>()) void k_render_bwd_ckpt(
     __shared__ float4 s_c[B];
     __shared__ uint32_t s_q[B];
     __shared__ uint8_t s_m[B];
-    __shared__ float s_g[NT / 64][9][B];
+    __shared__ float s_g[NT / 16 * kGradSlot<1>];
+    __shared__ uint64_t s_hit[NT / 64];
     __shared__ float s_h[B];
     __shared__ uint32_t s_nmax;
     const uint32_t m = m_dev ? *m_dev : m_host;
@@ -618,7 +651,7 @@ __global__ __launch_bounds__(bwd_threads<T>()) void k_render_bwd_ckpt(
         const uint32_t ue = min(rg.y, us + B);
         render_bwd_unit<T, B, 1>(lo, us, ue, u + 1 == units, rg, vals, sp, views, nviews, cams,
                                  tfinal, ncontrib, fstate, ckpt, nullptr, bg, dl, kp, s_a, s_b,
-                                 s_c, s_q, s_m, s_g, s_h, &s_nmax);
+                                 s_c, s_q, s_m, s_g, s_hit, s_h, &s_nmax);
     }
 }
 
