@@ -75,6 +75,11 @@ struct PlaneLr {
 // lies at row offset dyr = sb sqrt(Kp / sa) and its rows within +-ey,
 // ey = sqrt(Kp sc).  Plus the split-form mean (integer pixel ix, iy; offsets
 // hxo, hyo of that pixel's centre from the mean).
+// Number of set bits of a wave mask below the calling lane.
+__device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
 struct Ellipse {
     float slope, kw, ws, dyr, ey;
     float hxo, hyo;

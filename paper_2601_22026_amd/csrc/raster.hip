@@ -130,6 +130,8 @@ __global__ __launch_bounds__(T * T < 256 ? T * T : 256) void k_render_fwd(
     constexpr int ROWS = NT / T;
     constexpr bool QUAD = T == 16;   // wave w composites quadrant w (8 x 8 pixels)
     constexpr int U = 4;   // splats between wave-level completion checks
+    static_assert(U == 4, "a group of splat indices is read as one int4");
+    constexpr int kListLen = 64 + U;   // per wave: one 64-splat chunk, padded
     // PREF (a batch no larger than the workgroup): two LDS buffers; the
     // records of the next batch are copied from global memory straight into
     // the other buffer (global_load_lds, no registers; wave w copies entries
@@ -146,6 +148,7 @@ __global__ __launch_bounds__(T * T < 256 ? T * T : 256) void k_render_fwd(
     // start loses the alias information that lets reads of the other buffer
     // proceed while it is in flight.)
     constexpr int SEC = B + 1;
+    __shared__ __align__(16) int s_list[(NT / 64) * kListLen];
     __shared__ float4 s_buf0_[1 + 4 * SEC];
     __shared__ float4 s_buf1_[PREF ? 1 + 4 * SEC : 1];
     float4 *const s_buf0 = s_buf0_ + 1;
@@ -209,8 +212,15 @@ __global__ __launch_bounds__(T * T < 256 ? T * T : 256) void k_render_fwd(
                 const Ellipse e{e0.x, e0.y, e0.z, e0.w, sqrtf(e0.y / e0.z), a0.x, a0.y, (int)c0.z, (int)c0.w};
                 meet = quad_meets(e, tx * T + (wave & 1) * 8, ty * T + (wave >> 1) * 8);
             }
-            uint64_t m = __ballot(meet);
-            while (m != 0ull) {
+            // the wave's list of them in LDS, padded with the inert slot to whole
+            // groups of U, read back a group at a time (the indices stay in
+            // vector registers: no scalar bookkeeping per splat)
+            const uint64_t m = __ballot(meet);
+            const int cnt = (int)__popcll(m);
+            int *list = s_list + wave * kListLen;
+            if (meet) list[lanes_below(m)] = jl;
+            if (lane < U) list[cnt + lane] = B;
+            for (int g = 0; g < cnt; g += U) {
                 bool all = true;
 #pragma unroll
                 for (int k = 0; k < PPT; k++) all &= !(Tr[k] > 0.f);
@@ -218,13 +228,8 @@ __global__ __launch_bounds__(T * T < 256 ? T * T : 256) void k_render_fwd(
                     done = true;
                     break;
                 }
-                // the next U splats of the wave (the inert slot when m runs out)
-                int jj[U];
-#pragma unroll
-                for (int u = 0; u < U; u++) {
-                    jj[u] = m != 0ull ? cb0 + __builtin_ctzll(m) : B;
-                    m &= m - 1ull;
-                }
+                const int4 j4 = *(const int4 *)(list + g);
+                const int jj[U] = {j4.x, j4.y, j4.z, j4.w};
                 // Phase 1: the U splats' alphas are independent of each other and of
                 // the pixel state; computed without branches (skipped splats get
                 // valid = false; every operand is read whatever the outcome).

@@ -41,10 +41,6 @@ __device__ __forceinline__ uint32_t chunk_size(uint32_t n, int G) {
     return (per + 255u) & ~255u;
 }
 
-__device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
-    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-}
-
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
     const int lane = __lane_id();
 #pragma unroll
