@@ -172,6 +172,14 @@ def test_key_capacity_overflow_is_reported(gs, ctx):
     flags, _ = dev_sized.plan.poll()
     assert flags & _abi.GSF_FLAG_CAPACITY
     assert dev_sized.plan.poll()[0] == 0      # flags are cleared by the poll
+    # nothing was listed, so the adjoint passes no gradient: the per-record sum
+    # writes zeros without reading a key position
+    dl = np.random.default_rng(3).normal(size=(4, cam.npix))
+    g = dev_sized.backward([dl])
+    assert np.isfinite(g).all() and not g.any()
+    R = dev_sized.n
+    g2d = dev_sized.debug(_abi.GSF_DBG_G2D, np.float32, 9 * R)
+    assert not g2d.any()
 
 
 def test_nonfinite_loss_is_flagged(gs, ctx):
