@@ -115,8 +115,19 @@ __device__ __forceinline__ float row_sum_lane15(float x) {
 // tiles with more keys first, so the dispatcher starts the heavy tiles on
 // different CUs at once and fills in with light ones as slots free up, however
 // the keys cluster on screen.
-template <int T, int B, int MODE>
-__global__ __launch_bounds__(T * T < 256 ? T * T : 256) void k_render_fwd(
+// Threads of a forward workgroup: one per pixel (at most 256).  A 16-pixel
+// tile is composited by four waves, one per 8x8 quadrant, each skipping the
+// splats whose padded ellipse misses its quadrant.  SPLIT (16-pixel tiles):
+// the four quadrants are four one-wave workgroups instead (workgroup i takes
+// quadrant i & 3 of tile order[i >> 2]); they run independently, each with
+// no barrier shared with the others, at the cost of staging every batch four
+// times, which pays only where the heaviest tiles, not throughput, set the
+// time (few tiles; the launcher's choice).
+template <int T, bool SPLIT>
+constexpr int fwd_threads() { return SPLIT ? 64 : (T * T < 256 ? T * T : 256); }
+
+template <int T, int B, int MODE, bool SPLIT>
+__global__ __launch_bounds__((fwd_threads<T, SPLIT>())) void k_render_fwd(
     const uint32_t *__restrict__ order,
     const uint2 *__restrict__ ranges, const uint32_t *__restrict__ vals, SplatPtrs sp,
     const ViewDesc *__restrict__ views, int nviews, const gsf_camera *__restrict__ cams,
@@ -125,10 +136,11 @@ __global__ __launch_bounds__(T * T < 256 ? T * T : 256) void k_render_fwd(
     const float *__restrict__ bg, const float *__restrict__ cull_gaze, float cull_radius,
     const float4 *__restrict__ ell) {
     constexpr bool CKPT = MODE == 1;
-    constexpr int NT = T * T < 256 ? T * T : 256;
-    constexpr int PPT = T * T / NT;
+    constexpr bool QUAD = T == 16;   // a wave composites one 8 x 8 quadrant
+    static_assert(!SPLIT || QUAD, "only 16-pixel tiles are split");
+    constexpr int NT = fwd_threads<T, SPLIT>();
+    constexpr int PPT = QUAD ? 1 : T * T / NT;
     constexpr int ROWS = NT / T;
-    constexpr bool QUAD = T == 16;   // wave w composites quadrant w (8 x 8 pixels)
     constexpr int U = 4;   // splats between wave-level completion checks
     static_assert(U == 4, "a group of splat indices is read as one int4");
     constexpr int kListLen = 64 + U;   // per wave: one 64-splat chunk, padded
@@ -154,7 +166,8 @@ __global__ __launch_bounds__(T * T < 256 ? T * T : 256) void k_render_fwd(
     float4 *const s_buf0 = s_buf0_ + 1;
     float4 *const s_buf1 = s_buf1_ + 1;
 
-    const int gt = (int)order[blockIdx.x];
+    const int quad = SPLIT ? (int)(blockIdx.x & 3u) : (int)(threadIdx.x >> 6);
+    const int gt = (int)order[SPLIT ? blockIdx.x >> 2 : blockIdx.x];
     const int v = view_of_tile(views, nviews, gt);
     const ViewDesc vd = views[v];
     const int local = gt - vd.tile_off;
@@ -165,8 +178,8 @@ __global__ __launch_bounds__(T * T < 256 ? T * T : 256) void k_render_fwd(
     }
     const uint2 rg = ranges[gt];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int lx = QUAD ? (wave & 1) * 8 + (lane & 7) : threadIdx.x % T;
-    const int ly = QUAD ? (wave >> 1) * 8 + (lane >> 3) : threadIdx.x / T;
+    const int lx = QUAD ? (quad & 1) * 8 + (lane & 7) : threadIdx.x % T;
+    const int ly = QUAD ? (quad >> 1) * 8 + (lane >> 3) : threadIdx.x / T;
     if (threadIdx.x == 0) {
         s_buf0[B] = make_float4(0.f, 0.f, 0.f, 0.f);
         s_buf0[SEC + B] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -210,7 +223,7 @@ __global__ __launch_bounds__(T * T < 256 ? T * T : 256) void k_render_fwd(
             if (QUAD && meet) {
                 const float4 e0 = SE[jl], a0 = SA[jl], c0 = SC[jl];
                 const Ellipse e{e0.x, e0.y, e0.z, e0.w, sqrtf(e0.y / e0.z), a0.x, a0.y, (int)c0.z, (int)c0.w};
-                meet = quad_meets(e, tx * T + (wave & 1) * 8, ty * T + (wave >> 1) * 8);
+                meet = quad_meets(e, tx * T + (quad & 1) * 8, ty * T + (quad >> 1) * 8);
             }
             // the wave's list of them in LDS, padded with the inert slot to whole
             // groups of U, read back a group at a time (the indices stay in
@@ -993,22 +1006,39 @@ __global__ void k_fill_f32(float *p, int64_t n, float value) {
         p[e] = value;
 }
 
+template <int T, int B, bool SPLIT>
+void render_fwd_tbs(hipStream_t s, const RenderArgs &a, float *out) {
+    constexpr int NT = fwd_threads<T, SPLIT>();
+    const int g = SPLIT ? 4 * a.total_tiles : a.total_tiles;
+    if (a.t_mode == 1)
+        k_render_fwd<T, B, 1, SPLIT><<<g, NT, 0, s>>>(a.order, a.ranges, a.vals, a.sp, a.views,
+                                                     a.nviews, a.cams, out, a.tfinal, a.ncontrib, a.ckpt,
+                                                     a.fstate, nullptr, a.bg, a.cull_gaze, a.cull_radius,
+                                                     a.kp.ell);
+    else if (a.t_mode == 2)
+        k_render_fwd<T, B, 2, SPLIT><<<g, NT, 0, s>>>(a.order, a.ranges, a.vals, a.sp, a.views,
+                                                     a.nviews, a.cams, out, a.tfinal, a.ncontrib, nullptr,
+                                                     nullptr, a.tstore, a.bg, a.cull_gaze, a.cull_radius,
+                                                     a.kp.ell);
+    else
+        k_render_fwd<T, B, 0, SPLIT><<<g, NT, 0, s>>>(a.order, a.ranges, a.vals, a.sp, a.views,
+                                                     a.nviews, a.cams, out, a.tfinal, a.ncontrib, nullptr,
+                                                     nullptr, nullptr, a.bg, a.cull_gaze, a.cull_radius,
+                                                     a.kp.ell);
+}
+
+// Split 16-pixel tiles into one workgroup per quadrant when the plan has at
+// most kSplitTilesPerCu tiles per compute unit: measured on one 1024^2 view
+// (4096 tiles) it shortens the forward by 4%, on 8 to 16 views of 0.5-4 Mpix
+// (36k-230k tiles) the fourfold staging lengthens it by 40-55%.
+constexpr int kSplitTilesPerCu = 16;
+
 template <int T, int B>
 void render_fwd_tb(hipStream_t s, const RenderArgs &a, float *out) {
-    constexpr int NT = T * T < 256 ? T * T : 256;
-    const int g = a.total_tiles;
-    if (a.t_mode == 1)
-        k_render_fwd<T, B, 1><<<g, NT, 0, s>>>(a.order, a.ranges, a.vals, a.sp, a.views,
-                                              a.nviews, a.cams, out, a.tfinal, a.ncontrib, a.ckpt,
-                                              a.fstate, nullptr, a.bg, a.cull_gaze, a.cull_radius, a.kp.ell);
-    else if (a.t_mode == 2)
-        k_render_fwd<T, B, 2><<<g, NT, 0, s>>>(a.order, a.ranges, a.vals, a.sp, a.views,
-                                              a.nviews, a.cams, out, a.tfinal, a.ncontrib, nullptr,
-                                              nullptr, a.tstore, a.bg, a.cull_gaze, a.cull_radius, a.kp.ell);
+    if (T == 16 && (int64_t)a.total_tiles <= (int64_t)kSplitTilesPerCu * a.cus)
+        render_fwd_tbs<T, B, T == 16>(s, a, out);
     else
-        k_render_fwd<T, B, 0><<<g, NT, 0, s>>>(a.order, a.ranges, a.vals, a.sp, a.views,
-                                              a.nviews, a.cams, out, a.tfinal, a.ncontrib, nullptr,
-                                              nullptr, nullptr, a.bg, a.cull_gaze, a.cull_radius, a.kp.ell);
+        render_fwd_tbs<T, B, false>(s, a, out);
 }
 
 template <int T, int B>
