@@ -882,16 +882,24 @@ __global__ __launch_bounds__(kLossBlock) void k_loss_count(const float *__restri
                                                            float radius_frac,
                                                            const ViewDesc *__restrict__ views,
                                                            int nviews, int64_t total_pix, int box,
-                                                           int tile, uint32_t channels,
+                                                           int tile, uint32_t channels, int64_t npix,
                                                            uint32_t *__restrict__ mask_count) {
     __shared__ uint32_t s_cnt;
     if (threadIdx.x == 0) s_cnt = 0u;
     __syncthreads();
-    const int64_t p = (int64_t)blockIdx.x * kLossBlock + threadIdx.x;
-    int v, x, y;
-    if (loss_pixel(p, total_pix, box, tile, gaze, radius_frac, views, nviews, v, x, y)) {
-        const ViewDesc vd = views[v];
-        if (in_fovea(gaze, v, x, y, radius_frac * (float)vd.width)) atomicAdd(&s_cnt, channels);
+    // grid-stride over the launch's pixels: one LDS atomic per wave and step,
+    // one global atomic per workgroup (atomics on one address serialise, so
+    // their number is kept to the grid's)
+    for (int64_t p0 = (int64_t)blockIdx.x * kLossBlock; p0 < npix; p0 += (int64_t)gridDim.x * kLossBlock) {
+        const int64_t p = p0 + threadIdx.x;
+        int v, x, y;
+        bool in = false;
+        if (p < npix && loss_pixel(p, total_pix, box, tile, gaze, radius_frac, views, nviews, v, x, y)) {
+            const ViewDesc vd = views[v];
+            in = in_fovea(gaze, v, x, y, radius_frac * (float)vd.width);
+        }
+        const uint32_t n = (uint32_t)__popcll(__ballot(in));
+        if (__lane_id() == 0 && n) atomicAdd(&s_cnt, n * channels);
     }
     __syncthreads();
     if (threadIdx.x == 0 && s_cnt) atomicAdd(mask_count, s_cnt);
@@ -1116,8 +1124,10 @@ void launch_loss_l1(hipStream_t s, const float *rgba, const float *target, const
     const int nb = loss_partials(box ? (int64_t)nviews * box * box : total_pix);
     if (gaze) {
         k_fill_u32<<<1, 64, 0, s>>>(mask_count, 1, 0u);
-        k_loss_count<<<nb, kLossBlock, 0, s>>>(gaze, radius_frac, views, nviews, total_pix, box, tile,
-                                               channels, mask_count);
+        const int64_t npix = box ? (int64_t)nviews * box * box : total_pix;
+        k_loss_count<<<std::min(nb, 1024), kLossBlock, 0, s>>>(gaze, radius_frac, views, nviews,
+                                                               total_pix, box, tile, channels, npix,
+                                                               mask_count);
     }
     const uint32_t *mc = gaze ? mask_count : nullptr;
     const uint32_t cnt = (uint32_t)(channels * total_pix);
