@@ -118,11 +118,14 @@ __device__ __forceinline__ float row_sum_lane15(float x) {
 // Threads of a forward workgroup: one per pixel (at most 256).  A 16-pixel
 // tile is composited by four waves, one per 8x8 quadrant, each skipping the
 // splats whose padded ellipse misses its quadrant.  SPLIT (16-pixel tiles):
-// the four quadrants are four one-wave workgroups instead (workgroup i takes
-// quadrant i & 3 of tile order[i >> 2]); they run independently, each with
-// no barrier shared with the others, at the cost of staging every batch four
-// times, which pays only where the heaviest tiles, not throughput, set the
-// time (few tiles; the launcher's choice).
+// the four quadrants are four one-wave workgroups instead; they run
+// independently, each with no barrier shared with the others, at the cost of
+// staging every batch four times, which pays only where the heaviest tiles,
+// not throughput, set the time (few tiles; the launcher's choice).
+// Workgroups are dealt to the 8 XCDs round robin (workgroup g to XCD g mod
+// 8), so workgroup g takes quadrant (g >> 3) & 3 of the tile at position
+// 8 (g >> 5) + (g & 7) of the order: the four quadrants of a tile share an
+// XCD and its L2, and the order's heaviest tiles still come first.
 template <int T, bool SPLIT>
 constexpr int fwd_threads() { return SPLIT ? 64 : (T * T < 256 ? T * T : 256); }
 
@@ -134,7 +137,7 @@ __global__ __launch_bounds__((fwd_threads<T, SPLIT>())) void k_render_fwd(
     float *__restrict__ out_rgba, float *__restrict__ tfinal, uint32_t *__restrict__ ncontrib,
     float4 *__restrict__ ckpt, float4 *__restrict__ fstate, float *__restrict__ tstore,
     const float *__restrict__ bg, const float *__restrict__ cull_gaze, float cull_radius,
-    const float4 *__restrict__ ell) {
+    const float4 *__restrict__ ell, int total_tiles) {
     constexpr bool CKPT = MODE == 1;
     constexpr bool QUAD = T == 16;   // a wave composites one 8 x 8 quadrant
     static_assert(!SPLIT || QUAD, "only 16-pixel tiles are split");
@@ -166,8 +169,10 @@ __global__ __launch_bounds__((fwd_threads<T, SPLIT>())) void k_render_fwd(
     float4 *const s_buf0 = s_buf0_ + 1;
     float4 *const s_buf1 = s_buf1_ + 1;
 
-    const int quad = SPLIT ? (int)(blockIdx.x & 3u) : (int)(threadIdx.x >> 6);
-    const int gt = (int)order[SPLIT ? blockIdx.x >> 2 : blockIdx.x];
+    const int quad = SPLIT ? (int)((blockIdx.x >> 3) & 3u) : (int)(threadIdx.x >> 6);
+    const uint32_t oi = SPLIT ? (blockIdx.x >> 5) * 8u + (blockIdx.x & 7u) : blockIdx.x;
+    if (oi >= (uint32_t)total_tiles) return;   // the split grid is padded to whole groups of 8 tiles
+    const int gt = (int)order[oi];
     const int v = view_of_tile(views, nviews, gt);
     const ViewDesc vd = views[v];
     const int local = gt - vd.tile_off;
@@ -1017,28 +1022,29 @@ __global__ void k_fill_f32(float *p, int64_t n, float value) {
 template <int T, int B, bool SPLIT>
 void render_fwd_tbs(hipStream_t s, const RenderArgs &a, float *out) {
     constexpr int NT = fwd_threads<T, SPLIT>();
-    const int g = SPLIT ? 4 * a.total_tiles : a.total_tiles;
+    const int g = SPLIT ? 4 * ((a.total_tiles + 7) / 8 * 8) : a.total_tiles;
     if (a.t_mode == 1)
         k_render_fwd<T, B, 1, SPLIT><<<g, NT, 0, s>>>(a.order, a.ranges, a.vals, a.sp, a.views,
                                                      a.nviews, a.cams, out, a.tfinal, a.ncontrib, a.ckpt,
                                                      a.fstate, nullptr, a.bg, a.cull_gaze, a.cull_radius,
-                                                     a.kp.ell);
+                                                     a.kp.ell, a.total_tiles);
     else if (a.t_mode == 2)
         k_render_fwd<T, B, 2, SPLIT><<<g, NT, 0, s>>>(a.order, a.ranges, a.vals, a.sp, a.views,
                                                      a.nviews, a.cams, out, a.tfinal, a.ncontrib, nullptr,
                                                      nullptr, a.tstore, a.bg, a.cull_gaze, a.cull_radius,
-                                                     a.kp.ell);
+                                                     a.kp.ell, a.total_tiles);
     else
         k_render_fwd<T, B, 0, SPLIT><<<g, NT, 0, s>>>(a.order, a.ranges, a.vals, a.sp, a.views,
                                                      a.nviews, a.cams, out, a.tfinal, a.ncontrib, nullptr,
                                                      nullptr, nullptr, a.bg, a.cull_gaze, a.cull_radius,
-                                                     a.kp.ell);
+                                                     a.kp.ell, a.total_tiles);
 }
 
 // Split 16-pixel tiles into one workgroup per quadrant when the plan has at
 // most kSplitTilesPerCu tiles per compute unit: measured on one 1024^2 view
-// (4096 tiles) it shortens the forward by 4%, on 8 to 16 views of 0.5-4 Mpix
-// (36k-230k tiles) the fourfold staging lengthens it by 40-55%.
+// (4096 tiles) it shortens the forward by 5%, on 16 views of 1920^2 (230k
+// tiles) it lengthens it by 2.5% and on 8 views of 0.25-4 Mpix (63k tiles)
+// by 18%.
 constexpr int kSplitTilesPerCu = 16;
 
 template <int T, int B>
