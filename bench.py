@@ -193,7 +193,9 @@ def hbm_bytes_per_launch(stage, N, R, M, npix, planes, tiles):
         "render": 40 * M + 24 * npix,                         # splat gather per key; RGBA, T, count out
         "loss": 40 * npix,                                    # RGBA, target in; dL/dRGBA out
         "render_bwd": 76 * M + 24 * npix,                     # splat gather; pixel state in; per-key gradient out
-        "project_bwd": planes * 4 * N + 36 * R + planes * 4 * N,
+        # params in, grads out; SH 0-1: the per-key gradients (with count and offset) summed
+        # inside, SH 2-3: g2d, which grad_sum wrote
+        "project_bwd": planes * 8 * N + (36 * M + 8 * R if planes <= 23 else 36 * R),
         "adam": 28 * planes * N,
         "grad_sum": 36 * M + 44 * R,                          # per-key gradient, count, offset in; g2d out
     }.get(stage)

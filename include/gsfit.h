@@ -388,7 +388,7 @@ gsf_status gsf_raymarch(gsf_ctx *ctx, const uint16_t *vol, int32_t n, const gsf_
 /* Per-stage GPU timing of eager calls on a plan (hipEvents recorded around each
  * stage on the context stream; not available while capturing).  Enabling
  * resets the accumulators.  Stages holding exactly one kernel: PROJECT,
- * DEPTH_SORT, RENDER, RENDER_BWD, PROJECT_BWD, GRAD_SUM. */
+ * DEPTH_SORT, RENDER, RENDER_BWD, PROJECT_BWD. */
 enum {
     GSF_STAGE_PROJECT = 0,     /* projection + support boxes (one kernel) */
     GSF_STAGE_DUPLICATE = 1,   /* scan of the per-record tile counts + key emission */
@@ -400,7 +400,9 @@ enum {
     GSF_STAGE_RENDER_BWD = 7,  /* compositing adjoint (one kernel) */
     GSF_STAGE_PROJECT_BWD = 8, /* projection adjoint (one kernel) */
     GSF_STAGE_ADAM = 9,        /* step counter + Adam (inside gsf_step only) */
-    GSF_STAGE_GRAD_SUM = 10,   /* per-record sum of the per-key screen-space gradients (one kernel) */
+    GSF_STAGE_GRAD_SUM = 10,   /* per-record sum of the per-key screen-space gradients (one
+                                  kernel; SH degrees 2-3 only: for 0-1 it runs inside
+                                  PROJECT_BWD) */
     GSF_STAGE_COUNT = 11
 };
 gsf_status gsf_plan_set_timing(gsf_plan *plan, int enable);
@@ -427,7 +429,8 @@ enum {
     GSF_DBG_RANGES = 5,    /* uint32[2] per global tile: [start, end) */
     GSF_DBG_TFINAL = 6,    /* float per pixel (all views concatenated) */
     GSF_DBG_NCONTRIB = 7,  /* uint32 per pixel: list entries up to the last included */
-    GSF_DBG_G2D = 8,       /* float [9][n_views * n]: per-record screen-space gradient */
+    GSF_DBG_G2D = 8,       /* float [9][n_views * n]: per-record screen-space gradient of the
+                              last gsf_backward (summed from its per-key terms on request) */
     GSF_DBG_PROJ = 9,      /* float [11] per record: mean x, mean y, conic A, B, C, opacity,
                               red, green, blue, camera depth, valid (1 or 0) */
     GSF_DBG_ORDER = 10,    /* uint32 per global tile: compositing order of the tiles (a

@@ -379,14 +379,14 @@ gsf_status enqueue_backward(gsf_plan *p, const float *params, int64_t n, const g
         launch_render_bwd(s, ra, dl);
     }
     GSF_LAUNCHED(p->ctx);
-    {   // their per-record sums (every entry of g2d written)
+    if (!project_bwd_sums_keys(p->deg)) {   // their per-record sums (every entry of g2d written)
         StageTimer t(p, GSF_STAGE_GRAD_SUM);
         launch_grad_sum(s, ra.kp, (int)(n * p->V), p->b.g2d);
     }
     GSF_LAUNCHED(p->ctx);
-    {
+    {   // the chain rule to the parameters (summing the per-key terms itself for SH 0-1)
         StageTimer t(p, GSF_STAGE_PROJECT_BWD);
-        launch_project_bwd(s, params, (int)n, p->V, p->deg, cams, p->b.g2d, grads);
+        launch_project_bwd(s, params, (int)n, p->V, p->deg, cams, ra.kp, p->b.g2d, grads);
     }
     GSF_LAUNCHED(p->ctx);
     return GSF_OK;
@@ -985,7 +985,15 @@ gsf_status gsf_debug_copy(gsf_plan *p, int which, void *host_dst, size_t cap, si
     case GSF_DBG_VIS: src = p->b.vis; bytes = (size_t)p->fwd_n; break;
     case GSF_DBG_TFINAL: src = p->b.tfinal; bytes = (size_t)p->total_pix * 4; break;
     case GSF_DBG_NCONTRIB: src = p->b.ncontrib; bytes = (size_t)p->total_pix * 4; break;
-    case GSF_DBG_G2D: src = p->b.g2d; bytes = 9 * R * 4; break;
+    case GSF_DBG_G2D: {   // the per-record sums of the last adjoint's per-key gradients
+        RenderArgs ra = render_args(p, nullptr, p->fwd_n);
+        launch_grad_sum(p->ctx->stream, ra.kp, (int)R, p->b.g2d);
+        GSF_LAUNCHED(p->ctx);
+        GSF_HIP(p->ctx, hipStreamSynchronize(p->ctx->stream));
+        src = p->b.g2d;
+        bytes = 9 * R * 4;
+        break;
+    }
     case GSF_DBG_PROJ: {
         std::vector<float4> a(R), b(R);
         std::vector<float4> c(R);

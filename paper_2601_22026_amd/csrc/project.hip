@@ -351,17 +351,19 @@ __device__ __forceinline__ void quat_vjp(const float *q, const float *dR, float 
                    y * dR[5] + x * dR[6] + y * dR[7]);
 }
 
-template <int DEG>
+// FUSED: the per-record screen-space gradient is summed here from the
+// compositing adjoint's per-key terms (wave_key_sum); otherwise it is read
+// from g2d [9][V*n], which a separate pass wrote.
+template <int DEG, bool FUSED>
 __global__ __launch_bounds__(128) void k_project_bwd(const float *__restrict__ P, int n, int nviews,
-                                                     const gsf_camera *__restrict__ cams,
+                                                     const gsf_camera *__restrict__ cams, KeyPlace kp,
                                                      const float *__restrict__ g2d,
                                                      float *__restrict__ grads) {
     constexpr int K = (DEG + 1) * (DEG + 1);
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const size_t nrec = (size_t)nviews * n;
+    const bool valid = i < n;   // every lane takes part in the per-view key sums
     Gauss g;
-    load_gauss(P, n, i, g);
+    load_gauss(P, n, valid ? i : 0, g);
     float dmu[3] = {0.f, 0.f, 0.f};
     float dS[9];
 #pragma unroll
@@ -372,15 +374,20 @@ __global__ __launch_bounds__(128) void k_project_bwd(const float *__restrict__ P
     for (int k = 0; k < K; k++) dsh[k][0] = dsh[k][1] = dsh[k][2] = 0.f;
 
     for (int v = 0; v < nviews; v++) {
-        const size_t r = (size_t)v * n + i;
+        // this view's screen-space gradient: the sum of the record's per-key terms
         float gg[9];
+        const uint32_t r = (uint32_t)v * (uint32_t)n + (uint32_t)i;
+        if (FUSED) {
+            wave_key_sum(kp, r, valid, gg);
+        } else {
+            const size_t nrec = (size_t)nviews * n;
+#pragma unroll
+            for (int f = 0; f < 9; f++) gg[f] = valid ? g2d[f * nrec + r] : 0.f;
+        }
         bool any = false;
 #pragma unroll
-        for (int f = 0; f < 9; f++) {
-            gg[f] = g2d[f * nrec + r];
-            any |= gg[f] != 0.f;
-        }
-        if (!any) continue;
+        for (int f = 0; f < 9; f++) any |= gg[f] != 0.f;
+        if (!valid || !any) continue;
         const gsf_camera &cam = cams[v];
         Proj p;
         if (!project(g, cam, p)) continue;
@@ -486,6 +493,7 @@ __global__ __launch_bounds__(128) void k_project_bwd(const float *__restrict__ P
             ds[cc] += dm3 * g.R[3 * rr + cc];
             dR[3 * rr + cc] = dm3 * g.s[cc];
         }
+    if (!valid) return;
     float dqn[4];
     quat_vjp(g.qn, dR, dqn);
     const float qdot = dqn[0] * g.qn[0] + dqn[1] * g.qn[1] + dqn[2] * g.qn[2] + dqn[3] * g.qn[3];
@@ -519,14 +527,16 @@ void launch_project_fwd(hipStream_t s, const float *P, int n, int nviews, int de
     }
 }
 
+bool project_bwd_sums_keys(int deg) { return deg <= 1; }
+
 void launch_project_bwd(hipStream_t s, const float *P, int n, int nviews, int deg,
-                        const gsf_camera *cams, const float *g2d, float *grads) {
+                        const gsf_camera *cams, const KeyPlace &kp, const float *g2d, float *grads) {
     const dim3 grid((n + 127) / 128), block(128);
     switch (deg) {
-    case 0: k_project_bwd<0><<<grid, block, 0, s>>>(P, n, nviews, cams, g2d, grads); break;
-    case 1: k_project_bwd<1><<<grid, block, 0, s>>>(P, n, nviews, cams, g2d, grads); break;
-    case 2: k_project_bwd<2><<<grid, block, 0, s>>>(P, n, nviews, cams, g2d, grads); break;
-    default: k_project_bwd<3><<<grid, block, 0, s>>>(P, n, nviews, cams, g2d, grads); break;
+    case 0: k_project_bwd<0, true><<<grid, block, 0, s>>>(P, n, nviews, cams, kp, g2d, grads); break;
+    case 1: k_project_bwd<1, true><<<grid, block, 0, s>>>(P, n, nviews, cams, kp, g2d, grads); break;
+    case 2: k_project_bwd<2, false><<<grid, block, 0, s>>>(P, n, nviews, cams, kp, g2d, grads); break;
+    default: k_project_bwd<3, false><<<grid, block, 0, s>>>(P, n, nviews, cams, kp, g2d, grads); break;
     }
 }
 

@@ -91,11 +91,6 @@ __device__ __forceinline__ int view_of_tile(const ViewDesc *__restrict__ views, 
 // (DPP row_shr 1, 2, 4, 8) leave each 16-lane row's total in its lane 15, then
 // row_bcast:15 and row_bcast:31 fold the rows together.  All steps are VALU
 // instructions with DPP operands (no LDS traffic).
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ float dpp_shift(float x) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL,
-                                                                 ROW_MASK, 0xf, true));
-}
 
 // Sum over each 16-lane row, left in the row's last lane (15, 31, 47, 63).
 __device__ __forceinline__ float row_sum_lane15(float x) {
@@ -678,108 +673,14 @@ __global__ __launch_bounds__(bwd_threads<T>()) void k_render_bwd_ckpt(
     }
 }
 
-// Per-record sum of the per-key screen-space gradients into g2d [9][nrec]:
-// record r's keys sit at koff[r] .. koff[r] + count[r] - 1, so a wave's 64
-// records own one run of consecutive keys.  The wave reads that run 64 keys a
-// step (coalesced), sums each record's part of the step with a segmented scan
-// across the lanes, and the record's lane takes its part from the part's last
-// lane.  After a key overflow nothing was listed and g2d is written as zeros.
-
-// OR over the wave's lanes (DPP row prefix, then the rows folded together).
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ uint32_t dpp_shift_u(uint32_t x) {
-    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROW_MASK, 0xf, true);
-}
-__device__ __forceinline__ uint32_t wave_or(uint32_t x) {
-    x |= dpp_shift_u<0x111, 0xf>(x);   // row_shr:1
-    x |= dpp_shift_u<0x112, 0xf>(x);   // row_shr:2
-    x |= dpp_shift_u<0x114, 0xf>(x);   // row_shr:4
-    x |= dpp_shift_u<0x118, 0xf>(x);   // row_shr:8
-    x |= dpp_shift_u<0x142, 0xa>(x);   // row_bcast:15 into rows 1 and 3
-    x |= dpp_shift_u<0x143, 0xc>(x);   // row_bcast:31 into rows 2 and 3
-    return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
-}
-
-// True when bits a..l (0 <= a <= l <= 63) of the mask are all clear.
-__device__ __forceinline__ bool bits_clear(uint64_t m, int a, int l) {
-    return ((m << (63 - l)) >> (63 - l + a)) == 0ull;
-}
-
-// One step of the segmented inclusive scan: add the value the DPP control
-// brings (zero where it brings none) unless a segment starts between.
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ void seg_step(float (&v)[9], bool join) {
-#pragma unroll
-    for (int f = 0; f < 9; f++) {
-        const float t = dpp_shift<CTRL, ROW_MASK>(v[f]);
-        v[f] = join ? v[f] + t : v[f];
-    }
-}
-
-// One wave per workgroup, so that small record counts still spread over every CU.
+// Per-record sum of the per-key screen-space gradients into g2d [9][nrec]
+// (wave_key_sum; one wave per workgroup, so that small record counts still
+// spread over every CU).  The fit step sums inside the projection adjoint
+// instead; this pass serves the debug readout of g2d.
 __global__ __launch_bounds__(64) void k_grad_sum(KeyPlace kp, int nrec, float *__restrict__ g2d) {
     const int r = blockIdx.x * 64 + threadIdx.x;
-    const int lane = __lane_id();
-    const bool over = *kp.m_total > (unsigned long long)kp.capacity;
-    uint32_t cnt = 0u, base = 0u;
-    if (r < nrec && !over) {
-        cnt = kp.count[r];
-        if (cnt != 0u) base = kp.koff[r];
-    }
-    // wave-local key range [beg, end) of each lane's record
-    uint32_t end = cnt;
-#pragma unroll
-    for (int m = 1; m < 64; m <<= 1) {
-        const uint32_t t = __shfl_up(end, m, 64);
-        if (lane >= m) end += t;
-    }
-    const uint32_t beg = end - cnt;
-    const uint32_t K = __shfl(end, 63, 64);
-    const uint64_t nz = __ballot(cnt != 0u);
-    const uint32_t start = nz ? __shfl(base, __builtin_ctzll(nz), 64) : 0u;   // the run's first key
     float S[9];
-#pragma unroll
-    for (int f = 0; f < 9; f++) S[f] = 0.f;
-    // the next step's keys are loaded while this step is scanned
-    float4 na = make_float4(0.f, 0.f, 0.f, 0.f), nb = na;
-    float nc = 0.f;
-    if ((uint32_t)lane < K) {
-        na = kp.pa[start + lane];
-        nb = kp.pb[start + lane];
-        nc = kp.pc[start + lane];
-    }
-    for (uint32_t c0 = 0; c0 < K; c0 += 64u) {   // wave-uniform
-        float v[9] = {na.x, na.y, na.z, na.w, nb.x, nb.y, nb.z, nb.w, nc};
-        const uint32_t pn = c0 + 64u + (uint32_t)lane;
-        if (pn < K) {
-            na = kp.pa[start + pn];
-            nb = kp.pb[start + pn];
-            nc = kp.pc[start + pn];
-        } else {
-            na = nb = make_float4(0.f, 0.f, 0.f, 0.f);
-            nc = 0.f;
-        }
-        // segment starts in this step: lane 0 and each record's first key
-        const bool starts = cnt != 0u && beg >= c0 && beg < c0 + 64u;
-        const uint32_t bit = starts ? beg - c0 : 64u;
-        const uint64_t heads = 1ull | ((uint64_t)wave_or(bit < 32u ? 1u << bit : 0u)) |
-                               ((uint64_t)wave_or(bit >= 32u && bit < 64u ? 1u << (bit - 32u) : 0u) << 32);
-        // within rows of 16 lanes, then rows 0 -> 1 and 2 -> 3, then rows 0-1 -> 2-3
-        seg_step<0x111, 0xf>(v, lane >= 1 && bits_clear(heads, lane, lane));
-        seg_step<0x112, 0xf>(v, lane >= 2 && bits_clear(heads, lane - 1, lane));
-        seg_step<0x114, 0xf>(v, lane >= 4 && bits_clear(heads, lane - 3, lane));
-        seg_step<0x118, 0xf>(v, lane >= 8 && bits_clear(heads, lane - 7, lane));
-        seg_step<0x142, 0xa>(v, lane >= 16 && bits_clear(heads, lane & ~15, lane));
-        seg_step<0x143, 0xc>(v, lane >= 32 && bits_clear(heads, 32, lane));
-        // each record adds its part of the step, held by the part's last lane
-        const bool mine = cnt != 0u && beg < c0 + 64u && end > c0;
-        const int src = mine ? (int)(min(end, c0 + 64u) - 1u - c0) : lane;
-#pragma unroll
-        for (int f = 0; f < 9; f++) {
-            const float t = __shfl(v[f], src, 64);
-            S[f] = mine ? S[f] + t : S[f];
-        }
-    }
+    wave_key_sum(kp, (uint32_t)r, r < nrec, S);
     if (r < nrec) {
 #pragma unroll
         for (int f = 0; f < 9; f++) g2d[(size_t)f * nrec + r] = S[f];
