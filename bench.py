@@ -445,8 +445,9 @@ def main():
                           "copy_bytes_written_per_launch": x.numel() * 4, "launches": 5}))
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
-              "sharding of this path is described in DESIGN.md but not built.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the multi-GPU "
+              "sharding of this path (views split across GPUs, gradients all-reduced) is not "
+              "built.", file=sys.stderr)
         sys.exit(2)
 
     if args.workload == "reproject":
