@@ -302,17 +302,19 @@ __global__ __launch_bounds__((fwd_threads<T, SPLIT>())) void k_render_fwd(
                     // they are bit for bit.
 #pragma unroll
                     for (int u = 0; u < U; u++) {
+                        // A stopped pixel holds -T < 0, so its Tn < 0 < kTStop: it is
+                        // never included, and -|T| keeps it stopped.  A running pixel
+                        // stops where Tn < kTStop and then holds -T.
                         const float Tn = Tr[k] * (1.f - alpha[u]);
-                        const bool take = valid[u] && Tr[k] > 0.f;
-                        const bool stop = take && Tn < kTStop;
-                        const bool inc = take && !stop;
+                        const bool inc = valid[u] && !(Tn < kTStop);
+                        const bool stop = valid[u] && !inc;
                         if (MODE == 2 && inc)
                             tstore[(size_t)(bs + (uint32_t)jj[u]) * (T * T) + pix[k]] = Tr[k];
                         const float w = (inc ? alpha[u] : 0.f) * Tr[k];
                         cr[k] = fmaf(b[u].z, w, cr[k]);
                         cg[k] = fmaf(b[u].w, w, cg[k]);
                         cb[k] = fmaf(c[u].x, w, cb[k]);
-                        Tr[k] = inc ? Tn : (stop ? -Tr[k] : Tr[k]);
+                        Tr[k] = inc ? Tn : (stop ? -fabsf(Tr[k]) : Tr[k]);
                         last[k] = inc ? bs + (uint32_t)jj[u] - rg.x + 1u : last[k];
                     }
                 }
