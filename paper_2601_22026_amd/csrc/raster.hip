@@ -241,6 +241,10 @@ __global__ __launch_bounds__((fwd_threads<T, SPLIT>())) void k_render_fwd(
     auto composite = [&](uint32_t bs, const float4 *buf) -> bool {
         const float4 *SA = buf, *SB = buf + SEC, *SC = buf + 2 * SEC, *SE = buf + 3 * SEC;
         const int nb = (int)min((uint32_t)B, rg.y - bs);
+        // list entries are the splat's 1-based place in the tile's list (what
+        // last[] records); slot j of the batch is entry j + off
+        const int off = (int)(bs - rg.x) + 1;
+        const float4 *SAo = SA - off, *SBo = SB - off, *SCo = SC - off;
         bool done = false;
         // the batch 64 splats at a time: the wave's splats are the set bits of
         // m (with 16-pixel tiles, those whose padded ellipse reaches the wave's
@@ -259,8 +263,8 @@ __global__ __launch_bounds__((fwd_threads<T, SPLIT>())) void k_render_fwd(
             const uint64_t m = __ballot(meet);
             const int cnt = (int)__popcll(m);
             int *list = s_list + wave * kListLen;
-            if (meet) list[lanes_below(m)] = jl;
-            if (lane < U) list[cnt + lane] = B;
+            if (meet) list[lanes_below(m)] = jl + off;
+            if (lane < U) list[cnt + lane] = B + off;
             for (int g = 0; g < cnt; g += U) {
                 bool all = true;
 #pragma unroll
@@ -278,9 +282,9 @@ __global__ __launch_bounds__((fwd_threads<T, SPLIT>())) void k_render_fwd(
                 float4 c[U];
 #pragma unroll
                 for (int u = 0; u < U; u++) {
-                    a[u] = SA[jj[u]];
-                    b[u] = SB[jj[u]];
-                    c[u] = SC[jj[u]];
+                    a[u] = SAo[jj[u]];
+                    b[u] = SBo[jj[u]];
+                    c[u] = SCo[jj[u]];
                 }
 #pragma unroll
                 for (int k = 0; k < PPT; k++) {
@@ -309,13 +313,13 @@ __global__ __launch_bounds__((fwd_threads<T, SPLIT>())) void k_render_fwd(
                         const bool inc = valid[u] && !(Tn < kTStop);
                         const bool stop = valid[u] && !inc;
                         if (MODE == 2 && inc)
-                            tstore[(size_t)(bs + (uint32_t)jj[u]) * (T * T) + pix[k]] = Tr[k];
+                            tstore[(size_t)(rg.x - 1u + (uint32_t)jj[u]) * (T * T) + pix[k]] = Tr[k];
                         const float w = (inc ? alpha[u] : 0.f) * Tr[k];
                         cr[k] = fmaf(b[u].z, w, cr[k]);
                         cg[k] = fmaf(b[u].w, w, cg[k]);
                         cb[k] = fmaf(c[u].x, w, cb[k]);
                         Tr[k] = inc ? Tn : (stop ? -fabsf(Tr[k]) : Tr[k]);
-                        last[k] = inc ? bs + (uint32_t)jj[u] - rg.x + 1u : last[k];
+                        last[k] = inc ? (uint32_t)jj[u] : last[k];
                     }
                 }
             }

@@ -633,13 +633,41 @@ __global__ __launch_bounds__(kTileSortBlock) void k_tile_sort(
     uint32_t *__restrict__ vals, uint32_t *__restrict__ gk0, uint32_t *__restrict__ gk1,
     uint32_t *__restrict__ gv1) {
     __shared__ SortShared sh;
-    __shared__ uint32_t s_k0[kTileSortLds], s_v0[kTileSortLds], s_k1[kTileSortLds], s_v1[kTileSortLds];
+    __shared__ __align__(16) uint32_t s_k0[kTileSortLds];
+    __shared__ uint32_t s_v0[kTileSortLds], s_k1[kTileSortLds], s_v1[kTileSortLds];
     const uint2 rg = ranges[order[blockIdx.x]];   // tiles with the longest lists first
     const int n = (int)(rg.y - rg.x);
     if (n <= 1) return;
     uint32_t *lv = vals + rg.x;
     bool second;
-    if (n <= kTileSortLds) {
+    if (n <= kTileSortBlock) {
+        // Short list: entry i goes to the number of entries that precede it in
+        // (depth, list position) order, the order the stable passes produce.
+        // The depths are padded to a multiple of 4 with a key above every depth
+        // (depth bits of finite or infinite floats are below 0x7F800001).
+        const int i = threadIdx.x;
+        uint32_t r = 0u, k = 0u;
+        if (i < n) {
+            r = lv[i];
+            k = depth_key[r];
+            s_k0[i] = k;
+        } else if (i < ((n + 3) & ~3)) {
+            s_k0[i] = 0xFFFFFFFFu;
+        }
+        __syncthreads();
+        if (i < n) {
+            const uint4 *q = reinterpret_cast<const uint4 *>(s_k0);
+            uint32_t rank = 0u;
+            for (int j = 0; j < n; j += 4) {   // entries j..j+3 count when below k, or equal and earlier
+                const uint4 kj = q[j >> 2];
+                rank += (kj.x < k + (uint32_t)(j < i)) ? 1u : 0u;
+                rank += (kj.y < k + (uint32_t)(j + 1 < i)) ? 1u : 0u;
+                rank += (kj.z < k + (uint32_t)(j + 2 < i)) ? 1u : 0u;
+                rank += (kj.w < k + (uint32_t)(j + 3 < i)) ? 1u : 0u;
+            }
+            lv[rank] = r;
+        }
+    } else if (n <= kTileSortLds) {
         for (int i = threadIdx.x; i < n; i += kTileSortBlock) {
             const uint32_t r = lv[i];
             s_v0[i] = r;
