@@ -15,10 +15,11 @@
 //      scatter that ranks each wave's 64 keys with 8 ballots (peer masks) and
 //      combines the waves in order (stable);
 //   3. tile ranges from the boundaries of the sorted keys;
-//   4. one workgroup per tile sorts its list by the float32 depth bits with the
-//      same stable LDS ranking (4 passes, skipped when a digit is uniform); the
-//      list is in record order on entry, so equal depths stay in record order.
-//      Lists longer than the LDS capacity run the passes on global scratch.
+//   4. one workgroup per tile sorts its list by the float32 depth bits, equal
+//      depths keeping the record order the list has on entry: lists of at most
+//      256 keys are ranked (each entry counts the entries before it), longer
+//      ones run the same stable LDS ranking as the tile sort (4 passes, skipped
+//      when a digit is uniform), on global scratch beyond the LDS capacity.
 // Depth bits of positive floats order like the floats, so the result is the
 // (tile, depth, record) order.
 #include "gs_internal.h"
@@ -627,6 +628,21 @@ __device__ __forceinline__ void sort_list(uint32_t *k0, uint32_t *v0, uint32_t *
     in_second = second;
 }
 
+// Keys of s[j0, j1) below k (at most k when LE); j0 and j1 are multiples of 4.
+template <bool LE>
+__device__ __forceinline__ uint32_t count_keys(const uint32_t *s, int j0, int j1, uint32_t k) {
+    const uint4 *q = reinterpret_cast<const uint4 *>(s);
+    uint32_t c = 0u;
+    for (int j = j0; j < j1; j += 4) {
+        const uint4 v = q[j >> 2];
+        if (LE)
+            c += (uint32_t)(v.x <= k) + (uint32_t)(v.y <= k) + (uint32_t)(v.z <= k) + (uint32_t)(v.w <= k);
+        else
+            c += (uint32_t)(v.x < k) + (uint32_t)(v.y < k) + (uint32_t)(v.z < k) + (uint32_t)(v.w < k);
+    }
+    return c;
+}
+
 __global__ __launch_bounds__(kTileSortBlock) void k_tile_sort(
     const uint32_t *__restrict__ order, const uint2 *__restrict__ ranges,
     const uint32_t *__restrict__ depth_key,
@@ -641,29 +657,32 @@ __global__ __launch_bounds__(kTileSortBlock) void k_tile_sort(
     uint32_t *lv = vals + rg.x;
     bool second;
     if (n <= kTileSortBlock) {
-        // Short list: entry i goes to the number of entries that precede it in
-        // (depth, list position) order, the order the stable passes produce.
-        // The depths are padded to a multiple of 4 with a key above every depth
-        // (depth bits of finite or infinite floats are below 0x7F800001).
+        // Short list: entry i goes to the count of entries before it in (depth
+        // bits, list position) order, the order the stable passes give.  A
+        // wave's entries are 64 consecutive positions, so earlier waves' keys
+        // count when at most the entry's depth, later ones when below it, and
+        // only the wave's own run compares positions.  The depths are padded to
+        // a multiple of 4 with a key above every depth (depth bits of finite or
+        // infinite floats are below 0x7F800001).
         const int i = threadIdx.x;
-        uint32_t r = 0u, k = 0u;
+        const int np = (n + 3) & ~3;
+        uint32_t r = 0u;
         if (i < n) {
             r = lv[i];
-            k = depth_key[r];
-            s_k0[i] = k;
-        } else if (i < ((n + 3) & ~3)) {
+            s_k0[i] = depth_key[r];
+        } else if (i < np) {
             s_k0[i] = 0xFFFFFFFFu;
         }
         __syncthreads();
         if (i < n) {
+            const uint32_t k = s_k0[i];
+            const int w0 = i & ~63, w1 = min(w0 + 64, np);
+            uint32_t rank = count_keys<true>(s_k0, 0, w0, k) + count_keys<false>(s_k0, w1, np, k);
             const uint4 *q = reinterpret_cast<const uint4 *>(s_k0);
-            uint32_t rank = 0u;
-            for (int j = 0; j < n; j += 4) {   // entries j..j+3 count when below k, or equal and earlier
-                const uint4 kj = q[j >> 2];
-                rank += (kj.x < k + (uint32_t)(j < i)) ? 1u : 0u;
-                rank += (kj.y < k + (uint32_t)(j + 1 < i)) ? 1u : 0u;
-                rank += (kj.z < k + (uint32_t)(j + 2 < i)) ? 1u : 0u;
-                rank += (kj.w < k + (uint32_t)(j + 3 < i)) ? 1u : 0u;
+            for (int j = w0; j < w1; j += 4) {   // equal depths count when earlier
+                const uint4 v = q[j >> 2];
+                rank += (uint32_t)(v.x < k + (uint32_t)(j < i)) + (uint32_t)(v.y < k + (uint32_t)(j + 1 < i)) +
+                        (uint32_t)(v.z < k + (uint32_t)(j + 2 < i)) + (uint32_t)(v.w < k + (uint32_t)(j + 3 < i));
             }
             lv[rank] = r;
         }

@@ -79,14 +79,14 @@ def test_discrete_stage_bit_exact(ctx, tile):
 @pytest.mark.parametrize("planes", [1, 3])
 def test_equal_depths_keep_record_order(ctx, planes):
     """Means on one or three planes of constant camera depth, so most depths tie
-    exactly: every tile's list is in (depth bits, record) order, both for lists
-    of at most 256 keys (ranked in one step) and for longer ones (radix passes).
-    The oracle flags such ties as ambiguous under rounding; this checks the
-    order the GPU defines on its own depth keys."""
-    P = synth.random_gaussians(3000, seed=11)
+    exactly: every tile's list is in (depth bits, record) order, for lists ranked
+    in one step (at most 256 keys), sorted by radix passes in LDS (up to 1024)
+    and on global scratch (longer).  The oracle flags such ties as ambiguous under
+    rounding; this checks the order the GPU defines on its own depth keys."""
+    P = synth.random_gaussians(12000, seed=11)
     P[2] = np.float32([-0.25, 0.0, 0.4])[np.arange(P.shape[1]) % planes]
     cams = [synth.axis_camera(96, 64)]
-    log(f"[parity] equal depths on {planes} plane(s), 3000 Gaussians, tile 16")
+    log(f"[parity] equal depths on {planes} plane(s), 12000 Gaussians, tile 16")
     sc = GpuScene(ctx, P, cams, tile=16)
     sc.forward()
     count = sc.debug(_abi.GSF_DBG_COUNT, np.uint32, sc.n).astype(np.int64)
@@ -96,7 +96,9 @@ def test_equal_depths_keep_record_order(ctx, planes):
     depth = sc.debug(_abi.GSF_DBG_DEPTH, np.uint32, sc.n).astype(np.int64)
     ranges = sc.debug(_abi.GSF_DBG_RANGES, np.uint32, 2 * 24).reshape(-1, 2).astype(np.int64)
     lens = ranges[:, 1] - ranges[:, 0]
-    assert lens.sum() == M and (lens <= 256).any() and (lens > 256).any(), lens
+    assert lens.sum() == M, lens
+    for lo, hi in [(2, 256), (257, 1024), (1025, M)]:
+        assert ((lens >= lo) & (lens <= hi)).any(), (lo, hi, lens)
     want = np.lexsort((vals, depth[vals], keys))
     np.testing.assert_array_equal(want, np.arange(M))
     # each record appears once per tile it was counted for
