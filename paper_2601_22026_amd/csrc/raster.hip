@@ -42,12 +42,18 @@ constexpr float kLn2 = 0.69314718055994531f;
 // the integer pixel (as float) and (dx, dy) its centre's offset from the mean.
 __device__ __forceinline__ float splat_dx(float x, float ix, float hx) { return (x - ix) + hx; }
 
+// power2 = A2 dx^2 + B2 dx dy + C2 dy^2, evaluated as dx (A2 dx + B2 dy) + (C2 dy) dy
+// (five operations); every kernel that decides inclusion uses this one form.
+__device__ __forceinline__ float splat_power2(const float4 &a, const float4 &b, float dx, float dy) {
+    return fmaf(dx, fmaf(a.z, dx, a.w * dy), (b.x * dy) * dy);
+}
+
 __device__ __forceinline__ bool splat_alpha(const float4 &a, const float4 &b, const float4 &c,
                                             float x, float y, float &alpha, float &ae, float &ex,
                                             float &dx, float &dy) {
     dx = splat_dx(x, c.z, a.x);
     dy = splat_dx(y, c.w, a.y);
-    const float power2 = fmaf(a.z * dx, dx, fmaf(b.x * dy, dy, (a.w * dx) * dy));
+    const float power2 = splat_power2(a, b, dx, dy);
     if (power2 > 0.f || power2 < c.y) return false;
     ex = __builtin_amdgcn_exp2f(power2);
     ae = b.y * ex;
@@ -294,8 +300,7 @@ __global__ __launch_bounds__((fwd_threads<T, SPLIT>())) void k_render_fwd(
                     for (int u = 0; u < U; u++) {
                         const float dx = splat_dx(px[k], c[u].z, a[u].x);
                         const float dy = splat_dx(py[k], c[u].w, a[u].y);
-                        const float power2 =
-                            fmaf(a[u].z * dx, dx, fmaf(b[u].x * dy, dy, (a[u].w * dx) * dy));
+                        const float power2 = splat_power2(a[u], b[u], dx, dy);
                         valid[u] = !(power2 > 0.f) & !(power2 < c[u].y);
                         alpha[u] = fminf(kAlphaMax, b[u].y * __builtin_amdgcn_exp2f(power2));
                     }
@@ -533,9 +538,10 @@ __device__ __forceinline__ void render_bwd_unit(
             const uint32_t qm = QUAD ? s_m[j] : 0u;
             // row offset of the tile's first row from the mean; block k adds k ROWS
             const float dy0 = splat_dx((float)(ty * T), c.w, a.y);
-            // per lane sums: dpw dx, dpw dy, dpw dx^2, dpw dx dy, dpw dy^2 (dpw = dL/dpower),
-            // dL/do, dL/dcolour; the conic factors of the mean gradient are applied once
-            // per splat when the sums are flushed
+            // per lane sums: te dx, te dy, te dx^2, te dx dy, te dy^2 (te = dL/do, so
+            // that o te = dL/dpower), dL/do, dL/dcolour; the opacity and the conic
+            // factors of the mean gradient are applied once per splat when the sums
+            // are flushed
             // (-0 is the exact identity of addition, so the first term needs no add)
             float acc[9];
 #pragma unroll
@@ -551,7 +557,7 @@ __device__ __forceinline__ void render_bwd_unit(
                 // included pixel does exactly the float operations of the adjoint.
                 const float dx = splat_dx(px[k], c.z, a.x);
                 const float dy = splat_dx(py[k], c.w, a.y);
-                const float power2 = fmaf(a.z * dx, dx, fmaf(b.x * dy, dy, (a.w * dx) * dy));
+                const float power2 = splat_power2(a, b, dx, dy);
                 const bool inc = (pos < nc[k]) & !(power2 > 0.f) & !(power2 < c.y);
                 const float ex = __builtin_amdgcn_exp2f(power2);
                 const float ae = b.y * ex;
@@ -571,11 +577,13 @@ __device__ __forceinline__ void render_bwd_unit(
                 acc[8] = fmaf(wT, g2[k], acc[8]);
                 gR[k] = fmaf(gc, wT, gR[k]);
                 Tr[k] = inc ? Tb : Tr[k];
-                // a clamped alpha passes no gradient to the opacity or the power
+                // a clamped alpha passes no gradient to the opacity or the power;
+                // te = dL/do, and dL/dpower (natural units) = o te, the opacity
+                // factor being applied to the sums once per splat at the flush
                 const bool open = inc & !(ae > kAlphaMax);
-                const float dpw = (open ? ae : 0.f) * dalpha;   // d loss / d power (natural units)
-                acc[5] = fmaf(open ? ex : 0.f, dalpha, acc[5]);
-                const float ux = dpw * dx, uy = dpw * dy;
+                const float te = open ? ex * dalpha : 0.f;
+                acc[5] += te;
+                const float ux = te * dx, uy = te * dy;
                 acc[0] += ux;
                 acc[1] += uy;
                 acc[2] = fmaf(ux, dx, acc[2]);
@@ -632,8 +640,10 @@ __device__ __forceinline__ void render_bwd_unit(
 #pragma unroll
                         for (int f = 0; f < 9; f++) S[f] += s_g[w * GS + t * 9 + f];
                     }
-                    const float A2 = s_a[jj].z, B2 = s_a[jj].w, C2 = s_b[jj].x;
+                    const float A2 = s_a[jj].z, B2 = s_a[jj].w, C2 = s_b[jj].x, o = s_b[jj].y;
                     const uint32_t q = s_q[jj];
+#pragma unroll
+                    for (int f = 0; f < 5; f++) S[f] *= o;   // te sums -> dL/dpower sums
                     // dpower/dmean = (A dx + B dy, B dx + C dy) = -ln2 (2 A2 dx + B2 dy, B2 dx + 2 C2 dy);
                     // dpower/d(A, B, C) = (-dx^2 / 2, -dx dy, -dy^2 / 2)
                     kp.pa[q] = make_float4(-kLn2 * (2.f * A2 * S[0] + B2 * S[1]),
