@@ -341,11 +341,14 @@ __device__ __forceinline__ FoveaTiles fovea_tiles(const float *__restrict__ gaze
 // support ellipse reaches (row_span), the ellipse constants (slope, kw, ws,
 // dyr; ey follows as sqrt(kw / ws)) and the packed row spans of short boxes.
 // With cull_gaze (nullable) the rectangle is clipped to the view's
-// fovea tiles (fovea_tiles with cull_radius).
+// fovea tiles (fovea_tiles with cull_radius).  block_sums[b] receives the
+// total count of records 256 b .. 256 b + 255 (scan_blocks(nrec) words), the
+// input of launch_scan_duplicate.
 void launch_project_fwd(hipStream_t s, const float *P, int n, int nviews, int deg,
                         const gsf_camera *cams, const ViewDesc *views, int tile, SplatPtrs sp,
                         uint32_t *depth_key, uint2 *rect, uint32_t *count, float4 *ell,
-                        uint2 *rspan, const float *cull_gaze, float cull_radius);
+                        uint2 *rspan, const float *cull_gaze, float cull_radius,
+                        uint32_t *block_sums);
 
 // Parameter gradient from the per-key screen-space gradients the compositing
 // adjoint left in kp: for SH degrees 0-1 summed per record (wave_key_sum) on
@@ -358,7 +361,8 @@ void launch_project_bwd(hipStream_t s, const float *P, int n, int nviews, int de
 // Exclusive scan of the per-record tile counts and key emission in record
 // order (key = global tile id, value = record id).  Writes the key total to
 // m_total and (0 on overflow, with GSF_FLAG_CAPACITY) to m_dev; emits nothing on
-// overflow.  Clears ranges[total_tiles].  block_sums: scan_blocks(nrec) words.
+// overflow.  Clears ranges[total_tiles].  block_sums: the per-256-record count
+// totals launch_project_fwd wrote (scan_blocks(nrec) words), scanned in place.
 void launch_scan_duplicate(hipStream_t s, const uint32_t *count, const uint2 *rect,
                            const float4 *ell, const uint2 *rspan, SplatPtrs sp, uint32_t *koff,
                            int nrec, int n, int tile,

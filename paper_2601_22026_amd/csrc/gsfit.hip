@@ -292,7 +292,8 @@ gsf_status enqueue_forward(gsf_plan *p, const float *params, int64_t n, const gs
     {   // splats, support boxes and their tile counts, depth keys
         StageTimer t(p, GSF_STAGE_PROJECT);
         launch_project_fwd(s, params, (int)n, p->V, p->deg, cams, b.views, p->tile, splats(p),
-                           b.depth_key, b.rect, b.count, b.ell, b.rspan, cull_gaze, cull_radius);
+                           b.depth_key, b.rect, b.count, b.ell, b.rspan, cull_gaze, cull_radius,
+                           b.block_sums);
     }
     GSF_LAUNCHED(ctx);
     {   // one key per touched tile in record order; key total + capacity check on the device

@@ -222,8 +222,9 @@ __device__ __forceinline__ void view_dir(const Gauss &g, const gsf_camera &cam, 
     d[2] = u2 * inv_norm;
 }
 
+// Record r's projection; returns its key count (0 when culled).
 template <int DEG>
-__global__ __launch_bounds__(256) void k_project_fwd(const float *__restrict__ P, int n, int nrec,
+__device__ __forceinline__ uint32_t project_record(const float *__restrict__ P, int n, int r,
                                                      const gsf_camera *__restrict__ cams,
                                                      const ViewDesc *__restrict__ views, int tile,
                                                      SplatPtrs sp, uint32_t *__restrict__ depth_key,
@@ -234,8 +235,6 @@ __global__ __launch_bounds__(256) void k_project_fwd(const float *__restrict__ P
                                                      const float *__restrict__ cull_gaze,
                                                      float cull_radius) {
     constexpr int K = (DEG + 1) * (DEG + 1);
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= nrec) return;
     const int v = r / n;
     const int i = r - v * n;
     const gsf_camera &cam = cams[v];
@@ -248,7 +247,7 @@ __global__ __launch_bounds__(256) void k_project_fwd(const float *__restrict__ P
         depth_key[r] = 0xFFFFFFFFu;
         rect[r] = make_uint2(0u, 0u);
         count[r] = 0u;
-        return;
+        return 0u;
     }
     float d[3], inv_norm;
     view_dir<DEG>(g, cam, d, inv_norm);
@@ -292,7 +291,7 @@ __global__ __launch_bounds__(256) void k_project_fwd(const float *__restrict__ P
     if (!(x0 <= x1) || !(y0 <= y1)) {
         rect[r] = make_uint2(0u, 0u);
         count[r] = 0u;
-        return;
+        return 0u;
     }
     uint32_t tx0 = (uint32_t)x0 / tile, tx1 = (uint32_t)x1 / tile;
     uint32_t ty0 = (uint32_t)y0 / tile, ty1 = (uint32_t)y1 / tile;
@@ -301,7 +300,7 @@ __global__ __launch_bounds__(256) void k_project_fwd(const float *__restrict__ P
         if (f.tx0 > f.tx1 || (int)tx1 < f.tx0 || (int)tx0 > f.tx1 || (int)ty1 < f.ty0 || (int)ty0 > f.ty1) {
             rect[r] = make_uint2(0u, 0u);
             count[r] = 0u;
-            return;
+            return 0u;
         }
         tx0 = max(tx0, (uint32_t)f.tx0);
         tx1 = min(tx1, (uint32_t)f.tx1);
@@ -337,6 +336,33 @@ __global__ __launch_bounds__(256) void k_project_fwd(const float *__restrict__ P
         rspan[r] = make_uint2(packed[0], packed[1]);
     }
     count[r] = cnt;
+    return cnt;
+}
+
+// One thread per record, 256 records per block; block b also writes the key
+// count of its records to block_sums[b], the first level of the scan that
+// places the keys.
+template <int DEG>
+__global__ __launch_bounds__(256) void k_project_fwd(const float *__restrict__ P, int n, int nrec,
+                                                     const gsf_camera *__restrict__ cams,
+                                                     const ViewDesc *__restrict__ views, int tile,
+                                                     SplatPtrs sp, uint32_t *__restrict__ depth_key,
+                                                     uint2 *__restrict__ rect,
+                                                     uint32_t *__restrict__ count,
+                                                     float4 *__restrict__ ell,
+                                                     uint2 *__restrict__ rspan,
+                                                     const float *__restrict__ cull_gaze,
+                                                     float cull_radius, uint32_t *__restrict__ block_sums) {
+    __shared__ uint32_t s_w[4];
+    const int r = blockIdx.x * 256 + (int)threadIdx.x;
+    uint32_t c = r < nrec ? project_record<DEG>(P, n, r, cams, views, tile, sp, depth_key, rect, count,
+                                                ell, rspan, cull_gaze, cull_radius)
+                          : 0u;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) block_sums[blockIdx.x] = s_w[0] + s_w[1] + s_w[2] + s_w[3];
 }
 
 // d(quaternion)/... from d(R) for the rotation of a unit quaternion (w, x, y, z).
@@ -516,14 +542,15 @@ __global__ __launch_bounds__(128) void k_project_bwd(const float *__restrict__ P
 void launch_project_fwd(hipStream_t s, const float *P, int n, int nviews, int deg,
                         const gsf_camera *cams, const ViewDesc *views, int tile, SplatPtrs sp,
                         uint32_t *depth_key, uint2 *rect, uint32_t *count, float4 *ell,
-                        uint2 *rspan, const float *cull_gaze, float cull_radius) {
+                        uint2 *rspan, const float *cull_gaze, float cull_radius,
+                        uint32_t *block_sums) {
     const int nrec = n * nviews;
     const dim3 grid((nrec + 255) / 256), block(256);
     switch (deg) {
-    case 0: k_project_fwd<0><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rect, count, ell, rspan, cull_gaze, cull_radius); break;
-    case 1: k_project_fwd<1><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rect, count, ell, rspan, cull_gaze, cull_radius); break;
-    case 2: k_project_fwd<2><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rect, count, ell, rspan, cull_gaze, cull_radius); break;
-    default: k_project_fwd<3><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rect, count, ell, rspan, cull_gaze, cull_radius); break;
+    case 0: k_project_fwd<0><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rect, count, ell, rspan, cull_gaze, cull_radius, block_sums); break;
+    case 1: k_project_fwd<1><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rect, count, ell, rspan, cull_gaze, cull_radius, block_sums); break;
+    case 2: k_project_fwd<2><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rect, count, ell, rspan, cull_gaze, cull_radius, block_sums); break;
+    default: k_project_fwd<3><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rect, count, ell, rspan, cull_gaze, cull_radius, block_sums); break;
     }
 }
 

@@ -3,7 +3,8 @@
 // (global tile, camera depth, record), and per-tile [start, end) ranges.
 //
 //   1. scan + duplicate: an exclusive scan of the records' touched-tile counts
-//      (record order) places every record's keys; key = global tile id,
+//      (record order; the projection writes each 256-record block's total)
+//      places every record's keys; key = global tile id,
 //      value = record id.  The total is checked against the key capacity on the
 //      device.  No global atomics: counters with thousands of writers serialise
 //      badly across the XCDs of this chip.
@@ -34,6 +35,7 @@ constexpr int kSortMaxGrid = 1024;
 constexpr int kScanBlock = 256;
 constexpr int kScanIpt = 1;                  // 256 records per block: 50k records fill 196 blocks
 constexpr int kScanTile = kScanBlock * kScanIpt;
+static_assert(kScanTile == 256, "the projection writes the count totals of 256-record blocks");
 constexpr int kTileSortBlock = 256;
 constexpr int kTileSortLds = 1024;           // list length sorted in LDS (22 KB: 7 workgroups per CU); longer lists use global scratch
 
@@ -190,18 +192,8 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(
 
 // ---- 1. scan of the touched-tile counts + key duplication (record order) -------
 
-__global__ __launch_bounds__(kScanBlock) void k_scan_reduce(const uint32_t *__restrict__ count,
-                                                            int nrec, uint32_t *__restrict__ block_sums) {
-    __shared__ uint32_t s_wave[4];
-    const int base = blockIdx.x * kScanTile + threadIdx.x * kScanIpt;
-    uint32_t sum = 0;
-#pragma unroll
-    for (int k = 0; k < kScanIpt; k++)
-        if (base + k < nrec) sum += count[base + k];
-    uint32_t total;
-    block_excl_scan_256(sum, s_wave, total);
-    if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
-}
+// The per-block totals of the counts (256 records a block) come from the
+// projection kernel, which computes the counts.
 
 __global__ __launch_bounds__(1024) void k_scan_top(uint32_t *__restrict__ block_sums, int nblocks,
                                                    uint32_t *__restrict__ m_dev,
@@ -743,7 +735,6 @@ void launch_scan_duplicate(hipStream_t s, const uint32_t *count, const uint2 *re
                            uint32_t *vals, uint32_t *m_dev, unsigned long long *m_total,
                            uint32_t *flags, int64_t capacity, uint2 *ranges, int total_tiles) {
     const int nb = (nrec + kScanTile - 1) / kScanTile;
-    k_scan_reduce<<<nb, kScanBlock, 0, s>>>(count, nrec, block_sums);
     k_scan_top<<<1, 1024, 0, s>>>(block_sums, nb, m_dev, m_total, flags, capacity);
     k_scan_dup<<<nb, kScanBlock, 0, s>>>(count, rect, ell, rspan, sp, koff, nrec, n, tile, views,
                                          block_sums, m_total, capacity, keys, vals, ranges,
