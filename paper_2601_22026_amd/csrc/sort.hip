@@ -36,6 +36,7 @@ constexpr int kScanBlock = 256;
 constexpr int kScanIpt = 1;                  // 256 records per block: 50k records fill 196 blocks
 constexpr int kScanTile = kScanBlock * kScanIpt;
 static_assert(kScanTile == 256, "the projection writes the count totals of 256-record blocks");
+constexpr int kOwnPrefixBlocks = 1024;       // up to this many scan blocks, each sums its own prefix (no k_scan_top)
 constexpr int kTileSortBlock = 256;
 constexpr int kTileSortLds = 1024;           // list length sorted in LDS (22 KB: 7 workgroups per CU); longer lists use global scratch
 
@@ -245,10 +246,12 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_dup(
     const uint32_t *__restrict__ count, const uint2 *__restrict__ rect,
     const float4 *__restrict__ ell, const uint2 *__restrict__ rspan, SplatPtrs sp,
     uint32_t *__restrict__ koff, int nrec, int n, int tile,
-    const ViewDesc *__restrict__ views, const uint32_t *__restrict__ block_prefix,
-    const unsigned long long *__restrict__ m_total, int64_t capacity, uint32_t *__restrict__ keys,
+    const ViewDesc *__restrict__ views, const uint32_t *__restrict__ block_prefix, int nblocks,
+    bool own_prefix, uint32_t *__restrict__ m_dev, unsigned long long *__restrict__ m_total,
+    uint32_t *__restrict__ flags, int64_t capacity, uint32_t *__restrict__ keys,
     uint32_t *__restrict__ vals, uint2 *__restrict__ ranges, int total_tiles) {
     __shared__ uint32_t s_wave[4];
+    __shared__ unsigned long long s_tot[4];
     __shared__ uint32_t s_off[kScanTile];   // block-local exclusive key offset per record
     __shared__ uint2 s_rect[kScanTile];
     __shared__ int s_view[kScanTile];
@@ -258,7 +261,46 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_dup(
     __shared__ uint2 s_pack[kScanTile];       // packed row spans (kPackRows rows or fewer)
     for (int t = blockIdx.x * kScanBlock + threadIdx.x; t < total_tiles; t += gridDim.x * kScanBlock)
         ranges[t] = make_uint2(0u, 0u);
-    if (*m_total > (unsigned long long)capacity) return;    // overflow: emit nothing
+    // The block's first key and the key total.  With own_prefix (at most
+    // kOwnPrefixBlocks blocks) block_prefix holds the per-block totals and each
+    // block sums those before it itself, block 0 publishing the total; else
+    // k_scan_top has scanned them in place and published it.
+    uint32_t gbase;
+    unsigned long long total_keys;
+    if (own_prefix) {
+        unsigned long long pre = 0ull, all = 0ull;
+        for (int b = threadIdx.x; b < nblocks; b += kScanBlock) {
+            const unsigned long long c = block_prefix[b];
+            all += c;
+            if (b < (int)blockIdx.x) pre += c;
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            pre += __shfl_xor(pre, o, 64);
+            all += __shfl_xor(all, o, 64);
+        }
+        if ((threadIdx.x & 63) == 0) {
+            s_tot[threadIdx.x >> 6] = all;
+            s_wave[threadIdx.x >> 6] = (uint32_t)min(pre, 0xFFFFFFFFull);
+        }
+        __syncthreads();
+        total_keys = s_tot[0] + s_tot[1] + s_tot[2] + s_tot[3];
+        gbase = s_wave[0] + s_wave[1] + s_wave[2] + s_wave[3];   // used only when total fits
+        __syncthreads();   // s_wave is reused by the block scan below
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            *m_total = total_keys;
+            if (total_keys > (unsigned long long)capacity) {
+                *m_dev = 0u;
+                atomicOr(flags, GSF_FLAG_CAPACITY);
+            } else {
+                *m_dev = (uint32_t)total_keys;
+            }
+        }
+    } else {
+        total_keys = *m_total;
+        gbase = block_prefix[blockIdx.x];
+    }
+    if (total_keys > (unsigned long long)capacity) return;    // overflow: emit nothing
     const int rec0 = blockIdx.x * kScanTile;
     const int base = rec0 + threadIdx.x * kScanIpt;
     uint32_t cnt[kScanIpt];
@@ -270,7 +312,6 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_dup(
     }
     uint32_t total;
     uint32_t off = block_excl_scan_256(sum, s_wave, total);
-    const uint32_t gbase = block_prefix[blockIdx.x];
 #pragma unroll
     for (int k = 0; k < kScanIpt; k++) {
         const int i = threadIdx.x * kScanIpt + k;
@@ -735,10 +776,11 @@ void launch_scan_duplicate(hipStream_t s, const uint32_t *count, const uint2 *re
                            uint32_t *vals, uint32_t *m_dev, unsigned long long *m_total,
                            uint32_t *flags, int64_t capacity, uint2 *ranges, int total_tiles) {
     const int nb = (nrec + kScanTile - 1) / kScanTile;
-    k_scan_top<<<1, 1024, 0, s>>>(block_sums, nb, m_dev, m_total, flags, capacity);
+    const bool own_prefix = nb >= 1 && nb <= kOwnPrefixBlocks;   // else k_scan_top writes the total
+    if (!own_prefix) k_scan_top<<<1, 1024, 0, s>>>(block_sums, nb, m_dev, m_total, flags, capacity);
     k_scan_dup<<<nb, kScanBlock, 0, s>>>(count, rect, ell, rspan, sp, koff, nrec, n, tile, views,
-                                         block_sums, m_total, capacity, keys, vals, ranges,
-                                         total_tiles);
+                                         block_sums, nb, own_prefix, m_dev, m_total, flags,
+                                         capacity, keys, vals, ranges, total_tiles);
 }
 
 void launch_tile_bounds(hipStream_t s, const uint32_t *keys, const uint32_t *m_dev, uint32_t m_host,
