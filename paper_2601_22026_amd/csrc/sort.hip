@@ -459,61 +459,56 @@ __device__ __forceinline__ uint64_t class_peers(uint32_t c, bool valid) {
     return peers;
 }
 
-// One workgroup: a counting sort of the tile ids by descending class, each
-// wave aggregating its lanes per class before touching the LDS counters.  The
-// ranges of OU rounds of 1024 tiles are loaded before any is used, so the loop
-// is not a chain of dependent global loads.
+// One workgroup (at most 1024 kOrderU tiles): a counting sort of the tile ids
+// by descending class, each wave aggregating its lanes per class before
+// touching the LDS counters.  The classes of all rounds are loaded before any
+// is used, so there is no chain of dependent global loads, and they and each
+// wave's peer masks are kept from the counting to the placing; the 33 class
+// counters are scanned by one wave.
 constexpr int kOrderU = 8;
 
 __global__ __launch_bounds__(1024) void k_tile_order(const uint2 *__restrict__ ranges, int total_tiles,
                                                      uint32_t *__restrict__ order) {
-    __shared__ uint32_t s_cnt[33];
-    const int t = threadIdx.x;
-    if (t < 33) s_cnt[t] = 0u;
-    __syncthreads();
-    for (int base = 0; base < total_tiles; base += 1024 * kOrderU) {   // uniform trip count
-        uint32_t c[kOrderU];
+    __shared__ uint32_t s_cnt[64];
+    const int t = threadIdx.x, lane = __lane_id();
+    if (t < 64) s_cnt[t] = 0u;
+    uint32_t c[kOrderU];
+    uint64_t peers[kOrderU];
 #pragma unroll
-        for (int u = 0; u < kOrderU; u++) {
-            const int i = base + u * 1024 + t;
-            c[u] = i < total_tiles ? tile_class(ranges, i) : 0u;
-        }
-#pragma unroll
-        for (int u = 0; u < kOrderU; u++) {
-            const bool valid = base + u * 1024 + t < total_tiles;
-            const uint64_t peers = class_peers(c[u], valid);
-            if (valid && lanes_below(peers) == 0u) atomicAdd(&s_cnt[c[u]], (uint32_t)__popcll(peers));
-        }
+    for (int u = 0; u < kOrderU; u++) {
+        const int i = u * 1024 + t;
+        c[u] = i < total_tiles ? tile_class(ranges, i) : 0u;
     }
     __syncthreads();
-    if (t == 0) {   // class 32 first
-        uint32_t run = 0;
-        for (int k = 32; k >= 0; k--) {
-            const uint32_t n = s_cnt[k];
-            s_cnt[k] = run;
-            run += n;
-        }
+#pragma unroll
+    for (int u = 0; u < kOrderU; u++) {
+        const bool valid = u * 1024 + t < total_tiles;
+        peers[u] = class_peers(c[u], valid);
+        if (valid && lanes_below(peers[u]) == 0u) atomicAdd(&s_cnt[c[u]], (uint32_t)__popcll(peers[u]));
     }
     __syncthreads();
-    for (int base = 0; base < total_tiles; base += 1024 * kOrderU) {
-        uint32_t c[kOrderU];
+    if (t < 64) {   // first slot of each class, class 32 first: exclusive scan over lanes 32 - c
+        const int cls = 32 - lane;
+        const uint32_t x = cls >= 0 ? s_cnt[cls] : 0u;
+        uint32_t inc = x;
 #pragma unroll
-        for (int u = 0; u < kOrderU; u++) {
-            const int i = base + u * 1024 + t;
-            c[u] = i < total_tiles ? tile_class(ranges, i) : 0u;
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += y;
         }
+        if (cls >= 0) s_cnt[cls] = inc - x;
+    }
+    __syncthreads();
 #pragma unroll
-        for (int u = 0; u < kOrderU; u++) {
-            const int i = base + u * 1024 + t;
-            const bool valid = i < total_tiles;
-            const uint64_t peers = class_peers(c[u], valid);
-            const uint32_t below = lanes_below(peers);
-            uint32_t start = 0u;
-            if (valid && below == 0u) start = atomicAdd(&s_cnt[c[u]], (uint32_t)__popcll(peers));
-            const int leader = peers ? __builtin_ctzll(peers) : __lane_id();
-            start = __shfl(start, leader, 64);
-            if (valid) order[start + below] = (uint32_t)i;
-        }
+    for (int u = 0; u < kOrderU; u++) {
+        const int i = u * 1024 + t;
+        const bool valid = i < total_tiles;
+        const uint32_t below = lanes_below(peers[u]);
+        uint32_t start = 0u;
+        if (valid && below == 0u) start = atomicAdd(&s_cnt[c[u]], (uint32_t)__popcll(peers[u]));
+        const int leader = peers[u] ? __builtin_ctzll(peers[u]) : lane;
+        start = __shfl(start, leader, 64);
+        if (valid) order[start + below] = (uint32_t)i;
     }
 }
 
@@ -795,7 +790,7 @@ int order_groups(int64_t total_tiles) { return (int)((total_tiles + kOrderTiles 
 
 void launch_tile_order(hipStream_t s, const uint2 *ranges, int total_tiles, uint32_t *order,
                        uint32_t *counts) {
-    if (total_tiles <= 4 * kOrderTiles) {
+    if (total_tiles <= 1024 * kOrderU) {
         k_tile_order<<<1, 1024, 0, s>>>(ranges, total_tiles, order);
         return;
     }
