@@ -138,13 +138,22 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(
         const uint32_t dp = block_excl_scan_256(tot, s_wave, all);
         if (t < nd) s_base[t] = dp + hist[(size_t)t * G + blockIdx.x];
     }
-    for (uint32_t tile0 = start; tile0 < end; tile0 += kSortTile) {
+    // Each pass over the chunk takes up to kSortTile keys; wave w ranks the
+    // contiguous run [wbase, wbase + span) of them, span being the fewest whole
+    // rounds of 64 that cover the keys left, so a short chunk still spreads over
+    // the four waves (earlier waves hold earlier keys, as the in-order
+    // combination needs).
+    for (uint32_t tile0 = start, span; tile0 < end; tile0 += 4u * span) {
+        const uint32_t left = end - tile0;
+        span = min(64u * kSortIpt, (left + 255u) / 256u * 64u);
+        const int rounds = (int)(span / 64u);   // workgroup-uniform
         for (int k = t; k < 4 * 256; k += kSortBlock) (&s_cnt[0][0])[k] = 0u;
         __syncthreads();
         uint32_t key[kSortIpt], val[kSortIpt], rank[kSortIpt];
-        const uint32_t wbase = tile0 + (uint32_t)w * 64u * kSortIpt;
+        const uint32_t wbase = tile0 + (uint32_t)w * span;
 #pragma unroll
         for (int r = 0; r < kSortIpt; r++) {
+            if (r >= rounds) break;
             const uint32_t idx = wbase + (uint32_t)r * 64u + (uint32_t)lane;
             const bool valid = idx < end;
             key[r] = valid ? kin[idx] : 0u;
@@ -177,6 +186,7 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < kSortIpt; r++) {
+            if (r >= rounds) break;
             const uint32_t idx = wbase + (uint32_t)r * 64u + (uint32_t)lane;
             if (idx < end) {
                 const uint32_t d = (key[r] >> shift) & mask;
