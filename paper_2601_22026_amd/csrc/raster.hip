@@ -935,18 +935,19 @@ __global__ __launch_bounds__(1024) void k_loss_final(const float *__restrict__ p
                                                      uint32_t count_host, float *__restrict__ loss,
                                                      uint32_t *__restrict__ flags,
                                                      int32_t *__restrict__ step_inc) {
-    __shared__ float s_part[1024];
+    __shared__ float s_part[16];
     float s = 0.f;
     for (int k = threadIdx.x; k < nparts; k += 1024) s += partial[k];
-    s_part[threadIdx.x] = s;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);   // same tree on every lane
+    if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = s;
     __syncthreads();
-    for (int o = 512; o >= 1; o >>= 1) {
-        if ((int)threadIdx.x < o) s_part[threadIdx.x] += s_part[threadIdx.x + o];
-        __syncthreads();
-    }
     if (threadIdx.x == 0) {
+        float tot = 0.f;
+#pragma unroll
+        for (int w = 0; w < 16; w++) tot += s_part[w];
         const uint32_t cnt = mask_count ? *mask_count : count_host;
-        const float L = s_part[0] / (float)max(cnt, 1u);
+        const float L = tot / (float)max(cnt, 1u);
         loss[0] = L;
         if (!isfinite(L)) atomicOr(flags, GSF_FLAG_NONFINITE);
         // a step whose keys overflowed the capacity is not counted (its Adam
