@@ -269,8 +269,10 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_dup(
     __shared__ float4 s_e1[kScanTile];        // ey, hxo, hyo, -
     __shared__ int2 s_ixy[kScanTile];
     __shared__ uint2 s_pack[kScanTile];       // packed row spans (kPackRows rows or fewer)
+    __shared__ ViewDesc s_views[kMaxViews];   // read per key: kept in LDS, not reloaded from memory
     for (int t = blockIdx.x * kScanBlock + threadIdx.x; t < total_tiles; t += gridDim.x * kScanBlock)
         ranges[t] = make_uint2(0u, 0u);
+    if ((int)threadIdx.x < min(nrec / n, kMaxViews)) s_views[threadIdx.x] = views[threadIdx.x];
     // The block's first key and the key total.  With own_prefix (at most
     // kOwnPrefixBlocks blocks) block_prefix holds the per-block totals and each
     // block sums those before it itself, block 0 publishing the total; else
@@ -359,7 +361,7 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_dup(
         const uint2 rc = s_rect[lo];
         const int x0 = (int)(rc.x & 0xFFFFu), y0 = (int)(rc.x >> 16);
         const int x1 = (int)(rc.y & 0xFFFFu), y1 = (int)(rc.y >> 16);
-        const ViewDesc vd = views[s_view[lo]];
+        const ViewDesc vd = s_views[s_view[lo]];
         uint32_t key = 0u;
         if (y1 - y0 + 1 <= kPackRows && x1 - x0 + 1 <= kPackCols) {   // packed spans
             const uint2 pk = s_pack[lo];
