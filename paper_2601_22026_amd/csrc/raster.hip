@@ -72,6 +72,14 @@ constexpr int bwd_threads() { return T == 32 ? 128 : 64; }
 // threshold of the base-2 exponent, computed once by the projection.  The
 // padded half height of the support (where o e^power >= 1/255 can hold) is
 // the ellipse's y extent plus the absolute padding.
+// Half height of the padded ellipse for the quadrant test, with the hardware
+// reciprocal and square root: their few-ulp error lies far inside the padding,
+// and the forward and the adjoint both use this form, so they skip the same
+// quadrants.  (Tile enumeration keeps the exact form everywhere.)
+__device__ __forceinline__ float quad_half_height(const float4 &e0) {
+    return __builtin_amdgcn_sqrtf(e0.y * __builtin_amdgcn_rcpf(e0.z));
+}
+
 __device__ __forceinline__ float support_half_height(const float4 &e0) {
     return sqrtf(e0.y / e0.z) + kBoxAbs;
 }
@@ -260,7 +268,7 @@ __global__ __launch_bounds__((fwd_threads<T, SPLIT>())) void k_render_fwd(
             bool meet = jl < nb;
             if (QUAD && meet) {
                 const float4 e0 = SE[jl], a0 = SA[jl], c0 = SC[jl];
-                const Ellipse e{e0.x, e0.y, e0.z, e0.w, sqrtf(e0.y / e0.z), a0.x, a0.y, (int)c0.z, (int)c0.w};
+                const Ellipse e{e0.x, e0.y, e0.z, e0.w, quad_half_height(e0), a0.x, a0.y, (int)c0.z, (int)c0.w};
                 meet = quad_meets(e, tx * T + (quad & 1) * 8, ty * T + (quad >> 1) * 8);
             }
             // the wave's list of them in LDS, padded with the inert slot to whole
@@ -516,7 +524,7 @@ __device__ __forceinline__ void render_bwd_unit(
             s_c[j] = rc;
             s_q[j] = key_slot(kp, sp, r, ty, tx, TL, vd.width, vd.height);
             if (QUAD) {
-                const Ellipse e{e0.x, e0.y, e0.z, e0.w, sqrtf(e0.y / e0.z), ra.x, ra.y, (int)rc.z, (int)rc.w};
+                const Ellipse e{e0.x, e0.y, e0.z, e0.w, quad_half_height(e0), ra.x, ra.y, (int)rc.z, (int)rc.w};
                 s_m[j] = (uint8_t)quadrant_mask(e, tx * T, ty * T);
             } else {
                 s_h[j] = support_half_height(e0);
