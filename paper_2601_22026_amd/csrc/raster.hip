@@ -894,7 +894,7 @@ __global__ __launch_bounds__(kLossBlock) void k_loss_l1(
     int tile, int tgt_planes, bool alpha_term, const float *__restrict__ bg,
     const uint32_t *__restrict__ mask_count, uint32_t count_host, float *__restrict__ dl,
     float *__restrict__ partial) {
-    __shared__ float s_red[kLossBlock];
+    __shared__ float s_red[kLossBlock / 64];
     const uint32_t cnt = mask_count ? *mask_count : count_host;
     const int64_t p = (int64_t)blockIdx.x * kLossBlock + threadIdx.x;
     float s = 0.f;
@@ -927,13 +927,16 @@ __global__ __launch_bounds__(kLossBlock) void k_loss_l1(
             g[c * plane + q] = gv;
         }
     }
-    s_red[threadIdx.x] = s;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);   // fixed tree: deterministic
+    if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = s;
     __syncthreads();
-    for (int o = kLossBlock / 2; o >= 1; o >>= 1) {
-        if ((int)threadIdx.x < o) s_red[threadIdx.x] += s_red[threadIdx.x + o];
-        __syncthreads();
+    if (threadIdx.x == 0) {
+        float tot = 0.f;
+#pragma unroll
+        for (int w = 0; w < kLossBlock / 64; w++) tot += s_red[w];
+        partial[blockIdx.x] = tot;
     }
-    if (threadIdx.x == 0) partial[blockIdx.x] = s_red[0];
 }
 
 // Sum of the partials in a fixed order (deterministic) -> loss; optionally
