@@ -1,30 +1,36 @@
 #!/usr/bin/env python3
 """Fit-step benchmark of the MI355X Gaussian-splatting fit path.
 
-Default workload (phantom-seeded fit): a 128^3 uint16 CT-like phantom (20
-random ellipsoids, HU-like values, noise sigma 20, seed 3); one Gaussian per
-voxel above 1200 capped at 50,000 (seed 4), isotropic one-voxel scale,
-opacity 0.1, linear transfer-function colour (SH degree 0); one 1024x1024
-view, 60 degree FOV, on the radius-3 sphere (pose seed 2); L1 loss against an
-emission-absorption ray march of the same volume; Adam lr 1e-3.  All inputs
-are seeded and synthetic (the paper's CT datasets are not available).
+Default workload (foveal refinement, the configuration the metric's
+ms/regeneration is defined on): a 256^3 uint16 CT-like phantom (20 random
+ellipsoids, HU-like values, noise sigma 20, seed 3); one Gaussian per voxel
+above 1200 capped at 500,000 (seed 4), isotropic one-voxel scale, opacity 0.1,
+linear transfer-function colour (SH degree 0); 16 views of 1920x1920, 60 degree
+FOV, poses on the radius-3 sphere (seed 2); L1 loss masked to a circular fovea
+of radius 0.2 W around a random gaze point per view (seed 6), against FP32
+emission-absorption ray marches of the same volume; Adam lr 1e-3.  One
+regeneration = device seeding from the resident volume + plan + capture + 300
+captured steps.  All inputs are seeded and synthetic (the paper's CT datasets
+are not available).
 
 Other workloads (--workload): small (1,000 random Gaussians, one 128^2 view,
-target rendered by the oracle), batched (200,000 SH3 Gaussians, 8 views of
-uneven resolution), foveal (500,000 Gaussians seeded from a 256^3 phantom, 16
-views of 1920^2, loss masked to a fovea of radius 0.2 W at a random gaze point,
-ms per 300-step regeneration), stereo (1,000,000 SH3 Gaussians, two eyes of
-2064x2208, recomputed / checkpointed / stored transmittance compared).
+target rendered by the oracle), phantom (50,000 Gaussians from a 128^3
+phantom, one 1024^2 view), batched (200,000 SH3 Gaussians, 8 views of uneven
+resolution), stereo (1,000,000 SH3 Gaussians, two eyes of 2064x2208,
+recomputed / checkpointed / stored transmittance compared), p0 (the paper's
+initial-fit shape: 20,000 Gaussians from the 128^3 phantom, 12 views of 512^2,
+one view per step, a 700-step fit), reproject, firsthit.
 
 A "step" is one forward + loss + backward + Adam pass over all views.  The
 timed path is the fused step captured in a HIP graph (one launch per stage
 for all views, key count on the device), replayed K times after W warm-up
-replays, bracketed by stream synchronisation and timed with HIP events.
-Alongside: the plain path (one host-synchronised plan per view, eager), the
-eager fused path, per-stage kernel times (HIP events recorded by the library
-on the stream the kernels run on, over the same step indices as the timed
-replays), the roofline of the dominant kernel and the FP64 CPU oracle on a
-bounded sample of rows.
+replays, bracketed by device synchronisation and timed with HIP events.
+Alongside: the plain path (one host-synchronised plan per view, eager, the
+same loss normalisation and fovea culling), the eager fused path, per-stage
+kernel times (HIP events recorded by the library on the stream the kernels run
+on, over the same step indices as the timed replays), the roofline of the
+dominant kernel and the FP64 CPU oracle on a bounded sample.  Each phase
+announces itself on stderr before it starts.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload NAME]
 """
@@ -48,13 +54,34 @@ METRIC = "Gaussian fit-steps/s (fwd+bwd+Adam), Mpix/s, ms/regeneration vs plain"
 FLOPS_ALPHA = 18
 FLOPS_FWD_INCLUDED = 10
 FLOPS_BWD_INCLUDED = 48
-# Non-packed FP32 vector peak: 256 CUs x 4 SIMD x 16 lanes x 2 flops (FMA) x 2.4 GHz.
-PEAK_FP32_TFLOPS = 78.6
+# MI355X FP32 vector peak: 256 CUs x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz x 2
+# (packed dual-issue FP32) = 157.3 TFLOP/s.  Without packed FP32 instructions
+# (this build turns them off) the attainable peak is half that, 78.6 TFLOP/s,
+# which is quoted beside the published figure.
+PEAK_FP32_TFLOPS = 157.3
+PEAK_FP32_NONPACKED_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
+GSF_FLAG_CAPACITY = 1
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def phase(msg):
+    """Announce a phase before it starts (flushed), so a long phase is named."""
+    log(f"[bench] >> {msg}")
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
 
 
 @dataclasses.dataclass
@@ -68,31 +95,28 @@ class Workload:
     gaze: object = None             # float32 [V][2] or None
     target_params: object = None    # Gaussian set whose render is the target
     volume: object = None
+    device_targets: bool = False    # targets: FP32 ray march of `volume` on the device
+    views_per_step: int = 0         # 0: every view each step; 1: one view per step, cycled
+    fit_steps: int = 0              # steps of one fit (p0), reported as ms per fit
 
 
-def _phantom_fit(n_vol, cap, cams, gaze=None):
+def _phantom(n_vol, cap):
+    import synth
+    phase(f"phantom {n_vol}^3 and voxel seeding (cap {cap}) on the host")
+    vol = synth.phantom(n_vol, seed=synth.SEED_VOLUME)
+    P = synth.seed_from_volume(vol, cap=cap, seed=synth.SEED_CAP_SUBSET)
+    return P, vol
+
+
+def _marched_targets(vol, cams):
     import numpy as np
 
     import synth
-    vol = synth.phantom(n_vol, seed=synth.SEED_VOLUME)
-    P = synth.seed_from_volume(vol, cap=cap, seed=synth.SEED_CAP_SUBSET)
-    tg = []
-    for k, c in enumerate(cams):
-        if gaze is None:
-            tg.append(synth.raymarch_volume(vol, c)[:3])
-            continue
-        # only rows that meet the fovea carry loss; the others stay zero
-        r = 0.2 * c.width
-        y0 = max(0, int(np.floor(gaze[k][1] - r - 1)))
-        y1 = min(c.height, int(np.ceil(gaze[k][1] + r + 1)))
-        img = np.zeros((3, c.height, c.width), np.float32)
-        img[:, y0:y1] = synth.raymarch_volume(vol, c, rows=np.arange(y0, y1))[:3]
-        tg.append(img)
-    targets = np.concatenate([t.reshape(-1) for t in tg])
-    return P, targets, vol
+    phase(f"FP64 ray march of {len(cams)} target view(s) on the host")
+    return np.concatenate([synth.raymarch_volume(vol, c)[:3].reshape(-1) for c in cams])
 
 
-def build_workload(name="phantom"):
+def build_workload(name="foveal"):
     import numpy as np
 
     import synth
@@ -107,11 +131,20 @@ def build_workload(name="phantom"):
     if name == "phantom":
         d = synth.sphere_directions(1, seed=synth.SEED_POSES)[0]
         cam = synth.look_at_camera(3.0 * d, width=1024, height=1024, fov_x_deg=60.0)
-        P, targets, vol = _phantom_fit(128, 50_000, [cam])
+        P, vol = _phantom(128, 50_000)
         return Workload(name, "phantom-seeded fit: 128^3 phantom, 50,000 Gaussians (SH0), one "
                               "1024x1024 view, L1 vs ray-marched target, Adam lr 1e-3",
                         "synthetic: seeded CT-like phantom, voxel-seeded Gaussians, ray-marched target",
-                        P, [cam], targets=targets, volume=vol)
+                        P, [cam], targets=_marched_targets(vol, [cam]), volume=vol)
+    if name == "p0":
+        cams = synth.sphere_cameras([(512, 512)] * 12, radius=3.0, seed=synth.SEED_POSES)
+        P, vol = _phantom(128, 20_000)
+        return Workload(name, "paper-shape initial fit: 128^3 phantom, 20,000 Gaussians (SH0), 12 "
+                              "views of 512x512, one view per step (cycled), 700-step fit, L1 vs "
+                              "ray-marched targets, Adam lr 1e-3",
+                        "synthetic: seeded CT-like phantom, voxel-seeded Gaussians, ray-marched targets",
+                        P, cams, targets=_marched_targets(vol, cams), volume=vol,
+                        views_per_step=1, fit_steps=700)
     if name == "batched":
         n = 200_000
         mu = synth.scaled_logscale_mean(n)
@@ -128,12 +161,13 @@ def build_workload(name="phantom"):
         dirs = synth.sphere_directions(16, seed=synth.SEED_POSES)
         cams = [synth.look_at_camera(3.0 * d, width=1920, height=1920, fov_x_deg=60.0) for d in dirs]
         gaze = synth.gaze_points(cams, seed=synth.SEED_GAZE)
-        P, targets, vol = _phantom_fit(256, 500_000, cams, gaze)
+        P, vol = _phantom(256, 500_000)
         return Workload(name, "foveal refinement: 256^3 phantom, 500,000 Gaussians (SH0), 16 views "
                               "of 1920x1920, L1 masked to a fovea of radius 0.2 W at a random gaze "
-                              "point per view, ray-marched targets, Adam lr 1e-3",
-                        "synthetic: seeded CT-like phantom, voxel-seeded Gaussians, ray-marched target",
-                        P, cams, targets=targets, gaze=gaze, volume=vol)
+                              "point per view, FP32 ray-marched targets, 300-step regeneration, "
+                              "Adam lr 1e-3",
+                        "synthetic: seeded CT-like phantom, voxel-seeded Gaussians, FP32 ray-marched "
+                        "targets", P, cams, gaze=gaze, volume=vol, device_targets=True)
     if name == "stereo":
         n = 1_000_000
         mu = synth.scaled_logscale_mean(n)
@@ -168,16 +202,33 @@ def render_targets(ctx, wl, dev):
     return torch.cat(out).contiguous()
 
 
-def time_steps(fn, steps, stream):
+def device_marched_targets(ctx, vol_dev, cams):
+    """RGB planes of the FP32 ray march of every view on the device."""
     import torch
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    import paper_2601_22026_amd as gs
+    rgba = gs.raymarch(ctx, vol_dev, cams)
+    out, off = [], 0
+    for c in cams:
+        w, h = c.width, c.height
+        out.append(rgba[4 * off:4 * off + 3 * w * h])
+        off += w * h
+    return torch.cat(out).contiguous()
+
+
+def time_steps(fn, steps, stream):
+    """(mean ms over `steps` back-to-back calls, median ms of one call): an
+    event between consecutive calls, device synchronised before and after."""
+    import torch
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     torch.cuda.synchronize()
-    e0.record(stream)
-    for _ in range(steps):
+    ev[0].record(stream)
+    for k in range(steps):
         fn()
-    e1.record(stream)
+        ev[k + 1].record(stream)
     torch.cuda.synchronize()
-    return e0.elapsed_time(e1) / steps
+    per = sorted(ev[k].elapsed_time(ev[k + 1]) for k in range(steps))
+    return ev[0].elapsed_time(ev[steps]) / steps, per[len(per) // 2]
 
 
 def hbm_bytes_per_launch(stage, N, R, M, npix, planes, tiles):
@@ -223,45 +274,73 @@ def profiled_traffic(workload, kernel, tile, batch):
 
 
 def cpu_baseline(wl, targets_np, budget_s=15.0):
-    """FP64 oracle fit step (render, L1 sign, adjoint, Adam) on a bounded sample
-    of image rows of every view, extrapolated linearly in rows per view."""
+    """FP64 oracle fit step (render, masked L1, adjoint, Adam) timed on a
+    bounded sample of the pixels that carry loss (every pixel, or the fovea's
+    when the loss is masked), spread evenly over each view.  Two sample sizes
+    per view give the oracle's fixed per-view cost (projection and depth sort,
+    once for the render and once for the adjoint) and its cost per pixel; the
+    step is extrapolated to every loss-carrying pixel of every view, plus one
+    dense Adam update."""
     import numpy as np
 
     import oracle
     Pd = wl.P.astype(np.float64)
-    m, v = np.zeros_like(Pd), np.zeros_like(Pd)
     offs = np.cumsum([0] + [c.width * c.height for c in wl.cams])
+    views = wl.cams if wl.views_per_step == 0 else wl.cams[:1]
 
-    def run(rows_per_view):
-        est, used = 0.0, 0
-        G = np.zeros_like(Pd)
-        t_start = time.perf_counter()
-        for k, cam in enumerate(wl.cams):
-            H, W = cam.height, cam.width
-            nrows = min(H, rows_per_view)
-            rows = np.linspace(0, H - 1, nrows).astype(np.int64)
-            pix = (rows[:, None] * W + np.arange(W)[None, :]).reshape(-1)
-            t0 = time.perf_counter()
-            r = oracle.render(Pd, cam, pixels=pix)
-            tgt = targets_np[3 * offs[k]:3 * offs[k + 1]].reshape(3, -1)[:, pix]
-            s, cnt, dl = oracle.loss_l1_view(r.rgba, tgt, type("c", (), {"width": W, "height": nrows})())
-            G += oracle.backward(Pd, cam, dl / max(cnt, 1), pixels=pix)
-            est += (time.perf_counter() - t0) * H / nrows
-            used += nrows
+    def loss_pixels(k, cam):
+        W, H = cam.width, cam.height
+        if wl.gaze is None:
+            return np.arange(W * H)
+        gx, gy = float(wl.gaze[k][0]), float(wl.gaze[k][1])
+        r = 0.2 * W
+        ii, jj = np.meshgrid(np.arange(W) + 0.5, np.arange(H) + 0.5)
+        return np.flatnonzero(((ii - gx) ** 2 + (jj - gy) ** 2 <= r * r).reshape(-1))
+
+    full = [loss_pixels(k, c) for k, c in enumerate(views)]
+
+    def run_view(k, cam, count):
+        pix_all = full[k]
+        pix = pix_all[np.linspace(0, pix_all.size - 1, min(count, pix_all.size)).astype(np.int64)]
         t0 = time.perf_counter()
-        oracle.adam(Pd.copy(), G, m.copy(), v.copy(), 1)
-        est += time.perf_counter() - t0
-        return est, used, time.perf_counter() - t_start
+        r = oracle.render(Pd, cam, pixels=pix)
+        tgt = targets_np[3 * offs[k]:3 * offs[k + 1]].reshape(3, -1)[:, pix]
+        s, cnt, dl = oracle.loss_l1_view(r.rgba, tgt, type("c", (), {"width": pix.size, "height": 1})())
+        oracle.backward(Pd, cam, dl / max(cnt, 1), pixels=pix)
+        return time.perf_counter() - t0, pix.size
 
-    _, _, t_probe = run(2)
-    rows = max(2, int(2 * budget_s / max(t_probe, 1e-3)))
-    full, used, spent = run(rows)
-    tot_rows = sum(c.height for c in wl.cams)
-    return {"value": 1.0 / full, "unit": "fit-steps/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"{used} of {tot_rows} rows over {len(wl.cams)} view(s) of one step, "
-                      f"{spent:.1f} s, extrapolated per view in rows (all {wl.P.shape[1]} Gaussians "
-                      f"per pixel)"}
+    t_start = time.perf_counter()
+    most = max(f.size for f in full)
+    k, prev, cur = 4, None, None
+    while True:
+        t0 = time.perf_counter()
+        cur = (k, [run_view(v, c, k) for v, c in enumerate(views)])
+        took = time.perf_counter() - t0
+        log(f"[bench] oracle sample: {k} px per view in {took:.1f} s")
+        if prev is not None and (took >= budget_s / 3 or k >= most):
+            break
+        prev, k = cur, min(4 * k, most)
+    est, used = 0.0, 0
+    for v in range(len(views)):
+        (t1, n1), (t2, n2) = prev[1][v], cur[1][v]
+        slope = max((t2 - t1) / max(n2 - n1, 1), 0.0)
+        fixed = max(t1 - n1 * slope, 0.0)
+        est += fixed + slope * full[v].size
+        used += n2
+    k1 = prev[0]
+    G = np.zeros_like(Pd)
+    t0 = time.perf_counter()
+    oracle.adam(Pd.copy(), G, np.zeros_like(Pd), np.zeros_like(Pd), 1)
+    est += time.perf_counter() - t0
+    spent = time.perf_counter() - t_start
+    carried = int(sum(f.size for f in full))
+    return {"value": 1.0 / est, "unit": "fit-steps/s", "cores": oracle.num_threads(),
+            "kind": "oracle", "cpu": cpu_model(),
+            "sample": f"{used} of the step's {carried} loss-carrying pixels over {len(views)} "
+                      f"view(s) (plus {k1} per view to split the per-view cost from the per-pixel "
+                      f"cost), {spent:.1f} s, extrapolated to the whole step; all "
+                      f"{wl.P.shape[1]} Gaussians per pixel, no tiles",
+            "s_per_step_extrapolated": round(est, 2)}
 
 
 def bench_reproject(args):
@@ -305,7 +384,7 @@ def bench_reproject(args):
                 warp()
             for _ in range(args.warmup):
                 graph.replay()
-            ms = time_steps(graph.replay, args.steps, stream)
+            ms, _ = time_steps(graph.replay, args.steps, stream)
             landed = int((res["o"][1] >= 0).sum().item())
             # algorithmic bytes: depth and colour in, z-buffer cleared, one 64-bit
             # atomic per landing point, resolve reads the z-buffer and the winner's
@@ -406,13 +485,21 @@ def bench_first_hits(args):
     print(json.dumps(res), flush=True)
 
 
+def check_flags(flags, what):
+    if flags & GSF_FLAG_CAPACITY:
+        raise SystemExit(f"[bench] {what}: key capacity overflowed during timed steps "
+                         f"(flags {flags}); those steps did no fitting, so the timing is void")
+    if flags:
+        raise SystemExit(f"[bench] {what}: device flags {flags} (non-finite loss)")
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="phantom",
-                    choices=["small", "phantom", "batched", "foveal", "stereo", "reproject",
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="foveal",
+                    choices=["foveal", "small", "phantom", "batched", "stereo", "p0", "reproject",
                              "firsthit"])
     ap.add_argument("--tile", type=int, default=16)
     ap.add_argument("--lds-batch", type=int, default=128)
@@ -430,6 +517,7 @@ def main():
                     help="composite full frames even when the loss is masked to a fovea")
     ap.add_argument("--regen-steps", type=int, default=300,
                     help="steps of one regeneration (foveal workload)")
+    ap.add_argument("--regen-runs", type=int, default=3)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 256 MiB device buffer 5 times (reference for HBM byte "
                          "counters) and exit")
@@ -463,34 +551,83 @@ def main():
     import paper_2601_22026_amd as gs
 
     t0 = time.perf_counter()
+    phase(f"building workload {args.workload}")
     wl = build_workload(args.workload)
     P, cams = wl.P, wl.cams
     N, planes, V = P.shape[1], P.shape[0], len(cams)
-    npix = sum(c.width * c.height for c in cams)
-    log(f"[bench] workload {wl.name}: {N} Gaussians, {V} view(s), {npix} px, built in "
+    step_cams = cams if wl.views_per_step == 0 else cams[:1]
+    npix = sum(c.width * c.height for c in step_cams)
+    log(f"[bench] workload {wl.name}: {N} Gaussians, {V} view(s), {npix} px per step, built in "
         f"{time.perf_counter() - t0:.1f} s")
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.Stream(dev)
     # a masked loss lets the fused step composite only the tiles that meet each fovea
+    cull = wl.gaze is not None and not args.no_fovea_cull
     cfg = gs.FitConfig(lr=1e-3, tile=args.tile, lds_batch=args.lds_batch, t_mode=args.t_mode,
-                       fovea_cull=wl.gaze is not None and not args.no_fovea_cull)
+                       fovea_cull=cull)
     with torch.cuda.stream(stream):
         ctx = gs.Context(0)
-        if wl.targets is None:
+        vol_dev = None
+        if wl.volume is not None:
+            vol_dev = torch.from_numpy(np.ascontiguousarray(wl.volume).view(np.int16)).to(dev)
+        if wl.device_targets:
+            phase(f"FP32 ray march of {V} target views on the device")
+            tgt_dev = device_marched_targets(ctx, vol_dev, cams)
+        elif wl.targets is None:
+            phase("rendering the target Gaussian set")
             tgt_dev = render_targets(ctx, wl, dev)
         else:
             tgt_dev = torch.from_numpy(np.ascontiguousarray(wl.targets)).to(dev)
         gaze_dev = None if wl.gaze is None else torch.from_numpy(np.ascontiguousarray(wl.gaze)).to(dev)
         P_dev = torch.from_numpy(np.ascontiguousarray(P)).to(dev)
+        cams_all = gs.cameras_to_device(cams, dev)
+        view_off = np.cumsum([0] + [c.width * c.height for c in cams])
 
-        def fit(c, fused=True):
-            return gs.FitStep(ctx, P_dev.clone(), cams, tgt_dev, gaze_dev, cfg=c, fused=fused)
+        def fit(c, fused=True, params=None):
+            if wl.views_per_step == 0:
+                return gs.FitStep(ctx, (P_dev if params is None else params).clone(), cams,
+                                  tgt_dev, gaze_dev, cfg=c, fused=fused)
+            # one view per step: the step's camera and target are copied into its
+            # buffers before each step, so size the keys for the heaviest view
+            if c.key_capacity == 0:
+                c = dataclasses.replace(c, key_capacity=max_view_keys(c) * 3 // 2 + (1 << 16))
+            return gs.FitStep(ctx, P_dev.clone(), cams[:1],
+                              tgt_dev[:3 * cams[0].width * cams[0].height].clone(), None, cfg=c,
+                              fused=fused)
+
+        def max_view_keys(c):
+            m = 0
+            for k, cam in enumerate(cams):
+                pl = gs.Plan(ctx, N, [(cam.width, cam.height)], 0, c.tile, c.lds_batch,
+                             host_sized=True)
+                out = torch.empty(4 * cam.width * cam.height, dtype=torch.float32, device=dev)
+                pl.forward(P_dev, N, cams_all[128 * k:128 * (k + 1)], out)
+                m = max(m, pl.poll()[1])
+                pl.close()
+            return m
+
+        counter = [0]
+
+        def runner(fs, captured):
+            """The callable of one step: for one view per step, select the next
+            view's camera and target first."""
+            def one():
+                if wl.views_per_step:
+                    k = counter[0] % V
+                    counter[0] += 1
+                    fs.cams_dev.copy_(cams_all[128 * k:128 * (k + 1)], non_blocking=True)
+                    fs.targets.copy_(tgt_dev[3 * view_off[k]:3 * view_off[k + 1]], non_blocking=True)
+                (fs.replay if captured else fs.step)()
+            return one
 
         tune = None
         if not args.no_autotune:
-            best, sweep = gs.autotune(ctx, P_dev, cams, tgt_dev, gaze_dev, cfg=cfg, t_modes=(0, 1),
+            phase("autotune: captured step per tile x LDS batch x transmittance mode")
+            tp, tc, tt = (P_dev, cams, tgt_dev) if wl.views_per_step == 0 else \
+                (P_dev, cams[:1], tgt_dev[:3 * cams[0].width * cams[0].height])
+            best, sweep = gs.autotune(ctx, tp, tc, tt, gaze_dev, cfg=cfg, t_modes=(0, 1),
                                       stream=stream)
             tune = {"best": list(best), "us_per_step": {f"{t}x{b}/t{m}": round(ms * 1e3, 1)
                                                         for (t, b, m), ms in sorted(sweep.items())}}
@@ -499,41 +636,83 @@ def main():
                 f"{tune['us_per_step']}")
 
         # fused, captured: the timed path
+        phase(f"fused captured step: {args.warmup} warm-up + {args.steps} timed replays")
         fused = fit(cfg)
         fused.capture()
+        one = runner(fused, True)
         for _ in range(args.warmup):
-            fused.replay()
-        ms_fused = time_steps(fused.replay, args.steps, stream)
+            one()
+        ms_fused, med_fused = time_steps(one, args.steps, stream)
         flags, M = fused.poll()
+        check_flags(flags, "fused captured step")
         loss_fused = float(fused.loss.item())
-        log(f"[bench] fused+captured: {ms_fused * 1e3:.1f} us/step, keys {M}, flags {flags}, "
-            f"loss {loss_fused:.5f}")
+        log(f"[bench] fused+captured: {ms_fused * 1e3:.1f} us/step (median {med_fused * 1e3:.1f}), "
+            f"keys {M}, flags {flags}, loss {loss_fused:.5f}")
         ws_fused = fused.plan.workspace_bytes
         total_tiles = fused.plan.total_tiles
         fused.plan.close()
         del fused
+
+        fit_run = None
+        if wl.fit_steps:
+            phase(f"one {wl.fit_steps}-step fit, captured, one view per step")
+            fr = fit(cfg)
+            fr.capture()
+            one = runner(fr, True)
+            counter[0] = 0
+            torch.cuda.synchronize()
+            t_fit = time.perf_counter()
+            for _ in range(wl.fit_steps):
+                one()
+            torch.cuda.synchronize()
+            ms_fit = (time.perf_counter() - t_fit) * 1e3
+            flags, _ = fr.poll()
+            check_flags(flags, "fit")
+            fit_run = {"steps": wl.fit_steps, "ms_per_fit": round(ms_fit, 2),
+                       "ms_per_step": round(ms_fit / wl.fit_steps, 4),
+                       "loss_after_fit": round(float(fr.loss.item()), 6),
+                       "paper_context": "about 0.85 s for 700 iterations at 512^2 on an RTX 4090 "
+                                        "(about 1.2 ms per iteration; context only)"}
+            fr.plan.close()
+            del fr
+            log(f"[bench] {wl.fit_steps}-step fit: {ms_fit:.1f} ms")
+
+        culled_gain = None
+        if cull:
+            phase("fused captured step over full frames (no fovea culling), for the culling gain")
+            fu = fit(dataclasses.replace(cfg, fovea_cull=False))
+            fu.capture()
+            for _ in range(args.warmup):
+                fu.replay()
+            ms_full, _ = time_steps(fu.replay, args.steps, stream)
+            check_flags(fu.poll()[0], "full-frame step")
+            fu.plan.close()
+            del fu
+            culled_gain = {"full_frame_ms_per_step": round(ms_full, 4),
+                           "culling_speedup": round(ms_full / ms_fused, 3)}
+            log(f"[bench] fused full-frame: {ms_full * 1e3:.1f} us/step")
 
         regen = None
         if wl.name == "foveal":
             # one regeneration: seed the Gaussians on the device from the resident
             # volume, plan, capture, run the steps - wall clock, synchronised
             import synth
-            vol_dev = torch.from_numpy(np.ascontiguousarray(wl.volume).view(np.int16)).to(dev)
-            runs, seeds = [], []
-            for _ in range(3):
+            runs, seeds, replans = [], [], 0
+            same = None
+            for k in range(args.regen_runs):
+                phase(f"regeneration {k + 1}/{args.regen_runs} ({args.regen_steps} steps)")
                 torch.cuda.synchronize()
                 t_start = time.perf_counter()
                 Ps = gs.seed_volume(ctx, vol_dev, cap=N, seed=synth.SEED_CAP_SUBSET)
                 t_seeded = time.perf_counter()
-                if not runs:   # the device seeding reproduces the workload's Gaussians
-                    same = bool(torch.equal(Ps.cpu(), torch.from_numpy(P)))
                 rf = gs.FitStep(ctx, Ps, cams, tgt_dev, gaze_dev, cfg=cfg, fused=True)
                 rf.capture()
-                for _ in range(args.regen_steps):
-                    rf.replay()
+                replans += rf.run(args.regen_steps)
                 torch.cuda.synchronize()
                 runs.append((time.perf_counter() - t_start) * 1e3)
                 seeds.append((t_seeded - t_start) * 1e3)
+                if same is None:   # the device seeding reproduces the workload's Gaussians
+                    same = bool(torch.equal(Ps.cpu(), torch.from_numpy(P)))
                 rf.plan.close()
                 del rf
             # the targets' ray march on the device, reported apart (S24)
@@ -545,23 +724,29 @@ def main():
                 e1.record(stream)
                 e1.synchronize()
                 march.append(e0.elapsed_time(e1))
-            regen = {"ms_per_regeneration": round(sorted(runs)[1], 2), "steps": args.regen_steps,
-                     "runs_ms": [round(r, 2) for r in runs],
-                     "seeding_ms": round(sorted(seeds)[1], 2),
+            regen = {"ms_per_regeneration": round(sorted(runs)[len(runs) // 2], 2),
+                     "steps": args.regen_steps, "runs_ms": [round(r, 2) for r in runs],
+                     "seeding_ms": round(sorted(seeds)[len(seeds) // 2], 2),
+                     "key_replans": replans,
                      "seeded_on_device_equals_workload": same,
                      "target_raymarch_ms": round(sorted(march)[1], 2),
                      "includes": "seeding from the device-resident volume, plan creation, graph "
-                                 "capture and the captured fit steps (the targets' ray march is "
-                                 "timed apart)"}
+                                 "capture and the captured fit steps, with a flag poll every 100 "
+                                 "steps (the targets' ray march is timed apart)",
+                     "paper_context": "full peripheral-model regeneration in about 1.0 s on an RTX "
+                                      "4090, including path tracing the views (context only)"}
             log(f"[bench] regeneration ({args.regen_steps} steps): {regen['ms_per_regeneration']} ms "
-                f"(seeding {regen['seeding_ms']} ms, same Gaussians as the workload: {same}); "
-                f"target ray march {regen['target_raymarch_ms']} ms")
+                f"(seeding {regen['seeding_ms']} ms, same Gaussians as the workload: {same}, "
+                f"key re-plans {replans}); target ray march {regen['target_raymarch_ms']} ms")
 
         # fused, eager (same plan shape, no graph)
+        phase("fused eager step")
         eager = fit(cfg)
+        one = runner(eager, False)
         for _ in range(args.warmup):
-            eager.step()
-        ms_eager = time_steps(eager.step, args.steps, stream)
+            one()
+        ms_eager, _ = time_steps(one, args.steps, stream)
+        check_flags(eager.poll()[0], "eager step")
         eager.plan.close()
         del eager
         log(f"[bench] fused eager: {ms_eager * 1e3:.1f} us/step")
@@ -569,12 +754,15 @@ def main():
         # per-stage kernel times: a fresh eager fused step taken through the same
         # step indices as the timed replays (W warm-up, then K), with HIP events
         # recorded by the library around each stage on the stream it launches on
+        phase("per-stage kernel times (eager, library HIP events)")
         staged = fit(cfg)
+        one = runner(staged, False)
+        counter[0] = 0
         for _ in range(args.warmup):
-            staged.step()
+            one()
         staged.plan.set_timing(True)
         for _ in range(args.steps):
-            staged.step()
+            one()
         st = staged.plan.stage_times()
         staged.plan.set_timing(False)
         staged.plan.close()
@@ -582,12 +770,15 @@ def main():
         stages = {k: (ms / max(c, 1)) for k, (ms, c) in st.items() if c}
         log("[bench] stage us/launch: " + ", ".join(f"{k} {v * 1e3:.1f}" for k, v in stages.items()))
         # pair counts of the same K steps (a separate run: counting synchronises)
+        phase("pair counts of the same steps")
         counted = fit(cfg)
+        one = runner(counted, False)
+        counter[0] = 0
         for _ in range(args.warmup):
-            counted.step()
+            one()
         pairs = {}
         for _ in range(args.steps):
-            counted.step()
+            one()
             for k, v in counted.plan.count_pairs().items():
                 pairs[k] = pairs.get(k, 0) + v / args.steps
         counted.plan.close()
@@ -595,15 +786,17 @@ def main():
         pairs = {k: int(round(v)) for k, v in pairs.items()}
         log(f"[bench] pairs per step (mean of the K steps): {pairs}")
 
-        # plain path: one host-synchronised plan per view, eager, full frames
+        # plain path: one host-synchronised plan per view, eager
         ms_plain = None
         if not args.no_plain:
+            phase("plain step (one host-synchronised plan per view, eager)")
             plain = fit(cfg, fused=False)
+            one = runner(plain, False)
+            counter[0] = 0
             for _ in range(args.warmup):
-                plain.step()
-            ms_plain = time_steps(plain.step, args.steps, stream)
-            for p, _, _ in plain.view_plans:
-                p.close()
+                one()
+            ms_plain, _ = time_steps(one, args.steps, stream)
+            plain.close()
             del plain
             log(f"[bench] plain: {ms_plain * 1e3:.1f} us/step")
 
@@ -612,6 +805,7 @@ def main():
         if args.compare_t_modes or wl.name == "stereo":
             modes = {}
             for m, label in enumerate(["recompute", "checkpointed", "stored"]):
+                phase(f"transmittance mode {label}")
                 torch.cuda.synchronize()
                 torch.cuda.empty_cache()
                 torch.cuda.reset_peak_memory_stats(dev)
@@ -620,7 +814,8 @@ def main():
                 fm.capture()
                 for _ in range(args.warmup):
                     fm.replay()
-                ms_m = time_steps(fm.replay, args.steps, stream)
+                ms_m, _ = time_steps(fm.replay, args.steps, stream)
+                check_flags(fm.poll()[0], f"t_mode {m}")
                 peak = torch.cuda.max_memory_allocated(dev)
                 modes[label] = {"ms_per_step": round(ms_m, 4),
                                 "workspace_bytes": fm.plan.workspace_bytes,
@@ -629,10 +824,11 @@ def main():
                 del fm
                 log(f"[bench] t_mode {m} ({label}): {ms_m * 1e3:.1f} us/step, workspace "
                     f"{modes[label]['workspace_bytes'] / 2**30:.2f} GiB")
+        tgt_np = tgt_dev.detach().cpu().numpy() if not args.no_cpu_baseline else None
     torch.cuda.synchronize()
 
     # roofline of the dominant kernel
-    R = N * V
+    R = N * len(step_cams)
     dom = max(stages, key=stages.get)
     traffic = profiled_traffic(wl.name, dom, cfg.tile, cfg.lds_batch)
     if dom in ("render", "render_bwd"):
@@ -643,12 +839,16 @@ def main():
         ach = flops / (stages[dom] * 1e-3) / 1e12
         roof = {"kernel": dom, "bound": "alu", "achieved": round(ach, 3), "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
+                "peak_nonpacked": PEAK_FP32_NONPACKED_TFLOPS,
+                "frac_of_nonpacked": round(ach / PEAK_FP32_NONPACKED_TFLOPS, 4),
+                "us_per_launch": round(stages[dom] * 1e3, 2),
                 "work": {"flops_per_launch": int(flops), **pairs}}
     else:
         byt = hbm_bytes_per_launch(dom, N, R, M, npix, planes, total_tiles)
         ach = byt / (stages[dom] * 1e-3) / 1e9
         roof = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS,
-                "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": traffic}
+                "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": traffic,
+                "us_per_launch": round(stages[dom] * 1e3, 2)}
     stage_roof = {}
     for k, ms in stages.items():
         byt = hbm_bytes_per_launch(k, N, R, M, npix, planes, total_tiles)
@@ -675,13 +875,15 @@ def main():
         "dtype": "f32",
         "data": wl.data,
         "config": {"workload": wl.description, "name": wl.name, "gaussians": N, "views": V,
-                   "sizes": [[c.width, c.height] for c in cams], "pixels": npix,
+                   "views_per_step": len(step_cams),
+                   "sizes": [[c.width, c.height] for c in cams], "pixels_per_step": npix,
                    "sh_degree": int(round(((planes - 11) // 3) ** 0.5)) - 1,
                    "tile": cfg.tile, "lds_batch": cfg.lds_batch, "t_mode": cfg.t_mode,
                    "fovea_cull": bool(cfg.fovea_cull),
                    "keys_per_step": M, "form": "fused, hipGraph-captured"},
+        "median_step_ms": round(med_fused, 4),
+        "flags_after_timed_steps": flags,
         "mpix_per_s": round(npix * steps_per_s / 1e6, 1),
-        "ms_per_100_step_fit": round(100 * ms_fused, 2),
         "eager_fused_steps_per_s": round(1000.0 / ms_eager, 2),
         "plain_steps_per_s": round(1000.0 / ms_plain, 2) if ms_plain else None,
         "vs_plain": round(ms_plain / ms_fused, 3) if ms_plain else None,
@@ -695,12 +897,19 @@ def main():
         "roofline": roof,
     }
     if regen:
+        res["ms_per_regeneration"] = regen["ms_per_regeneration"]
         res["regeneration"] = regen
+    if fit_run:
+        res["fit"] = fit_run
+    if culled_gain:
+        res["fovea_culling"] = culled_gain
     if modes:
         res["transmittance_modes"] = modes
     if not args.no_cpu_baseline:
-        log("[bench] CPU oracle baseline ...")
-        res["cpu_baseline"] = cpu_baseline(wl, tgt_dev.detach().cpu().numpy())
+        phase("FP64 CPU oracle baseline on a bounded sample")
+        res["cpu_baseline"] = cpu_baseline(wl, tgt_np)
+        log(f"[bench] CPU oracle: {res['cpu_baseline']['value']:.3g} fit-steps/s on "
+            f"{res['cpu_baseline']['cores']} threads")
     else:
         res["cpu_baseline"] = None
     print(json.dumps(res), flush=True)

@@ -461,6 +461,39 @@ class FitStep:
         self.ctx.use_stream()
         self.ctx.check(lib().gsf_step_replay(self.plan.handle), "gsf_step_replay")
 
+    def steps_done(self) -> int:
+        """The device step counter (synchronises): steps that updated the model
+        since the last optimiser reset."""
+        return int(self.step_dev.item())
+
+    def run(self, steps: int, check_every: int = 100) -> int:
+        """Replay the captured step until ``steps`` steps have updated the model.
+        The device flags are polled every ``check_every`` replays (one
+        synchronisation each).  A step that overflows the key capacity changes
+        nothing (parameters, moments and step counter stay), so after an
+        overflow the plan is re-made with room (``ensure_capacity``) and the
+        missing steps are replayed.  Returns the number of re-plans."""
+        if not self.captured:
+            raise GsfError(_abi.GSF_E_STATE, "capture() first")
+        target = self.steps_done() + int(steps)
+        replans = 0
+        while True:
+            left = target - self.steps_done()
+            if left <= 0:
+                return replans
+            for _ in range(min(left, max(1, int(check_every)))):
+                self.replay()
+            if self.ensure_capacity():
+                replans += 1
+
+    def close(self):
+        """Release the plans (and their workspaces)."""
+        if self.fused:
+            self.plan.close()
+        else:
+            for p, _, _ in self.view_plans:
+                p.close()
+
     def backgrounds(self):
         """The per-view backgrounds [V][3] drawn by the last random_bg step."""
         if not (self.fused and self.cfg.random_bg):
@@ -557,10 +590,11 @@ class Refiner:
         return self.fit
 
     def run(self, steps: int):
+        """``steps`` captured fit steps that update the model (a step lost to a
+        key overflow is repeated after a re-plan, see FitStep.run)."""
         if self.fit is None:
             raise GsfError(_abi.GSF_E_STATE, "restart() first")
-        for _ in range(int(steps)):
-            self.fit.replay()
+        return self.fit.run(steps)
 
 
 def seed_first_hits(ctx: Context, vol: torch.Tensor, cams, cap: int, seed: int, step: float,
@@ -701,7 +735,8 @@ def autotune(ctx: Context, params: torch.Tensor, cams, targets: torch.Tensor,
     import dataclasses
     t_modes = tuple(t_modes) if t_modes is not None else (cfg.t_mode,)
     key = (params.shape[1], params.shape[0], tuple((c.width, c.height) for c in cams),
-           tuple(tiles), tuple(batches), t_modes)
+           tuple(tiles), tuple(batches), t_modes, bool(cfg.fovea_cull), bool(cfg.alpha_loss),
+           bool(cfg.random_bg), bool(cfg.masked_adam), gaze is not None, float(cfg.radius_frac))
     if key in _TUNE_CACHE:
         return _TUNE_CACHE[key]
     stream = stream or torch.cuda.current_stream()

@@ -8,7 +8,6 @@ into paper_2601_22026_amd/libgsfit.so.  Flags:
                        template instantiation of the compositing loop does the
                        same float operations (images are bitwise independent of
                        the tile and batch sizes)
-  -munsafe-fp-atomics  hardware float atomics for gradient accumulation
   -packed-fp32-ops off no packed FP32 instructions
 """
 from __future__ import annotations
@@ -29,7 +28,7 @@ ARCH = os.environ.get("GSF_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 CFLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=off",
-          "-munsafe-fp-atomics", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wall", "-Wno-unused-function", "-I", INCLUDE, "-I", CSRC]
 
 
