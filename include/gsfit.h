@@ -146,30 +146,68 @@ gsf_status gsf_plan_destroy(gsf_plan *plan);
 
 /* ---- the fit step --------------------------------------------------------------- */
 
-/* Render all views of the plan.  params: [C][n] (1 <= n <= n_max); cams:
- * [n_views]; out_rgba: concatenated per-view [4][H][W].  With host_sized = 1
- * this synchronises the stream once and returns GSF_E_CAPACITY if the key count
- * exceeded the capacity (the image is then background only). */
+/* Render all views of the plan: the 3D Gaussian Splatting image formation the
+ * paper's fit adopts (Related Work, "Novel View Synthesis"; Method, "Periphery
+ * Model Training": Mini-Splatting2 with the rasterization of Taming 3DGS) -
+ * each Gaussian projected to a screen-space conic (EWA splatting: local affine
+ * approximation of the perspective map, 0.3 px^2 low-pass), listed in the
+ * tiles its opacity-aware support ellipse reaches, sorted by (tile, depth), and
+ * composited front to back per pixel (alpha = min(0.99, o e^power), skipped
+ * below 1/255, stopping before transmittance falls under 1e-4; RGB = C + T bg,
+ * A = 1 - T).  params: [C][n] (1 <= n <= n_max); cams: [n_views]; out_rgba:
+ * concatenated per-view [4][H][W] (caller-owned).  cull_gaze_px: nullable device
+ * [n_views][2]; when given (with cull_radius_frac in [0, 4]), only the tiles that
+ * meet each view's fovea box (the pixels whose centre can lie within
+ * cull_radius_frac * width of the gaze point, plus one pixel) are composited and
+ * out_rgba elsewhere is left as it was; a later gsf_loss_l1 with the same gaze
+ * then reads only those tiles.  With host_sized = 1 this synchronises the
+ * stream once and returns GSF_E_CAPACITY if the key count exceeded the capacity
+ * (the image is then background only).  GSF_E_INVALID for null pointers, n out
+ * of range or a bad radius; GSF_E_STATE without a workspace. */
 gsf_status gsf_forward(gsf_plan *plan, const float *params, int64_t n, const gsf_camera *cams,
-                       float *out_rgba);
+                       const float *cull_gaze_px, float cull_radius_frac, float *out_rgba);
 
-/* Mean absolute error over the masked (view, pixel, RGB channel) entries of
- * `rgba` against `target_rgb` (concatenated per-view [3][H][W]).  gaze_px:
- * nullable device [n_views][2] pixel coordinates; when given, only pixels whose
- * centre lies within mask_radius_frac * width of the gaze point count.  Writes
- * the loss to loss[0] (device) and dL/dRGBA (sign / count; alpha plane zero) to
- * dl_drgba (concatenated per-view [4][H][W]).  A non-finite loss sets
- * GSF_FLAG_NONFINITE. */
+/* The fit's image loss (Method, "Periphery Model Training": the model is
+ * optimised against the rendered training views; L1 on colour, the 3DGS
+ * photometric term; the fovea mask restricts a foveated view to the region it
+ * renders): the mean absolute error over the masked (view, pixel, RGB channel)
+ * entries of `rgba` against `target_rgb` (concatenated per-view [3][H][W]).
+ * gaze_px: nullable device [n_views][2] pixel coordinates; when given, only
+ * pixels whose centre lies within mask_radius_frac * width of the gaze point
+ * count.  norm_count: 0 = divide by this plan's own masked entry count; > 0 =
+ * divide by it instead (the entry count over every plan of a loss split across
+ * plans, e.g. one plan per view; see gsf_loss_count).  accumulate: 0 = loss[0]
+ * = this plan's mean, 1 = loss[0] += it.  Writes the loss to loss[0] (device)
+ * and dL/dRGBA (sign / count; alpha plane zero) to dl_drgba (concatenated
+ * per-view [4][H][W]).  A non-finite loss sets GSF_FLAG_NONFINITE.
+ * GSF_E_INVALID for null pointers, a bad radius, norm_count outside
+ * [0, 2^32 - 1] or accumulate not 0/1. */
 gsf_status gsf_loss_l1(gsf_plan *plan, const float *rgba, const float *target_rgb,
-                       const float *gaze_px, float mask_radius_frac, float *loss,
-                       float *dl_drgba);
+                       const float *gaze_px, float mask_radius_frac, int64_t norm_count,
+                       int32_t accumulate, float *loss, float *dl_drgba);
 
-/* Gradient of the loss w.r.t. the parameters given dL/dRGBA of the last
- * gsf_forward on this plan (same params, n and cams).  grads: [C][n], overwritten. */
+/* Number of entries gsf_loss_l1 averages over on this plan (host *count): 3 x
+ * pixels without a gaze, else 3 x the pixels inside the fovea masks.
+ * Synchronises the context stream. */
+gsf_status gsf_loss_count(gsf_plan *plan, const float *gaze_px, float mask_radius_frac,
+                          int64_t *count);
+
+/* Gradient of the loss w.r.t. the parameters (the adjoint of gsf_forward, which
+ * the fit's gradient-based optimisation needs; Method, "Periphery Model
+ * Training") given dL/dRGBA of the last gsf_forward on this plan (same params,
+ * n and cams): back to front through the compositing, then through the conic
+ * projection to mean, log-scale, rotation, opacity logit and SH colour, summed
+ * over the plan's views.  grads: [C][n]; accumulate = 0 overwrites it, 1 adds
+ * to it (a gradient summed over several plans).  GSF_E_STATE before a forward;
+ * GSF_E_INVALID for null pointers, n differing from the forward's or
+ * accumulate not 0/1. */
 gsf_status gsf_backward(gsf_plan *plan, const float *params, int64_t n, const gsf_camera *cams,
-                        const float *dl_drgba, float *grads);
+                        const float *dl_drgba, int32_t accumulate, float *grads);
 
-/* One Adam step on n_elems float32 elements: m <- b1 m + (1-b1) g,
+/* The fit's optimiser (Method, "Periphery Model Training": the Mini-Splatting2
+ * / 3DGS optimisation, Adam; per-group learning rates, which the paper raises
+ * by about 50 % for scale, opacity and colour).
+ * One Adam step on n_elems float32 elements: m <- b1 m + (1-b1) g,
  * v <- b2 v + (1-b2) g^2, p <- p - lr m_hat / (sqrt(v_hat) + eps), with bias
  * correction by the step number held in step_dev[0] (device int32), which this
  * call increments first.  Element e uses seg_lr[s] for seg_off[s] <= e <
@@ -304,6 +342,53 @@ typedef struct gsf_step_args {
 gsf_status gsf_loss_l1_rgba(gsf_plan *plan, const float *rgba, const float *target_rgba,
                             const float *bg, int32_t alpha, const float *gaze_px,
                             float mask_radius_frac, float *loss, float *dl_drgba);
+
+/* ---- tile size and LDS batch by measurement ----------------------------------------- */
+
+/* The candidates of gsf_autotune.  80 bytes. */
+typedef struct gsf_tune_space {
+    int32_t n_tiles;            /* 1 .. 3 */
+    int32_t tiles[3];           /* each 8, 16 or 32 */
+    int64_t key_capacity[3];    /* key capacity of the plans of tiles[k] (0: the plan default) */
+    int32_t n_batches;          /* 1 .. 3 */
+    int32_t batches[3];         /* each 64, 128 or 256 */
+    int32_t n_t_modes;          /* 1 .. 3 */
+    int32_t t_modes[3];         /* each 0, 1 or 2 (gsf_plan_desc.t_mode) */
+    int32_t warmup;             /* untimed replays per candidate (>= 0) */
+    int32_t reps;               /* timed replays per candidate (>= 1) */
+} gsf_tune_space;
+
+/* 120 bytes. */
+typedef struct gsf_tune_result {
+    int32_t tile, lds_batch, t_mode;   /* the fastest candidate */
+    float ms[27];                      /* ms per step of candidate (tiles[k], batches[j],
+                                          t_modes[m]) at [9 k + 3 j + m]; -1 outside the
+                                          space; +inf when its keys overflowed */
+} gsf_tune_result;
+
+/* Device workspace (bytes, host) gsf_autotune needs: the largest candidate
+ * plan plus 256 bytes. */
+gsf_status gsf_autotune_workspace_bytes(gsf_ctx *ctx, const gsf_plan_desc *base,
+                                        const gsf_tune_space *space, size_t *bytes);
+/* Pick the tile size, LDS batch and adjoint transmittance mode that make the
+ * captured fused step fastest on this input (the fused, captured form of the
+ * fit step: one launch per stage over every view).  For every candidate a plan
+ * is made from `base` (n_max, SH degree, views) with that tile, batch, mode and
+ * the tile's key capacity, device-sized, bound to `workspace` (caller-owned,
+ * 256-byte aligned, gsf_autotune_workspace_bytes long); the forward, loss and
+ * backward of `args` (with its options: fovea culling, alpha loss, random
+ * backgrounds) are captured in a HIP graph, replayed `warmup` times, then timed
+ * with HIP events over `reps` replays on the context stream.  Adam is left
+ * out, its time does not depend on the candidate, so params, adam_m, adam_v
+ * and *step_dev are not touched (a private step counter drives the loss and
+ * the backgrounds); rgba, dl_drgba, grads and loss are overwritten.  A
+ * candidate whose keys overflow its capacity is timed +inf.  Writes *out
+ * (host).  Synchronises the stream.  GSF_E_INVALID for a bad space, null
+ * pointers or a short workspace; GSF_E_STATE on the null stream (graphs cannot
+ * be captured there); GSF_E_CAPACITY when every candidate overflowed. */
+gsf_status gsf_autotune(gsf_ctx *ctx, const gsf_plan_desc *base, const gsf_tune_space *space,
+                        const gsf_step_args *args, void *workspace, size_t bytes,
+                        gsf_tune_result *out);
 
 /* Enqueue one step eagerly.  With host_sized = 0 the key count stays on the
  * device: if it exceeds the plan's capacity the step sets GSF_FLAG_CAPACITY

@@ -78,9 +78,6 @@ static const double LOWPASS = 0.3;
 static const double JCLAMP = 1.3;
 static const double BOX_REL = 1e-4;
 static const double BOX_ABS = 1.0 / 64.0;
-/* boxes of at most this many tile rows list only the tiles their support
- * ellipse reaches in each row; taller boxes list every tile of the box */
-#define SPAN_ROWS 32
 
 static int n_coeffs(int deg) { return (deg + 1) * (deg + 1); }
 
@@ -767,20 +764,9 @@ int orc_discrete(const double *P, int64_t n, int deg, const double *cams, int nv
                 int64_t x0, x1, y0, y1;
                 if (tile_rect(r[R_EX0], r[R_EX1], W, tile, &x0, &x1)
                     && tile_rect(r[R_EY0], r[R_EY1], H, tile, &y0, &y1)) {
-                    const int spans = y1 - y0 + 1 <= SPAN_ROWS;   /* else the whole box */
                     for (int64_t ty = y0; ty <= y1; ty++) {
                         /* the tiles of this row the support ellipse reaches */
                         int64_t s0 = x0, s1 = x1, p0, p1, q0, q1;
-                        if (!spans) {
-                            for (int64_t tx = s0; tx <= s1; tx++) {
-                                if (count == alloc) { alloc *= 2; list = realloc(list, sizeof(tkey) * alloc); }
-                                list[count].tile = total_tiles + ty * tw + tx;
-                                list[count].dbits = f32bits(r[R_TZ]);
-                                list[count].rec = (int64_t)v * n + i;
-                                count++;
-                            }
-                            continue;
-                        }
                         const double m = 2e-4 + 4e-6 * (fabs(r[R_MX]) + fabs(r[R_EX1] - r[R_EX0]));
                         const int in = row_span(r, ty, tile, W, H, x0, x1, 0.0, &s0, &s1);
                         const int out = row_span(r, ty, tile, W, H, x0, x1, m, &p0, &p1);

@@ -137,15 +137,30 @@ class Plan:
         self.total_tiles, self.total_pixels = tt.value, tp.value
 
     # -- raw calls (tensors in, status checked) ------------------------------------
-    def forward(self, params, n, cams_dev, out_rgba):
+    def forward(self, params, n, cams_dev, out_rgba, cull_gaze=None, cull_radius_frac=0.0):
+        """gsf_forward; with cull_gaze ([V][2] device) only the tiles meeting each
+        view's fovea are composited."""
         self.ctx.use_stream()
         self.ctx.check(lib().gsf_forward(self.handle, _ptr(params), int(n), _ptr(cams_dev),
-                                         _ptr(out_rgba)), "gsf_forward")
+                                         _ptr(cull_gaze), float(cull_radius_frac), _ptr(out_rgba)),
+                       "gsf_forward")
 
-    def loss_l1(self, rgba, target, loss, dl, gaze=None, radius_frac=0.0):
+    def loss_l1(self, rgba, target, loss, dl, gaze=None, radius_frac=0.0, norm_count=0,
+                accumulate=False):
+        """gsf_loss_l1; norm_count > 0 divides by that entry count (a loss split
+        over several plans), accumulate adds this plan's share to loss[0]."""
         self.ctx.use_stream()
         self.ctx.check(lib().gsf_loss_l1(self.handle, _ptr(rgba), _ptr(target), _ptr(gaze),
-                                         float(radius_frac), _ptr(loss), _ptr(dl)), "gsf_loss_l1")
+                                         float(radius_frac), int(norm_count), int(bool(accumulate)),
+                                         _ptr(loss), _ptr(dl)), "gsf_loss_l1")
+
+    def loss_count(self, gaze=None, radius_frac=0.0) -> int:
+        """gsf_loss_count: the entries gsf_loss_l1 averages over (synchronises)."""
+        c = ct.c_int64()
+        self.ctx.use_stream()
+        self.ctx.check(lib().gsf_loss_count(self.handle, _ptr(gaze), float(radius_frac),
+                                            ct.byref(c)), "gsf_loss_count")
+        return int(c.value)
 
     def loss_l1_rgba(self, rgba, target_rgba, loss, dl, bg=None, alpha=True, gaze=None,
                      radius_frac=0.0):
@@ -156,10 +171,12 @@ class Plan:
                                               int(bool(alpha)), _ptr(gaze), float(radius_frac),
                                               _ptr(loss), _ptr(dl)), "gsf_loss_l1_rgba")
 
-    def backward(self, params, n, cams_dev, dl, grads):
+    def backward(self, params, n, cams_dev, dl, grads, accumulate=False):
+        """gsf_backward; accumulate adds to grads instead of overwriting them."""
         self.ctx.use_stream()
         self.ctx.check(lib().gsf_backward(self.handle, _ptr(params), int(n), _ptr(cams_dev),
-                                          _ptr(dl), _ptr(grads)), "gsf_backward")
+                                          _ptr(dl), int(bool(accumulate)), _ptr(grads)),
+                       "gsf_backward")
 
     def poll(self):
         f, m = ct.c_uint32(), ct.c_int64()
@@ -324,9 +341,10 @@ class FitStep:
     on the device, checkpointed transmittance (cfg.t_mode), and ``capture()``
     records the whole step in a HIP graph that ``replay()`` launches.
     fused=False: the plain path - one host-synchronised plan per view (same
-    tile, LDS batch and transmittance mode), eager launches, views one after
-    another (the loss of each view is normalised by that view's own masked
-    count).
+    tile, LDS batch, transmittance mode and fovea culling), eager launches,
+    views one after another; the library normalises each view's L1 by the
+    entry count over all views and adds the views' losses and gradients, so
+    the step optimises the same objective as the fused one.
     """
 
     def __init__(self, ctx: Context, params: torch.Tensor, cams, targets: torch.Tensor,
@@ -369,8 +387,18 @@ class FitStep:
                 sl = slice(off, off + w * h)
                 self.view_plans.append((p, self.cams_dev[128 * k:128 * (k + 1)], sl))
                 off += w * h
-            self.view_grads = torch.zeros_like(params)
+            # the fused step's normaliser: masked entries over all views
+            self.norm_count = sum(
+                p.loss_count(self._view_gaze(k), cfg.radius_frac)
+                for k, (p, _, _) in enumerate(self.view_plans))
         self.captured = False
+
+    def _view_gaze(self, k):
+        return self.gaze[k] if self.gaze is not None else None
+
+    @property
+    def culls(self) -> bool:
+        return bool(self.cfg.fovea_cull and self.gaze is not None)
 
     def _make_plan(self):
         self.plan = Plan(self.ctx, self.n, self.sizes, self.sh_degree, self.cfg.tile,
@@ -400,12 +428,9 @@ class FitStep:
         return True
 
     def _measure_capacity(self) -> int:
-        probe = Plan(self.ctx, self.n, self.sizes, self.sh_degree, self.cfg.tile,
-                     self.cfg.lds_batch, host_sized=True, key_capacity=self.cfg.key_capacity)
-        probe.forward(self.params, self.n, self.cams_dev, self.rgba)
-        _, m = probe.poll()
-        probe.close()
-        return int(m * 1.5) + (1 << 16)
+        return measure_keys(self.ctx, self.params, self.cams_dev, self.sizes, self.sh_degree,
+                            self.cfg.tile, self.gaze if self.culls else None,
+                            self.cfg.radius_frac) * 3 // 2 + (1 << 16)
 
     def _args(self, plan, cams_dev, targets, rgba, dl, gaze):
         return gsf_step_args(
@@ -427,17 +452,18 @@ class FitStep:
         if self.fused:
             self.ctx.check(lib().gsf_step(self.plan.handle, ct.byref(self.args)), "gsf_step")
             return
-        # plain: per view forward + loss + backward, gradients summed, then Adam
+        # plain: per view forward + loss share + backward, the library adding the
+        # views' losses and gradients, then Adam
         for k, (p, cam, sl) in enumerate(self.view_plans):
             rgba = self.rgba[4 * sl.start:4 * sl.stop]
             dl = self.dl[4 * sl.start:4 * sl.stop]
             tgt = self.targets[3 * sl.start:3 * sl.stop]
-            gz = self.gaze[k] if self.gaze is not None else None
-            p.forward(self.params, self.n, cam, rgba)
-            p.loss_l1(rgba, tgt, self.loss, dl, gz, self.cfg.radius_frac)
-            p.backward(self.params, self.n, cam, dl, self.grads if k == 0 else self.view_grads)
-            if k > 0:
-                self.grads += self.view_grads
+            gz = self._view_gaze(k)
+            p.forward(self.params, self.n, cam, rgba, gz if self.culls else None,
+                      self.cfg.radius_frac)
+            p.loss_l1(rgba, tgt, self.loss, dl, gz, self.cfg.radius_frac,
+                      norm_count=self.norm_count, accumulate=k > 0)
+            p.backward(self.params, self.n, cam, dl, self.grads, accumulate=k > 0)
         seg_off = [c * self.n for c in range(self.C + 1)]
         lr = list(self._seg_lr)
         so, sl_ = [0], [lr[0]]
@@ -718,6 +744,19 @@ def raymarch(ctx: Context, vol: torch.Tensor, cams, step: Optional[float] = None
     return out
 
 
+def measure_keys(ctx: Context, params: torch.Tensor, cams_dev: torch.Tensor, sizes, sh_degree: int,
+                 tile: int, cull_gaze: Optional[torch.Tensor] = None, radius_frac: float = 0.0) -> int:
+    """Keys one forward of these Gaussians lists at this tile size (a host-sized
+    plan; fovea-culled when cull_gaze is given).  Synchronises."""
+    n = params.shape[1]
+    probe = Plan(ctx, n, sizes, sh_degree, tile, 64, host_sized=True)
+    out = torch.empty(4 * probe.total_pixels, dtype=torch.float32, device=params.device)
+    probe.forward(params, n, cams_dev, out, cull_gaze, radius_frac)
+    _, m = probe.poll()
+    probe.close()
+    return int(m)
+
+
 _TUNE_CACHE: dict = {}
 
 
@@ -725,14 +764,14 @@ def autotune(ctx: Context, params: torch.Tensor, cams, targets: torch.Tensor,
              gaze: Optional[torch.Tensor] = None, cfg: FitConfig = FitConfig(),
              tiles=(8, 16, 32), batches=(64, 128, 256), t_modes=None, warmup: int = 3,
              reps: int = 10, stream=None):
-    """Pick the tile size, LDS batch and (optionally) adjoint transmittance mode
-    that make the captured fused step fastest on this input shape.  Each
-    candidate is captured once and timed with HIP events over ``reps`` replays
-    (Adam disabled so every candidate sees the same parameters).  ``t_modes``
-    defaults to ``(cfg.t_mode,)``.  Results are cached per (n, SH degree, view
-    sizes, candidates).  Returns (best (tile, batch, t_mode),
-    {(tile, batch, t_mode): ms/step})."""
-    import dataclasses
+    """gsf_autotune: the tile size, LDS batch and adjoint transmittance mode that
+    make the captured fused step fastest on this input.  Each tile size's key
+    capacity is 1.5 times the keys one forward lists there.  The library times
+    every candidate's captured forward + loss + backward with HIP events over
+    ``reps`` replays (Adam left out, so params are not changed).  ``t_modes``
+    defaults to ``(cfg.t_mode,)``.  Results are cached per input shape and step
+    options.  Returns (best (tile, batch, t_mode), {(tile, batch, t_mode):
+    ms/step}); overflowing candidates are left out of the dict."""
     t_modes = tuple(t_modes) if t_modes is not None else (cfg.t_mode,)
     key = (params.shape[1], params.shape[0], tuple((c.width, c.height) for c in cams),
            tuple(tiles), tuple(batches), t_modes, bool(cfg.fovea_cull), bool(cfg.alpha_loss),
@@ -742,25 +781,66 @@ def autotune(ctx: Context, params: torch.Tensor, cams, targets: torch.Tensor,
     stream = stream or torch.cuda.current_stream()
     if stream.cuda_stream == 0:          # graphs cannot be captured on the null stream
         stream = torch.cuda.Stream()
-    times = {}
+    C, n = params.shape
+    sh_degree = int(round(((C - 11) // 3) ** 0.5)) - 1
+    sizes = [(c.width, c.height) for c in cams]
+    cull = bool(cfg.fovea_cull and gaze is not None)
     with torch.cuda.stream(stream):
-        for t in tiles:
-            for b in batches:
-                for m in t_modes:
-                    c = dataclasses.replace(cfg, tile=t, lds_batch=b, t_mode=m, lr=0.0)
-                    fs = FitStep(ctx, params.detach().clone(), cams, targets, gaze, c, fused=True)
-                    fs.capture()
-                    for _ in range(warmup):
-                        fs.replay()
-                    e0 = torch.cuda.Event(enable_timing=True)
-                    e1 = torch.cuda.Event(enable_timing=True)
-                    e0.record(stream)
-                    for _ in range(reps):
-                        fs.replay()
-                    e1.record(stream)
-                    e1.synchronize()
-                    times[(t, b, m)] = e0.elapsed_time(e1) / reps
-                    fs.plan.close()
-    best = min(times, key=times.get)
+        ctx.use_stream()
+        dev = params.device
+        cams_dev = cameras_to_device(cams, dev)
+        space = _abi.gsf_tune_space(n_tiles=len(tiles), n_batches=len(batches),
+                                    n_t_modes=len(t_modes), warmup=int(warmup), reps=int(reps))
+        for k, t in enumerate(tiles):
+            space.tiles[k] = int(t)
+            space.key_capacity[k] = measure_keys(ctx, params, cams_dev, sizes, sh_degree, t,
+                                                 gaze if cull else None,
+                                                 cfg.radius_frac) * 3 // 2 + (1 << 16)
+        for j, b in enumerate(batches):
+            space.batches[j] = int(b)
+        for m, tm in enumerate(t_modes):
+            space.t_modes[m] = int(tm)
+        w = (ct.c_int32 * len(sizes))(*[a for a, _ in sizes])
+        h = (ct.c_int32 * len(sizes))(*[b for _, b in sizes])
+        desc = gsf_plan_desc(n_max=n, sh_degree=sh_degree, n_views=len(sizes),
+                             widths=ct.cast(w, ct.POINTER(ct.c_int32)),
+                             heights=ct.cast(h, ct.POINTER(ct.c_int32)), tile=int(tiles[0]),
+                             lds_batch=int(batches[0]), t_mode=int(t_modes[0]), host_sized=0,
+                             key_capacity=0)
+        nb = ct.c_size_t()
+        ctx.check(lib().gsf_autotune_workspace_bytes(ctx.handle, ct.byref(desc), ct.byref(space),
+                                                     ct.byref(nb)), "gsf_autotune_workspace_bytes")
+        raw = torch.empty(int(nb.value) + 256, dtype=torch.uint8, device=dev)
+        ws = (raw.data_ptr() + 255) & ~255
+        total = sum(a * b for a, b in sizes)
+        rgba = torch.zeros(4 * total, dtype=torch.float32, device=dev)
+        dl = torch.zeros_like(rgba)
+        grads = torch.zeros_like(params)
+        loss = torch.zeros(1, dtype=torch.float32, device=dev)
+        step_dev = torch.zeros(1, dtype=torch.int32, device=dev)
+        lr = (ct.c_float * C)(*([0.0] * C))
+        tgt = targets.contiguous()
+        args = gsf_step_args(
+            params=params.data_ptr(), n=n, cams=cams_dev.data_ptr(), target_rgb=tgt.data_ptr(),
+            gaze_px=gaze.data_ptr() if gaze is not None else None,
+            mask_radius_frac=cfg.radius_frac, loss=loss.data_ptr(), rgba=rgba.data_ptr(),
+            dl_drgba=dl.data_ptr(), grads=grads.data_ptr(), adam_m=grads.data_ptr(),
+            adam_v=grads.data_ptr(), step_dev=step_dev.data_ptr(),
+            seg_lr=ct.cast(lr, ct.POINTER(ct.c_float)), beta1=cfg.betas[0], beta2=cfg.betas[1],
+            eps=cfg.eps, fovea_cull=int(cull), alpha_loss=int(bool(cfg.alpha_loss)),
+            random_bg=int(bool(cfg.random_bg)), bg_seed=int(cfg.bg_seed) & ((1 << 64) - 1),
+            masked_adam=int(bool(cfg.masked_adam)))
+        res = _abi.gsf_tune_result()
+        ctx.check(lib().gsf_autotune(ctx.handle, ct.byref(desc), ct.byref(space), ct.byref(args),
+                                     ct.c_void_p(ws), nb.value, ct.byref(res)), "gsf_autotune")
+        del raw
+    times = {}
+    for k, t in enumerate(tiles):
+        for j, b in enumerate(batches):
+            for m, tm in enumerate(t_modes):
+                ms = float(res.ms[9 * k + 3 * j + m])
+                if ms >= 0 and ms != float("inf"):
+                    times[(int(t), int(b), int(tm))] = ms
+    best = (int(res.tile), int(res.lds_batch), int(res.t_mode))
     _TUNE_CACHE[key] = (best, times)
     return best, times

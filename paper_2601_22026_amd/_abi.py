@@ -28,7 +28,8 @@ EXPORTED = ["gsf_ctx_create", "gsf_ctx_destroy", "gsf_ctx_set_stream", "gsf_last
             "gsf_count_pairs", "gsf_loss_l1_rgba", "gsf_seed_scratch_bytes",
             "gsf_seed_volume", "gsf_raymarch", "gsf_adam_masked", "gsf_adam_reset",
             "gsf_view_select", "gsf_reproject", "gsf_reproject_warp",
-            "gsf_first_hit_scratch_bytes", "gsf_seed_first_hits"]
+            "gsf_first_hit_scratch_bytes", "gsf_seed_first_hits", "gsf_loss_count",
+            "gsf_autotune_workspace_bytes", "gsf_autotune"]
 STAGES = ["project", "duplicate", "tile_sort", "ranges", "depth_sort", "render", "loss",
           "render_bwd", "project_bwd", "adam", "grad_sum"]
 
@@ -65,7 +66,20 @@ class gsf_step_args(ct.Structure):
                 ("random_bg", ct.c_int32), ("bg_seed", ct.c_uint64), ("masked_adam", ct.c_int32)]
 
 
+class gsf_tune_space(ct.Structure):
+    _fields_ = [("n_tiles", ct.c_int32), ("tiles", ct.c_int32 * 3),
+                ("key_capacity", ct.c_int64 * 3), ("n_batches", ct.c_int32),
+                ("batches", ct.c_int32 * 3), ("n_t_modes", ct.c_int32), ("t_modes", ct.c_int32 * 3),
+                ("warmup", ct.c_int32), ("reps", ct.c_int32)]
+
+
+class gsf_tune_result(ct.Structure):
+    _fields_ = [("tile", ct.c_int32), ("lds_batch", ct.c_int32), ("t_mode", ct.c_int32),
+                ("ms", ct.c_float * 27)]
+
+
 assert ct.sizeof(gsf_camera) == 128
+assert ct.sizeof(gsf_tune_space) == 80 and ct.sizeof(gsf_tune_result) == 120
 
 
 def _declare(L):
@@ -81,10 +95,15 @@ def _declare(L):
         "gsf_plan_bind_workspace": [vp, vp, ct.c_size_t],
         "gsf_plan_info": [vp, ct.POINTER(ct.c_int64), ct.POINTER(ct.c_int64)],
         "gsf_plan_destroy": [vp],
-        "gsf_forward": [vp, vp, i64, vp, vp],
-        "gsf_loss_l1": [vp, vp, vp, vp, f32, vp, vp],
+        "gsf_forward": [vp, vp, i64, vp, vp, f32, vp],
+        "gsf_loss_l1": [vp, vp, vp, vp, f32, i64, i32, vp, vp],
+        "gsf_loss_count": [vp, vp, f32, ct.POINTER(ct.c_int64)],
+        "gsf_autotune_workspace_bytes": [vp, ct.POINTER(gsf_plan_desc), ct.POINTER(gsf_tune_space),
+                                         ct.POINTER(ct.c_size_t)],
+        "gsf_autotune": [vp, ct.POINTER(gsf_plan_desc), ct.POINTER(gsf_tune_space),
+                         ct.POINTER(gsf_step_args), vp, ct.c_size_t, ct.POINTER(gsf_tune_result)],
         "gsf_loss_l1_rgba": [vp, vp, vp, vp, i32, vp, f32, vp, vp],
-        "gsf_backward": [vp, vp, i64, vp, vp, vp],
+        "gsf_backward": [vp, vp, i64, vp, vp, i32, vp],
         "gsf_adam": [vp, vp, vp, vp, vp, i64, ct.POINTER(ct.c_int64), ct.POINTER(ct.c_float), i32,
                      f32, f32, f32, vp],
         "gsf_adam_masked": [vp, vp, vp, vp, vp, i64, i32, ct.POINTER(ct.c_float), vp, f32, f32,

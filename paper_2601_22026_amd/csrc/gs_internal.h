@@ -90,12 +90,15 @@ __device__ __forceinline__ float4 ellipse_pack(float sa, float sb, float sc, flo
     ey = sqrtf(Kp * sc);
     return make_float4(slope, Kp * wid, wid / sc, sb * sqrtf(Kp / sa));
 }
-// Boxes of at most kSpanRows tile rows list only the tiles their ellipse
-// reaches in each row; taller boxes list every tile of the box.
-constexpr int kSpanRows = 32;
-// Boxes of at most kPackRows tile rows and kPackCols tile columns carry their
-// row spans packed (per row: first column - x0 in the low byte, tile count in
-// the high byte of a 16-bit field), so the duplicate pass needs no arithmetic.
+// Every box lists, in each of its tile rows, only the tiles its padded
+// support ellipse reaches (row_span).  Boxes of at most kPackRows tile rows
+// and kPackCols tile columns carry their row spans packed (per row: first
+// column - x0 in the low byte, tile count in the high byte of a 16-bit field),
+// so the duplicate pass needs no arithmetic.  Every other box gets a row table
+// at its own key positions: the duplicate pass writes, for the j-th row that
+// lists a tile, entry koff[r] + j = (row - y0 | first column << 16, keys of the
+// rows before it).  A listed row holds at least one key, so the entries fit in
+// the record's count[r] key slots; rspan[r].x holds the entry count.
 constexpr int kPackRows = 4;
 constexpr int kPackCols = 255;
 
@@ -164,6 +167,7 @@ __device__ __forceinline__ uint32_t quadrant_mask(const Ellipse &e, int x0, int 
 struct KeyPlace {
     const uint32_t *koff = nullptr, *count = nullptr;
     const uint2 *rect = nullptr, *rspan = nullptr;
+    const uint2 *rowtab = nullptr;              // row tables of the boxes not packed
     const float4 *ell = nullptr;
     float4 *pa = nullptr, *pb = nullptr;
     float *pc = nullptr;
@@ -171,34 +175,33 @@ struct KeyPlace {
     int64_t capacity = 0;
 };
 
-// Position of the key of record r in tile (ty, tx) of its view (W x H,
-// tile = 1 << tile_log2): koff[r] plus the tile's rank among the record's
-// listed tiles, found from the packed row spans, the box, or the row spans.
-__device__ __forceinline__ uint32_t key_slot(const KeyPlace &kp, SplatPtrs sp, uint32_t r, int ty,
-                                             int tx, int tile_log2, int W, int H) {
+// Position of the key of record r in tile (ty, tx) of its view: koff[r] plus
+// the tile's rank among the record's listed tiles, from the packed row spans
+// or (other boxes) the row table entry of row ty, found by binary search.
+__device__ __forceinline__ uint32_t key_slot(const KeyPlace &kp, uint32_t r, int ty, int tx) {
     const uint2 rc = kp.rect[r];
     const int x0 = (int)(rc.x & 0xFFFFu), y0 = (int)(rc.x >> 16);
     const int x1 = (int)(rc.y & 0xFFFFu), y1 = (int)(rc.y >> 16);
     const int rows = y1 - y0 + 1, cols = x1 - x0 + 1;
+    const uint32_t base = kp.koff[r];
     uint32_t rank = 0;
+    const uint2 pk = kp.rspan[r];
     if (rows <= kPackRows && cols <= kPackCols) {
-        const uint2 pk = kp.rspan[r];
         const int kr = ty - y0;
         for (int k = 0; k < kr; k++) rank += (((k < 2 ? pk.x : pk.y) >> (16 * (k & 1))) >> 8) & 0xFFu;
         const uint32_t f = ((kr < 2 ? pk.x : pk.y) >> (16 * (kr & 1))) & 0xFFFFu;
         rank += (uint32_t)(tx - x0) - (f & 0xFFu);
-    } else if (rows > kSpanRows) {
-        rank = (uint32_t)((ty - y0) * cols + (tx - x0));
     } else {
-        const float4 e0 = kp.ell[r], a = sp.a[r], c = sp.c[r];
-        const Ellipse e{e0.x, e0.y, e0.z, e0.w, sqrtf(e0.y / e0.z), a.x, a.y, (int)c.z, (int)c.w};
-        int c0, c1;
-        for (int y = y0; y < ty; y++)
-            if (row_span(e, y, tile_log2, W, H, x0, x1, c0, c1)) rank += (uint32_t)(c1 - c0 + 1);
-        row_span(e, ty, tile_log2, W, H, x0, x1, c0, c1);
-        rank += (uint32_t)(tx - c0);
+        const uint32_t row = (uint32_t)(ty - y0);
+        int lo = 0, hi = (int)pk.x - 1;   // the last entry of a row <= ty (it is row ty: listed)
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if ((kp.rowtab[base + (uint32_t)mid].x & 0xFFFFu) <= row) lo = mid; else hi = mid - 1;
+        }
+        const uint2 e = kp.rowtab[base + (uint32_t)lo];
+        rank = e.y + (uint32_t)tx - (e.x >> 16);
     }
-    return kp.koff[r] + rank;
+    return base + rank;
 }
 
 // ---- wave-level helpers shared by the adjoint passes ------------------------------
@@ -339,7 +342,8 @@ __device__ __forceinline__ FoveaTiles fovea_tiles(const float *__restrict__ gaze
 // splat, the depth key (float32 bits of the camera depth, 0xFFFFFFFF when
 // culled), the tile rectangle of the support box, the number of its tiles the
 // support ellipse reaches (row_span), the ellipse constants (slope, kw, ws,
-// dyr; ey follows as sqrt(kw / ws)) and the packed row spans of short boxes.
+// dyr; ey follows as sqrt(kw / ws)) and the packed row spans of short boxes
+// (other boxes: the number of their rows that list a tile).
 // With cull_gaze (nullable) the rectangle is clipped to the view's
 // fovea tiles (fovea_tiles with cull_radius).  block_sums[b] receives the
 // total count of records 256 b .. 256 b + 255 (scan_blocks(nrec) words), the
@@ -355,17 +359,20 @@ void launch_project_fwd(hipStream_t s, const float *P, int n, int nviews, int de
 // the way; for degrees 2-3, whose larger state leaves no registers for the
 // sum, read from g2d, which launch_grad_sum must have written.
 bool project_bwd_sums_keys(int deg);
+// accumulate: grads += the gradient (else grads = it).
 void launch_project_bwd(hipStream_t s, const float *P, int n, int nviews, int deg,
-                        const gsf_camera *cams, const KeyPlace &kp, const float *g2d, float *grads);
+                        const gsf_camera *cams, const KeyPlace &kp, const float *g2d, float *grads,
+                        bool accumulate = false);
 
 // Exclusive scan of the per-record tile counts and key emission in record
 // order (key = global tile id, value = record id).  Writes the key total to
 // m_total and (0 on overflow, with GSF_FLAG_CAPACITY) to m_dev; emits nothing on
 // overflow.  Clears ranges[total_tiles].  block_sums: the per-256-record count
 // totals launch_project_fwd wrote (scan_blocks(nrec) words), scanned in place.
+// rowtab (key capacity entries): the row tables of the boxes not packed.
 void launch_scan_duplicate(hipStream_t s, const uint32_t *count, const uint2 *rect,
                            const float4 *ell, const uint2 *rspan, SplatPtrs sp, uint32_t *koff,
-                           int nrec, int n, int tile,
+                           uint2 *rowtab, int nrec, int n, int tile,
                            const ViewDesc *views, uint32_t *block_sums, uint32_t *keys,
                            uint32_t *vals, uint32_t *m_dev, unsigned long long *m_total,
                            uint32_t *flags, int64_t capacity, uint2 *ranges, int total_tiles);
@@ -450,7 +457,13 @@ void launch_loss_l1(hipStream_t s, const float *rgba, const float *target, const
                     float radius_frac, const ViewDesc *views, int nviews, int64_t total_pix,
                     float *dl, float *partial, uint32_t *mask_count, float *loss, uint32_t *flags,
                     int32_t *step_inc, int box, int tile, int tgt_planes, bool alpha_term,
-                    const float *bg);
+                    const float *bg, uint32_t norm_count = 0u, bool accumulate = false);
+// norm_count > 0: the mean divides by it (entries over all plans of a multi-plan
+// loss) instead of the plan's own masked count; accumulate: loss[0] += the share.
+// The masked entry count alone (gaze required) into mask_count[0].
+void launch_loss_count(hipStream_t s, const float *gaze, float radius_frac, const ViewDesc *views,
+                       int nviews, int64_t total_pix, int box, int tile, uint32_t channels,
+                       uint32_t *mask_count);
 
 // bg[v][c] = top 24 bits of output 1 + (step[0] * kMaxViews + v) * 4 + c of
 // SplitMix64(seed), scaled to [0, 1).

@@ -41,7 +41,7 @@ struct Buffers {
     uint2 *rect = nullptr;                       // touched tile rectangle
     uint32_t *count = nullptr;                   // listed tiles
     float4 *ell = nullptr;                       // support ellipse constants (Ellipse)
-    uint2 *rspan = nullptr;                      // packed row spans of short boxes
+    uint2 *rspan = nullptr;                      // packed row spans of short boxes (else row-table size)
     uint32_t *koff = nullptr;                    // position of the record's first key
     uint32_t *block_sums = nullptr;              // scan of the per-record tile counts
     // per global tile
@@ -55,6 +55,7 @@ struct Buffers {
     uint32_t *keys = nullptr, *vals = nullptr;   // sorted pair (aliases k0/v0 or k1/v1)
     uint32_t *ok = nullptr, *ov = nullptr;       // the other pair
     uint32_t *hist = nullptr, *digit_tot = nullptr;   // radix-sort histograms
+    uint2 *rowtab = nullptr;                     // per key position: row tables of boxes not packed
     // per key, at its position in the duplicate pass's order: the adjoint's
     // screen-space gradient (fields 0-3, 4-7, 8)
     float4 *pa = nullptr, *pb = nullptr;
@@ -91,6 +92,7 @@ struct gsf_plan {
     void *ws = nullptr;
     Buffers b;
     bool have_forward = false;
+    bool fwd_culled = false;                  // the last forward composited only fovea tiles
     int64_t fwd_n = 0;
     unsigned long long *pinned = nullptr;     // host-pinned readback of the key count
     hipGraph_t graph = nullptr;
@@ -166,6 +168,7 @@ size_t carve(gsf_plan *p, char *base, Buffers *out) {
     b.ov = odd ? b.v0 : b.v1;
     b.hist = (uint32_t *)take((size_t)256 * p->radix_grid * 4);
     b.digit_tot = (uint32_t *)take(256 * 4);
+    b.rowtab = (uint2 *)take((size_t)p->cap * sizeof(uint2));
     b.pa = (float4 *)take((size_t)p->cap * sizeof(float4));
     b.pb = (float4 *)take((size_t)p->cap * sizeof(float4));
     b.pc = (float *)take((size_t)p->cap * 4);
@@ -225,6 +228,7 @@ RenderArgs render_args(gsf_plan *p, const gsf_camera *cams, int64_t n) {
     a.kp.count = p->b.count;
     a.kp.rect = p->b.rect;
     a.kp.rspan = p->b.rspan;
+    a.kp.rowtab = p->b.rowtab;
     a.kp.ell = p->b.ell;
     a.kp.pa = p->b.pa;
     a.kp.pb = p->b.pb;
@@ -298,7 +302,8 @@ gsf_status enqueue_forward(gsf_plan *p, const float *params, int64_t n, const gs
     GSF_LAUNCHED(ctx);
     {   // one key per touched tile in record order; key total + capacity check on the device
         StageTimer t(p, GSF_STAGE_DUPLICATE);
-        launch_scan_duplicate(s, b.count, b.rect, b.ell, b.rspan, splats(p), b.koff, nrec, (int)n,
+        launch_scan_duplicate(s, b.count, b.rect, b.ell, b.rspan, splats(p), b.koff, b.rowtab,
+                              nrec, (int)n,
                               p->tile,
                               b.views, b.block_sums, b.k0, b.v0, b.m_dev, b.m_total, b.flags,
                               p->cap, b.ranges, (int)p->total_tiles);
@@ -341,6 +346,7 @@ gsf_status enqueue_forward(gsf_plan *p, const float *params, int64_t n, const gs
     }
     GSF_LAUNCHED(ctx);
     p->have_forward = true;
+    p->fwd_culled = cull_gaze != nullptr;
     p->fwd_n = n;
     return GSF_OK;
 }
@@ -349,29 +355,34 @@ gsf_status enqueue_forward(gsf_plan *p, const float *params, int64_t n, const gs
 // required) - a window of box x box pixels per view, when that is smaller.
 // tgt_planes 4: RGBA targets composited over bg (nullable) with an alpha term
 // when alpha_term.
+// Side of the per-view pixel window that holds every tile meeting the fovea
+// (0 when the window would not be smaller than the views).
+int fovea_box(const gsf_plan *p, float radius_frac) {
+    int wmax = 1;
+    for (const ViewDesc &vd : p->views) wmax = std::max(wmax, (int)vd.width);
+    const double r = (double)radius_frac * wmax;
+    const int64_t tiles = (int64_t)std::ceil((2.0 * r + 4.0) / p->tile) + 1;
+    const int64_t side = tiles * p->tile;
+    return side > 0 && (int64_t)p->V * side * side <= p->total_pix ? (int)side : 0;
+}
+
 gsf_status enqueue_loss(gsf_plan *p, const float *rgba, const float *target, const float *gaze,
                         float radius_frac, float *loss, float *dl, int32_t *step_inc,
                         bool cull = false, int tgt_planes = 3, bool alpha_term = false,
-                        const float *bg = nullptr) {
-    int box = 0;
-    if (cull && gaze) {
-        int wmax = 1;
-        for (const ViewDesc &vd : p->views) wmax = std::max(wmax, (int)vd.width);
-        const double r = (double)radius_frac * wmax;
-        const int64_t tiles = (int64_t)std::ceil((2.0 * r + 4.0) / p->tile) + 1;
-        const int64_t side = tiles * p->tile;
-        if (side > 0 && (int64_t)p->V * side * side <= p->total_pix) box = (int)side;
-    }
+                        const float *bg = nullptr, uint32_t norm_count = 0u,
+                        bool accumulate = false) {
+    const int box = cull && gaze ? fovea_box(p, radius_frac) : 0;
     StageTimer t(p, GSF_STAGE_LOSS);
     launch_loss_l1(p->ctx->stream, rgba, target, gaze, radius_frac, p->b.views, p->V,
                    p->total_pix, dl, p->b.loss_partial, p->b.mask_count, loss, p->b.flags,
-                   step_inc, box, p->tile, tgt_planes, alpha_term, bg);
+                   step_inc, box, p->tile, tgt_planes, alpha_term, bg, norm_count, accumulate);
     GSF_LAUNCHED(p->ctx);
     return GSF_OK;
 }
 
 gsf_status enqueue_backward(gsf_plan *p, const float *params, int64_t n, const gsf_camera *cams,
-                            const float *dl, float *grads, const float *bg = nullptr) {
+                            const float *dl, float *grads, const float *bg = nullptr,
+                            bool accumulate = false) {
     hipStream_t s = p->ctx->stream;
     RenderArgs ra = render_args(p, cams, n);
     ra.bg = bg;
@@ -387,7 +398,7 @@ gsf_status enqueue_backward(gsf_plan *p, const float *params, int64_t n, const g
     GSF_LAUNCHED(p->ctx);
     {   // the chain rule to the parameters (summing the per-key terms itself for SH 0-1)
         StageTimer t(p, GSF_STAGE_PROJECT_BWD);
-        launch_project_bwd(s, params, (int)n, p->V, p->deg, cams, ra.kp, p->b.g2d, grads);
+        launch_project_bwd(s, params, (int)n, p->V, p->deg, cams, ra.kp, p->b.g2d, grads, accumulate);
     }
     GSF_LAUNCHED(p->ctx);
     return GSF_OK;
@@ -435,7 +446,9 @@ gsf_status check_step(gsf_plan *p, const gsf_step_args *a) {
     return GSF_OK;
 }
 
-gsf_status enqueue_step(gsf_plan *p, const gsf_step_args *a) {
+// with_adam = false: forward, loss and backward only (the autotuner's timing,
+// which leaves parameters and moments alone).
+gsf_status enqueue_step(gsf_plan *p, const gsf_step_args *a, bool with_adam = true) {
     bool overflow = false;
     const bool cull = a->fovea_cull != 0;
     const float *bg = nullptr;
@@ -453,6 +466,7 @@ gsf_status enqueue_step(gsf_plan *p, const gsf_step_args *a) {
     if (st != GSF_OK) return st;
     st = enqueue_backward(p, a->params, a->n, a->cams, a->dl_drgba, a->grads, bg);
     if (st != GSF_OK) return st;
+    if (!with_adam) return overflow ? fail(p->ctx, GSF_E_CAPACITY, "key capacity exceeded") : GSF_OK;
     const int C = planes_of(p->deg);
     std::vector<int64_t> off(C + 1);
     for (int c = 0; c <= C; c++) off[c] = (int64_t)c * a->n;
@@ -631,24 +645,54 @@ gsf_status gsf_plan_destroy(gsf_plan *p) {
 }
 
 gsf_status gsf_forward(gsf_plan *p, const float *params, int64_t n, const gsf_camera *cams,
-                       float *out_rgba) {
+                       const float *cull_gaze_px, float cull_radius_frac, float *out_rgba) {
     gsf_status st = check_ready(p);
     if (st != GSF_OK) return st;
     if (!params || !cams || !out_rgba) return fail(p->ctx, GSF_E_INVALID, "gsf_forward: null argument");
     if (n < 1 || n > p->n_max) return fail(p->ctx, GSF_E_INVALID, "gsf_forward: n out of range");
+    if (cull_gaze_px && !(cull_radius_frac >= 0.f && cull_radius_frac <= 4.f))
+        return fail(p->ctx, GSF_E_INVALID, "gsf_forward: cull_radius_frac must lie in [0, 4]");
     bool overflow = false;
-    st = enqueue_forward(p, params, n, cams, out_rgba, &overflow);
+    st = enqueue_forward(p, params, n, cams, out_rgba, &overflow, cull_gaze_px, cull_radius_frac);
     if (st != GSF_OK) return st;
     return overflow ? fail(p->ctx, GSF_E_CAPACITY, "key capacity exceeded") : GSF_OK;
 }
 
 gsf_status gsf_loss_l1(gsf_plan *p, const float *rgba, const float *target_rgb, const float *gaze_px,
-                       float mask_radius_frac, float *loss, float *dl_drgba) {
+                       float mask_radius_frac, int64_t norm_count, int32_t accumulate, float *loss,
+                       float *dl_drgba) {
     gsf_status st = check_ready(p);
     if (st != GSF_OK) return st;
     if (!rgba || !target_rgb || !loss || !dl_drgba) return fail(p->ctx, GSF_E_INVALID, "gsf_loss_l1: null argument");
     if (gaze_px && !(mask_radius_frac >= 0.f)) return fail(p->ctx, GSF_E_INVALID, "gsf_loss_l1: bad radius");
-    return enqueue_loss(p, rgba, target_rgb, gaze_px, mask_radius_frac, loss, dl_drgba, nullptr);
+    if (norm_count < 0 || norm_count > 0xFFFFFFFFll)
+        return fail(p->ctx, GSF_E_INVALID, "gsf_loss_l1: norm_count must lie in [0, 2^32 - 1]");
+    if (accumulate != 0 && accumulate != 1)
+        return fail(p->ctx, GSF_E_INVALID, "gsf_loss_l1: accumulate must be 0 or 1");
+    // after a fovea-culled forward only the fovea tiles hold this step's image
+    const bool cull = gaze_px && p->have_forward && p->fwd_culled;
+    return enqueue_loss(p, rgba, target_rgb, gaze_px, mask_radius_frac, loss, dl_drgba, nullptr,
+                        cull, 3, false, nullptr, (uint32_t)norm_count, accumulate != 0);
+}
+
+gsf_status gsf_loss_count(gsf_plan *p, const float *gaze_px, float mask_radius_frac,
+                          int64_t *count) {
+    gsf_status st = check_ready(p);
+    if (st != GSF_OK) return st;
+    if (!count) return fail(p->ctx, GSF_E_INVALID, "gsf_loss_count: null count");
+    if (!gaze_px) {
+        *count = 3 * p->total_pix;
+        return GSF_OK;
+    }
+    if (!(mask_radius_frac >= 0.f)) return fail(p->ctx, GSF_E_INVALID, "gsf_loss_count: bad radius");
+    launch_loss_count(p->ctx->stream, gaze_px, mask_radius_frac, p->b.views, p->V, p->total_pix,
+                      fovea_box(p, mask_radius_frac), p->tile, 3u, p->b.mask_count);
+    GSF_LAUNCHED(p->ctx);
+    uint32_t c = 0;
+    GSF_HIP(p->ctx, hipStreamSynchronize(p->ctx->stream));
+    GSF_HIP(p->ctx, hipMemcpy(&c, p->b.mask_count, 4, hipMemcpyDeviceToHost));
+    *count = c;
+    return GSF_OK;
 }
 
 gsf_status gsf_loss_l1_rgba(gsf_plan *p, const float *rgba, const float *target_rgba,
@@ -666,13 +710,15 @@ gsf_status gsf_loss_l1_rgba(gsf_plan *p, const float *rgba, const float *target_
 }
 
 gsf_status gsf_backward(gsf_plan *p, const float *params, int64_t n, const gsf_camera *cams,
-                        const float *dl_drgba, float *grads) {
+                        const float *dl_drgba, int32_t accumulate, float *grads) {
     gsf_status st = check_ready(p);
     if (st != GSF_OK) return st;
     if (!params || !cams || !dl_drgba || !grads) return fail(p->ctx, GSF_E_INVALID, "gsf_backward: null argument");
+    if (accumulate != 0 && accumulate != 1)
+        return fail(p->ctx, GSF_E_INVALID, "gsf_backward: accumulate must be 0 or 1");
     if (!p->have_forward) return fail(p->ctx, GSF_E_STATE, "gsf_backward before gsf_forward");
     if (n != p->fwd_n) return fail(p->ctx, GSF_E_INVALID, "gsf_backward: n differs from the forward");
-    return enqueue_backward(p, params, n, cams, dl_drgba, grads);
+    return enqueue_backward(p, params, n, cams, dl_drgba, grads, nullptr, accumulate != 0);
 }
 
 gsf_status gsf_seed_scratch_bytes(int32_t n, size_t *bytes) {
@@ -889,6 +935,151 @@ gsf_status gsf_step_replay(gsf_plan *p) {
     if (!p) return GSF_E_INVALID;
     if (!p->exec) return fail(p->ctx, GSF_E_STATE, "no captured step");
     GSF_HIP(p->ctx, hipGraphLaunch(p->exec, p->ctx->stream));
+    return GSF_OK;
+}
+
+namespace {
+
+gsf_status check_tune_space(gsf_ctx *ctx, const gsf_plan_desc *base, const gsf_tune_space *t) {
+    if (!base || !t) return fail(ctx, GSF_E_INVALID, "gsf_autotune: null argument");
+    if (t->n_tiles < 1 || t->n_tiles > 3 || t->n_batches < 1 || t->n_batches > 3 ||
+        t->n_t_modes < 1 || t->n_t_modes > 3)
+        return fail(ctx, GSF_E_INVALID, "gsf_autotune: 1..3 tiles, LDS batches and transmittance modes");
+    for (int k = 0; k < t->n_tiles; k++) {
+        if (t->tiles[k] != 8 && t->tiles[k] != 16 && t->tiles[k] != 32)
+            return fail(ctx, GSF_E_INVALID, "gsf_autotune: tiles must be 8, 16 or 32");
+        if (t->key_capacity[k] < 0) return fail(ctx, GSF_E_INVALID, "gsf_autotune: negative key capacity");
+    }
+    for (int j = 0; j < t->n_batches; j++)
+        if (t->batches[j] != 64 && t->batches[j] != 128 && t->batches[j] != 256)
+            return fail(ctx, GSF_E_INVALID, "gsf_autotune: LDS batches must be 64, 128 or 256");
+    for (int m = 0; m < t->n_t_modes; m++)
+        if (t->t_modes[m] < 0 || t->t_modes[m] > 2)
+            return fail(ctx, GSF_E_INVALID, "gsf_autotune: transmittance modes must be 0, 1 or 2");
+    if (t->warmup < 0 || t->reps < 1) return fail(ctx, GSF_E_INVALID, "gsf_autotune: warmup >= 0, reps >= 1");
+    return GSF_OK;
+}
+
+gsf_plan_desc tune_desc(const gsf_plan_desc *base, const gsf_tune_space *t, int k, int j, int m) {
+    gsf_plan_desc d = *base;
+    d.tile = t->tiles[k];
+    d.lds_batch = t->batches[j];
+    d.t_mode = t->t_modes[m];
+    d.host_sized = 0;
+    d.key_capacity = t->key_capacity[k];
+    return d;
+}
+
+// The autotune workspace starts with the candidates' private step counter.
+constexpr size_t kTuneHead = 256;
+
+}  // namespace
+
+gsf_status gsf_autotune_workspace_bytes(gsf_ctx *ctx, const gsf_plan_desc *base,
+                                        const gsf_tune_space *space, size_t *bytes) {
+    if (!ctx) return GSF_E_INVALID;
+    gsf_status st = check_tune_space(ctx, base, space);
+    if (st != GSF_OK) return st;
+    if (!bytes) return fail(ctx, GSF_E_INVALID, "gsf_autotune_workspace_bytes: null bytes");
+    size_t most = 0;
+    for (int k = 0; k < space->n_tiles; k++)
+        for (int j = 0; j < space->n_batches; j++)
+            for (int m = 0; m < space->n_t_modes; m++) {
+                const gsf_plan_desc d = tune_desc(base, space, k, j, m);
+                gsf_plan *p = nullptr;
+                st = gsf_plan_create(ctx, &d, &p);
+                if (st != GSF_OK) return st;
+                most = std::max(most, p->ws_bytes);
+                gsf_plan_destroy(p);
+            }
+    *bytes = kTuneHead + most;
+    return GSF_OK;
+}
+
+gsf_status gsf_autotune(gsf_ctx *ctx, const gsf_plan_desc *base, const gsf_tune_space *space,
+                        const gsf_step_args *args, void *workspace, size_t bytes,
+                        gsf_tune_result *out) {
+    if (!ctx) return GSF_E_INVALID;
+    gsf_status st = check_tune_space(ctx, base, space);
+    if (st != GSF_OK) return st;
+    if (!args || !workspace || !out) return fail(ctx, GSF_E_INVALID, "gsf_autotune: null argument");
+    if (((uintptr_t)workspace & 255u) != 0)
+        return fail(ctx, GSF_E_INVALID, "gsf_autotune: workspace must be 256-byte aligned");
+    if (bytes <= kTuneHead) return fail(ctx, GSF_E_INVALID, "gsf_autotune: workspace too small");
+    if (!ctx->stream) return fail(ctx, GSF_E_STATE, "gsf_autotune captures graphs: needs a non-null stream");
+    std::memset(out, 0, sizeof *out);
+    for (int e = 0; e < 27; e++) out->ms[e] = -1.f;
+    hipStream_t s = ctx->stream;
+    int32_t *counter = (int32_t *)workspace;
+    char *ws = (char *)workspace + kTuneHead;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    GSF_HIP(ctx, hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        return fail(ctx, GSF_E_HIP, "gsf_autotune: hipEventCreate failed");
+    }
+    float best = INFINITY;
+    gsf_status result = GSF_OK;
+    for (int k = 0; k < space->n_tiles && result == GSF_OK; k++)
+        for (int j = 0; j < space->n_batches && result == GSF_OK; j++)
+            for (int m = 0; m < space->n_t_modes && result == GSF_OK; m++) {
+                const gsf_plan_desc d = tune_desc(base, space, k, j, m);
+                gsf_plan *p = nullptr;
+                result = gsf_plan_create(ctx, &d, &p);
+                if (result != GSF_OK) break;
+                float ms = INFINITY;
+                do {
+                    if ((result = gsf_plan_bind_workspace(p, ws, bytes - kTuneHead)) != GSF_OK) break;
+                    gsf_step_args a = *args;
+                    a.step_dev = counter;   // private: the caller's step count is not advanced
+                    if ((result = check_step(p, &a)) != GSF_OK) break;
+                    launch_fill_u32(s, (uint32_t *)counter, 1, 0u);
+                    hipGraph_t g = nullptr;
+                    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+                        result = fail(ctx, GSF_E_HIP, "gsf_autotune: hipStreamBeginCapture failed");
+                        break;
+                    }
+                    gsf_status est = enqueue_step(p, &a, false);
+                    const hipError_t ce = hipStreamEndCapture(s, &g);
+                    if (est != GSF_OK || ce != hipSuccess) {
+                        if (g) hipGraphDestroy(g);
+                        result = est != GSF_OK ? est : fail(ctx, GSF_E_HIP, "gsf_autotune: capture failed");
+                        break;
+                    }
+                    p->graph = g;
+                    if (hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) != hipSuccess) {
+                        result = fail(ctx, GSF_E_HIP, "gsf_autotune: hipGraphInstantiate failed");
+                        break;
+                    }
+                    bool ok = true;
+                    for (int w = 0; w < space->warmup && ok; w++) ok = hipGraphLaunch(p->exec, s) == hipSuccess;
+                    ok = ok && hipEventRecord(e0, s) == hipSuccess;
+                    for (int r = 0; r < space->reps && ok; r++) ok = hipGraphLaunch(p->exec, s) == hipSuccess;
+                    ok = ok && hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+                    float el = 0.f;
+                    ok = ok && hipEventElapsedTime(&el, e0, e1) == hipSuccess;
+                    uint32_t f = 0;
+                    ok = ok && hipMemcpy(&f, p->b.flags, 4, hipMemcpyDeviceToHost) == hipSuccess;
+                    if (!ok) {
+                        result = fail(ctx, GSF_E_HIP, "gsf_autotune: timing a candidate failed");
+                        break;
+                    }
+                    if (!(f & GSF_FLAG_CAPACITY)) ms = el / (float)space->reps;   // else: overflowed
+                } while (false);
+                gsf_plan_destroy(p);
+                out->ms[9 * k + 3 * j + m] = ms;
+                if (result == GSF_OK && ms < best) {
+                    best = ms;
+                    out->tile = d.tile;
+                    out->lds_batch = d.lds_batch;
+                    out->t_mode = d.t_mode;
+                }
+            }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (result != GSF_OK) return result;
+    if (!(best < INFINITY))
+        return fail(ctx, GSF_E_CAPACITY, "gsf_autotune: every candidate overflowed its key capacity");
     return GSF_OK;
 }
 

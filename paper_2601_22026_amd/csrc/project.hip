@@ -313,28 +313,26 @@ __device__ __forceinline__ uint32_t project_record(const float *__restrict__ P, 
     float ey;
     const float4 ep = ellipse_pack(p.a, p.b, p.c, Kp, ey);
     ell[r] = ep;
-    uint32_t cnt = 0;
-    if (ty1 - ty0 + 1 > (uint32_t)kSpanRows) {
-        cnt = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
-    } else {
-        const Ellipse e{ep.x, ep.y, ep.z, ep.w, sqrtf(ep.y / ep.z), (float)(ixd + 0.5 - mxd),
-                        (float)(iyd + 0.5 - myd), (int)ixd, (int)iyd};
-        const int tl = 31 - __clz(tile);
-        const bool pack = ty1 - ty0 + 1 <= (uint32_t)kPackRows && tx1 - tx0 + 1 <= (uint32_t)kPackCols;
-        uint32_t packed[2] = {0u, 0u};
-        for (uint32_t ty = ty0; ty <= ty1; ty++) {
-            int c0, c1;
-            if (row_span(e, (int)ty, tl, vd.width, vd.height, (int)tx0, (int)tx1, c0, c1)) {
-                const uint32_t w = (uint32_t)(c1 - c0 + 1);
-                cnt += w;
-                if (pack) {
-                    const uint32_t k = ty - ty0;
-                    packed[k >> 1] |= (((uint32_t)c0 - tx0) | (w << 8)) << (16 * (k & 1));
-                }
+    uint32_t cnt = 0, listed_rows = 0;
+    const Ellipse e{ep.x, ep.y, ep.z, ep.w, sqrtf(ep.y / ep.z), (float)(ixd + 0.5 - mxd),
+                    (float)(iyd + 0.5 - myd), (int)ixd, (int)iyd};
+    const int tl = 31 - __clz(tile);
+    const bool pack = ty1 - ty0 + 1 <= (uint32_t)kPackRows && tx1 - tx0 + 1 <= (uint32_t)kPackCols;
+    uint32_t packed[2] = {0u, 0u};
+    for (uint32_t ty = ty0; ty <= ty1; ty++) {
+        int c0, c1;
+        if (row_span(e, (int)ty, tl, vd.width, vd.height, (int)tx0, (int)tx1, c0, c1)) {
+            const uint32_t w = (uint32_t)(c1 - c0 + 1);
+            cnt += w;
+            listed_rows++;
+            if (pack) {
+                const uint32_t k = ty - ty0;
+                packed[k >> 1] |= (((uint32_t)c0 - tx0) | (w << 8)) << (16 * (k & 1));
             }
         }
-        rspan[r] = make_uint2(packed[0], packed[1]);
     }
+    // packed spans, or the number of row-table entries the duplicate pass writes
+    rspan[r] = pack ? make_uint2(packed[0], packed[1]) : make_uint2(listed_rows, 0u);
     count[r] = cnt;
     return cnt;
 }
@@ -384,7 +382,7 @@ template <int DEG, bool FUSED>
 __global__ __launch_bounds__(128) void k_project_bwd(const float *__restrict__ P, int n, int nviews,
                                                      const gsf_camera *__restrict__ cams, KeyPlace kp,
                                                      const float *__restrict__ g2d,
-                                                     float *__restrict__ grads) {
+                                                     float *__restrict__ grads, bool accumulate) {
     constexpr int K = (DEG + 1) * (DEG + 1);
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const bool valid = i < n;   // every lane takes part in the per-view key sums
@@ -523,18 +521,23 @@ __global__ __launch_bounds__(128) void k_project_bwd(const float *__restrict__ P
     float dqn[4];
     quat_vjp(g.qn, dR, dqn);
     const float qdot = dqn[0] * g.qn[0] + dqn[1] * g.qn[1] + dqn[2] * g.qn[2] + dqn[3] * g.qn[3];
+    // plane c of Gaussian i: written, or added to what is there (accumulate)
+    auto put = [&](int c, float val) {
+        float *q = grads + (size_t)c * n + i;
+        *q = accumulate ? *q + val : val;
+    };
 #pragma unroll
     for (int a = 0; a < 3; a++) {
-        grads[(size_t)a * n + i] = dmu[a];
-        grads[(size_t)(3 + a) * n + i] = ds[a] * g.s[a];
+        put(a, dmu[a]);
+        put(3 + a, ds[a] * g.s[a]);
     }
 #pragma unroll
-    for (int a = 0; a < 4; a++) grads[(size_t)(6 + a) * n + i] = (dqn[a] - g.qn[a] * qdot) * g.qinv;
-    grads[(size_t)10 * n + i] = g.o * (1.f - g.o) * dop;
+    for (int a = 0; a < 4; a++) put(6 + a, (dqn[a] - g.qn[a] * qdot) * g.qinv);
+    put(10, g.o * (1.f - g.o) * dop);
 #pragma unroll
     for (int k = 0; k < K; k++)
 #pragma unroll
-        for (int ch = 0; ch < 3; ch++) grads[(size_t)(11 + 3 * k + ch) * n + i] = dsh[k][ch];
+        for (int ch = 0; ch < 3; ch++) put(11 + 3 * k + ch, dsh[k][ch]);
 }
 
 }  // namespace
@@ -557,13 +560,14 @@ void launch_project_fwd(hipStream_t s, const float *P, int n, int nviews, int de
 bool project_bwd_sums_keys(int deg) { return deg <= 1; }
 
 void launch_project_bwd(hipStream_t s, const float *P, int n, int nviews, int deg,
-                        const gsf_camera *cams, const KeyPlace &kp, const float *g2d, float *grads) {
+                        const gsf_camera *cams, const KeyPlace &kp, const float *g2d, float *grads,
+                        bool accumulate) {
     const dim3 grid((n + 127) / 128), block(128);
     switch (deg) {
-    case 0: k_project_bwd<0, true><<<grid, block, 0, s>>>(P, n, nviews, cams, kp, g2d, grads); break;
-    case 1: k_project_bwd<1, true><<<grid, block, 0, s>>>(P, n, nviews, cams, kp, g2d, grads); break;
-    case 2: k_project_bwd<2, false><<<grid, block, 0, s>>>(P, n, nviews, cams, kp, g2d, grads); break;
-    default: k_project_bwd<3, false><<<grid, block, 0, s>>>(P, n, nviews, cams, kp, g2d, grads); break;
+    case 0: k_project_bwd<0, true><<<grid, block, 0, s>>>(P, n, nviews, cams, kp, g2d, grads, accumulate); break;
+    case 1: k_project_bwd<1, true><<<grid, block, 0, s>>>(P, n, nviews, cams, kp, g2d, grads, accumulate); break;
+    case 2: k_project_bwd<2, false><<<grid, block, 0, s>>>(P, n, nviews, cams, kp, g2d, grads, accumulate); break;
+    default: k_project_bwd<3, false><<<grid, block, 0, s>>>(P, n, nviews, cams, kp, g2d, grads, accumulate); break;
     }
 }
 

@@ -522,7 +522,7 @@ __device__ __forceinline__ void render_bwd_unit(
             s_a[j] = ra;
             s_b[j] = rb;
             s_c[j] = rc;
-            s_q[j] = key_slot(kp, sp, r, ty, tx, TL, vd.width, vd.height);
+            s_q[j] = key_slot(kp, r, ty, tx);
             if (QUAD) {
                 const Ellipse e{e0.x, e0.y, e0.z, e0.w, quad_half_height(e0), ra.x, ra.y, (int)rc.z, (int)rc.w};
                 s_m[j] = (uint8_t)quadrant_mask(e, tx * T, ty * T);
@@ -667,7 +667,7 @@ __device__ __forceinline__ void render_bwd_unit(
     }
     // keys behind every pixel's last included splat pass no gradient
     for (uint32_t e = max(top, us) + threadIdx.x; e < ue; e += NT) {
-        const uint32_t q = key_slot(kp, sp, vals[e], ty, tx, TL, vd.width, vd.height);
+        const uint32_t q = key_slot(kp, vals[e], ty, tx);
         kp.pa[q] = make_float4(0.f, 0.f, 0.f, 0.f);
         kp.pb[q] = make_float4(0.f, 0.f, 0.f, 0.f);
         kp.pc[q] = 0.f;
@@ -945,7 +945,7 @@ __global__ __launch_bounds__(1024) void k_loss_final(const float *__restrict__ p
                                                      const uint32_t *__restrict__ mask_count,
                                                      uint32_t count_host, float *__restrict__ loss,
                                                      uint32_t *__restrict__ flags,
-                                                     int32_t *__restrict__ step_inc) {
+                                                     int32_t *__restrict__ step_inc, bool accumulate) {
     __shared__ float s_part[16];
     float s = 0.f;
     for (int k = threadIdx.x; k < nparts; k += 1024) s += partial[k];
@@ -959,7 +959,7 @@ __global__ __launch_bounds__(1024) void k_loss_final(const float *__restrict__ p
         for (int w = 0; w < 16; w++) tot += s_part[w];
         const uint32_t cnt = mask_count ? *mask_count : count_host;
         const float L = tot / (float)max(cnt, 1u);
-        loss[0] = L;
+        loss[0] = accumulate ? loss[0] + L : L;   // accumulate: one share of a multi-plan loss
         if (!isfinite(L)) atomicOr(flags, GSF_FLAG_NONFINITE);
         // a step whose keys overflowed the capacity is not counted (its Adam
         // update is skipped too, so it can be repeated after a re-plan)
@@ -1101,22 +1101,29 @@ void launch_loss_l1(hipStream_t s, const float *rgba, const float *target, const
                     float radius_frac, const ViewDesc *views, int nviews, int64_t total_pix,
                     float *dl, float *partial, uint32_t *mask_count, float *loss, uint32_t *flags,
                     int32_t *step_inc, int box, int tile, int tgt_planes, bool alpha_term,
-                    const float *bg) {
+                    const float *bg, uint32_t norm_count, bool accumulate) {
     if (!gaze) box = 0;
     const uint32_t channels = alpha_term ? 4u : 3u;
     const int nb = loss_partials(box ? (int64_t)nviews * box * box : total_pix);
-    if (gaze) {
-        k_fill_u32<<<1, 64, 0, s>>>(mask_count, 1, 0u);
-        const int64_t npix = box ? (int64_t)nviews * box * box : total_pix;
-        k_loss_count<<<std::min(nb, 1024), kLossBlock, 0, s>>>(gaze, radius_frac, views, nviews,
-                                                               total_pix, box, tile, channels, npix,
-                                                               mask_count);
-    }
-    const uint32_t *mc = gaze ? mask_count : nullptr;
-    const uint32_t cnt = (uint32_t)(channels * total_pix);
+    if (gaze && norm_count == 0u)
+        launch_loss_count(s, gaze, radius_frac, views, nviews, total_pix, box, tile, channels,
+                          mask_count);
+    const uint32_t *mc = gaze && norm_count == 0u ? mask_count : nullptr;
+    const uint32_t cnt = norm_count ? norm_count : (uint32_t)(channels * total_pix);
     k_loss_l1<<<nb, kLossBlock, 0, s>>>(rgba, target, gaze, radius_frac, views, nviews, total_pix, box,
                                         tile, tgt_planes, alpha_term, bg, mc, cnt, dl, partial);
-    k_loss_final<<<1, 1024, 0, s>>>(partial, nb, mc, cnt, loss, flags, step_inc);
+    k_loss_final<<<1, 1024, 0, s>>>(partial, nb, mc, cnt, loss, flags, step_inc, accumulate);
+}
+
+void launch_loss_count(hipStream_t s, const float *gaze, float radius_frac, const ViewDesc *views,
+                       int nviews, int64_t total_pix, int box, int tile, uint32_t channels,
+                       uint32_t *mask_count) {
+    const int64_t npix = box ? (int64_t)nviews * box * box : total_pix;
+    const int nb = loss_partials(npix);
+    k_fill_u32<<<1, 64, 0, s>>>(mask_count, 1, 0u);
+    k_loss_count<<<std::min(nb, 1024), kLossBlock, 0, s>>>(gaze, radius_frac, views, nviews,
+                                                           total_pix, box, tile, channels, npix,
+                                                           mask_count);
 }
 
 void launch_draw_bg(hipStream_t s, uint64_t seed, const int32_t *step, int nviews, float *bg) {

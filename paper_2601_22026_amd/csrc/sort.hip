@@ -251,11 +251,14 @@ __global__ __launch_bounds__(1024) void k_scan_top(uint32_t *__restrict__ block_
 // block's offsets in LDS, so one record's many keys are spread over the block
 // and consecutive threads write consecutive addresses.  Within a record the
 // keys run over the box rows, each row's tiles being those its support
-// ellipse reaches (row_span, the rule the projection counted with).
+// ellipse reaches (row_span, the rule the projection counted with): from the
+// packed spans, or from the record's row table, which the thread owning the
+// record writes first (at the record's own key positions) and the key's
+// thread then searches for the key's row.
 __global__ __launch_bounds__(kScanBlock) void k_scan_dup(
     const uint32_t *__restrict__ count, const uint2 *__restrict__ rect,
     const float4 *__restrict__ ell, const uint2 *__restrict__ rspan, SplatPtrs sp,
-    uint32_t *__restrict__ koff, int nrec, int n, int tile,
+    uint32_t *__restrict__ koff, uint2 *rowtab, int nrec, int n, int tile,
     const ViewDesc *__restrict__ views, const uint32_t *__restrict__ block_prefix, int nblocks,
     bool own_prefix, uint32_t *__restrict__ m_dev, unsigned long long *__restrict__ m_total,
     uint32_t *__restrict__ flags, int64_t capacity, uint32_t *__restrict__ keys,
@@ -265,10 +268,7 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_dup(
     __shared__ uint32_t s_off[kScanTile];   // block-local exclusive key offset per record
     __shared__ uint2 s_rect[kScanTile];
     __shared__ int s_view[kScanTile];
-    __shared__ float4 s_e0[kScanTile];        // ellipse: slope, kw, ws, dyr
-    __shared__ float4 s_e1[kScanTile];        // ey, hxo, hyo, -
-    __shared__ int2 s_ixy[kScanTile];
-    __shared__ uint2 s_pack[kScanTile];       // packed row spans (kPackRows rows or fewer)
+    __shared__ uint2 s_pack[kScanTile];       // packed row spans, or (row-table entries, -)
     __shared__ ViewDesc s_views[kMaxViews];   // read per key: kept in LDS, not reloaded from memory
     for (int t = blockIdx.x * kScanBlock + threadIdx.x; t < total_tiles; t += gridDim.x * kScanBlock)
         ranges[t] = make_uint2(0u, 0u);
@@ -334,20 +334,28 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_dup(
             const uint2 rc = rect[r];
             s_rect[i] = rc;
             s_view[i] = (int)(r / (uint32_t)n);
-            const int rows = (int)(rc.y >> 16) - (int)(rc.x >> 16) + 1;
-            const int cols = (int)(rc.y & 0xFFFFu) - (int)(rc.x & 0xFFFFu) + 1;
-            if (rows <= kPackRows && cols <= kPackCols) {
-                s_pack[i] = rspan[r];
-            } else if (rows <= kSpanRows) {
+            const int x0 = (int)(rc.x & 0xFFFFu), y0 = (int)(rc.x >> 16);
+            const int x1 = (int)(rc.y & 0xFFFFu), y1 = (int)(rc.y >> 16);
+            const uint2 pk = rspan[r];
+            s_pack[i] = pk;
+            if (y1 - y0 + 1 > kPackRows || x1 - x0 + 1 > kPackCols) {   // the row table
                 const float4 ea = ell[r], a = sp.a[r], c = sp.c[r];
-                s_e0[i] = ea;
-                s_e1[i] = make_float4(sqrtf(ea.y / ea.z), a.x, a.y, 0.f);
-                s_ixy[i] = make_int2((int)c.z, (int)c.w);
+                const Ellipse e{ea.x, ea.y, ea.z, ea.w, sqrtf(ea.y / ea.z), a.x, a.y, (int)c.z, (int)c.w};
+                const ViewDesc vd = views[r / (uint32_t)n];
+                const int tl = 31 - __clz(tile);
+                uint32_t j = 0, pre = 0;
+                for (int ty = y0; ty <= y1 && j < pk.x; ty++) {
+                    int c0, c1;
+                    if (!row_span(e, ty, tl, vd.width, vd.height, x0, x1, c0, c1)) continue;
+                    rowtab[gbase + off + j] = make_uint2((uint32_t)(ty - y0) | ((uint32_t)c0 << 16), pre);
+                    pre += (uint32_t)(c1 - c0 + 1);
+                    j++;
+                }
             }
         }
         off += cnt[k];
     }
-    __syncthreads();
+    __syncthreads();   // row tables written (the block's own global stores) and LDS filled
     for (uint32_t q = threadIdx.x; q < total; q += kScanBlock) {
         // the last record whose offset is <= q (records without keys share the
         // offset of the next record, so the last one is the owner)
@@ -375,26 +383,16 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_dup(
                 }
                 li -= w;
             }
-        } else if (y1 - y0 + 1 > kSpanRows) {     // the whole box, row by row
-            const uint32_t w = (uint32_t)(x1 - x0 + 1);
-            const uint32_t row = li / w;
-            key = (uint32_t)vd.tile_off + ((uint32_t)y0 + row) * (uint32_t)vd.tiles_x + (uint32_t)x0 +
-                  (li - row * w);
-        } else {
-            const float4 e0 = s_e0[lo], e1 = s_e1[lo];
-            const int2 ixy = s_ixy[lo];
-            const Ellipse e{e0.x, e0.y, e0.z, e0.w, e1.x, e1.y, e1.z, ixy.x, ixy.y};
-            const int tl = 31 - __clz(tile);
-            for (int ty = y0; ty <= y1; ty++) {
-                int c0, c1;
-                if (!row_span(e, ty, tl, vd.width, vd.height, x0, x1, c0, c1)) continue;
-                const uint32_t w = (uint32_t)(c1 - c0 + 1);
-                if (li < w) {
-                    key = (uint32_t)vd.tile_off + (uint32_t)ty * (uint32_t)vd.tiles_x + (uint32_t)c0 + li;
-                    break;
-                }
-                li -= w;
+        } else {   // the last row-table entry whose key prefix is <= li holds key li
+            const uint32_t tb = gbase + s_off[lo];
+            int a = 0, b = (int)s_pack[lo].x - 1;
+            while (a < b) {
+                const int mid = (a + b + 1) >> 1;
+                if (rowtab[tb + (uint32_t)mid].y <= li) a = mid; else b = mid - 1;
             }
+            const uint2 te = rowtab[tb + (uint32_t)a];
+            key = (uint32_t)vd.tile_off + ((uint32_t)y0 + (te.x & 0xFFFFu)) * (uint32_t)vd.tiles_x +
+                  (te.x >> 16) + (li - te.y);
         }
         keys[gbase + q] = key;
         vals[gbase + q] = r;
@@ -778,14 +776,14 @@ int scan_blocks(int64_t nrec) { return (int)((nrec + kScanTile - 1) / kScanTile)
 
 void launch_scan_duplicate(hipStream_t s, const uint32_t *count, const uint2 *rect,
                            const float4 *ell, const uint2 *rspan, SplatPtrs sp, uint32_t *koff,
-                           int nrec, int n, int tile,
+                           uint2 *rowtab, int nrec, int n, int tile,
                            const ViewDesc *views, uint32_t *block_sums, uint32_t *keys,
                            uint32_t *vals, uint32_t *m_dev, unsigned long long *m_total,
                            uint32_t *flags, int64_t capacity, uint2 *ranges, int total_tiles) {
     const int nb = (nrec + kScanTile - 1) / kScanTile;
     const bool own_prefix = nb >= 1 && nb <= kOwnPrefixBlocks;   // else k_scan_top writes the total
     if (!own_prefix) k_scan_top<<<1, 1024, 0, s>>>(block_sums, nb, m_dev, m_total, flags, capacity);
-    k_scan_dup<<<nb, kScanBlock, 0, s>>>(count, rect, ell, rspan, sp, koff, nrec, n, tile, views,
+    k_scan_dup<<<nb, kScanBlock, 0, s>>>(count, rect, ell, rspan, sp, koff, rowtab, nrec, n, tile, views,
                                          block_sums, nb, own_prefix, m_dev, m_total, flags,
                                          capacity, keys, vals, ranges, total_tiles);
 }

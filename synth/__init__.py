@@ -96,6 +96,25 @@ def random_gaussians(n: int, seed: int = SEED_GAUSSIANS, sh_degree: int = 0,
     return _f32(P)
 
 
+def with_near_splats(P: np.ndarray, n_near: int, seed: int = SEED_GAUSSIANS,
+                     depth=(1.0, 1.6), scale=(0.08, 0.25), spread: float = 0.4) -> np.ndarray:
+    """``P`` followed by ``n_near`` large splats close to an axis camera at
+    distance 3 (camera-space depth U[depth], so world z = depth - 3), centred
+    within +-spread of the optical axis, log-scales of U[scale] per axis (so
+    anisotropic), random rotation, opacity logit U[1, 4]; the rest of each
+    column as ``random_gaussians`` draws it.  Their support boxes span tens of
+    tile rows at 8-pixel tiles in a 512-pixel view."""
+    rng = _rng(seed + 1000)
+    Q = random_gaussians(n_near, seed=seed + 1000, sh_degree=int(round(math.sqrt((P.shape[0] - 11) // 3))) - 1)
+    Q = Q.astype(np.float64)
+    Q[0] = rng.uniform(-spread, spread, size=n_near)
+    Q[1] = rng.uniform(-spread, spread, size=n_near)
+    Q[2] = rng.uniform(depth[0], depth[1], size=n_near) - 3.0
+    Q[3:6] = np.log(rng.uniform(scale[0], scale[1], size=(3, n_near)))
+    Q[10] = rng.uniform(1.0, 4.0, size=n_near)
+    return _f32(np.concatenate([np.asarray(P, np.float64), Q], axis=1))
+
+
 def scaled_logscale_mean(n: int) -> float:
     """Log-scale mean that keeps world-space overlap equal to the 1k-Gaussian set."""
     return -3.0 - math.log(n / 1000.0) / 3.0

@@ -27,7 +27,7 @@ def _declared_functions():
 def test_header_declares_the_boundary():
     names = _declared_functions()
     for must in ["gsf_forward", "gsf_backward", "gsf_loss_l1", "gsf_adam", "gsf_step_capture",
-                 "gsf_step_replay", "gsf_plan_create", "gsf_debug_copy"]:
+                 "gsf_step_replay", "gsf_plan_create", "gsf_debug_copy", "gsf_autotune"]:
         assert must in names
 
 
@@ -56,7 +56,8 @@ def test_struct_layouts_match_the_c_header(tmp_path):
     if cc is None:
         pytest.skip("no C compiler")
     structs = {"gsf_camera": _abi.gsf_camera, "gsf_plan_desc": _abi.gsf_plan_desc,
-               "gsf_step_args": _abi.gsf_step_args}
+               "gsf_step_args": _abi.gsf_step_args, "gsf_tune_space": _abi.gsf_tune_space,
+               "gsf_tune_result": _abi.gsf_tune_result}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "gsfit.h"', 'int main(void) {']
     for name, cls in structs.items():
         lines.append(f'printf("{name} size %zu\\n", sizeof({name}));')

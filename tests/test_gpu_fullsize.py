@@ -99,3 +99,87 @@ def test_stereo_workload(ctx):
     log(f"[full] stereo: {wl.P.shape[1]} SH3 Gaussians, two eyes 2064x2208")
     sc = _sampled_parity(ctx, wl.P, wl.cams, 1, per_view=96, seed=13)
     _check_order(sc)
+
+
+_FOVEAL = {}
+
+
+def _foveal():
+    if not _FOVEAL:
+        import bench
+        wl = bench.build_workload("foveal")
+        rng = np.random.default_rng(14)
+        # seeded stand-in targets: only the sign of (image - target) enters the loss
+        tgt = np.concatenate([rng.uniform(0.0, 1.0, size=3 * c.npix).astype(np.float32)
+                              for c in wl.cams])
+        _FOVEAL.update(wl=wl, tgt=tgt)
+    return _FOVEAL["wl"], _FOVEAL["tgt"]
+
+
+@pytest.mark.parametrize("t_mode", [0, 1])
+def test_foveal_workload(ctx, t_mode):
+    """The foveal refinement workload (500,000 Gaussians from the 256^3
+    phantom, 16 views of 1920^2, loss masked to a fovea of radius 0.2 W per
+    view) in the benchmark's launch configuration: one fused device-sized plan,
+    fovea-culled, tile 16, LDS batch 64, the step captured and replayed, with
+    either adjoint transmittance mode the autotuner picks between.  Sampled
+    in-fovea pixels match the oracle's image; the step's masked L1 equals the
+    oracle's loss of the same image; and the gradient of the step's own
+    dL/dRGBA restricted to the sampled pixels matches the oracle's."""
+    import paper_2601_22026_amd as gs
+    wl, tgt = _foveal()
+    P, cams, gaze = wl.P, wl.cams, wl.gaze
+    log(f"[full] foveal: {P.shape[1]} Gaussians, 16 x 1920^2, culled, t_mode {t_mode}")
+    dev = "cuda:0"
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        cfg = gs.FitConfig(lr=0.0, tile=16, lds_batch=64, t_mode=t_mode, fovea_cull=True)
+        params = torch.from_numpy(np.ascontiguousarray(P)).to(dev)
+        fs = gs.FitStep(ctx, params, cams, torch.from_numpy(tgt).to(dev),
+                        torch.from_numpy(np.ascontiguousarray(gaze)).to(dev), cfg=cfg, fused=True)
+        fs.capture()
+        fs.replay()
+        flags, m = fs.poll()
+        assert flags == 0, flags
+        torch.cuda.synchronize()
+        rgba = fs.rgba.cpu().numpy()
+        dl_step = fs.dl.cpu().numpy()
+        loss = float(fs.loss.item())
+    log(f"[full]   keys {m}, loss {loss:.6f}")
+    rng = np.random.default_rng(15 + t_mode)
+    imgs, tgts, dls = [], [], []
+    G = np.zeros_like(P, dtype=np.float64)
+    off = 0
+    for v, cam in enumerate(cams):
+        npx = cam.npix
+        img = rgba[4 * off:4 * (off + npx)].reshape(4, npx)
+        ys, xs = np.divmod(np.arange(npx), cam.width)
+        inside = np.nonzero((xs + 0.5 - gaze[v][0]) ** 2 + (ys + 0.5 - gaze[v][1]) ** 2
+                            <= (0.2 * cam.width) ** 2)[0]
+        covered = inside[img[3, inside] > 0.05]
+        pix = np.sort(rng.choice(covered if covered.size >= 24 else inside, 24, replace=False))
+        ref = oracle.render(P, cam, pixels=pix)
+        nbad, worst, nflag = image_close(img[:, pix], ref.rgba, ref.flags)
+        log(f"[full]   view {v}: {pix.size} in-fovea px, worst {worst:.2e}, flagged {nflag}")
+        assert nbad == 0, (v, worst)
+        keep = pix[ref.flags == 0]
+        d = np.zeros((4, npx), np.float32)
+        d[:, keep] = dl_step[4 * off:4 * (off + npx)].reshape(4, npx)[:, keep]
+        dls.append(d)
+        G += oracle.backward(P, cam, d[:, keep].astype(np.float64), pixels=keep)
+        imgs.append(img.astype(np.float64))
+        tgts.append(tgt[3 * off:3 * (off + npx)].astype(np.float64))
+        off += npx
+    L, _ = oracle.loss_l1(imgs, tgts, cams, gazes=gaze.astype(np.float64), radius_frac=0.2)
+    log(f"[full]   loss {loss:.7f} vs oracle {L:.7f}")
+    assert abs(loss - L) <= 1e-5 * L
+    with torch.cuda.stream(stream):
+        dl_dev = torch.from_numpy(np.concatenate([d.reshape(-1) for d in dls])).to(dev)
+        g = torch.zeros_like(params)
+        fs.plan.backward(params, params.shape[1], fs.cams_dev, dl_dev, g)
+        torch.cuda.synchronize()
+        g = g.cpu().numpy()
+    rep = grads_close(g, G)
+    log(f"[full]   gradient groups {rep}")
+    assert all(nb == 0 for _, nb, _ in rep), rep
+    fs.close()

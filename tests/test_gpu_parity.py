@@ -44,36 +44,60 @@ def test_projection_matches_oracle(ctx):
         assert (err <= 1e-4 * np.abs(r) + 1e-6 * scale).all(), (k, err.max())
 
 
+def _discrete_scenes():
+    yield "3 uneven views", synth.random_gaussians(600, seed=3), [
+        synth.axis_camera(128, 96), synth.look_at_camera([2.0, -1.0, 2.0], width=77, height=53),
+        synth.look_at_camera([0.0, 3.0, 0.2], width=40, height=64)]
+    # boxes of tens of tile rows (over 32 at 8-pixel tiles), listed row by row
+    yield "512^2 + 480x400 with near splats", \
+        synth.with_near_splats(synth.random_gaussians(300, seed=12), 8, seed=12), [
+            synth.axis_camera(512, 512), synth.look_at_camera([1.2, -0.8, -2.6], width=480,
+                                                               height=400)]
+
+
 @pytest.mark.parametrize("tile", [8, 16, 32])
 def test_discrete_stage_bit_exact(ctx, tile):
-    P = synth.random_gaussians(600, seed=3)
-    cams = [synth.axis_camera(128, 96), synth.look_at_camera([2.0, -1.0, 2.0], width=77, height=53),
-            synth.look_at_camera([0.0, 3.0, 0.2], width=40, height=64)]
-    log(f"[parity] discrete stage tile {tile}, 3 uneven views")
-    sc = GpuScene(ctx, P, cams, tile=tile)
-    sc.forward()
-    d = oracle.discrete(P, cams, tile)
-    flagged = np.nonzero(d.rflags != 0)[0]
-    R = sc.n * len(cams)
-    M = d.m
-    keys = sc.debug(_abi.GSF_DBG_KEYS, np.uint32, M + 1024).astype(np.int64)
-    vals = sc.debug(_abi.GSF_DBG_VALS, np.uint32, M + 1024).astype(np.int64)
-    ranges = sc.debug(_abi.GSF_DBG_RANGES, np.uint32, 2 * d.ranges.shape[0]).reshape(-1, 2)
-    # remove the keys of records whose box or depth order is legitimately ambiguous
-    drop_g = np.isin(vals, flagged)
-    drop_o = np.isin(d.vals, flagged)
-    np.testing.assert_array_equal(keys[~drop_g], d.keys[~drop_o])
-    np.testing.assert_array_equal(vals[~drop_g], d.vals[~drop_o])
-    if flagged.size == 0:
-        assert keys.size == M
-        np.testing.assert_array_equal(ranges.astype(np.int64), d.ranges)
-    # sort properties on the GPU output itself; range starts never decrease,
-    # empty tiles included (the checkpointed adjoint numbers its units by them)
-    assert (np.diff(keys) >= 0).all()
-    assert (np.diff(ranges[:, 0].astype(np.int64)) >= 0).all()
-    count = sc.debug(_abi.GSF_DBG_COUNT, np.uint32, R)
-    assert keys.size == int(count.sum())
-    log(f"[parity]   keys {M}, flagged records {flagged.size}")
+    """Keys, values and ranges against the oracle, bit for bit.  Records the
+    oracle flags (a box edge or depth tie within rounding) are removed from both
+    key lists; ranges are compared on every tile no flagged record is listed in
+    on either side (as that tile's list of records), and the GPU's ranges are
+    checked to be the lower and upper bounds of its own sorted keys everywhere."""
+    for name, P, cams in _discrete_scenes():
+        log(f"[parity] discrete stage tile {tile}, {name}")
+        sc = GpuScene(ctx, P, cams, tile=tile)
+        sc.forward()
+        d = oracle.discrete(P, cams, tile)
+        flagged = np.nonzero(d.rflags != 0)[0]
+        R = sc.n * len(cams)
+        M = d.m
+        count = sc.debug(_abi.GSF_DBG_COUNT, np.uint32, R)
+        Mg = int(count.sum())
+        keys = sc.debug(_abi.GSF_DBG_KEYS, np.uint32, Mg).astype(np.int64)
+        vals = sc.debug(_abi.GSF_DBG_VALS, np.uint32, Mg).astype(np.int64)
+        tiles = d.ranges.shape[0]
+        ranges = sc.debug(_abi.GSF_DBG_RANGES, np.uint32, 2 * tiles).reshape(-1, 2).astype(np.int64)
+        assert keys.size == Mg
+        # remove the keys of records whose box or depth order is legitimately ambiguous
+        drop_g = np.isin(vals, flagged)
+        drop_o = np.isin(d.vals, flagged)
+        np.testing.assert_array_equal(keys[~drop_g], d.keys[~drop_o])
+        np.testing.assert_array_equal(vals[~drop_g], d.vals[~drop_o])
+        # ranges: the GPU's own bounds everywhere ...
+        assert (np.diff(keys) >= 0).all()
+        np.testing.assert_array_equal(ranges[:, 0], np.searchsorted(keys, np.arange(tiles), "left"))
+        np.testing.assert_array_equal(ranges[:, 1], np.searchsorted(keys, np.arange(tiles), "right"))
+        # ... and the oracle's lists on every tile untouched by a flagged record
+        touched = np.zeros(tiles, bool)
+        touched[keys[drop_g]] = True
+        touched[d.keys[drop_o]] = True
+        for t in np.nonzero(~touched)[0]:
+            np.testing.assert_array_equal(vals[ranges[t, 0]:ranges[t, 1]],
+                                          d.vals[d.ranges[t, 0]:d.ranges[t, 1]])
+        if flagged.size == 0:
+            assert Mg == M
+            np.testing.assert_array_equal(ranges, d.ranges)
+        log(f"[parity]   keys {M}, flagged records {flagged.size}, tiles compared "
+            f"{int((~touched).sum())} of {tiles}")
 
 
 @pytest.mark.parametrize("planes", [1, 3])
@@ -266,4 +290,30 @@ def test_gradient_of_wide_splats_is_exact_and_reproducible(ctx, t_mode):
     G = oracle.backward(P, cam, dl.astype(np.float32).astype(np.float64))
     rep = grads_close(g1, G)
     log(f"[parity]   gradient groups {rep}")
+    assert all(nb == 0 for _, nb, _ in rep), rep
+
+
+@pytest.mark.parametrize("tile,t_mode", [(8, 0), (8, 1), (16, 2)])
+def test_tall_boxes_image_and_gradient_match_oracle(ctx, tile, t_mode):
+    """Near splats whose support boxes are tens of tile rows tall (over 32 at
+    8-pixel tiles) over a field of small ones in a 512^2 view: every box is
+    listed row by row, the adjoint finds each key's slot through the record's
+    row table, and image and gradient match the oracle."""
+    P = synth.with_near_splats(synth.random_gaussians(300, seed=12), 8, seed=12)
+    cam = synth.axis_camera(512, 512, bg=(0.1, 0.2, 0.3))
+    log(f"[parity] tall boxes 512^2, tile {tile}, t_mode {t_mode}: image and gradient vs oracle")
+    sc = GpuScene(ctx, P, [cam], tile=tile, batch=64, t_mode=t_mode)
+    img = sc.forward()[0]
+    rect = sc.debug(_abi.GSF_DBG_RECT, np.uint32, 2 * sc.n).reshape(-1, 2)
+    rows = (rect[:, 1] >> 16) - (rect[:, 0] >> 16) + 1
+    assert rows.max() > 32 if tile == 8 else rows.max() > 16, rows.max()
+    ref = oracle.render(P, cam)
+    nbad, worst, nflag = image_close(img, ref.rgba, ref.flags)
+    assert nbad == 0, worst
+    dl = np.random.default_rng(8).normal(size=(4, cam.npix))
+    dl[:, ref.flags != 0] = 0.0
+    g = sc.backward([dl])
+    G = oracle.backward(P, cam, dl.astype(np.float32).astype(np.float64))
+    rep = grads_close(g, G)
+    log(f"[parity]   tallest box {int(rows.max())} tile rows, flagged px {nflag}, groups {rep}")
     assert all(nb == 0 for _, nb, _ in rep), rep

@@ -422,3 +422,52 @@ def test_capacity_overflow_skips_the_update_and_replans(gs, ctx):
         rep = grads_close(fs.grads.cpu().numpy(), ref.grads.cpu().numpy().astype(np.float64),
                           rtol=1e-5)
         assert all(nb == 0 for _, nb, _ in rep), rep
+
+
+@pytest.mark.parametrize("masked", [False, True])
+def test_plain_step_equals_fused_step(gs, ctx, masked):
+    """One plain step (a host-synchronised plan per view; the library divides
+    each view's L1 by the entry count over all views and adds the views' losses
+    and gradients) against one fused step over 3 uneven views, with and without
+    a fovea mask and fovea culling: the same image bits (in the fovea when
+    masked), the same loss, gradients within the parity tolerance, and every
+    parameter whose gradient is not tiny moved by Adam to within 1e-6 of the
+    fused step's value."""
+    P = synth.random_gaussians(2500, seed=31)
+    cams = [synth.look_at_camera([0.3, -0.2, -3.0], width=160, height=96),
+            synth.look_at_camera([2.5, 1.0, 1.0], width=112, height=144),
+            synth.look_at_camera([-1.0, 2.6, 1.2], width=128, height=128)]
+    gaze = synth.gaze_points(cams, seed=6) if masked else None
+    gz = torch.from_numpy(np.ascontiguousarray(gaze)).to(DEV) if masked else None
+    rng = np.random.default_rng(32)
+    tgt = torch.from_numpy(np.concatenate([rng.uniform(0, 1, size=3 * c.npix)
+                                           for c in cams]).astype(np.float32)).to(DEV)
+    log(f"[plain] 3 uneven views, masked {masked}: plain step vs fused step")
+    runs = {}
+    for fused in (True, False):
+        cfg = gs.FitConfig(lr=1e-3, tile=16, lds_batch=64, t_mode=1, fovea_cull=masked)
+        fs = gs.FitStep(ctx, torch.from_numpy(P).to(DEV), cams, tgt, gz, cfg=cfg, fused=fused)
+        fs.step()
+        torch.cuda.synchronize()
+        runs[fused] = (fs.loss.item(), fs.rgba.cpu().numpy(), fs.grads.cpu().numpy(),
+                       fs.params.cpu().numpy())
+        fs.close()
+    (lf, imf, gf, pf), (lp, imp, gp, pp) = runs[True], runs[False]
+    log(f"[plain]   loss fused {lf:.8f} plain {lp:.8f}")
+    assert abs(lp - lf) <= 1e-6 * abs(lf)
+    off = 0
+    for v, c in enumerate(cams):
+        a = imf[4 * off:4 * (off + c.npix)].reshape(4, c.npix)
+        b = imp[4 * off:4 * (off + c.npix)].reshape(4, c.npix)
+        keep = np.ones(c.npix, bool)
+        if masked:
+            ys, xs = np.divmod(np.arange(c.npix), c.width)
+            keep = (xs + 0.5 - gaze[v][0]) ** 2 + (ys + 0.5 - gaze[v][1]) ** 2 <= (0.2 * c.width) ** 2
+        np.testing.assert_array_equal(a[:, keep].view(np.uint32), b[:, keep].view(np.uint32))
+        off += c.npix
+    rep = grads_close(gp, gf.astype(np.float64))
+    log(f"[plain]   gradient groups {rep}")
+    assert all(nb == 0 for _, nb, _ in rep), rep
+    big = np.abs(gf) > 1e-3 * np.abs(gf).max()
+    assert big.sum() > 100
+    assert np.abs(pp - pf)[big].max() <= 1e-6

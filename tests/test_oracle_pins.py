@@ -496,6 +496,88 @@ def test_discrete_stage_is_conservative_sorted_and_ranged():
         np.testing.assert_array_equal(d.ranges[:, 1], hi)
 
 
+def _tile_span(e0, e1, size, T):
+    lo, hi = max(0, math.ceil(e0)), min(size - 1, math.floor(e1))
+    return (lo // T, hi // T) if lo <= hi else None
+
+
+def _band_columns(rec, i, ty, T, W, H, cols, nsamp=20001):
+    """Brute force of one tile row's list: the tile columns whose pixel-centre
+    columns lie within 1/64 px of the x extent of the padded support ellipse
+    A x^2 + 2 B x y + C y^2 <= 2 ln(255 o) (1 + 1e-4)^2 over the row's band of
+    pixel-centre rows (clamped to the ellipse's rows).  The extent is the
+    max / min of the ellipse's chord ends, solved from the conic at nsamp
+    evenly spaced band offsets.  Returns ((c0, c1) or None, distance of the
+    nearest pixel-centre column threshold from either end of the extent)."""
+    A, B, C = rec["A"][i], rec["B"][i], rec["C"][i]
+    mx, my = rec["mx"][i], rec["my"][i]
+    Kp = 2.0 * math.log(255.0 * rec["o"][i]) * (1.0 + 1e-4) ** 2
+    ey = math.sqrt(A * Kp / (A * C - B * B))
+    ja, jb = ty * T, min(ty * T + T, H) - 1
+    ya, yb = ja + 0.5 - my, jb + 0.5 - my
+    lo, hi = max(ya, -ey), min(yb, ey)
+    if lo > hi:
+        lo = hi = ey if ya > ey else -ey
+    d = np.linspace(lo, hi, nsamp)
+    root = np.sqrt(np.maximum(B * B * d * d - A * (C * d * d - Kp), 0.0))
+    xr = ((-B * d + root) / A).max() + 1.0 / 64
+    xl = ((-B * d - root) / A).min() - 1.0 / 64
+    ul, ur = mx + xl - 0.5, mx + xr - 0.5          # column i is in when ul <= i <= ur
+    margin = min(abs(ul - round(ul)), abs(ur - round(ur)))
+    a, b = max(math.ceil(ul), 0), min(math.floor(ur), W - 1)
+    if a > b:
+        return None, margin
+    c0, c1 = max(a // T, cols[0]), min(b // T, cols[1])
+    return ((c0, c1) if c0 <= c1 else None), margin
+
+
+@pytest.mark.parametrize("T", [8, 16, 32])
+def test_tile_lists_equal_brute_force_band_extents(T):
+    """Every record's listed tiles, row by row, equal the brute-force band
+    extents of its padded support ellipse, for boxes of every height: a 512^2
+    view holding large near splats whose boxes are tens of tile rows tall, and
+    an oblique view of the same set.  Rows whose extent ends within 1e-4 px of a
+    pixel-centre column (where sampling can decide either way) are skipped and
+    counted."""
+    P = synth.with_near_splats(synth.random_gaussians(150, seed=11), 8, seed=11).astype(np.float64)
+    cams = [synth.axis_camera(512, 512), synth.look_at_camera([1.2, -0.8, -2.6], width=480,
+                                                               height=400)]
+    d = oracle.discrete(P, cams, T)
+    n = P.shape[1]
+    listed = {}
+    for k, v in zip(d.keys, d.vals):
+        listed.setdefault(int(v), set()).add(int(k))
+    tile_base, tallest, rows, skipped = 0, 0, 0, 0
+    for vi, cam in enumerate(cams):
+        rec = oracle.project(P, cam)
+        W, H = cam.width, cam.height
+        tw = (W + T - 1) // T
+        for i in range(n):
+            r = vi * n + i
+            if not rec["valid"][i] or d.rflags[r] & oracle.F_NEAR_BOX:
+                continue
+            cs = _tile_span(rec["ex0"][i], rec["ex1"][i], W, T)
+            rs = _tile_span(rec["ey0"][i], rec["ey1"][i], H, T)
+            if cs is None or rs is None:
+                assert r not in listed
+                continue
+            tallest = max(tallest, rs[1] - rs[0] + 1)
+            got = listed.get(r, set())
+            for ty in range(rs[0], rs[1] + 1):
+                want, margin = _band_columns(rec, i, ty, T, W, H, cs)
+                row = {t - tile_base - ty * tw for t in got if (t - tile_base) // tw == ty}
+                if margin < 1e-4:
+                    skipped += 1
+                    continue
+                rows += 1
+                expect = set() if want is None else set(range(want[0], want[1] + 1))
+                assert row == expect, (vi, i, ty, sorted(row), want)
+            assert all(rs[0] <= (t - tile_base) // tw <= rs[1] for t in got)
+        tile_base += tw * ((H + T - 1) // T)
+    assert tallest > 32 if T == 8 else tallest > 8
+    assert skipped <= 0.01 * rows, (skipped, rows)
+
+
 # ---------------------------------------------------------------- loss and Adam
 
 def test_l1_loss_and_sign_gradient():
