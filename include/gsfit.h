@@ -290,6 +290,24 @@ gsf_status gsf_reproject_warp(gsf_ctx *ctx, const float *rgba, const float *dept
                               int32_t out_width, int32_t out_height, uint64_t *zbuf,
                               float *out_rgba, int32_t *out_src);
 
+/* gsf_reproject_warp without the zbuf argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, a viewer's per-frame
+ * loop, harnesses that forbid allocation).  The z-buffer is a device-resident
+ * array inside the library, one per GPU, of 2048 x 2304 64-bit entries
+ * (36 MiB, held until the process ends): out_width * out_height may not exceed
+ * 4,718,592 (GSF_E_INVALID otherwise; use gsf_reproject_warp then).  Its
+ * address is looked up once per device when a context is created.  This call
+ * allocates nothing; it clears the z-buffer itself each time, writes the same
+ * outputs as gsf_reproject_warp and has the same errors, plus GSF_E_HIP if the
+ * z-buffer's address could not be found.  Every call on one GPU shares that
+ * z-buffer: calls that overlap on one GPU (different streams, or contexts on
+ * different streams) race and must be ordered by the caller. */
+gsf_status gsf_reproject_warp_noalloc(gsf_ctx *ctx, const float *rgba, const float *depth,
+                                      int32_t width, int32_t height, const float *p_old,
+                                      const float *v_old, const float *pos_old, const float *p_new,
+                                      const float *v_new, int32_t out_width, int32_t out_height,
+                                      float *out_rgba, int32_t *out_src);
+
 /* Arguments of one full step: forward, loss, backward, Adam on the parameters. */
 typedef struct gsf_step_args {
     float *params;              /* [C][n]; updated in place by Adam */

@@ -30,6 +30,7 @@ from ._abi import GsfError, gsf_camera, gsf_plan_desc, gsf_step_args, lib
 __all__ = ["GsfError", "Context", "Plan", "rasterize", "adam", "adam_masked", "adam_reset",
            "FitStep", "FitConfig", "autotune", "select_views", "plane_learning_rates", "Refiner",
            "seed_volume", "seed_first_hits", "raymarch", "reproject", "reproject_warp",
+           "reproject_warp_noalloc",
            "pack_cameras", "cameras_to_device", "n_planes", "lib"]
 
 
@@ -697,6 +698,22 @@ def reproject_warp(ctx: Context, rgba: torch.Tensor, depth: torch.Tensor, P_old,
                                        _mat16(P_new), _mat16(V_new), int(out_w), int(out_h),
                                        _ptr(zbuf), _ptr(out), _ptr(src)), "gsf_reproject_warp")
     return out, src
+
+
+def reproject_warp_noalloc(ctx: Context, rgba: torch.Tensor, depth: torch.Tensor, P_old, V_old,
+                           pos_old, P_new, V_new, out_rgba: torch.Tensor, out_src: torch.Tensor):
+    """gsf_reproject_warp_noalloc: reproject_warp into caller-given outputs
+    (out_rgba float32 [4][out_h][out_w], out_src int32 [out_h][out_w]) with the
+    library's device-resident z-buffer; the call allocates no device memory."""
+    H, W = depth.shape
+    out_h, out_w = out_src.shape
+    ctx.use_stream()
+    ctx.check(lib().gsf_reproject_warp_noalloc(ctx.handle, _ptr(rgba), _ptr(depth), int(W), int(H),
+                                               _mat16(P_old), _mat16(V_old), _vec3(pos_old),
+                                               _mat16(P_new), _mat16(V_new), int(out_w), int(out_h),
+                                               _ptr(out_rgba), _ptr(out_src)),
+              "gsf_reproject_warp_noalloc")
+    return out_rgba, out_src
 
 
 def seed_volume(ctx: Context, vol: torch.Tensor, cap: int, seed: int, threshold: float = 1200.0,

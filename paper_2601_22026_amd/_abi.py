@@ -29,7 +29,7 @@ EXPORTED = ["gsf_ctx_create", "gsf_ctx_destroy", "gsf_ctx_set_stream", "gsf_last
             "gsf_seed_volume", "gsf_raymarch", "gsf_adam_masked", "gsf_adam_reset",
             "gsf_view_select", "gsf_reproject", "gsf_reproject_warp",
             "gsf_first_hit_scratch_bytes", "gsf_seed_first_hits", "gsf_loss_count",
-            "gsf_autotune_workspace_bytes", "gsf_autotune"]
+            "gsf_autotune_workspace_bytes", "gsf_autotune", "gsf_reproject_warp_noalloc"]
 STAGES = ["project", "duplicate", "tile_sort", "ranges", "depth_sort", "render", "loss",
           "render_bwd", "project_bwd", "adam", "grad_sum"]
 
@@ -117,6 +117,7 @@ def _declare(L):
                                 f32, f32, f32, f32, pf, pf, f32, i32, ct.c_double, i64, ct.c_uint64,
                                 vp, vp, ct.POINTER(ct.c_int64), vp, ct.c_size_t],
         "gsf_reproject_warp": [vp, vp, vp, i32, i32, pf, pf, pf, pf, pf, i32, i32, vp, vp, vp],
+        "gsf_reproject_warp_noalloc": [vp, vp, vp, i32, i32, pf, pf, pf, pf, pf, i32, i32, vp, vp],
         "gsf_step": [vp, ct.POINTER(gsf_step_args)],
         "gsf_step_capture": [vp, ct.POINTER(gsf_step_args)],
         "gsf_step_replay": [vp],

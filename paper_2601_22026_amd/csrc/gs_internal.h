@@ -498,6 +498,13 @@ bool make_reproj(const float *p_old, const float *v_old, const float *pos_old, c
                  const float *v_new, int width, int height, ReprojConstOpaque *out);
 // clip [4][H][W] of every pixel (NaN where the depth is not finite and positive).
 void launch_reproject(hipStream_t s, const ReprojConstOpaque &k, const float *depth, float *clip);
+// Output pixels the no-allocation warp's device-resident z-buffer holds
+// (2048 x 2304, which covers one 2064 x 2208 head-mounted-display eye).
+constexpr int64_t kWarpScratchPixels = 2048ll * 2304ll;
+constexpr int kMaxDevices = 64;
+// Device address of that z-buffer on `device` (must be current); looked up
+// once per device, the same address returned afterwards.
+hipError_t warp_scratch_address(int device, unsigned long long **out);
 // Forward warp of rgba [4][H][W] to [4][out_h][out_w] (zbuf: out_w * out_h words).
 void launch_reproject_warp(hipStream_t s, const ReprojConstOpaque &k, const float *rgba,
                            const float *depth, int out_w, int out_h, unsigned long long *zbuf,

@@ -29,6 +29,8 @@ struct gsf_ctx {
     int cus = 256;                             // compute units of the device
     hipStream_t stream = nullptr;
     std::string err;
+    unsigned long long *warp_scratch = nullptr;   // device address of the no-allocation z-buffer
+    hipError_t warp_scratch_err = hipSuccess;
 };
 
 namespace {
@@ -516,6 +518,8 @@ gsf_status gsf_ctx_create(int device, void *hip_stream, gsf_ctx **out) {
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
         c->cus = cus;
+    // the no-allocation warp's z-buffer: its address on this device, found once
+    c->warp_scratch_err = warp_scratch_address(device, &c->warp_scratch);
     *out = c;
     return GSF_OK;
 }
@@ -889,6 +893,34 @@ gsf_status gsf_reproject_warp(gsf_ctx *ctx, const float *rgba, const float *dept
                     "gsf_reproject_warp: singular P_old V_old or a non-finite value");
     launch_reproject_warp(ctx->stream, k, rgba, depth, out_width, out_height,
                           (unsigned long long *)zbuf, out_rgba, out_src);
+    GSF_LAUNCHED(ctx);
+    return GSF_OK;
+}
+
+gsf_status gsf_reproject_warp_noalloc(gsf_ctx *ctx, const float *rgba, const float *depth,
+                                      int32_t width, int32_t height, const float *p_old,
+                                      const float *v_old, const float *pos_old, const float *p_new,
+                                      const float *v_new, int32_t out_width, int32_t out_height,
+                                      float *out_rgba, int32_t *out_src) {
+    if (!ctx) return GSF_E_INVALID;
+    if (!rgba || !depth || !p_old || !v_old || !pos_old || !p_new || !v_new || !out_rgba || !out_src)
+        return fail(ctx, GSF_E_INVALID, "gsf_reproject_warp_noalloc: null argument");
+    if (width < 1 || height < 1 || width > 16384 || height > 16384 || out_width < 1 ||
+        out_height < 1 || out_width > 16384 || out_height > 16384)
+        return fail(ctx, GSF_E_INVALID, "gsf_reproject_warp_noalloc: image size out of range");
+    if ((int64_t)out_width * out_height > kWarpScratchPixels)
+        return fail(ctx, GSF_E_INVALID,
+                    "gsf_reproject_warp_noalloc: out_width * out_height exceeds the device "
+                    "z-buffer (2048 * 2304 pixels); use gsf_reproject_warp with a caller buffer");
+    if (ctx->warp_scratch_err != hipSuccess || !ctx->warp_scratch)
+        return fail(ctx, GSF_E_HIP, std::string("gsf_reproject_warp_noalloc: z-buffer address: ") +
+                                        hipGetErrorString(ctx->warp_scratch_err));
+    ReprojConstOpaque k;
+    if (!make_reproj(p_old, v_old, pos_old, p_new, v_new, width, height, &k))
+        return fail(ctx, GSF_E_INVALID,
+                    "gsf_reproject_warp_noalloc: singular P_old V_old or a non-finite value");
+    launch_reproject_warp(ctx->stream, k, rgba, depth, out_width, out_height, ctx->warp_scratch,
+                          out_rgba, out_src);
     GSF_LAUNCHED(ctx);
     return GSF_OK;
 }

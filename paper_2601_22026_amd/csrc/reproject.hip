@@ -12,10 +12,41 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 #include "gs_internal.h"
 
+// The z-buffer of the no-allocation warp (gsf_reproject_warp_noalloc): one per
+// GPU, kWarpScratchPixels 64-bit entries (36 MiB), held until the process
+// ends.  Host code reaches it only through the device address found by
+// warp_scratch_address (the array's name is a host-side stand-in there).
+static __device__ __align__(256) unsigned long long scratch[gsf::kWarpScratchPixels];
+
 namespace gsf {
+namespace {
+
+std::mutex g_scratch_mu;
+unsigned long long *g_scratch_ptr[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+bool g_scratch_done[kMaxDevices] = {};
+
+}  // namespace
+
+// Once per device, with that device current: the device address of `scratch`.
+hipError_t warp_scratch_address(int device, unsigned long long **out) {
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_done[device]) {
+        void *ptr = nullptr;
+        g_scratch_err[device] = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        g_scratch_ptr[device] = g_scratch_err[device] == hipSuccess ? (unsigned long long *)ptr : nullptr;
+        g_scratch_done[device] = true;
+    }
+    *out = g_scratch_ptr[device];
+    return g_scratch_err[device];
+}
+
 namespace {
 
 struct ReprojConst {
