@@ -231,16 +231,26 @@ def time_steps(fn, steps, stream):
     return ev[0].elapsed_time(ev[steps]) / steps, per[len(per) // 2]
 
 
-def hbm_bytes_per_launch(stage, N, R, M, npix, planes, tiles):
+def radix_passes(bits):
+    """Passes of the library's radix sorts: digits of at most 8 bits."""
+    return 0 if bits <= 0 else (bits + 7) // 8
+
+
+def hbm_bytes_per_launch(stage, N, R, M, npix, planes, tiles, A):
     """Algorithmic HBM bytes one launch of a stage must move: N Gaussians,
-    R = N * views records, M keys, npix pixels, `planes` floats per Gaussian."""
-    passes = (max(1, (tiles - 1).bit_length()) + 7) // 8
+    R = N * views records, A of them listing a tile, M keys, npix pixels,
+    `planes` floats per Gaussian."""
+    tile_passes = radix_passes(max(1, (tiles - 1).bit_length()))
     return {
         "project": planes * 4 * N + 88 * R,                   # params in; splat, key, box, count, ellipse, spans
-        "duplicate": 20 * R + 8 * M + 8 * tiles,              # counts (twice), boxes in; first-key offset, pairs out; ranges cleared
-        "tile_sort": passes * 20 * M,                         # per pass: key histogram, pair in, pair out
+        # counts in; slots, depth keys in, (depth, entry) pairs and 32-byte entries out; ranges cleared
+        "duplicate": 4 * R + 48 * A + 8 * tiles,
+        # depth sort of the A entries (per pass: key histogram, pair in, pair out), the
+        # emission's count totals and the emission (sorted entries, 32-byte entries in;
+        # (tile, record) keys out)
+        "depth_sort": radix_passes(31) * 20 * A + 8 * A + 36 * A + 8 * M,
+        "tile_sort": tile_passes * 20 * M,                    # per pass: key histogram, pair in, pair out
         "ranges": 4 * M + 28 * tiles,                         # sorted tile ids in; ranges out; order
-        "depth_sort": 12 * M,                                 # record ids in, depth gather, record ids out
         "render": 40 * M + 24 * npix,                         # splat gather per key; RGBA, T, count out
         "loss": 40 * npix,                                    # RGBA, target in; dL/dRGBA out
         "render_bwd": 76 * M + 24 * npix,                     # splat gather; pixel state in; per-key gradient out
@@ -515,6 +525,9 @@ def main():
                          "transmittance mode (always on for --workload stereo)")
     ap.add_argument("--no-fovea-cull", action="store_true",
                     help="composite full frames even when the loss is masked to a fovea")
+    ap.add_argument("--full-frame", action="store_true",
+                    help="with a fovea-masked loss, also time the captured step without fovea "
+                         "culling (the culling gain)")
     ap.add_argument("--regen-steps", type=int, default=300,
                     help="steps of one regeneration (foveal workload)")
     ap.add_argument("--regen-runs", type=int, default=3)
@@ -645,6 +658,9 @@ def main():
         ms_fused, med_fused = time_steps(one, args.steps, stream)
         flags, M = fused.poll()
         check_flags(flags, "fused captured step")
+        # records that list a tile (the depth sort's input) in the last step
+        A = int((fused.plan.debug(gs._abi.GSF_DBG_COUNT, np.uint32,
+                                  N * len(step_cams)) > 0).sum())
         loss_fused = float(fused.loss.item())
         log(f"[bench] fused+captured: {ms_fused * 1e3:.1f} us/step (median {med_fused * 1e3:.1f}), "
             f"keys {M}, flags {flags}, loss {loss_fused:.5f}")
@@ -678,7 +694,7 @@ def main():
             log(f"[bench] {wl.fit_steps}-step fit: {ms_fit:.1f} ms")
 
         culled_gain = None
-        if cull:
+        if cull and args.full_frame:
             phase("fused captured step over full frames (no fovea culling), for the culling gain")
             fu = fit(dataclasses.replace(cfg, fovea_cull=False))
             fu.capture()
@@ -845,21 +861,21 @@ def main():
                 "us_per_launch": round(stages[dom] * 1e3, 2),
                 "work": {"flops_per_launch": int(flops), **pairs}}
     else:
-        byt = hbm_bytes_per_launch(dom, N, R, M, npix, planes, total_tiles)
+        byt = hbm_bytes_per_launch(dom, N, R, M, npix, planes, total_tiles, A)
         ach = byt / (stages[dom] * 1e-3) / 1e9
         roof = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS,
                 "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": traffic,
                 "us_per_launch": round(stages[dom] * 1e3, 2)}
     stage_roof = {}
     for k, ms in stages.items():
-        byt = hbm_bytes_per_launch(k, N, R, M, npix, planes, total_tiles)
+        byt = hbm_bytes_per_launch(k, N, R, M, npix, planes, total_tiles, A)
         stage_roof[k] = {"us": round(ms * 1e3, 2), "gbs": round(byt / (ms * 1e-3) / 1e9, 1)}
         if k in ("render", "render_bwd"):
             fl = (FLOPS_ALPHA * pairs["visited_fwd"] + FLOPS_FWD_INCLUDED * pairs["included"]
                   if k == "render" else
                   FLOPS_ALPHA * pairs["visited_bwd"] + FLOPS_BWD_INCLUDED * pairs["included"])
             stage_roof[k]["tflops"] = round(fl / (ms * 1e-3) / 1e12, 3)
-    step_bytes = sum(hbm_bytes_per_launch(k, N, R, M, npix, planes, total_tiles) for k in stages)
+    step_bytes = sum(hbm_bytes_per_launch(k, N, R, M, npix, planes, total_tiles, A) for k in stages)
 
     steps_per_s = 1000.0 / ms_fused
     res = {
@@ -881,7 +897,7 @@ def main():
                    "sh_degree": int(round(((planes - 11) // 3) ** 0.5)) - 1,
                    "tile": cfg.tile, "lds_batch": cfg.lds_batch, "t_mode": cfg.t_mode,
                    "fovea_cull": bool(cfg.fovea_cull),
-                   "keys_per_step": M, "form": "fused, hipGraph-captured"},
+                   "keys_per_step": M, "records_with_keys": A, "form": "fused, hipGraph-captured"},
         "median_step_ms": round(med_fused, 4),
         "flags_after_timed_steps": flags,
         "mpix_per_s": round(npix * steps_per_s / 1e6, 1),

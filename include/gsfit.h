@@ -491,13 +491,15 @@ gsf_status gsf_raymarch(gsf_ctx *ctx, const uint16_t *vol, int32_t n, const gsf_
 /* Per-stage GPU timing of eager calls on a plan (hipEvents recorded around each
  * stage on the context stream; not available while capturing).  Enabling
  * resets the accumulators.  Stages holding exactly one kernel: PROJECT,
- * DEPTH_SORT, RENDER, RENDER_BWD, PROJECT_BWD. */
+ * RENDER, RENDER_BWD, PROJECT_BWD. */
 enum {
     GSF_STAGE_PROJECT = 0,     /* projection + support boxes (one kernel) */
-    GSF_STAGE_DUPLICATE = 1,   /* scan of the per-record tile counts + key emission */
+    GSF_STAGE_DUPLICATE = 1,   /* record-order scan of the listed-tile counts (gradient slots,
+                                  key total, the records with keys compacted) */
     GSF_STAGE_TILE_SORT = 2,   /* stable radix sort of the keys by tile */
     GSF_STAGE_RANGES = 3,      /* per-tile ranges from the key boundaries + compositing order */
-    GSF_STAGE_DEPTH_SORT = 4,  /* per-tile stable LDS radix sort by depth (one kernel) */
+    GSF_STAGE_DEPTH_SORT = 4,  /* stable radix sort of the records with keys by depth, then
+                                  their keys emitted in that order */
     GSF_STAGE_RENDER = 5,      /* forward compositing (one kernel) */
     GSF_STAGE_LOSS = 6,        /* masked L1 loss */
     GSF_STAGE_RENDER_BWD = 7,  /* compositing adjoint (one kernel) */

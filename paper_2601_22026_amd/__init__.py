@@ -766,12 +766,22 @@ def measure_keys(ctx: Context, params: torch.Tensor, cams_dev: torch.Tensor, siz
     """Keys one forward of these Gaussians lists at this tile size (a host-sized
     plan; fovea-culled when cull_gaze is given).  Synchronises."""
     n = params.shape[1]
-    probe = Plan(ctx, n, sizes, sh_degree, tile, 64, host_sized=True)
-    out = torch.empty(4 * probe.total_pixels, dtype=torch.float32, device=params.device)
-    probe.forward(params, n, cams_dev, out, cull_gaze, radius_frac)
-    _, m = probe.poll()
-    probe.close()
-    return int(m)
+    cap = 4 * n * len(sizes) + (1 << 20)
+    while True:
+        # the key total a host-sized forward reports is exact even when it exceeds
+        # the capacity, so the probe's workspace can stay modest
+        probe = Plan(ctx, n, sizes, sh_degree, tile, 64, host_sized=True, key_capacity=cap)
+        out = torch.empty(4 * probe.total_pixels, dtype=torch.float32, device=params.device)
+        ctx.use_stream()
+        st = lib().gsf_forward(probe.handle, _ptr(params), int(n), _ptr(cams_dev), _ptr(cull_gaze),
+                               float(radius_frac), _ptr(out))
+        if st not in (_abi.GSF_OK, _abi.GSF_E_CAPACITY):
+            ctx.check(st, "gsf_forward")
+        _, m = probe.poll()
+        probe.close()
+        if m > 0 or st == _abi.GSF_OK:
+            return int(m)
+        cap *= 4   # no total reported: try again with room
 
 
 _TUNE_CACHE: dict = {}

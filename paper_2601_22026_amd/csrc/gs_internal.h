@@ -332,9 +332,22 @@ __device__ __forceinline__ FoveaTiles fovea_tiles(const float *__restrict__ gaze
     const float y0 = fmaxf(floorf(gy - r - 0.5f) - 1.f, 0.f);
     const float y1 = fminf(ceilf(gy + r - 0.5f) + 1.f, (float)(height - 1));
     FoveaTiles f{1, 0, 1, 0};
-    if (x0 <= x1 && y0 <= y1) f = FoveaTiles{(int)x0 / tile, (int)x1 / tile, (int)y0 / tile, (int)y1 / tile};
+    const int tl = __builtin_ctz((unsigned)tile);   // tile: a power of two; x0, y0 >= 0
+    if (x0 <= x1 && y0 <= y1) f = FoveaTiles{(int)x0 >> tl, (int)x1 >> tl, (int)y0 >> tl, (int)y1 >> tl};
     return f;
 }
+
+// Sort keys of a fovea-culled forward: only the tiles of each view's fovea box
+// receive keys, so the key is the tile's place in a compact space instead of
+// its global id - view v's box of box x box tiles (from its first fovea tile)
+// at v box^2, row-major.  The map is increasing in the global id, so sorting
+// by it sorts by tile; the tile ranges are written at the global ids.
+struct TileMap {
+    const float *gaze = nullptr;   // null: keys are global tile ids
+    float radius = 0.f;            // fovea radius as a fraction of the width
+    int box = 0;                   // tiles per side of the compact box
+    int tile = 16;
+};
 
 // ---- launchers (all asynchronous on `s`) -----------------------------------------
 
@@ -345,14 +358,15 @@ __device__ __forceinline__ FoveaTiles fovea_tiles(const float *__restrict__ gaze
 // dyr; ey follows as sqrt(kw / ws)) and the packed row spans of short boxes
 // (other boxes: the number of their rows that list a tile).
 // With cull_gaze (nullable) the rectangle is clipped to the view's
-// fovea tiles (fovea_tiles with cull_radius).  block_sums[b] receives the
-// total count of records 256 b .. 256 b + 255 (scan_blocks(nrec) words), the
-// input of launch_scan_duplicate.
+// fovea tiles (fovea_tiles with cull_radius).  block_sums[b] / block_act[b]
+// receive the total count / the number of records with a nonzero count among
+// records 256 b .. 256 b + 255 (scan_blocks(nrec) words each), the input of
+// launch_scan_records.
 void launch_project_fwd(hipStream_t s, const float *P, int n, int nviews, int deg,
                         const gsf_camera *cams, const ViewDesc *views, int tile, SplatPtrs sp,
                         uint32_t *depth_key, uint2 *rect, uint32_t *count, float4 *ell,
                         uint2 *rspan, const float *cull_gaze, float cull_radius,
-                        uint32_t *block_sums);
+                        uint32_t *block_sums, uint32_t *block_act);
 
 // Parameter gradient from the per-key screen-space gradients the compositing
 // adjoint left in kp: for SH degrees 0-1 summed per record (wave_key_sum) on
@@ -364,33 +378,53 @@ void launch_project_bwd(hipStream_t s, const float *P, int n, int nviews, int de
                         const gsf_camera *cams, const KeyPlace &kp, const float *g2d, float *grads,
                         bool accumulate = false);
 
-// Exclusive scan of the per-record tile counts and key emission in record
-// order (key = global tile id, value = record id).  Writes the key total to
-// m_total and (0 on overflow, with GSF_FLAG_CAPACITY) to m_dev; emits nothing on
-// overflow.  Clears ranges[total_tiles].  block_sums: the per-256-record count
-// totals launch_project_fwd wrote (scan_blocks(nrec) words), scanned in place.
-// rowtab (key capacity entries): the row tables of the boxes not packed.
-void launch_scan_duplicate(hipStream_t s, const uint32_t *count, const uint2 *rect,
-                           const float4 *ell, const uint2 *rspan, SplatPtrs sp, uint32_t *koff,
-                           uint2 *rowtab, int nrec, int n, int tile,
-                           const ViewDesc *views, uint32_t *block_sums, uint32_t *keys,
-                           uint32_t *vals, uint32_t *m_dev, unsigned long long *m_total,
-                           uint32_t *flags, int64_t capacity, uint2 *ranges, int total_tiles);
+// Record-order exclusive scan of the per-record tile counts: koff[r] (record
+// r's gradient slots, its keys in record order), the row tables of the boxes
+// not packed (rowtab, key capacity entries, at those slots), the key total to
+// m_total and (0 on overflow, with GSF_FLAG_CAPACITY) to m_dev; the records with
+// keys compacted in record order: entry e = (dkey = depth bits, dval = e) and
+// arec[2e], arec[2e + 1] = (record, first slot, count, spans.x or row-table
+// size), (box x0 | y0 << 16, x1 | y1 << 16, spans.y, 0); their number to a_dev
+// (0 on overflow).  Clears ranges[total_tiles].  block_sums, block_act: the
+// per-256-record totals launch_project_fwd wrote, scanned in place; seg_tot,
+// seg_act: seg_count(nrec) entries of scratch.
+void launch_scan_records(hipStream_t s, const uint32_t *count, const uint2 *rect, const float4 *ell,
+                         const uint2 *rspan, SplatPtrs sp, const uint32_t *depth_key, uint32_t *koff,
+                         uint2 *rowtab, int nrec, int n, int tile, const ViewDesc *views,
+                         uint32_t *block_sums, uint32_t *block_act, unsigned long long *seg_tot,
+                         uint32_t *seg_act, uint32_t *m_dev, unsigned long long *m_total,
+                         uint32_t *a_dev, uint32_t *flags, int64_t capacity, uint32_t *dkey,
+                         uint32_t *dval, uint4 *arec, uint2 *ranges, int total_tiles);
+// Keys of the a_dev active records in the order dval lists their entries
+// (depth order): key = global tile id, value = record id, each record's keys
+// over its box rows, each row's listed tiles left to right.  block_sums:
+// scratch of scan_blocks(nrec) words, seg_tot of seg_count(nrec).  Emits
+// nothing after a key overflow.
+void launch_emit(hipStream_t s, const uint32_t *dval, const uint32_t *a_dev, const uint4 *arec,
+                 const uint2 *rowtab, int nrec, int n, const ViewDesc *views, int nviews,
+                 uint32_t *block_sums, unsigned long long *seg_tot, const unsigned long long *m_total,
+                 int64_t capacity, const TileMap &tm, uint32_t *keys, uint32_t *vals);
+int seg_count(int64_t nrec);
 int scan_blocks(int64_t nrec);
 
-// Stable LSD radix sort of (key, value) pairs by the low `bits` key bits; the
-// count is read from n_dev (or n_host when n_dev is null).  Passes write a, b,
-// a, ... (b may alias the input); returns 1 when the result is in (ka, va), 2
-// when in (kb, vb).  hist: 256 * grid words; digit_tot: 256 words.
+// Stable LSD radix sort of (key, value) pairs by the low `bits` key bits in
+// radix_passes(bits) passes of at most 8-bit digits; the count is read from
+// n_dev (or n_host when n_dev is null).  Passes write a, b, a, ... (b may alias
+// the input); returns 1 when the result is in (ka, va), 2 when in (kb, vb), 0
+// when no pass ran (the input).  hist: kRadixBins * grid words; digit_tot:
+// kRadixBins words.
 int launch_radix_sort(hipStream_t s, const uint32_t *kin, const uint32_t *vin, uint32_t *ka,
                       uint32_t *va, uint32_t *kb, uint32_t *vb, const uint32_t *n_dev,
                       uint32_t n_host, int bits, int grid, uint32_t *hist, uint32_t *digit_tot);
 int radix_grid_for(int64_t capacity);
+int radix_passes(int bits);
+constexpr int kRadixBins = 256;
 
 // ranges[t] = [lower_bound(t), lower_bound(t + 1)) in the sorted keys for every
-// tile (ranges cleared beforehand).
+// tile (ranges cleared beforehand); keys mapped by tm when it has a gaze.
 void launch_tile_bounds(hipStream_t s, const uint32_t *keys, const uint32_t *m_dev, uint32_t m_host,
-                        int64_t capacity, int total_tiles, uint2 *ranges);
+                        int64_t capacity, int total_tiles, const ViewDesc *views, int nviews,
+                        const TileMap &tm, uint2 *ranges);
 
 // order = all tile ids, tiles with more keys first (by floor(log2(key count)),
 // empty tiles last; order within a class unspecified).  counts: scratch of
@@ -398,13 +432,6 @@ void launch_tile_bounds(hipStream_t s, const uint32_t *keys, const uint32_t *m_d
 void launch_tile_order(hipStream_t s, const uint2 *ranges, int total_tiles, uint32_t *order,
                        uint32_t *counts);
 int order_groups(int64_t total_tiles);
-
-// Stable per-tile sort of vals by depth_key[val], one workgroup per tile in the
-// compositing order (order: a permutation of the tiles); gk0, gk1, gv1:
-// key-capacity scratch for lists longer than the LDS capacity.
-void launch_tile_sort(hipStream_t s, const uint32_t *order, const uint2 *ranges, int total_tiles,
-                      const uint32_t *depth_key, uint32_t *vals, uint32_t *gk0, uint32_t *gk1,
-                      uint32_t *gv1);
 
 // Everything the compositing kernels share.
 struct RenderArgs {

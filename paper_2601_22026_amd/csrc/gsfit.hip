@@ -4,8 +4,10 @@
 // degree, tile size, LDS batch and key capacity, carves the caller-owned
 // workspace into the buffers of the pipeline and enqueues the kernels:
 //
-//   forward   project (+ per-tile key counts) -> scan of the tile counts (ranges)
-//             -> place keys in their tile ranges -> per-tile sort by depth -> composite
+//   forward   project (+ per-record tile counts) -> record-order scan (gradient
+//             slots, key total) -> depth sort of the records with keys -> their keys
+//             emitted in depth order -> stable sort by tile -> tile ranges and
+//             compositing order -> composite
 //   loss      masked L1 -> dL/dRGBA
 //   backward  zero screen-space gradient -> composite adjoint -> projection adjoint
 //   adam      step counter + update
@@ -44,18 +46,27 @@ struct Buffers {
     uint32_t *count = nullptr;                   // listed tiles
     float4 *ell = nullptr;                       // support ellipse constants (Ellipse)
     uint2 *rspan = nullptr;                      // packed row spans of short boxes (else row-table size)
-    uint32_t *koff = nullptr;                    // position of the record's first key
+    uint32_t *koff = nullptr;                    // position of the record's first key (record order)
     uint32_t *block_sums = nullptr;              // scan of the per-record tile counts
+    uint32_t *block_act = nullptr;               // scan of the records that list a tile
+    uint32_t *emit_sums = nullptr;               // scan of the counts in depth order
+    unsigned long long *seg_tot = nullptr;       // segment totals of those scans
+    uint32_t *seg_act = nullptr;
+    uint4 *arec = nullptr;                       // per record with keys: the emission's data (32 B)
     // per global tile
     uint2 *ranges = nullptr;
     uint32_t *order = nullptr;                   // compositing order of the tiles
     uint32_t *order_counts = nullptr;            // per-workgroup class counts of that order
-    // per key (key capacity): two (tile id, record id) buffers for the radix
-    // sort.  After the sort, `vals` is the sorted record-id list the compositing
-    // reads; the rest is scratch for per-tile lists longer than the LDS sort holds.
+    // per key (key capacity): two (key, value) buffer pairs.  The active
+    // records' (depth, record) pairs are sorted in them first (ending in the
+    // depth pair), their keys emitted in depth order into the emission pair,
+    // and the keys sorted by tile between the two; `vals` is then the sorted
+    // record-id list the compositing reads.
     uint32_t *k0 = nullptr, *v0 = nullptr, *k1 = nullptr, *v1 = nullptr;
-    uint32_t *keys = nullptr, *vals = nullptr;   // sorted pair (aliases k0/v0 or k1/v1)
-    uint32_t *ok = nullptr, *ov = nullptr;       // the other pair
+    uint32_t *dsorted = nullptr;                 // depth-ordered active records (values of the depth pair)
+    uint32_t *ek = nullptr, *ev = nullptr;       // emission pair
+    uint32_t *tk = nullptr, *tv = nullptr;       // the other pair
+    uint32_t *keys = nullptr, *vals = nullptr;   // sorted pair (one of the above)
     uint32_t *hist = nullptr, *digit_tot = nullptr;   // radix-sort histograms
     uint2 *rowtab = nullptr;                     // per key position: row tables of boxes not packed
     // per key, at its position in the duplicate pass's order: the adjoint's
@@ -68,7 +79,7 @@ struct Buffers {
     float4 *ckpt = nullptr, *fstate = nullptr;   // checkpointed mode only
     float *tstore = nullptr;                     // stored mode only
     float *g2d = nullptr;
-    uint32_t *m_dev = nullptr, *flags = nullptr, *mask_count = nullptr;
+    uint32_t *m_dev = nullptr, *a_dev = nullptr, *flags = nullptr, *mask_count = nullptr;
     unsigned long long *m_total = nullptr;
     unsigned long long *counters = nullptr;
     float *loss_partial = nullptr;
@@ -78,6 +89,9 @@ struct Buffers {
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Depth keys are float32 bits of positive depths: the sign bit is zero.
+constexpr int kDepthBits = 31;
 
 }  // namespace
 
@@ -155,6 +169,11 @@ size_t carve(gsf_plan *p, char *base, Buffers *out) {
     b.koff = (uint32_t *)take(R * 4);
     const size_t T = (size_t)p->total_tiles;
     b.block_sums = (uint32_t *)take((size_t)scan_blocks(p->nrec_max) * 4);
+    b.block_act = (uint32_t *)take((size_t)scan_blocks(p->nrec_max) * 4);
+    b.emit_sums = (uint32_t *)take((size_t)scan_blocks(p->nrec_max) * 4);
+    b.seg_tot = (unsigned long long *)take((size_t)seg_count(p->nrec_max) * 8);
+    b.seg_act = (uint32_t *)take((size_t)seg_count(p->nrec_max) * 4);
+    b.arec = (uint4 *)take((size_t)std::min<int64_t>(p->nrec_max, p->cap) * 32);
     b.ranges = (uint2 *)take(T * sizeof(uint2));
     b.order = (uint32_t *)take(T * 4);
     b.order_counts = (uint32_t *)take((size_t)33 * order_groups(p->total_tiles) * 4);
@@ -162,14 +181,19 @@ size_t carve(gsf_plan *p, char *base, Buffers *out) {
     b.v0 = (uint32_t *)take((size_t)p->cap * 4);
     b.k1 = (uint32_t *)take((size_t)p->cap * 4);
     b.v1 = (uint32_t *)take((size_t)p->cap * 4);
-    // passes write (k1, v1), (k0, v0), ...: an odd pass count ends in (k1, v1)
-    const bool odd = ((p->tile_bits + 7) / 8) % 2 == 1;
-    b.keys = odd ? b.k1 : b.k0;
-    b.vals = odd ? b.v1 : b.v0;
-    b.ok = odd ? b.k0 : b.k1;
-    b.ov = odd ? b.v0 : b.v1;
-    b.hist = (uint32_t *)take((size_t)256 * p->radix_grid * 4);
-    b.digit_tot = (uint32_t *)take(256 * 4);
+    // radix passes write the first then the second pair given, alternately: the
+    // depth sort starts in (k0, v0), so an odd pass count ends in (k1, v1)
+    const bool depth_in_1 = radix_passes(kDepthBits) % 2 == 1;
+    b.dsorted = depth_in_1 ? b.v1 : b.v0;
+    b.ek = depth_in_1 ? b.k0 : b.k1;
+    b.ev = depth_in_1 ? b.v0 : b.v1;
+    b.tk = depth_in_1 ? b.k1 : b.k0;
+    b.tv = depth_in_1 ? b.v1 : b.v0;
+    const bool tiles_odd = radix_passes(p->tile_bits) % 2 == 1;   // tile sort: (tk, tv) first
+    b.keys = tiles_odd ? b.tk : b.ek;
+    b.vals = tiles_odd ? b.tv : b.ev;
+    b.hist = (uint32_t *)take((size_t)kRadixBins * p->radix_grid * 4);
+    b.digit_tot = (uint32_t *)take(kRadixBins * 4);
     b.rowtab = (uint2 *)take((size_t)p->cap * sizeof(uint2));
     b.pa = (float4 *)take((size_t)p->cap * sizeof(float4));
     b.pb = (float4 *)take((size_t)p->cap * sizeof(float4));
@@ -183,6 +207,7 @@ size_t carve(gsf_plan *p, char *base, Buffers *out) {
     if (p->t_mode == 2) b.tstore = (float *)take((size_t)p->cap * p->tile * p->tile * sizeof(float));
     b.g2d = (float *)take(9 * R * 4);
     b.m_dev = (uint32_t *)take(4);
+    b.a_dev = (uint32_t *)take(4);
     b.flags = (uint32_t *)take(4);
     b.mask_count = (uint32_t *)take(4);
     b.m_total = (unsigned long long *)take(8);
@@ -282,6 +307,17 @@ struct StageTimer {
     }
 };
 
+// Side of the per-view pixel window that holds every tile meeting the fovea
+// (0 when the window would not be smaller than the views).
+int fovea_box(const gsf_plan *p, float radius_frac) {
+    int wmax = 1;
+    for (const ViewDesc &vd : p->views) wmax = std::max(wmax, (int)vd.width);
+    const double r = (double)radius_frac * wmax;
+    const int64_t tiles = (int64_t)std::ceil((2.0 * r + 4.0) / p->tile) + 1;
+    const int64_t side = tiles * p->tile;
+    return side > 0 && (int64_t)p->V * side * side <= p->total_pix ? (int)side : 0;
+}
+
 // cull_gaze (nullable): fovea culling with radius fraction cull_radius.
 gsf_status enqueue_forward(gsf_plan *p, const float *params, int64_t n, const gsf_camera *cams,
                            float *out_rgba, bool *overflow, const float *cull_gaze = nullptr,
@@ -299,16 +335,16 @@ gsf_status enqueue_forward(gsf_plan *p, const float *params, int64_t n, const gs
         StageTimer t(p, GSF_STAGE_PROJECT);
         launch_project_fwd(s, params, (int)n, p->V, p->deg, cams, b.views, p->tile, splats(p),
                            b.depth_key, b.rect, b.count, b.ell, b.rspan, cull_gaze, cull_radius,
-                           b.block_sums);
+                           b.block_sums, b.block_act);
     }
     GSF_LAUNCHED(ctx);
-    {   // one key per touched tile in record order; key total + capacity check on the device
+    {   // record-order scan: gradient slots, row tables, key total + capacity check on
+        // the device; the records with keys compacted with their depths
         StageTimer t(p, GSF_STAGE_DUPLICATE);
-        launch_scan_duplicate(s, b.count, b.rect, b.ell, b.rspan, splats(p), b.koff, b.rowtab,
-                              nrec, (int)n,
-                              p->tile,
-                              b.views, b.block_sums, b.k0, b.v0, b.m_dev, b.m_total, b.flags,
-                              p->cap, b.ranges, (int)p->total_tiles);
+        launch_scan_records(s, b.count, b.rect, b.ell, b.rspan, splats(p), b.depth_key, b.koff,
+                            b.rowtab, nrec, (int)n, p->tile, b.views, b.block_sums, b.block_act,
+                            b.seg_tot, b.seg_act, b.m_dev, b.m_total, b.a_dev, b.flags, p->cap,
+                            b.k0, b.v0, b.arec, b.ranges, (int)p->total_tiles);
     }
     GSF_LAUNCHED(ctx);
     if (p->host_sized) {   // plain path: one host synchronisation per forward
@@ -319,23 +355,44 @@ gsf_status enqueue_forward(gsf_plan *p, const float *params, int64_t n, const gs
         p->m_host = *overflow ? 0u : (uint32_t)total;
     }
     const uint32_t *m_dev = p->host_sized ? nullptr : b.m_dev;
-    {   // stable by tile: each tile's keys stay in record order
+    // fovea culling: keys in the compact space of the views' fovea boxes (fewer
+    // bits to sort) when that space is smaller than the plan's tiles
+    TileMap tm;
+    int sort_bits = p->tile_bits;
+    if (cull_gaze) {
+        const int box = fovea_box(p, cull_radius) / p->tile;
+        const int64_t space = (int64_t)p->V * box * box;
+        if (box > 0 && space < p->total_tiles) {
+            tm = TileMap{cull_gaze, cull_radius, box, p->tile};
+            sort_bits = 0;
+            while ((int64_t(1) << sort_bits) < space) sort_bits++;
+        }
+    }
+    {   // depth order of the records with keys (stable: equal depths keep the
+        // record order), then their keys emitted in that order
+        StageTimer t(p, GSF_STAGE_DEPTH_SORT);
+        const int where = launch_radix_sort(s, b.k0, b.v0, b.k1, b.v1, b.k0, b.v0, b.a_dev, 0u,
+                                            kDepthBits, p->radix_grid, b.hist, b.digit_tot);
+        if ((where == 1 ? b.v1 : b.v0) != b.dsorted)
+            return fail(ctx, GSF_E_STATE, "depth sort pass count does not match the workspace");
+        launch_emit(s, b.dsorted, b.a_dev, b.arec, b.rowtab, nrec, (int)n, b.views, p->V,
+                    b.emit_sums, b.seg_tot, b.m_total, p->cap, tm, b.ek, b.ev);
+    }
+    GSF_LAUNCHED(ctx);
+    {   // stable by tile: each tile's keys stay in (depth, record) order
         StageTimer t(p, GSF_STAGE_TILE_SORT);
         const int grid = p->host_sized ? radix_grid_for(p->m_host) : p->radix_grid;
-        launch_radix_sort(s, b.k0, b.v0, b.k1, b.v1, b.k0, b.v0, m_dev, p->m_host, p->tile_bits,
-                          grid, b.hist, b.digit_tot);
+        const int where = launch_radix_sort(s, b.ek, b.ev, b.tk, b.tv, b.ek, b.ev, m_dev, p->m_host,
+                                            sort_bits, grid, b.hist, b.digit_tot);
+        p->b.keys = where == 1 ? b.tk : b.ek;   // the sorted pair (passes depend on the key space)
+        p->b.vals = where == 1 ? b.tv : b.ev;
     }
     GSF_LAUNCHED(ctx);
     {
         StageTimer t(p, GSF_STAGE_RANGES);
-        launch_tile_bounds(s, b.keys, m_dev, p->m_host, p->cap, (int)p->total_tiles, b.ranges);
+        launch_tile_bounds(s, b.keys, m_dev, p->m_host, p->cap, (int)p->total_tiles, b.views, p->V,
+                           tm, b.ranges);
         launch_tile_order(s, b.ranges, (int)p->total_tiles, b.order, b.order_counts);
-    }
-    GSF_LAUNCHED(ctx);
-    {   // each tile's list by (depth, record); the sorted tile ids are free scratch now
-        StageTimer t(p, GSF_STAGE_DEPTH_SORT);
-        launch_tile_sort(s, b.order, b.ranges, (int)p->total_tiles, b.depth_key, b.vals, b.keys, b.ok,
-                         b.ov);
     }
     GSF_LAUNCHED(ctx);
     {
@@ -357,17 +414,6 @@ gsf_status enqueue_forward(gsf_plan *p, const float *params, int64_t n, const gs
 // required) - a window of box x box pixels per view, when that is smaller.
 // tgt_planes 4: RGBA targets composited over bg (nullable) with an alpha term
 // when alpha_term.
-// Side of the per-view pixel window that holds every tile meeting the fovea
-// (0 when the window would not be smaller than the views).
-int fovea_box(const gsf_plan *p, float radius_frac) {
-    int wmax = 1;
-    for (const ViewDesc &vd : p->views) wmax = std::max(wmax, (int)vd.width);
-    const double r = (double)radius_frac * wmax;
-    const int64_t tiles = (int64_t)std::ceil((2.0 * r + 4.0) / p->tile) + 1;
-    const int64_t side = tiles * p->tile;
-    return side > 0 && (int64_t)p->V * side * side <= p->total_pix ? (int)side : 0;
-}
-
 gsf_status enqueue_loss(gsf_plan *p, const float *rgba, const float *target, const float *gaze,
                         float radius_frac, float *loss, float *dl, int32_t *step_inc,
                         bool cull = false, int tgt_planes = 3, bool alpha_term = false,

@@ -249,18 +249,6 @@ __device__ __forceinline__ uint32_t project_record(const float *__restrict__ P, 
         count[r] = 0u;
         return 0u;
     }
-    float d[3], inv_norm;
-    view_dir<DEG>(g, cam, d, inv_norm);
-    float Y[16];
-    sh_basis<DEG>(d[0], d[1], d[2], Y);
-    float col[3];
-#pragma unroll
-    for (int ch = 0; ch < 3; ch++) {
-        float acc = 0.f;
-#pragma unroll
-        for (int k = 0; k < K; k++) acc = fmaf(P[(size_t)(11 + 3 * k + ch) * n + i], Y[k], acc);
-        col[ch] = fmaxf(acc + 0.5f, 0.f);
-    }
     // pixel mean in double precision (camera transform included), stored as an
     // integer pixel plus the offset of the mean from that pixel's centre
     double td[3];
@@ -276,32 +264,56 @@ __device__ __forceinline__ uint32_t project_record(const float *__restrict__ P, 
     const float k2 = 2.f * logf(255.f * g.o);
     const float hx = fmaf(sqrtf(k2 * p.a), 1.f + kBoxRel, kBoxAbs);
     const float hy = fmaf(sqrtf(k2 * p.c), 1.f + kBoxRel, kBoxAbs);
+    const ViewDesc vd = views[v];
+    const float x0 = fmaxf(ceilf((float)(mxd - hx - 0.5)), 0.f);
+    const float x1 = fminf(floorf((float)(mxd + hx - 0.5)), (float)(vd.width - 1));
+    const float y0 = fmaxf(ceilf((float)(myd - hy - 0.5)), 0.f);
+    const float y1 = fminf(floorf((float)(myd + hy - 0.5)), (float)(vd.height - 1));
+    const bool empty = !(x0 <= x1) || !(y0 <= y1);
+    uint32_t tx0 = 0u, tx1 = 0u, ty0 = 0u, ty1 = 0u;
+    FoveaTiles f{0, -1, 0, -1};
+    bool away = false;   // fovea culling: the box meets no tile of the fovea
+    if (!empty) {
+        tx0 = (uint32_t)x0 / tile;
+        tx1 = (uint32_t)x1 / tile;
+        ty0 = (uint32_t)y0 / tile;
+        ty1 = (uint32_t)y1 / tile;
+        if (cull_gaze) {
+            f = fovea_tiles(cull_gaze, v, cull_radius, vd.width, vd.height, tile);
+            away = f.tx0 > f.tx1 || (int)tx1 < f.tx0 || (int)tx0 > f.tx1 || (int)ty1 < f.ty0 ||
+                   (int)ty0 > f.ty1;
+        }
+    }
+    depth_key[r] = __float_as_uint(p.t[2]);
+    if (away) {   // never read: no colour, no splat record
+        rect[r] = make_uint2(0u, 0u);
+        count[r] = 0u;
+        return 0u;
+    }
+    float d[3], inv_norm;
+    view_dir<DEG>(g, cam, d, inv_norm);
+    float Y[16];
+    sh_basis<DEG>(d[0], d[1], d[2], Y);
+    float col[3];
+#pragma unroll
+    for (int ch = 0; ch < 3; ch++) {
+        float acc = 0.f;
+#pragma unroll
+        for (int k = 0; k < K; k++) acc = fmaf(P[(size_t)(11 + 3 * k + ch) * n + i], Y[k], acc);
+        col[ch] = fmaxf(acc + 0.5f, 0.f);
+    }
     // conic pre-scaled for a base-2 exponent, and the alpha threshold of the
     // same exponent: o 2^power2 >= 1/255 where power2 >= tau = -log2(255 o)
     sp.a[r] = make_float4((float)(ixd + 0.5 - mxd), (float)(iyd + 0.5 - myd), (-0.5f * kLog2e) * p.A,
                           -kLog2e * p.B);
     sp.b[r] = make_float4((-0.5f * kLog2e) * p.C, g.o, col[0], col[1]);
     sp.c[r] = make_float4(col[2], -log2f(255.f * g.o), (float)ixd, (float)iyd);
-    depth_key[r] = __float_as_uint(p.t[2]);
-    const ViewDesc vd = views[v];
-    const float x0 = fmaxf(ceilf((float)(mxd - hx - 0.5)), 0.f);
-    const float x1 = fminf(floorf((float)(mxd + hx - 0.5)), (float)(vd.width - 1));
-    const float y0 = fmaxf(ceilf((float)(myd - hy - 0.5)), 0.f);
-    const float y1 = fminf(floorf((float)(myd + hy - 0.5)), (float)(vd.height - 1));
-    if (!(x0 <= x1) || !(y0 <= y1)) {
+    if (empty) {
         rect[r] = make_uint2(0u, 0u);
         count[r] = 0u;
         return 0u;
     }
-    uint32_t tx0 = (uint32_t)x0 / tile, tx1 = (uint32_t)x1 / tile;
-    uint32_t ty0 = (uint32_t)y0 / tile, ty1 = (uint32_t)y1 / tile;
     if (cull_gaze) {   // only the tiles that meet the fovea are composited
-        const FoveaTiles f = fovea_tiles(cull_gaze, v, cull_radius, vd.width, vd.height, tile);
-        if (f.tx0 > f.tx1 || (int)tx1 < f.tx0 || (int)tx0 > f.tx1 || (int)ty1 < f.ty0 || (int)ty0 > f.ty1) {
-            rect[r] = make_uint2(0u, 0u);
-            count[r] = 0u;
-            return 0u;
-        }
         tx0 = max(tx0, (uint32_t)f.tx0);
         tx1 = min(tx1, (uint32_t)f.tx1);
         ty0 = max(ty0, (uint32_t)f.ty0);
@@ -350,17 +362,25 @@ __global__ __launch_bounds__(256) void k_project_fwd(const float *__restrict__ P
                                                      float4 *__restrict__ ell,
                                                      uint2 *__restrict__ rspan,
                                                      const float *__restrict__ cull_gaze,
-                                                     float cull_radius, uint32_t *__restrict__ block_sums) {
-    __shared__ uint32_t s_w[4];
+                                                     float cull_radius, uint32_t *__restrict__ block_sums,
+                                                     uint32_t *__restrict__ block_act) {
+    __shared__ uint32_t s_w[4], s_a[4];
     const int r = blockIdx.x * 256 + (int)threadIdx.x;
     uint32_t c = r < nrec ? project_record<DEG>(P, n, r, cams, views, tile, sp, depth_key, rect, count,
                                                 ell, rspan, cull_gaze, cull_radius)
                           : 0u;
+    const uint32_t a = (uint32_t)__popcll(__ballot(c != 0u));   // records that list a tile
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
-    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = c;
+    if ((threadIdx.x & 63) == 0) {
+        s_w[threadIdx.x >> 6] = c;
+        s_a[threadIdx.x >> 6] = a;
+    }
     __syncthreads();
-    if (threadIdx.x == 0) block_sums[blockIdx.x] = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+    if (threadIdx.x == 0) {
+        block_sums[blockIdx.x] = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+        block_act[blockIdx.x] = s_a[0] + s_a[1] + s_a[2] + s_a[3];
+    }
 }
 
 // d(quaternion)/... from d(R) for the rotation of a unit quaternion (w, x, y, z).
@@ -546,14 +566,14 @@ void launch_project_fwd(hipStream_t s, const float *P, int n, int nviews, int de
                         const gsf_camera *cams, const ViewDesc *views, int tile, SplatPtrs sp,
                         uint32_t *depth_key, uint2 *rect, uint32_t *count, float4 *ell,
                         uint2 *rspan, const float *cull_gaze, float cull_radius,
-                        uint32_t *block_sums) {
+                        uint32_t *block_sums, uint32_t *block_act) {
     const int nrec = n * nviews;
     const dim3 grid((nrec + 255) / 256), block(256);
     switch (deg) {
-    case 0: k_project_fwd<0><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rect, count, ell, rspan, cull_gaze, cull_radius, block_sums); break;
-    case 1: k_project_fwd<1><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rect, count, ell, rspan, cull_gaze, cull_radius, block_sums); break;
-    case 2: k_project_fwd<2><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rect, count, ell, rspan, cull_gaze, cull_radius, block_sums); break;
-    default: k_project_fwd<3><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rect, count, ell, rspan, cull_gaze, cull_radius, block_sums); break;
+    case 0: k_project_fwd<0><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rect, count, ell, rspan, cull_gaze, cull_radius, block_sums, block_act); break;
+    case 1: k_project_fwd<1><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rect, count, ell, rspan, cull_gaze, cull_radius, block_sums, block_act); break;
+    case 2: k_project_fwd<2><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rect, count, ell, rspan, cull_gaze, cull_radius, block_sums, block_act); break;
+    default: k_project_fwd<3><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rect, count, ell, rspan, cull_gaze, cull_radius, block_sums, block_act); break;
     }
 }
 

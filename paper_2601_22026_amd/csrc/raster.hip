@@ -814,9 +814,9 @@ __global__ void k_zero_u64(unsigned long long *p, int n) {
 
 constexpr int kLossBlock = 256;
 
-__device__ __forceinline__ int view_of_pixel(const ViewDesc *__restrict__ views, int nviews, int64_t p) {
+__device__ __forceinline__ int view_of_pixel(const ViewDesc *__restrict__ views, int nviews, uint32_t p) {
     int v = 0;
-    while (v + 1 < nviews && p >= views[v + 1].pix_off) v++;
+    while (v + 1 < nviews && p >= (uint32_t)views[v + 1].pix_off) v++;
     return v;
 }
 
@@ -830,8 +830,8 @@ __device__ __forceinline__ bool in_fovea(const float *__restrict__ gaze, int v, 
 // Pixel p of a loss launch: every pixel of every view (box == 0), or pixel p of
 // view p / box^2's box x box window that starts at its first fovea tile
 // (fovea culling; false for window pixels outside the view or past its last
-// fovea tile).
-__device__ __forceinline__ bool loss_pixel(int64_t p, int64_t total_pix, int box, int tile,
+// fovea tile).  Plans hold fewer than 2^31 pixels: 32-bit index arithmetic.
+__device__ __forceinline__ bool loss_pixel(uint32_t p, uint32_t total_pix, int box, int tile,
                                            const float *__restrict__ gaze, float radius_frac,
                                            const ViewDesc *__restrict__ views, int nviews, int &v,
                                            int &x, int &y) {
@@ -839,20 +839,21 @@ __device__ __forceinline__ bool loss_pixel(int64_t p, int64_t total_pix, int box
         if (p >= total_pix) return false;
         v = view_of_pixel(views, nviews, p);
         const ViewDesc vd = views[v];
-        const int q = (int)(p - vd.pix_off);
-        y = q / vd.width;
-        x = q - y * vd.width;
+        const uint32_t q = p - (uint32_t)vd.pix_off;
+        y = (int)(q / (uint32_t)vd.width);
+        x = (int)(q - (uint32_t)y * (uint32_t)vd.width);
         return true;
     }
-    const int64_t area = (int64_t)box * box;
+    const uint32_t area = (uint32_t)box * (uint32_t)box;
     v = (int)(p / area);
     if (v >= nviews) return false;
-    const int l = (int)(p - (int64_t)v * area);
+    const uint32_t l = p - (uint32_t)v * area;
     const ViewDesc vd = views[v];
     const FoveaTiles f = fovea_tiles(gaze, v, radius_frac, vd.width, vd.height, tile);
     if (f.tx0 > f.tx1) return false;
-    x = f.tx0 * tile + l % box;
-    y = f.ty0 * tile + l / box;
+    const uint32_t ly = l / (uint32_t)box;
+    x = f.tx0 * tile + (int)(l - ly * (uint32_t)box);
+    y = f.ty0 * tile + (int)ly;
     return x < vd.width && y < vd.height && x < (f.tx1 + 1) * tile && y < (f.ty1 + 1) * tile;
 }
 
@@ -868,11 +869,12 @@ __global__ __launch_bounds__(kLossBlock) void k_loss_count(const float *__restri
     // grid-stride over the launch's pixels: one LDS atomic per wave and step,
     // one global atomic per workgroup (atomics on one address serialise, so
     // their number is kept to the grid's)
-    for (int64_t p0 = (int64_t)blockIdx.x * kLossBlock; p0 < npix; p0 += (int64_t)gridDim.x * kLossBlock) {
-        const int64_t p = p0 + threadIdx.x;
+    for (uint32_t p0 = blockIdx.x * kLossBlock; p0 < (uint32_t)npix; p0 += gridDim.x * kLossBlock) {
+        const uint32_t p = p0 + threadIdx.x;
         int v, x, y;
         bool in = false;
-        if (p < npix && loss_pixel(p, total_pix, box, tile, gaze, radius_frac, views, nviews, v, x, y)) {
+        if (p < (uint32_t)npix &&
+            loss_pixel(p, (uint32_t)total_pix, box, tile, gaze, radius_frac, views, nviews, v, x, y)) {
             const ViewDesc vd = views[v];
             in = in_fovea(gaze, v, x, y, radius_frac * (float)vd.width);
         }
@@ -896,10 +898,10 @@ __global__ __launch_bounds__(kLossBlock) void k_loss_l1(
     float *__restrict__ partial) {
     __shared__ float s_red[kLossBlock / 64];
     const uint32_t cnt = mask_count ? *mask_count : count_host;
-    const int64_t p = (int64_t)blockIdx.x * kLossBlock + threadIdx.x;
+    const uint32_t p = blockIdx.x * kLossBlock + threadIdx.x;
     float s = 0.f;
     int v, x, y;
-    if (loss_pixel(p, total_pix, box, tile, gaze, radius_frac, views, nviews, v, x, y)) {
+    if (loss_pixel(p, (uint32_t)total_pix, box, tile, gaze, radius_frac, views, nviews, v, x, y)) {
         const ViewDesc vd = views[v];
         const int q = y * vd.width + x;
         const size_t plane = (size_t)vd.width * vd.height;

@@ -1,28 +1,30 @@
 // sort.hip - the discrete stage of tile-based splatting: one key per
-// (tile, record) pair whose support box touches the tile, ordered by
+// (tile, record) pair whose support ellipse reaches the tile, ordered by
 // (global tile, camera depth, record), and per-tile [start, end) ranges.
 //
-//   1. scan + duplicate: an exclusive scan of the records' touched-tile counts
-//      (record order; the projection writes each 256-record block's total)
-//      places every record's keys; key = global tile id,
-//      value = record id.  The total is checked against the key capacity on the
-//      device.  No global atomics: counters with thousands of writers serialise
-//      badly across the XCDs of this chip.
-//   2. a stable least-significant-digit radix sort of the keys by tile id
-//      (8-bit digits, ceil(log2(tiles)) bits): a fixed grid of G workgroups,
-//      each owning one contiguous chunk whose size follows from the key count
-//      read on the device (graph capture).  Per pass: per-workgroup digit
+//   1. record scan: an exclusive scan of the records' listed-tile counts in
+//      record order (the projection writes each 256-record block's total) gives
+//      each record its run of gradient slots (koff, where the adjoint stores the
+//      per-key gradients and a record's row table lives); the key total is
+//      checked against the capacity on the device; the records that list a tile
+//      are compacted with their float32 depth bits.  No global atomics:
+//      counters with thousands of writers serialise badly across the XCDs.
+//   2. depth sort: a stable least-significant-digit radix sort of those
+//      (depth bits, record) pairs (31 bits: depths are positive), so equal
+//      depths keep the record order;
+//   3. emission: every record's keys (key = global tile id, value = record id)
+//      written in that depth order, placed by a second scan of the counts;
+//   4. a stable LSD radix sort of the keys by tile id: each tile's list then
+//      holds its records in (depth, record) order with no per-tile sort.
+//      Both sorts use a fixed grid of G workgroups, each owning one contiguous
+//      chunk whose size follows from the count read on the device (graph
+//      capture).  Per pass of a digit of at most 11 bits: per-workgroup digit
 //      histograms (per-wave LDS sub-histograms), a column scan per digit, and a
-//      scatter that ranks each wave's 64 keys with 8 ballots (peer masks) and
-//      combines the waves in order (stable);
-//   3. tile ranges from the boundaries of the sorted keys;
-//   4. one workgroup per tile sorts its list by the float32 depth bits, equal
-//      depths keeping the record order the list has on entry: lists of at most
-//      256 keys are ranked (each entry counts the entries before it), longer
-//      ones run the same stable LDS ranking as the tile sort (4 passes, skipped
-//      when a digit is uniform), on global scratch beyond the LDS capacity.
-// Depth bits of positive floats order like the floats, so the result is the
-// (tile, depth, record) order.
+//      scatter that ranks each wave's 64 keys with one ballot per digit bit
+//      (peer masks) and combines the waves in order (stable);
+//   5. tile ranges from the boundaries of the sorted keys, and the compositing
+//      order (tiles with more keys first).
+// Depth bits of positive floats order like the floats.
 #include "gs_internal.h"
 
 namespace gsf {
@@ -32,13 +34,13 @@ constexpr int kSortBlock = 256;              // threads per radix-sort workgroup
 constexpr int kSortIpt = 8;                  // keys per thread per chunk tile
 constexpr int kSortTile = kSortBlock * kSortIpt;
 constexpr int kSortMaxGrid = 1024;
+constexpr int kMaxDigit = 8;                 // radix digits of at most 256 bins
 constexpr int kScanBlock = 256;
 constexpr int kScanIpt = 1;                  // 256 records per block: 50k records fill 196 blocks
 constexpr int kScanTile = kScanBlock * kScanIpt;
 static_assert(kScanTile == 256, "the projection writes the count totals of 256-record blocks");
-constexpr int kOwnPrefixBlocks = 1024;       // up to this many scan blocks, each sums its own prefix (no k_scan_top)
-constexpr int kTileSortBlock = 256;
-constexpr int kTileSortLds = 1024;           // list length sorted in LDS (22 KB: 7 workgroups per CU); longer lists use global scratch
+constexpr int kOwnPrefixBlocks = 1024;       // up to this many scan blocks, each sums its own prefix (no k_seg_scan)
+constexpr int kSegBlocks = 1024;             // block totals per segment of k_seg_scan
 
 __device__ __forceinline__ uint32_t chunk_size(uint32_t n, int G) {
     const uint32_t per = (n + (uint32_t)G - 1u) / (uint32_t)G;
@@ -70,7 +72,8 @@ __device__ __forceinline__ uint32_t block_excl_scan_256(uint32_t x, uint32_t *s_
     return base + inc - x;
 }
 
-// ---- 2. stable radix sort by tile id ------------------------------------------
+// ---- stable LSD radix sort of (key, value) pairs ------------------------------------
+// A pass sorts by a digit of `bits` <= 8 bits at `shift`.
 
 __global__ __launch_bounds__(kSortBlock) void k_radix_hist(const uint32_t *__restrict__ keys,
                                                            const uint32_t *__restrict__ n_dev,
@@ -117,14 +120,21 @@ __global__ __launch_bounds__(256) void k_radix_colscan(uint32_t *__restrict__ hi
     if (threadIdx.x == 0) digit_tot[blockIdx.x] = total;
 }
 
+// Each workgroup ranks its chunk a round of up to kSortTile keys at a time,
+// reorders the round by digit in LDS (stable) and then writes it out in that
+// order: consecutive threads write consecutive addresses within each digit's
+// run, so the stores coalesce.
 __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(
     const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout,
     uint32_t *__restrict__ vout, const uint32_t *__restrict__ n_dev, uint32_t n_host, int shift,
     int bits, const uint32_t *__restrict__ hist, const uint32_t *__restrict__ digit_tot, int G) {
-    __shared__ uint32_t s_base[256];
+    __shared__ uint32_t s_base[256];      // next global position of each digit
+    __shared__ uint32_t s_loc[256];       // first local position of each digit in the round
     __shared__ uint32_t s_cnt[4][256];
     __shared__ uint32_t s_tot[256];
     __shared__ uint32_t s_wave[4];
+    __shared__ uint32_t s_key[kSortTile];
+    __shared__ uint32_t s_val[kSortTile];
     const uint32_t n = n_dev ? *n_dev : n_host;
     const uint32_t chunk = chunk_size(n, G);
     const uint32_t start = min(n, (uint32_t)blockIdx.x * chunk);
@@ -138,11 +148,10 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(
         const uint32_t dp = block_excl_scan_256(tot, s_wave, all);
         if (t < nd) s_base[t] = dp + hist[(size_t)t * G + blockIdx.x];
     }
-    // Each pass over the chunk takes up to kSortTile keys; wave w ranks the
-    // contiguous run [wbase, wbase + span) of them, span being the fewest whole
-    // rounds of 64 that cover the keys left, so a short chunk still spreads over
-    // the four waves (earlier waves hold earlier keys, as the in-order
-    // combination needs).
+    // Each round takes up to kSortTile keys; wave w ranks the contiguous run
+    // [wbase, wbase + span) of them, span being the fewest whole rounds of 64
+    // that cover the keys left, so a short chunk still spreads over the four
+    // waves (earlier waves hold earlier keys, as the in-order combination needs).
     for (uint32_t tile0 = start, span; tile0 < end; tile0 += 4u * span) {
         const uint32_t left = end - tile0;
         span = min(64u * kSortIpt, (left + 255u) / 256u * 64u);
@@ -173,8 +182,8 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(
             rank[r] = base + below;
         }
         __syncthreads();
-        if (t < nd) {   // combine the waves of this tile in order, per digit
-            uint32_t run = 0;
+        uint32_t run = 0;   // combine the waves of this round in order, per digit
+        if (t < nd) {
 #pragma unroll
             for (int k = 0; k < 4; k++) {
                 const uint32_t c = s_cnt[k][t];
@@ -183,17 +192,28 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(
             }
             s_tot[t] = run;
         }
+        uint32_t nround;
+        const uint32_t loc = block_excl_scan_256(t < nd ? run : 0u, s_wave, nround);
+        if (t < nd) s_loc[t] = loc;
         __syncthreads();
 #pragma unroll
-        for (int r = 0; r < kSortIpt; r++) {
+        for (int r = 0; r < kSortIpt; r++) {   // the round in digit order, in LDS
             if (r >= rounds) break;
             const uint32_t idx = wbase + (uint32_t)r * 64u + (uint32_t)lane;
             if (idx < end) {
                 const uint32_t d = (key[r] >> shift) & mask;
-                const uint32_t pos = s_base[d] + s_cnt[w][d] + rank[r];
-                kout[pos] = key[r];
-                vout[pos] = val[r];
+                const uint32_t lp = s_loc[d] + s_cnt[w][d] + rank[r];
+                s_key[lp] = key[r];
+                s_val[lp] = val[r];
             }
+        }
+        __syncthreads();
+        for (uint32_t p = (uint32_t)t; p < nround; p += kSortBlock) {
+            const uint32_t k = s_key[p];
+            const uint32_t d = (k >> shift) & mask;
+            const uint32_t pos = s_base[d] + (p - s_loc[d]);
+            kout[pos] = k;
+            vout[pos] = s_val[p];
         }
         __syncthreads();
         if (t < nd) s_base[t] += s_tot[t];
@@ -201,201 +221,322 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(
     }
 }
 
-// ---- 1. scan of the touched-tile counts + key duplication (record order) -------
+// ---- 1. scans of the touched-tile counts, depth order, key emission ------------------
 
-// The per-block totals of the counts (256 records a block) come from the
-// projection kernel, which computes the counts.
-
-__global__ __launch_bounds__(1024) void k_scan_top(uint32_t *__restrict__ block_sums, int nblocks,
-                                                   uint32_t *__restrict__ m_dev,
-                                                   unsigned long long *__restrict__ m_total,
-                                                   uint32_t *__restrict__ flags, int64_t capacity) {
-    __shared__ unsigned long long s_part[1024];
-    const int per = (nblocks + 1023) / 1024;
-    const int base = threadIdx.x * per;
-    unsigned long long sum = 0;
-    for (int k = 0; k < per; k++)
-        if (base + k < nblocks) sum += block_sums[base + k];
-    s_part[threadIdx.x] = sum;
-    __syncthreads();
-    // Hillis-Steele inclusive scan of the 1024 partial sums
-    for (int o = 1; o < 1024; o <<= 1) {
-        const unsigned long long y = threadIdx.x >= (unsigned)o ? s_part[threadIdx.x - o] : 0ull;
-        __syncthreads();
-        s_part[threadIdx.x] += y;
-        __syncthreads();
-    }
-    unsigned long long run = s_part[threadIdx.x] - sum;
-    for (int k = 0; k < per; k++)
-        if (base + k < nblocks) {
-            const uint32_t c = block_sums[base + k];
-            block_sums[base + k] = (uint32_t)min(run, 0xFFFFFFFFull);
-            run += c;
+// Top level of the two-level scans when there are more blocks than each block
+// can sum itself: one workgroup per segment of kSegBlocks block totals scans its
+// segment in place (exclusive, coalesced) and writes the segment's totals;
+// each block then adds the totals of the segments before its own.
+__global__ __launch_bounds__(kSegBlocks) void k_seg_scan(uint32_t *__restrict__ sums,
+                                                         uint32_t *__restrict__ act, int nblocks,
+                                                         unsigned long long *__restrict__ seg_tot,
+                                                         uint32_t *__restrict__ seg_act) {
+    __shared__ unsigned long long s_w[kSegBlocks / 64];
+    __shared__ uint32_t s_a[kSegBlocks / 64];
+    const int i = blockIdx.x * kSegBlocks + threadIdx.x;
+    const int w = threadIdx.x >> 6, lane = __lane_id();
+    const unsigned long long c = i < nblocks ? sums[i] : 0ull;
+    const uint32_t a = act && i < nblocks ? act[i] : 0u;
+    unsigned long long ic = c;
+    uint32_t ia = a;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const unsigned long long y = __shfl_up(ic, o, 64);
+        const uint32_t ya = __shfl_up(ia, o, 64);
+        if (lane >= o) {
+            ic += y;
+            ia += ya;
         }
-    if (threadIdx.x == 1023) {
-        const unsigned long long total = s_part[1023];
-        *m_total = total;
-        if (total > (unsigned long long)capacity) {
-            *m_dev = 0u;
-            atomicOr(flags, GSF_FLAG_CAPACITY);
-        } else {
-            *m_dev = (uint32_t)total;
+    }
+    if (lane == 63) {
+        s_w[w] = ic;
+        s_a[w] = ia;
+    }
+    __syncthreads();
+    if (w == 0) {   // the waves' totals
+        constexpr int NW = kSegBlocks / 64;
+        const unsigned long long x = lane < NW ? s_w[lane] : 0ull;
+        const uint32_t y = lane < NW ? s_a[lane] : 0u;
+        unsigned long long xi = x;
+        uint32_t yi = y;
+#pragma unroll
+        for (int o = 1; o < NW; o <<= 1) {
+            const unsigned long long u = __shfl_up(xi, o, 64);
+            const uint32_t ua = __shfl_up(yi, o, 64);
+            if (lane >= o) {
+                xi += u;
+                yi += ua;
+            }
+        }
+        if (lane < NW) {
+            s_w[lane] = xi - x;
+            s_a[lane] = yi - y;
+        }
+        if (lane == NW - 1) {
+            seg_tot[blockIdx.x] = xi;
+            if (seg_act) seg_act[blockIdx.x] = yi;
+        }
+    }
+    __syncthreads();
+    if (i < nblocks) {
+        sums[i] = (uint32_t)min(s_w[w] + ic - c, 0xFFFFFFFFull);
+        if (act) act[i] = s_a[w] + ia - a;
+    }
+}
+
+// The first offsets of block blockIdx.x and the totals: with at most
+// kOwnPrefixBlocks blocks each block sums the totals of the blocks before it
+// itself; otherwise k_seg_scan has scanned each segment in place and the block
+// adds the totals of the segments before its own.  With `publish`, block 0
+// writes the totals (m_total; m_dev = key total, 0 on overflow with
+// GSF_FLAG_CAPACITY; a_dev = active records, 0 on overflow).  Returns false on
+// a key overflow.
+__device__ __forceinline__ bool block_prefix(const uint32_t *__restrict__ sums,
+                                             const uint32_t *__restrict__ act, int nblocks,
+                                             const unsigned long long *__restrict__ seg_tot,
+                                             const uint32_t *__restrict__ seg_act,
+                                             int64_t capacity, uint32_t *m_dev,
+                                             unsigned long long *m_total, uint32_t *a_dev,
+                                             uint32_t *flags, bool publish,
+                                             unsigned long long *s_tot, uint32_t &gbase,
+                                             uint32_t &abase) {
+    const bool own = nblocks <= kOwnPrefixBlocks;
+    const int n = own ? nblocks : (nblocks + kSegBlocks - 1) / kSegBlocks;
+    const int mine = own ? (int)blockIdx.x : (int)blockIdx.x / kSegBlocks;
+    unsigned long long pre = 0ull, all = 0ull, apre = 0ull, aall = 0ull;
+    for (int b = threadIdx.x; b < n; b += kScanBlock) {
+        const unsigned long long c = own ? sums[b] : seg_tot[b];
+        const unsigned long long a = own ? (act ? act[b] : 0ull) : (seg_act ? seg_act[b] : 0ull);
+        all += c;
+        aall += a;
+        if (b < mine) {
+            pre += c;
+            apre += a;
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        pre += __shfl_xor(pre, o, 64);
+        all += __shfl_xor(all, o, 64);
+        apre += __shfl_xor(apre, o, 64);
+        aall += __shfl_xor(aall, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        s_tot[threadIdx.x >> 6] = all;
+        s_tot[4 + (threadIdx.x >> 6)] = aall;
+        s_tot[8 + (threadIdx.x >> 6)] = pre;
+        s_tot[12 + (threadIdx.x >> 6)] = apre;
+    }
+    __syncthreads();
+    const unsigned long long total_keys = s_tot[0] + s_tot[1] + s_tot[2] + s_tot[3];
+    const unsigned long long total_act = s_tot[4] + s_tot[5] + s_tot[6] + s_tot[7];
+    unsigned long long g = s_tot[8] + s_tot[9] + s_tot[10] + s_tot[11];
+    unsigned long long ga = s_tot[12] + s_tot[13] + s_tot[14] + s_tot[15];
+    if (!own) {   // plus this block's place within its segment
+        g += sums[blockIdx.x];
+        ga += act ? act[blockIdx.x] : 0u;
+    }
+    gbase = (uint32_t)min(g, 0xFFFFFFFFull);   // used only when the total fits
+    abase = (uint32_t)ga;
+    __syncthreads();   // s_tot is free again
+    if (publish && blockIdx.x == 0 && threadIdx.x == 0) {
+        *m_total = total_keys;
+        const bool over = total_keys > (unsigned long long)capacity;
+        if (over) atomicOr(flags, GSF_FLAG_CAPACITY);
+        *m_dev = over ? 0u : (uint32_t)total_keys;
+        if (a_dev) *a_dev = over ? 0u : (uint32_t)total_act;
+    }
+    return total_keys <= (unsigned long long)capacity;
+}
+
+// Record-order scan of the listed-tile counts: koff[r], the position of record
+// r's first gradient slot (its keys in record order), the row tables of the
+// boxes not packed (written at those slots), the key total and the capacity
+// check; and the records that list a tile, compacted in record order: entry e
+// holds (depth bits, e) in (dkey, dval) for the depth sort and, in arec, the
+// record's data the emission needs (record id, first slot, count, packed spans
+// or row-table size, box) as one 32-byte entry, so that the emission, which
+// visits the records in depth order, gathers one cache line per record.
+// a_dev: their number (0 on overflow).  Also clears the tile ranges
+// (grid-stride).  The per-block totals of counts and of active records come
+// from the projection.
+__global__ __launch_bounds__(kScanBlock) void k_scan_rec(
+    const uint32_t *__restrict__ count, const uint2 *__restrict__ rect,
+    const float4 *__restrict__ ell, const uint2 *__restrict__ rspan, SplatPtrs sp,
+    const uint32_t *__restrict__ depth_key, uint32_t *__restrict__ koff, uint2 *__restrict__ rowtab,
+    int nrec, int n, int tile, const ViewDesc *__restrict__ views,
+    const uint32_t *__restrict__ block_sums, const uint32_t *__restrict__ block_act, int nblocks,
+    const unsigned long long *__restrict__ seg_tot, const uint32_t *__restrict__ seg_act,
+    uint32_t *__restrict__ m_dev, unsigned long long *__restrict__ m_total,
+    uint32_t *__restrict__ a_dev, uint32_t *__restrict__ flags, int64_t capacity,
+    uint32_t *__restrict__ dkey, uint32_t *__restrict__ dval, uint4 *__restrict__ arec,
+    uint2 *__restrict__ ranges, int total_tiles) {
+    __shared__ uint32_t s_wave[4];
+    __shared__ unsigned long long s_tot[16];
+    for (int t = blockIdx.x * kScanBlock + threadIdx.x; t < total_tiles; t += gridDim.x * kScanBlock)
+        ranges[t] = make_uint2(0u, 0u);
+    uint32_t gbase, abase;
+    if (!block_prefix(block_sums, block_act, nblocks, seg_tot, seg_act, capacity, m_dev, m_total,
+                      a_dev, flags, true, s_tot, gbase, abase))
+        return;   // overflow: nothing placed, nothing to sort
+    const int r = blockIdx.x * kScanTile + threadIdx.x;
+    const uint32_t c = r < nrec ? count[r] : 0u;
+    uint32_t total, atot;
+    const uint32_t off = block_excl_scan_256(c, s_wave, total);
+    const uint32_t apos = block_excl_scan_256(c != 0u ? 1u : 0u, s_wave, atot);
+    if (c == 0u) return;
+    const uint32_t first = gbase + off, e = abase + apos;
+    koff[r] = first;
+    const uint2 rc = rect[r];
+    const uint2 pk = rspan[r];
+    dkey[e] = depth_key[r];
+    dval[e] = e;
+    arec[2 * e] = make_uint4((uint32_t)r, first, c, pk.x);
+    arec[2 * e + 1] = make_uint4(rc.x, rc.y, pk.y, 0u);
+    const int x0 = (int)(rc.x & 0xFFFFu), y0 = (int)(rc.x >> 16);
+    const int x1 = (int)(rc.y & 0xFFFFu), y1 = (int)(rc.y >> 16);
+    if (y1 - y0 + 1 > kPackRows || x1 - x0 + 1 > kPackCols) {   // the row table
+        const float4 ea = ell[r], a = sp.a[r], cc = sp.c[r];
+        const Ellipse el{ea.x, ea.y, ea.z, ea.w, sqrtf(ea.y / ea.z), a.x, a.y, (int)cc.z, (int)cc.w};
+        const ViewDesc vd = views[r / n];
+        const int tl = 31 - __clz(tile);
+        uint32_t j = 0, pre = 0;
+        for (int ty = y0; ty <= y1 && j < pk.x; ty++) {
+            int c0, c1;
+            if (!row_span(el, ty, tl, vd.width, vd.height, x0, x1, c0, c1)) continue;
+            rowtab[first + j] = make_uint2((uint32_t)(ty - y0) | ((uint32_t)c0 << 16), pre);
+            pre += (uint32_t)(c1 - c0 + 1);
+            j++;
         }
     }
 }
 
-// Keys of each record (one per listed tile) at its scanned offset; also
-// clears the tile ranges (grid-stride) before the boundary pass fills them.
-// The block's keys are written by all its threads together, key q of the block
-// by thread q mod 256: the record owning q is found by binary search over the
-// block's offsets in LDS, so one record's many keys are spread over the block
-// and consecutive threads write consecutive addresses.  Within a record the
-// keys run over the box rows, each row's tiles being those its support
-// ellipse reaches (row_span, the rule the projection counted with): from the
-// packed spans, or from the record's row table, which the thread owning the
-// record writes first (at the record's own key positions) and the key's
-// thread then searches for the key's row.
-__global__ __launch_bounds__(kScanBlock) void k_scan_dup(
-    const uint32_t *__restrict__ count, const uint2 *__restrict__ rect,
-    const float4 *__restrict__ ell, const uint2 *__restrict__ rspan, SplatPtrs sp,
-    uint32_t *__restrict__ koff, uint2 *rowtab, int nrec, int n, int tile,
-    const ViewDesc *__restrict__ views, const uint32_t *__restrict__ block_prefix, int nblocks,
-    bool own_prefix, uint32_t *__restrict__ m_dev, unsigned long long *__restrict__ m_total,
-    uint32_t *__restrict__ flags, int64_t capacity, uint32_t *__restrict__ keys,
-    uint32_t *__restrict__ vals, uint2 *__restrict__ ranges, int total_tiles) {
-    __shared__ uint32_t s_wave[4];
-    __shared__ unsigned long long s_tot[4];
-    __shared__ uint32_t s_off[kScanTile];   // block-local exclusive key offset per record
-    __shared__ uint2 s_rect[kScanTile];
-    __shared__ int s_view[kScanTile];
-    __shared__ uint2 s_pack[kScanTile];       // packed row spans, or (row-table entries, -)
-    __shared__ ViewDesc s_views[kMaxViews];   // read per key: kept in LDS, not reloaded from memory
-    for (int t = blockIdx.x * kScanBlock + threadIdx.x; t < total_tiles; t += gridDim.x * kScanBlock)
-        ranges[t] = make_uint2(0u, 0u);
-    if ((int)threadIdx.x < min(nrec / n, kMaxViews)) s_views[threadIdx.x] = views[threadIdx.x];
-    // The block's first key and the key total.  With own_prefix (at most
-    // kOwnPrefixBlocks blocks) block_prefix holds the per-block totals and each
-    // block sums those before it itself, block 0 publishing the total; else
-    // k_scan_top has scanned them in place and published it.
-    uint32_t gbase;
-    unsigned long long total_keys;
-    if (own_prefix) {
-        unsigned long long pre = 0ull, all = 0ull;
-        for (int b = threadIdx.x; b < nblocks; b += kScanBlock) {
-            const unsigned long long c = block_prefix[b];
-            all += c;
-            if (b < (int)blockIdx.x) pre += c;
-        }
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            pre += __shfl_xor(pre, o, 64);
-            all += __shfl_xor(all, o, 64);
-        }
-        if ((threadIdx.x & 63) == 0) {
-            s_tot[threadIdx.x >> 6] = all;
-            s_wave[threadIdx.x >> 6] = (uint32_t)min(pre, 0xFFFFFFFFull);
-        }
-        __syncthreads();
-        total_keys = s_tot[0] + s_tot[1] + s_tot[2] + s_tot[3];
-        gbase = s_wave[0] + s_wave[1] + s_wave[2] + s_wave[3];   // used only when total fits
-        __syncthreads();   // s_wave is reused by the block scan below
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            *m_total = total_keys;
-            if (total_keys > (unsigned long long)capacity) {
-                *m_dev = 0u;
-                atomicOr(flags, GSF_FLAG_CAPACITY);
-            } else {
-                *m_dev = (uint32_t)total_keys;
-            }
-        }
-    } else {
-        total_keys = *m_total;
-        gbase = block_prefix[blockIdx.x];
+// Per view, the first tile (column, row) of its fovea box, into LDS (threads
+// below nviews), for the compact keys of a fovea-culled forward.
+__device__ __forceinline__ void fovea_origins(const TileMap &tm, const ViewDesc *__restrict__ views,
+                                              int nviews, int2 *s_f0) {
+    const int v = threadIdx.x;
+    if (tm.gaze && v < nviews) {
+        const ViewDesc vd = views[v];
+        const FoveaTiles f = fovea_tiles(tm.gaze, v, tm.radius, vd.width, vd.height, tm.tile);
+        s_f0[v] = make_int2(f.tx0, f.ty0);
     }
-    if (total_keys > (unsigned long long)capacity) return;    // overflow: emit nothing
-    const int rec0 = blockIdx.x * kScanTile;
-    const int base = rec0 + threadIdx.x * kScanIpt;
-    uint32_t cnt[kScanIpt];
-    uint32_t sum = 0;
+}
+
+// Global tile id of a sort key (identity without a gaze).
+__device__ __forceinline__ uint32_t global_tile(uint32_t c, const TileMap &tm,
+                                                const ViewDesc *s_views, const int2 *s_f0) {
+    if (!tm.gaze) return c;
+    const uint32_t box = (uint32_t)tm.box, area = box * box;
+    const uint32_t v = c / area, l = c - v * area, ly = l / box, lx = l - ly * box;
+    const ViewDesc vd = s_views[v];
+    return (uint32_t)vd.tile_off + ((uint32_t)s_f0[v].y + ly) * (uint32_t)vd.tiles_x +
+           (uint32_t)s_f0[v].x + lx;
+}
+
+// Per block of 256 depth-ordered active records: the sum of their counts (the
+// first level of the emission scan).
+__global__ __launch_bounds__(kScanBlock) void k_emit_totals(const uint32_t *__restrict__ dval,
+                                                            const uint32_t *__restrict__ a_dev,
+                                                            const uint4 *__restrict__ arec,
+                                                            uint32_t *__restrict__ sums) {
+    __shared__ uint32_t s_w[4];
+    const uint32_t pos = blockIdx.x * kScanTile + threadIdx.x;
+    uint32_t c = pos < *a_dev ? arec[2 * dval[pos]].z : 0u;
 #pragma unroll
-    for (int k = 0; k < kScanIpt; k++) {
-        cnt[k] = base + k < nrec ? count[base + k] : 0u;
-        sum += cnt[k];
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) sums[blockIdx.x] = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+}
+
+// Keys of the active records in depth order (key = global tile id, value =
+// record id): block b emits the keys of depth positions 256 b .. 256 b + 255,
+// all its threads together, key q of the block by thread q mod 256, the record
+// owning q found by binary search over the block's offsets in LDS (one record's
+// many keys spread over the block, consecutive threads writing consecutive
+// addresses).  Within a record the keys run over the box rows, each row's tiles
+// being those its support ellipse reaches: from the packed spans, or the row
+// table at the record's gradient slots.  The stable sort by tile that follows
+// then leaves every tile's list in (depth, record) order.
+__global__ __launch_bounds__(kScanBlock) void k_emit(
+    const uint32_t *__restrict__ dval, const uint32_t *__restrict__ a_dev,
+    const uint4 *__restrict__ arec, const uint2 *__restrict__ rowtab, int n,
+    const ViewDesc *__restrict__ views, int nviews, const uint32_t *__restrict__ block_sums,
+    int nblocks, const unsigned long long *__restrict__ seg_tot,
+    const unsigned long long *__restrict__ m_total, int64_t capacity, TileMap tm,
+    uint32_t *__restrict__ keys, uint32_t *__restrict__ vals) {
+    __shared__ uint32_t s_wave[4];
+    __shared__ unsigned long long s_tot[16];
+    __shared__ uint32_t s_off[kScanTile];   // block-local exclusive key offset per record
+    __shared__ uint4 s_r0[kScanTile];       // record, first slot, count, spans.x / table size
+    __shared__ uint4 s_r1[kScanTile];       // box, spans.y
+    __shared__ ViewDesc s_views[kMaxViews];   // read per key: kept in LDS
+    __shared__ int2 s_f0[kMaxViews];          // fovea box origins (compact keys)
+    const uint32_t A = *a_dev;
+    if ((uint32_t)blockIdx.x * kScanTile >= A) return;   // beyond the active records
+    if ((int)threadIdx.x < min(nviews, kMaxViews)) s_views[threadIdx.x] = views[threadIdx.x];
+    fovea_origins(tm, views, nviews, s_f0);
+    uint32_t gbase, abase;
+    if (!block_prefix(block_sums, nullptr, nblocks, seg_tot, nullptr, capacity, nullptr,
+                      const_cast<unsigned long long *>(m_total), nullptr, nullptr, false, s_tot,
+                      gbase, abase))
+        return;
+    const uint32_t pos = blockIdx.x * kScanTile + threadIdx.x;
+    uint4 r0 = make_uint4(0u, 0u, 0u, 0u), r1 = r0;
+    if (pos < A) {
+        const uint32_t e = dval[pos];
+        r0 = arec[2 * e];
+        r1 = arec[2 * e + 1];
     }
     uint32_t total;
-    uint32_t off = block_excl_scan_256(sum, s_wave, total);
-#pragma unroll
-    for (int k = 0; k < kScanIpt; k++) {
-        const int i = threadIdx.x * kScanIpt + k;
-        s_off[i] = off;
-        if (cnt[k] != 0u) {
-            const uint32_t r = (uint32_t)(base + k);
-            koff[r] = gbase + off;             // the record's first key
-            const uint2 rc = rect[r];
-            s_rect[i] = rc;
-            s_view[i] = (int)(r / (uint32_t)n);
-            const int x0 = (int)(rc.x & 0xFFFFu), y0 = (int)(rc.x >> 16);
-            const int x1 = (int)(rc.y & 0xFFFFu), y1 = (int)(rc.y >> 16);
-            const uint2 pk = rspan[r];
-            s_pack[i] = pk;
-            if (y1 - y0 + 1 > kPackRows || x1 - x0 + 1 > kPackCols) {   // the row table
-                const float4 ea = ell[r], a = sp.a[r], c = sp.c[r];
-                const Ellipse e{ea.x, ea.y, ea.z, ea.w, sqrtf(ea.y / ea.z), a.x, a.y, (int)c.z, (int)c.w};
-                const ViewDesc vd = views[r / (uint32_t)n];
-                const int tl = 31 - __clz(tile);
-                uint32_t j = 0, pre = 0;
-                for (int ty = y0; ty <= y1 && j < pk.x; ty++) {
-                    int c0, c1;
-                    if (!row_span(e, ty, tl, vd.width, vd.height, x0, x1, c0, c1)) continue;
-                    rowtab[gbase + off + j] = make_uint2((uint32_t)(ty - y0) | ((uint32_t)c0 << 16), pre);
-                    pre += (uint32_t)(c1 - c0 + 1);
-                    j++;
-                }
-            }
-        }
-        off += cnt[k];
-    }
-    __syncthreads();   // row tables written (the block's own global stores) and LDS filled
+    const uint32_t off = block_excl_scan_256(r0.z, s_wave, total);
+    s_off[threadIdx.x] = off;
+    s_r0[threadIdx.x] = r0;
+    s_r1[threadIdx.x] = r1;
+    __syncthreads();
     for (uint32_t q = threadIdx.x; q < total; q += kScanBlock) {
-        // the last record whose offset is <= q (records without keys share the
-        // offset of the next record, so the last one is the owner)
+        // the last record whose offset is <= q (every active record has keys)
         int lo = 0, hi = kScanTile - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
             if (s_off[mid] <= q) lo = mid; else hi = mid - 1;
         }
         uint32_t li = q - s_off[lo];              // index of the key within its record
-        const uint32_t r = (uint32_t)(rec0 + lo);
-        const uint2 rc = s_rect[lo];
-        const int x0 = (int)(rc.x & 0xFFFFu), y0 = (int)(rc.x >> 16);
-        const int x1 = (int)(rc.y & 0xFFFFu), y1 = (int)(rc.y >> 16);
-        const ViewDesc vd = s_views[s_view[lo]];
-        uint32_t key = 0u;
+        const uint4 a = s_r0[lo], b = s_r1[lo];
+        const uint32_t rr = a.x;
+        const int x0 = (int)(b.x & 0xFFFFu), y0 = (int)(b.x >> 16);
+        const int x1 = (int)(b.y & 0xFFFFu), y1 = (int)(b.y >> 16);
+        const uint32_t v = rr / (uint32_t)n;
+        uint32_t ty = 0u, tx = 0u;   // the key's tile
         if (y1 - y0 + 1 <= kPackRows && x1 - x0 + 1 <= kPackCols) {   // packed spans
-            const uint2 pk = s_pack[lo];
             for (int k = 0; k < kPackRows; k++) {
-                const uint32_t f = ((k < 2 ? pk.x : pk.y) >> (16 * (k & 1))) & 0xFFFFu;
+                const uint32_t f = ((k < 2 ? a.w : b.z) >> (16 * (k & 1))) & 0xFFFFu;
                 const uint32_t w = f >> 8;
                 if (li < w) {
-                    key = (uint32_t)vd.tile_off + (uint32_t)(y0 + k) * (uint32_t)vd.tiles_x +
-                          (uint32_t)x0 + (f & 0xFFu) + li;
+                    ty = (uint32_t)(y0 + k);
+                    tx = (uint32_t)x0 + (f & 0xFFu) + li;
                     break;
                 }
                 li -= w;
             }
         } else {   // the last row-table entry whose key prefix is <= li holds key li
-            const uint32_t tb = gbase + s_off[lo];
-            int a = 0, b = (int)s_pack[lo].x - 1;
-            while (a < b) {
-                const int mid = (a + b + 1) >> 1;
-                if (rowtab[tb + (uint32_t)mid].y <= li) a = mid; else b = mid - 1;
+            const uint32_t tb = a.y;
+            int ta = 0, tz = (int)a.w - 1;
+            while (ta < tz) {
+                const int mid = (ta + tz + 1) >> 1;
+                if (rowtab[tb + (uint32_t)mid].y <= li) ta = mid; else tz = mid - 1;
             }
-            const uint2 te = rowtab[tb + (uint32_t)a];
-            key = (uint32_t)vd.tile_off + ((uint32_t)y0 + (te.x & 0xFFFFu)) * (uint32_t)vd.tiles_x +
-                  (te.x >> 16) + (li - te.y);
+            const uint2 te = rowtab[tb + (uint32_t)ta];
+            ty = (uint32_t)y0 + (te.x & 0xFFFFu);
+            tx = (te.x >> 16) + (li - te.y);
         }
-        keys[gbase + q] = key;
-        vals[gbase + q] = r;
+        const ViewDesc vd = s_views[v];
+        keys[gbase + q] = tm.gaze ? v * (uint32_t)(tm.box * tm.box) +
+                                        (ty - (uint32_t)s_f0[v].y) * (uint32_t)tm.box +
+                                        (tx - (uint32_t)s_f0[v].x)
+                                  : (uint32_t)vd.tile_off + ty * (uint32_t)vd.tiles_x + tx;
+        vals[gbase + q] = rr;
     }
 }
 
@@ -422,7 +563,15 @@ __device__ __forceinline__ void fill_runs(uint2 *ranges, uint32_t lo, uint32_t h
 __global__ __launch_bounds__(256) void k_tile_bounds(const uint32_t *__restrict__ keys,
                                                      const uint32_t *__restrict__ m_dev,
                                                      uint32_t m_host, int total_tiles,
-                                                     uint2 *__restrict__ ranges) {
+                                                     const ViewDesc *__restrict__ views, int nviews,
+                                                     TileMap tm, uint2 *__restrict__ ranges) {
+    __shared__ ViewDesc s_views[kMaxViews];
+    __shared__ int2 s_f0[kMaxViews];
+    if (tm.gaze) {
+        if ((int)threadIdx.x < min(nviews, kMaxViews)) s_views[threadIdx.x] = views[threadIdx.x];
+        fovea_origins(tm, views, nviews, s_f0);
+        __syncthreads();
+    }
     const uint32_t m = m_dev ? *m_dev : m_host;
     const uint32_t stride = gridDim.x * blockDim.x;
     // wave-uniform trip count: every lane takes part in the run fills
@@ -430,9 +579,11 @@ __global__ __launch_bounds__(256) void k_tile_bounds(const uint32_t *__restrict_
         const uint32_t k = base + threadIdx.x;
         uint32_t lo = 0, hi = 0, lo2 = 0, hi2 = 0;
         if (k < m) {
-            const uint32_t t = keys[k];
-            if (k == 0 || keys[k - 1] != t) {
-                lo = k == 0 ? t : keys[k - 1] + 1u;   // empty tiles before t
+            const uint32_t c = keys[k];
+            const uint32_t t = global_tile(c, tm, s_views, s_f0);
+            if (k == 0 || keys[k - 1] != c) {
+                // empty tiles before t
+                lo = k == 0 ? t : global_tile(keys[k - 1], tm, s_views, s_f0) + 1u;
                 hi = t;
                 ranges[t].x = k;
             }
@@ -440,7 +591,7 @@ __global__ __launch_bounds__(256) void k_tile_bounds(const uint32_t *__restrict_
                 ranges[t].y = m;
                 lo2 = t + 1u;                         // empty tiles after the last key
                 hi2 = (uint32_t)total_tiles;
-            } else if (keys[k + 1] != t) {
+            } else if (keys[k + 1] != c) {
                 ranges[t].y = k + 1;
             }
         }
@@ -583,167 +734,6 @@ __global__ __launch_bounds__(256) void k_order_place(const uint2 *__restrict__ r
     order_walk(ranges, total_tiles, s_cnt, order);
 }
 
-// ---- 4. per-tile sort by depth ----------------------------------------------------
-
-struct SortShared {
-    uint32_t hist[4][256];   // per-wave digit counts
-    uint32_t base[256];      // running output offset per digit
-    uint32_t tot[256];
-    uint32_t wave[4];
-    uint32_t skip;
-};
-
-// One stable pass by the 8-bit digit (k >> shift) & 0xFF.  Returns false (and
-// moves nothing) when every key has the same digit.  Generic pointers: called
-// on LDS arrays or on global scratch.
-__device__ __forceinline__ bool sort_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout,
-                                          uint32_t *vout, int n, int shift, SortShared &sh) {
-    const int t = threadIdx.x, w = t >> 6, lane = __lane_id();
-    for (int e = t; e < 4 * 256; e += kTileSortBlock) (&sh.hist[0][0])[e] = 0u;
-    if (t == 0) sh.skip = 0u;
-    __syncthreads();
-    for (int i = t; i < n; i += kTileSortBlock) {
-        const uint32_t d = (kin[i] >> shift) & 0xFFu;
-        atomicAdd(&sh.hist[w][d], 1u);
-    }
-    __syncthreads();
-    const uint32_t cnt = sh.hist[0][t] + sh.hist[1][t] + sh.hist[2][t] + sh.hist[3][t];
-    if (cnt == (uint32_t)n) sh.skip = 1u;
-    uint32_t all;
-    sh.base[t] = block_excl_scan_256(cnt, sh.wave, all);   // (has barriers)
-    const bool skip = sh.skip != 0u;
-    __syncthreads();                       // all have read skip before a later pass resets it
-    if (skip) return false;
-    for (int c0 = 0; c0 < n; c0 += kTileSortBlock) {
-        for (int e = t; e < 4 * 256; e += kTileSortBlock) (&sh.hist[0][0])[e] = 0u;
-        __syncthreads();
-        const int i = c0 + w * 64 + lane;
-        const bool valid = i < n;
-        const uint32_t k = valid ? kin[i] : 0u, v = valid ? vin[i] : 0u;
-        const uint32_t d = (k >> shift) & 0xFFu;
-        uint64_t peers = __ballot(valid);
-#pragma unroll
-        for (int b = 0; b < 8; b++) {
-            const uint64_t bal = __ballot((d >> b) & 1u);
-            peers &= ((d >> b) & 1u) ? bal : ~bal;
-        }
-        const uint32_t below = lanes_below(peers);
-        if (valid && below == 0u) sh.hist[w][d] = (uint32_t)__popcll(peers);
-        __syncthreads();
-        {   // earlier waves of this chunk, per digit
-            uint32_t run = 0;
-#pragma unroll
-            for (int q = 0; q < 4; q++) {
-                const uint32_t c = sh.hist[q][t];
-                sh.hist[q][t] = run;
-                run += c;
-            }
-            sh.tot[t] = run;
-        }
-        __syncthreads();
-        if (valid) {
-            const uint32_t pos = sh.base[d] + sh.hist[w][d] + below;
-            kout[pos] = k;
-            vout[pos] = v;
-        }
-        __syncthreads();
-        sh.base[t] += sh.tot[t];
-    }
-    __syncthreads();
-    return true;
-}
-
-// Four stable passes over the 32 depth bits.  The list arrives in record order
-// (stable tile sort of keys emitted in record order), so equal depths keep it.
-__device__ __forceinline__ void sort_list(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
-                                          int n, SortShared &sh, bool &in_second) {
-    bool second = false;
-    for (int p = 0; p < 4; p++) {
-        const bool moved = second ? sort_pass(k1, v1, k0, v0, n, 8 * p, sh)
-                                  : sort_pass(k0, v0, k1, v1, n, 8 * p, sh);
-        if (moved) second = !second;
-    }
-    in_second = second;
-}
-
-// Keys of s[j0, j1) below k (at most k when LE); j0 and j1 are multiples of 4.
-template <bool LE>
-__device__ __forceinline__ uint32_t count_keys(const uint32_t *s, int j0, int j1, uint32_t k) {
-    const uint4 *q = reinterpret_cast<const uint4 *>(s);
-    uint32_t c = 0u;
-    for (int j = j0; j < j1; j += 4) {
-        const uint4 v = q[j >> 2];
-        if (LE)
-            c += (uint32_t)(v.x <= k) + (uint32_t)(v.y <= k) + (uint32_t)(v.z <= k) + (uint32_t)(v.w <= k);
-        else
-            c += (uint32_t)(v.x < k) + (uint32_t)(v.y < k) + (uint32_t)(v.z < k) + (uint32_t)(v.w < k);
-    }
-    return c;
-}
-
-__global__ __launch_bounds__(kTileSortBlock) void k_tile_sort(
-    const uint32_t *__restrict__ order, const uint2 *__restrict__ ranges,
-    const uint32_t *__restrict__ depth_key,
-    uint32_t *__restrict__ vals, uint32_t *__restrict__ gk0, uint32_t *__restrict__ gk1,
-    uint32_t *__restrict__ gv1) {
-    __shared__ SortShared sh;
-    __shared__ __align__(16) uint32_t s_k0[kTileSortLds];
-    __shared__ uint32_t s_v0[kTileSortLds], s_k1[kTileSortLds], s_v1[kTileSortLds];
-    const uint2 rg = ranges[order[blockIdx.x]];   // tiles with the longest lists first
-    const int n = (int)(rg.y - rg.x);
-    if (n <= 1) return;
-    uint32_t *lv = vals + rg.x;
-    bool second;
-    if (n <= kTileSortBlock) {
-        // Short list: entry i goes to the count of entries before it in (depth
-        // bits, list position) order, the order the stable passes give.  A
-        // wave's entries are 64 consecutive positions, so earlier waves' keys
-        // count when at most the entry's depth, later ones when below it, and
-        // only the wave's own run compares positions.  The depths are padded to
-        // a multiple of 4 with a key above every depth (depth bits of finite or
-        // infinite floats are below 0x7F800001).
-        const int i = threadIdx.x;
-        const int np = (n + 3) & ~3;
-        uint32_t r = 0u;
-        if (i < n) {
-            r = lv[i];
-            s_k0[i] = depth_key[r];
-        } else if (i < np) {
-            s_k0[i] = 0xFFFFFFFFu;
-        }
-        __syncthreads();
-        if (i < n) {
-            const uint32_t k = s_k0[i];
-            const int w0 = i & ~63, w1 = min(w0 + 64, np);
-            uint32_t rank = count_keys<true>(s_k0, 0, w0, k) + count_keys<false>(s_k0, w1, np, k);
-            const uint4 *q = reinterpret_cast<const uint4 *>(s_k0);
-            for (int j = w0; j < w1; j += 4) {   // equal depths count when earlier
-                const uint4 v = q[j >> 2];
-                rank += (uint32_t)(v.x < k + (uint32_t)(j < i)) + (uint32_t)(v.y < k + (uint32_t)(j + 1 < i)) +
-                        (uint32_t)(v.z < k + (uint32_t)(j + 2 < i)) + (uint32_t)(v.w < k + (uint32_t)(j + 3 < i));
-            }
-            lv[rank] = r;
-        }
-    } else if (n <= kTileSortLds) {
-        for (int i = threadIdx.x; i < n; i += kTileSortBlock) {
-            const uint32_t r = lv[i];
-            s_v0[i] = r;
-            s_k0[i] = depth_key[r];
-        }
-        __syncthreads();
-        sort_list(s_k0, s_v0, s_k1, s_v1, n, sh, second);
-        const uint32_t *res = second ? s_v1 : s_v0;
-        for (int i = threadIdx.x; i < n; i += kTileSortBlock) lv[i] = res[i];
-    } else {
-        uint32_t *k0 = gk0 + rg.x, *k1 = gk1 + rg.x, *v1 = gv1 + rg.x;
-        for (int i = threadIdx.x; i < n; i += kTileSortBlock) k0[i] = depth_key[lv[i]];
-        __syncthreads();
-        sort_list(k0, lv, k1, v1, n, sh, second);
-        if (second)
-            for (int i = threadIdx.x; i < n; i += kTileSortBlock) lv[i] = v1[i];
-    }
-}
-
 }  // namespace
 
 int radix_grid_for(int64_t capacity) {
@@ -753,13 +743,17 @@ int radix_grid_for(int64_t capacity) {
     return (int)g;
 }
 
+int radix_passes(int bits) { return bits <= 0 ? 0 : (bits + kMaxDigit - 1) / kMaxDigit; }
+
 int launch_radix_sort(hipStream_t s, const uint32_t *kin, const uint32_t *vin, uint32_t *ka,
                       uint32_t *va, uint32_t *kb, uint32_t *vb, const uint32_t *n_dev,
                       uint32_t n_host, int bits, int grid, uint32_t *hist, uint32_t *digit_tot) {
     int where = 0;
     const uint32_t *ks = kin, *vs = vin;
-    for (int shift = 0; shift < bits; shift += 8) {
-        const int b = bits - shift < 8 ? bits - shift : 8;
+    const int passes = radix_passes(bits);
+    // balanced digits: `passes` digits of at most kMaxDigit bits covering `bits`
+    for (int p = 0, shift = 0; p < passes; p++) {
+        const int b = (bits - shift + (passes - p) - 1) / (passes - p);
         uint32_t *kd = where == 1 ? kb : ka, *vd = where == 1 ? vb : va;
         k_radix_hist<<<grid, kSortBlock, 0, s>>>(ks, n_dev, n_host, shift, b, hist, grid);
         k_radix_colscan<<<1 << b, 256, 0, s>>>(hist, grid, digit_tot);
@@ -768,32 +762,56 @@ int launch_radix_sort(hipStream_t s, const uint32_t *kin, const uint32_t *vin, u
         where = where == 1 ? 2 : 1;
         ks = kd;
         vs = vd;
+        shift += b;
     }
     return where;
 }
 
 int scan_blocks(int64_t nrec) { return (int)((nrec + kScanTile - 1) / kScanTile) + 1; }
 
-void launch_scan_duplicate(hipStream_t s, const uint32_t *count, const uint2 *rect,
-                           const float4 *ell, const uint2 *rspan, SplatPtrs sp, uint32_t *koff,
-                           uint2 *rowtab, int nrec, int n, int tile,
-                           const ViewDesc *views, uint32_t *block_sums, uint32_t *keys,
-                           uint32_t *vals, uint32_t *m_dev, unsigned long long *m_total,
-                           uint32_t *flags, int64_t capacity, uint2 *ranges, int total_tiles) {
+
+int seg_count(int64_t nrec) {
+    const int64_t nb = (nrec + kScanTile - 1) / kScanTile;
+    return (int)((nb + kSegBlocks - 1) / kSegBlocks) + 1;
+}
+
+void launch_scan_records(hipStream_t s, const uint32_t *count, const uint2 *rect, const float4 *ell,
+                         const uint2 *rspan, SplatPtrs sp, const uint32_t *depth_key, uint32_t *koff,
+                         uint2 *rowtab, int nrec, int n, int tile, const ViewDesc *views,
+                         uint32_t *block_sums, uint32_t *block_act, unsigned long long *seg_tot,
+                         uint32_t *seg_act, uint32_t *m_dev, unsigned long long *m_total,
+                         uint32_t *a_dev, uint32_t *flags, int64_t capacity, uint32_t *dkey,
+                         uint32_t *dval, uint4 *arec, uint2 *ranges, int total_tiles) {
     const int nb = (nrec + kScanTile - 1) / kScanTile;
-    const bool own_prefix = nb >= 1 && nb <= kOwnPrefixBlocks;   // else k_scan_top writes the total
-    if (!own_prefix) k_scan_top<<<1, 1024, 0, s>>>(block_sums, nb, m_dev, m_total, flags, capacity);
-    k_scan_dup<<<nb, kScanBlock, 0, s>>>(count, rect, ell, rspan, sp, koff, rowtab, nrec, n, tile, views,
-                                         block_sums, nb, own_prefix, m_dev, m_total, flags,
-                                         capacity, keys, vals, ranges, total_tiles);
+    if (nb > kOwnPrefixBlocks)
+        k_seg_scan<<<(nb + kSegBlocks - 1) / kSegBlocks, kSegBlocks, 0, s>>>(block_sums, block_act, nb,
+                                                                            seg_tot, seg_act);
+    k_scan_rec<<<nb, kScanBlock, 0, s>>>(count, rect, ell, rspan, sp, depth_key, koff, rowtab, nrec, n,
+                                         tile, views, block_sums, block_act, nb, seg_tot, seg_act,
+                                         m_dev, m_total, a_dev, flags, capacity, dkey, dval, arec,
+                                         ranges, total_tiles);
+}
+
+void launch_emit(hipStream_t s, const uint32_t *dval, const uint32_t *a_dev, const uint4 *arec,
+                 const uint2 *rowtab, int nrec, int n, const ViewDesc *views, int nviews,
+                 uint32_t *block_sums, unsigned long long *seg_tot, const unsigned long long *m_total,
+                 int64_t capacity, const TileMap &tm, uint32_t *keys, uint32_t *vals) {
+    const int nb = (nrec + kScanTile - 1) / kScanTile;
+    k_emit_totals<<<nb, kScanBlock, 0, s>>>(dval, a_dev, arec, block_sums);
+    if (nb > kOwnPrefixBlocks)
+        k_seg_scan<<<(nb + kSegBlocks - 1) / kSegBlocks, kSegBlocks, 0, s>>>(block_sums, nullptr, nb,
+                                                                            seg_tot, nullptr);
+    k_emit<<<nb, kScanBlock, 0, s>>>(dval, a_dev, arec, rowtab, n, views, nviews, block_sums, nb,
+                                     seg_tot, m_total, capacity, tm, keys, vals);
 }
 
 void launch_tile_bounds(hipStream_t s, const uint32_t *keys, const uint32_t *m_dev, uint32_t m_host,
-                        int64_t capacity, int total_tiles, uint2 *ranges) {
+                        int64_t capacity, int total_tiles, const ViewDesc *views, int nviews,
+                        const TileMap &tm, uint2 *ranges) {
     int64_t g = (capacity + 255) / 256;
     if (g > 2048) g = 2048;
     if (g < 1) g = 1;
-    k_tile_bounds<<<(int)g, 256, 0, s>>>(keys, m_dev, m_host, total_tiles, ranges);
+    k_tile_bounds<<<(int)g, 256, 0, s>>>(keys, m_dev, m_host, total_tiles, views, nviews, tm, ranges);
 }
 
 int order_groups(int64_t total_tiles) { return (int)((total_tiles + kOrderTiles - 1) / kOrderTiles); }
@@ -809,10 +827,5 @@ void launch_tile_order(hipStream_t s, const uint2 *ranges, int total_tiles, uint
     k_order_place<<<g, 256, 0, s>>>(ranges, total_tiles, counts, g, order);
 }
 
-void launch_tile_sort(hipStream_t s, const uint32_t *order, const uint2 *ranges, int total_tiles,
-                      const uint32_t *depth_key, uint32_t *vals, uint32_t *gk0, uint32_t *gk1,
-                      uint32_t *gv1) {
-    k_tile_sort<<<total_tiles, kTileSortBlock, 0, s>>>(order, ranges, depth_key, vals, gk0, gk1, gv1);
-}
 
 }  // namespace gsf
