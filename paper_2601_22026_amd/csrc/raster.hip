@@ -511,6 +511,20 @@ __device__ __forceinline__ void render_bwd_unit(
     __syncthreads();
     const uint32_t nmax = *s_nmax;
     const uint32_t top = min(ue, rg.x + nmax);
+    // 16-pixel tiles: per quadrant (one per pixel block of the wave) the largest
+    // contributor count; a splat at or past it reaches no pixel of the quadrant
+    // (each would add exact zeros and keep its state), so the quadrant is skipped
+    uint32_t qmax[PPT];
+#pragma unroll
+    for (int k = 0; k < PPT; k++) {
+        uint32_t x = nc[k];
+        if (QUAD) {
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) x = max(x, (uint32_t)__shfl_xor((int)x, o, 64));
+            x = __builtin_amdgcn_readfirstlane(x);
+        }
+        qmax[k] = x;
+    }
 
     for (uint32_t be = top; be > us;) {
         const uint32_t bs = be - us > (uint32_t)B ? be - (uint32_t)B : us;
@@ -557,7 +571,7 @@ __device__ __forceinline__ void render_bwd_unit(
             bool any = false;
 #pragma unroll
             for (int k = 0; k < PPT; k++) {
-                if (QUAD ? !((qm >> k) & 1u)                                        // wave-uniform
+                if (QUAD ? (!((qm >> k) & 1u) || pos >= qmax[k])                     // wave-uniform
                          : !rows_meet(dy0 + (float)(k * ROWS), (float)(ROWS - 1), hy)) continue;
                 // Branch-free per lane: every value is computed and a pixel the
                 // splat does not reach (behind its last contributor, or alpha
@@ -827,15 +841,25 @@ __device__ __forceinline__ bool in_fovea(const float *__restrict__ gaze, int v, 
     return dx * dx + dy * dy <= radius * radius;
 }
 
-// Pixel p of a loss launch: every pixel of every view (box == 0), or pixel p of
-// view p / box^2's box x box window that starts at its first fovea tile
-// (fovea culling; false for window pixels outside the view or past its last
-// fovea tile).  Plans hold fewer than 2^31 pixels: 32-bit index arithmetic.
-__device__ __forceinline__ bool loss_pixel(uint32_t p, uint32_t total_pix, int box, int tile,
-                                           const float *__restrict__ gaze, float radius_frac,
+// Blocks per view of a fovea-window loss launch: each view's box x box window
+// is covered by whole blocks, so a block's view is uniform.
+__host__ __device__ __forceinline__ int loss_blocks_per_view(int box) {
+    return (box * box + kLossBlock - 1) / kLossBlock;
+}
+
+// Pixel (block bi, thread t) of a loss launch: every pixel of every view
+// (box == 0: pixel bi kLossBlock + t), or in view bi / bpv the pixel
+// (bi mod bpv) kLossBlock + t of its box x box window, which starts at its
+// first fovea tile (fovea culling; false for window pixels outside the view or
+// past its last fovea tile).  f: the view's fovea tiles (box mode, computed once
+// per block by the caller).  Plans hold fewer than 2^31 pixels: 32-bit
+// arithmetic.
+__device__ __forceinline__ bool loss_pixel(uint32_t bi, uint32_t t, uint32_t total_pix, int box,
+                                           int tile, const FoveaTiles &f,
                                            const ViewDesc *__restrict__ views, int nviews, int &v,
                                            int &x, int &y) {
     if (box == 0) {
+        const uint32_t p = bi * kLossBlock + t;
         if (p >= total_pix) return false;
         v = view_of_pixel(views, nviews, p);
         const ViewDesc vd = views[v];
@@ -844,37 +868,56 @@ __device__ __forceinline__ bool loss_pixel(uint32_t p, uint32_t total_pix, int b
         x = (int)(q - (uint32_t)y * (uint32_t)vd.width);
         return true;
     }
-    const uint32_t area = (uint32_t)box * (uint32_t)box;
-    v = (int)(p / area);
-    if (v >= nviews) return false;
-    const uint32_t l = p - (uint32_t)v * area;
-    const ViewDesc vd = views[v];
-    const FoveaTiles f = fovea_tiles(gaze, v, radius_frac, vd.width, vd.height, tile);
-    if (f.tx0 > f.tx1) return false;
-    const uint32_t ly = l / (uint32_t)box;
+    const int bpv = loss_blocks_per_view(box);
+    v = (int)(bi / (uint32_t)bpv);
+    if (v >= nviews || f.tx0 > f.tx1) return false;
+    const uint32_t l = (bi - (uint32_t)v * (uint32_t)bpv) * kLossBlock + t;
+    if (l >= (uint32_t)(box * box)) return false;
+    // l / box by a float reciprocal: exact, since l < 2^23 and box < 2^12 keep the
+    // quotient's fraction at least 1 / (2 box) from an integer
+    const uint32_t ly = (uint32_t)(((float)l + 0.5f) * __builtin_amdgcn_rcpf((float)box));
     x = f.tx0 * tile + (int)(l - ly * (uint32_t)box);
     y = f.ty0 * tile + (int)ly;
+    const ViewDesc vd = views[v];
     return x < vd.width && y < vd.height && x < (f.tx1 + 1) * tile && y < (f.ty1 + 1) * tile;
+}
+
+// The fovea tiles of block bi's view (box mode), computed once per block.
+__device__ __forceinline__ FoveaTiles block_fovea(uint32_t bi, int box, int tile,
+                                                  const float *__restrict__ gaze, float radius_frac,
+                                                  const ViewDesc *__restrict__ views, int nviews,
+                                                  FoveaTiles *s_f) {
+    __syncthreads();   // s_f of the previous block is no longer read
+    if (threadIdx.x == 0) {
+        FoveaTiles f{1, 0, 1, 0};
+        const int v = box ? (int)(bi / (uint32_t)loss_blocks_per_view(box)) : 0;
+        if (box && v < nviews) {
+            const ViewDesc vd = views[v];
+            f = fovea_tiles(gaze, v, radius_frac, vd.width, vd.height, tile);
+        }
+        *s_f = f;
+    }
+    __syncthreads();
+    return *s_f;
 }
 
 __global__ __launch_bounds__(kLossBlock) void k_loss_count(const float *__restrict__ gaze,
                                                            float radius_frac,
                                                            const ViewDesc *__restrict__ views,
                                                            int nviews, int64_t total_pix, int box,
-                                                           int tile, uint32_t channels, int64_t npix,
+                                                           int tile, uint32_t channels, int nblocks,
                                                            uint32_t *__restrict__ mask_count) {
     __shared__ uint32_t s_cnt;
+    __shared__ FoveaTiles s_f;
     if (threadIdx.x == 0) s_cnt = 0u;
-    __syncthreads();
-    // grid-stride over the launch's pixels: one LDS atomic per wave and step,
+    // grid-stride over the launch's blocks: one LDS atomic per wave and step,
     // one global atomic per workgroup (atomics on one address serialise, so
     // their number is kept to the grid's)
-    for (uint32_t p0 = blockIdx.x * kLossBlock; p0 < (uint32_t)npix; p0 += gridDim.x * kLossBlock) {
-        const uint32_t p = p0 + threadIdx.x;
+    for (uint32_t bi = blockIdx.x; bi < (uint32_t)nblocks; bi += gridDim.x) {
+        const FoveaTiles f = block_fovea(bi, box, tile, gaze, radius_frac, views, nviews, &s_f);
         int v, x, y;
         bool in = false;
-        if (p < (uint32_t)npix &&
-            loss_pixel(p, (uint32_t)total_pix, box, tile, gaze, radius_frac, views, nviews, v, x, y)) {
+        if (loss_pixel(bi, threadIdx.x, (uint32_t)total_pix, box, tile, f, views, nviews, v, x, y)) {
             const ViewDesc vd = views[v];
             in = in_fovea(gaze, v, x, y, radius_frac * (float)vd.width);
         }
@@ -897,11 +940,13 @@ __global__ __launch_bounds__(kLossBlock) void k_loss_l1(
     const uint32_t *__restrict__ mask_count, uint32_t count_host, float *__restrict__ dl,
     float *__restrict__ partial) {
     __shared__ float s_red[kLossBlock / 64];
+    __shared__ FoveaTiles s_f;
     const uint32_t cnt = mask_count ? *mask_count : count_host;
-    const uint32_t p = blockIdx.x * kLossBlock + threadIdx.x;
+    const FoveaTiles f = box ? block_fovea(blockIdx.x, box, tile, gaze, radius_frac, views, nviews, &s_f)
+                             : FoveaTiles{1, 0, 1, 0};
     float s = 0.f;
     int v, x, y;
-    if (loss_pixel(p, (uint32_t)total_pix, box, tile, gaze, radius_frac, views, nviews, v, x, y)) {
+    if (loss_pixel(blockIdx.x, threadIdx.x, (uint32_t)total_pix, box, tile, f, views, nviews, v, x, y)) {
         const ViewDesc vd = views[v];
         const int q = y * vd.width + x;
         const size_t plane = (size_t)vd.width * vd.height;
@@ -1097,7 +1142,15 @@ void launch_count_pairs(hipStream_t s, int tile, int total_tiles, const uint2 *r
         k_count_pairs<32><<<total_tiles, 256, 0, s>>>(ranges, vals, sp, views, nviews, counters);
 }
 
-int loss_partials(int64_t total_pix) { return (int)((total_pix + kLossBlock - 1) / kLossBlock); }
+// Partial sums of a loss launch: one per block (a fovea-window launch's views
+// are padded to whole blocks, at most one more block per view).
+int loss_partials(int64_t total_pix) {
+    return (int)((total_pix + kLossBlock - 1) / kLossBlock) + kMaxViews;
+}
+
+int loss_launch_blocks(int64_t total_pix, int nviews, int box) {
+    return box ? nviews * loss_blocks_per_view(box) : (int)((total_pix + kLossBlock - 1) / kLossBlock);
+}
 
 void launch_loss_l1(hipStream_t s, const float *rgba, const float *target, const float *gaze,
                     float radius_frac, const ViewDesc *views, int nviews, int64_t total_pix,
@@ -1106,7 +1159,7 @@ void launch_loss_l1(hipStream_t s, const float *rgba, const float *target, const
                     const float *bg, uint32_t norm_count, bool accumulate) {
     if (!gaze) box = 0;
     const uint32_t channels = alpha_term ? 4u : 3u;
-    const int nb = loss_partials(box ? (int64_t)nviews * box * box : total_pix);
+    const int nb = loss_launch_blocks(total_pix, nviews, box);
     if (gaze && norm_count == 0u)
         launch_loss_count(s, gaze, radius_frac, views, nviews, total_pix, box, tile, channels,
                           mask_count);
@@ -1120,11 +1173,10 @@ void launch_loss_l1(hipStream_t s, const float *rgba, const float *target, const
 void launch_loss_count(hipStream_t s, const float *gaze, float radius_frac, const ViewDesc *views,
                        int nviews, int64_t total_pix, int box, int tile, uint32_t channels,
                        uint32_t *mask_count) {
-    const int64_t npix = box ? (int64_t)nviews * box * box : total_pix;
-    const int nb = loss_partials(npix);
+    const int nb = loss_launch_blocks(total_pix, nviews, box);
     k_fill_u32<<<1, 64, 0, s>>>(mask_count, 1, 0u);
     k_loss_count<<<std::min(nb, 1024), kLossBlock, 0, s>>>(gaze, radius_frac, views, nviews,
-                                                           total_pix, box, tile, channels, npix,
+                                                           total_pix, box, tile, channels, nb,
                                                            mask_count);
 }
 
