@@ -39,7 +39,7 @@ _lib = None
 def build(force: bool = False) -> str:
     """Compile the oracle with gcc (FP64, OpenMP, no fast-math)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
+        tmp = f"{_LIB}.{os.getpid()}.tmp"   # concurrent test workers each build their own
         cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
                "-fno-fast-math", "-Wall", "-o", tmp, _SRC, "-lm"]
         subprocess.run(cmd, check=True)
@@ -189,6 +189,13 @@ def discrete(params, cams, tile: int) -> Discrete:
     return Discrete(keys[:M], vals[:M], ranges, rflags, M)
 
 
+def fovea_radius(radius_frac, width):
+    """The fovea radius in pixels as the compositing path forms it: the
+    fraction and the width in float32, their product rounded to float32 (the
+    mask decides an integer, so both sides take it in the same precision)."""
+    return float(np.float32(np.float32(radius_frac) * np.float32(width)))
+
+
 def loss_l1_view(rgba, target, cam, gaze=None, radius=0.0):
     """(sum, count, sign[4][npix]) of one view's masked L1 term."""
     rgba = _d(rgba).reshape(4, -1)
@@ -208,7 +215,7 @@ def loss_l1(rgbas, targets, cams, gazes=None, radius_frac=0.2):
     sums, cnts, dls = 0.0, 0, []
     for v, cam in enumerate(cams):
         g = None if gazes is None else gazes[v]
-        s, c, dl = loss_l1_view(rgbas[v], targets[v], cam, g, radius_frac * cam.width)
+        s, c, dl = loss_l1_view(rgbas[v], targets[v], cam, g, fovea_radius(radius_frac, cam.width))
         sums += s
         cnts += c
         dls.append(dl)
@@ -230,7 +237,7 @@ def loss_l1_rgba(rgbas, targets, cams, bgs=None, alpha=True, gazes=None, radius_
         g = None if gazes is None else _d(gazes[v])
         bg = None if bgs is None else _d(bgs[v])
         sums += lib().orc_loss_l1_rgba(_p(rgba), _p(tgt), _p(bg), cam.width, cam.height, _p(g),
-                                       float(radius_frac * cam.width), int(bool(alpha)), _p(dl),
+                                       fovea_radius(radius_frac, cam.width), int(bool(alpha)), _p(dl),
                                        _p(cnt, ct.c_int64))
         cnts += int(cnt[0])
         dls.append(dl)

@@ -808,21 +808,32 @@ int orc_discrete(const double *P, int64_t n, int deg, const double *cams, int nv
 }
 
 /* --------------------------------------------------------------- loss, Adam */
+/* Fovea mask of pixel (x, y): its centre within `radius` of the gaze point,
+ * inclusive (Method, "Periphery Model Training": the loss covers the fovea).
+ * The test decides which entries the mean covers, an integer, so it is taken
+ * in the compositing path's single precision: gaze and radius rounded to
+ * float, then (x + 0.5 - gx)^2 + (y + 0.5 - gy)^2 <= radius^2 with every
+ * operation rounded to float (no contraction; the build passes
+ * -ffp-contract=off).  In double, a centre within a few float ulps of the
+ * circle could land on the other side. */
+static int in_fovea32(int64_t x, int64_t y, const double *gaze, double radius) {
+    const float r = (float)radius;
+    const float dx = ((float)x + 0.5f) - (float)gaze[0];
+    const float dy = ((float)y + 0.5f) - (float)gaze[1];
+    return dx * dx + dy * dy <= r * r;
+}
+
 /* Sum of |RGB - target| over the masked pixel-channels of one view and its
- * sign (written to dl [4][H*W], alpha channel zero).  Mask: pixel centre
- * within radius of the gaze point (inclusive); gaze == NULL means no mask.
- * Returns the number of masked pixel-channels in *count. */
+ * sign (written to dl [4][H*W], alpha channel zero).  Mask: in_fovea32;
+ * gaze == NULL means no mask.  Returns the number of masked pixel-channels in
+ * *count. */
 double orc_loss_l1(const double *rgba, const double *target, int64_t w, int64_t h,
                    const double *gaze, double radius, double *dl, int64_t *count) {
     const int64_t npix = w * h;
     double sum = 0;
     int64_t cnt = 0;
     for (int64_t k = 0; k < npix; k++) {
-        int in = 1;
-        if (gaze) {
-            const double dx = (double)(k % w) + 0.5 - gaze[0], dy = (double)(k / w) + 0.5 - gaze[1];
-            in = dx * dx + dy * dy <= radius * radius;
-        }
+        const int in = gaze ? in_fovea32(k % w, k / w, gaze, radius) : 1;
         dl[3 * npix + k] = 0;
         for (int c = 0; c < 3; c++) {
             const double d = rgba[c * npix + k] - target[c * npix + k];
@@ -854,11 +865,7 @@ double orc_loss_l1_rgba(const double *rgba, const double *target_rgba, const dou
     double sum = 0;
     int64_t cnt = 0;
     for (int64_t k = 0; k < npix; k++) {
-        int in = 1;
-        if (gaze) {
-            const double dx = (double)(k % w) + 0.5 - gaze[0], dy = (double)(k / w) + 0.5 - gaze[1];
-            in = dx * dx + dy * dy <= radius * radius;
-        }
+        const int in = gaze ? in_fovea32(k % w, k / w, gaze, radius) : 1;
         const double ta = target_rgba[3 * npix + k];
         for (int c = 0; c < 4; c++) {
             double t = target_rgba[c * npix + k];

@@ -599,6 +599,22 @@ def test_l1_loss_and_sign_gradient():
     assert (dlm[0][:, ~m] == 0).all()
 
 
+def test_fovea_mask_counts_the_lattice_points_of_the_disk():
+    """Gaze on a pixel centre and an integer radius: the mask holds the
+    integer points of a closed disk, whose number the Gauss circle problem
+    gives as 1 + 4 floor(r) + 4 sum_{i=1}^{floor(r)} floor(sqrt(r^2 - i^2));
+    known values N(1..10) = 5, 13, 29, 49, 81, 113, 149, 197, 253, 317."""
+    known = [5, 13, 29, 49, 81, 113, 149, 197, 253, 317]
+    cam = synth.axis_camera(64, 64)
+    z, t = np.zeros((4, cam.npix)), np.ones((3, cam.npix))
+    for r, n in zip(range(1, 11), known):
+        closed = 1 + 4 * r + 4 * sum(int(np.floor(np.sqrt(r * r - i * i))) for i in range(1, r + 1))
+        assert closed == n
+        _, cnt, _ = oracle.loss_l1_view(z, t, cam, np.array([32.5, 31.5]),
+                                        oracle.fovea_radius(r / 64, 64))
+        assert cnt == 3 * n, (r, cnt)
+
+
 def test_rgba_loss_reduces_to_rgb_loss_and_hand_values():
     rng = np.random.default_rng(3)
     cam = synth.axis_camera(12, 9)
