@@ -484,12 +484,13 @@ void launch_loss_l1(hipStream_t s, const float *rgba, const float *target, const
                     float radius_frac, const ViewDesc *views, int nviews, int64_t total_pix,
                     float *dl, float *partial, uint32_t *mask_count, float *loss, uint32_t *flags,
                     int32_t *step_inc, int box, int tile, int tgt_planes, bool alpha_term,
-                    const float *bg, uint32_t norm_count = 0u, bool accumulate = false);
+                    const float *bg, uint32_t norm_count, bool accumulate, int max_height);
 // norm_count > 0: the mean divides by it (entries over all plans of a multi-plan
 // loss) instead of the plan's own masked count; accumulate: loss[0] += the share.
+// max_height: the tallest view's height.
 // The masked entry count alone (gaze required) into mask_count[0].
 void launch_loss_count(hipStream_t s, const float *gaze, float radius_frac, const ViewDesc *views,
-                       int nviews, int64_t total_pix, int box, int tile, uint32_t channels,
+                       int nviews, int max_height, int box, int tile, uint32_t channels,
                        uint32_t *mask_count);
 
 // bg[v][c] = top 24 bits of output 1 + (step[0] * kMaxViews + v) * 4 + c of

@@ -309,6 +309,12 @@ struct StageTimer {
 
 // Side of the per-view pixel window that holds every tile meeting the fovea
 // (0 when the window would not be smaller than the views).
+int max_height(const gsf_plan *p) {
+    int h = 0;
+    for (const ViewDesc &vd : p->views) h = std::max(h, (int)vd.height);
+    return h;
+}
+
 int fovea_box(const gsf_plan *p, float radius_frac) {
     int wmax = 1;
     for (const ViewDesc &vd : p->views) wmax = std::max(wmax, (int)vd.width);
@@ -423,7 +429,8 @@ gsf_status enqueue_loss(gsf_plan *p, const float *rgba, const float *target, con
     StageTimer t(p, GSF_STAGE_LOSS);
     launch_loss_l1(p->ctx->stream, rgba, target, gaze, radius_frac, p->b.views, p->V,
                    p->total_pix, dl, p->b.loss_partial, p->b.mask_count, loss, p->b.flags,
-                   step_inc, box, p->tile, tgt_planes, alpha_term, bg, norm_count, accumulate);
+                   step_inc, box, p->tile, tgt_planes, alpha_term, bg, norm_count, accumulate,
+                   max_height(p));
     GSF_LAUNCHED(p->ctx);
     return GSF_OK;
 }
@@ -735,7 +742,7 @@ gsf_status gsf_loss_count(gsf_plan *p, const float *gaze_px, float mask_radius_f
         return GSF_OK;
     }
     if (!(mask_radius_frac >= 0.f)) return fail(p->ctx, GSF_E_INVALID, "gsf_loss_count: bad radius");
-    launch_loss_count(p->ctx->stream, gaze_px, mask_radius_frac, p->b.views, p->V, p->total_pix,
+    launch_loss_count(p->ctx->stream, gaze_px, mask_radius_frac, p->b.views, p->V, max_height(p),
                       fovea_box(p, mask_radius_frac), p->tile, 3u, p->b.mask_count);
     GSF_LAUNCHED(p->ctx);
     uint32_t c = 0;

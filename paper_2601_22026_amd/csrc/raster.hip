@@ -581,6 +581,9 @@ __device__ __forceinline__ void render_bwd_unit(
                 const float dy = splat_dx(py[k], c.w, a.y);
                 const float power2 = splat_power2(a, b, dx, dy);
                 const bool inc = (pos < nc[k]) & !(power2 > 0.f) & !(power2 < c.y);
+                // no pixel of the block takes the splat: every lane would add
+                // zeros and keep its state (wave-uniform)
+                if (QUAD && !__any(inc)) continue;
                 const float ex = __builtin_amdgcn_exp2f(power2);
                 const float ae = b.y * ex;
                 const float alpha = fminf(kAlphaMax, ae);
@@ -901,31 +904,69 @@ __device__ __forceinline__ FoveaTiles block_fovea(uint32_t bi, int box, int tile
     return *s_f;
 }
 
+// The masked entries, one thread per (view, row of the pixels the loss visits):
+// every pixel of the view (box == 0) or of its box x box window from its first
+// fovea tile, clipped to the view and to the fovea tiles (as loss_pixel).  On a
+// row the mask is an interval: in_fovea compares fl(dx)^2 + dy^2 with r^2, where
+// dx = fl(x + 0.5 - gaze_x), and rounding is monotone, so the test can only turn
+// false as |x + 0.5 - gaze_x| grows.  The row's pixel nearest the gaze column
+// decides whether it has any, and a binary search each way (on that same test)
+// finds the ends: the count equals the pixel-by-pixel count exactly.
 __global__ __launch_bounds__(kLossBlock) void k_loss_count(const float *__restrict__ gaze,
                                                            float radius_frac,
                                                            const ViewDesc *__restrict__ views,
-                                                           int nviews, int64_t total_pix, int box,
-                                                           int tile, uint32_t channels, int nblocks,
+                                                           int nviews, int rows, int box, int tile,
+                                                           uint32_t channels,
                                                            uint32_t *__restrict__ mask_count) {
-    __shared__ uint32_t s_cnt;
-    __shared__ FoveaTiles s_f;
-    if (threadIdx.x == 0) s_cnt = 0u;
-    // grid-stride over the launch's blocks: one LDS atomic per wave and step,
-    // one global atomic per workgroup (atomics on one address serialise, so
-    // their number is kept to the grid's)
-    for (uint32_t bi = blockIdx.x; bi < (uint32_t)nblocks; bi += gridDim.x) {
-        const FoveaTiles f = block_fovea(bi, box, tile, gaze, radius_frac, views, nviews, &s_f);
-        int v, x, y;
-        bool in = false;
-        if (loss_pixel(bi, threadIdx.x, (uint32_t)total_pix, box, tile, f, views, nviews, v, x, y)) {
-            const ViewDesc vd = views[v];
-            in = in_fovea(gaze, v, x, y, radius_frac * (float)vd.width);
+    __shared__ uint32_t s_red[kLossBlock / 64];
+    const uint32_t i = blockIdx.x * kLossBlock + threadIdx.x;
+    const int v = (int)(i / (uint32_t)rows);
+    const int row = (int)(i - (uint32_t)v * (uint32_t)rows);
+    uint32_t n = 0u;
+    if (v < nviews) {
+        const ViewDesc vd = views[v];
+        int x0 = 0, x1 = vd.width - 1, y = row;
+        bool ok = row < vd.height;
+        if (box) {
+            const FoveaTiles f = fovea_tiles(gaze, v, radius_frac, vd.width, vd.height, tile);
+            x0 = f.tx0 * tile;
+            x1 = min(min((f.tx1 + 1) * tile, vd.width), x0 + box) - 1;
+            y = f.ty0 * tile + row;
+            ok = f.tx0 <= f.tx1 && y < min((f.ty1 + 1) * tile, vd.height);
         }
-        const uint32_t n = (uint32_t)__popcll(__ballot(in));
-        if (__lane_id() == 0 && n) atomicAdd(&s_cnt, n * channels);
+        if (ok) {
+            const float rad = radius_frac * (float)vd.width;
+            // the row's pixel nearest the gaze column (fmaxf takes x0 for a NaN gaze)
+            const int xm = (int)fminf(fmaxf(rintf(gaze[2 * v] - 0.5f), (float)x0), (float)x1);
+            if (in_fovea(gaze, v, xm, y, rad)) {
+                int lo = xm, hi = x1 + 1;   // in at lo, out at hi (or past the row)
+                while (hi - lo > 1) {
+                    const int mid = lo + (hi - lo) / 2;
+                    if (in_fovea(gaze, v, mid, y, rad)) lo = mid;
+                    else hi = mid;
+                }
+                const int xr = lo;
+                lo = x0 - 1;   // out at lo (or before the row), in at hi
+                hi = xm;
+                while (hi - lo > 1) {
+                    const int mid = lo + (hi - lo) / 2;
+                    if (in_fovea(gaze, v, mid, y, rad)) hi = mid;
+                    else lo = mid;
+                }
+                n = (uint32_t)(xr - hi + 1) * channels;
+            }
+        }
     }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) n += (uint32_t)__shfl_xor((int)n, o, 64);
+    if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = n;
     __syncthreads();
-    if (threadIdx.x == 0 && s_cnt) atomicAdd(mask_count, s_cnt);
+    if (threadIdx.x == 0) {
+        uint32_t tot = 0u;
+#pragma unroll
+        for (int w = 0; w < kLossBlock / 64; w++) tot += s_red[w];
+        if (tot) atomicAdd(mask_count, tot);
+    }
 }
 
 // Per-pixel L1 terms and sign gradient, and one partial sum per workgroup.
@@ -1156,12 +1197,12 @@ void launch_loss_l1(hipStream_t s, const float *rgba, const float *target, const
                     float radius_frac, const ViewDesc *views, int nviews, int64_t total_pix,
                     float *dl, float *partial, uint32_t *mask_count, float *loss, uint32_t *flags,
                     int32_t *step_inc, int box, int tile, int tgt_planes, bool alpha_term,
-                    const float *bg, uint32_t norm_count, bool accumulate) {
+                    const float *bg, uint32_t norm_count, bool accumulate, int max_height) {
     if (!gaze) box = 0;
     const uint32_t channels = alpha_term ? 4u : 3u;
     const int nb = loss_launch_blocks(total_pix, nviews, box);
     if (gaze && norm_count == 0u)
-        launch_loss_count(s, gaze, radius_frac, views, nviews, total_pix, box, tile, channels,
+        launch_loss_count(s, gaze, radius_frac, views, nviews, max_height, box, tile, channels,
                           mask_count);
     const uint32_t *mc = gaze && norm_count == 0u ? mask_count : nullptr;
     const uint32_t cnt = norm_count ? norm_count : (uint32_t)(channels * total_pix);
@@ -1171,13 +1212,14 @@ void launch_loss_l1(hipStream_t s, const float *rgba, const float *target, const
 }
 
 void launch_loss_count(hipStream_t s, const float *gaze, float radius_frac, const ViewDesc *views,
-                       int nviews, int64_t total_pix, int box, int tile, uint32_t channels,
+                       int nviews, int max_height, int box, int tile, uint32_t channels,
                        uint32_t *mask_count) {
-    const int nb = loss_launch_blocks(total_pix, nviews, box);
+    const int rows = box ? box : max_height;
+    const int64_t threads = (int64_t)nviews * rows;
     k_fill_u32<<<1, 64, 0, s>>>(mask_count, 1, 0u);
-    k_loss_count<<<std::min(nb, 1024), kLossBlock, 0, s>>>(gaze, radius_frac, views, nviews,
-                                                           total_pix, box, tile, channels, nb,
-                                                           mask_count);
+    if (threads > 0)
+        k_loss_count<<<(int)((threads + kLossBlock - 1) / kLossBlock), kLossBlock, 0, s>>>(
+            gaze, radius_frac, views, nviews, rows, box, tile, channels, mask_count);
 }
 
 void launch_draw_bg(hipStream_t s, uint64_t seed, const int32_t *step, int nviews, float *bg) {

@@ -35,6 +35,7 @@ constexpr int kSortIpt = 8;                  // keys per thread per chunk tile
 constexpr int kSortTile = kSortBlock * kSortIpt;
 constexpr int kSortMaxGrid = 1024;
 constexpr int kMaxDigit = 8;                 // radix digits of at most 256 bins
+constexpr int kHistU = 16;                   // keys in flight per thread while counting digits
 constexpr int kScanBlock = 256;
 constexpr int kScanIpt = 1;                  // 256 records per block: 50k records fill 196 blocks
 constexpr int kScanTile = kScanBlock * kScanIpt;
@@ -88,8 +89,20 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_hist(const uint32_t *__res
     for (int d = threadIdx.x; d < 4 * 256; d += kSortBlock) (&h[0][0])[d] = 0u;
     __syncthreads();
     const uint32_t mask = (1u << bits) - 1u;
-    for (uint32_t idx = start + threadIdx.x; idx < end; idx += kSortBlock)
-        atomicAdd(&h[w][(keys[idx] >> shift) & mask], 1u);
+    // kHistU keys per thread are loaded before any is counted, so their loads
+    // are in flight together
+    for (uint32_t base = start; base < end; base += kSortBlock * kHistU) {
+        uint32_t k[kHistU];
+#pragma unroll
+        for (int u = 0; u < kHistU; u++) {
+            const uint32_t idx = base + (uint32_t)(u * kSortBlock) + threadIdx.x;
+            k[u] = idx < end ? keys[idx] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < kHistU; u++)
+            if (base + (uint32_t)(u * kSortBlock) + threadIdx.x < end)
+                atomicAdd(&h[w][(k[u] >> shift) & mask], 1u);
+    }
     __syncthreads();
     const int nd = 1 << bits;
     for (int d = threadIdx.x; d < nd; d += kSortBlock)
@@ -160,13 +173,19 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(
         __syncthreads();
         uint32_t key[kSortIpt], val[kSortIpt], rank[kSortIpt];
         const uint32_t wbase = tile0 + (uint32_t)w * span;
+        // every load of the round is issued before the ranking waits on any
+#pragma unroll
+        for (int r = 0; r < kSortIpt; r++) {
+            const uint32_t idx = wbase + (uint32_t)r * 64u + (uint32_t)lane;
+            const bool valid = r < rounds && idx < end;
+            key[r] = valid ? kin[idx] : 0u;
+            val[r] = valid ? vin[idx] : 0u;
+        }
 #pragma unroll
         for (int r = 0; r < kSortIpt; r++) {
             if (r >= rounds) break;
             const uint32_t idx = wbase + (uint32_t)r * 64u + (uint32_t)lane;
             const bool valid = idx < end;
-            key[r] = valid ? kin[idx] : 0u;
-            val[r] = valid ? vin[idx] : 0u;
             const uint32_t d = (key[r] >> shift) & mask;
             uint64_t peers = __ballot(valid);
             for (int b = 0; b < bits; b++) {

@@ -207,6 +207,47 @@ def test_loss_and_dl_match_oracle(ctx):
     np.testing.assert_allclose(dl.cpu().numpy().reshape(4, -1), dls[0], rtol=1e-6, atol=0)
 
 
+@pytest.mark.parametrize("radius_frac", [0.05, 0.2, 0.9])
+def test_loss_mask_count_is_exact(ctx, radius_frac):
+    """The masked entry count (one thread per row: the row's mask is an
+    interval whose ends a binary search finds) equals the oracle's
+    pixel-by-pixel count, which takes the same single-precision test, on
+    uneven views with gaze points inside, on a corner of, on the edge of and
+    outside the image; the fovea windows (radius 0.05, 0.2) and the whole
+    frames (0.9) are both counted.  The loss then divides by it."""
+    sizes = [(1920, 1920), (333, 217), (64, 48), (1000, 700), (517, 901)]
+    cams = [synth.axis_camera(w, h) for w, h in sizes]
+    rng = np.random.default_rng(11)
+    gaze = np.array([[rng.uniform(0, w), rng.uniform(0, h)] for w, h in sizes], np.float32)
+    gaze[1] = (0.0, 0.0)
+    gaze[2] = (-5.0, 24.0)
+    gaze[3] = (999.7, 700.0)
+    sc = GpuScene(ctx, synth.random_gaussians(10, seed=1), cams)
+    gz = torch.from_numpy(gaze).to("cuda:0")
+    got = sc.plan.loss_count(gz, radius_frac)
+    imgs = sc.forward()
+    tgts = [np.random.default_rng(12 + v).uniform(size=(3, c.npix)).astype(np.float32)
+            for v, c in enumerate(cams)]
+    want = 0
+    for v, c in enumerate(cams):
+        _, cnt, _ = oracle.loss_l1_view(imgs[v].astype(np.float64), tgts[v].astype(np.float64), c,
+                                        gaze[v].astype(np.float64),
+                                        oracle.fovea_radius(radius_frac, c.width))
+        want += cnt
+    log(f"[parity] mask count radius {radius_frac}: {got} (oracle {want})")
+    assert got == want
+    loss = torch.zeros(1, device="cuda:0")
+    dl = torch.zeros(4 * sum(c.npix for c in cams), device="cuda:0")
+    tgt = torch.from_numpy(np.concatenate([t.reshape(-1) for t in tgts])).to("cuda:0")
+    sc.plan.loss_l1(sc.rgba, tgt, loss, dl, gaze=gz, radius_frac=radius_frac)
+    torch.cuda.synchronize()
+    L, dls = oracle.loss_l1([i.astype(np.float64) for i in imgs], [t.astype(np.float64) for t in tgts],
+                            cams, gazes=gaze.astype(np.float64), radius_frac=radius_frac)
+    assert abs(loss.item() - L) <= 1e-5 * L
+    np.testing.assert_allclose(dl.cpu().numpy(), np.concatenate([d.reshape(-1) for d in dls]),
+                               rtol=1e-6, atol=0)
+
+
 @pytest.mark.parametrize("tile,batch", [(8, 64), (16, 64), (16, 128), (32, 64)])
 def test_transmittance_modes_agree(ctx, tile, batch):
     """Recomputed, checkpointed and stored transmittance: same image bits,
