@@ -236,9 +236,30 @@ def radix_passes(bits):
     return 0 if bits <= 0 else (bits + 7) // 8
 
 
+def composited_pixels(cams, gaze, radius_frac, tile):
+    """Pixels of the tiles a fovea-culled step composites, back-propagates and
+    takes the loss over: per view, the tiles that meet the box of pixel centres
+    within the radius of the gaze point plus one pixel, clipped to the view."""
+    import numpy as np
+    n = 0
+    for c, (gx, gy) in zip(cams, gaze):
+        r = np.float32(radius_frac) * np.float32(c.width)
+        x0 = max(np.floor(gx - r - 0.5) - 1, 0)
+        x1 = min(np.ceil(gx + r - 0.5) + 1, c.width - 1)
+        y0 = max(np.floor(gy - r - 0.5) - 1, 0)
+        y1 = min(np.ceil(gy + r - 0.5) + 1, c.height - 1)
+        if x0 > x1 or y0 > y1:
+            continue
+        tx0, tx1, ty0, ty1 = int(x0) // tile, int(x1) // tile, int(y0) // tile, int(y1) // tile
+        n += ((min((tx1 + 1) * tile, c.width) - tx0 * tile)
+              * (min((ty1 + 1) * tile, c.height) - ty0 * tile))
+    return n
+
+
 def hbm_bytes_per_launch(stage, N, R, M, npix, planes, tiles, A):
     """Algorithmic HBM bytes one launch of a stage must move: N Gaussians,
-    R = N * views records, A of them listing a tile, M keys, npix pixels,
+    R = N * views records, A of them listing a tile, M keys, npix pixels
+    composited (the fovea tiles' pixels when the step is fovea-culled),
     `planes` floats per Gaussian."""
     tile_passes = radix_passes(max(1, (tiles - 1).bit_length()))
     return {
@@ -709,7 +730,7 @@ def main():
             log(f"[bench] fused full-frame: {ms_full * 1e3:.1f} us/step")
 
         regen = None
-        if wl.name == "foveal":
+        if wl.name == "foveal" and args.regen_runs > 0:
             # one regeneration: seed the Gaussians on the device from the resident
             # volume, plan, capture, run the steps - wall clock, synchronised
             import synth
@@ -846,6 +867,7 @@ def main():
 
     # roofline of the dominant kernel
     R = N * len(step_cams)
+    apix = (composited_pixels(step_cams, wl.gaze, cfg.radius_frac, cfg.tile) if cull else npix)
     dom = max(stages, key=stages.get)
     traffic = profiled_traffic(wl.name, dom, cfg.tile, cfg.lds_batch)
     if dom in ("render", "render_bwd"):
@@ -861,21 +883,21 @@ def main():
                 "us_per_launch": round(stages[dom] * 1e3, 2),
                 "work": {"flops_per_launch": int(flops), **pairs}}
     else:
-        byt = hbm_bytes_per_launch(dom, N, R, M, npix, planes, total_tiles, A)
+        byt = hbm_bytes_per_launch(dom, N, R, M, apix, planes, total_tiles, A)
         ach = byt / (stages[dom] * 1e-3) / 1e9
         roof = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS,
                 "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": traffic,
                 "us_per_launch": round(stages[dom] * 1e3, 2)}
     stage_roof = {}
     for k, ms in stages.items():
-        byt = hbm_bytes_per_launch(k, N, R, M, npix, planes, total_tiles, A)
+        byt = hbm_bytes_per_launch(k, N, R, M, apix, planes, total_tiles, A)
         stage_roof[k] = {"us": round(ms * 1e3, 2), "gbs": round(byt / (ms * 1e-3) / 1e9, 1)}
         if k in ("render", "render_bwd"):
             fl = (FLOPS_ALPHA * pairs["visited_fwd"] + FLOPS_FWD_INCLUDED * pairs["included"]
                   if k == "render" else
                   FLOPS_ALPHA * pairs["visited_bwd"] + FLOPS_BWD_INCLUDED * pairs["included"])
             stage_roof[k]["tflops"] = round(fl / (ms * 1e-3) / 1e12, 3)
-    step_bytes = sum(hbm_bytes_per_launch(k, N, R, M, npix, planes, total_tiles, A) for k in stages)
+    step_bytes = sum(hbm_bytes_per_launch(k, N, R, M, apix, planes, total_tiles, A) for k in stages)
 
     steps_per_s = 1000.0 / ms_fused
     res = {
@@ -901,6 +923,8 @@ def main():
         "median_step_ms": round(med_fused, 4),
         "flags_after_timed_steps": flags,
         "mpix_per_s": round(npix * steps_per_s / 1e6, 1),
+        "composited_pixels_per_step": apix,
+        "composited_mpix_per_s": round(apix * steps_per_s / 1e6, 1),
         "eager_fused_steps_per_s": round(1000.0 / ms_eager, 2),
         "plain_steps_per_s": round(1000.0 / ms_plain, 2) if ms_plain else None,
         "vs_plain": round(ms_plain / ms_fused, 3) if ms_plain else None,
