@@ -31,7 +31,7 @@ namespace gsf {
 namespace {
 
 constexpr int kSortBlock = 256;              // threads per radix-sort workgroup (4 waves)
-constexpr int kSortIpt = 8;                  // keys per thread per chunk tile
+constexpr int kSortIpt = 16;                 // keys per thread per chunk tile
 constexpr int kSortTile = kSortBlock * kSortIpt;
 constexpr int kSortMaxGrid = 1024;
 constexpr int kMaxDigit = 8;                 // radix digits of at most 256 bins
