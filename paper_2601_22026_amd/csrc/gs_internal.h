@@ -48,10 +48,18 @@ struct ViewDesc {
 // i.e. A2 = -log2(e) A / 2, B2 = -log2(e) B, C2 = -log2(e) C / 2; the
 // compositing kernels compare power2 with tau = log2(1 / (255 opacity)), below
 // which alpha < 1/255.
+// The splat of a record (record = Gaussian x view) as one 64-byte aligned
+// chunk, the four float4 that staging a key reads: a, b, c and the support
+// ellipse.  A key's staging gathers one chunk instead of a piece of four
+// arrays; the projection writes each chunk whole (a partial 64-byte chunk
+// would cost the memory a read-modify-write).
+constexpr int kRecF4 = 4;
+constexpr int kRecA = 0, kRecB = 1, kRecC = 2, kRecEll = 3;
 struct SplatPtrs {
-    float4 *a;
-    float4 *b;
-    float4 *c;
+    float4 *rec;   // [records][kRecF4]
+    __host__ __device__ float4 *at(uint32_t r, int slot) const {
+        return rec + (size_t)r * kRecF4 + slot;
+    }
 };
 constexpr float kLog2e = 1.4426950408889634f;
 
@@ -168,7 +176,6 @@ struct KeyPlace {
     const uint32_t *koff = nullptr, *count = nullptr;
     const uint2 *rect = nullptr, *rspan = nullptr;
     const uint2 *rowtab = nullptr;              // row tables of the boxes not packed
-    const float4 *ell = nullptr;
     float4 *pa = nullptr, *pb = nullptr;
     float *pc = nullptr;
     const unsigned long long *m_total = nullptr;
@@ -179,13 +186,12 @@ struct KeyPlace {
 // the tile's rank among the record's listed tiles, from the packed row spans
 // or (other boxes) the row table entry of row ty, found by binary search.
 __device__ __forceinline__ uint32_t key_slot(const KeyPlace &kp, uint32_t r, int ty, int tx) {
-    const uint2 rc = kp.rect[r];
+    const uint2 rc = kp.rect[r], pk = kp.rspan[r];
     const int x0 = (int)(rc.x & 0xFFFFu), y0 = (int)(rc.x >> 16);
     const int x1 = (int)(rc.y & 0xFFFFu), y1 = (int)(rc.y >> 16);
     const int rows = y1 - y0 + 1, cols = x1 - x0 + 1;
     const uint32_t base = kp.koff[r];
     uint32_t rank = 0;
-    const uint2 pk = kp.rspan[r];
     if (rows <= kPackRows && cols <= kPackCols) {
         const int kr = ty - y0;
         for (int k = 0; k < kr; k++) rank += (((k < 2 ? pk.x : pk.y) >> (16 * (k & 1))) >> 8) & 0xFFu;
@@ -352,11 +358,12 @@ struct TileMap {
 // ---- launchers (all asynchronous on `s`) -----------------------------------------
 
 // Projection of n Gaussians into V views: records r = v*n + i.  Writes the
-// splat, the depth key (float32 bits of the camera depth, 0xFFFFFFFF when
-// culled), the tile rectangle of the support box, the number of its tiles the
-// support ellipse reaches (row_span), the ellipse constants (slope, kw, ws,
-// dyr; ey follows as sqrt(kw / ws)) and the packed row spans of short boxes
-// (other boxes: the number of their rows that list a tile).
+// splat and the ellipse constants (slope, kw, ws, dyr; ey follows as
+// sqrt(kw / ws)) into the record (kRecA-kRecEll), the depth key (float32 bits
+// of the camera depth, 0xFFFFFFFF when culled), the tile rectangle of the
+// support box, the number of its tiles the support ellipse reaches (row_span)
+// and the packed row spans of short boxes (other boxes: the number of their
+// rows that list a tile).
 // With cull_gaze (nullable) the rectangle is clipped to the view's
 // fovea tiles (fovea_tiles with cull_radius).  block_sums[b] / block_act[b]
 // receive the total count / the number of records with a nonzero count among
@@ -364,9 +371,9 @@ struct TileMap {
 // launch_scan_records.
 void launch_project_fwd(hipStream_t s, const float *P, int n, int nviews, int deg,
                         const gsf_camera *cams, const ViewDesc *views, int tile, SplatPtrs sp,
-                        uint32_t *depth_key, uint2 *rect, uint32_t *count, float4 *ell,
-                        uint2 *rspan, const float *cull_gaze, float cull_radius,
-                        uint32_t *block_sums, uint32_t *block_act);
+                        uint32_t *depth_key, uint2 *rect, uint32_t *count, uint2 *rspan,
+                        const float *cull_gaze, float cull_radius, uint32_t *block_sums,
+                        uint32_t *block_act);
 
 // Parameter gradient from the per-key screen-space gradients the compositing
 // adjoint left in kp: for SH degrees 0-1 summed per record (wave_key_sum) on
@@ -388,7 +395,7 @@ void launch_project_bwd(hipStream_t s, const float *P, int n, int nviews, int de
 // (0 on overflow).  Clears ranges[total_tiles].  block_sums, block_act: the
 // per-256-record totals launch_project_fwd wrote, scanned in place; seg_tot,
 // seg_act: seg_count(nrec) entries of scratch.
-void launch_scan_records(hipStream_t s, const uint32_t *count, const uint2 *rect, const float4 *ell,
+void launch_scan_records(hipStream_t s, const uint32_t *count, const uint2 *rect,
                          const uint2 *rspan, SplatPtrs sp, const uint32_t *depth_key, uint32_t *koff,
                          uint2 *rowtab, int nrec, int n, int tile, const ViewDesc *views,
                          uint32_t *block_sums, uint32_t *block_act, unsigned long long *seg_tot,

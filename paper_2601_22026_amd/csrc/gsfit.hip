@@ -39,12 +39,10 @@ namespace {
 
 struct Buffers {
     // per record (view v, Gaussian i)
-    float4 *rec_a = nullptr, *rec_b = nullptr;
-    float4 *rec_c = nullptr;
+    float4 *rec = nullptr;                       // 64 B: splat and support ellipse (SplatPtrs)
     uint32_t *depth_key = nullptr;               // float32 depth bits; 0xFFFFFFFF = culled
     uint2 *rect = nullptr;                       // touched tile rectangle
     uint32_t *count = nullptr;                   // listed tiles
-    float4 *ell = nullptr;                       // support ellipse constants (Ellipse)
     uint2 *rspan = nullptr;                      // packed row spans of short boxes (else row-table size)
     uint32_t *koff = nullptr;                    // position of the record's first key (record order)
     uint32_t *block_sums = nullptr;              // scan of the per-record tile counts
@@ -158,13 +156,10 @@ size_t carve(gsf_plan *p, char *base, Buffers *out) {
     };
     const size_t R = (size_t)p->nrec_max;
     Buffers b;
-    b.rec_a = (float4 *)take(R * sizeof(float4));
-    b.rec_b = (float4 *)take(R * sizeof(float4));
-    b.rec_c = (float4 *)take(R * sizeof(float4));
+    b.rec = (float4 *)take(R * kRecF4 * sizeof(float4));   // 256-aligned: records on 64-byte chunks
     b.depth_key = (uint32_t *)take(R * 4);
     b.rect = (uint2 *)take(R * sizeof(uint2));
     b.count = (uint32_t *)take(R * 4);
-    b.ell = (float4 *)take(R * sizeof(float4));
     b.rspan = (uint2 *)take(R * sizeof(uint2));
     b.koff = (uint32_t *)take(R * 4);
     const size_t T = (size_t)p->total_tiles;
@@ -226,7 +221,7 @@ gsf_status check_ready(gsf_plan *p) {
     return GSF_OK;
 }
 
-SplatPtrs splats(gsf_plan *p) { return SplatPtrs{p->b.rec_a, p->b.rec_b, p->b.rec_c}; }
+SplatPtrs splats(gsf_plan *p) { return SplatPtrs{p->b.rec}; }
 
 RenderArgs render_args(gsf_plan *p, const gsf_camera *cams, int64_t n) {
     RenderArgs a;
@@ -256,7 +251,6 @@ RenderArgs render_args(gsf_plan *p, const gsf_camera *cams, int64_t n) {
     a.kp.rect = p->b.rect;
     a.kp.rspan = p->b.rspan;
     a.kp.rowtab = p->b.rowtab;
-    a.kp.ell = p->b.ell;
     a.kp.pa = p->b.pa;
     a.kp.pb = p->b.pb;
     a.kp.pc = p->b.pc;
@@ -340,14 +334,14 @@ gsf_status enqueue_forward(gsf_plan *p, const float *params, int64_t n, const gs
     {   // splats, support boxes and their tile counts, depth keys
         StageTimer t(p, GSF_STAGE_PROJECT);
         launch_project_fwd(s, params, (int)n, p->V, p->deg, cams, b.views, p->tile, splats(p),
-                           b.depth_key, b.rect, b.count, b.ell, b.rspan, cull_gaze, cull_radius,
+                           b.depth_key, b.rect, b.count, b.rspan, cull_gaze, cull_radius,
                            b.block_sums, b.block_act);
     }
     GSF_LAUNCHED(ctx);
     {   // record-order scan: gradient slots, row tables, key total + capacity check on
         // the device; the records with keys compacted with their depths
         StageTimer t(p, GSF_STAGE_DUPLICATE);
-        launch_scan_records(s, b.count, b.rect, b.ell, b.rspan, splats(p), b.depth_key, b.koff,
+        launch_scan_records(s, b.count, b.rect, b.rspan, splats(p), b.depth_key, b.koff,
                             b.rowtab, nrec, (int)n, p->tile, b.views, b.block_sums, b.block_act,
                             b.seg_tot, b.seg_act, b.m_dev, b.m_total, b.a_dev, b.flags, p->cap,
                             b.k0, b.v0, b.arec, b.ranges, (int)p->total_tiles);
@@ -1272,14 +1266,17 @@ gsf_status gsf_debug_copy(gsf_plan *p, int which, void *host_dst, size_t cap, si
         break;
     }
     case GSF_DBG_PROJ: {
-        std::vector<float4> a(R), b(R);
-        std::vector<float4> c(R);
+        std::vector<float4> rec(R * kRecF4);
         std::vector<uint32_t> dk(R);
         if (R) {
-            GSF_HIP(p->ctx, hipMemcpy(a.data(), p->b.rec_a, R * 16, hipMemcpyDeviceToHost));
-            GSF_HIP(p->ctx, hipMemcpy(b.data(), p->b.rec_b, R * 16, hipMemcpyDeviceToHost));
-            GSF_HIP(p->ctx, hipMemcpy(c.data(), p->b.rec_c, R * 16, hipMemcpyDeviceToHost));
+            GSF_HIP(p->ctx, hipMemcpy(rec.data(), p->b.rec, R * kRecF4 * 16, hipMemcpyDeviceToHost));
             GSF_HIP(p->ctx, hipMemcpy(dk.data(), p->b.depth_key, R * 4, hipMemcpyDeviceToHost));
+        }
+        std::vector<float4> a(R), b(R), c(R);
+        for (size_t r = 0; r < R; r++) {
+            a[r] = rec[r * kRecF4 + kRecA];
+            b[r] = rec[r * kRecF4 + kRecB];
+            c[r] = rec[r * kRecF4 + kRecC];
         }
         proj.resize(R * 11);
         // the stored conic is pre-scaled by -log2(e)/2 (A, C) and -log2(e) (B)

@@ -230,7 +230,6 @@ __device__ __forceinline__ uint32_t project_record(const float *__restrict__ P, 
                                                      SplatPtrs sp, uint32_t *__restrict__ depth_key,
                                                      uint2 *__restrict__ rect,
                                                      uint32_t *__restrict__ count,
-                                                     float4 *__restrict__ ell,
                                                      uint2 *__restrict__ rspan,
                                                      const float *__restrict__ cull_gaze,
                                                      float cull_radius) {
@@ -304,10 +303,10 @@ __device__ __forceinline__ uint32_t project_record(const float *__restrict__ P, 
     }
     // conic pre-scaled for a base-2 exponent, and the alpha threshold of the
     // same exponent: o 2^power2 >= 1/255 where power2 >= tau = -log2(255 o)
-    sp.a[r] = make_float4((float)(ixd + 0.5 - mxd), (float)(iyd + 0.5 - myd), (-0.5f * kLog2e) * p.A,
-                          -kLog2e * p.B);
-    sp.b[r] = make_float4((-0.5f * kLog2e) * p.C, g.o, col[0], col[1]);
-    sp.c[r] = make_float4(col[2], -log2f(255.f * g.o), (float)ixd, (float)iyd);
+    *sp.at(r, kRecA) = make_float4((float)(ixd + 0.5 - mxd), (float)(iyd + 0.5 - myd),
+                                   (-0.5f * kLog2e) * p.A, -kLog2e * p.B);
+    *sp.at(r, kRecB) = make_float4((-0.5f * kLog2e) * p.C, g.o, col[0], col[1]);
+    *sp.at(r, kRecC) = make_float4(col[2], -log2f(255.f * g.o), (float)ixd, (float)iyd);
     if (empty) {
         rect[r] = make_uint2(0u, 0u);
         count[r] = 0u;
@@ -324,7 +323,7 @@ __device__ __forceinline__ uint32_t project_record(const float *__restrict__ P, 
     const float Kp = k2 * ((1.f + kBoxRel) * (1.f + kBoxRel));
     float ey;
     const float4 ep = ellipse_pack(p.a, p.b, p.c, Kp, ey);
-    ell[r] = ep;
+    *sp.at(r, kRecEll) = ep;
     uint32_t cnt = 0, listed_rows = 0;
     const Ellipse e{ep.x, ep.y, ep.z, ep.w, sqrtf(ep.y / ep.z), (float)(ixd + 0.5 - mxd),
                     (float)(iyd + 0.5 - myd), (int)ixd, (int)iyd};
@@ -359,7 +358,6 @@ __global__ __launch_bounds__(256) void k_project_fwd(const float *__restrict__ P
                                                      SplatPtrs sp, uint32_t *__restrict__ depth_key,
                                                      uint2 *__restrict__ rect,
                                                      uint32_t *__restrict__ count,
-                                                     float4 *__restrict__ ell,
                                                      uint2 *__restrict__ rspan,
                                                      const float *__restrict__ cull_gaze,
                                                      float cull_radius, uint32_t *__restrict__ block_sums,
@@ -367,7 +365,7 @@ __global__ __launch_bounds__(256) void k_project_fwd(const float *__restrict__ P
     __shared__ uint32_t s_w[4], s_a[4];
     const int r = blockIdx.x * 256 + (int)threadIdx.x;
     uint32_t c = r < nrec ? project_record<DEG>(P, n, r, cams, views, tile, sp, depth_key, rect, count,
-                                                ell, rspan, cull_gaze, cull_radius)
+                                                rspan, cull_gaze, cull_radius)
                           : 0u;
     const uint32_t a = (uint32_t)__popcll(__ballot(c != 0u));   // records that list a tile
 #pragma unroll
@@ -564,16 +562,16 @@ __global__ __launch_bounds__(128) void k_project_bwd(const float *__restrict__ P
 
 void launch_project_fwd(hipStream_t s, const float *P, int n, int nviews, int deg,
                         const gsf_camera *cams, const ViewDesc *views, int tile, SplatPtrs sp,
-                        uint32_t *depth_key, uint2 *rect, uint32_t *count, float4 *ell,
-                        uint2 *rspan, const float *cull_gaze, float cull_radius,
-                        uint32_t *block_sums, uint32_t *block_act) {
+                        uint32_t *depth_key, uint2 *rect, uint32_t *count, uint2 *rspan,
+                        const float *cull_gaze, float cull_radius, uint32_t *block_sums,
+                        uint32_t *block_act) {
     const int nrec = n * nviews;
     const dim3 grid((nrec + 255) / 256), block(256);
     switch (deg) {
-    case 0: k_project_fwd<0><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rect, count, ell, rspan, cull_gaze, cull_radius, block_sums, block_act); break;
-    case 1: k_project_fwd<1><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rect, count, ell, rspan, cull_gaze, cull_radius, block_sums, block_act); break;
-    case 2: k_project_fwd<2><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rect, count, ell, rspan, cull_gaze, cull_radius, block_sums, block_act); break;
-    default: k_project_fwd<3><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rect, count, ell, rspan, cull_gaze, cull_radius, block_sums, block_act); break;
+    case 0: k_project_fwd<0><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rect, count, rspan, cull_gaze, cull_radius, block_sums, block_act); break;
+    case 1: k_project_fwd<1><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rect, count, rspan, cull_gaze, cull_radius, block_sums, block_act); break;
+    case 2: k_project_fwd<2><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rect, count, rspan, cull_gaze, cull_radius, block_sums, block_act); break;
+    default: k_project_fwd<3><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rect, count, rspan, cull_gaze, cull_radius, block_sums, block_act); break;
     }
 }
 

@@ -174,7 +174,7 @@ __global__ __launch_bounds__((fwd_threads<T, SPLIT>())) void k_render_fwd(
     float *__restrict__ out_rgba, float *__restrict__ tfinal, uint32_t *__restrict__ ncontrib,
     float4 *__restrict__ ckpt, float4 *__restrict__ fstate, float *__restrict__ tstore,
     const float *__restrict__ bg, const float *__restrict__ cull_gaze, float cull_radius,
-    const float4 *__restrict__ ell, int total_tiles) {
+    int total_tiles) {
     constexpr bool CKPT = MODE == 1;
     constexpr bool QUAD = T == 16;   // a wave composites one 8 x 8 quadrant
     static_assert(!SPLIT || QUAD, "only 16-pixel tiles are split");
@@ -353,11 +353,12 @@ __global__ __launch_bounds__((fwd_threads<T, SPLIT>())) void k_render_fwd(
         // copy record r of entry threadIdx.x into a buffer (this wave's 64 slots)
         auto stage = [&](float4 *buf, uint32_t r) {
             float4 *d = buf + (threadIdx.x & ~63u);
-            __builtin_amdgcn_global_load_lds((const void *)(sp.a + r), lds_ptr(d), 16, 0, 0);
-            __builtin_amdgcn_global_load_lds((const void *)(sp.b + r), lds_ptr(d + SEC), 16, 0, 0);
-            __builtin_amdgcn_global_load_lds((const void *)(sp.c + r), lds_ptr(d + 2 * SEC), 16, 0, 0);
+            const float4 *rr = sp.at(r, 0);   // one 64-byte chunk: a, b, c, ellipse
+            __builtin_amdgcn_global_load_lds((const void *)(rr + kRecA), lds_ptr(d), 16, 0, 0);
+            __builtin_amdgcn_global_load_lds((const void *)(rr + kRecB), lds_ptr(d + SEC), 16, 0, 0);
+            __builtin_amdgcn_global_load_lds((const void *)(rr + kRecC), lds_ptr(d + 2 * SEC), 16, 0, 0);
             if constexpr (QUAD)
-                __builtin_amdgcn_global_load_lds((const void *)(ell + r), lds_ptr(d + 3 * SEC), 16, 0, 0);
+                __builtin_amdgcn_global_load_lds((const void *)(rr + kRecEll), lds_ptr(d + 3 * SEC), 16, 0, 0);
         };
         const uint32_t j = threadIdx.x;
         uint32_t rnext = 0u;
@@ -383,11 +384,11 @@ __global__ __launch_bounds__((fwd_threads<T, SPLIT>())) void k_render_fwd(
         for (uint32_t bs = rg.x; bs < rg.y; bs += B) {
             const int nb = (int)min((uint32_t)B, rg.y - bs);
             for (int j = threadIdx.x; j < nb; j += NT) {
-                const uint32_t r = vals[bs + j];
-                s_buf0[j] = sp.a[r];
-                s_buf0[SEC + j] = sp.b[r];
-                s_buf0[2 * SEC + j] = sp.c[r];
-                if constexpr (QUAD) s_buf0[3 * SEC + j] = ell[r];
+                const float4 *rr = sp.at(vals[bs + j], 0);
+                s_buf0[j] = rr[kRecA];
+                s_buf0[SEC + j] = rr[kRecB];
+                s_buf0[2 * SEC + j] = rr[kRecC];
+                if constexpr (QUAD) s_buf0[3 * SEC + j] = rr[kRecEll];
             }
             __syncthreads();
             if (composite(bs, s_buf0)) break;
@@ -532,7 +533,8 @@ __device__ __forceinline__ void render_bwd_unit(
         __syncthreads();
         for (int j = threadIdx.x; j < nb; j += NT) {
             const uint32_t r = vals[bs + j];
-            const float4 ra = sp.a[r], rb = sp.b[r], rc = sp.c[r], e0 = kp.ell[r];
+            const float4 *rr = sp.at(r, 0);   // one 64-byte chunk: splat and ellipse
+            const float4 ra = rr[kRecA], rb = rr[kRecB], rc = rr[kRecC], e0 = rr[kRecEll];
             s_a[j] = ra;
             s_b[j] = rb;
             s_c[j] = rc;
@@ -806,7 +808,8 @@ __global__ __launch_bounds__(T * T < 256 ? T * T : 256) void k_count_pairs(
             const uint32_t r = vals[e];
             visit++;
             float alpha, ae, ex, dx, dy;
-            const float4 ra = sp.a[r], rb = sp.b[r], c = sp.c[r];
+            const float4 *rr = sp.at(r, 0);
+            const float4 ra = rr[kRecA], rb = rr[kRecB], c = rr[kRecC];
             if (!splat_alpha(ra, rb, c, px, py, alpha, ae, ex, dx, dy)) continue;
             const float Tn = Tr * (1.f - alpha);
             if (Tn < kTStop) break;
@@ -1092,17 +1095,17 @@ void render_fwd_tbs(hipStream_t s, const RenderArgs &a, float *out) {
         k_render_fwd<T, B, 1, SPLIT><<<g, NT, 0, s>>>(a.order, a.ranges, a.vals, a.sp, a.views,
                                                      a.nviews, a.cams, out, a.tfinal, a.ncontrib, a.ckpt,
                                                      a.fstate, nullptr, a.bg, a.cull_gaze, a.cull_radius,
-                                                     a.kp.ell, a.total_tiles);
+                                                     a.total_tiles);
     else if (a.t_mode == 2)
         k_render_fwd<T, B, 2, SPLIT><<<g, NT, 0, s>>>(a.order, a.ranges, a.vals, a.sp, a.views,
                                                      a.nviews, a.cams, out, a.tfinal, a.ncontrib, nullptr,
                                                      nullptr, a.tstore, a.bg, a.cull_gaze, a.cull_radius,
-                                                     a.kp.ell, a.total_tiles);
+                                                     a.total_tiles);
     else
         k_render_fwd<T, B, 0, SPLIT><<<g, NT, 0, s>>>(a.order, a.ranges, a.vals, a.sp, a.views,
                                                      a.nviews, a.cams, out, a.tfinal, a.ncontrib, nullptr,
                                                      nullptr, nullptr, a.bg, a.cull_gaze, a.cull_radius,
-                                                     a.kp.ell, a.total_tiles);
+                                                     a.total_tiles);
 }
 
 // Split 16-pixel tiles into one workgroup per quadrant when the plan has at

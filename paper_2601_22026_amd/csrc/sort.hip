@@ -381,7 +381,7 @@ __device__ __forceinline__ bool block_prefix(const uint32_t *__restrict__ sums,
 // from the projection.
 __global__ __launch_bounds__(kScanBlock) void k_scan_rec(
     const uint32_t *__restrict__ count, const uint2 *__restrict__ rect,
-    const float4 *__restrict__ ell, const uint2 *__restrict__ rspan, SplatPtrs sp,
+    const uint2 *__restrict__ rspan, SplatPtrs sp,
     const uint32_t *__restrict__ depth_key, uint32_t *__restrict__ koff, uint2 *__restrict__ rowtab,
     int nrec, int n, int tile, const ViewDesc *__restrict__ views,
     const uint32_t *__restrict__ block_sums, const uint32_t *__restrict__ block_act, int nblocks,
@@ -415,7 +415,8 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_rec(
     const int x0 = (int)(rc.x & 0xFFFFu), y0 = (int)(rc.x >> 16);
     const int x1 = (int)(rc.y & 0xFFFFu), y1 = (int)(rc.y >> 16);
     if (y1 - y0 + 1 > kPackRows || x1 - x0 + 1 > kPackCols) {   // the row table
-        const float4 ea = ell[r], a = sp.a[r], cc = sp.c[r];
+        const float4 ea = *sp.at((uint32_t)r, kRecEll), a = *sp.at((uint32_t)r, kRecA),
+                     cc = *sp.at((uint32_t)r, kRecC);
         const Ellipse el{ea.x, ea.y, ea.z, ea.w, sqrtf(ea.y / ea.z), a.x, a.y, (int)cc.z, (int)cc.w};
         const ViewDesc vd = views[r / n];
         const int tl = 31 - __clz(tile);
@@ -794,7 +795,7 @@ int seg_count(int64_t nrec) {
     return (int)((nb + kSegBlocks - 1) / kSegBlocks) + 1;
 }
 
-void launch_scan_records(hipStream_t s, const uint32_t *count, const uint2 *rect, const float4 *ell,
+void launch_scan_records(hipStream_t s, const uint32_t *count, const uint2 *rect,
                          const uint2 *rspan, SplatPtrs sp, const uint32_t *depth_key, uint32_t *koff,
                          uint2 *rowtab, int nrec, int n, int tile, const ViewDesc *views,
                          uint32_t *block_sums, uint32_t *block_act, unsigned long long *seg_tot,
@@ -805,7 +806,7 @@ void launch_scan_records(hipStream_t s, const uint32_t *count, const uint2 *rect
     if (nb > kOwnPrefixBlocks)
         k_seg_scan<<<(nb + kSegBlocks - 1) / kSegBlocks, kSegBlocks, 0, s>>>(block_sums, block_act, nb,
                                                                             seg_tot, seg_act);
-    k_scan_rec<<<nb, kScanBlock, 0, s>>>(count, rect, ell, rspan, sp, depth_key, koff, rowtab, nrec, n,
+    k_scan_rec<<<nb, kScanBlock, 0, s>>>(count, rect, rspan, sp, depth_key, koff, rowtab, nrec, n,
                                          tile, views, block_sums, block_act, nb, seg_tot, seg_act,
                                          m_dev, m_total, a_dev, flags, capacity, dkey, dval, arec,
                                          ranges, total_tiles);
