@@ -168,16 +168,18 @@ __device__ __forceinline__ uint32_t quadrant_mask(const Ellipse &e, int x0, int 
 // Where the adjoint puts each key's screen-space gradient: the duplicate pass
 // writes a record's count[r] keys at consecutive positions (its first at
 // koff[r]), box rows top to bottom and each row's listed tiles left to right;
-// the adjoint writes key (r, tile) at that position of pa / pb / pc (fields
-// 0-3, 4-7, 8, plain stores), and one pass per record sums its positions into
-// g2d.  After a key overflow (m_total > capacity) nothing was listed and g2d
-// is zero.
+// the adjoint writes key (r, tile) at that position of pg, one 64-byte chunk
+// per key (fields 0-3, 4-7, then 8 and seven zeros, plain stores of the whole
+// chunk: a key's slots are written by different workgroups at different times,
+// and a partial chunk would cost the memory a read-modify-write), and one pass
+// per record sums its positions into g2d.  After a key overflow
+// (m_total > capacity) nothing was listed and g2d is zero.
+constexpr int kKeyGradF4 = 4;
 struct KeyPlace {
     const uint32_t *koff = nullptr, *count = nullptr;
     const uint2 *rect = nullptr, *rspan = nullptr;
     const uint2 *rowtab = nullptr;              // row tables of the boxes not packed
-    float4 *pa = nullptr, *pb = nullptr;
-    float *pc = nullptr;
+    float4 *pg = nullptr;                       // [capacity][kKeyGradF4]
     const unsigned long long *m_total = nullptr;
     int64_t capacity = 0;
 };
@@ -283,17 +285,19 @@ __device__ __forceinline__ void wave_key_sum(const KeyPlace &kp, uint32_t r, boo
     float4 na = make_float4(0.f, 0.f, 0.f, 0.f), nb = na;
     float nc = 0.f;
     if ((uint32_t)lane < K) {
-        na = kp.pa[start + lane];
-        nb = kp.pb[start + lane];
-        nc = kp.pc[start + lane];
+        const float4 *g = kp.pg + (size_t)(start + lane) * kKeyGradF4;
+        na = g[0];
+        nb = g[1];
+        nc = g[2].x;
     }
     for (uint32_t c0 = 0; c0 < K; c0 += 64u) {   // wave-uniform
         float v[9] = {na.x, na.y, na.z, na.w, nb.x, nb.y, nb.z, nb.w, nc};
         const uint32_t pn = c0 + 64u + (uint32_t)lane;
         if (pn < K) {
-            na = kp.pa[start + pn];
-            nb = kp.pb[start + pn];
-            nc = kp.pc[start + pn];
+            const float4 *g = kp.pg + (size_t)(start + pn) * kKeyGradF4;
+            na = g[0];
+            nb = g[1];
+            nc = g[2].x;
         } else {
             na = nb = make_float4(0.f, 0.f, 0.f, 0.f);
             nc = 0.f;

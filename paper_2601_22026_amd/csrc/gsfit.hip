@@ -67,10 +67,9 @@ struct Buffers {
     uint32_t *keys = nullptr, *vals = nullptr;   // sorted pair (one of the above)
     uint32_t *hist = nullptr, *digit_tot = nullptr;   // radix-sort histograms
     uint2 *rowtab = nullptr;                     // per key position: row tables of boxes not packed
-    // per key, at its position in the duplicate pass's order: the adjoint's
-    // screen-space gradient (fields 0-3, 4-7, 8)
-    float4 *pa = nullptr, *pb = nullptr;
-    float *pc = nullptr;
+    // per key, at its position in the record-order scan: the adjoint's
+    // screen-space gradient, one 64-byte chunk (fields 0-3, 4-7, 8)
+    float4 *pg = nullptr;
     // per pixel
     float *tfinal = nullptr;
     uint32_t *ncontrib = nullptr;
@@ -190,9 +189,7 @@ size_t carve(gsf_plan *p, char *base, Buffers *out) {
     b.hist = (uint32_t *)take((size_t)kRadixBins * p->radix_grid * 4);
     b.digit_tot = (uint32_t *)take(kRadixBins * 4);
     b.rowtab = (uint2 *)take((size_t)p->cap * sizeof(uint2));
-    b.pa = (float4 *)take((size_t)p->cap * sizeof(float4));
-    b.pb = (float4 *)take((size_t)p->cap * sizeof(float4));
-    b.pc = (float *)take((size_t)p->cap * 4);
+    b.pg = (float4 *)take((size_t)p->cap * kKeyGradF4 * sizeof(float4));
     b.tfinal = (float *)take((size_t)p->total_pix * 4);
     b.ncontrib = (uint32_t *)take((size_t)p->total_pix * 4);
     if (p->t_mode == 1) {
@@ -251,9 +248,7 @@ RenderArgs render_args(gsf_plan *p, const gsf_camera *cams, int64_t n) {
     a.kp.rect = p->b.rect;
     a.kp.rspan = p->b.rspan;
     a.kp.rowtab = p->b.rowtab;
-    a.kp.pa = p->b.pa;
-    a.kp.pb = p->b.pb;
-    a.kp.pc = p->b.pc;
+    a.kp.pg = p->b.pg;
     a.kp.m_total = p->b.m_total;
     a.kp.capacity = p->cap;
     return a;

@@ -673,10 +673,12 @@ __device__ __forceinline__ void render_bwd_unit(
                     for (int f = 0; f < 5; f++) S[f] *= o;   // te sums -> dL/dpower sums
                     // dpower/dmean = (A dx + B dy, B dx + C dy) = -ln2 (2 A2 dx + B2 dy, B2 dx + 2 C2 dy);
                     // dpower/d(A, B, C) = (-dx^2 / 2, -dx dy, -dy^2 / 2)
-                    kp.pa[q] = make_float4(-kLn2 * (2.f * A2 * S[0] + B2 * S[1]),
+                    float4 *g = kp.pg + (size_t)q * kKeyGradF4;
+                    g[0] = make_float4(-kLn2 * (2.f * A2 * S[0] + B2 * S[1]),
                                            -kLn2 * (B2 * S[0] + 2.f * C2 * S[1]), -0.5f * S[2], -S[3]);
-                    kp.pb[q] = make_float4(-0.5f * S[4], S[5], S[6], S[7]);
-                    kp.pc[q] = S[8];
+                    g[1] = make_float4(-0.5f * S[4], S[5], S[6], S[7]);
+                    g[2] = make_float4(S[8], 0.f, 0.f, 0.f);
+                    g[3] = make_float4(0.f, 0.f, 0.f, 0.f);
                 }
                 if (NW > 1) __syncthreads();   // the slots are free again
                 hit = 0ull;
@@ -687,9 +689,9 @@ __device__ __forceinline__ void render_bwd_unit(
     // keys behind every pixel's last included splat pass no gradient
     for (uint32_t e = max(top, us) + threadIdx.x; e < ue; e += NT) {
         const uint32_t q = key_slot(kp, vals[e], ty, tx);
-        kp.pa[q] = make_float4(0.f, 0.f, 0.f, 0.f);
-        kp.pb[q] = make_float4(0.f, 0.f, 0.f, 0.f);
-        kp.pc[q] = 0.f;
+        float4 *g = kp.pg + (size_t)q * kKeyGradF4;
+#pragma unroll
+        for (int f = 0; f < kKeyGradF4; f++) g[f] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
 }
 
