@@ -245,6 +245,7 @@ __device__ __forceinline__ uint32_t project_record(const float *__restrict__ P, 
     if (!ok) {
         depth_key[r] = 0xFFFFFFFFu;
         rect[r] = make_uint2(0u, 0u);
+        rspan[r] = make_uint2(0u, 0u);   // every record: whole 64-byte chunks are written
         count[r] = 0u;
         return 0u;
     }
@@ -286,6 +287,7 @@ __device__ __forceinline__ uint32_t project_record(const float *__restrict__ P, 
     depth_key[r] = __float_as_uint(p.t[2]);
     if (away) {   // never read: no colour, no splat record
         rect[r] = make_uint2(0u, 0u);
+        rspan[r] = make_uint2(0u, 0u);   // every record: whole 64-byte chunks are written
         count[r] = 0u;
         return 0u;
     }
@@ -309,6 +311,7 @@ __device__ __forceinline__ uint32_t project_record(const float *__restrict__ P, 
     *sp.at(r, kRecC) = make_float4(col[2], -log2f(255.f * g.o), (float)ixd, (float)iyd);
     if (empty) {
         rect[r] = make_uint2(0u, 0u);
+        rspan[r] = make_uint2(0u, 0u);   // every record: whole 64-byte chunks are written
         count[r] = 0u;
         return 0u;
     }

@@ -505,13 +505,6 @@ __device__ __forceinline__ void render_bwd_unit(
         gR[k] -= gA[k] * Tf[k];
         my_max = max(my_max, nc[k]);
     }
-    __syncthreads();
-    if (threadIdx.x == 0) *s_nmax = 0u;
-    __syncthreads();
-    atomicMax(s_nmax, my_max);
-    __syncthreads();
-    const uint32_t nmax = *s_nmax;
-    const uint32_t top = min(ue, rg.x + nmax);
     // 16-pixel tiles: per quadrant (one per pixel block of the wave) the largest
     // contributor count; a splat at or past it reaches no pixel of the quadrant
     // (each would add exact zeros and keep its state), so the quadrant is skipped
@@ -526,6 +519,25 @@ __device__ __forceinline__ void render_bwd_unit(
         }
         qmax[k] = x;
     }
+    // the tile's largest contributor count: a wave reduction, then (several
+    // waves) their maximum through LDS (an LDS atomic with per-lane values
+    // would be serialised over the lanes)
+    uint32_t nmax;
+    if (QUAD) {
+        nmax = max(max(qmax[0], qmax[1]), max(qmax[2], qmax[3]));
+    } else {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) my_max = max(my_max, (uint32_t)__shfl_xor((int)my_max, o, 64));
+        nmax = __builtin_amdgcn_readfirstlane(my_max);
+        if (NW > 1) {
+            __syncthreads();
+            if (lane == 0) s_nmax[threadIdx.x >> 6] = nmax;
+            __syncthreads();
+#pragma unroll
+            for (int w = 0; w < NW; w++) nmax = max(nmax, s_nmax[w]);
+        }
+    }
+    const uint32_t top = min(ue, rg.x + nmax);
 
     for (uint32_t be = top; be > us;) {
         const uint32_t bs = be - us > (uint32_t)B ? be - (uint32_t)B : us;
@@ -714,12 +726,15 @@ __global__ __launch_bounds__(bwd_threads<T>()) void k_render_bwd(
     __shared__ float s_g[NT / 64 * kGradSlot<MODE>];
     __shared__ uint64_t s_hit[NT / 64];
     __shared__ float s_h[B];
-    __shared__ uint32_t s_nmax;
+    __shared__ uint32_t s_nmax[NT / 64];
     const int gt = (int)order[blockIdx.x];
     const uint2 rg = ranges[gt];
+    // a tile without keys passes no gradient (and a fovea-culled step's tiles
+    // away from the fovea hold no pixel state to read)
+    if (rg.x == rg.y) return;
     render_bwd_unit<T, B, MODE>(gt, rg.x, rg.y, true, rg, vals, sp, views, nviews, cams, tfinal,
                                 ncontrib, nullptr, nullptr, tstore, bg, dl, kp, s_a, s_b, s_c, s_q,
-                                s_m, s_g, s_hit, s_h, &s_nmax);
+                                s_m, s_g, s_hit, s_h, s_nmax);
 }
 
 // Checkpoint mode: one workgroup per (tile, batch) unit id.  Unit u of tile t
@@ -744,7 +759,7 @@ __global__ __launch_bounds__(bwd_threads<T>()) void k_render_bwd_ckpt(
     __shared__ float s_g[NT / 64 * kGradSlot<1>];
     __shared__ uint64_t s_hit[NT / 64];
     __shared__ float s_h[B];
-    __shared__ uint32_t s_nmax;
+    __shared__ uint32_t s_nmax[NT / 64];
     const uint32_t m = m_dev ? *m_dev : m_host;
     const uint32_t n_ids = m / B + (uint32_t)total_tiles;
     for (uint32_t id = blockIdx.x; id < n_ids; id += gridDim.x) {   // one trip when the grid covers n_ids
@@ -762,7 +777,7 @@ __global__ __launch_bounds__(bwd_threads<T>()) void k_render_bwd_ckpt(
         const uint32_t ue = min(rg.y, us + B);
         render_bwd_unit<T, B, 1>(lo, us, ue, u + 1 == units, rg, vals, sp, views, nviews, cams,
                                  tfinal, ncontrib, fstate, ckpt, nullptr, bg, dl, kp, s_a, s_b,
-                                 s_c, s_q, s_m, s_g, s_hit, s_h, &s_nmax);
+                                 s_c, s_q, s_m, s_g, s_hit, s_h, s_nmax);
     }
 }
 

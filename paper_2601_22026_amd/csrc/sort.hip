@@ -403,9 +403,9 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_rec(
     uint32_t total, atot;
     const uint32_t off = block_excl_scan_256(c, s_wave, total);
     const uint32_t apos = block_excl_scan_256(c != 0u ? 1u : 0u, s_wave, atot);
-    if (c == 0u) return;
     const uint32_t first = gbase + off, e = abase + apos;
-    koff[r] = first;
+    if (r < nrec) koff[r] = first;   // every record: whole 64-byte chunks are written
+    if (c == 0u) return;
     const uint2 rc = rect[r];
     const uint2 pk = rspan[r];
     dkey[e] = depth_key[r];
@@ -580,6 +580,13 @@ __device__ __forceinline__ void fill_runs(uint2 *ranges, uint32_t lo, uint32_t h
     }
 }
 
+// Each thread takes kBoundKeys consecutive sorted keys (16-byte loads) and the
+// keys on either side: a key opens its tile's range where it differs from the
+// key before and closes it where it differs from the key after.  Only those
+// keys (one in several hundred on large plans) map the key to its tile, write
+// the range and fill the empty tiles since the previous tile with (k, k).
+constexpr int kBoundKeys = 8;
+
 __global__ __launch_bounds__(256) void k_tile_bounds(const uint32_t *__restrict__ keys,
                                                      const uint32_t *__restrict__ m_dev,
                                                      uint32_t m_host, int total_tiles,
@@ -593,30 +600,49 @@ __global__ __launch_bounds__(256) void k_tile_bounds(const uint32_t *__restrict_
         __syncthreads();
     }
     const uint32_t m = m_dev ? *m_dev : m_host;
-    const uint32_t stride = gridDim.x * blockDim.x;
+    const uint32_t stride = gridDim.x * blockDim.x * kBoundKeys;
     // wave-uniform trip count: every lane takes part in the run fills
-    for (uint32_t base = blockIdx.x * blockDim.x; base < m; base += stride) {
-        const uint32_t k = base + threadIdx.x;
-        uint32_t lo = 0, hi = 0, lo2 = 0, hi2 = 0;
-        if (k < m) {
-            const uint32_t c = keys[k];
-            const uint32_t t = global_tile(c, tm, s_views, s_f0);
-            if (k == 0 || keys[k - 1] != c) {
-                // empty tiles before t
-                lo = k == 0 ? t : global_tile(keys[k - 1], tm, s_views, s_f0) + 1u;
-                hi = t;
-                ranges[t].x = k;
-            }
-            if (k + 1 == m) {
-                ranges[t].y = m;
-                lo2 = t + 1u;                         // empty tiles after the last key
-                hi2 = (uint32_t)total_tiles;
-            } else if (keys[k + 1] != c) {
-                ranges[t].y = k + 1;
-            }
+    for (uint32_t b0 = blockIdx.x * blockDim.x * kBoundKeys; b0 < m; b0 += stride) {
+        const uint32_t k0 = b0 + threadIdx.x * kBoundKeys;
+        uint32_t c[kBoundKeys + 2];   // c[0]: the key before k0; c[j + 1]: key k0 + j
+        if (k0 + kBoundKeys <= m) {
+            const uint4 u0 = *reinterpret_cast<const uint4 *>(keys + k0);
+            const uint4 u1 = *reinterpret_cast<const uint4 *>(keys + k0 + 4);
+            c[1] = u0.x; c[2] = u0.y; c[3] = u0.z; c[4] = u0.w;
+            c[5] = u1.x; c[6] = u1.y; c[7] = u1.z; c[8] = u1.w;
+        } else {
+#pragma unroll
+            for (int j = 0; j < kBoundKeys; j++) c[j + 1] = k0 + j < m ? keys[k0 + j] : 0u;
         }
-        fill_runs(ranges, lo, hi, k);
-        fill_runs(ranges, lo2, hi2, m);
+        c[0] = k0 > 0 && k0 <= m ? keys[k0 - 1] : 0u;
+        c[kBoundKeys + 1] = k0 + kBoundKeys < m ? keys[k0 + kBoundKeys] : 0u;
+#pragma unroll
+        for (int j = 0; j < kBoundKeys; j++) {
+            const uint32_t k = k0 + (uint32_t)j;
+            uint32_t lo = 0, hi = 0, lo2 = 0, hi2 = 0;
+            if (k < m) {
+                const bool first = k == 0 || c[j] != c[j + 1];
+                const bool last = k + 1 == m || c[j + 2] != c[j + 1];
+                if (first || last) {
+                    const uint32_t t = global_tile(c[j + 1], tm, s_views, s_f0);
+                    if (first) {
+                        // empty tiles before t
+                        lo = k == 0 ? t : global_tile(c[j], tm, s_views, s_f0) + 1u;
+                        hi = t;
+                        ranges[t].x = k;
+                    }
+                    if (k + 1 == m) {
+                        ranges[t].y = m;
+                        lo2 = t + 1u;                         // empty tiles after the last key
+                        hi2 = (uint32_t)total_tiles;
+                    } else if (last) {
+                        ranges[t].y = k + 1;
+                    }
+                }
+            }
+            fill_runs(ranges, lo, hi, k);
+            fill_runs(ranges, lo2, hi2, m);
+        }
     }
 }
 
@@ -697,7 +723,7 @@ __global__ __launch_bounds__(1024) void k_tile_order(const uint2 *__restrict__ r
 // k_order_count writes each workgroup's class counts; k_order_place turns them
 // into the workgroup's first slot per class (classes descending, workgroups in
 // order) and places its tiles.
-constexpr int kOrderTiles = 4096;
+constexpr int kOrderTiles = 1024;
 
 __device__ __forceinline__ void order_walk(const uint2 *__restrict__ ranges, int total_tiles,
                                            uint32_t *s_cnt, uint32_t *__restrict__ order) {
@@ -732,17 +758,36 @@ __global__ __launch_bounds__(256) void k_order_count(const uint2 *__restrict__ r
 __global__ __launch_bounds__(256) void k_order_place(const uint2 *__restrict__ ranges, int total_tiles,
                                                      const uint32_t *__restrict__ counts, int groups,
                                                      uint32_t *__restrict__ order) {
-    __shared__ uint32_t s_tot[33], s_cnt[33];
+    constexpr int kStrips = 7;   // 33 classes x 7 strips of the workgroups <= 256 threads
+    __shared__ uint32_t s_tot[33], s_cnt[33], s_part[2][kStrips][33];
     const int c = threadIdx.x;
+    {   // the class totals over all workgroups and over those before this
+        // one: thread (class, strip) sums every kStrips-th row, then the
+        // strips are added (no atomics, which the compiler would serialise
+        // over the lanes)
+        const int cls = (int)threadIdx.x % 33, strip = (int)threadIdx.x / 33;
+        if (strip < kStrips) {
+            uint32_t tot = 0u, bef = 0u;
+#pragma unroll 4
+            for (int w = strip; w < groups; w += kStrips) {
+                const uint32_t n = counts[(size_t)w * 33 + cls];
+                tot += n;
+                bef += w < (int)blockIdx.x ? n : 0u;
+            }
+            s_part[0][strip][cls] = tot;
+            s_part[1][strip][cls] = bef;
+        }
+    }
+    __syncthreads();
     if (c < 33) {
-        uint32_t tot = 0, before = 0;
-        for (int w = 0; w < groups; w++) {
-            const uint32_t n = counts[(size_t)w * 33 + c];
-            tot += n;
-            if (w < (int)blockIdx.x) before += n;
+        uint32_t tot = 0u, bef = 0u;
+#pragma unroll
+        for (int k = 0; k < kStrips; k++) {
+            tot += s_part[0][k][c];
+            bef += s_part[1][k][c];
         }
         s_tot[c] = tot;
-        s_cnt[c] = before;
+        s_cnt[c] = bef;
     }
     __syncthreads();
     if (c < 33) {
@@ -828,8 +873,8 @@ void launch_emit(hipStream_t s, const uint32_t *dval, const uint32_t *a_dev, con
 void launch_tile_bounds(hipStream_t s, const uint32_t *keys, const uint32_t *m_dev, uint32_t m_host,
                         int64_t capacity, int total_tiles, const ViewDesc *views, int nviews,
                         const TileMap &tm, uint2 *ranges) {
-    int64_t g = (capacity + 255) / 256;
-    if (g > 2048) g = 2048;
+    int64_t g = (capacity + 256 * kBoundKeys - 1) / (256 * kBoundKeys);
+    if (g > 4096) g = 4096;
     if (g < 1) g = 1;
     k_tile_bounds<<<(int)g, 256, 0, s>>>(keys, m_dev, m_host, total_tiles, views, nviews, tm, ranges);
 }
