@@ -43,6 +43,29 @@ static_assert(kScanTile == 256, "the projection writes the count totals of 256-r
 constexpr int kOwnPrefixBlocks = 1024;       // up to this many scan blocks, each sums its own prefix (no k_seg_scan)
 constexpr int kSegBlocks = 1024;             // block totals per segment of k_seg_scan
 
+// A depth-sort value holds the entry index in its low `ebits` bits and the
+// record's tile count, saturated, above them, so that the emission's block
+// totals read the sorted values instead of gathering an entry per record.
+// ebits = 32: no room for a count (plans of more than 2^26 records).
+int entry_bits(int nrec) {
+    int b = 1;
+    while ((int64_t(1) << b) < nrec) b++;
+    return b > 26 ? 32 : b;
+}
+struct ValPack {
+    uint32_t emask, cmax;
+    int ebits;
+    __host__ __device__ explicit ValPack(int eb)
+        : emask(eb >= 32 ? 0xFFFFFFFFu : (1u << eb) - 1u), cmax(eb >= 32 ? 0u : (1u << (32 - eb)) - 1u),
+          ebits(eb) {}
+    __device__ uint32_t pack(uint32_t e, uint32_t c) const {
+        return ebits >= 32 ? e : e | (min(c, cmax) << ebits);
+    }
+    __device__ uint32_t entry(uint32_t v) const { return v & emask; }
+    // the count, or cmax (saturated: read the entry instead)
+    __device__ uint32_t count(uint32_t v) const { return ebits >= 32 ? cmax : v >> ebits; }
+};
+
 __device__ __forceinline__ uint32_t chunk_size(uint32_t n, int G) {
     const uint32_t per = (n + (uint32_t)G - 1u) / (uint32_t)G;
     return (per + 255u) & ~255u;
@@ -389,7 +412,7 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_rec(
     uint32_t *__restrict__ m_dev, unsigned long long *__restrict__ m_total,
     uint32_t *__restrict__ a_dev, uint32_t *__restrict__ flags, int64_t capacity,
     uint32_t *__restrict__ dkey, uint32_t *__restrict__ dval, uint4 *__restrict__ arec,
-    uint2 *__restrict__ ranges, int total_tiles) {
+    uint2 *__restrict__ ranges, int total_tiles, ValPack vp) {
     __shared__ uint32_t s_wave[4];
     __shared__ unsigned long long s_tot[16];
     for (int t = blockIdx.x * kScanBlock + threadIdx.x; t < total_tiles; t += gridDim.x * kScanBlock)
@@ -409,7 +432,7 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_rec(
     const uint2 rc = rect[r];
     const uint2 pk = rspan[r];
     dkey[e] = depth_key[r];
-    dval[e] = e;
+    dval[e] = vp.pack(e, c);
     arec[2 * e] = make_uint4((uint32_t)r, first, c, pk.x);
     arec[2 * e + 1] = make_uint4(rc.x, rc.y, pk.y, 0u);
     const int x0 = (int)(rc.x & 0xFFFFu), y0 = (int)(rc.x >> 16);
@@ -459,10 +482,15 @@ __device__ __forceinline__ uint32_t global_tile(uint32_t c, const TileMap &tm,
 __global__ __launch_bounds__(kScanBlock) void k_emit_totals(const uint32_t *__restrict__ dval,
                                                             const uint32_t *__restrict__ a_dev,
                                                             const uint4 *__restrict__ arec,
-                                                            uint32_t *__restrict__ sums) {
+                                                            uint32_t *__restrict__ sums, ValPack vp) {
     __shared__ uint32_t s_w[4];
     const uint32_t pos = blockIdx.x * kScanTile + threadIdx.x;
-    uint32_t c = pos < *a_dev ? arec[2 * dval[pos]].z : 0u;
+    uint32_t c = 0u;
+    if (pos < *a_dev) {
+        const uint32_t v = dval[pos];
+        c = vp.count(v);
+        if (c == vp.cmax) c = arec[2 * vp.entry(v)].z;   // saturated: the entry's count
+    }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
     if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = c;
@@ -485,7 +513,7 @@ __global__ __launch_bounds__(kScanBlock) void k_emit(
     const ViewDesc *__restrict__ views, int nviews, const uint32_t *__restrict__ block_sums,
     int nblocks, const unsigned long long *__restrict__ seg_tot,
     const unsigned long long *__restrict__ m_total, int64_t capacity, TileMap tm,
-    uint32_t *__restrict__ keys, uint32_t *__restrict__ vals) {
+    uint32_t *__restrict__ keys, uint32_t *__restrict__ vals, ValPack vp) {
     __shared__ uint32_t s_wave[4];
     __shared__ unsigned long long s_tot[16];
     __shared__ uint32_t s_off[kScanTile];   // block-local exclusive key offset per record
@@ -505,9 +533,10 @@ __global__ __launch_bounds__(kScanBlock) void k_emit(
     const uint32_t pos = blockIdx.x * kScanTile + threadIdx.x;
     uint4 r0 = make_uint4(0u, 0u, 0u, 0u), r1 = r0;
     if (pos < A) {
-        const uint32_t e = dval[pos];
+        const uint32_t e = vp.entry(dval[pos]);
         r0 = arec[2 * e];
         r1 = arec[2 * e + 1];
+        r1.w = r0.x / (uint32_t)n;   // the record's view, once per record
     }
     uint32_t total;
     const uint32_t off = block_excl_scan_256(r0.z, s_wave, total);
@@ -516,18 +545,18 @@ __global__ __launch_bounds__(kScanBlock) void k_emit(
     s_r1[threadIdx.x] = r1;
     __syncthreads();
     for (uint32_t q = threadIdx.x; q < total; q += kScanBlock) {
-        // the last record whose offset is <= q (every active record has keys)
-        int lo = 0, hi = kScanTile - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (s_off[mid] <= q) lo = mid; else hi = mid - 1;
-        }
+        // the last record whose offset is <= q (every active record has keys;
+        // slots past the active records hold the total): a fixed 8-step search
+        int lo = 0;
+#pragma unroll
+        for (int step = kScanTile / 2; step > 0; step >>= 1)
+            lo = s_off[lo + step] <= q ? lo + step : lo;
         uint32_t li = q - s_off[lo];              // index of the key within its record
         const uint4 a = s_r0[lo], b = s_r1[lo];
         const uint32_t rr = a.x;
         const int x0 = (int)(b.x & 0xFFFFu), y0 = (int)(b.x >> 16);
         const int x1 = (int)(b.y & 0xFFFFu), y1 = (int)(b.y >> 16);
-        const uint32_t v = rr / (uint32_t)n;
+        const uint32_t v = b.w;
         uint32_t ty = 0u, tx = 0u;   // the key's tile
         if (y1 - y0 + 1 <= kPackRows && x1 - x0 + 1 <= kPackCols) {   // packed spans
             for (int k = 0; k < kPackRows; k++) {
@@ -854,7 +883,7 @@ void launch_scan_records(hipStream_t s, const uint32_t *count, const uint2 *rect
     k_scan_rec<<<nb, kScanBlock, 0, s>>>(count, rect, rspan, sp, depth_key, koff, rowtab, nrec, n,
                                          tile, views, block_sums, block_act, nb, seg_tot, seg_act,
                                          m_dev, m_total, a_dev, flags, capacity, dkey, dval, arec,
-                                         ranges, total_tiles);
+                                         ranges, total_tiles, ValPack(entry_bits(nrec)));
 }
 
 void launch_emit(hipStream_t s, const uint32_t *dval, const uint32_t *a_dev, const uint4 *arec,
@@ -862,12 +891,13 @@ void launch_emit(hipStream_t s, const uint32_t *dval, const uint32_t *a_dev, con
                  uint32_t *block_sums, unsigned long long *seg_tot, const unsigned long long *m_total,
                  int64_t capacity, const TileMap &tm, uint32_t *keys, uint32_t *vals) {
     const int nb = (nrec + kScanTile - 1) / kScanTile;
-    k_emit_totals<<<nb, kScanBlock, 0, s>>>(dval, a_dev, arec, block_sums);
+    const ValPack vp(entry_bits(nrec));   // as launch_scan_records packed them
+    k_emit_totals<<<nb, kScanBlock, 0, s>>>(dval, a_dev, arec, block_sums, vp);
     if (nb > kOwnPrefixBlocks)
         k_seg_scan<<<(nb + kSegBlocks - 1) / kSegBlocks, kSegBlocks, 0, s>>>(block_sums, nullptr, nb,
                                                                             seg_tot, nullptr);
     k_emit<<<nb, kScanBlock, 0, s>>>(dval, a_dev, arec, rowtab, n, views, nviews, block_sums, nb,
-                                     seg_tot, m_total, capacity, tm, keys, vals);
+                                     seg_tot, m_total, capacity, tm, keys, vals, vp);
 }
 
 void launch_tile_bounds(hipStream_t s, const uint32_t *keys, const uint32_t *m_dev, uint32_t m_host,
