@@ -539,7 +539,9 @@ enum {
     GSF_DBG_PROJ = 9,      /* float [11] per record: mean x, mean y, conic A, B, C, opacity,
                               red, green, blue, camera depth, valid (1 or 0) */
     GSF_DBG_ORDER = 10,    /* uint32 per global tile: compositing order of the tiles (a
-                              permutation; tiles with more keys first) */
+                              permutation; tiles with more keys first); after a
+                              fovea-culled forward, the global ids of the tiles it
+                              composited, in that order */
     GSF_DBG_BG = 11,       /* float [n_views][3]: backgrounds drawn by the last random_bg step */
     GSF_DBG_VIS = 12       /* uint8 [n]: Gaussian visibility of the last masked_adam step */
 };

@@ -333,7 +333,7 @@ struct FoveaTiles {
     int tx0, tx1, ty0, ty1;
 };
 
-__device__ __forceinline__ FoveaTiles fovea_tiles(const float *__restrict__ gaze, int v,
+__host__ __device__ __forceinline__ FoveaTiles fovea_tiles(const float *__restrict__ gaze, int v,
                                                   float radius_frac, int width, int height, int tile) {
     const float r = radius_frac * (float)width;
     const float gx = gaze[2 * v], gy = gaze[2 * v + 1];
@@ -467,6 +467,10 @@ struct RenderArgs {
     const uint32_t *m_dev = nullptr;      // key count on the device, or
     uint32_t m_host = 0;                  //   on the host when m_dev is null
     KeyPlace kp{};                        // where the adjoint writes each key's gradient
+    // the launch tiles (total_tiles of them, which ranges and order index):
+    // global tile ids, or (tm.gaze, a fovea-culled forward) the compact
+    // fovea-box ids of the sort keys
+    TileMap tm{};
 };
 
 // Front-to-back compositing of all tiles of all views.
@@ -481,7 +485,7 @@ void launch_grad_sum(hipStream_t s, const KeyPlace &kp, int nrec, float *g2d);
 // Pair accounting of the last forward: counters[3] (visited, included, adjoint visited).
 void launch_count_pairs(hipStream_t s, int tile, int total_tiles, const uint2 *ranges,
                         const uint32_t *vals, SplatPtrs sp, const ViewDesc *views, int nviews,
-                        unsigned long long *counters);
+                        const TileMap &tm, unsigned long long *counters);
 
 // Masked L1 loss.  partial: scratch of loss_partials(total_pix) floats.
 int loss_partials(int64_t total_pix);

@@ -107,6 +107,10 @@ struct gsf_plan {
     bool have_forward = false;
     bool fwd_culled = false;                  // the last forward composited only fovea tiles
     int64_t fwd_n = 0;
+    // the last forward's launch tiles, which ranges and order index: the plan's
+    // global tiles, or (fwd_tm.gaze) the compact fovea-box tiles of its keys
+    TileMap fwd_tm{};
+    int64_t fwd_tiles = 0;
     unsigned long long *pinned = nullptr;     // host-pinned readback of the key count
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -224,7 +228,8 @@ RenderArgs render_args(gsf_plan *p, const gsf_camera *cams, int64_t n) {
     RenderArgs a;
     a.tile = p->tile;
     a.batch = p->batch;
-    a.total_tiles = (int)p->total_tiles;
+    a.total_tiles = (int)(p->fwd_tiles > 0 ? p->fwd_tiles : p->total_tiles);
+    a.tm = p->fwd_tm;
     a.nviews = p->V;
     a.nrec = (int)(n * p->V);
     a.t_mode = p->t_mode;
@@ -363,6 +368,11 @@ gsf_status enqueue_forward(gsf_plan *p, const float *params, int64_t n, const gs
             while ((int64_t(1) << sort_bits) < space) sort_bits++;
         }
     }
+    // ranges, the compositing order and the compositing launches then cover
+    // only those tiles
+    const int64_t ltiles = tm.gaze ? (int64_t)p->V * tm.box * tm.box : p->total_tiles;
+    p->fwd_tm = tm;
+    p->fwd_tiles = ltiles;
     {   // depth order of the records with keys (stable: equal depths keep the
         // record order), then their keys emitted in that order
         StageTimer t(p, GSF_STAGE_DEPTH_SORT);
@@ -385,9 +395,9 @@ gsf_status enqueue_forward(gsf_plan *p, const float *params, int64_t n, const gs
     GSF_LAUNCHED(ctx);
     {
         StageTimer t(p, GSF_STAGE_RANGES);
-        launch_tile_bounds(s, b.keys, m_dev, p->m_host, p->cap, (int)p->total_tiles, b.views, p->V,
-                           tm, b.ranges);
-        launch_tile_order(s, b.ranges, (int)p->total_tiles, b.order, b.order_counts);
+        launch_tile_bounds(s, b.keys, m_dev, p->m_host, p->cap, (int)ltiles, b.views, p->V,
+                           TileMap{}, b.ranges);
+        launch_tile_order(s, b.ranges, (int)ltiles, b.order, b.order_counts);
     }
     GSF_LAUNCHED(ctx);
     {
@@ -1203,8 +1213,8 @@ gsf_status gsf_count_pairs(gsf_plan *p, int64_t *out) {
     if (st != GSF_OK) return st;
     if (!out) return fail(p->ctx, GSF_E_INVALID, "gsf_count_pairs: null output");
     if (!p->have_forward) return fail(p->ctx, GSF_E_STATE, "gsf_count_pairs before gsf_forward");
-    launch_count_pairs(p->ctx->stream, p->tile, (int)p->total_tiles, p->b.ranges, p->b.vals,
-                       splats(p), p->b.views, p->V, p->b.counters);
+    launch_count_pairs(p->ctx->stream, p->tile, (int)p->fwd_tiles, p->b.ranges, p->b.vals,
+                       splats(p), p->b.views, p->V, p->fwd_tm, p->b.counters);
     GSF_LAUNCHED(p->ctx);
     unsigned long long c[3] = {0, 0, 0};
     GSF_HIP(p->ctx, hipStreamSynchronize(p->ctx->stream));
@@ -1212,6 +1222,59 @@ gsf_status gsf_count_pairs(gsf_plan *p, int64_t *out) {
     for (int k = 0; k < 3; k++) out[k] = (int64_t)c[k];
     return GSF_OK;
 }
+
+namespace {
+
+// The last forward's ranges per global tile and its compositing order as
+// global tile ids (after a fovea-culled forward: its composited tiles only).
+// Compact fovea-box ranges are mapped back; a tile without keys gets [lb, lb),
+// lb being its lower bound among the sorted keys.
+gsf_status global_tiles(gsf_plan *p, std::vector<uint2> *ranges, std::vector<uint32_t> *order) {
+    const int64_t L = p->fwd_tiles > 0 ? p->fwd_tiles : p->total_tiles;
+    std::vector<uint2> lr((size_t)L);
+    std::vector<uint32_t> lo((size_t)L);
+    if (L) {
+        GSF_HIP(p->ctx, hipMemcpy(lr.data(), p->b.ranges, (size_t)L * 8, hipMemcpyDeviceToHost));
+        GSF_HIP(p->ctx, hipMemcpy(lo.data(), p->b.order, (size_t)L * 4, hipMemcpyDeviceToHost));
+    }
+    const TileMap tm = p->fwd_tm;
+    if (!tm.gaze) {
+        *ranges = std::move(lr);
+        *order = std::move(lo);
+        return GSF_OK;
+    }
+    std::vector<float> gz(2 * (size_t)p->V);
+    GSF_HIP(p->ctx, hipMemcpy(gz.data(), tm.gaze, gz.size() * 4, hipMemcpyDeviceToHost));
+    const int64_t area = (int64_t)tm.box * tm.box;
+    std::vector<int64_t> glob((size_t)L, -1);   // global id of each launch tile (-1: none)
+    for (int v = 0; v < p->V; v++) {
+        const ViewDesc &vd = p->views[v];
+        const FoveaTiles f = fovea_tiles(gz.data(), v, tm.radius, vd.width, vd.height, tm.tile);
+        for (int64_t l = 0; l < area; l++) {
+            const int ty = f.ty0 + (int)(l / tm.box), tx = f.tx0 + (int)(l % tm.box);
+            if (tx <= f.tx1 && ty <= f.ty1)
+                glob[(size_t)(v * area + l)] = vd.tile_off + (int64_t)ty * vd.tiles_x + tx;
+        }
+    }
+    ranges->assign((size_t)p->total_tiles, make_uint2(0u, 0u));
+    std::vector<char> has((size_t)p->total_tiles, 0);
+    for (size_t c = 0; c < glob.size(); c++)
+        if (glob[c] >= 0) {
+            (*ranges)[(size_t)glob[c]] = lr[c];
+            has[(size_t)glob[c]] = 1;
+        }
+    uint32_t pos = 0;
+    for (size_t t = 0; t < has.size(); t++) {
+        if (has[t]) pos = (*ranges)[t].y;
+        else (*ranges)[t] = make_uint2(pos, pos);
+    }
+    order->clear();
+    for (uint32_t c : lo)
+        if (c < glob.size() && glob[c] >= 0) order->push_back((uint32_t)glob[c]);
+    return GSF_OK;
+}
+
+}  // namespace
 
 gsf_status gsf_debug_copy(gsf_plan *p, int which, void *host_dst, size_t cap, size_t *written) {
     gsf_status st = check_ready(p);
@@ -1232,9 +1295,10 @@ gsf_status gsf_debug_copy(gsf_plan *p, int which, void *host_dst, size_t cap, si
     case GSF_DBG_COUNT: src = p->b.count; bytes = R * 4; break;
     case GSF_DBG_DEPTH: src = p->b.depth_key; bytes = R * 4; break;
     case GSF_DBG_KEYS: {   // the tile id of every key position, from the ranges
-        std::vector<uint2> rg((size_t)p->total_tiles);
-        if (!rg.empty())
-            GSF_HIP(p->ctx, hipMemcpy(rg.data(), p->b.ranges, rg.size() * 8, hipMemcpyDeviceToHost));
+        std::vector<uint2> rg;
+        std::vector<uint32_t> od;
+        st = global_tiles(p, &rg, &od);
+        if (st != GSF_OK) return st;
         std::vector<uint32_t> keys(M);
         for (size_t t = 0; t < rg.size(); t++)
             for (uint32_t k = rg[t].x; k < rg[t].y && k < M; k++) keys[k] = (uint32_t)t;
@@ -1245,8 +1309,19 @@ gsf_status gsf_debug_copy(gsf_plan *p, int which, void *host_dst, size_t cap, si
         return GSF_OK;
     }
     case GSF_DBG_VALS: src = p->b.vals; bytes = M * 4; break;
-    case GSF_DBG_RANGES: src = p->b.ranges; bytes = (size_t)p->total_tiles * 8; break;
-    case GSF_DBG_ORDER: src = p->b.order; bytes = (size_t)p->total_tiles * 4; break;
+    case GSF_DBG_RANGES:
+    case GSF_DBG_ORDER: {
+        std::vector<uint2> rg;
+        std::vector<uint32_t> od;
+        st = global_tiles(p, &rg, &od);
+        if (st != GSF_OK) return st;
+        const void *data = which == GSF_DBG_RANGES ? (const void *)rg.data() : (const void *)od.data();
+        bytes = which == GSF_DBG_RANGES ? rg.size() * 8 : od.size() * 4;
+        if (bytes > cap) return fail(p->ctx, GSF_E_INVALID, "gsf_debug_copy: destination too small");
+        if (bytes) std::memcpy(host_dst, data, bytes);
+        *written = bytes;
+        return GSF_OK;
+    }
     case GSF_DBG_BG: src = p->b.bg; bytes = p->views.size() * 3 * sizeof(float); break;
     case GSF_DBG_VIS: src = p->b.vis; bytes = (size_t)p->fwd_n; break;
     case GSF_DBG_TFINAL: src = p->b.tfinal; bytes = (size_t)p->total_pix * 4; break;

@@ -101,6 +101,31 @@ __device__ __forceinline__ int view_of_tile(const ViewDesc *__restrict__ views, 
     return v;
 }
 
+// Launch tile c of the compositing kernels: a global tile id, or (tm.gaze) a
+// compact fovea-box id (view c / box^2, then row-major from the view's first
+// fovea tile, as the fovea-culled sort keys).  False for a box tile past the
+// view's fovea tiles (no pixel of it is composited).
+__device__ __forceinline__ bool launch_tile(uint32_t c, const TileMap &tm,
+                                            const ViewDesc *__restrict__ views, int nviews, int T,
+                                            int &v, ViewDesc &vd, int &ty, int &tx) {
+    if (tm.gaze) {
+        const uint32_t box = (uint32_t)tm.box, area = box * box;
+        v = (int)(c / area);
+        const uint32_t l = c - (uint32_t)v * area, ly = l / box;
+        vd = views[v];
+        const FoveaTiles f = fovea_tiles(tm.gaze, v, tm.radius, vd.width, vd.height, T);
+        ty = f.ty0 + (int)ly;
+        tx = f.tx0 + (int)(l - ly * box);
+        return tx <= f.tx1 && ty <= f.ty1;
+    }
+    v = view_of_tile(views, nviews, (int)c);
+    vd = views[v];
+    const int local = (int)c - vd.tile_off;
+    ty = local / vd.tiles_x;
+    tx = local - ty * vd.tiles_x;
+    return true;
+}
+
 // Sum of x over the 64 lanes of a wave, valid in lane 63: four row shifts
 // (DPP row_shr 1, 2, 4, 8) leave each 16-lane row's total in its lane 15, then
 // row_bcast:15 and row_bcast:31 fold the rows together.  All steps are VALU
@@ -174,7 +199,7 @@ __global__ __launch_bounds__((fwd_threads<T, SPLIT>())) void k_render_fwd(
     float *__restrict__ out_rgba, float *__restrict__ tfinal, uint32_t *__restrict__ ncontrib,
     float4 *__restrict__ ckpt, float4 *__restrict__ fstate, float *__restrict__ tstore,
     const float *__restrict__ bg, const float *__restrict__ cull_gaze, float cull_radius,
-    int total_tiles) {
+    int total_tiles, TileMap tm) {
     constexpr bool CKPT = MODE == 1;
     constexpr bool QUAD = T == 16;   // a wave composites one 8 x 8 quadrant
     static_assert(!SPLIT || QUAD, "only 16-pixel tiles are split");
@@ -209,16 +234,15 @@ __global__ __launch_bounds__((fwd_threads<T, SPLIT>())) void k_render_fwd(
     const int quad = SPLIT ? (int)((blockIdx.x >> 3) & 3u) : (int)(threadIdx.x >> 6);
     const uint32_t oi = SPLIT ? (blockIdx.x >> 5) * 8u + (blockIdx.x & 7u) : blockIdx.x;
     if (oi >= (uint32_t)total_tiles) return;   // the split grid is padded to whole groups of 8 tiles
-    const int gt = (int)order[oi];
-    const int v = view_of_tile(views, nviews, gt);
-    const ViewDesc vd = views[v];
-    const int local = gt - vd.tile_off;
-    const int ty = local / vd.tiles_x, tx = local - ty * vd.tiles_x;
-    if (cull_gaze) {   // fovea culling: tiles away from the fovea are not composited
+    const uint32_t ti = order[oi];
+    int v, ty, tx;
+    ViewDesc vd;
+    if (!launch_tile(ti, tm, views, nviews, T, v, vd, ty, tx)) return;
+    if (cull_gaze && !tm.gaze) {   // fovea culling over global tiles: only tiles meeting the fovea
         const FoveaTiles f = fovea_tiles(cull_gaze, v, cull_radius, vd.width, vd.height, T);
         if (tx < f.tx0 || tx > f.tx1 || ty < f.ty0 || ty > f.ty1) return;
     }
-    const uint2 rg = ranges[gt];
+    const uint2 rg = ranges[ti];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int lx = QUAD ? (quad & 1) * 8 + (lane & 7) : threadIdx.x % T;
     const int ly = QUAD ? (quad >> 1) * 8 + (lane >> 3) : threadIdx.x / T;
@@ -428,14 +452,15 @@ template <int MODE>
 constexpr int kGradSlot = 9 * kRing<MODE> + 1;
 static_assert(kRing<0> % 2 == 0 && kRing<1> % 2 == 0, "splat pairs stay within a block");
 
-// Unit of adjoint work: the entries [us, ue) of tile gt's list.  With
+// Unit of adjoint work: the entries [us, ue) of launch tile ti's list (tm maps
+// it to its view and tile).  With
 // checkpoints (MODE 1) a unit is one LDS batch of B entries and starts from the
 // state the forward stored at the batch's end; otherwise a unit is the whole
 // list and starts from the final state.  MODE 2 reads each included pair's
 // transmittance from tstore instead of dividing.
 template <int T, int B, int MODE>
 __device__ __forceinline__ void render_bwd_unit(
-    int gt, uint32_t us, uint32_t ue, bool last_unit, const uint2 &rg,
+    uint32_t ti, const TileMap &tm, uint32_t us, uint32_t ue, bool last_unit, const uint2 &rg,
     const uint32_t *__restrict__ vals, SplatPtrs sp, const ViewDesc *__restrict__ views,
     int nviews, const gsf_camera *__restrict__ cams, const float *__restrict__ tfinal,
     const uint32_t *__restrict__ ncontrib, const float4 *__restrict__ fstate,
@@ -453,10 +478,9 @@ __device__ __forceinline__ void render_bwd_unit(
     // and a splat skips the quadrants its padded ellipse does not reach
     constexpr bool QUAD = T == 16;
     static_assert(!QUAD || (NT == 64 && PPT == 4), "quadrant layout: one wave, four blocks");
-    const int v = view_of_tile(views, nviews, gt);
-    const ViewDesc vd = views[v];
-    const int local = gt - vd.tile_off;
-    const int ty = local / vd.tiles_x, tx = local - ty * vd.tiles_x;
+    int v, ty, tx;
+    ViewDesc vd;
+    launch_tile(ti, tm, views, nviews, T, v, vd, ty, tx);   // a tile with keys: valid
     const int lane = threadIdx.x & 63;
     const float *bgv = bg ? bg + 3 * v : cams[v].bg;
     const float bg0 = bgv[0], bg1 = bgv[1], bg2 = bgv[2];
@@ -571,7 +595,8 @@ __device__ __forceinline__ void render_bwd_unit(
             const float4 b = s_b[j];
             const float4 c = s_c[j];
             const float hy = QUAD ? 0.f : s_h[j];
-            const uint32_t qm = QUAD ? s_m[j] : 0u;
+            // the splat's quadrant mask, wave-uniform: tested in scalar registers
+            const uint32_t qm = QUAD ? __builtin_amdgcn_readfirstlane((uint32_t)s_m[j]) : 0u;
             // row offset of the tile's first row from the mean; block k adds k ROWS
             const float dy0 = splat_dx((float)(ty * T), c.w, a.y);
             // per lane sums: te dx, te dy, te dx^2, te dx dy, te dy^2 (te = dL/do, so
@@ -716,7 +741,7 @@ __global__ __launch_bounds__(bwd_threads<T>()) void k_render_bwd(
     const ViewDesc *__restrict__ views, int nviews, const gsf_camera *__restrict__ cams,
     const float *__restrict__ tfinal, const uint32_t *__restrict__ ncontrib,
     const float *__restrict__ tstore, const float *__restrict__ bg, const float *__restrict__ dl,
-    KeyPlace kp) {
+    KeyPlace kp, TileMap tm) {
     constexpr int NT = bwd_threads<T>();
     __shared__ float4 s_a[B];
     __shared__ float4 s_b[B];
@@ -727,12 +752,12 @@ __global__ __launch_bounds__(bwd_threads<T>()) void k_render_bwd(
     __shared__ uint64_t s_hit[NT / 64];
     __shared__ float s_h[B];
     __shared__ uint32_t s_nmax[NT / 64];
-    const int gt = (int)order[blockIdx.x];
-    const uint2 rg = ranges[gt];
+    const uint32_t ti = order[blockIdx.x];
+    const uint2 rg = ranges[ti];
     // a tile without keys passes no gradient (and a fovea-culled step's tiles
     // away from the fovea hold no pixel state to read)
     if (rg.x == rg.y) return;
-    render_bwd_unit<T, B, MODE>(gt, rg.x, rg.y, true, rg, vals, sp, views, nviews, cams, tfinal,
+    render_bwd_unit<T, B, MODE>(ti, tm, rg.x, rg.y, true, rg, vals, sp, views, nviews, cams, tfinal,
                                 ncontrib, nullptr, nullptr, tstore, bg, dl, kp, s_a, s_b, s_c, s_q,
                                 s_m, s_g, s_hit, s_h, s_nmax);
 }
@@ -749,7 +774,7 @@ __global__ __launch_bounds__(bwd_threads<T>()) void k_render_bwd_ckpt(
     const ViewDesc *__restrict__ views, int nviews, const gsf_camera *__restrict__ cams,
     const float *__restrict__ tfinal, const uint32_t *__restrict__ ncontrib,
     const float4 *__restrict__ fstate, const float4 *__restrict__ ckpt,
-    const float *__restrict__ bg, const float *__restrict__ dl, KeyPlace kp) {
+    const float *__restrict__ bg, const float *__restrict__ dl, KeyPlace kp, TileMap tm) {
     constexpr int NT = bwd_threads<T>();
     __shared__ float4 s_a[B];
     __shared__ float4 s_b[B];
@@ -775,7 +800,7 @@ __global__ __launch_bounds__(bwd_threads<T>()) void k_render_bwd_ckpt(
         if (u >= units) continue;
         const uint32_t us = rg.x + u * B;
         const uint32_t ue = min(rg.y, us + B);
-        render_bwd_unit<T, B, 1>(lo, us, ue, u + 1 == units, rg, vals, sp, views, nviews, cams,
+        render_bwd_unit<T, B, 1>((uint32_t)lo, tm, us, ue, u + 1 == units, rg, vals, sp, views, nviews, cams,
                                  tfinal, ncontrib, fstate, ckpt, nullptr, bg, dl, kp, s_a, s_b,
                                  s_c, s_q, s_m, s_g, s_hit, s_h, s_nmax);
     }
@@ -800,19 +825,18 @@ __global__ __launch_bounds__(64) void k_grad_sum(KeyPlace kp, int nrec, float *_
 template <int T>
 __global__ __launch_bounds__(T * T < 256 ? T * T : 256) void k_count_pairs(
     const uint2 *__restrict__ ranges, const uint32_t *__restrict__ vals, SplatPtrs sp,
-    const ViewDesc *__restrict__ views, int nviews, unsigned long long *__restrict__ counters) {
+    const ViewDesc *__restrict__ views, int nviews, TileMap tm,
+    unsigned long long *__restrict__ counters) {
     constexpr int NT = T * T < 256 ? T * T : 256;
     constexpr int PPT = T * T / NT;
     constexpr int ROWS = NT / T;
     __shared__ unsigned long long s_cnt[3];
     if (threadIdx.x < 3) s_cnt[threadIdx.x] = 0ull;
     __syncthreads();
-    const int gt = blockIdx.x;
-    const int v = view_of_tile(views, nviews, gt);
-    const ViewDesc vd = views[v];
-    const int local = gt - vd.tile_off;
-    const int ty = local / vd.tiles_x, tx = local - ty * vd.tiles_x;
-    const uint2 rg = ranges[gt];
+    int v, ty, tx;
+    ViewDesc vd;
+    const bool valid = launch_tile(blockIdx.x, tm, views, nviews, T, v, vd, ty, tx);
+    const uint2 rg = valid ? ranges[blockIdx.x] : make_uint2(0u, 0u);
     unsigned long long visit = 0, incl = 0, visit_bwd = 0;
 #pragma unroll
     for (int k = 0; k < PPT; k++) {
@@ -1055,8 +1079,19 @@ __global__ __launch_bounds__(1024) void k_loss_final(const float *__restrict__ p
                                                      uint32_t *__restrict__ flags,
                                                      int32_t *__restrict__ step_inc, bool accumulate) {
     __shared__ float s_part[16];
-    float s = 0.f;
-    for (int k = threadIdx.x; k < nparts; k += 1024) s += partial[k];
+    // four partials per thread and step (16-byte loads; the tail one by one),
+    // in four sums: a fixed order, so the loss is deterministic
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+    const int n4 = nparts / 4;
+    for (int k = threadIdx.x; k < n4; k += 1024) {
+        const float4 v = reinterpret_cast<const float4 *>(partial)[k];
+        s0 += v.x;
+        s1 += v.y;
+        s2 += v.z;
+        s3 += v.w;
+    }
+    for (int k = 4 * n4 + (int)threadIdx.x; k < nparts; k += 1024) s0 += partial[k];
+    float s = (s0 + s1) + (s2 + s3);
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);   // same tree on every lane
     if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = s;
@@ -1112,17 +1147,17 @@ void render_fwd_tbs(hipStream_t s, const RenderArgs &a, float *out) {
         k_render_fwd<T, B, 1, SPLIT><<<g, NT, 0, s>>>(a.order, a.ranges, a.vals, a.sp, a.views,
                                                      a.nviews, a.cams, out, a.tfinal, a.ncontrib, a.ckpt,
                                                      a.fstate, nullptr, a.bg, a.cull_gaze, a.cull_radius,
-                                                     a.total_tiles);
+                                                     a.total_tiles, a.tm);
     else if (a.t_mode == 2)
         k_render_fwd<T, B, 2, SPLIT><<<g, NT, 0, s>>>(a.order, a.ranges, a.vals, a.sp, a.views,
                                                      a.nviews, a.cams, out, a.tfinal, a.ncontrib, nullptr,
                                                      nullptr, a.tstore, a.bg, a.cull_gaze, a.cull_radius,
-                                                     a.total_tiles);
+                                                     a.total_tiles, a.tm);
     else
         k_render_fwd<T, B, 0, SPLIT><<<g, NT, 0, s>>>(a.order, a.ranges, a.vals, a.sp, a.views,
                                                      a.nviews, a.cams, out, a.tfinal, a.ncontrib, nullptr,
                                                      nullptr, nullptr, a.bg, a.cull_gaze, a.cull_radius,
-                                                     a.total_tiles);
+                                                     a.total_tiles, a.tm);
 }
 
 // Split 16-pixel tiles into one workgroup per quadrant when the plan has at
@@ -1147,15 +1182,15 @@ void render_bwd_tb(hipStream_t s, const RenderArgs &a, const float *dl) {
         k_render_bwd_ckpt<T, B><<<a.bwd_grid, NT, 0, s>>>(a.ranges, a.total_tiles, a.m_dev, a.m_host,
                                                          a.vals, a.sp, a.views, a.nviews, a.cams,
                                                          a.tfinal, a.ncontrib, a.fstate, a.ckpt, a.bg,
-                                                         dl, a.kp);
+                                                         dl, a.kp, a.tm);
     else if (a.t_mode == 2)
         k_render_bwd<T, B, 2><<<a.total_tiles, NT, 0, s>>>(a.order, a.ranges, a.vals, a.sp,
                                                         a.views, a.nviews, a.cams, a.tfinal,
-                                                        a.ncontrib, a.tstore, a.bg, dl, a.kp);
+                                                        a.ncontrib, a.tstore, a.bg, dl, a.kp, a.tm);
     else
         k_render_bwd<T, B, 0><<<a.total_tiles, NT, 0, s>>>(a.order, a.ranges, a.vals, a.sp,
                                                         a.views, a.nviews, a.cams, a.tfinal,
-                                                        a.ncontrib, nullptr, a.bg, dl, a.kp);
+                                                        a.ncontrib, nullptr, a.bg, dl, a.kp, a.tm);
 }
 
 template <int T>
@@ -1193,14 +1228,14 @@ void launch_grad_sum(hipStream_t s, const KeyPlace &kp, int nrec, float *g2d) {
 
 void launch_count_pairs(hipStream_t s, int tile, int total_tiles, const uint2 *ranges,
                         const uint32_t *vals, SplatPtrs sp, const ViewDesc *views, int nviews,
-                        unsigned long long *counters) {
+                        const TileMap &tm, unsigned long long *counters) {
     k_zero_u64<<<1, 64, 0, s>>>(counters, 3);
     if (tile == 8)
-        k_count_pairs<8><<<total_tiles, 64, 0, s>>>(ranges, vals, sp, views, nviews, counters);
+        k_count_pairs<8><<<total_tiles, 64, 0, s>>>(ranges, vals, sp, views, nviews, tm, counters);
     else if (tile == 16)
-        k_count_pairs<16><<<total_tiles, 256, 0, s>>>(ranges, vals, sp, views, nviews, counters);
+        k_count_pairs<16><<<total_tiles, 256, 0, s>>>(ranges, vals, sp, views, nviews, tm, counters);
     else
-        k_count_pairs<32><<<total_tiles, 256, 0, s>>>(ranges, vals, sp, views, nviews, counters);
+        k_count_pairs<32><<<total_tiles, 256, 0, s>>>(ranges, vals, sp, views, nviews, tm, counters);
 }
 
 // Partial sums of a loss launch: one per block (a fovea-window launch's views

@@ -283,15 +283,31 @@ def test_fovea_culling_matches_full_frame(gs, ctx):
     tgt = np.concatenate([rng.uniform(0, 1, size=3 * c.npix) for c in cams]).astype(np.float32)
     tgt_dev = torch.from_numpy(tgt).to(DEV)
     gz = torch.from_numpy(np.ascontiguousarray(gaze)).to(DEV)
-    runs = {}
+    runs, lists = {}, {}
     for cull in (False, True):
         cfg = gs.FitConfig(lr=0.0, tile=16, lds_batch=64, fovea_cull=cull)
         fs = gs.FitStep(ctx, torch.from_numpy(P).to(DEV), cams, tgt_dev, gz, cfg=cfg, fused=True)
         fs.step()
         torch.cuda.synchronize()
         runs[cull] = (fs.loss.item(), fs.rgba.cpu().numpy(), fs.grads.cpu().numpy(), fs.poll()[1])
+        T, M = fs.plan.total_tiles, runs[cull][3]
+        lists[cull] = (fs.plan.debug(_abi.GSF_DBG_RANGES, np.uint32, 2 * T).reshape(-1, 2).astype(np.int64),
+                       fs.plan.debug(_abi.GSF_DBG_KEYS, np.uint32, M).astype(np.int64),
+                       fs.plan.debug(_abi.GSF_DBG_VALS, np.uint32, M).astype(np.int64),
+                       fs.plan.debug(_abi.GSF_DBG_ORDER, np.uint32, T).astype(np.int64))
         fs.plan.close()
     (l0, img0, g0, m0), (l1, img1, g1, m1) = runs[False], runs[True]
+    # the culled step sorts, ranges and composites compact fovea-box tiles; mapped
+    # back to global tiles its lists are the full frame's lists of those tiles
+    (r0, k0, v0, o0), (r1, k1, v1, o1) = lists[False], lists[True]
+    T = r0.shape[0]
+    assert (np.diff(k1) >= 0).all() and k1.size == m1
+    np.testing.assert_array_equal(r1[:, 0], np.searchsorted(k1, np.arange(T), "left"))
+    np.testing.assert_array_equal(r1[:, 1], np.searchsorted(k1, np.arange(T), "right"))
+    assert np.unique(o1).size == o1.size and set(np.unique(k1)) <= set(o1.tolist())
+    assert o1.size < T
+    for t in o1:
+        np.testing.assert_array_equal(v1[r1[t, 0]:r1[t, 1]], v0[r0[t, 0]:r0[t, 1]])
     log(f"[cull] loss {l0:.7f} vs {l1:.7f}, keys {m0} -> {m1}")
     assert m1 < m0
     assert abs(l1 - l0) <= 1e-6 * abs(l0)
