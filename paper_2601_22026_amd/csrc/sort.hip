@@ -36,6 +36,7 @@ constexpr int kSortTile = kSortBlock * kSortIpt;
 constexpr int kSortMaxGrid = 1024;
 constexpr int kMaxDigit = 8;                 // radix digits of at most 256 bins
 constexpr int kHistU = 16;                   // keys in flight per thread while counting digits
+constexpr int kLocalScanGrid = 64;           // radix grids up to this sum their digit offsets in the scatter
 constexpr int kScanBlock = 256;
 constexpr int kScanIpt = 1;                  // 256 records per block: 50k records fill 196 blocks
 constexpr int kScanTile = kScanBlock * kScanIpt;
@@ -178,11 +179,25 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(
     const int nd = 1 << bits;
     const uint32_t mask = (uint32_t)nd - 1u;
     const int t = threadIdx.x, w = t >> 6, lane = __lane_id();
-    {   // global base of each digit for this workgroup
+    if (digit_tot) {   // global base of each digit for this workgroup (hist scanned per digit)
         const uint32_t tot = t < nd ? digit_tot[t] : 0u;
         uint32_t all;
         const uint32_t dp = block_excl_scan_256(tot, s_wave, all);
         if (t < nd) s_base[t] = dp + hist[(size_t)t * G + blockIdx.x];
+    } else {   // few workgroups: each sums the raw counts itself (no scan launch)
+        uint32_t tot = 0u, before = 0u;
+        if (t < nd) {
+            const uint32_t *row = hist + (size_t)t * G;
+#pragma unroll 8
+            for (int g = 0; g < G; g++) {
+                const uint32_t c = row[g];
+                tot += c;
+                before += g < (int)blockIdx.x ? c : 0u;
+            }
+        }
+        uint32_t all;
+        const uint32_t dp = block_excl_scan_256(tot, s_wave, all);
+        if (t < nd) s_base[t] = dp + before;
     }
     // Each round takes up to kSortTile keys; wave w ranks the contiguous run
     // [wbase, wbase + span) of them, span being the fewest whole rounds of 64
@@ -850,9 +865,11 @@ int launch_radix_sort(hipStream_t s, const uint32_t *kin, const uint32_t *vin, u
         const int b = (bits - shift + (passes - p) - 1) / (passes - p);
         uint32_t *kd = where == 1 ? kb : ka, *vd = where == 1 ? vb : va;
         k_radix_hist<<<grid, kSortBlock, 0, s>>>(ks, n_dev, n_host, shift, b, hist, grid);
-        k_radix_colscan<<<1 << b, 256, 0, s>>>(hist, grid, digit_tot);
+        // up to kLocalScanGrid workgroups sum their digit offsets themselves
+        const bool local = grid <= kLocalScanGrid;
+        if (!local) k_radix_colscan<<<1 << b, 256, 0, s>>>(hist, grid, digit_tot);
         k_radix_scatter<<<grid, kSortBlock, 0, s>>>(ks, vs, kd, vd, n_dev, n_host, shift, b, hist,
-                                                    digit_tot, grid);
+                                                    local ? nullptr : digit_tot, grid);
         where = where == 1 ? 2 : 1;
         ks = kd;
         vs = vd;
