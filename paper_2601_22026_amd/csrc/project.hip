@@ -222,23 +222,23 @@ __device__ __forceinline__ void view_dir(const Gauss &g, const gsf_camera &cam, 
     d[2] = u2 * inv_norm;
 }
 
-// Record r's projection; returns its key count (0 when culled).
+// Record r = v n + i's projection of Gaussian g; returns its key count (0 when
+// culled).  shc: its SH coefficients [K][3] in registers, or null to read them
+// from P.
 template <int DEG>
-__device__ __forceinline__ uint32_t project_record(const float *__restrict__ P, int n, int r,
-                                                     const gsf_camera *__restrict__ cams,
-                                                     const ViewDesc *__restrict__ views, int tile,
-                                                     SplatPtrs sp, uint32_t *__restrict__ depth_key,
-                                                     uint2 *__restrict__ rect,
-                                                     uint32_t *__restrict__ count,
-                                                     uint2 *__restrict__ rspan,
-                                                     const float *__restrict__ cull_gaze,
-                                                     float cull_radius) {
+__device__ __forceinline__ uint32_t project_gauss(const Gauss &g, const float *shc,
+                                                    const float *__restrict__ P, int n, int v, int i,
+                                                    const gsf_camera *__restrict__ cams,
+                                                    const ViewDesc *__restrict__ views, int tile,
+                                                    SplatPtrs sp, uint32_t *__restrict__ depth_key,
+                                                    uint2 *__restrict__ rect,
+                                                    uint32_t *__restrict__ count,
+                                                    uint2 *__restrict__ rspan,
+                                                    const float *__restrict__ cull_gaze,
+                                                    float cull_radius) {
     constexpr int K = (DEG + 1) * (DEG + 1);
-    const int v = r / n;
-    const int i = r - v * n;
+    const int r = v * n + i;
     const gsf_camera &cam = cams[v];
-    Gauss g;
-    load_gauss(P, n, i, g);
     Proj p;
     bool ok = project(g, cam, p) && (g.o >= kAlphaMin);
     if (ok) ok = isfinite(p.mx) && isfinite(p.my) && isfinite(p.A) && isfinite(p.B) && isfinite(p.C);
@@ -300,7 +300,8 @@ __device__ __forceinline__ uint32_t project_record(const float *__restrict__ P, 
     for (int ch = 0; ch < 3; ch++) {
         float acc = 0.f;
 #pragma unroll
-        for (int k = 0; k < K; k++) acc = fmaf(P[(size_t)(11 + 3 * k + ch) * n + i], Y[k], acc);
+        for (int k = 0; k < K; k++)
+            acc = fmaf(shc ? shc[3 * k + ch] : P[(size_t)(11 + 3 * k + ch) * n + i], Y[k], acc);
         col[ch] = fmaxf(acc + 0.5f, 0.f);
     }
     // conic pre-scaled for a base-2 exponent, and the alpha threshold of the
@@ -349,6 +350,76 @@ __device__ __forceinline__ uint32_t project_record(const float *__restrict__ P, 
     rspan[r] = pack ? make_uint2(packed[0], packed[1]) : make_uint2(listed_rows, 0u);
     count[r] = cnt;
     return cnt;
+}
+
+// Record r's projection (its Gaussian's parameters read from P).
+template <int DEG>
+__device__ __forceinline__ uint32_t project_record(const float *__restrict__ P, int n, int r,
+                                                     const gsf_camera *__restrict__ cams,
+                                                     const ViewDesc *__restrict__ views, int tile,
+                                                     SplatPtrs sp, uint32_t *__restrict__ depth_key,
+                                                     uint2 *__restrict__ rect,
+                                                     uint32_t *__restrict__ count,
+                                                     uint2 *__restrict__ rspan,
+                                                     const float *__restrict__ cull_gaze,
+                                                     float cull_radius) {
+    const int v = r / n;
+    const int i = r - v * n;
+    Gauss g;
+    load_gauss(P, n, i, g);
+    return project_gauss<DEG>(g, nullptr, P, n, v, i, cams, views, tile, sp, depth_key, rect, count,
+                              rspan, cull_gaze, cull_radius);
+}
+
+// Several views, SH degrees 0-1: one thread per Gaussian projects it into every
+// view, its parameters read once instead of once per view (records of one
+// view stay consecutive across the threads, so the stores coalesce).  The
+// per-block count totals come from k_block_totals.
+template <int DEG>
+__global__ __launch_bounds__(256) void k_project_fwd_views(const float *__restrict__ P, int n,
+                                                           int nviews,
+                                                           const gsf_camera *__restrict__ cams,
+                                                           const ViewDesc *__restrict__ views,
+                                                           int tile, SplatPtrs sp,
+                                                           uint32_t *__restrict__ depth_key,
+                                                           uint2 *__restrict__ rect,
+                                                           uint32_t *__restrict__ count,
+                                                           uint2 *__restrict__ rspan,
+                                                           const float *__restrict__ cull_gaze,
+                                                           float cull_radius) {
+    constexpr int K = (DEG + 1) * (DEG + 1);
+    const int i = blockIdx.x * 256 + (int)threadIdx.x;
+    if (i >= n) return;
+    Gauss g;
+    load_gauss(P, n, i, g);
+    float shc[3 * K];
+#pragma unroll
+    for (int k = 0; k < 3 * K; k++) shc[k] = P[(size_t)(11 + k) * n + i];
+    for (int v = 0; v < nviews; v++)
+        project_gauss<DEG>(g, shc, P, n, v, i, cams, views, tile, sp, depth_key, rect, count, rspan,
+                           cull_gaze, cull_radius);
+}
+
+// block_sums[b] / block_act[b]: the total count / the records with a nonzero
+// count among records 256 b .. 256 b + 255.
+__global__ __launch_bounds__(256) void k_block_totals(const uint32_t *__restrict__ count, int nrec,
+                                                      uint32_t *__restrict__ block_sums,
+                                                      uint32_t *__restrict__ block_act) {
+    __shared__ uint32_t s_w[4], s_a[4];
+    const int r = blockIdx.x * 256 + (int)threadIdx.x;
+    uint32_t c = r < nrec ? count[r] : 0u;
+    const uint32_t a = (uint32_t)__popcll(__ballot(c != 0u));
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+    if ((threadIdx.x & 63) == 0) {
+        s_w[threadIdx.x >> 6] = c;
+        s_a[threadIdx.x >> 6] = a;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        block_sums[blockIdx.x] = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+        block_act[blockIdx.x] = s_a[0] + s_a[1] + s_a[2] + s_a[3];
+    }
 }
 
 // One thread per record, 256 records per block; block b also writes the key
@@ -570,6 +641,17 @@ void launch_project_fwd(hipStream_t s, const float *P, int n, int nviews, int de
                         uint32_t *block_act) {
     const int nrec = n * nviews;
     const dim3 grid((nrec + 255) / 256), block(256);
+    if (deg <= 1 && nviews > 1) {   // one thread per Gaussian for all views, then the block totals
+        const dim3 ggrid((n + 255) / 256);
+        if (deg == 0)
+            k_project_fwd_views<0><<<ggrid, block, 0, s>>>(P, n, nviews, cams, views, tile, sp, depth_key,
+                                                            rect, count, rspan, cull_gaze, cull_radius);
+        else
+            k_project_fwd_views<1><<<ggrid, block, 0, s>>>(P, n, nviews, cams, views, tile, sp, depth_key,
+                                                            rect, count, rspan, cull_gaze, cull_radius);
+        k_block_totals<<<grid, block, 0, s>>>(count, nrec, block_sums, block_act);
+        return;
+    }
     switch (deg) {
     case 0: k_project_fwd<0><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rect, count, rspan, cull_gaze, cull_radius, block_sums, block_act); break;
     case 1: k_project_fwd<1><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rect, count, rspan, cull_gaze, cull_radius, block_sums, block_act); break;
