@@ -401,24 +401,32 @@ __global__ __launch_bounds__(256) void k_project_fwd_views(const float *__restri
 }
 
 // block_sums[b] / block_act[b]: the total count / the records with a nonzero
-// count among records 256 b .. 256 b + 255.
+// count among records 256 b .. 256 b + 255.  One wave per 256 records, four
+// per lane in one 16-byte load (the count array is 256-byte aligned).
 __global__ __launch_bounds__(256) void k_block_totals(const uint32_t *__restrict__ count, int nrec,
                                                       uint32_t *__restrict__ block_sums,
                                                       uint32_t *__restrict__ block_act) {
-    __shared__ uint32_t s_w[4], s_a[4];
-    const int r = blockIdx.x * 256 + (int)threadIdx.x;
-    uint32_t c = r < nrec ? count[r] : 0u;
-    const uint32_t a = (uint32_t)__popcll(__ballot(c != 0u));
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
-    if ((threadIdx.x & 63) == 0) {
-        s_w[threadIdx.x >> 6] = c;
-        s_a[threadIdx.x >> 6] = a;
+    const int bb = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+    if (bb * 256 >= nrec) return;
+    const int lane = (int)(threadIdx.x & 63), r0 = bb * 256 + lane * 4;
+    uint4 q = make_uint4(0u, 0u, 0u, 0u);
+    if (r0 + 3 < nrec) {
+        q = *reinterpret_cast<const uint4 *>(count + r0);
+    } else {
+        if (r0 < nrec) q.x = count[r0];
+        if (r0 + 1 < nrec) q.y = count[r0 + 1];
+        if (r0 + 2 < nrec) q.z = count[r0 + 2];
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        block_sums[blockIdx.x] = s_w[0] + s_w[1] + s_w[2] + s_w[3];
-        block_act[blockIdx.x] = s_a[0] + s_a[1] + s_a[2] + s_a[3];
+    uint32_t c = q.x + q.y + q.z + q.w;
+    uint32_t a = (q.x != 0u) + (q.y != 0u) + (q.z != 0u) + (q.w != 0u);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        c += __shfl_xor(c, o, 64);
+        a += __shfl_xor(a, o, 64);
+    }
+    if (lane == 0) {
+        block_sums[bb] = c;
+        block_act[bb] = a;
     }
 }
 
@@ -649,7 +657,7 @@ void launch_project_fwd(hipStream_t s, const float *P, int n, int nviews, int de
         else
             k_project_fwd_views<1><<<ggrid, block, 0, s>>>(P, n, nviews, cams, views, tile, sp, depth_key,
                                                             rect, count, rspan, cull_gaze, cull_radius);
-        k_block_totals<<<grid, block, 0, s>>>(count, nrec, block_sums, block_act);
+        k_block_totals<<<(nrec + 1023) / 1024, block, 0, s>>>(count, nrec, block_sums, block_act);
         return;
     }
     switch (deg) {

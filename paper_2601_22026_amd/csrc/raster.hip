@@ -623,7 +623,11 @@ __device__ __forceinline__ void render_bwd_unit(
                 // no pixel of the block takes the splat: every lane would add
                 // zeros and keep its state (wave-uniform)
                 if (QUAD && !__any(inc)) continue;
-                const float ex = __builtin_amdgcn_exp2f(power2);
+                // Recomputed transmittance: a pixel the splat does not reach
+                // takes power -inf instead, so exp2 = 0, alpha = 0, 1 / (1 - alpha)
+                // = 1 and its state passes through unchanged bit for bit (Tr x 1,
+                // gR + gc x 0) with zero sums, without a select per quantity.
+                const float ex = __builtin_amdgcn_exp2f(MODE == 2 || inc ? power2 : -__builtin_inff());
                 const float ae = b.y * ex;
                 const float alpha = fminf(kAlphaMax, ae);
                 any |= inc;
@@ -635,16 +639,17 @@ __device__ __forceinline__ void render_bwd_unit(
                     Tb = Tr[k] * inv;
                 const float gc = fmaf(g2[k], c.x, fmaf(g1[k], b.w, g0[k] * b.z));
                 const float dalpha = fmaf(Tb, gc, -(gR[k] * inv));
-                const float wT = inc ? alpha * Tb : 0.f;
+                const float wT = MODE != 2 || inc ? alpha * Tb : 0.f;
                 acc[6] = fmaf(wT, g0[k], acc[6]);
                 acc[7] = fmaf(wT, g1[k], acc[7]);
                 acc[8] = fmaf(wT, g2[k], acc[8]);
                 gR[k] = fmaf(gc, wT, gR[k]);
-                Tr[k] = inc ? Tb : Tr[k];
+                if (MODE == 2) Tr[k] = inc ? Tb : Tr[k];
+                else Tr[k] = Tb;
                 // a clamped alpha passes no gradient to the opacity or the power;
                 // te = dL/do, and dL/dpower (natural units) = o te, the opacity
                 // factor being applied to the sums once per splat at the flush
-                const bool open = inc & !(ae > kAlphaMax);
+                const bool open = (MODE != 2 || inc) & !(ae > kAlphaMax);
                 const float te = open ? ex * dalpha : 0.f;
                 acc[5] += te;
                 const float ux = te * dx, uy = te * dy;

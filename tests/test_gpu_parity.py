@@ -100,6 +100,45 @@ def test_discrete_stage_bit_exact(ctx, tile):
             f"{int((~touched).sum())} of {tiles}")
 
 
+def test_discrete_stage_with_saturated_counts(ctx):
+    """A plan of over 2^23 records, so that a depth-sort value keeps only 8 bits
+    for the record's tile count above its entry index: near splats list more
+    tiles than that (the emission then reads their count from the entry).  All
+    but 308 of the 4.2M Gaussians lie behind the cameras; the visible ones sit
+    at spread indices, and the keys, values and ranges equal the oracle's for
+    them alone (record ids mapped to the full plan), bit for bit."""
+    n = (1 << 22) + 1000
+    vis = synth.with_near_splats(synth.random_gaussians(300, seed=14), 8, seed=14)
+    rng = np.random.default_rng(14)
+    idx = np.sort(rng.choice(n, size=vis.shape[1], replace=False))
+    P = np.repeat(vis[:, :1], n, axis=1)
+    P[0:3] = [[0.0], [0.0], [-10.0]]   # every other Gaussian behind both cameras (negative view depth)
+    P[:, idx] = vis
+    cams = [synth.axis_camera(256, 256), synth.look_at_camera([0.4, -0.3, -2.8], width=224, height=200)]
+    log(f"[parity] saturated counts: {n} Gaussians x 2 views, {vis.shape[1]} visible, tile 8")
+    sc = GpuScene(ctx, P, cams, tile=8)
+    sc.forward()
+    d = oracle.discrete(vis, cams, 8)
+    nv = vis.shape[1]
+    full = lambda r: (r // nv) * n + idx[r % nv]   # subset record id -> plan record id
+    count = sc.debug(_abi.GSF_DBG_COUNT, np.uint32, 2 * n).astype(np.int64)
+    Mg = int(count.sum())
+    assert count.max() > 255, count.max()   # counts that do not fit the value's 8 bits
+    keys = sc.debug(_abi.GSF_DBG_KEYS, np.uint32, Mg).astype(np.int64)
+    vals = sc.debug(_abi.GSF_DBG_VALS, np.uint32, Mg).astype(np.int64)
+    tiles = d.ranges.shape[0]
+    ranges = sc.debug(_abi.GSF_DBG_RANGES, np.uint32, 2 * tiles).reshape(-1, 2).astype(np.int64)
+    flagged = full(np.nonzero(d.rflags != 0)[0])
+    dvals = full(d.vals)
+    drop_g, drop_o = np.isin(vals, flagged), np.isin(dvals, flagged)
+    np.testing.assert_array_equal(keys[~drop_g], d.keys[~drop_o])
+    np.testing.assert_array_equal(vals[~drop_g], dvals[~drop_o])
+    assert (np.diff(keys) >= 0).all()
+    np.testing.assert_array_equal(ranges[:, 0], np.searchsorted(keys, np.arange(tiles), "left"))
+    np.testing.assert_array_equal(ranges[:, 1], np.searchsorted(keys, np.arange(tiles), "right"))
+    log(f"[parity]   keys {Mg}, largest count {count.max()}, flagged records {flagged.size}")
+
+
 @pytest.mark.parametrize("planes", [1, 3])
 def test_equal_depths_keep_record_order(ctx, planes):
     """Means on one or three planes of constant camera depth, so most depths tie
