@@ -734,7 +734,7 @@ def main():
             # one regeneration: seed the Gaussians on the device from the resident
             # volume, plan, capture, run the steps - wall clock, synchronised
             import synth
-            runs, seeds, replans = [], [], 0
+            runs, seeds, plans, caps, replans = [], [], [], [], 0
             same = None
             for k in range(args.regen_runs):
                 phase(f"regeneration {k + 1}/{args.regen_runs} ({args.regen_steps} steps)")
@@ -743,11 +743,17 @@ def main():
                 Ps = gs.seed_volume(ctx, vol_dev, cap=N, seed=synth.SEED_CAP_SUBSET)
                 t_seeded = time.perf_counter()
                 rf = gs.FitStep(ctx, Ps, cams, tgt_dev, gaze_dev, cfg=cfg, fused=True)
+                torch.cuda.synchronize()
+                t_planned = time.perf_counter()
                 rf.capture()
+                torch.cuda.synchronize()
+                t_captured = time.perf_counter()
                 replans += rf.run(args.regen_steps)
                 torch.cuda.synchronize()
                 runs.append((time.perf_counter() - t_start) * 1e3)
                 seeds.append((t_seeded - t_start) * 1e3)
+                plans.append((t_planned - t_seeded) * 1e3)
+                caps.append((t_captured - t_planned) * 1e3)
                 if same is None:   # the device seeding reproduces the workload's Gaussians
                     again = gs.seed_volume(ctx, vol_dev, cap=N, seed=synth.SEED_CAP_SUBSET)
                     same = bool(torch.equal(again.cpu(), torch.from_numpy(P)))
@@ -765,6 +771,8 @@ def main():
             regen = {"ms_per_regeneration": round(sorted(runs)[len(runs) // 2], 2),
                      "steps": args.regen_steps, "runs_ms": [round(r, 2) for r in runs],
                      "seeding_ms": round(sorted(seeds)[len(seeds) // 2], 2),
+                     "plan_ms": round(sorted(plans)[len(plans) // 2], 2),
+                     "capture_ms": round(sorted(caps)[len(caps) // 2], 2),
                      "key_replans": replans,
                      "seeded_on_device_equals_workload": same,
                      "target_raymarch_ms": round(sorted(march)[1], 2),
@@ -774,7 +782,8 @@ def main():
                      "paper_context": "full peripheral-model regeneration in about 1.0 s on an RTX "
                                       "4090, including path tracing the views (context only)"}
             log(f"[bench] regeneration ({args.regen_steps} steps): {regen['ms_per_regeneration']} ms "
-                f"(seeding {regen['seeding_ms']} ms, same Gaussians as the workload: {same}, "
+                f"(seeding {regen['seeding_ms']} ms, plan {regen['plan_ms']} ms, capture "
+                f"{regen['capture_ms']} ms, same Gaussians as the workload: {same}, "
                 f"key re-plans {replans}); target ray march {regen['target_raymarch_ms']} ms")
 
         # fused, eager (same plan shape, no graph)

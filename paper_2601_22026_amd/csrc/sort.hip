@@ -341,15 +341,15 @@ __global__ __launch_bounds__(kSegBlocks) void k_seg_scan(uint32_t *__restrict__ 
     }
 }
 
-// The first offsets of block blockIdx.x and the totals: with at most
-// kOwnPrefixBlocks blocks each block sums the totals of the blocks before it
-// itself; otherwise k_seg_scan has scanned each segment in place and the block
+// The first offsets of scan block `first` (a workgroup's first block of 256
+// records) and the totals: with at most kOwnPrefixBlocks blocks each workgroup
+// sums the totals of the blocks before it itself; otherwise k_seg_scan has scanned each segment in place and the block
 // adds the totals of the segments before its own.  With `publish`, block 0
 // writes the totals (m_total; m_dev = key total, 0 on overflow with
 // GSF_FLAG_CAPACITY; a_dev = active records, 0 on overflow).  Returns false on
 // a key overflow.
 __device__ __forceinline__ bool block_prefix(const uint32_t *__restrict__ sums,
-                                             const uint32_t *__restrict__ act, int nblocks,
+                                             const uint32_t *__restrict__ act, int nblocks, int first,
                                              const unsigned long long *__restrict__ seg_tot,
                                              const uint32_t *__restrict__ seg_act,
                                              int64_t capacity, uint32_t *m_dev,
@@ -359,7 +359,7 @@ __device__ __forceinline__ bool block_prefix(const uint32_t *__restrict__ sums,
                                              uint32_t &abase) {
     const bool own = nblocks <= kOwnPrefixBlocks;
     const int n = own ? nblocks : (nblocks + kSegBlocks - 1) / kSegBlocks;
-    const int mine = own ? (int)blockIdx.x : (int)blockIdx.x / kSegBlocks;
+    const int mine = own ? first : first / kSegBlocks;
     unsigned long long pre = 0ull, all = 0ull, apre = 0ull, aall = 0ull;
     for (int b = threadIdx.x; b < n; b += kScanBlock) {
         const unsigned long long c = own ? sums[b] : seg_tot[b];
@@ -390,8 +390,8 @@ __device__ __forceinline__ bool block_prefix(const uint32_t *__restrict__ sums,
     unsigned long long g = s_tot[8] + s_tot[9] + s_tot[10] + s_tot[11];
     unsigned long long ga = s_tot[12] + s_tot[13] + s_tot[14] + s_tot[15];
     if (!own) {   // plus this block's place within its segment
-        g += sums[blockIdx.x];
-        ga += act ? act[blockIdx.x] : 0u;
+        g += sums[first];
+        ga += act ? act[first] : 0u;
     }
     gbase = (uint32_t)min(g, 0xFFFFFFFFull);   // used only when the total fits
     abase = (uint32_t)ga;
@@ -416,7 +416,9 @@ __device__ __forceinline__ bool block_prefix(const uint32_t *__restrict__ sums,
 // visits the records in depth order, gathers one cache line per record.
 // a_dev: their number (0 on overflow).  Also clears the tile ranges
 // (grid-stride).  The per-block totals of counts and of active records come
-// from the projection.
+// from the projection.  The record's own loads are issued before the block's
+// prefix is summed, so that they are in flight while it waits on the totals
+// (nrec >= 1).
 __global__ __launch_bounds__(kScanBlock) void k_scan_rec(
     const uint32_t *__restrict__ count, const uint2 *__restrict__ rect,
     const uint2 *__restrict__ rspan, SplatPtrs sp,
@@ -430,23 +432,26 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_rec(
     uint2 *__restrict__ ranges, int total_tiles, ValPack vp) {
     __shared__ uint32_t s_wave[4];
     __shared__ unsigned long long s_tot[16];
+    const int r = blockIdx.x * kScanTile + threadIdx.x;
+    // every record's entries, with no branch (the lines hold records with
+    // keys anyway; past the end, the last record's, unused)
+    const int rl = min(r, nrec - 1);
+    const uint32_t c = r < nrec ? count[rl] : 0u;
+    const uint2 rc = rect[rl], pk = rspan[rl];
+    const uint32_t dk = depth_key[rl];
     for (int t = blockIdx.x * kScanBlock + threadIdx.x; t < total_tiles; t += gridDim.x * kScanBlock)
         ranges[t] = make_uint2(0u, 0u);
     uint32_t gbase, abase;
-    if (!block_prefix(block_sums, block_act, nblocks, seg_tot, seg_act, capacity, m_dev, m_total,
-                      a_dev, flags, true, s_tot, gbase, abase))
+    if (!block_prefix(block_sums, block_act, nblocks, (int)blockIdx.x, seg_tot, seg_act, capacity,
+                      m_dev, m_total, a_dev, flags, true, s_tot, gbase, abase))
         return;   // overflow: nothing placed, nothing to sort
-    const int r = blockIdx.x * kScanTile + threadIdx.x;
-    const uint32_t c = r < nrec ? count[r] : 0u;
     uint32_t total, atot;
     const uint32_t off = block_excl_scan_256(c, s_wave, total);
     const uint32_t apos = block_excl_scan_256(c != 0u ? 1u : 0u, s_wave, atot);
     const uint32_t first = gbase + off, e = abase + apos;
     if (r < nrec) koff[r] = first;   // every record: whole 64-byte chunks are written
     if (c == 0u) return;
-    const uint2 rc = rect[r];
-    const uint2 pk = rspan[r];
-    dkey[e] = depth_key[r];
+    dkey[e] = dk;
     dval[e] = vp.pack(e, c);
     arec[2 * e] = make_uint4((uint32_t)r, first, c, pk.x);
     arec[2 * e + 1] = make_uint4(rc.x, rc.y, pk.y, 0u);
@@ -538,20 +543,23 @@ __global__ __launch_bounds__(kScanBlock) void k_emit(
     __shared__ int2 s_f0[kMaxViews];          // fovea box origins (compact keys)
     const uint32_t A = *a_dev;
     if ((uint32_t)blockIdx.x * kScanTile >= A) return;   // beyond the active records
+    // the record's entry first, with no branch (past the end: the last one's,
+    // unused), so that its gather is in flight while the block's prefix is summed
+    const uint32_t pos = blockIdx.x * kScanTile + threadIdx.x;
+    const uint32_t e = vp.entry(dval[min(pos, A - 1u)]);
+    uint4 r0 = arec[2 * e], r1 = arec[2 * e + 1];
     if ((int)threadIdx.x < min(nviews, kMaxViews)) s_views[threadIdx.x] = views[threadIdx.x];
     fovea_origins(tm, views, nviews, s_f0);
     uint32_t gbase, abase;
-    if (!block_prefix(block_sums, nullptr, nblocks, seg_tot, nullptr, capacity, nullptr,
+    if (!block_prefix(block_sums, nullptr, nblocks, (int)blockIdx.x, seg_tot, nullptr, capacity, nullptr,
                       const_cast<unsigned long long *>(m_total), nullptr, nullptr, false, s_tot,
                       gbase, abase))
         return;
-    const uint32_t pos = blockIdx.x * kScanTile + threadIdx.x;
-    uint4 r0 = make_uint4(0u, 0u, 0u, 0u), r1 = r0;
     if (pos < A) {
-        const uint32_t e = vp.entry(dval[pos]);
-        r0 = arec[2 * e];
-        r1 = arec[2 * e + 1];
         r1.w = r0.x / (uint32_t)n;   // the record's view, once per record
+    } else {
+        r0 = make_uint4(0u, 0u, 0u, 0u);
+        r1 = r0;
     }
     uint32_t total;
     const uint32_t off = block_excl_scan_256(r0.z, s_wave, total);
