@@ -584,12 +584,11 @@ __device__ __forceinline__ void render_bwd_unit(
         }
         __syncthreads();
         uint64_t hit = 0ull;   // splats of the current block of R some pixel of the wave took
-        // the odd splat of each pair (2 g + 1, 2 g) waits for the even one
-        float accA[9];
-#pragma unroll
-        for (int f = 0; f < 9; f++) accA[f] = -0.f;
-        bool hitA = false;
-        for (int j = nb - 1; j >= 0; j--) {
+        // Splat j's per-lane sums: te dx, te dy, te dx^2, te dx dy, te dy^2 (te =
+        // dL/do, so that o te = dL/dpower), dL/do, dL/dcolour; the opacity and
+        // the conic factors of the mean gradient are applied once per splat when
+        // the sums are flushed.  True if some pixel of the wave took the splat.
+        auto splat_terms = [&](int j, float (&acc)[9]) -> bool {
             const uint32_t pos = bs + (uint32_t)j - rg.x;   // list position in the tile
             const float4 a = s_a[j];
             const float4 b = s_b[j];
@@ -599,12 +598,7 @@ __device__ __forceinline__ void render_bwd_unit(
             const uint32_t qm = QUAD ? __builtin_amdgcn_readfirstlane((uint32_t)s_m[j]) : 0u;
             // row offset of the tile's first row from the mean; block k adds k ROWS
             const float dy0 = splat_dx((float)(ty * T), c.w, a.y);
-            // per lane sums: te dx, te dy, te dx^2, te dx dy, te dy^2 (te = dL/do, so
-            // that o te = dL/dpower), dL/do, dL/dcolour; the opacity and the conic
-            // factors of the mean gradient are applied once per splat when the sums
-            // are flushed
             // (-0 is the exact identity of addition, so the first term needs no add)
-            float acc[9];
 #pragma unroll
             for (int f = 0; f < 9; f++) acc[f] = -0.f;
             bool any = false;
@@ -659,72 +653,87 @@ __device__ __forceinline__ void render_bwd_unit(
                 acc[3] = fmaf(ux, dy, acc[3]);
                 acc[4] = fmaf(uy, dy, acc[4]);
             }
-            // Wave sums of a pair of splats at once (pair_sums); the row
-            // leaders store them into the wave's slots, and the wave notes the
-            // splats some pixel took in its hit mask (a splat none took is
-            // read as zero).  With an odd count the first pair has no odd
-            // splat (accA stays -0).
-            const bool hitj = __any(any);
-            if (j & 1) {
-#pragma unroll
-                for (int f = 0; f < 9; f++) accA[f] = acc[f];
-                hitA = hitj;
-            } else {
-                if (hitA || hitj) {
-                    float out[5];
-                    pair_sums(accA, acc, out);
-                    const int lane = __lane_id();
-                    if ((lane & 15) == 15) {
-                        const int row = lane >> 4, par = row & 1;
-                        const int js = row < 2 ? j + 1 : j;
-                        float *g = s_g + (threadIdx.x >> 6) * GS + (js & (R - 1)) * 9 + par;
-                        g[0] = out[0];
-                        g[2] = out[1];
-                        g[4] = out[2];
-                        g[6] = out[3];
-                        if (!par) g[8] = out[4];
-                    }
-                    if (hitA) hit |= 1ull << ((j + 1) & (R - 1));
-                    if (hitj) hit |= 1ull << (j & (R - 1));
-                }
-                hitA = false;
+            return __any(any);
+        };
+        // Wave sums of the pair of splats (j + 1, j), j even, at once
+        // (pair_sums); the row leaders store them into the wave's slots, and the
+        // wave notes the splats some pixel took in its hit mask (a splat none
+        // took is read as zero).
+        auto store_pair = [&](int j, const float (&accA)[9], bool hitA, const float (&acc)[9],
+                              bool hitj) {
+            if (!(hitA || hitj)) return;
+            float out[5];
+            pair_sums(accA, acc, out);
+            const int lane = __lane_id();
+            if ((lane & 15) == 15) {
+                const int row = lane >> 4, par = row & 1;
+                const int js = row < 2 ? j + 1 : j;
+                float *g = s_g + (threadIdx.x >> 6) * GS + (js & (R - 1)) * 9 + par;
+                g[0] = out[0];
+                g[2] = out[1];
+                g[4] = out[2];
+                g[6] = out[3];
+                if (!par) g[8] = out[4];
             }
-            if ((j & (R - 1)) == 0) {
-                // splats j .. j + R - 1 are done: one lane per splat adds the
-                // waves' sums, applies the conic factors and stores them at the
-                // key's own position (no other workgroup writes it)
-                if (NW > 1) {
-                    if (__lane_id() == 0) s_hit[threadIdx.x >> 6] = hit;
-                    __syncthreads();
-                }
-                const int t = (int)threadIdx.x, jj = j + t;
-                if (t < R && jj < nb) {
-                    float S[9];
-#pragma unroll
-                    for (int f = 0; f < 9; f++) S[f] = 0.f;
-#pragma unroll
-                    for (int w = 0; w < NW; w++) {
-                        const uint64_t hw = NW > 1 ? s_hit[w] : hit;
-                        if (!((hw >> t) & 1ull)) continue;
-#pragma unroll
-                        for (int f = 0; f < 9; f++) S[f] += s_g[w * GS + t * 9 + f];
-                    }
-                    const float A2 = s_a[jj].z, B2 = s_a[jj].w, C2 = s_b[jj].x, o = s_b[jj].y;
-                    const uint32_t q = s_q[jj];
-#pragma unroll
-                    for (int f = 0; f < 5; f++) S[f] *= o;   // te sums -> dL/dpower sums
-                    // dpower/dmean = (A dx + B dy, B dx + C dy) = -ln2 (2 A2 dx + B2 dy, B2 dx + 2 C2 dy);
-                    // dpower/d(A, B, C) = (-dx^2 / 2, -dx dy, -dy^2 / 2)
-                    float4 *g = kp.pg + (size_t)q * kKeyGradF4;
-                    g[0] = make_float4(-kLn2 * (2.f * A2 * S[0] + B2 * S[1]),
-                                           -kLn2 * (B2 * S[0] + 2.f * C2 * S[1]), -0.5f * S[2], -S[3]);
-                    g[1] = make_float4(-0.5f * S[4], S[5], S[6], S[7]);
-                    g[2] = make_float4(S[8], 0.f, 0.f, 0.f);
-                    g[3] = make_float4(0.f, 0.f, 0.f, 0.f);
-                }
-                if (NW > 1) __syncthreads();   // the slots are free again
-                hit = 0ull;
+            if (hitA) hit |= 1ull << ((j + 1) & (R - 1));
+            if (hitj) hit |= 1ull << (j & (R - 1));
+        };
+        // after splat j (even): at a multiple of R, splats j .. j + R - 1 are
+        // done: one lane per splat adds the waves' sums, applies the conic
+        // factors and stores them at the key's own position (no other workgroup
+        // writes it)
+        auto flush = [&](int j) {
+            if ((j & (R - 1)) != 0) return;
+            if (NW > 1) {
+                if (__lane_id() == 0) s_hit[threadIdx.x >> 6] = hit;
+                __syncthreads();
             }
+            const int t = (int)threadIdx.x, jj = j + t;
+            if (t < R && jj < nb) {
+                float S[9];
+#pragma unroll
+                for (int f = 0; f < 9; f++) S[f] = 0.f;
+#pragma unroll
+                for (int w = 0; w < NW; w++) {
+                    const uint64_t hw = NW > 1 ? s_hit[w] : hit;
+                    if (!((hw >> t) & 1ull)) continue;
+#pragma unroll
+                    for (int f = 0; f < 9; f++) S[f] += s_g[w * GS + t * 9 + f];
+                }
+                const float A2 = s_a[jj].z, B2 = s_a[jj].w, C2 = s_b[jj].x, o = s_b[jj].y;
+                const uint32_t q = s_q[jj];
+#pragma unroll
+                for (int f = 0; f < 5; f++) S[f] *= o;   // te sums -> dL/dpower sums
+                // dpower/dmean = (A dx + B dy, B dx + C dy) = -ln2 (2 A2 dx + B2 dy, B2 dx + 2 C2 dy);
+                // dpower/d(A, B, C) = (-dx^2 / 2, -dx dy, -dy^2 / 2)
+                float4 *g = kp.pg + (size_t)q * kKeyGradF4;
+                g[0] = make_float4(-kLn2 * (2.f * A2 * S[0] + B2 * S[1]),
+                                   -kLn2 * (B2 * S[0] + 2.f * C2 * S[1]), -0.5f * S[2], -S[3]);
+                g[1] = make_float4(-0.5f * S[4], S[5], S[6], S[7]);
+                g[2] = make_float4(S[8], 0.f, 0.f, 0.f);
+                g[3] = make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+            if (NW > 1) __syncthreads();   // the slots are free again
+            hit = 0ull;
+        };
+        // back to front by pairs (2 g + 1, 2 g), both splats' sums in registers
+        // of their own; with an odd count the top splat (even) pairs with zeros
+        int j = nb - 1;
+        if (!(j & 1)) {
+            float accA[9], acc[9];
+#pragma unroll
+            for (int f = 0; f < 9; f++) accA[f] = -0.f;
+            const bool hitj = splat_terms(j, acc);
+            store_pair(j, accA, false, acc, hitj);
+            flush(j);
+            j--;
+        }
+        for (; j > 0; j -= 2) {
+            float accA[9], acc[9];
+            const bool hitA = splat_terms(j, accA);
+            const bool hitj = splat_terms(j - 1, acc);
+            store_pair(j - 1, accA, hitA, acc, hitj);
+            flush(j - 1);
         }
         be = bs;
     }
