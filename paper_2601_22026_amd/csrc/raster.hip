@@ -601,7 +601,9 @@ __device__ __forceinline__ void render_bwd_unit(
             // (-0 is the exact identity of addition, so the first term needs no add)
 #pragma unroll
             for (int f = 0; f < 9; f++) acc[f] = -0.f;
-            bool any = false;
+            // some pixel of the wave took the splat: with quadrants, known
+            // (wave-uniform) from the quadrant skip; else from a per-lane flag
+            bool took = false, any = false;
 #pragma unroll
             for (int k = 0; k < PPT; k++) {
                 if (QUAD ? (!((qm >> k) & 1u) || pos >= qmax[k])                     // wave-uniform
@@ -616,7 +618,12 @@ __device__ __forceinline__ void render_bwd_unit(
                 const bool inc = (pos < nc[k]) & !(power2 > 0.f) & !(power2 < c.y);
                 // no pixel of the block takes the splat: every lane would add
                 // zeros and keep its state (wave-uniform)
-                if (QUAD && !__any(inc)) continue;
+                if (QUAD) {
+                    if (!__any(inc)) continue;
+                    took = true;
+                } else {
+                    any |= inc;
+                }
                 // Recomputed transmittance: a pixel the splat does not reach
                 // takes power -inf instead, so exp2 = 0, alpha = 0, 1 / (1 - alpha)
                 // = 1 and its state passes through unchanged bit for bit (Tr x 1,
@@ -624,7 +631,6 @@ __device__ __forceinline__ void render_bwd_unit(
                 const float ex = __builtin_amdgcn_exp2f(MODE == 2 || inc ? power2 : -__builtin_inff());
                 const float ae = b.y * ex;
                 const float alpha = fminf(kAlphaMax, ae);
-                any |= inc;
                 const float inv = __builtin_amdgcn_rcpf(1.f - alpha);   // alpha <= 0.99
                 float Tb;
                 if (MODE == 2)
@@ -653,7 +659,7 @@ __device__ __forceinline__ void render_bwd_unit(
                 acc[3] = fmaf(ux, dy, acc[3]);
                 acc[4] = fmaf(uy, dy, acc[4]);
             }
-            return __any(any);
+            return QUAD ? took : __any(any);
         };
         // Wave sums of the pair of splats (j + 1, j), j even, at once
         // (pair_sums); the row leaders store them into the wave's slots, and the
