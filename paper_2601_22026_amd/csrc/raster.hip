@@ -279,10 +279,15 @@ __global__ __launch_bounds__((fwd_threads<T, SPLIT>())) void k_render_fwd(
     auto composite = [&](uint32_t bs, const float4 *buf) -> bool {
         const float4 *SA = buf, *SB = buf + SEC, *SC = buf + 2 * SEC, *SE = buf + 3 * SEC;
         const int nb = (int)min((uint32_t)B, rg.y - bs);
-        // list entries are the splat's 1-based place in the tile's list (what
-        // last[] records); slot j of the batch is entry j + off
+        // list entries are the byte offset 16 j of the splat's slot j in a
+        // section, which the LDS reads take as their address (the section's
+        // start being the constant part); slot j is the splat's 1-based place
+        // j + off in the tile's list, what last[] records: within the batch the
+        // pixel keeps the offset (lastb, ~0 for none) and converts it at the end
         const int off = (int)(bs - rg.x) + 1;
-        const float4 *SAo = SA - off, *SBo = SB - off, *SCo = SC - off;
+        uint32_t lastb[PPT];
+#pragma unroll
+        for (int k = 0; k < PPT; k++) lastb[k] = ~0u;
         bool done = false;
         // the batch 64 splats at a time: the wave's splats are the set bits of
         // m (with 16-pixel tiles, those whose padded ellipse reaches the wave's
@@ -301,8 +306,8 @@ __global__ __launch_bounds__((fwd_threads<T, SPLIT>())) void k_render_fwd(
             const uint64_t m = __ballot(meet);
             const int cnt = (int)__popcll(m);
             int *list = s_list + wave * kListLen;
-            if (meet) list[lanes_below(m)] = jl + off;
-            if (lane < U) list[cnt + lane] = B + off;
+            if (meet) list[lanes_below(m)] = jl * (int)sizeof(float4);
+            if (lane < U) list[cnt + lane] = B * (int)sizeof(float4);
             for (int g = 0; g < cnt; g += U) {
                 bool all = true;
 #pragma unroll
@@ -312,7 +317,7 @@ __global__ __launch_bounds__((fwd_threads<T, SPLIT>())) void k_render_fwd(
                     break;
                 }
                 const int4 j4 = *(const int4 *)(list + g);
-                const int jj[U] = {j4.x, j4.y, j4.z, j4.w};
+                const uint32_t bo[U] = {(uint32_t)j4.x, (uint32_t)j4.y, (uint32_t)j4.z, (uint32_t)j4.w};
                 // Phase 1: the U splats' alphas are independent of each other and of
                 // the pixel state; computed without branches (skipped splats get
                 // valid = false; every operand is read whatever the outcome).
@@ -320,9 +325,9 @@ __global__ __launch_bounds__((fwd_threads<T, SPLIT>())) void k_render_fwd(
                 float4 c[U];
 #pragma unroll
                 for (int u = 0; u < U; u++) {
-                    a[u] = SAo[jj[u]];
-                    b[u] = SBo[jj[u]];
-                    c[u] = SCo[jj[u]];
+                    a[u] = *(const float4 *)((const char *)SA + bo[u]);
+                    b[u] = *(const float4 *)((const char *)SB + bo[u]);
+                    c[u] = *(const float4 *)((const char *)SC + bo[u]);
                 }
 #pragma unroll
                 for (int k = 0; k < PPT; k++) {
@@ -350,17 +355,20 @@ __global__ __launch_bounds__((fwd_threads<T, SPLIT>())) void k_render_fwd(
                         const bool inc = valid[u] && !(Tn < kTStop);
                         const bool stop = valid[u] && !inc;
                         if (MODE == 2 && inc)
-                            tstore[(size_t)(rg.x - 1u + (uint32_t)jj[u]) * (T * T) + pix[k]] = Tr[k];
+                            tstore[(size_t)(bs + bo[u] / (uint32_t)sizeof(float4)) * (T * T) + pix[k]] = Tr[k];
                         const float w = (inc ? alpha[u] : 0.f) * Tr[k];
                         cr[k] = fmaf(b[u].z, w, cr[k]);
                         cg[k] = fmaf(b[u].w, w, cg[k]);
                         cb[k] = fmaf(c[u].x, w, cb[k]);
                         Tr[k] = inc ? Tn : (stop ? -fabsf(Tr[k]) : Tr[k]);
-                        last[k] = inc ? (uint32_t)jj[u] : last[k];
+                        lastb[k] = inc ? bo[u] : lastb[k];
                     }
                 }
             }
         }
+#pragma unroll
+        for (int k = 0; k < PPT; k++)
+            if (lastb[k] != ~0u) last[k] = lastb[k] / (uint32_t)sizeof(float4) + (uint32_t)off;
         if (CKPT && bs + B < rg.y) {
             float4 *slot = ckpt + (size_t)((bs + B) / B) * (T * T);
 #pragma unroll
