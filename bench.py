@@ -239,20 +239,32 @@ def radix_passes(bits):
 def composited_pixels(cams, gaze, radius_frac, tile):
     """Pixels of the tiles a fovea-culled step composites, back-propagates and
     takes the loss over: per view, the tiles that meet the box of pixel centres
-    within the radius of the gaze point plus one pixel, clipped to the view."""
+    within the radius of the gaze point plus one pixel, clipped to the view,
+    and of those the ones whose rectangle of pixel centres comes within the
+    radius plus one pixel of the gaze point (the box's corners are skipped);
+    the FP32 arithmetic of the kernels' tests."""
     import numpy as np
+    f32 = np.float32
     n = 0
     for c, (gx, gy) in zip(cams, gaze):
-        r = np.float32(radius_frac) * np.float32(c.width)
-        x0 = max(np.floor(gx - r - 0.5) - 1, 0)
-        x1 = min(np.ceil(gx + r - 0.5) + 1, c.width - 1)
-        y0 = max(np.floor(gy - r - 0.5) - 1, 0)
-        y1 = min(np.ceil(gy + r - 0.5) + 1, c.height - 1)
+        gx, gy = f32(gx), f32(gy)
+        r = f32(radius_frac) * f32(c.width)
+        x0 = max(np.floor(gx - r - f32(0.5)) - 1, 0)
+        x1 = min(np.ceil(gx + r - f32(0.5)) + 1, c.width - 1)
+        y0 = max(np.floor(gy - r - f32(0.5)) - 1, 0)
+        y1 = min(np.ceil(gy + r - f32(0.5)) + 1, c.height - 1)
         if x0 > x1 or y0 > y1:
             continue
         tx0, tx1, ty0, ty1 = int(x0) // tile, int(x1) // tile, int(y0) // tile, int(y1) // tile
-        n += ((min((tx1 + 1) * tile, c.width) - tx0 * tile)
-              * (min((ty1 + 1) * tile, c.height) - ty0 * tile))
+        rl = r + f32(1)
+        for ty in range(ty0, ty1 + 1):
+            py0, py1 = f32(ty * tile) + f32(0.5), f32(min((ty + 1) * tile, c.height)) - f32(0.5)
+            dy = max(py0 - gy, gy - py1, f32(0))
+            for tx in range(tx0, tx1 + 1):
+                px0, px1 = f32(tx * tile) + f32(0.5), f32(min((tx + 1) * tile, c.width)) - f32(0.5)
+                dx = max(px0 - gx, gx - px1, f32(0))
+                if dx * dx + dy * dy <= rl * rl:
+                    n += (min((tx + 1) * tile, c.width) - tx * tile) * (min((ty + 1) * tile, c.height) - ty * tile)
     return n
 
 

@@ -156,11 +156,13 @@ gsf_status gsf_plan_destroy(gsf_plan *plan);
  * below 1/255, stopping before transmittance falls under 1e-4; RGB = C + T bg,
  * A = 1 - T).  params: [C][n] (1 <= n <= n_max); cams: [n_views]; out_rgba:
  * concatenated per-view [4][H][W] (caller-owned).  cull_gaze_px: nullable device
- * [n_views][2]; when given (with cull_radius_frac in [0, 4]), only the tiles that
- * meet each view's fovea box (the pixels whose centre can lie within
- * cull_radius_frac * width of the gaze point, plus one pixel) are composited and
- * out_rgba elsewhere is left as it was; a later gsf_loss_l1 with the same gaze
- * then reads only those tiles.  With host_sized = 1 this synchronises the
+ * [n_views][2]; when given (with cull_radius_frac in [0, 4]), only the pixels of
+ * each view's fovea disk (centre within cull_radius_frac * width of the gaze
+ * point, the loss's FP32 mask test) are composited: the other pixels of the
+ * tiles composited are written as background with alpha 0, and the tiles that
+ * cannot hold a pixel of the disk (outside the fovea box, or in its corners
+ * when the box's tiles are fewer than the plan's) may be left as they were; a
+ * later gsf_loss_l1 with the same gaze and radius reads only the disk.  With host_sized = 1 this synchronises the
  * stream once and returns GSF_E_CAPACITY if the key count exceeded the capacity
  * (the image is then background only).  GSF_E_INVALID for null pointers, n out
  * of range or a bad radius; GSF_E_STATE without a workspace. */
@@ -325,11 +327,12 @@ typedef struct gsf_step_args {
     const float *seg_lr;        /* (host) [11 + 3K]: learning rate per parameter plane */
     float beta1, beta2, eps;
     int32_t fovea_cull;         /* 1: with gaze_px, composite and back-propagate only the
-                                   tiles that meet each view's fovea box (the pixels whose
-                                   centre can lie within the mask radius, plus one pixel);
-                                   loss and gradients are those of the full frame (other
-                                   pixels carry no loss); rgba and dl_drgba outside those
-                                   tiles are left as they were.  0: full frames. */
+                                   pixels of each view's fovea disk (the loss's mask), over
+                                   the tiles of its fovea box that can hold one; loss and
+                                   gradients are those of the full frame (other pixels
+                                   carry no loss); rgba outside the disk is background or
+                                   left as it was, as gsf_forward says; dl_drgba outside
+                                   the fovea box is left as it was.  0: full frames. */
     int32_t alpha_loss;         /* 1: target_rgb is RGBA per view ([4][H][W], colour
                                    premultiplied) and the L1 also covers alpha (alpha
                                    training, Method "Periphery Model Training") */
@@ -344,8 +347,8 @@ typedef struct gsf_step_args {
     int32_t masked_adam;        /* 1: visibility-masked Adam (the sparse Adam of Taming
                                    3DGS, on which the paper's optimiser builds): only the
                                    Gaussians that touched at least one tile in some view
-                                   of this step (with fovea_cull: one of the composited
-                                   tiles) take the Adam update; the others keep their
+                                   of this step (with fovea_cull: a tile of the fovea
+                                   boxes) take the Adam update; the others keep their
                                    parameters, m and v.  Bias correction still uses the
                                    shared step counter.  0: every Gaussian is updated. */
 } gsf_step_args;
@@ -515,7 +518,9 @@ gsf_status gsf_plan_set_timing(gsf_plan *plan, int enable);
  * splat) pairs the forward compositing visits (up to and including the splat
  * that stops a pixel, else the whole tile list), out[1] = pairs included in
  * the image, out[2] = pairs the adjoint visits (up to each pixel's last
- * included splat).  Runs an extra counting kernel; not part of the fit step. */
+ * included splat), over the pixels that forward composited (after a
+ * fovea-culled forward: those of the fovea disk; its gaze buffer must still
+ * be valid).  Runs an extra counting kernel; not part of the fit step. */
 gsf_status gsf_count_pairs(gsf_plan *plan, int64_t *out /* (host) [3] */);
 /* Synchronise and return the accumulated milliseconds and call counts per
  * stage (host arrays of GSF_STAGE_COUNT entries; either may be NULL). */
@@ -540,8 +545,8 @@ enum {
                               red, green, blue, camera depth, valid (1 or 0) */
     GSF_DBG_ORDER = 10,    /* uint32 per global tile: compositing order of the tiles (a
                               permutation; tiles with more keys first); after a
-                              fovea-culled forward, the global ids of the tiles it
-                              composited, in that order */
+                              fovea-culled forward, the global ids of its launch
+                              tiles (those of the fovea boxes), in that order */
     GSF_DBG_BG = 11,       /* float [n_views][3]: backgrounds drawn by the last random_bg step */
     GSF_DBG_VIS = 12       /* uint8 [n]: Gaussian visibility of the last masked_adam step */
 };

@@ -347,6 +347,24 @@ __host__ __device__ __forceinline__ FoveaTiles fovea_tiles(const float *__restri
     return f;
 }
 
+// Tile (tx, ty) of a view may hold a pixel of the fovea disk: the nearest point
+// of its rectangle of pixel centres lies within radius_frac * width + 1 of the
+// gaze point.  The pixel of slack covers the rounding of the per-pixel FP32
+// test (the loss's mask), so no tile holding a masked-in pixel is left out; a
+// fovea-culled step composites only these tiles of the fovea box (the box's
+// corners lie outside the disk).
+__host__ __device__ __forceinline__ bool fovea_tile_live(const float *__restrict__ gaze, int v,
+                                                        float radius_frac, int width, int height,
+                                                        int tile, int tx, int ty) {
+    const float r = radius_frac * (float)width + 1.f;
+    const float gx = gaze[2 * v], gy = gaze[2 * v + 1];
+    const float x0 = (float)(tx * tile) + 0.5f, x1 = (float)min((tx + 1) * tile, width) - 0.5f;
+    const float y0 = (float)(ty * tile) + 0.5f, y1 = (float)min((ty + 1) * tile, height) - 0.5f;
+    const float dx = fmaxf(fmaxf(x0 - gx, gx - x1), 0.f);
+    const float dy = fmaxf(fmaxf(y0 - gy, gy - y1), 0.f);
+    return dx * dx + dy * dy <= r * r;
+}
+
 // Sort keys of a fovea-culled forward: only the tiles of each view's fovea box
 // receive keys, so the key is the tile's place in a compact space instead of
 // its global id - view v's box of box x box tiles (from its first fovea tile)
@@ -482,10 +500,13 @@ void launch_render_bwd(hipStream_t s, const RenderArgs &a, const float *dl_drgba
 // Their sum per record into g2d [9][nrec] (every entry written).
 void launch_grad_sum(hipStream_t s, const KeyPlace &kp, int nrec, float *g2d);
 
-// Pair accounting of the last forward: counters[3] (visited, included, adjoint visited).
+// Pair accounting of the last forward: counters[3] (visited, included, adjoint
+// visited), over the tiles and pixels it composited (cull_gaze, nullable: its
+// fovea culling).
 void launch_count_pairs(hipStream_t s, int tile, int total_tiles, const uint2 *ranges,
                         const uint32_t *vals, SplatPtrs sp, const ViewDesc *views, int nviews,
-                        const TileMap &tm, unsigned long long *counters);
+                        const TileMap &tm, const float *cull_gaze, float cull_radius,
+                        unsigned long long *counters);
 
 // Masked L1 loss.  partial: scratch of loss_partials(total_pix) floats.
 int loss_partials(int64_t total_pix);

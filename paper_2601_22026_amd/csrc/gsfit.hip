@@ -106,6 +106,8 @@ struct gsf_plan {
     Buffers b;
     bool have_forward = false;
     bool fwd_culled = false;                  // the last forward composited only fovea tiles
+    const float *fwd_cull_gaze = nullptr;     // its fovea culling (device [V][2]) and radius
+    float fwd_cull_radius = 0.f;
     int64_t fwd_n = 0;
     // the last forward's launch tiles, which ranges and order index: the plan's
     // global tiles, or (fwd_tm.gaze) the compact fovea-box tiles of its keys
@@ -411,6 +413,8 @@ gsf_status enqueue_forward(gsf_plan *p, const float *params, int64_t n, const gs
     GSF_LAUNCHED(ctx);
     p->have_forward = true;
     p->fwd_culled = cull_gaze != nullptr;
+    p->fwd_cull_gaze = cull_gaze;
+    p->fwd_cull_radius = cull_radius;
     p->fwd_n = n;
     return GSF_OK;
 }
@@ -1214,7 +1218,8 @@ gsf_status gsf_count_pairs(gsf_plan *p, int64_t *out) {
     if (!out) return fail(p->ctx, GSF_E_INVALID, "gsf_count_pairs: null output");
     if (!p->have_forward) return fail(p->ctx, GSF_E_STATE, "gsf_count_pairs before gsf_forward");
     launch_count_pairs(p->ctx->stream, p->tile, (int)p->fwd_tiles, p->b.ranges, p->b.vals,
-                       splats(p), p->b.views, p->V, p->fwd_tm, p->b.counters);
+                       splats(p), p->b.views, p->V, p->fwd_tm, p->fwd_cull_gaze,
+                       p->fwd_cull_radius, p->b.counters);
     GSF_LAUNCHED(p->ctx);
     unsigned long long c[3] = {0, 0, 0};
     GSF_HIP(p->ctx, hipStreamSynchronize(p->ctx->stream));

@@ -126,6 +126,15 @@ __device__ __forceinline__ bool launch_tile(uint32_t c, const TileMap &tm,
     return true;
 }
 
+// Pixel (x, y) of view v lies in the fovea disk (the loss's mask): its centre
+// within `radius` pixels of the gaze point, tested in FP32; no gaze: every pixel.
+__device__ __forceinline__ bool in_fovea(const float *__restrict__ gaze, int v, int x, int y,
+                                         float radius) {
+    if (!gaze) return true;
+    const float dx = (float)x + 0.5f - gaze[2 * v], dy = (float)y + 0.5f - gaze[2 * v + 1];
+    return dx * dx + dy * dy <= radius * radius;
+}
+
 // Sum of x over the 64 lanes of a wave, valid in lane 63: four row shifts
 // (DPP row_shr 1, 2, 4, 8) leave each 16-lane row's total in its lane 15, then
 // row_bcast:15 and row_bcast:31 fold the rows together.  All steps are VALU
@@ -238,10 +247,13 @@ __global__ __launch_bounds__((fwd_threads<T, SPLIT>())) void k_render_fwd(
     int v, ty, tx;
     ViewDesc vd;
     if (!launch_tile(ti, tm, views, nviews, T, v, vd, ty, tx)) return;
-    if (cull_gaze && !tm.gaze) {   // fovea culling over global tiles: only tiles meeting the fovea
-        const FoveaTiles f = fovea_tiles(cull_gaze, v, cull_radius, vd.width, vd.height, T);
-        if (tx < f.tx0 || tx > f.tx1 || ty < f.ty0 || ty > f.ty1) return;
-    }
+    // Fovea culling: only the pixels of the fovea disk are composited; the others,
+    // which carry no loss, start stopped (background, no contributor).  Over the
+    // compact fovea-box tiles, a tile that cannot hold a pixel of the disk is not
+    // visited at all (the adjoint skips it alike); over global tiles every tile
+    // is, so that each holds its pixels' state.
+    if (tm.gaze && !fovea_tile_live(tm.gaze, v, tm.radius, vd.width, vd.height, T, tx, ty)) return;
+    const float disk_r = cull_gaze ? cull_radius * (float)vd.width : 0.f;
     const uint2 rg = ranges[ti];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int lx = QUAD ? (quad & 1) * 8 + (lane & 7) : threadIdx.x % T;
@@ -269,7 +281,7 @@ __global__ __launch_bounds__((fwd_threads<T, SPLIT>())) void k_render_fwd(
         px[k] = (float)x;   // integer pixel; its centre's offset from a mean is splat_dx
         py[k] = (float)y;
         pix[k] = (ly + k * ROWS) * T + lx;
-        Tr[k] = x < vd.width && y < vd.height ? 1.f : -1.f;
+        Tr[k] = x < vd.width && y < vd.height && in_fovea(cull_gaze, v, x, y, disk_r) ? 1.f : -1.f;
         cr[k] = cg[k] = cb[k] = 0.f;
         last[k] = 0u;
     }
@@ -489,6 +501,12 @@ __device__ __forceinline__ void render_bwd_unit(
     int v, ty, tx;
     ViewDesc vd;
     launch_tile(ti, tm, views, nviews, T, v, vd, ty, tx);   // a tile with keys: valid
+    // a fovea-culled forward over compact tiles composited only the disk's pixels
+    // of the tiles that may hold some (the others carry no loss): the rest have no
+    // contributor here (over global tiles the forward left them stopped, with no
+    // contributor, which the pixel state says)
+    const bool live = !tm.gaze || fovea_tile_live(tm.gaze, v, tm.radius, vd.width, vd.height, T, tx, ty);
+    const float disk_r = tm.gaze ? tm.radius * (float)vd.width : 0.f;
     const int lane = threadIdx.x & 63;
     const float *bgv = bg ? bg + 3 * v : cams[v].bg;
     const float bg0 = bgv[0], bg1 = bgv[1], bg2 = bgv[2];
@@ -507,7 +525,7 @@ __device__ __forceinline__ void render_bwd_unit(
         const int ly = QUAD ? (k >> 1) * 8 + (lane >> 3) : threadIdx.x / T + k * ROWS;
         pix[k] = ly * T + lx;
         const int x = tx * T + lx, y = ty * T + ly;
-        const bool inside = x < vd.width && y < vd.height;
+        const bool inside = live && x < vd.width && y < vd.height && in_fovea(tm.gaze, v, x, y, disk_r);
         const size_t q = inside ? (size_t)y * vd.width + x : 0;
         px[k] = (float)x;   // integer pixel; its centre's offset from a mean is splat_dx
         py[k] = (float)y;
@@ -853,8 +871,8 @@ __global__ __launch_bounds__(64) void k_grad_sum(KeyPlace kp, int nrec, float *_
 template <int T>
 __global__ __launch_bounds__(T * T < 256 ? T * T : 256) void k_count_pairs(
     const uint2 *__restrict__ ranges, const uint32_t *__restrict__ vals, SplatPtrs sp,
-    const ViewDesc *__restrict__ views, int nviews, TileMap tm,
-    unsigned long long *__restrict__ counters) {
+    const ViewDesc *__restrict__ views, int nviews, TileMap tm, const float *__restrict__ cull_gaze,
+    float cull_radius, unsigned long long *__restrict__ counters) {
     constexpr int NT = T * T < 256 ? T * T : 256;
     constexpr int PPT = T * T / NT;
     constexpr int ROWS = NT / T;
@@ -863,13 +881,17 @@ __global__ __launch_bounds__(T * T < 256 ? T * T : 256) void k_count_pairs(
     __syncthreads();
     int v, ty, tx;
     ViewDesc vd;
-    const bool valid = launch_tile(blockIdx.x, tm, views, nviews, T, v, vd, ty, tx);
+    // the tiles and pixels the compositing kernels take (fovea-culled: the disk's)
+    const bool valid = launch_tile(blockIdx.x, tm, views, nviews, T, v, vd, ty, tx) &&
+                       (!tm.gaze || fovea_tile_live(tm.gaze, v, tm.radius, vd.width, vd.height, T, tx, ty));
+    const float disk_r = cull_gaze ? cull_radius * (float)vd.width : 0.f;
     const uint2 rg = valid ? ranges[blockIdx.x] : make_uint2(0u, 0u);
     unsigned long long visit = 0, incl = 0, visit_bwd = 0;
 #pragma unroll
     for (int k = 0; k < PPT; k++) {
         const int x = tx * T + threadIdx.x % T, y = ty * T + threadIdx.x / T + k * ROWS;
         if (!(x < vd.width && y < vd.height)) continue;
+        if (!in_fovea(cull_gaze, v, x, y, disk_r)) continue;
         const float px = (float)x, py = (float)y;
         float Tr = 1.f;
         uint32_t last = 0;
@@ -909,12 +931,6 @@ __device__ __forceinline__ int view_of_pixel(const ViewDesc *__restrict__ views,
     return v;
 }
 
-__device__ __forceinline__ bool in_fovea(const float *__restrict__ gaze, int v, int x, int y,
-                                         float radius) {
-    if (!gaze) return true;
-    const float dx = (float)x + 0.5f - gaze[2 * v], dy = (float)y + 0.5f - gaze[2 * v + 1];
-    return dx * dx + dy * dy <= radius * radius;
-}
 
 // Blocks per view of a fovea-window loss launch: each view's box x box window
 // is covered by whole blocks, so a block's view is uniform.
@@ -1068,19 +1084,17 @@ __global__ __launch_bounds__(kLossBlock) void k_loss_l1(
         float *g = dl + 4 * (size_t)vd.pix_off;
         const bool in = in_fovea(gaze, v, x, y, radius_frac * (float)vd.width);
         const float inv = 1.f / (float)max(cnt, 1u);
-        // RGBA targets: colour premultiplied, composited over the view background
-        const float ta = tgt_planes == 4 ? tgt[3 * plane + q] : 1.f;
+        // RGBA targets: colour premultiplied, composited over the view background.
+        // A pixel outside the mask reads nothing (a fovea-culled forward did not
+        // composite it) and gets a zero gradient.
+        const float ta = in && tgt_planes == 4 ? tgt[3 * plane + q] : 1.f;
 #pragma unroll
         for (int c = 0; c < 4; c++) {
-            if (c == 3 && !alpha_term) {
-                g[3 * plane + q] = 0.f;
-                continue;
-            }
-            float t = tgt[c * plane + q];
-            if (c < 3 && bg) t = fmaf(1.f - ta, bg[3 * v + c], t);
-            const float d = img[c * plane + q] - t;
             float gv = 0.f;
-            if (in) {
+            if (in && (c < 3 || alpha_term)) {
+                float t = tgt[c * plane + q];
+                if (c < 3 && bg) t = fmaf(1.f - ta, bg[3 * v + c], t);
+                const float d = img[c * plane + q] - t;
                 s += fabsf(d);
                 gv = d > 0.f ? inv : (d < 0.f ? -inv : 0.f);
             }
@@ -1256,14 +1270,15 @@ void launch_grad_sum(hipStream_t s, const KeyPlace &kp, int nrec, float *g2d) {
 
 void launch_count_pairs(hipStream_t s, int tile, int total_tiles, const uint2 *ranges,
                         const uint32_t *vals, SplatPtrs sp, const ViewDesc *views, int nviews,
-                        const TileMap &tm, unsigned long long *counters) {
+                        const TileMap &tm, const float *cull_gaze, float cull_radius,
+                        unsigned long long *counters) {
     k_zero_u64<<<1, 64, 0, s>>>(counters, 3);
     if (tile == 8)
-        k_count_pairs<8><<<total_tiles, 64, 0, s>>>(ranges, vals, sp, views, nviews, tm, counters);
+        k_count_pairs<8><<<total_tiles, 64, 0, s>>>(ranges, vals, sp, views, nviews, tm, cull_gaze, cull_radius, counters);
     else if (tile == 16)
-        k_count_pairs<16><<<total_tiles, 256, 0, s>>>(ranges, vals, sp, views, nviews, tm, counters);
+        k_count_pairs<16><<<total_tiles, 256, 0, s>>>(ranges, vals, sp, views, nviews, tm, cull_gaze, cull_radius, counters);
     else
-        k_count_pairs<32><<<total_tiles, 256, 0, s>>>(ranges, vals, sp, views, nviews, tm, counters);
+        k_count_pairs<32><<<total_tiles, 256, 0, s>>>(ranges, vals, sp, views, nviews, tm, cull_gaze, cull_radius, counters);
 }
 
 // Partial sums of a loss launch: one per block (a fovea-window launch's views

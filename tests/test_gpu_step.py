@@ -270,6 +270,62 @@ def test_autotune_sweeps_and_candidates_render_identically(gs, ctx):
         np.testing.assert_array_equal(imgs[0].view(np.uint32), img.view(np.uint32))
 
 
+def test_fovea_culling_composites_only_the_disk(gs, ctx):
+    """A fovea-culled step composites the pixels of the fovea disk only: over a
+    view whose fovea box holds far more tiles than the disk, the tiles whose
+    pixel centres all lie more than the radius plus two pixels from the gaze
+    point (the box's corners) keep what the image buffer held, every masked-in
+    pixel is written, and the other pixels of the tiles composited are the
+    camera background with alpha 0.  Pair counting covers the same pixels: it
+    visits fewer pairs than over the full frame."""
+    P = synth.random_gaussians(6000, seed=22)
+    cams = [synth.look_at_camera([0.2, -0.3, -3.0], width=512, height=384),
+            synth.look_at_camera([-2.0, 1.2, -2.0], width=384, height=448)]
+    gaze = synth.gaze_points(cams, seed=9)
+    rng = np.random.default_rng(8)
+    tgt = np.concatenate([rng.uniform(0, 1, size=3 * c.npix) for c in cams]).astype(np.float32)
+    gz = torch.from_numpy(np.ascontiguousarray(gaze)).to(DEV)
+    sentinel = np.float32(7.0)
+    pairs = {}
+    for cull in (True, False):
+        cfg = gs.FitConfig(lr=0.0, tile=16, lds_batch=64, fovea_cull=cull)
+        fs = gs.FitStep(ctx, torch.from_numpy(P).to(DEV), cams, torch.from_numpy(tgt).to(DEV), gz,
+                        cfg=cfg, fused=True)
+        fs.rgba.fill_(float(sentinel))
+        fs.step()
+        torch.cuda.synchronize()
+        assert fs.poll()[0] == 0
+        pairs[cull] = fs.plan.count_pairs()
+        if cull:
+            img = fs.rgba.cpu().numpy()
+        fs.plan.close()
+    log(f"[cull] pairs culled {pairs[True]} vs full frame {pairs[False]}")
+    assert pairs[True]["visited_fwd"] < pairs[False]["visited_fwd"]
+    off, skipped = 0, 0
+    for v, c in enumerate(cams):
+        a = img[4 * off:4 * (off + c.npix)].reshape(4, c.height, c.width)
+        ys, xs = np.mgrid[0:c.height, 0:c.width]
+        d2 = (xs + 0.5 - np.float64(gaze[v][0])) ** 2 + (ys + 0.5 - np.float64(gaze[v][1])) ** 2
+        r = 0.2 * c.width
+        inside = d2 <= r * r
+        written = ~(a == sentinel).all(axis=0)
+        assert written[inside].all()
+        for ty in range(0, c.height, 16):
+            for tx in range(0, c.width, 16):
+                t = (slice(ty, ty + 16), slice(tx, tx + 16))
+                if np.sqrt(d2[t].min()) > r + 2.0:      # no pixel centre near the disk
+                    skipped += 1
+                    assert not written[t].any(), (v, tx, ty)
+                elif written[t].any():                   # composited: the disk, else background
+                    out = ~inside[t]
+                    np.testing.assert_array_equal(a[3][t][out], 0.0)
+                    for ch in range(3):
+                        np.testing.assert_array_equal(a[ch][t][out], np.float32(c.bg[ch]))
+        off += c.npix
+    log(f"[cull] tiles left untouched: {skipped}")
+    assert skipped > 0
+
+
 def test_fovea_culling_matches_full_frame(gs, ctx):
     """Fovea culling composites only the tiles that meet each view's fovea:
     in-mask pixels keep their bits, the masked loss and the gradient equal the
