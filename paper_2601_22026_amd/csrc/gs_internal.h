@@ -365,6 +365,35 @@ __host__ __device__ __forceinline__ bool fovea_tile_live(const float *__restrict
     return dx * dx + dy * dy <= r * r;
 }
 
+// Tile columns [c0, c1] of tile row ty clipped to the tiles that can hold a
+// pixel of the fovea disk (false: none remain).  Along a row those tiles form
+// one interval (the distance test is monotone in the column on either side of
+// the gaze point), so the ends move inwards until they pass it.
+__host__ __device__ __forceinline__ bool fovea_row_clip(const float *__restrict__ gaze, int v,
+                                                       float radius_frac, int width, int height,
+                                                       int tile, int ty, int &c0, int &c1) {
+    while (c0 <= c1 && !fovea_tile_live(gaze, v, radius_frac, width, height, tile, c0, ty)) c0++;
+    while (c1 >= c0 && !fovea_tile_live(gaze, v, radius_frac, width, height, tile, c1, ty)) c1--;
+    return c0 <= c1;
+}
+
+// Per view and tile row, the tile columns [lo, hi] that can hold a pixel of the
+// fovea disk (lo > hi: none), the clip of every record's row spans in a
+// fovea-culled step: entry v * rows + ty.  rows = null: no culling.
+struct FoveaRows {
+    const uint2 *rows = nullptr;
+    int per_view = 0;
+};
+// Clip tile columns [c0, c1] of view v's tile row ty to the disk's (false: none
+// remain).  Without culling, unchanged.
+__device__ __forceinline__ bool fovea_rows_clip(const FoveaRows &fr, int v, int ty, int &c0, int &c1) {
+    if (!fr.rows) return c0 <= c1;
+    const uint2 lr = fr.rows[v * fr.per_view + ty];
+    c0 = max(c0, (int)lr.x);
+    c1 = min(c1, (int)lr.y);
+    return c0 <= c1;
+}
+
 // Sort keys of a fovea-culled forward: only the tiles of each view's fovea box
 // receive keys, so the key is the tile's place in a compact space instead of
 // its global id - view v's box of box x box tiles (from its first fovea tile)
@@ -387,15 +416,21 @@ struct TileMap {
 // and the packed row spans of short boxes (other boxes: the number of their
 // rows that list a tile).
 // With cull_gaze (nullable) the rectangle is clipped to the view's
-// fovea tiles (fovea_tiles with cull_radius).  block_sums[b] / block_act[b]
+// fovea tiles (fovea_tiles with cull_radius) and each row's span to the tiles
+// that can hold a pixel of the disk (fr, which launch_fovea_rows must have
+// written for the same gaze and radius).  block_sums[b] / block_act[b]
 // receive the total count / the number of records with a nonzero count among
 // records 256 b .. 256 b + 255 (scan_blocks(nrec) words each), the input of
 // launch_scan_records.
 void launch_project_fwd(hipStream_t s, const float *P, int n, int nviews, int deg,
                         const gsf_camera *cams, const ViewDesc *views, int tile, SplatPtrs sp,
                         uint32_t *depth_key, uint2 *rect, uint32_t *count, uint2 *rspan,
-                        const float *cull_gaze, float cull_radius, uint32_t *block_sums,
-                        uint32_t *block_act);
+                        const float *cull_gaze, float cull_radius, const FoveaRows &fr,
+                        uint32_t *block_sums, uint32_t *block_act);
+// The row table of fovea culling: fr.rows[v * fr.per_view + ty] for every view
+// and tile row up to fr.per_view (rows past a view's last: none).
+void launch_fovea_rows(hipStream_t s, const float *gaze, float radius_frac, const ViewDesc *views,
+                       int nviews, int tile, const FoveaRows &fr);
 
 // Parameter gradient from the per-key screen-space gradients the compositing
 // adjoint left in kp: for SH degrees 0-1 summed per record (wave_key_sum) on
@@ -416,10 +451,12 @@ void launch_project_bwd(hipStream_t s, const float *P, int n, int nviews, int de
 // size), (box x0 | y0 << 16, x1 | y1 << 16, spans.y, 0); their number to a_dev
 // (0 on overflow).  Clears ranges[total_tiles].  block_sums, block_act: the
 // per-256-record totals launch_project_fwd wrote, scanned in place; seg_tot,
-// seg_act: seg_count(nrec) entries of scratch.
+// seg_act: seg_count(nrec) entries of scratch.  fr: as the projection took it
+// (the row tables clip the rows alike).
 void launch_scan_records(hipStream_t s, const uint32_t *count, const uint2 *rect,
                          const uint2 *rspan, SplatPtrs sp, const uint32_t *depth_key, uint32_t *koff,
                          uint2 *rowtab, int nrec, int n, int tile, const ViewDesc *views,
+                         const FoveaRows &fr,
                          uint32_t *block_sums, uint32_t *block_act, unsigned long long *seg_tot,
                          uint32_t *seg_act, uint32_t *m_dev, unsigned long long *m_total,
                          uint32_t *a_dev, uint32_t *flags, int64_t capacity, uint32_t *dkey,

@@ -54,6 +54,7 @@ struct Buffers {
     // per global tile
     uint2 *ranges = nullptr;
     uint32_t *order = nullptr;                   // compositing order of the tiles
+    uint2 *fovea_rows = nullptr;                 // fovea culling: per view and tile row, the disk's columns
     uint32_t *order_counts = nullptr;            // per-workgroup class counts of that order
     // per key (key capacity): two (key, value) buffer pairs.  The active
     // records' (depth, record) pairs are sorted in them first (ending in the
@@ -151,6 +152,13 @@ gsf_status fail(gsf_ctx *ctx, gsf_status st, const std::string &msg) {
 
 int planes_of(int deg) { return 11 + 3 * (deg + 1) * (deg + 1); }
 
+// Tile rows of the tallest view: the rows of the fovea-culling row table per view.
+int fovea_rows_per_view(const gsf_plan *p) {
+    int ty = 1;
+    for (const ViewDesc &vd : p->views) ty = std::max(ty, (int)vd.tiles_y);
+    return ty;
+}
+
 // Carve the workspace (base == nullptr: only measure).  Returns the byte count.
 size_t carve(gsf_plan *p, char *base, Buffers *out) {
     size_t off = 0;
@@ -176,6 +184,7 @@ size_t carve(gsf_plan *p, char *base, Buffers *out) {
     b.arec = (uint4 *)take((size_t)std::min<int64_t>(p->nrec_max, p->cap) * 32);
     b.ranges = (uint2 *)take(T * sizeof(uint2));
     b.order = (uint32_t *)take(T * 4);
+    b.fovea_rows = (uint2 *)take((size_t)p->V * fovea_rows_per_view(p) * sizeof(uint2));
     b.order_counts = (uint32_t *)take((size_t)33 * order_groups(p->total_tiles) * 4);
     b.k0 = (uint32_t *)take((size_t)p->cap * 4);
     b.v0 = (uint32_t *)take((size_t)p->cap * 4);
@@ -335,8 +344,10 @@ gsf_status enqueue_forward(gsf_plan *p, const float *params, int64_t n, const gs
     }
     {   // splats, support boxes and their tile counts, depth keys
         StageTimer t(p, GSF_STAGE_PROJECT);
+        const FoveaRows fr{cull_gaze ? b.fovea_rows : nullptr, fovea_rows_per_view(p)};
+        if (cull_gaze) launch_fovea_rows(s, cull_gaze, cull_radius, b.views, p->V, p->tile, fr);
         launch_project_fwd(s, params, (int)n, p->V, p->deg, cams, b.views, p->tile, splats(p),
-                           b.depth_key, b.rect, b.count, b.rspan, cull_gaze, cull_radius,
+                           b.depth_key, b.rect, b.count, b.rspan, cull_gaze, cull_radius, fr,
                            b.block_sums, b.block_act);
     }
     GSF_LAUNCHED(ctx);
@@ -344,7 +355,9 @@ gsf_status enqueue_forward(gsf_plan *p, const float *params, int64_t n, const gs
         // the device; the records with keys compacted with their depths
         StageTimer t(p, GSF_STAGE_DUPLICATE);
         launch_scan_records(s, b.count, b.rect, b.rspan, splats(p), b.depth_key, b.koff,
-                            b.rowtab, nrec, (int)n, p->tile, b.views, b.block_sums, b.block_act,
+                            b.rowtab, nrec, (int)n, p->tile, b.views,
+                            FoveaRows{cull_gaze ? b.fovea_rows : nullptr, fovea_rows_per_view(p)},
+                            b.block_sums, b.block_act,
                             b.seg_tot, b.seg_act, b.m_dev, b.m_total, b.a_dev, b.flags, p->cap,
                             b.k0, b.v0, b.arec, b.ranges, (int)p->total_tiles);
     }

@@ -235,7 +235,7 @@ __device__ __forceinline__ uint32_t project_gauss(const Gauss &g, const float *s
                                                     uint32_t *__restrict__ count,
                                                     uint2 *__restrict__ rspan,
                                                     const float *__restrict__ cull_gaze,
-                                                    float cull_radius) {
+                                                    float cull_radius, const FoveaRows &fr) {
     constexpr int K = (DEG + 1) * (DEG + 1);
     const int r = v * n + i;
     const gsf_camera &cam = cams[v];
@@ -316,7 +316,7 @@ __device__ __forceinline__ uint32_t project_gauss(const Gauss &g, const float *s
         count[r] = 0u;
         return 0u;
     }
-    if (cull_gaze) {   // only the tiles that meet the fovea are composited
+    if (cull_gaze) {   // only the tiles that meet the fovea are composited (rows clipped below)
         tx0 = max(tx0, (uint32_t)f.tx0);
         tx1 = min(tx1, (uint32_t)f.tx1);
         ty0 = max(ty0, (uint32_t)f.ty0);
@@ -336,7 +336,8 @@ __device__ __forceinline__ uint32_t project_gauss(const Gauss &g, const float *s
     uint32_t packed[2] = {0u, 0u};
     for (uint32_t ty = ty0; ty <= ty1; ty++) {
         int c0, c1;
-        if (row_span(e, (int)ty, tl, vd.width, vd.height, (int)tx0, (int)tx1, c0, c1)) {
+        if (row_span(e, (int)ty, tl, vd.width, vd.height, (int)tx0, (int)tx1, c0, c1) &&
+            fovea_rows_clip(fr, v, (int)ty, c0, c1)) {
             const uint32_t w = (uint32_t)(c1 - c0 + 1);
             cnt += w;
             listed_rows++;
@@ -362,13 +363,13 @@ __device__ __forceinline__ uint32_t project_record(const float *__restrict__ P, 
                                                      uint32_t *__restrict__ count,
                                                      uint2 *__restrict__ rspan,
                                                      const float *__restrict__ cull_gaze,
-                                                     float cull_radius) {
+                                                     float cull_radius, const FoveaRows &fr) {
     const int v = r / n;
     const int i = r - v * n;
     Gauss g;
     load_gauss(P, n, i, g);
     return project_gauss<DEG>(g, nullptr, P, n, v, i, cams, views, tile, sp, depth_key, rect, count,
-                              rspan, cull_gaze, cull_radius);
+                              rspan, cull_gaze, cull_radius, fr);
 }
 
 // Several views, SH degrees 0-1: one thread per Gaussian projects it into every
@@ -386,7 +387,7 @@ __global__ __launch_bounds__(256) void k_project_fwd_views(const float *__restri
                                                            uint32_t *__restrict__ count,
                                                            uint2 *__restrict__ rspan,
                                                            const float *__restrict__ cull_gaze,
-                                                           float cull_radius) {
+                                                           float cull_radius, FoveaRows fr) {
     constexpr int K = (DEG + 1) * (DEG + 1);
     const int i = blockIdx.x * 256 + (int)threadIdx.x;
     if (i >= n) return;
@@ -397,7 +398,7 @@ __global__ __launch_bounds__(256) void k_project_fwd_views(const float *__restri
     for (int k = 0; k < 3 * K; k++) shc[k] = P[(size_t)(11 + k) * n + i];
     for (int v = 0; v < nviews; v++)
         project_gauss<DEG>(g, shc, P, n, v, i, cams, views, tile, sp, depth_key, rect, count, rspan,
-                           cull_gaze, cull_radius);
+                           cull_gaze, cull_radius, fr);
 }
 
 // block_sums[b] / block_act[b]: the total count / the records with a nonzero
@@ -442,12 +443,13 @@ __global__ __launch_bounds__(256) void k_project_fwd(const float *__restrict__ P
                                                      uint32_t *__restrict__ count,
                                                      uint2 *__restrict__ rspan,
                                                      const float *__restrict__ cull_gaze,
-                                                     float cull_radius, uint32_t *__restrict__ block_sums,
+                                                     float cull_radius, FoveaRows fr,
+                                                     uint32_t *__restrict__ block_sums,
                                                      uint32_t *__restrict__ block_act) {
     __shared__ uint32_t s_w[4], s_a[4];
     const int r = blockIdx.x * 256 + (int)threadIdx.x;
     uint32_t c = r < nrec ? project_record<DEG>(P, n, r, cams, views, tile, sp, depth_key, rect, count,
-                                                rspan, cull_gaze, cull_radius)
+                                                rspan, cull_gaze, cull_radius, fr)
                           : 0u;
     const uint32_t a = (uint32_t)__popcll(__ballot(c != 0u));   // records that list a tile
 #pragma unroll
@@ -640,12 +642,31 @@ __global__ __launch_bounds__(128) void k_project_bwd(const float *__restrict__ P
         for (int ch = 0; ch < 3; ch++) put(11 + 3 * k + ch, dsh[k][ch]);
 }
 
+// The row table of fovea culling: per view and tile row, the columns of the
+// tiles that can hold a pixel of the disk (fovea_tile_live, one interval per
+// row), or none (lo > hi).
+__global__ __launch_bounds__(256) void k_fovea_rows(const float *__restrict__ gaze, float radius_frac,
+                                                    const ViewDesc *__restrict__ views, int nviews,
+                                                    int tile, int per_view, uint2 *__restrict__ rows) {
+    const int i = blockIdx.x * 256 + (int)threadIdx.x;
+    if (i >= nviews * per_view) return;
+    const int v = i / per_view, ty = i - v * per_view;
+    const ViewDesc vd = views[v];
+    int c0 = 0, c1 = vd.tiles_x - 1;
+    if (ty >= vd.tiles_y || !fovea_row_clip(gaze, v, radius_frac, vd.width, vd.height, tile, ty, c0, c1)) {
+        c0 = 1;
+        c1 = 0;
+    }
+    rows[i] = make_uint2((uint32_t)c0, (uint32_t)c1);
+}
+
 }  // namespace
 
 void launch_project_fwd(hipStream_t s, const float *P, int n, int nviews, int deg,
                         const gsf_camera *cams, const ViewDesc *views, int tile, SplatPtrs sp,
                         uint32_t *depth_key, uint2 *rect, uint32_t *count, uint2 *rspan,
-                        const float *cull_gaze, float cull_radius, uint32_t *block_sums,
+                        const float *cull_gaze, float cull_radius, const FoveaRows &fr,
+                        uint32_t *block_sums,
                         uint32_t *block_act) {
     const int nrec = n * nviews;
     const dim3 grid((nrec + 255) / 256), block(256);
@@ -653,19 +674,26 @@ void launch_project_fwd(hipStream_t s, const float *P, int n, int nviews, int de
         const dim3 ggrid((n + 255) / 256);
         if (deg == 0)
             k_project_fwd_views<0><<<ggrid, block, 0, s>>>(P, n, nviews, cams, views, tile, sp, depth_key,
-                                                            rect, count, rspan, cull_gaze, cull_radius);
+                                                            rect, count, rspan, cull_gaze, cull_radius, fr);
         else
             k_project_fwd_views<1><<<ggrid, block, 0, s>>>(P, n, nviews, cams, views, tile, sp, depth_key,
-                                                            rect, count, rspan, cull_gaze, cull_radius);
+                                                            rect, count, rspan, cull_gaze, cull_radius, fr);
         k_block_totals<<<(nrec + 1023) / 1024, block, 0, s>>>(count, nrec, block_sums, block_act);
         return;
     }
     switch (deg) {
-    case 0: k_project_fwd<0><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rect, count, rspan, cull_gaze, cull_radius, block_sums, block_act); break;
-    case 1: k_project_fwd<1><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rect, count, rspan, cull_gaze, cull_radius, block_sums, block_act); break;
-    case 2: k_project_fwd<2><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rect, count, rspan, cull_gaze, cull_radius, block_sums, block_act); break;
-    default: k_project_fwd<3><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rect, count, rspan, cull_gaze, cull_radius, block_sums, block_act); break;
+    case 0: k_project_fwd<0><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rect, count, rspan, cull_gaze, cull_radius, fr, block_sums, block_act); break;
+    case 1: k_project_fwd<1><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rect, count, rspan, cull_gaze, cull_radius, fr, block_sums, block_act); break;
+    case 2: k_project_fwd<2><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rect, count, rspan, cull_gaze, cull_radius, fr, block_sums, block_act); break;
+    default: k_project_fwd<3><<<grid, block, 0, s>>>(P, n, nrec, cams, views, tile, sp, depth_key, rect, count, rspan, cull_gaze, cull_radius, fr, block_sums, block_act); break;
     }
+}
+
+void launch_fovea_rows(hipStream_t s, const float *gaze, float radius_frac, const ViewDesc *views,
+                       int nviews, int tile, const FoveaRows &fr) {
+    const int total = nviews * fr.per_view;
+    k_fovea_rows<<<(total + 255) / 256, 256, 0, s>>>(gaze, radius_frac, views, nviews, tile, fr.per_view,
+                                                      const_cast<uint2 *>(fr.rows));
 }
 
 bool project_bwd_sums_keys(int deg) { return deg <= 1; }

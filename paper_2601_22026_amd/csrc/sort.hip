@@ -423,7 +423,7 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_rec(
     const uint32_t *__restrict__ count, const uint2 *__restrict__ rect,
     const uint2 *__restrict__ rspan, SplatPtrs sp,
     const uint32_t *__restrict__ depth_key, uint32_t *__restrict__ koff, uint2 *__restrict__ rowtab,
-    int nrec, int n, int tile, const ViewDesc *__restrict__ views,
+    int nrec, int n, int tile, const ViewDesc *__restrict__ views, FoveaRows fr,
     const uint32_t *__restrict__ block_sums, const uint32_t *__restrict__ block_act, int nblocks,
     const unsigned long long *__restrict__ seg_tot, const uint32_t *__restrict__ seg_act,
     uint32_t *__restrict__ m_dev, unsigned long long *__restrict__ m_total,
@@ -461,12 +461,15 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_rec(
         const float4 ea = *sp.at((uint32_t)r, kRecEll), a = *sp.at((uint32_t)r, kRecA),
                      cc = *sp.at((uint32_t)r, kRecC);
         const Ellipse el{ea.x, ea.y, ea.z, ea.w, sqrtf(ea.y / ea.z), a.x, a.y, (int)cc.z, (int)cc.w};
-        const ViewDesc vd = views[r / n];
+        const int v = r / n;
+        const ViewDesc vd = views[v];
         const int tl = 31 - __clz(tile);
         uint32_t j = 0, pre = 0;
         for (int ty = y0; ty <= y1 && j < pk.x; ty++) {
             int c0, c1;
-            if (!row_span(el, ty, tl, vd.width, vd.height, x0, x1, c0, c1)) continue;
+            if (!row_span(el, ty, tl, vd.width, vd.height, x0, x1, c0, c1) ||
+                !fovea_rows_clip(fr, v, ty, c0, c1))
+                continue;
             rowtab[first + j] = make_uint2((uint32_t)(ty - y0) | ((uint32_t)c0 << 16), pre);
             pre += (uint32_t)(c1 - c0 + 1);
             j++;
@@ -897,7 +900,7 @@ int seg_count(int64_t nrec) {
 void launch_scan_records(hipStream_t s, const uint32_t *count, const uint2 *rect,
                          const uint2 *rspan, SplatPtrs sp, const uint32_t *depth_key, uint32_t *koff,
                          uint2 *rowtab, int nrec, int n, int tile, const ViewDesc *views,
-                         uint32_t *block_sums, uint32_t *block_act, unsigned long long *seg_tot,
+                         const FoveaRows &fr, uint32_t *block_sums, uint32_t *block_act, unsigned long long *seg_tot,
                          uint32_t *seg_act, uint32_t *m_dev, unsigned long long *m_total,
                          uint32_t *a_dev, uint32_t *flags, int64_t capacity, uint32_t *dkey,
                          uint32_t *dval, uint4 *arec, uint2 *ranges, int total_tiles) {
@@ -906,7 +909,7 @@ void launch_scan_records(hipStream_t s, const uint32_t *count, const uint2 *rect
         k_seg_scan<<<(nb + kSegBlocks - 1) / kSegBlocks, kSegBlocks, 0, s>>>(block_sums, block_act, nb,
                                                                             seg_tot, seg_act);
     k_scan_rec<<<nb, kScanBlock, 0, s>>>(count, rect, rspan, sp, depth_key, koff, rowtab, nrec, n,
-                                         tile, views, block_sums, block_act, nb, seg_tot, seg_act,
+                                         tile, views, fr, block_sums, block_act, nb, seg_tot, seg_act,
                                          m_dev, m_total, a_dev, flags, capacity, dkey, dval, arec,
                                          ranges, total_tiles, ValPack(entry_bits(nrec)));
 }

@@ -270,6 +270,20 @@ def test_autotune_sweeps_and_candidates_render_identically(gs, ctx):
         np.testing.assert_array_equal(imgs[0].view(np.uint32), img.view(np.uint32))
 
 
+def _fovea_tile_live(g, radius_frac, cam, tile, tx, ty):
+    """Tile (tx, ty) can hold a pixel of the fovea disk: the nearest point of
+    its rectangle of pixel centres within the radius plus one pixel of the gaze
+    point, in the kernels' FP32 arithmetic."""
+    f = np.float32
+    r = f(radius_frac) * f(cam.width) + f(1)
+    gx, gy = f(g[0]), f(g[1])
+    x0, x1 = f(tx * tile) + f(0.5), f(min((tx + 1) * tile, cam.width)) - f(0.5)
+    y0, y1 = f(ty * tile) + f(0.5), f(min((ty + 1) * tile, cam.height)) - f(0.5)
+    dx = max(max(x0 - gx, gx - x1), f(0))
+    dy = max(max(y0 - gy, gy - y1), f(0))
+    return bool(dx * dx + dy * dy <= r * r)
+
+
 def test_fovea_culling_composites_only_the_disk(gs, ctx):
     """A fovea-culled step composites the pixels of the fovea disk only: over a
     view whose fovea box holds far more tiles than the disk, the tiles whose
@@ -362,8 +376,20 @@ def test_fovea_culling_matches_full_frame(gs, ctx):
     np.testing.assert_array_equal(r1[:, 1], np.searchsorted(k1, np.arange(T), "right"))
     assert np.unique(o1).size == o1.size and set(np.unique(k1)) <= set(o1.tolist())
     assert o1.size < T
+    # a launch tile that can hold a pixel of the disk lists what the full frame
+    # lists there; the box's other tiles list nothing
+    tile_off = np.cumsum([0] + [((c.width + 15) // 16) * ((c.height + 15) // 16) for c in cams])
+    live_tiles = 0
     for t in o1:
-        np.testing.assert_array_equal(v1[r1[t, 0]:r1[t, 1]], v0[r0[t, 0]:r0[t, 1]])
+        v = int(np.searchsorted(tile_off, t, "right") - 1)
+        c = cams[v]
+        ty, tx = divmod(int(t - tile_off[v]), (c.width + 15) // 16)
+        if _fovea_tile_live(gaze[v], 0.2, c, 16, tx, ty):
+            live_tiles += 1
+            np.testing.assert_array_equal(v1[r1[t, 0]:r1[t, 1]], v0[r0[t, 0]:r0[t, 1]])
+        else:
+            assert r1[t, 0] == r1[t, 1], (v, tx, ty)
+    assert 0 < live_tiles < o1.size
     log(f"[cull] loss {l0:.7f} vs {l1:.7f}, keys {m0} -> {m1}")
     assert m1 < m0
     assert abs(l1 - l0) <= 1e-6 * abs(l0)
