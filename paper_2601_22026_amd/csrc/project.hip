@@ -12,6 +12,7 @@
 // One thread per record (view v, Gaussian i) in the forward pass; one thread
 // per Gaussian looping over views in the backward pass (no atomics).  Parameter
 // planes are read coalesced across i.
+#include <climits>
 #include "gs_internal.h"
 
 namespace gsf {
@@ -644,20 +645,28 @@ __global__ __launch_bounds__(128) void k_project_bwd(const float *__restrict__ P
 
 // The row table of fovea culling: per view and tile row, the columns of the
 // tiles that can hold a pixel of the disk (fovea_tile_live, one interval per
-// row), or none (lo > hi).
+// row: its first and last), or none (lo > hi).  One wave per row, a lane per
+// column.
 __global__ __launch_bounds__(256) void k_fovea_rows(const float *__restrict__ gaze, float radius_frac,
                                                     const ViewDesc *__restrict__ views, int nviews,
                                                     int tile, int per_view, uint2 *__restrict__ rows) {
-    const int i = blockIdx.x * 256 + (int)threadIdx.x;
+    const int i = blockIdx.x * 4 + (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
     if (i >= nviews * per_view) return;
     const int v = i / per_view, ty = i - v * per_view;
     const ViewDesc vd = views[v];
-    int c0 = 0, c1 = vd.tiles_x - 1;
-    if (ty >= vd.tiles_y || !fovea_row_clip(gaze, v, radius_frac, vd.width, vd.height, tile, ty, c0, c1)) {
-        c0 = 1;
-        c1 = 0;
+    int lo = INT_MAX, hi = -1;
+    if (ty < vd.tiles_y) {
+        for (int t0 = 0; t0 < vd.tiles_x; t0 += 64) {
+            const int tx = t0 + lane;
+            const uint64_t m =
+                __ballot(tx < vd.tiles_x && fovea_tile_live(gaze, v, radius_frac, vd.width, vd.height, tile, tx, ty));
+            if (m) {
+                lo = min(lo, t0 + __builtin_ctzll(m));
+                hi = t0 + 63 - __builtin_clzll(m);
+            }
+        }
     }
-    rows[i] = make_uint2((uint32_t)c0, (uint32_t)c1);
+    if (lane == 0) rows[i] = hi >= 0 ? make_uint2((uint32_t)lo, (uint32_t)hi) : make_uint2(1u, 0u);
 }
 
 }  // namespace
@@ -691,9 +700,9 @@ void launch_project_fwd(hipStream_t s, const float *P, int n, int nviews, int de
 
 void launch_fovea_rows(hipStream_t s, const float *gaze, float radius_frac, const ViewDesc *views,
                        int nviews, int tile, const FoveaRows &fr) {
-    const int total = nviews * fr.per_view;
-    k_fovea_rows<<<(total + 255) / 256, 256, 0, s>>>(gaze, radius_frac, views, nviews, tile, fr.per_view,
-                                                      const_cast<uint2 *>(fr.rows));
+    const int total = nviews * fr.per_view;   // one wave per row, four per workgroup
+    k_fovea_rows<<<(total + 3) / 4, 256, 0, s>>>(gaze, radius_frac, views, nviews, tile, fr.per_view,
+                                                  const_cast<uint2 *>(fr.rows));
 }
 
 bool project_bwd_sums_keys(int deg) { return deg <= 1; }
