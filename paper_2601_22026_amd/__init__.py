@@ -139,8 +139,8 @@ class Plan:
 
     # -- raw calls (tensors in, status checked) ------------------------------------
     def forward(self, params, n, cams_dev, out_rgba, cull_gaze=None, cull_radius_frac=0.0):
-        """gsf_forward; with cull_gaze ([V][2] device) only the tiles meeting each
-        view's fovea are composited."""
+        """gsf_forward; with cull_gaze ([V][2] device) only the pixels of each
+        view's fovea disk are composited (the rest of their tiles as background)."""
         self.ctx.use_stream()
         self.ctx.check(lib().gsf_forward(self.handle, _ptr(params), int(n), _ptr(cams_dev),
                                          _ptr(cull_gaze), float(cull_radius_frac), _ptr(out_rgba)),
@@ -327,7 +327,7 @@ class FitConfig:
     radius_frac: float = 0.2
     key_capacity: int = 0
     t_mode: int = 1          # adjoint transmittance of the fused step: 0 recomputed, 1 checkpointed, 2 stored
-    fovea_cull: bool = False  # fused step with a gaze: composite only the tiles that meet the fovea
+    fovea_cull: bool = False  # fused step with a gaze: composite only the fovea disks' pixels
     alpha_loss: bool = False  # targets are RGBA ([4][H][W] per view) and the L1 covers alpha
     random_bg: bool = False   # fused step: a new background per view each step (needs alpha_loss)
     bg_seed: int = 0
