@@ -536,7 +536,10 @@ __device__ __forceinline__ void render_bwd_unit(
             g1[k] = dimg[plane + q];
             g2[k] = dimg[2 * plane + q];
             gA[k] = dimg[3 * plane + q];
-        } else {
+        }
+        // a pixel no splat reached passes no gradient, whatever its dL/dimage
+        // (which a fovea-culled loss may not have written): it starts at zero
+        if (!inside || nc[k] == 0u) {
             Tf[k] = 1.f;
             nc[k] = 0u;
             g0[k] = g1[k] = g2[k] = gA[k] = 0.f;
