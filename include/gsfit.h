@@ -181,7 +181,9 @@ gsf_status gsf_forward(gsf_plan *plan, const float *params, int64_t n, const gsf
  * plans, e.g. one plan per view; see gsf_loss_count).  accumulate: 0 = loss[0]
  * = this plan's mean, 1 = loss[0] += it.  Writes the loss to loss[0] (device)
  * and dL/dRGBA (sign / count; alpha plane zero) to dl_drgba (concatenated
- * per-view [4][H][W]).  A non-finite loss sets GSF_FLAG_NONFINITE.
+ * per-view [4][H][W]); after a fovea-culled gsf_forward on this plan (same gaze
+ * and radius), only the masked-in pixels of dl_drgba are written (gsf_backward
+ * reads no other).  A non-finite loss sets GSF_FLAG_NONFINITE.
  * GSF_E_INVALID for null pointers, a bad radius, norm_count outside
  * [0, 2^32 - 1] or accumulate not 0/1. */
 gsf_status gsf_loss_l1(gsf_plan *plan, const float *rgba, const float *target_rgb,
@@ -332,7 +334,7 @@ typedef struct gsf_step_args {
                                    gradients are those of the full frame (other pixels
                                    carry no loss); rgba outside the disk is background or
                                    left as it was, as gsf_forward says; dl_drgba outside
-                                   the fovea box is left as it was.  0: full frames. */
+                                   the disk is left as it was.  0: full frames. */
     int32_t alpha_loss;         /* 1: target_rgb is RGBA per view ([4][H][W], colour
                                    premultiplied) and the L1 also covers alpha (alpha
                                    training, Method "Periphery Model Training") */

@@ -1096,19 +1096,23 @@ __global__ __launch_bounds__(kLossBlock) void k_loss_l1(
         const float inv = 1.f / (float)max(cnt, 1u);
         // RGBA targets: colour premultiplied, composited over the view background.
         // A pixel outside the mask reads nothing (a fovea-culled forward did not
-        // composite it) and gets a zero gradient.
+        // composite it) and gets a zero gradient - written only on full frames:
+        // after a fovea-culled forward (box > 0) the adjoint does not read it
+        // (no splat reached the pixel).
         const float ta = in && tgt_planes == 4 ? tgt[3 * plane + q] : 1.f;
+        if (in || !box) {
 #pragma unroll
-        for (int c = 0; c < 4; c++) {
-            float gv = 0.f;
-            if (in && (c < 3 || alpha_term)) {
-                float t = tgt[c * plane + q];
-                if (c < 3 && bg) t = fmaf(1.f - ta, bg[3 * v + c], t);
-                const float d = img[c * plane + q] - t;
-                s += fabsf(d);
-                gv = d > 0.f ? inv : (d < 0.f ? -inv : 0.f);
+            for (int c = 0; c < 4; c++) {
+                float gv = 0.f;
+                if (in && (c < 3 || alpha_term)) {
+                    float t = tgt[c * plane + q];
+                    if (c < 3 && bg) t = fmaf(1.f - ta, bg[3 * v + c], t);
+                    const float d = img[c * plane + q] - t;
+                    s += fabsf(d);
+                    gv = d > 0.f ? inv : (d < 0.f ? -inv : 0.f);
+                }
+                g[c * plane + q] = gv;
             }
-            g[c * plane + q] = gv;
         }
     }
 #pragma unroll
