@@ -934,6 +934,8 @@ __global__ void k_zero_u64(unsigned long long *p, int n) {
 // ---- loss -----------------------------------------------------------------------
 
 constexpr int kLossBlock = 256;
+constexpr int kLossPx = 4;                         // pixels per thread of a loss launch
+constexpr int kLossSpan = kLossBlock * kLossPx;    // pixels per block
 
 __device__ __forceinline__ int view_of_pixel(const ViewDesc *__restrict__ views, int nviews, uint32_t p) {
     int v = 0;
@@ -945,12 +947,12 @@ __device__ __forceinline__ int view_of_pixel(const ViewDesc *__restrict__ views,
 // Blocks per view of a fovea-window loss launch: each view's box x box window
 // is covered by whole blocks, so a block's view is uniform.
 __host__ __device__ __forceinline__ int loss_blocks_per_view(int box) {
-    return (box * box + kLossBlock - 1) / kLossBlock;
+    return (box * box + kLossSpan - 1) / kLossSpan;
 }
 
-// Pixel (block bi, thread t) of a loss launch: every pixel of every view
-// (box == 0: pixel bi kLossBlock + t), or in view bi / bpv the pixel
-// (bi mod bpv) kLossBlock + t of its box x box window, which starts at its
+// Pixel t (< kLossSpan) of block bi of a loss launch: every pixel of every view
+// (box == 0: pixel bi kLossSpan + t), or in view bi / bpv the pixel
+// (bi mod bpv) kLossSpan + t of its box x box window, which starts at its
 // first fovea tile (fovea culling; false for window pixels outside the view or
 // past its last fovea tile).  f: the view's fovea tiles (box mode, computed once
 // per block by the caller).  Plans hold fewer than 2^31 pixels: 32-bit
@@ -960,7 +962,7 @@ __device__ __forceinline__ bool loss_pixel(uint32_t bi, uint32_t t, uint32_t tot
                                            const ViewDesc *__restrict__ views, int nviews, int &v,
                                            int &x, int &y) {
     if (box == 0) {
-        const uint32_t p = bi * kLossBlock + t;
+        const uint32_t p = bi * kLossSpan + t;
         if (p >= total_pix) return false;
         v = view_of_pixel(views, nviews, p);
         const ViewDesc vd = views[v];
@@ -972,7 +974,7 @@ __device__ __forceinline__ bool loss_pixel(uint32_t bi, uint32_t t, uint32_t tot
     const int bpv = loss_blocks_per_view(box);
     v = (int)(bi / (uint32_t)bpv);
     if (v >= nviews || f.tx0 > f.tx1) return false;
-    const uint32_t l = (bi - (uint32_t)v * (uint32_t)bpv) * kLossBlock + t;
+    const uint32_t l = (bi - (uint32_t)v * (uint32_t)bpv) * kLossSpan + t;
     if (l >= (uint32_t)(box * box)) return false;
     // l / box by a float reciprocal: exact, since l < 2^23 and box < 2^12 keep the
     // quotient's fraction at least 1 / (2 box) from an integer
@@ -1084,34 +1086,38 @@ __global__ __launch_bounds__(kLossBlock) void k_loss_l1(
     const FoveaTiles f = box ? block_fovea(blockIdx.x, box, tile, gaze, radius_frac, views, nviews, &s_f)
                              : FoveaTiles{1, 0, 1, 0};
     float s = 0.f;
-    int v, x, y;
-    if (loss_pixel(blockIdx.x, threadIdx.x, (uint32_t)total_pix, box, tile, f, views, nviews, v, x, y)) {
-        const ViewDesc vd = views[v];
-        const int q = y * vd.width + x;
-        const size_t plane = (size_t)vd.width * vd.height;
-        const float *img = rgba + 4 * (size_t)vd.pix_off;
-        const float *tgt = target + (size_t)tgt_planes * vd.pix_off;
-        float *g = dl + 4 * (size_t)vd.pix_off;
-        const bool in = in_fovea(gaze, v, x, y, radius_frac * (float)vd.width);
-        const float inv = 1.f / (float)max(cnt, 1u);
-        // RGBA targets: colour premultiplied, composited over the view background.
-        // A pixel outside the mask reads nothing (a fovea-culled forward did not
-        // composite it) and gets a zero gradient - written only on full frames:
-        // after a fovea-culled forward (box > 0) the adjoint does not read it
-        // (no splat reached the pixel).
-        const float ta = in && tgt_planes == 4 ? tgt[3 * plane + q] : 1.f;
-        if (in || !box) {
+    const float inv = 1.f / (float)max(cnt, 1u);
+    // kLossPx pixels per thread, kLossBlock apart (each step coalesced)
+    for (int k = 0; k < kLossPx; k++) {
+        int v, x, y;
+        if (loss_pixel(blockIdx.x, (uint32_t)(k * kLossBlock) + threadIdx.x, (uint32_t)total_pix, box, tile, f,
+                       views, nviews, v, x, y)) {
+            const ViewDesc vd = views[v];
+            const int q = y * vd.width + x;
+            const size_t plane = (size_t)vd.width * vd.height;
+            const float *img = rgba + 4 * (size_t)vd.pix_off;
+            const float *tgt = target + (size_t)tgt_planes * vd.pix_off;
+            float *g = dl + 4 * (size_t)vd.pix_off;
+            const bool in = in_fovea(gaze, v, x, y, radius_frac * (float)vd.width);
+            // RGBA targets: colour premultiplied, composited over the view background.
+            // A pixel outside the mask reads nothing (a fovea-culled forward did not
+            // composite it) and gets a zero gradient - written only on full frames:
+            // after a fovea-culled forward (box > 0) the adjoint does not read it
+            // (no splat reached the pixel).
+            const float ta = in && tgt_planes == 4 ? tgt[3 * plane + q] : 1.f;
+            if (in || !box) {
 #pragma unroll
-            for (int c = 0; c < 4; c++) {
-                float gv = 0.f;
-                if (in && (c < 3 || alpha_term)) {
-                    float t = tgt[c * plane + q];
-                    if (c < 3 && bg) t = fmaf(1.f - ta, bg[3 * v + c], t);
-                    const float d = img[c * plane + q] - t;
-                    s += fabsf(d);
-                    gv = d > 0.f ? inv : (d < 0.f ? -inv : 0.f);
+                for (int c = 0; c < 4; c++) {
+                    float gv = 0.f;
+                    if (in && (c < 3 || alpha_term)) {
+                        float t = tgt[c * plane + q];
+                        if (c < 3 && bg) t = fmaf(1.f - ta, bg[3 * v + c], t);
+                        const float d = img[c * plane + q] - t;
+                        s += fabsf(d);
+                        gv = d > 0.f ? inv : (d < 0.f ? -inv : 0.f);
+                    }
+                    g[c * plane + q] = gv;
                 }
-                g[c * plane + q] = gv;
             }
         }
     }
@@ -1220,14 +1226,12 @@ void render_fwd_tbs(hipStream_t s, const RenderArgs &a, float *out) {
 // most kSplitTilesPerCu tiles per compute unit: measured on one 1024^2 view
 // (4096 tiles) it shortens the forward by 5%, on 16 views of 1920^2 (230k
 // tiles) it lengthens it by 2.5% and on 8 views of 0.25-4 Mpix (63k tiles)
-// by 6-18%.  A fovea-culled forward over compact tiles is split too: the
-// quadrants outside the disk then exit at once, without staging a batch or
-// waiting at a barrier for the others (16 views of 1920^2: 910 -> 886 us).
+// by 6-18%.
 constexpr int kSplitTilesPerCu = 16;
 
 template <int T, int B>
 void render_fwd_tb(hipStream_t s, const RenderArgs &a, float *out) {
-    if (T == 16 && ((int64_t)a.total_tiles <= (int64_t)kSplitTilesPerCu * a.cus || a.tm.gaze))
+    if (T == 16 && (int64_t)a.total_tiles <= (int64_t)kSplitTilesPerCu * a.cus)
         render_fwd_tbs<T, B, T == 16>(s, a, out);
     else
         render_fwd_tbs<T, B, false>(s, a, out);
@@ -1304,7 +1308,7 @@ int loss_partials(int64_t total_pix) {
 }
 
 int loss_launch_blocks(int64_t total_pix, int nviews, int box) {
-    return box ? nviews * loss_blocks_per_view(box) : (int)((total_pix + kLossBlock - 1) / kLossBlock);
+    return box ? nviews * loss_blocks_per_view(box) : (int)((total_pix + kLossSpan - 1) / kLossSpan);
 }
 
 void launch_loss_l1(hipStream_t s, const float *rgba, const float *target, const float *gaze,

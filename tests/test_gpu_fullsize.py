@@ -160,7 +160,14 @@ def test_foveal_workload(ctx, t_mode):
         pix = np.sort(rng.choice(covered if covered.size >= 24 else inside, 24, replace=False))
         ref = oracle.render(P, cam, pixels=pix)
         nbad, worst, nflag = image_close(img[:, pix], ref.rgba, ref.flags)
-        log(f"[full]   view {v}: {pix.size} in-fovea px, worst {worst:.2e}, flagged {nflag}")
+        log(f"[full]   view {v}: {pix.size} in-fovea px ({covered.size} covered), worst {worst:.2e}, "
+            f"flagged {nflag}")
+        if nbad:
+            bad = np.nonzero((np.abs(img[:, pix] - ref.rgba) > 1e-4 * np.abs(ref.rgba) + 1e-6).any(axis=0)
+                             & (ref.flags == 0))[0]
+            for b in bad:
+                log(f"[full]     pixel {pix[b]} (x {pix[b] % cam.width}, y {pix[b] // cam.width}): "
+                    f"gpu {img[:, pix[b]]} oracle {ref.rgba[:, b]}")
         assert nbad == 0, (v, worst)
         keep = pix[ref.flags == 0]
         d = np.zeros((4, npx), np.float32)
