@@ -95,6 +95,56 @@ def test_graph_replay_equals_eager(gs, ctx):
         assert flags == 0 and m > 0
 
 
+def test_culled_step_replays_are_bitwise_identical(gs, ctx):
+    """The fovea-culled multi-view step is deterministic: four replays of the
+    captured step (lr = 0, the image buffer refilled between them) give the
+    eager step's bits in every masked-in pixel, its loss, and gradients equal
+    to each other bit for bit."""
+    P = synth.random_gaussians(20000, seed=23, logscale_mean=synth.scaled_logscale_mean(20000))
+    cams = [synth.look_at_camera([0.2, -0.3, -3.0], width=512, height=384),
+            synth.look_at_camera([-2.0, 1.2, -2.0], width=384, height=448),
+            synth.look_at_camera([2.4, 0.5, 1.6], width=448, height=448)]
+    gaze = synth.gaze_points(cams, seed=10)
+    gz = torch.from_numpy(np.ascontiguousarray(gaze)).to(DEV)
+    rng = np.random.default_rng(9)
+    tgt = torch.from_numpy(np.concatenate([rng.uniform(0, 1, size=3 * c.npix)
+                                           for c in cams]).astype(np.float32)).to(DEV)
+    masks = []
+    for v, c in enumerate(cams):
+        ys, xs = np.divmod(np.arange(c.npix), c.width)
+        dx = (xs + np.float32(0.5) - gaze[v][0]).astype(np.float32)
+        dy = (ys + np.float32(0.5) - gaze[v][1]).astype(np.float32)
+        r = np.float32(0.2) * np.float32(c.width)
+        masks.append(np.tile(dx * dx + dy * dy <= r * r, 4))
+    inside = np.concatenate(masks)
+    cfg = gs.FitConfig(lr=0.0, tile=16, lds_batch=64, t_mode=0, fovea_cull=True)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        eager = gs.FitStep(ctx, torch.from_numpy(P).to(DEV), cams, tgt, gz, cfg=cfg, fused=True)
+        eager.step()
+        torch.cuda.synchronize()
+        img0, l0 = eager.rgba.cpu().numpy(), eager.loss.item()
+        eager.close()
+        cap = gs.FitStep(ctx, torch.from_numpy(P).to(DEV), cams, tgt, gz, cfg=cfg, fused=True)
+        cap.capture()
+        g_first = None
+        for k in range(4):
+            cap.rgba.fill_(float(k + 3))
+            cap.replay()
+            torch.cuda.synchronize()
+            img = cap.rgba.cpu().numpy()
+            np.testing.assert_array_equal(img[inside].view(np.uint32), img0[inside].view(np.uint32))
+            assert cap.loss.item() == l0
+            g = cap.grads.cpu().numpy()
+            if g_first is None:
+                g_first = g
+            np.testing.assert_array_equal(g.view(np.uint32), g_first.view(np.uint32))
+        flags, m = cap.poll()
+        assert flags == 0 and m > 0
+        log(f"[cull] 4 replays bitwise equal, keys {m}, loss {l0:.7f}")
+        cap.close()
+
+
 def test_fit_loss_curve_matches_oracle(gs, ctx):
     """Ten fit steps of the 1,000-Gaussian single-view workload: the GPU loss
     curve follows the FP64 oracle's within 1e-3 relative."""
