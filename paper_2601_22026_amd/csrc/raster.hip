@@ -300,7 +300,12 @@ __global__ __launch_bounds__((fwd_threads<T, SPLIT>())) void k_render_fwd(
         uint32_t lastb[PPT];
 #pragma unroll
         for (int k = 0; k < PPT; k++) lastb[k] = ~0u;
-        bool done = false;
+        // a wave whose pixels have all stopped (or start outside the disk or
+        // the image) skips the batch: no quadrant tests, no list
+        bool stopped = true;
+#pragma unroll
+        for (int k = 0; k < PPT; k++) stopped &= !(Tr[k] > 0.f);
+        bool done = __all(stopped);
         // the batch 64 splats at a time: the wave's splats are the set bits of
         // m (with 16-pixel tiles, those whose padded ellipse reaches the wave's
         // quadrant)
