@@ -390,11 +390,13 @@ def test_fovea_culling_composites_only_the_disk(gs, ctx):
     assert skipped > 0
 
 
-def test_fovea_culling_matches_full_frame(gs, ctx):
-    """Fovea culling composites only the tiles that meet each view's fovea:
-    in-mask pixels keep their bits, the masked loss and the gradient equal the
-    full-frame step's, with fewer keys; the loss also equals the oracle's on
-    the same image."""
+@pytest.mark.parametrize("tile,t_mode", [(16, 0), (8, 1), (32, 0)])
+def test_fovea_culling_matches_full_frame(gs, ctx, tile, t_mode):
+    """Fovea culling composites only the fovea disks' pixels: in-mask pixels
+    keep their bits, the masked loss and the gradient equal the full-frame
+    step's, with fewer keys; the loss also equals the oracle's on the same
+    image.  Tiles of 8, 16 and 32 pixels, recomputed and checkpointed
+    transmittance."""
     P = synth.random_gaussians(3000, seed=21)
     cams = [synth.look_at_camera([0.3, -0.2, -3.0], width=224, height=160),
             synth.look_at_camera([2.5, 1.0, 1.0], width=160, height=208)]
@@ -405,7 +407,7 @@ def test_fovea_culling_matches_full_frame(gs, ctx):
     gz = torch.from_numpy(np.ascontiguousarray(gaze)).to(DEV)
     runs, lists = {}, {}
     for cull in (False, True):
-        cfg = gs.FitConfig(lr=0.0, tile=16, lds_batch=64, fovea_cull=cull)
+        cfg = gs.FitConfig(lr=0.0, tile=tile, lds_batch=64, t_mode=t_mode, fovea_cull=cull)
         fs = gs.FitStep(ctx, torch.from_numpy(P).to(DEV), cams, tgt_dev, gz, cfg=cfg, fused=True)
         fs.step()
         torch.cuda.synchronize()
@@ -428,13 +430,14 @@ def test_fovea_culling_matches_full_frame(gs, ctx):
     assert o1.size < T
     # a launch tile that can hold a pixel of the disk lists what the full frame
     # lists there; the box's other tiles list nothing
-    tile_off = np.cumsum([0] + [((c.width + 15) // 16) * ((c.height + 15) // 16) for c in cams])
+    tile_off = np.cumsum([0] + [((c.width + tile - 1) // tile) * ((c.height + tile - 1) // tile)
+                                for c in cams])
     live_tiles = 0
     for t in o1:
         v = int(np.searchsorted(tile_off, t, "right") - 1)
         c = cams[v]
-        ty, tx = divmod(int(t - tile_off[v]), (c.width + 15) // 16)
-        if _fovea_tile_live(gaze[v], 0.2, c, 16, tx, ty):
+        ty, tx = divmod(int(t - tile_off[v]), (c.width + tile - 1) // tile)
+        if _fovea_tile_live(gaze[v], 0.2, c, tile, tx, ty):
             live_tiles += 1
             np.testing.assert_array_equal(v1[r1[t, 0]:r1[t, 1]], v0[r0[t, 0]:r0[t, 1]])
         else:
