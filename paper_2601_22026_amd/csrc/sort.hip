@@ -343,8 +343,9 @@ __global__ __launch_bounds__(kSegBlocks) void k_seg_scan(uint32_t *__restrict__ 
 
 // The first offsets of scan block `first` (a workgroup's first block of 256
 // records) and the totals: with at most kOwnPrefixBlocks blocks each workgroup
-// sums the totals of the blocks before it itself; otherwise k_seg_scan has scanned each segment in place and the block
-// adds the totals of the segments before its own.  With `publish`, block 0
+// sums the totals of the blocks before it itself; otherwise k_seg_scan has
+// scanned each segment in place and the workgroup adds the totals of the
+// segments before its own.  With `publish`, block 0
 // writes the totals (m_total; m_dev = key total, 0 on overflow with
 // GSF_FLAG_CAPACITY; a_dev = active records, 0 on overflow).  Returns false on
 // a key overflow.
@@ -900,8 +901,8 @@ int seg_count(int64_t nrec) {
 void launch_scan_records(hipStream_t s, const uint32_t *count, const uint2 *rect,
                          const uint2 *rspan, SplatPtrs sp, const uint32_t *depth_key, uint32_t *koff,
                          uint2 *rowtab, int nrec, int n, int tile, const ViewDesc *views,
-                         const FoveaRows &fr, uint32_t *block_sums, uint32_t *block_act, unsigned long long *seg_tot,
-                         uint32_t *seg_act, uint32_t *m_dev, unsigned long long *m_total,
+                         const FoveaRows &fr, uint32_t *block_sums, uint32_t *block_act,
+                         unsigned long long *seg_tot, uint32_t *seg_act, uint32_t *m_dev, unsigned long long *m_total,
                          uint32_t *a_dev, uint32_t *flags, int64_t capacity, uint32_t *dkey,
                          uint32_t *dval, uint4 *arec, uint2 *ranges, int total_tiles) {
     const int nb = (nrec + kScanTile - 1) / kScanTile;
@@ -909,8 +910,9 @@ void launch_scan_records(hipStream_t s, const uint32_t *count, const uint2 *rect
         k_seg_scan<<<(nb + kSegBlocks - 1) / kSegBlocks, kSegBlocks, 0, s>>>(block_sums, block_act, nb,
                                                                             seg_tot, seg_act);
     k_scan_rec<<<nb, kScanBlock, 0, s>>>(count, rect, rspan, sp, depth_key, koff, rowtab, nrec, n,
-                                         tile, views, fr, block_sums, block_act, nb, seg_tot, seg_act,
-                                         m_dev, m_total, a_dev, flags, capacity, dkey, dval, arec,
+                                         tile, views, fr, block_sums, block_act, nb, seg_tot,
+                                         seg_act, m_dev, m_total, a_dev, flags, capacity, dkey, dval,
+                                         arec,
                                          ranges, total_tiles, ValPack(entry_bits(nrec)));
 }
 
