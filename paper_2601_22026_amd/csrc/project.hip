@@ -9,9 +9,10 @@
 // conic = inverse(Sigma'); opacity = sigmoid(logit); colour = max(0, SH . Y(d)
 // + 0.5) with d the unit direction from the camera centre.
 //
-// One thread per record (view v, Gaussian i) in the forward pass; one thread
-// per Gaussian looping over views in the backward pass (no atomics).  Parameter
-// planes are read coalesced across i.
+// Forward pass: one thread per record (view v, Gaussian i), or, with several
+// views and SH degree 0-1, one thread per Gaussian looping over the views (its
+// parameters read once); backward pass: one thread per Gaussian looping over
+// views (no atomics).  Parameter planes are read coalesced across i.
 #include <climits>
 #include "gs_internal.h"
 
@@ -658,8 +659,9 @@ __global__ __launch_bounds__(256) void k_fovea_rows(const float *__restrict__ ga
     if (ty < vd.tiles_y) {
         for (int t0 = 0; t0 < vd.tiles_x; t0 += 64) {
             const int tx = t0 + lane;
-            const uint64_t m =
-                __ballot(tx < vd.tiles_x && fovea_tile_live(gaze, v, radius_frac, vd.width, vd.height, tile, tx, ty));
+            const bool live = tx < vd.tiles_x &&
+                              fovea_tile_live(gaze, v, radius_frac, vd.width, vd.height, tile, tx, ty);
+            const uint64_t m = __ballot(live);
             if (m) {
                 lo = min(lo, t0 + __builtin_ctzll(m));
                 hi = t0 + 63 - __builtin_clzll(m);
