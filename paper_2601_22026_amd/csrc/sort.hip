@@ -41,6 +41,7 @@ constexpr int kScanBlock = 256;
 constexpr int kScanIpt = 1;                  // 256 records per block: 50k records fill 196 blocks
 constexpr int kScanTile = kScanBlock * kScanIpt;
 static_assert(kScanTile == 256, "the projection writes the count totals of 256-record blocks");
+constexpr int kScanRecRounds = 2;           // 256-record rounds per workgroup of the record scan
 constexpr int kOwnPrefixBlocks = 1024;       // up to this many scan blocks, each sums its own prefix (no k_seg_scan)
 constexpr int kSegBlocks = 1024;             // block totals per segment of k_seg_scan
 
@@ -407,6 +408,40 @@ __device__ __forceinline__ bool block_prefix(const uint32_t *__restrict__ sums,
     return total_keys <= (unsigned long long)capacity;
 }
 
+// One record with keys: its compacted entry e (depth key, value, arec) and,
+// for a box not packed, its row table at its first gradient slot.
+__device__ __forceinline__ void scan_rec_place(uint32_t r, uint32_t c, uint32_t first, uint32_t e,
+                                               uint2 rc, uint2 pk, uint32_t dk, const SplatPtrs &sp,
+                                               uint2 *__restrict__ rowtab, int n, int tile,
+                                               const ViewDesc *__restrict__ views, const FoveaRows &fr,
+                                               uint32_t *__restrict__ dkey, uint32_t *__restrict__ dval,
+                                               uint4 *__restrict__ arec, const ValPack &vp) {
+    dkey[e] = dk;
+    dval[e] = vp.pack(e, c);
+    arec[2 * e] = make_uint4(r, first, c, pk.x);
+    arec[2 * e + 1] = make_uint4(rc.x, rc.y, pk.y, 0u);
+    const int x0 = (int)(rc.x & 0xFFFFu), y0 = (int)(rc.x >> 16);
+    const int x1 = (int)(rc.y & 0xFFFFu), y1 = (int)(rc.y >> 16);
+    if (y1 - y0 + 1 > kPackRows || x1 - x0 + 1 > kPackCols) {   // the row table
+        const float4 ea = *sp.at(r, kRecEll), a = *sp.at(r, kRecA),
+                     cc = *sp.at(r, kRecC);
+        const Ellipse el{ea.x, ea.y, ea.z, ea.w, sqrtf(ea.y / ea.z), a.x, a.y, (int)cc.z, (int)cc.w};
+        const int v = (int)r / n;
+        const ViewDesc vd = views[v];
+        const int tl = 31 - __clz(tile);
+        uint32_t j = 0, pre = 0;
+        for (int ty = y0; ty <= y1 && j < pk.x; ty++) {
+            int c0, c1;
+            if (!row_span(el, ty, tl, vd.width, vd.height, x0, x1, c0, c1) ||
+                !fovea_rows_clip(fr, v, ty, c0, c1))
+                continue;
+            rowtab[first + j] = make_uint2((uint32_t)(ty - y0) | ((uint32_t)c0 << 16), pre);
+            pre += (uint32_t)(c1 - c0 + 1);
+            j++;
+        }
+    }
+}
+
 // Record-order scan of the listed-tile counts: koff[r], the position of record
 // r's first gradient slot (its keys in record order), the row tables of the
 // boxes not packed (written at those slots), the key total and the capacity
@@ -417,9 +452,9 @@ __device__ __forceinline__ bool block_prefix(const uint32_t *__restrict__ sums,
 // visits the records in depth order, gathers one cache line per record.
 // a_dev: their number (0 on overflow).  Also clears the tile ranges
 // (grid-stride).  The per-block totals of counts and of active records come
-// from the projection.  The record's own loads are issued before the block's
-// prefix is summed, so that they are in flight while it waits on the totals
-// (nrec >= 1).
+// from the projection.  A workgroup scans kScanRecRounds consecutive blocks of
+// 256 records; their loads are all issued before its prefix is summed, so that
+// they are in flight while it waits on the totals (nrec >= 1).
 __global__ __launch_bounds__(kScanBlock) void k_scan_rec(
     const uint32_t *__restrict__ count, const uint2 *__restrict__ rect,
     const uint2 *__restrict__ rspan, SplatPtrs sp,
@@ -433,48 +468,38 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_rec(
     uint2 *__restrict__ ranges, int total_tiles, ValPack vp) {
     __shared__ uint32_t s_wave[4];
     __shared__ unsigned long long s_tot[16];
-    const int r = blockIdx.x * kScanTile + threadIdx.x;
-    // every record's entries, with no branch (the lines hold records with
-    // keys anyway; past the end, the last record's, unused)
-    const int rl = min(r, nrec - 1);
-    const uint32_t c = r < nrec ? count[rl] : 0u;
-    const uint2 rc = rect[rl], pk = rspan[rl];
-    const uint32_t dk = depth_key[rl];
+    // kScanRecRounds rounds of 256 consecutive records per workgroup; every
+    // record's entries are read first, with no branch (the lines hold records
+    // with keys anyway; past the end, the last record's, unused)
+    uint32_t c[kScanRecRounds], dk[kScanRecRounds];
+    uint2 rc[kScanRecRounds], pk[kScanRecRounds];
+#pragma unroll
+    for (int k = 0; k < kScanRecRounds; k++) {
+        const int r = (blockIdx.x * kScanRecRounds + k) * kScanTile + threadIdx.x;
+        const int rl = min(r, nrec - 1);
+        c[k] = r < nrec ? count[rl] : 0u;
+        rc[k] = rect[rl];
+        pk[k] = rspan[rl];
+        dk[k] = depth_key[rl];
+    }
     for (int t = blockIdx.x * kScanBlock + threadIdx.x; t < total_tiles; t += gridDim.x * kScanBlock)
         ranges[t] = make_uint2(0u, 0u);
     uint32_t gbase, abase;
-    if (!block_prefix(block_sums, block_act, nblocks, (int)blockIdx.x, seg_tot, seg_act, capacity,
-                      m_dev, m_total, a_dev, flags, true, s_tot, gbase, abase))
+    if (!block_prefix(block_sums, block_act, nblocks, (int)blockIdx.x * kScanRecRounds, seg_tot, seg_act,
+                      capacity, m_dev, m_total, a_dev, flags, true, s_tot, gbase, abase))
         return;   // overflow: nothing placed, nothing to sort
-    uint32_t total, atot;
-    const uint32_t off = block_excl_scan_256(c, s_wave, total);
-    const uint32_t apos = block_excl_scan_256(c != 0u ? 1u : 0u, s_wave, atot);
-    const uint32_t first = gbase + off, e = abase + apos;
-    if (r < nrec) koff[r] = first;   // every record: whole 64-byte chunks are written
-    if (c == 0u) return;
-    dkey[e] = dk;
-    dval[e] = vp.pack(e, c);
-    arec[2 * e] = make_uint4((uint32_t)r, first, c, pk.x);
-    arec[2 * e + 1] = make_uint4(rc.x, rc.y, pk.y, 0u);
-    const int x0 = (int)(rc.x & 0xFFFFu), y0 = (int)(rc.x >> 16);
-    const int x1 = (int)(rc.y & 0xFFFFu), y1 = (int)(rc.y >> 16);
-    if (y1 - y0 + 1 > kPackRows || x1 - x0 + 1 > kPackCols) {   // the row table
-        const float4 ea = *sp.at((uint32_t)r, kRecEll), a = *sp.at((uint32_t)r, kRecA),
-                     cc = *sp.at((uint32_t)r, kRecC);
-        const Ellipse el{ea.x, ea.y, ea.z, ea.w, sqrtf(ea.y / ea.z), a.x, a.y, (int)cc.z, (int)cc.w};
-        const int v = r / n;
-        const ViewDesc vd = views[v];
-        const int tl = 31 - __clz(tile);
-        uint32_t j = 0, pre = 0;
-        for (int ty = y0; ty <= y1 && j < pk.x; ty++) {
-            int c0, c1;
-            if (!row_span(el, ty, tl, vd.width, vd.height, x0, x1, c0, c1) ||
-                !fovea_rows_clip(fr, v, ty, c0, c1))
-                continue;
-            rowtab[first + j] = make_uint2((uint32_t)(ty - y0) | ((uint32_t)c0 << 16), pre);
-            pre += (uint32_t)(c1 - c0 + 1);
-            j++;
-        }
+#pragma unroll
+    for (int k = 0; k < kScanRecRounds; k++) {
+        const int r = (blockIdx.x * kScanRecRounds + k) * kScanTile + threadIdx.x;
+        uint32_t total, atot;
+        const uint32_t off = block_excl_scan_256(c[k], s_wave, total);
+        const uint32_t apos = block_excl_scan_256(c[k] != 0u ? 1u : 0u, s_wave, atot);
+        const uint32_t first = gbase + off, e = abase + apos;
+        gbase += total;
+        abase += atot;
+        if (r < nrec) koff[r] = first;   // every record: whole 64-byte chunks are written
+        if (c[k] != 0u) scan_rec_place((uint32_t)r, c[k], first, e, rc[k], pk[k], dk[k], sp, rowtab, n,
+                                       tile, views, fr, dkey, dval, arec, vp);
     }
 }
 
@@ -909,7 +934,7 @@ void launch_scan_records(hipStream_t s, const uint32_t *count, const uint2 *rect
     if (nb > kOwnPrefixBlocks)
         k_seg_scan<<<(nb + kSegBlocks - 1) / kSegBlocks, kSegBlocks, 0, s>>>(block_sums, block_act, nb,
                                                                             seg_tot, seg_act);
-    k_scan_rec<<<nb, kScanBlock, 0, s>>>(count, rect, rspan, sp, depth_key, koff, rowtab, nrec, n,
+    k_scan_rec<<<(nb + kScanRecRounds - 1) / kScanRecRounds, kScanBlock, 0, s>>>(count, rect, rspan, sp, depth_key, koff, rowtab, nrec, n,
                                          tile, views, fr, block_sums, block_act, nb, seg_tot,
                                          seg_act, m_dev, m_total, a_dev, flags, capacity, dkey, dval,
                                          arec,
