@@ -234,7 +234,12 @@ __global__ __launch_bounds__((fwd_threads<T, SPLIT>())) void k_render_fwd(
     // start loses the alias information that lets reads of the other buffer
     // proceed while it is in flight.)
     constexpr int SEC = B + 1;
-    __shared__ __align__(16) int s_list[(NT / 64) * kListLen];
+    constexpr int NW = NT / 64;
+    __shared__ __align__(16) int s_list[NW * kListLen];
+    // the waves' votes of a workgroup-wide test, two rows used in turn: a row is
+    // written again only two votes later, after a barrier that every wave
+    // reaches once it has read the row
+    __shared__ __align__(16) uint32_t s_vote[2][NW < 4 ? 4 : NW];
     __shared__ float4 s_buf0_[1 + 4 * SEC];
     __shared__ float4 s_buf1_[PREF ? 1 + 4 * SEC : 1];
     float4 *const s_buf0 = s_buf0_ + 1;
@@ -268,6 +273,26 @@ __global__ __launch_bounds__((fwd_threads<T, SPLIT>())) void k_render_fwd(
             s_buf1[2 * SEC + B] = make_float4(0.f, __builtin_inff(), 0.f, 0.f);
         }
     }
+
+    // Whether `pred` holds on every thread of the workgroup: one barrier (the
+    // waves' votes in LDS), which also ends the batch's copies into LDS and its
+    // reads of the buffer.
+    uint32_t vrow = 0u;
+    auto block_all = [&](bool pred) -> bool {
+        const bool w = __all(pred);
+        if constexpr (NW == 1) {
+            __syncthreads();
+            return w;
+        } else {
+            if (lane == 0) s_vote[vrow][wave] = w ? 1u : 0u;
+            __syncthreads();
+            uint32_t r = 1u;
+#pragma unroll
+            for (int i = 0; i < NW; i++) r &= s_vote[vrow][i];
+            vrow ^= 1u;
+            return r != 0u;
+        }
+    };
 
     // Tr[k] is the pixel's transmittance while it composites; a pixel that has
     // stopped (or lies outside the image) holds -T instead, so one compare
@@ -395,7 +420,7 @@ __global__ __launch_bounds__((fwd_threads<T, SPLIT>())) void k_render_fwd(
         bool all = true;
 #pragma unroll
         for (int k = 0; k < PPT; k++) all &= !(Tr[k] > 0.f);
-        return __syncthreads_and(all);
+        return block_all(all);
     };
 
     // A workgroup none of whose pixels composites (all outside the fovea disk or
@@ -403,7 +428,7 @@ __global__ __launch_bounds__((fwd_threads<T, SPLIT>())) void k_render_fwd(
     bool any_px = false;
 #pragma unroll
     for (int k = 0; k < PPT; k++) any_px |= Tr[k] > 0.f;
-    if (__syncthreads_or(any_px)) {
+    if (!block_all(!any_px)) {
         if constexpr (PREF) {
             // copy record r of entry threadIdx.x into a buffer (this wave's 64 slots)
             auto stage = [&](float4 *buf, uint32_t r) {
