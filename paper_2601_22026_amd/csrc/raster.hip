@@ -1117,38 +1117,82 @@ __global__ __launch_bounds__(kLossBlock) void k_loss_l1(
                              : FoveaTiles{1, 0, 1, 0};
     float s = 0.f;
     const float inv = 1.f / (float)max(cnt, 1u);
-    // kLossPx pixels per thread, kLossBlock apart (each step coalesced)
-    for (int k = 0; k < kLossPx; k++) {
-        int v, x, y;
-        if (loss_pixel(blockIdx.x, (uint32_t)(k * kLossBlock) + threadIdx.x, (uint32_t)total_pix, box, tile, f,
-                       views, nviews, v, x, y)) {
-            const ViewDesc vd = views[v];
-            const int q = y * vd.width + x;
-            const size_t plane = (size_t)vd.width * vd.height;
-            const float *img = rgba + 4 * (size_t)vd.pix_off;
-            const float *tgt = target + (size_t)tgt_planes * vd.pix_off;
-            float *g = dl + 4 * (size_t)vd.pix_off;
-            const bool in = in_fovea(gaze, v, x, y, radius_frac * (float)vd.width);
-            // RGBA targets: colour premultiplied, composited over the view background.
-            // A pixel outside the mask reads nothing (a fovea-culled forward did not
-            // composite it) and gets a zero gradient - written only on full frames:
-            // after a fovea-culled forward (box > 0) the adjoint does not read it
-            // (no splat reached the pixel).
-            const float ta = in && tgt_planes == 4 ? tgt[3 * plane + q] : 1.f;
-            if (in || !box) {
+    // kLossPx pixels per thread, kLossBlock apart (each step coalesced); all
+    // their loads are issued before any is used
+    bool ok[kLossPx], in[kLossPx];
+    int vk[kLossPx];
+    uint32_t qk[kLossPx], plk[kLossPx], offk[kLossPx];
+    if (box) {   // the block's view is uniform: its descriptor is read once
+        const int vb = min((int)(blockIdx.x / (uint32_t)loss_blocks_per_view(box)), nviews - 1);
+        const ViewDesc vd = views[vb];
+        const float rad = radius_frac * (float)vd.width;
 #pragma unroll
-                for (int c = 0; c < 4; c++) {
-                    float gv = 0.f;
-                    if (in && (c < 3 || alpha_term)) {
-                        float t = tgt[c * plane + q];
-                        if (c < 3 && bg) t = fmaf(1.f - ta, bg[3 * v + c], t);
-                        const float d = img[c * plane + q] - t;
-                        s += fabsf(d);
-                        gv = d > 0.f ? inv : (d < 0.f ? -inv : 0.f);
-                    }
-                    g[c * plane + q] = gv;
-                }
+        for (int k = 0; k < kLossPx; k++) {
+            int v = 0, x = 0, y = 0;
+            ok[k] = loss_pixel(blockIdx.x, (uint32_t)(k * kLossBlock) + threadIdx.x, (uint32_t)total_pix,
+                               box, tile, f, views, nviews, v, x, y);
+            vk[k] = vb;
+            qk[k] = (uint32_t)(y * vd.width + x);
+            plk[k] = (uint32_t)vd.width * (uint32_t)vd.height;
+            offk[k] = (uint32_t)vd.pix_off;
+            in[k] = ok[k] && in_fovea(gaze, vb, x, y, rad);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < kLossPx; k++) {
+            int v = 0, x = 0, y = 0;
+            ok[k] = loss_pixel(blockIdx.x, (uint32_t)(k * kLossBlock) + threadIdx.x, (uint32_t)total_pix,
+                               box, tile, f, views, nviews, v, x, y);
+            const ViewDesc vd = views[ok[k] ? v : 0];
+            vk[k] = v;
+            qk[k] = (uint32_t)(y * vd.width + x);
+            plk[k] = (uint32_t)vd.width * (uint32_t)vd.height;
+            offk[k] = (uint32_t)vd.pix_off;
+            in[k] = ok[k] && in_fovea(gaze, v, x, y, radius_frac * (float)vd.width);
+        }
+    }
+    // RGBA targets: colour premultiplied, composited over the view background.
+    // A pixel outside the mask reads nothing (a fovea-culled forward did not
+    // composite it) and gets a zero gradient - written only on full frames:
+    // after a fovea-culled forward (box > 0) the adjoint does not read it (no
+    // splat reached the pixel).
+    float im[kLossPx][4], tg[kLossPx][4], bk[kLossPx][3];
+#pragma unroll
+    for (int k = 0; k < kLossPx; k++) {
+        const size_t plane = plk[k], q = qk[k];
+        const float *img = rgba + 4 * (size_t)offk[k];
+        const float *tgt = target + (size_t)tgt_planes * offk[k];
+        if (in[k]) {
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                im[k][c] = img[c * plane + q];
+                tg[k][c] = tgt[c * plane + q];
             }
+            im[k][3] = alpha_term ? img[3 * plane + q] : 0.f;
+            tg[k][3] = tgt_planes == 4 || alpha_term ? tgt[3 * plane + q] : 1.f;
+            if (bg) {
+#pragma unroll
+                for (int c = 0; c < 3; c++) bk[k][c] = bg[3 * vk[k] + c];
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kLossPx; k++) {
+        if (!(ok[k] && (in[k] || !box))) continue;
+        const size_t plane = plk[k], q = qk[k];
+        float *g = dl + 4 * (size_t)offk[k];
+        const float ta = in[k] && tgt_planes == 4 ? tg[k][3] : 1.f;
+#pragma unroll
+        for (int c = 0; c < 4; c++) {
+            float gv = 0.f;
+            if (in[k] && (c < 3 || alpha_term)) {
+                float t = tg[k][c];
+                if (c < 3 && bg) t = fmaf(1.f - ta, bk[k][c], t);
+                const float d = im[k][c] - t;
+                s += fabsf(d);
+                gv = d > 0.f ? inv : (d < 0.f ? -inv : 0.f);
+            }
+            g[c * plane + q] = gv;
         }
     }
 #pragma unroll
