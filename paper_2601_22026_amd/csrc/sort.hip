@@ -139,9 +139,9 @@ __global__ __launch_bounds__(256) void k_radix_colscan(uint32_t *__restrict__ hi
                                                        uint32_t *__restrict__ digit_tot) {
     __shared__ uint32_t s_wave[4];
     uint32_t *row = hist + (size_t)blockIdx.x * G;
-    const int per = (G + 255) / 256;
+    const int per = (G + 255) / 256;   // G <= kSortMaxGrid
     const int base = threadIdx.x * per;
-    uint32_t local[4];
+    uint32_t local[(kSortMaxGrid + 255) / 256];
     uint32_t sum = 0;
     for (int k = 0; k < per; k++) {
         const uint32_t c = base + k < G ? row[base + k] : 0u;
@@ -934,11 +934,10 @@ void launch_scan_records(hipStream_t s, const uint32_t *count, const uint2 *rect
     if (nb > kOwnPrefixBlocks)
         k_seg_scan<<<(nb + kSegBlocks - 1) / kSegBlocks, kSegBlocks, 0, s>>>(block_sums, block_act, nb,
                                                                             seg_tot, seg_act);
-    k_scan_rec<<<(nb + kScanRecRounds - 1) / kScanRecRounds, kScanBlock, 0, s>>>(count, rect, rspan, sp, depth_key, koff, rowtab, nrec, n,
-                                         tile, views, fr, block_sums, block_act, nb, seg_tot,
-                                         seg_act, m_dev, m_total, a_dev, flags, capacity, dkey, dval,
-                                         arec,
-                                         ranges, total_tiles, ValPack(entry_bits(nrec)));
+    k_scan_rec<<<(nb + kScanRecRounds - 1) / kScanRecRounds, kScanBlock, 0, s>>>(
+        count, rect, rspan, sp, depth_key, koff, rowtab, nrec, n, tile, views, fr, block_sums,
+        block_act, nb, seg_tot, seg_act, m_dev, m_total, a_dev, flags, capacity, dkey, dval, arec,
+        ranges, total_tiles, ValPack(entry_bits(nrec)));
 }
 
 void launch_emit(hipStream_t s, const uint32_t *dval, const uint32_t *a_dev, const uint4 *arec,
