@@ -56,7 +56,7 @@ FLOPS_FWD_INCLUDED = 10
 FLOPS_BWD_INCLUDED = 48
 # MI355X FP32 vector peak: 256 CUs x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz x 2
 # (packed dual-issue FP32) = 157.3 TFLOP/s.  Without packed FP32 instructions
-# (this build turns them off) the attainable peak is half that, 78.6 TFLOP/s,
+# (the library is compiled without them) the attainable peak is half that, 78.6 TFLOP/s,
 # which is quoted beside the published figure.
 PEAK_FP32_TFLOPS = 157.3
 PEAK_FP32_NONPACKED_TFLOPS = 78.6

@@ -69,7 +69,7 @@ typedef enum {
     GSF_E_HIP = 3,         /* a HIP runtime call failed; see gsf_last_error */
     GSF_E_STATE = 4,       /* call out of order (no workspace, no forward, no graph) */
     GSF_E_NONFINITE = 5,   /* non-finite loss detected */
-    GSF_E_UNSUPPORTED = 6  /* option not supported by this build */
+    GSF_E_UNSUPPORTED = 6  /* option the library does not support */
 } gsf_status;
 
 /* sticky device flags reported by gsf_poll */
