@@ -268,20 +268,30 @@ def composited_pixels(cams, gaze, radius_frac, tile):
     return n
 
 
-def hbm_bytes_per_launch(stage, N, R, M, npix, planes, tiles, A):
+def depth_sort_passes(keys):
+    """Passes of the library's depth sort over these depth keys (the records
+    that list a tile): three when every key lies below 2^24 above the smallest
+    key with its low 8 bits cleared, else four."""
+    if keys.size == 0:
+        return 3
+    base = int(keys.min()) & ~0xFF
+    return 3 if int(keys.max()) - base < (1 << 24) else 4
+
+
+def hbm_bytes_per_launch(stage, N, R, M, npix, planes, tiles, A, depth_passes=4):
     """Algorithmic HBM bytes one launch of a stage must move: N Gaussians,
     R = N * views records, A of them listing a tile, M keys, npix pixels
     composited (the fovea tiles' pixels when the step is fovea-culled),
-    `planes` floats per Gaussian."""
+    `planes` floats per Gaussian, `depth_passes` passes of the depth sort."""
     tile_passes = radix_passes(max(1, (tiles - 1).bit_length()))
     return {
         "project": planes * 4 * N + 88 * R,                   # params in; splat, key, box, count, ellipse, spans
         # counts in; slots, depth keys in, (depth, entry) pairs and 32-byte entries out; ranges cleared
         "duplicate": 4 * R + 48 * A + 8 * tiles,
-        # depth sort of the A entries (per pass: key histogram, pair in, pair out), the
-        # emission's count totals and the emission (sorted entries, 32-byte entries in;
-        # (tile, record) keys out)
-        "depth_sort": radix_passes(31) * 20 * A + 8 * A + 36 * A + 8 * M,
+        # depth sort of the A entries (per pass: key histogram, pair in, pair out; the
+        # last pass writes no keys), the emission's count totals and the emission
+        # (sorted entries, 32-byte entries in; (tile, record) keys out)
+        "depth_sort": (depth_passes - 1) * 20 * A + 16 * A + 8 * A + 36 * A + 8 * M,
         "tile_sort": tile_passes * 20 * M,                    # per pass: key histogram, pair in, pair out
         "ranges": 4 * M + 28 * tiles,                         # sorted tile ids in; ranges out; order
         "render": 40 * M + 24 * npix,                         # splat gather per key; RGBA, T, count out
@@ -692,8 +702,10 @@ def main():
         flags, M = fused.poll()
         check_flags(flags, "fused captured step")
         # records that list a tile (the depth sort's input) in the last step
-        A = int((fused.plan.debug(gs._abi.GSF_DBG_COUNT, np.uint32,
-                                  N * len(step_cams)) > 0).sum())
+        act = fused.plan.debug(gs._abi.GSF_DBG_COUNT, np.uint32, N * len(step_cams)) > 0
+        act_depth = fused.plan.debug(gs._abi.GSF_DBG_DEPTH, np.uint32, N * len(step_cams))[act]
+        A = int(act_depth.size)
+        depth_passes = depth_sort_passes(act_depth)
         loss_fused = float(fused.loss.item())
         log(f"[bench] fused+captured: {ms_fused * 1e3:.1f} us/step (median {med_fused * 1e3:.1f}), "
             f"keys {M}, flags {flags}, loss {loss_fused:.5f}")
@@ -904,21 +916,22 @@ def main():
                 "us_per_launch": round(stages[dom] * 1e3, 2),
                 "work": {"flops_per_launch": int(flops), **pairs}}
     else:
-        byt = hbm_bytes_per_launch(dom, N, R, M, apix, planes, total_tiles, A)
+        byt = hbm_bytes_per_launch(dom, N, R, M, apix, planes, total_tiles, A, depth_passes)
         ach = byt / (stages[dom] * 1e-3) / 1e9
         roof = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS,
                 "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": traffic,
                 "us_per_launch": round(stages[dom] * 1e3, 2)}
     stage_roof = {}
     for k, ms in stages.items():
-        byt = hbm_bytes_per_launch(k, N, R, M, apix, planes, total_tiles, A)
+        byt = hbm_bytes_per_launch(k, N, R, M, apix, planes, total_tiles, A, depth_passes)
         stage_roof[k] = {"us": round(ms * 1e3, 2), "gbs": round(byt / (ms * 1e-3) / 1e9, 1)}
         if k in ("render", "render_bwd"):
             fl = (FLOPS_ALPHA * pairs["visited_fwd"] + FLOPS_FWD_INCLUDED * pairs["included"]
                   if k == "render" else
                   FLOPS_ALPHA * pairs["visited_bwd"] + FLOPS_BWD_INCLUDED * pairs["included"])
             stage_roof[k]["tflops"] = round(fl / (ms * 1e-3) / 1e12, 3)
-    step_bytes = sum(hbm_bytes_per_launch(k, N, R, M, apix, planes, total_tiles, A) for k in stages)
+    step_bytes = sum(hbm_bytes_per_launch(k, N, R, M, apix, planes, total_tiles, A, depth_passes)
+                     for k in stages)
 
     steps_per_s = 1000.0 / ms_fused
     res = {
@@ -940,7 +953,8 @@ def main():
                    "sh_degree": int(round(((planes - 11) // 3) ** 0.5)) - 1,
                    "tile": cfg.tile, "lds_batch": cfg.lds_batch, "t_mode": cfg.t_mode,
                    "fovea_cull": bool(cfg.fovea_cull),
-                   "keys_per_step": M, "records_with_keys": A, "form": "fused, hipGraph-captured"},
+                   "keys_per_step": M, "records_with_keys": A,
+                   "depth_sort_passes": depth_passes, "form": "fused, hipGraph-captured"},
         "median_step_ms": round(med_fused, 4),
         "flags_after_timed_steps": flags,
         "mpix_per_s": round(npix * steps_per_s / 1e6, 1),

@@ -482,6 +482,17 @@ int scan_blocks(int64_t nrec);
 int launch_radix_sort(hipStream_t s, const uint32_t *kin, const uint32_t *vin, uint32_t *ka,
                       uint32_t *va, uint32_t *kb, uint32_t *vb, const uint32_t *n_dev,
                       uint32_t n_host, int bits, int grid, uint32_t *hist, uint32_t *digit_tot);
+// Stable sort of the (depth bits, value) pairs (k0, v0) of the records that
+// list a tile (count n_dev; positive float bits, below 2^31) by depth: pass 1
+// by the low 8 bits, passes 2 and 3 by bits 8 - 23 of key - base, where base
+// is the smallest key with its low 8 bits clear (found by pass 1: mm holds 2
+// grid words, ctl 2), and a fourth pass by bits 24 - 30 of key - base only
+// when some key lies 2^24 or more above base (else it returns at once).  The
+// sorted values end in vfinal; the keys of the last pass are not written.
+// (k1, v1) and (k0, v0) are the passes' intermediates.
+void launch_depth_sort(hipStream_t s, uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
+                       const uint32_t *n_dev, int grid, uint32_t *hist, uint32_t *digit_tot,
+                       uint32_t *mm, uint32_t *ctl, uint32_t *vfinal);
 int radix_grid_for(int64_t capacity);
 int radix_passes(int bits);
 constexpr int kRadixBins = 256;

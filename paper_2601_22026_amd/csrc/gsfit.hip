@@ -62,7 +62,9 @@ struct Buffers {
     // and the keys sorted by tile between the two; `vals` is then the sorted
     // record-id list the compositing reads.
     uint32_t *k0 = nullptr, *v0 = nullptr, *k1 = nullptr, *v1 = nullptr;
-    uint32_t *dsorted = nullptr;                 // depth-ordered active records (values of the depth pair)
+    uint32_t *dsorted = nullptr;                 // depth-ordered active records (the depth sort's values)
+    uint32_t *depth_mm = nullptr;                // per depth-sort workgroup: smallest, largest key
+    uint32_t *depth_ctl = nullptr;               // depth sort: key base, 24 bits suffice
     uint32_t *ek = nullptr, *ev = nullptr;       // emission pair
     uint32_t *tk = nullptr, *tv = nullptr;       // the other pair
     uint32_t *keys = nullptr, *vals = nullptr;   // sorted pair (one of the above)
@@ -89,7 +91,6 @@ struct Buffers {
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Depth keys are float32 bits of positive depths: the sign bit is zero.
-constexpr int kDepthBits = 31;
 
 }  // namespace
 
@@ -190,14 +191,16 @@ size_t carve(gsf_plan *p, char *base, Buffers *out) {
     b.v0 = (uint32_t *)take((size_t)p->cap * 4);
     b.k1 = (uint32_t *)take((size_t)p->cap * 4);
     b.v1 = (uint32_t *)take((size_t)p->cap * 4);
-    // radix passes write the first then the second pair given, alternately: the
-    // depth sort starts in (k0, v0), so an odd pass count ends in (k1, v1)
-    const bool depth_in_1 = radix_passes(kDepthBits) % 2 == 1;
-    b.dsorted = depth_in_1 ? b.v1 : b.v0;
-    b.ek = depth_in_1 ? b.k0 : b.k1;
-    b.ev = depth_in_1 ? b.v0 : b.v1;
-    b.tk = depth_in_1 ? b.k1 : b.k0;
-    b.tv = depth_in_1 ? b.v1 : b.v0;
+    // the depth sort passes between (k0, v0) and (k1, v1) and ends in dsorted;
+    // the keys are emitted into (ek, ev) and the tile sort's passes write
+    // (tk, tv) then (ek, ev), alternately
+    b.dsorted = (uint32_t *)take((size_t)std::min<int64_t>(p->nrec_max, p->cap) * 4);
+    b.depth_mm = (uint32_t *)take((size_t)2 * p->radix_grid * 4);
+    b.depth_ctl = (uint32_t *)take(2 * 4);
+    b.ek = b.k1;
+    b.ev = b.v1;
+    b.tk = b.k0;
+    b.tv = b.v0;
     const bool tiles_odd = radix_passes(p->tile_bits) % 2 == 1;   // tile sort: (tk, tv) first
     b.keys = tiles_odd ? b.tk : b.ek;
     b.vals = tiles_odd ? b.tv : b.ev;
@@ -391,10 +394,8 @@ gsf_status enqueue_forward(gsf_plan *p, const float *params, int64_t n, const gs
     {   // depth order of the records with keys (stable: equal depths keep the
         // record order), then their keys emitted in that order
         StageTimer t(p, GSF_STAGE_DEPTH_SORT);
-        const int where = launch_radix_sort(s, b.k0, b.v0, b.k1, b.v1, b.k0, b.v0, b.a_dev, 0u,
-                                            kDepthBits, p->radix_grid, b.hist, b.digit_tot);
-        if ((where == 1 ? b.v1 : b.v0) != b.dsorted)
-            return fail(ctx, GSF_E_STATE, "depth sort pass count does not match the workspace");
+        launch_depth_sort(s, b.k0, b.v0, b.k1, b.v1, b.a_dev, p->radix_grid, b.hist, b.digit_tot,
+                          b.depth_mm, b.depth_ctl, b.dsorted);
         launch_emit(s, b.dsorted, b.a_dev, b.arec, b.rowtab, nrec, (int)n, b.views, p->V,
                     b.emit_sums, b.seg_tot, b.m_total, p->cap, tm, b.ek, b.ev);
     }

@@ -73,6 +73,24 @@ __device__ __forceinline__ uint32_t chunk_size(uint32_t n, int G) {
     return (per + 255u) & ~255u;
 }
 
+// Optional controls of a radix pass (all null: a plain pass over the key bits).
+//   base:  the digits are those of key - *base (the keys are written unchanged)
+//   skip:  *skip != 0: the pass has nothing to do and returns at once
+//   last:  *last != 0: this is the sort's last pass: the values go to vlast
+//          and no keys are written
+//   mm:    the histogram writes each workgroup's smallest and largest key
+//          (mm[2 g], mm[2 g + 1]); with ctl, workgroup 0 of the scatter
+//          reduces them to ctl[0] = the smallest key with its low 8 bits
+//          cleared and ctl[1] = 1 when every key lies below ctl[0] + 2^24
+struct RadixCtl {
+    const uint32_t *base = nullptr;
+    const uint32_t *skip = nullptr;
+    const uint32_t *last = nullptr;
+    uint32_t *vlast = nullptr;
+    uint32_t *mm = nullptr;
+    uint32_t *ctl = nullptr;
+};
+
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
     const int lane = __lane_id();
 #pragma unroll
@@ -104,8 +122,12 @@ __device__ __forceinline__ uint32_t block_excl_scan_256(uint32_t x, uint32_t *s_
 __global__ __launch_bounds__(kSortBlock) void k_radix_hist(const uint32_t *__restrict__ keys,
                                                            const uint32_t *__restrict__ n_dev,
                                                            uint32_t n_host, int shift, int bits,
-                                                           uint32_t *__restrict__ hist, int G) {
+                                                           uint32_t *__restrict__ hist, int G,
+                                                           RadixCtl ctl) {
     __shared__ uint32_t h[4][256];
+    __shared__ uint32_t s_mm[8];
+    if (ctl.skip && *ctl.skip) return;
+    const uint32_t kb = ctl.base ? *ctl.base : 0u;
     const uint32_t n = n_dev ? *n_dev : n_host;
     const uint32_t chunk = chunk_size(n, G);
     const uint32_t start = min(n, (uint32_t)blockIdx.x * chunk);
@@ -114,6 +136,7 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_hist(const uint32_t *__res
     for (int d = threadIdx.x; d < 4 * 256; d += kSortBlock) (&h[0][0])[d] = 0u;
     __syncthreads();
     const uint32_t mask = (1u << bits) - 1u;
+    uint32_t kmin = 0xFFFFFFFFu, kmax = 0u;
     // kHistU keys per thread are loaded before any is counted, so their loads
     // are in flight together
     for (uint32_t base = start; base < end; base += kSortBlock * kHistU) {
@@ -125,10 +148,28 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_hist(const uint32_t *__res
         }
 #pragma unroll
         for (int u = 0; u < kHistU; u++)
-            if (base + (uint32_t)(u * kSortBlock) + threadIdx.x < end)
-                atomicAdd(&h[w][(k[u] >> shift) & mask], 1u);
+            if (base + (uint32_t)(u * kSortBlock) + threadIdx.x < end) {
+                atomicAdd(&h[w][((k[u] - kb) >> shift) & mask], 1u);
+                kmin = min(kmin, k[u]);
+                kmax = max(kmax, k[u]);
+            }
+    }
+    if (ctl.mm) {   // the workgroup's smallest and largest key
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            kmin = min(kmin, (uint32_t)__shfl_xor((int)kmin, o, 64));
+            kmax = max(kmax, (uint32_t)__shfl_xor((int)kmax, o, 64));
+        }
+        if ((threadIdx.x & 63) == 0) {
+            s_mm[w] = kmin;
+            s_mm[4 + w] = kmax;
+        }
     }
     __syncthreads();
+    if (ctl.mm && threadIdx.x == 0) {
+        ctl.mm[2 * blockIdx.x] = min(min(s_mm[0], s_mm[1]), min(s_mm[2], s_mm[3]));
+        ctl.mm[2 * blockIdx.x + 1] = max(max(s_mm[4], s_mm[5]), max(s_mm[6], s_mm[7]));
+    }
     const int nd = 1 << bits;
     for (int d = threadIdx.x; d < nd; d += kSortBlock)
         hist[(size_t)d * G + blockIdx.x] = h[0][d] + h[1][d] + h[2][d] + h[3][d];
@@ -136,8 +177,10 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_hist(const uint32_t *__res
 
 // One workgroup per digit: exclusive scan of that digit's per-workgroup counts.
 __global__ __launch_bounds__(256) void k_radix_colscan(uint32_t *__restrict__ hist, int G,
-                                                       uint32_t *__restrict__ digit_tot) {
+                                                       uint32_t *__restrict__ digit_tot,
+                                                       const uint32_t *__restrict__ skip) {
     __shared__ uint32_t s_wave[4];
+    if (skip && *skip) return;
     uint32_t *row = hist + (size_t)blockIdx.x * G;
     const int per = (G + 255) / 256;   // G <= kSortMaxGrid
     const int base = threadIdx.x * per;
@@ -165,7 +208,8 @@ __global__ __launch_bounds__(256) void k_radix_colscan(uint32_t *__restrict__ hi
 __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(
     const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout,
     uint32_t *__restrict__ vout, const uint32_t *__restrict__ n_dev, uint32_t n_host, int shift,
-    int bits, const uint32_t *__restrict__ hist, const uint32_t *__restrict__ digit_tot, int G) {
+    int bits, const uint32_t *__restrict__ hist, const uint32_t *__restrict__ digit_tot, int G,
+    RadixCtl ctl) {
     __shared__ uint32_t s_base[256];      // next global position of each digit
     __shared__ uint32_t s_loc[256];       // first local position of each digit in the round
     __shared__ uint32_t s_cnt[4][256];
@@ -173,6 +217,12 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(
     __shared__ uint32_t s_wave[4];
     __shared__ uint32_t s_key[kSortTile];
     __shared__ uint32_t s_val[kSortTile];
+    if (ctl.skip && *ctl.skip) return;
+    const uint32_t kb = ctl.base ? *ctl.base : 0u;
+    // the sort's last pass: the values to vlast, no keys
+    const bool lastp = ctl.last && *ctl.last;
+    uint32_t *const ko = lastp ? nullptr : kout;
+    uint32_t *const vo = lastp ? ctl.vlast : vout;
     const uint32_t n = n_dev ? *n_dev : n_host;
     const uint32_t chunk = chunk_size(n, G);
     const uint32_t start = min(n, (uint32_t)blockIdx.x * chunk);
@@ -180,6 +230,31 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(
     const int nd = 1 << bits;
     const uint32_t mask = (uint32_t)nd - 1u;
     const int t = threadIdx.x, w = t >> 6, lane = __lane_id();
+    if (ctl.ctl && blockIdx.x == 0) {   // the key range from the histogram's per-workgroup extremes
+        uint32_t kmin = 0xFFFFFFFFu, kmax = 0u;
+        for (int g = t; g < G; g += kSortBlock) {
+            kmin = min(kmin, ctl.mm[2 * g]);
+            kmax = max(kmax, ctl.mm[2 * g + 1]);
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            kmin = min(kmin, (uint32_t)__shfl_xor((int)kmin, o, 64));
+            kmax = max(kmax, (uint32_t)__shfl_xor((int)kmax, o, 64));
+        }
+        if (lane == 0) {
+            s_base[w] = kmin;
+            s_base[4 + w] = kmax;
+        }
+        __syncthreads();
+        if (t == 0) {
+            kmin = min(min(s_base[0], s_base[1]), min(s_base[2], s_base[3]));
+            kmax = max(max(s_base[4], s_base[5]), max(s_base[6], s_base[7]));
+            const uint32_t b = kmin <= kmax ? kmin & ~0xFFu : 0u;   // no keys: any base
+            ctl.ctl[0] = b;
+            ctl.ctl[1] = kmin > kmax || kmax - b < (1u << 24) ? 1u : 0u;
+        }
+        __syncthreads();   // s_base is free again
+    }
     if (digit_tot) {   // global base of each digit for this workgroup (hist scanned per digit)
         const uint32_t tot = t < nd ? digit_tot[t] : 0u;
         uint32_t all;
@@ -225,7 +300,7 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(
             if (r >= rounds) break;
             const uint32_t idx = wbase + (uint32_t)r * 64u + (uint32_t)lane;
             const bool valid = idx < end;
-            const uint32_t d = (key[r] >> shift) & mask;
+            const uint32_t d = ((key[r] - kb) >> shift) & mask;
             uint64_t peers = __ballot(valid);
             for (int b = 0; b < bits; b++) {
                 const uint64_t bal = __ballot((d >> b) & 1u);
@@ -259,7 +334,7 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(
             if (r >= rounds) break;
             const uint32_t idx = wbase + (uint32_t)r * 64u + (uint32_t)lane;
             if (idx < end) {
-                const uint32_t d = (key[r] >> shift) & mask;
+                const uint32_t d = ((key[r] - kb) >> shift) & mask;
                 const uint32_t lp = s_loc[d] + s_cnt[w][d] + rank[r];
                 s_key[lp] = key[r];
                 s_val[lp] = val[r];
@@ -268,10 +343,10 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(
         __syncthreads();
         for (uint32_t p = (uint32_t)t; p < nround; p += kSortBlock) {
             const uint32_t k = s_key[p];
-            const uint32_t d = (k >> shift) & mask;
+            const uint32_t d = ((k - kb) >> shift) & mask;
             const uint32_t pos = s_base[d] + (p - s_loc[d]);
-            kout[pos] = k;
-            vout[pos] = s_val[p];
+            if (ko) ko[pos] = k;
+            vo[pos] = s_val[p];
         }
         __syncthreads();
         if (t < nd) s_base[t] += s_tot[t];
@@ -891,6 +966,44 @@ int radix_grid_for(int64_t capacity) {
 
 int radix_passes(int bits) { return bits <= 0 ? 0 : (bits + kMaxDigit - 1) / kMaxDigit; }
 
+namespace {
+
+// One pass: histogram, digit scan (more than kLocalScanGrid workgroups) and
+// scatter.
+void radix_pass(hipStream_t s, const uint32_t *kin, const uint32_t *vin, uint32_t *kout,
+                uint32_t *vout, const uint32_t *n_dev, uint32_t n_host, int shift, int bits, int grid,
+                uint32_t *hist, uint32_t *digit_tot, const RadixCtl &ctl) {
+    k_radix_hist<<<grid, kSortBlock, 0, s>>>(kin, n_dev, n_host, shift, bits, hist, grid, ctl);
+    // up to kLocalScanGrid workgroups sum their digit offsets themselves
+    const bool local = grid <= kLocalScanGrid;
+    if (!local) k_radix_colscan<<<1 << bits, 256, 0, s>>>(hist, grid, digit_tot, ctl.skip);
+    k_radix_scatter<<<grid, kSortBlock, 0, s>>>(kin, vin, kout, vout, n_dev, n_host, shift, bits, hist,
+                                                local ? nullptr : digit_tot, grid, ctl);
+}
+
+}  // namespace
+
+void launch_depth_sort(hipStream_t s, uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
+                       const uint32_t *n_dev, int grid, uint32_t *hist, uint32_t *digit_tot,
+                       uint32_t *mm, uint32_t *ctl, uint32_t *vfinal) {
+    // pass 1 sorts by the low 8 bits, which the base (low 8 bits clear) leaves
+    // as they are, and finds the base and whether 24 bits above it hold every key
+    RadixCtl c1;
+    c1.mm = mm;
+    c1.ctl = ctl;
+    radix_pass(s, k0, v0, k1, v1, n_dev, 0u, 0, 8, grid, hist, digit_tot, c1);
+    RadixCtl c2;
+    c2.base = ctl;
+    radix_pass(s, k1, v1, k0, v0, n_dev, 0u, 8, 8, grid, hist, digit_tot, c2);
+    RadixCtl c3 = c2;   // the last pass when 24 bits hold the keys
+    c3.last = ctl + 1;
+    c3.vlast = vfinal;
+    radix_pass(s, k0, v0, k1, v1, n_dev, 0u, 16, 8, grid, hist, digit_tot, c3);
+    RadixCtl c4 = c2;   // otherwise bits 24 - 30
+    c4.skip = ctl + 1;
+    radix_pass(s, k1, v1, nullptr, vfinal, n_dev, 0u, 24, 7, grid, hist, digit_tot, c4);
+}
+
 int launch_radix_sort(hipStream_t s, const uint32_t *kin, const uint32_t *vin, uint32_t *ka,
                       uint32_t *va, uint32_t *kb, uint32_t *vb, const uint32_t *n_dev,
                       uint32_t n_host, int bits, int grid, uint32_t *hist, uint32_t *digit_tot) {
@@ -901,12 +1014,7 @@ int launch_radix_sort(hipStream_t s, const uint32_t *kin, const uint32_t *vin, u
     for (int p = 0, shift = 0; p < passes; p++) {
         const int b = (bits - shift + (passes - p) - 1) / (passes - p);
         uint32_t *kd = where == 1 ? kb : ka, *vd = where == 1 ? vb : va;
-        k_radix_hist<<<grid, kSortBlock, 0, s>>>(ks, n_dev, n_host, shift, b, hist, grid);
-        // up to kLocalScanGrid workgroups sum their digit offsets themselves
-        const bool local = grid <= kLocalScanGrid;
-        if (!local) k_radix_colscan<<<1 << b, 256, 0, s>>>(hist, grid, digit_tot);
-        k_radix_scatter<<<grid, kSortBlock, 0, s>>>(ks, vs, kd, vd, n_dev, n_host, shift, b, hist,
-                                                    local ? nullptr : digit_tot, grid);
+        radix_pass(s, ks, vs, kd, vd, n_dev, n_host, shift, b, grid, hist, digit_tot, RadixCtl{});
         where = where == 1 ? 2 : 1;
         ks = kd;
         vs = vd;
