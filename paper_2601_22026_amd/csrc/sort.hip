@@ -79,7 +79,7 @@ __device__ __forceinline__ uint32_t chunk_size(uint32_t n, int G) {
 //   last:  *last != 0: this is the sort's last pass: the values go to vlast
 //          and no keys are written
 //   mm:    the histogram writes each workgroup's smallest and largest key
-//          (mm[2 g], mm[2 g + 1]); with ctl, workgroup 0 of the scatter
+//          (mm[2 g], mm[2 g + 1]); with ctl, the scatter's last workgroup
 //          reduces them to ctl[0] = the smallest key with its low 8 bits
 //          cleared and ctl[1] = 1 when every key lies below ctl[0] + 2^24
 struct RadixCtl {
@@ -230,7 +230,9 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(
     const int nd = 1 << bits;
     const uint32_t mask = (uint32_t)nd - 1u;
     const int t = threadIdx.x, w = t >> 6, lane = __lane_id();
-    if (ctl.ctl && blockIdx.x == 0) {   // the key range from the histogram's per-workgroup extremes
+    // the key range from the histogram's per-workgroup extremes, reduced by the
+    // last workgroup (chunks are rounded up, so it holds the fewest keys)
+    if (ctl.ctl && (int)blockIdx.x == G - 1) {
         uint32_t kmin = 0xFFFFFFFFu, kmax = 0u;
         for (int g = t; g < G; g += kSortBlock) {
             kmin = min(kmin, ctl.mm[2 * g]);

@@ -55,13 +55,27 @@ def _discrete_scenes():
                                                                height=400)]
 
 
+def _depth_sort_passes(sc, R):
+    """Passes the library's depth sort takes for the last forward: three when
+    the depth keys of the records that list a tile lie below 2^24 above the
+    smallest with its low 8 bits cleared, else four (its documented rule)."""
+    count = sc.debug(_abi.GSF_DBG_COUNT, np.uint32, R)
+    depth = sc.debug(_abi.GSF_DBG_DEPTH, np.uint32, R)[count > 0].astype(np.int64)
+    if depth.size == 0:
+        return 3
+    return 3 if depth.max() - (depth.min() & ~0xFF) < (1 << 24) else 4
+
+
 @pytest.mark.parametrize("tile", [8, 16, 32])
 def test_discrete_stage_bit_exact(ctx, tile):
     """Keys, values and ranges against the oracle, bit for bit.  Records the
     oracle flags (a box edge or depth tie within rounding) are removed from both
     key lists; ranges are compared on every tile no flagged record is listed in
     on either side (as that tile's list of records), and the GPU's ranges are
-    checked to be the lower and upper bounds of its own sorted keys everywhere."""
+    checked to be the lower and upper bounds of its own sorted keys everywhere.
+    The scenes take both forms of the depth sort: three passes (depths within
+    about two binades) and four (near splats)."""
+    passes = set()
     for name, P, cams in _discrete_scenes():
         log(f"[parity] discrete stage tile {tile}, {name}")
         sc = GpuScene(ctx, P, cams, tile=tile)
@@ -96,8 +110,10 @@ def test_discrete_stage_bit_exact(ctx, tile):
         if flagged.size == 0:
             assert Mg == M
             np.testing.assert_array_equal(ranges, d.ranges)
+        passes.add(_depth_sort_passes(sc, R))
         log(f"[parity]   keys {M}, flagged records {flagged.size}, tiles compared "
-            f"{int((~touched).sum())} of {tiles}")
+            f"{int((~touched).sum())} of {tiles}, depth-sort passes {_depth_sort_passes(sc, R)}")
+    assert passes == {3, 4}, passes
 
 
 def test_discrete_stage_with_saturated_counts(ctx):
