@@ -497,14 +497,13 @@ __global__ __launch_bounds__((fwd_threads<T, SPLIT>())) void k_render_fwd(
     }
 }
 
-// Per-splat gradient sums of one adjoint wave, for a block of R consecutive
-// splats (stored as soon as a block is done): nine fields of R splats, plus
-// one word so that two waves' slots fall in different LDS banks.  A
-// checkpointed unit (one LDS batch of up to 64) stores once (R = 64); the
-// whole-tile modes, whose many one-wave workgroups need the occupancy, store
-// every 32 splats.
+// Per-splat gradient sums of one adjoint wave, for a block of R = 64
+// consecutive splats (stored as soon as a block is done, one lane per splat,
+// so that every lane of the wave stores): nine fields of R splats, plus one
+// word so that two waves' slots fall in different LDS banks.  A checkpointed
+// unit (one LDS batch of up to 64) stores once.
 template <int MODE>
-constexpr int kRing = MODE == 1 ? 64 : 32;
+constexpr int kRing = 64;
 template <int MODE>
 constexpr int kGradSlot = 9 * kRing<MODE> + 1;
 static_assert(kRing<0> % 2 == 0 && kRing<1> % 2 == 0, "splat pairs stay within a block");
